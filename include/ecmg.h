@@ -1,0 +1,226 @@
+/*
+ * ecmg.h - C interface of the MI355X (gfx950) ECMG_jcg library.
+ *
+ * ECMG_jcg (Pan, He & Hu, arXiv 1506.02983, Algorithm 4) solves
+ *     -div(beta grad u) = f  in a box,  u = g_D on Dirichlet faces,
+ *     alpha u + beta du/dn = g_R on Robin faces            (Section 1, eq. bvp)
+ * with trilinear (Q1) hexahedral finite elements on a hierarchy of uniform
+ * grids (Section 2): the two coarsest grids are solved directly, every finer
+ * grid starts Jacobi-preconditioned CG (JCG) from an extrapolated and
+ * interpolated initial guess (EXP_finite, Sections 4.2.2-4.3) and iterates while
+ * ||A u - f||_2 > eps ||f||_2, and a fourth-order extrapolation (EXP_true,
+ * Section 4.2.1) combines the two finest solutions.
+ *
+ * Conventions shared by every call:
+ *  - Level l (0-based) has n0[d] * 2^l elements on axis d; "levels" counts all
+ *    grids, so levels - 2 grids are solved by JCG (Algorithm 4).
+ *  - A node vector of level l has (nx+1)(ny+1)(nz+1) doubles, node (i,j,k) at
+ *    index i + (nx+1)*(j + (ny+1)*k): x fastest, each z-plane contiguous.
+ *  - Faces are numbered 0..5 = x-lo, x-hi, y-lo, y-hi, z-lo, z-hi.  A node on
+ *    any Dirichlet face is a Dirichlet node (Dirichlet wins on shared edges).
+ *  - The library owns all device memory it allocates; the caller owns every
+ *    host buffer it passes.  Host buffers are read or written only during the
+ *    call.  Nothing here allocates or frees caller memory.
+ *  - Every function returns ECMG_OK (0) or a negative status; the message of
+ *    the last failure is available from ecmg_last_error.  No C++ exception
+ *    crosses this interface.  A context is not thread-safe: calls on one
+ *    context must not overlap.
+ *  - All arithmetic on the device is IEEE FP64 unless a call says otherwise.
+ */
+#ifndef ECMG_H
+#define ECMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define ECMG_OK           0
+#define ECMG_EINVAL      -1   /* invalid argument or problem data                  */
+#define ECMG_ENOMEM      -2   /* device or host allocation failed                  */
+#define ECMG_ENOTCONV    -3   /* JCG reached max_iter; the iterate is kept         */
+#define ECMG_EBREAKDOWN  -4   /* p.q <= 0 or not finite inside JCG                 */
+#define ECMG_EDEVICE     -5   /* a HIP runtime call failed                         */
+#define ECMG_ESTATE      -6   /* call out of order (e.g. solve before setup)       */
+#define ECMG_ECALLBACK   -7   /* a field callback returned nonzero                 */
+
+/* ---- face types (Section 1: Neumann is Robin with alpha = 0) ---------- */
+#define ECMG_DIRICHLET 0
+#define ECMG_ROBIN     1
+
+/* ---- precision of the JCG iterations ---------------------------------- */
+#define ECMG_FP64  0   /* everything in FP64                                          */
+#define ECMG_MIXED 1   /* FP32 stencil and CG vectors inside an FP64 residual /
+                          iterative-refinement loop; dots, stopping test, DSOLVE,
+                          EXP_finite and EXP_true stay FP64                         */
+
+/* ---- EXP_finite interpolation (Section 4.3) --------------------------- */
+#define ECMG_SERENDIPITY20 0   /* 8 corners (eq. jiedian) + 12 mid-edges (eq. zhongdian)
+                                  and 20-node tri-quadratic serendipity (eq. inter)   */
+#define ECMG_LAGRANGE27    1   /* the Remark after eq. inter: face and body centres as
+                                  means of eq. zhongdian along diagonals, then 27-node
+                                  tri-quadratic Lagrange interpolation                 */
+
+/* ---- vectors of a level (ecmg_get / ecmg_set / ecmg_device_view) ------ */
+#define ECMG_VEC_U      0   /* u_l: DSOLVE or JCG solution (g_D on Dirichlet nodes)    */
+#define ECMG_VEC_W      1   /* W_l: EXP_finite output on every node, before g_D is
+                               imposed (kept only with options.keep_w)                  */
+#define ECMG_VEC_UTILDE 2   /* U~_l: EXP_true output (after ecmg_extrapolate)          */
+#define ECMG_VEC_F      3   /* load vector F = int f phi + int_R g_R phi (Section 2)   */
+#define ECMG_VEC_DINV   4   /* 1/diag(A) on free nodes, 0 on Dirichlet nodes           */
+#define ECMG_VEC_NONE  -1
+
+/* Field sampled on a tensor product of coordinates.  The library asks for
+ * out[(k*ny + j)*nx + i] = value at (x[i], y[j], z[k]).  face = -1 for points
+ * inside the box, 0..5 when every point lies on that face (Robin data needs the
+ * outward normal).  Return 0 on success; nonzero aborts setup with
+ * ECMG_ECALLBACK.  Host version: x, y, z, out are host pointers. */
+typedef int (*ecmg_host_fn)(int32_t face, int64_t nx, int64_t ny, int64_t nz,
+                            const double *x, const double *y, const double *z,
+                            double *out, void *user);
+/* Device version: x, y, z, out are device pointers; work must be ordered on
+ * the given HIP stream (hipStream_t passed as void*). */
+typedef int (*ecmg_device_fn)(int32_t face, int64_t nx, int64_t ny, int64_t nz,
+                              const double *x, const double *y, const double *z,
+                              double *out, void *hip_stream, void *user);
+
+/* A coefficient or data field: device callback if set, else host callback if
+ * set, else the constant `value`. */
+typedef struct {
+    double value;
+    ecmg_host_fn host;
+    ecmg_device_fn device;
+    void *user;
+} ecmg_field;
+
+/* The boundary value problem of Section 1 (eq. bvp) and its grid hierarchy. */
+typedef struct {
+    double lo[3], hi[3];       /* the box, lo < hi                                  */
+    int32_t n0[3];             /* coarsest elements per axis, >= 1                  */
+    int32_t levels;            /* number of grids, >= 2 (levels 0 and 1 are DSOLVE) */
+    int32_t face_type[6];      /* ECMG_DIRICHLET or ECMG_ROBIN per face             */
+    ecmg_field beta;           /* diffusion coefficient, > 0, sampled at element centroids */
+    ecmg_field f;              /* right-hand side, sampled at 2x2x2 Gauss points     */
+    ecmg_field g_D;            /* Dirichlet data, sampled at Dirichlet nodes         */
+    ecmg_field alpha;          /* Robin coefficient, >= 0, at Robin face-element centroids */
+    ecmg_field g_R;            /* Robin data, sampled at 2x2 Gauss points of Robin faces */
+} ecmg_problem;
+
+typedef struct {
+    int32_t precision;         /* ECMG_FP64 (default) or ECMG_MIXED                      */
+    int32_t max_iter;          /* JCG iteration cap per level (default 20000)            */
+    int32_t interp;            /* ECMG_SERENDIPITY20 (default) or ECMG_LAGRANGE27        */
+    int32_t keep_w;            /* keep W_l of every level for diagnostics (default 1)    */
+    double inner_tol;          /* ECMG_MIXED: inner FP32 JCG relative reduction (1e-4)   */
+    double dsolve_tol;         /* DSOLVE as FP64 JCG to this relative residual (1e-14)   */
+    int32_t chunk;             /* JCG iterations between host status reads (0 = auto)    */
+    int32_t timing;            /* 1 = time kernels with HIP events (ecmg_kernel_times)   */
+    void *hip_stream;          /* hipStream_t to order all work on; NULL = own stream    */
+} ecmg_options;
+
+/* Per-level report (Algorithm 4 and the "Iters"/"RRe" columns of Section 5). */
+typedef struct {
+    int32_t level, nx, ny, nz; /* level index and elements per axis                    */
+    int32_t iters;             /* JCG iterations (DSOLVE levels: iterations used)      */
+    int32_t outer_steps;       /* ECMG_MIXED: FP64 refinement steps; else 0            */
+    int32_t status;            /* ECMG_OK, ECMG_ENOTCONV or ECMG_EBREAKDOWN            */
+    int32_t reserved;
+    double rre;                /* ||r||_2 / ||f_h||_2 at exit (recurrence residual)     */
+    double nf;                 /* ||f_h||_2 of the stopping test                        */
+    double ms;                 /* wall time of the level on the device stream          */
+} ecmg_level_info;
+
+typedef struct ecmg_ctx ecmg_ctx;
+
+/* Fill *opt with the defaults listed above. */
+void ecmg_default_options(ecmg_options *opt);
+
+/* Create a context on the current HIP device.  opt may be NULL (defaults).
+ * Fails with ECMG_EDEVICE when no gfx950 device is present. */
+int ecmg_create(const ecmg_options *opt, ecmg_ctx **out);
+
+/* Discretise every level (Section 2): beta at element centroids, alpha at
+ * Robin face-element centroids, the load vector F by 2x2x2 Gauss per element
+ * and 2x2 Gauss per Robin face element, g_D at Dirichlet nodes, the Jacobi
+ * diagonal, and ||f_h||_2 = ||(F - A_FD g_D on free nodes, g_D on Dirichlet
+ * nodes)||_2.  Validates the problem: ECMG_EINVAL for lo >= hi, n0 < 1,
+ * levels < 2, a bad face type, beta <= 0, alpha < 0, non-finite samples, or a
+ * singular system (no Dirichlet face and alpha == 0 everywhere).  May be called
+ * again; it frees the previous hierarchy first. */
+int ecmg_setup(ecmg_ctx *ctx, const ecmg_problem *problem);
+
+/* Algorithm 4: DSOLVE on levels 0 and 1 (FP64 JCG to options.dsolve_tol), then
+ * for each finer level W = EXP_finite(u_{l-1}, u_{l-2}), JCG from W (with g_D
+ * imposed) while ||r||_2 > rel_tol ||f_h||_2.  info: NULL or an array of
+ * `levels` entries.  Returns ECMG_ENOTCONV / ECMG_EBREAKDOWN if any level
+ * failed (all levels still run; each entry has its own status). */
+int ecmg_solve(ecmg_ctx *ctx, double rel_tol, ecmg_level_info *info);
+
+/* As ecmg_solve, but JCG on level l >= 2 runs exactly iters[l] iterations
+ * (iters has `levels` entries; entries 0 and 1 are ignored). */
+int ecmg_solve_fixed(ecmg_ctx *ctx, const int32_t *iters, ecmg_level_info *info);
+
+/* EXP_true (Section 4.2.1, eqs. t1 and chenlin; face and body centres as the
+ * mean along their diagonals): U~_l from u_l and u_{l-1}, for 1 <= level <
+ * levels (-1 = finest).  host_out: NULL, or a node array of the level that
+ * receives U~_l. */
+int ecmg_extrapolate(ecmg_ctx *ctx, int32_t level, double *host_out);
+
+/* EXP_finite alone: W_l from the current u_{l-1} and u_{l-2} (2 <= level);
+ * writes W_l into u_l on free nodes (Dirichlet nodes keep g_D) and into the W
+ * vector when kept.  Used for testing and for resuming a cascade. */
+int ecmg_prolongate(ecmg_ctx *ctx, int32_t level);
+
+/* JCG on one level from the current u_l: while ||r|| > rel_tol ||f_h|| (or
+ * exactly fixed_iters iterations when fixed_iters >= 0). */
+int ecmg_jcg(ecmg_ctx *ctx, int32_t level, double rel_tol, int32_t fixed_iters, ecmg_level_info *info);
+
+/* q = A v on free rows of level `level`, 0 on Dirichlet rows (every column is
+ * used, so v may carry g_D on Dirichlet nodes).  host_in, host_out: node
+ * arrays.  This is the matrix-free operator of Section 2. */
+int ecmg_apply(ecmg_ctx *ctx, int32_t level, const double *host_in, double *host_out);
+
+/* Copy a vector of a level to / from a host node array (ECMG_VEC_*). */
+int ecmg_get(ecmg_ctx *ctx, int32_t level, int32_t which, double *host_out);
+int ecmg_set(ecmg_ctx *ctx, int32_t level, int32_t which, const double *host_in);
+
+/* Device pointer of a vector (FP64, node layout above) for zero-copy use.
+ * dims receives (nx+1, ny+1, nz+1).  The pointer stays valid until the next
+ * ecmg_setup or ecmg_destroy. */
+int ecmg_device_view(ecmg_ctx *ctx, int32_t level, int32_t which, void **dptr, int64_t dims[3]);
+
+/* Error norms of the tables of Section 5 on a level: v = vec[which]
+ * - vec[minus_which] (ECMG_VEC_NONE = 0) - minus_host (NULL = 0);
+ * out[0] = max |v|, out[1] = (sum v^2 / N)^(1/2) over all N nodes. */
+int ecmg_norms(ecmg_ctx *ctx, int32_t level, int32_t which, int32_t minus_which,
+               const double *minus_host, double out[2]);
+
+/* Elements per axis of a level. */
+int ecmg_level_dims(ecmg_ctx *ctx, int32_t level, int64_t n[3]);
+
+/* Device bytes the hierarchy of `problem` needs at `precision` (no device
+ * needed). */
+int ecmg_plan_bytes(const ecmg_problem *problem, int32_t precision, size_t *bytes);
+
+/* Kernel timing (options.timing = 1): for level `level` and kernel class k
+ * (0 = JCG pass A, 1 = JCG pass B, 2 = JCG init, 3 = EXP_finite, 4 = EXP_true,
+ * 5 = mixed-precision pass A, 6 = mixed-precision pass B),
+ * out[0] = total milliseconds and out[1] = launches that did work since the
+ * last ecmg_reset_kernel_times.  Measured with HIP events on the library's
+ * stream around each launch. */
+int ecmg_kernel_times(ecmg_ctx *ctx, int32_t level, int32_t k, double out[2]);
+int ecmg_reset_kernel_times(ecmg_ctx *ctx);
+
+/* The last error message of ctx (or of the calling thread when ctx is NULL). */
+const char *ecmg_last_error(const ecmg_ctx *ctx);
+
+/* Release every device allocation of ctx and the context itself. */
+void ecmg_destroy(ecmg_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ECMG_H */

@@ -1,0 +1,355 @@
+"""Python binding of the MI355X ECMG_jcg library (include/ecmg.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+libecmg.so.  Importing this module fails loudly if the library has not been
+built (``python -m paper_1506_02983_amd.build`` or ``__graft_entry__.build()``);
+there is no CPU fallback.
+
+Fields are given as numpy functions ``fn(x, y, z, face)`` evaluated with
+broadcasting (see ``workloads``), as constants, or as torch functions evaluated
+on the device (``device_fields=True``), which samples every field with torch on
+the GPU through the library's device-callback interface.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libecmg.so")
+
+OK, EINVAL, ENOMEM, ENOTCONV, EBREAKDOWN, EDEVICE, ESTATE, ECALLBACK = 0, -1, -2, -3, -4, -5, -6, -7
+DIRICHLET, ROBIN = 0, 1
+FP64, MIXED = 0, 1
+SERENDIPITY20, LAGRANGE27 = 0, 1
+VEC_U, VEC_W, VEC_UTILDE, VEC_F, VEC_DINV, VEC_NONE = 0, 1, 2, 3, 4, -1
+K_PASSA, K_PASSB, K_INIT, K_EXPF, K_EXPT, K_PASSA32, K_PASSB32 = range(7)
+
+_STATUS = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", ENOTCONV: "ENOTCONV", EBREAKDOWN: "EBREAKDOWN",
+           EDEVICE: "EDEVICE", ESTATE: "ESTATE", ECALLBACK: "ECALLBACK"}
+
+HOST_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+DEVICE_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                             ctypes.c_void_p)
+
+
+class Field(ctypes.Structure):
+    _fields_ = [("value", ctypes.c_double), ("host", HOST_FN), ("device", DEVICE_FN), ("user", ctypes.c_void_p)]
+
+
+class ProblemC(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3), ("n0", ctypes.c_int32 * 3),
+                ("levels", ctypes.c_int32), ("face_type", ctypes.c_int32 * 6),
+                ("beta", Field), ("f", Field), ("g_D", Field), ("alpha", Field), ("g_R", Field)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("interp", ctypes.c_int32),
+                ("keep_w", ctypes.c_int32), ("inner_tol", ctypes.c_double), ("dsolve_tol", ctypes.c_double),
+                ("chunk", ctypes.c_int32), ("timing", ctypes.c_int32), ("hip_stream", ctypes.c_void_p)]
+
+
+class LevelInfo(ctypes.Structure):
+    _fields_ = [("level", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("iters", ctypes.c_int32), ("outer_steps", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("rre", ctypes.c_double), ("nf", ctypes.c_double),
+                ("ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+# Every symbol include/ecmg.h declares (checked by the CPU test suite).
+EXPORTS = ["ecmg_default_options", "ecmg_create", "ecmg_setup", "ecmg_solve", "ecmg_solve_fixed",
+           "ecmg_extrapolate", "ecmg_prolongate", "ecmg_jcg", "ecmg_apply", "ecmg_get", "ecmg_set",
+           "ecmg_device_view", "ecmg_norms", "ecmg_level_dims", "ecmg_plan_bytes", "ecmg_kernel_times",
+           "ecmg_reset_kernel_times", "ecmg_last_error", "ecmg_destroy"]
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libecmg.so; raises ImportError if it is missing (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError("libecmg.so not built at %s: run __graft_entry__.build()" % path)
+    L = ctypes.CDLL(path)
+    P, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    L.ecmg_default_options.argtypes = [ctypes.POINTER(Options)]
+    L.ecmg_default_options.restype = None
+    L.ecmg_create.argtypes = [ctypes.POINTER(Options), ctypes.POINTER(P)]
+    L.ecmg_setup.argtypes = [P, ctypes.POINTER(ProblemC)]
+    L.ecmg_solve.argtypes = [P, dbl, P]
+    L.ecmg_solve_fixed.argtypes = [P, P, P]
+    L.ecmg_extrapolate.argtypes = [P, i32, P]
+    L.ecmg_prolongate.argtypes = [P, i32]
+    L.ecmg_jcg.argtypes = [P, i32, dbl, i32, P]
+    L.ecmg_apply.argtypes = [P, i32, P, P]
+    L.ecmg_get.argtypes = [P, i32, i32, P]
+    L.ecmg_set.argtypes = [P, i32, i32, P]
+    L.ecmg_device_view.argtypes = [P, i32, i32, ctypes.POINTER(P), P]
+    L.ecmg_norms.argtypes = [P, i32, i32, i32, P, P]
+    L.ecmg_level_dims.argtypes = [P, i32, P]
+    L.ecmg_plan_bytes.argtypes = [ctypes.POINTER(ProblemC), i32, ctypes.POINTER(ctypes.c_size_t)]
+    L.ecmg_kernel_times.argtypes = [P, i32, i32, P]
+    L.ecmg_reset_kernel_times.argtypes = [P]
+    L.ecmg_last_error.argtypes = [P]
+    L.ecmg_last_error.restype = ctypes.c_char_p
+    L.ecmg_destroy.argtypes = [P]
+    L.ecmg_destroy.restype = None
+    for name in EXPORTS:
+        getattr(L, name)
+    _lib = L
+    return L
+
+
+class EcmgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (_STATUS.get(code, "?"), code, msg))
+        self.code = code
+
+
+# ---------------------------------------------------------------------------
+# fields
+# ---------------------------------------------------------------------------
+
+def _host_callback(fn):
+    """Wrap a numpy field fn(x, y, z, face) as a tensor-product host callback."""
+    def cb(face, nx, ny, nz, px, py, pz, pout, user):
+        try:
+            x = np.ctypeslib.as_array(ctypes.cast(px, ctypes.POINTER(ctypes.c_double)), shape=(nx,))
+            y = np.ctypeslib.as_array(ctypes.cast(py, ctypes.POINTER(ctypes.c_double)), shape=(ny,))
+            z = np.ctypeslib.as_array(ctypes.cast(pz, ctypes.POINTER(ctypes.c_double)), shape=(nz,))
+            out = np.ctypeslib.as_array(ctypes.cast(pout, ctypes.POINTER(ctypes.c_double)), shape=(nz, ny, nx))
+            v = fn(x[None, None, :], y[None, :, None], z[:, None, None], int(face))
+            out[...] = np.broadcast_to(v, (nz, ny, nx))
+            return 0
+        except Exception:                      # noqa: BLE001 - reported as ECMG_ECALLBACK
+            import traceback
+            traceback.print_exc()
+            return 1
+    return HOST_FN(cb)
+
+
+class _DevArray:
+    def __init__(self, ptr, shape):
+        self.__cuda_array_interface__ = {"shape": tuple(shape), "typestr": "<f8", "data": (int(ptr), False),
+                                         "version": 3, "strides": None}
+
+
+def _device_callback(fn):
+    """Wrap a field fn(x, y, z, face) written with array methods torch supports
+    as a device callback evaluated by torch on the GPU."""
+    import torch
+
+    def cb(face, nx, ny, nz, px, py, pz, pout, stream, user):
+        try:
+            with torch.cuda.stream(torch.cuda.ExternalStream(int(stream))):
+                x = torch.as_tensor(_DevArray(px, (nx,)), device="cuda")
+                y = torch.as_tensor(_DevArray(py, (ny,)), device="cuda")
+                z = torch.as_tensor(_DevArray(pz, (nz,)), device="cuda")
+                out = torch.as_tensor(_DevArray(pout, (nz, ny, nx)), device="cuda")
+                v = fn(x[None, None, :], y[None, :, None], z[:, None, None], int(face))
+                out.copy_(torch.as_tensor(v, dtype=torch.float64, device="cuda").expand(nz, ny, nx))
+            return 0
+        except Exception:                      # noqa: BLE001
+            import traceback
+            traceback.print_exc()
+            return 1
+    return DEVICE_FN(cb)
+
+
+def _field(fn, device: bool, keep: list) -> Field:
+    f = Field()
+    c = getattr(fn, "constant", None)
+    if c is not None or isinstance(fn, (int, float)):
+        f.value = float(c if c is not None else fn)
+        return f
+    if device:
+        cb = _device_callback(fn)
+        f.device = cb
+    else:
+        cb = _host_callback(fn)
+        f.host = cb
+    keep.append(cb)
+    return f
+
+
+def problem_struct(problem, device_fields: bool = False):
+    """ctypes ecmg_problem for a workloads.Problem; returns (struct, keepalive)."""
+    keep: list = []
+    p = ProblemC()
+    for d in range(3):
+        p.lo[d] = float(problem.lo[d])
+        p.hi[d] = float(problem.hi[d])
+        p.n0[d] = int(problem.n0[d])
+    p.levels = int(problem.levels)
+    for f in range(6):
+        p.face_type[f] = int(problem.face_type[f])
+    p.beta = _field(problem.beta, device_fields, keep)
+    p.f = _field(problem.f, device_fields, keep)
+    p.g_D = _field(problem.gD, device_fields, keep)
+    p.alpha = _field(problem.alpha, device_fields, keep)
+    p.g_R = _field(problem.gR, device_fields, keep)
+    return p, keep
+
+
+# ---------------------------------------------------------------------------
+# context
+# ---------------------------------------------------------------------------
+
+class Solver:
+    """One ECMG_jcg context (one problem hierarchy resident on the device)."""
+
+    def __init__(self, precision: int = FP64, interp: int = SERENDIPITY20, keep_w: bool = True,
+                 max_iter: int = 20000, dsolve_tol: float = 1e-14, inner_tol: float = 1e-4,
+                 chunk: int = 0, timing: bool = False, stream=None):
+        self.L = load_library()
+        o = Options()
+        self.L.ecmg_default_options(ctypes.byref(o))
+        o.precision, o.interp, o.keep_w, o.max_iter = precision, interp, int(keep_w), max_iter
+        o.dsolve_tol, o.inner_tol, o.chunk, o.timing = dsolve_tol, inner_tol, chunk, int(timing)
+        o.hip_stream = stream
+        self.opt = o
+        h = ctypes.c_void_p()
+        self._check(self.L.ecmg_create(ctypes.byref(o), ctypes.byref(h)), None)
+        self.h = h
+        self.levels = 0
+        self._keep = None
+
+    def _check(self, rc, h="self"):
+        if rc != OK:
+            msg = self.L.ecmg_last_error(self.h if h == "self" else None)
+            raise EcmgError(rc, (msg or b"").decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.ecmg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # ---- calls --------------------------------------------------------------
+    def setup(self, problem, device_fields: bool = False):
+        p, keep = problem_struct(problem, device_fields)
+        self._keep = (p, keep)
+        self._check(self.L.ecmg_setup(self.h, ctypes.byref(p)))
+        self.levels = int(problem.levels)
+        return self
+
+    def _infos(self):
+        return (LevelInfo * self.levels)()
+
+    def solve(self, rel_tol: float, allow_fail: bool = False) -> List[dict]:
+        info = self._infos()
+        rc = self.L.ecmg_solve(self.h, float(rel_tol), info)
+        if not allow_fail:
+            self._check(rc)
+        return [i.as_dict() for i in info]
+
+    def solve_fixed(self, iters: Sequence[int]) -> List[dict]:
+        info = self._infos()
+        arr = (ctypes.c_int32 * self.levels)(*[int(v) for v in iters])
+        self._check(self.L.ecmg_solve_fixed(self.h, arr, info))
+        return [i.as_dict() for i in info]
+
+    def dims(self, level: int) -> tuple:
+        n = (ctypes.c_int64 * 3)()
+        self._check(self.L.ecmg_level_dims(self.h, int(level), n))
+        return tuple(int(v) for v in n)
+
+    def nodes(self, level: int) -> int:
+        n = self.dims(level)
+        return (n[0] + 1) * (n[1] + 1) * (n[2] + 1)
+
+    def extrapolate(self, level: int = -1, out: bool = True) -> Optional[np.ndarray]:
+        if level < 0:
+            level = self.levels - 1
+        buf = np.empty(self.nodes(level)) if out else None
+        self._check(self.L.ecmg_extrapolate(self.h, int(level), None if buf is None else buf.ctypes.data))
+        return buf
+
+    def prolongate(self, level: int):
+        self._check(self.L.ecmg_prolongate(self.h, int(level)))
+
+    def jcg(self, level: int, rel_tol: float, fixed_iters: int = -1, allow_fail: bool = False) -> dict:
+        info = LevelInfo()
+        rc = self.L.ecmg_jcg(self.h, int(level), float(rel_tol), int(fixed_iters), ctypes.byref(info))
+        if not allow_fail:
+            self._check(rc)
+        d = info.as_dict()
+        d["rc"] = rc
+        return d
+
+    def apply(self, level: int, v: np.ndarray) -> np.ndarray:
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        assert v.size == self.nodes(level)
+        out = np.empty_like(v)
+        self._check(self.L.ecmg_apply(self.h, int(level), v.ctypes.data, out.ctypes.data))
+        return out
+
+    def get(self, level: int, which: int = VEC_U) -> np.ndarray:
+        if level < 0:
+            level = self.levels - 1
+        out = np.empty(self.nodes(level))
+        self._check(self.L.ecmg_get(self.h, int(level), int(which), out.ctypes.data))
+        return out
+
+    def set(self, level: int, which: int, v: np.ndarray):
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        assert v.size == self.nodes(level)
+        self._check(self.L.ecmg_set(self.h, int(level), int(which), v.ctypes.data))
+
+    def device_view(self, level: int, which: int = VEC_U):
+        ptr = ctypes.c_void_p()
+        dims = (ctypes.c_int64 * 3)()
+        self._check(self.L.ecmg_device_view(self.h, int(level), int(which), ctypes.byref(ptr), dims))
+        return int(ptr.value), tuple(int(v) for v in dims)
+
+    def norms(self, level: int, which: int, minus_which: int = VEC_NONE, minus: Optional[np.ndarray] = None):
+        out = (ctypes.c_double * 2)()
+        m = None if minus is None else np.ascontiguousarray(minus, dtype=np.float64)
+        self._check(self.L.ecmg_norms(self.h, int(level), int(which), int(minus_which),
+                                      None if m is None else m.ctypes.data, out))
+        return float(out[0]), float(out[1])
+
+    def kernel_times(self, level: int, kind: int) -> tuple:
+        out = (ctypes.c_double * 2)()
+        self._check(self.L.ecmg_kernel_times(self.h, int(level), int(kind), out))
+        return float(out[0]), int(out[1])
+
+    def reset_kernel_times(self):
+        self._check(self.L.ecmg_reset_kernel_times(self.h))
+
+
+def plan_bytes(problem, precision: int = FP64) -> int:
+    L = load_library()
+    p, keep = problem_struct(problem)
+    out = ctypes.c_size_t()
+    rc = L.ecmg_plan_bytes(ctypes.byref(p), int(precision), ctypes.byref(out))
+    if rc != OK:
+        raise EcmgError(rc, (L.ecmg_last_error(None) or b"").decode())
+    return int(out.value)
+
+
+def last_error() -> str:
+    return (load_library().ecmg_last_error(None) or b"").decode()

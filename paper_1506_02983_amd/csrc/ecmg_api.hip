@@ -1,0 +1,883 @@
+// Host side of the C interface in include/ecmg.h: problem validation, the level
+// hierarchy resident in HBM, discretisation (Section 2), the Algorithm 4
+// driver, and the per-level operators exposed for testing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ecmg_internal.h"
+
+using namespace ecmg;
+
+namespace {
+thread_local std::string g_thread_error;
+}
+
+struct ecmg_ctx {
+    ecmg_options opt{};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+    std::vector<Level> lv;
+    int nlev = 0;
+    int face_type[6] = {};
+    bool ready = false;        // setup done
+    bool solved = false;       // u of every level available
+    // shared JCG scratch, sized for the finest level
+    double *r = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr;
+    int64_t scratch_n = 0;
+    JcgScalars *sc = nullptr;  // device
+    JcgScalars *sc_host = nullptr;  // pinned
+    double *partials = nullptr;
+    int64_t partials_n = 0;
+    unsigned *counters = nullptr;   // [0] stencil, [1] pass B, [2] norms
+    double *dres = nullptr;         // device results of reductions [4]
+    double *hres = nullptr;         // pinned host copy
+    double *hstage = nullptr;       // pinned host staging for callback samples
+    double *dstage = nullptr;       // device staging
+    int64_t stage_n = 0;
+    int KZ = 32;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // kernel timing (options.timing)
+    struct Rec { hipEvent_t a, b; int level, kind, iter; };
+    std::vector<hipEvent_t> evpool;
+    std::vector<Rec> recs;
+    size_t evnext = 0;
+};
+
+// ---------------------------------------------------------------------------
+// error helpers
+// ---------------------------------------------------------------------------
+static int fail(ecmg_ctx *c, int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    g_thread_error = buf;
+    return code;
+}
+
+#define HIPCHK(c, call)                                                                             \
+    do {                                                                                            \
+        hipError_t e_ = (call);                                                                     \
+        if (e_ != hipSuccess)                                                                       \
+            return fail((c), ECMG_EDEVICE, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, \
+                        __LINE__);                                                                  \
+    } while (0)
+
+#define CHK(call)                     \
+    do {                              \
+        int s_ = (call);              \
+        if (s_ != ECMG_OK) return s_; \
+    } while (0)
+
+static int dalloc(ecmg_ctx *c, void **p, size_t bytes) {
+    if (bytes == 0) bytes = 8;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(c, ECMG_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
+    return ECMG_OK;
+}
+template <typename T>
+static int dalloc_n(ecmg_ctx *c, T **p, int64_t n) {
+    return dalloc(c, (void **)p, sizeof(T) * (size_t)std::max<int64_t>(n, 1));
+}
+static void dfree(void *p) {
+    if (p) (void)hipFree(p);
+}
+
+// ---------------------------------------------------------------------------
+// geometry
+// ---------------------------------------------------------------------------
+static Geom make_geom(const ecmg_problem *p, int l, double lo[3]) {
+    Geom g{};
+    g.nx = p->n0[0] << l;
+    g.ny = p->n0[1] << l;
+    g.nz = p->n0[2] << l;
+    g.sx = g.nx + 1;
+    g.sy = g.ny + 1;
+    g.nnodes = (int64_t)g.sx * g.sy * (g.nz + 1);
+    const int n[3] = {g.nx, g.ny, g.nz};
+    for (int d = 0; d < 3; ++d) {
+        g.h[d] = (p->hi[d] - p->lo[d]) / (double)n[d];
+        lo[d] = p->lo[d];
+    }
+    for (int f = 0; f < 6; ++f) g.ft[f] = p->face_type[f];
+    // Q1 element stiffness classes: product over axes of 1-D stiffness
+    // K1 = (+1 same node, -1 other)/h and 1-D mass M1 = h (1/3 same, 1/6 other),
+    // summed over which axis carries the derivative.
+    for (int m = 0; m < 8; ++m) {
+        double s = 0.0;
+        for (int dv = 0; dv < 3; ++dv) {
+            double t = 1.0;
+            for (int ax = 0; ax < 3; ++ax) {
+                const bool other = (m >> ax) & 1;
+                if (ax == dv) t *= (other ? -1.0 : 1.0) / g.h[ax];
+                else t *= g.h[ax] * (other ? 1.0 / 6.0 : 1.0 / 3.0);
+            }
+            s += t;
+        }
+        g.C[m] = s;
+    }
+    for (int f = 0; f < 6; ++f) {
+        const int ax = f / 2;
+        const int pax = (ax == 0) ? 1 : 0, qax = (ax == 2) ? 1 : 2;
+        const double A = g.h[pax] * g.h[qax];
+        g.M[f][0] = A / 9.0;
+        g.M[f][1] = A / 18.0;
+        g.M[f][2] = A / 36.0;
+    }
+    return g;
+}
+
+static void face_axes_h(int f, int &p, int &q) {
+    const int ax = f / 2;
+    p = (ax == 0) ? 1 : 0;
+    q = (ax == 2) ? 1 : 2;
+}
+
+// coordinates of the sampling sets along axis d of a level
+static std::vector<double> node_coords(const Geom &g, const double lo[3], int d) {
+    const int n[3] = {g.nx, g.ny, g.nz};
+    std::vector<double> v(n[d] + 1);
+    for (int i = 0; i <= n[d]; ++i) v[i] = lo[d] + (double)i * g.h[d];
+    return v;
+}
+static std::vector<double> centroid_coords(const Geom &g, const double lo[3], int d) {
+    const int n[3] = {g.nx, g.ny, g.nz};
+    std::vector<double> v(n[d]);
+    for (int i = 0; i < n[d]; ++i) v[i] = lo[d] + ((double)i + 0.5) * g.h[d];
+    return v;
+}
+// two Gauss-Legendre points per element: origin + (1 -/+ 1/sqrt3) h/2
+static std::vector<double> gauss_coords(const Geom &g, const double lo[3], int d) {
+    const int n[3] = {g.nx, g.ny, g.nz};
+    const double G = 1.0 / std::sqrt(3.0);
+    std::vector<double> v(2 * (size_t)n[d]);
+    for (int i = 0; i < n[d]; ++i) {
+        const double e0 = lo[d] + (double)i * g.h[d];
+        v[2 * i] = e0 + (1.0 - G) * g.h[d] / 2.0;
+        v[2 * i + 1] = e0 + (1.0 + G) * g.h[d] / 2.0;
+    }
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// field sampling: evaluates `fld` on x (fastest) by y by z into device memory
+// `dout`, validating host samples.  check: 0 finite, 1 > 0, 2 >= 0.
+// ---------------------------------------------------------------------------
+static int ensure_stage(ecmg_ctx *c, int64_t n) {
+    if (n <= c->stage_n) return ECMG_OK;
+    if (c->hstage) (void)hipHostFree(c->hstage);
+    dfree(c->dstage);
+    c->hstage = nullptr;
+    c->dstage = nullptr;
+    c->stage_n = 0;
+    HIPCHK(c, hipHostMalloc((void **)&c->hstage, sizeof(double) * (size_t)n, hipHostMallocDefault));
+    CHK(dalloc_n(c, &c->dstage, n));
+    c->stage_n = n;
+    return ECMG_OK;
+}
+
+static int sample(ecmg_ctx *c, const ecmg_field &fld, const char *name, int face, const std::vector<double> &x,
+                  const std::vector<double> &y, const std::vector<double> &z, double *dout, int check) {
+    const int64_t n = (int64_t)x.size() * (int64_t)y.size() * (int64_t)z.size();
+    if (n == 0) return ECMG_OK;
+    if (fld.device) {
+        double *dx = nullptr, *dy = nullptr, *dz = nullptr;
+        CHK(dalloc_n(c, &dx, (int64_t)x.size()));
+        CHK(dalloc_n(c, &dy, (int64_t)y.size()));
+        CHK(dalloc_n(c, &dz, (int64_t)z.size()));
+        HIPCHK(c, hipMemcpyAsync(dx, x.data(), 8 * x.size(), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(dy, y.data(), 8 * y.size(), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(dz, z.data(), 8 * z.size(), hipMemcpyHostToDevice, c->stream));
+        const int rc = fld.device(face, (int64_t)x.size(), (int64_t)y.size(), (int64_t)z.size(), dx, dy, dz, dout,
+                                  (void *)c->stream, fld.user);
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        dfree(dx);
+        dfree(dy);
+        dfree(dz);
+        if (rc != 0) return fail(c, ECMG_ECALLBACK, "device callback for %s returned %d", name, rc);
+        return ECMG_OK;
+    }
+    if (!fld.host) {
+        const double v = fld.value;
+        if (!std::isfinite(v) || (check == 1 && !(v > 0)) || (check == 2 && !(v >= 0)))
+            return fail(c, ECMG_EINVAL, "invalid constant %s = %g", name, v);
+        launch_fill(dout, n, v, c->stream);
+        HIPCHK(c, hipGetLastError());
+        return ECMG_OK;
+    }
+    CHK(ensure_stage(c, n));
+    HIPCHK(c, hipStreamSynchronize(c->stream));  // staging buffer may still be in use
+    const int rc = fld.host(face, (int64_t)x.size(), (int64_t)y.size(), (int64_t)z.size(), x.data(), y.data(),
+                            z.data(), c->hstage, fld.user);
+    if (rc != 0) return fail(c, ECMG_ECALLBACK, "host callback for %s returned %d", name, rc);
+    for (int64_t i = 0; i < n; ++i) {
+        const double v = c->hstage[i];
+        if (!std::isfinite(v) || (check == 1 && !(v > 0)) || (check == 2 && !(v >= 0)))
+            return fail(c, ECMG_EINVAL, "invalid sample of %s: %g at point %lld", name, v, (long long)i);
+    }
+    HIPCHK(c, hipMemcpyAsync(dout, c->hstage, sizeof(double) * (size_t)n, hipMemcpyHostToDevice, c->stream));
+    return ECMG_OK;
+}
+
+static const int64_t kBatchPoints = (int64_t)1 << 23;
+
+// ---------------------------------------------------------------------------
+// timing records
+// ---------------------------------------------------------------------------
+static int rec_begin(ecmg_ctx *c, int level, int kind, int iter, size_t *slot) {
+    if (!c->opt.timing) return ECMG_OK;
+    if (c->evnext + 2 > c->evpool.size()) {
+        for (int t = 0; t < 256; ++t) {
+            hipEvent_t e;
+            HIPCHK(c, hipEventCreate(&e));
+            c->evpool.push_back(e);
+        }
+    }
+    ecmg_ctx::Rec r{c->evpool[c->evnext], c->evpool[c->evnext + 1], level, kind, iter};
+    c->evnext += 2;
+    HIPCHK(c, hipEventRecord(r.a, c->stream));
+    *slot = c->recs.size();
+    c->recs.push_back(r);
+    return ECMG_OK;
+}
+static int rec_end(ecmg_ctx *c, size_t slot) {
+    if (!c->opt.timing) return ECMG_OK;
+    HIPCHK(c, hipEventRecord(c->recs[slot].b, c->stream));
+    return ECMG_OK;
+}
+// fold the records of a finished section; launches with iter >= iter_limit did no work
+static int rec_flush(ecmg_ctx *c, int iter_limit) {
+    if (!c->opt.timing) return ECMG_OK;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (auto &r : c->recs) {
+        if (r.iter >= iter_limit) continue;
+        float ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&ms, r.a, r.b));
+        c->lv[r.level].kt_ms[r.kind] += ms;
+        c->lv[r.level].kt_n[r.kind] += 1;
+    }
+    c->recs.clear();
+    c->evnext = 0;
+    return ECMG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// JCG on one level (the loop of Algorithm 4, lines 7-9)
+// ---------------------------------------------------------------------------
+static StencilArgs<double> stencil_args(ecmg_ctx *c, Level &L) {
+    StencilArgs<double> a{};
+    a.g = L.g;
+    a.KZ = c->KZ;
+    stencil_blocks(L.g, c->KZ, &a.ntx, &a.nty, &a.nkz);
+    a.beta = L.beta;
+    for (int f = 0; f < 6; ++f) a.alpha[f] = L.alpha[f];
+    a.dinv = L.dinv;
+    a.F = L.F;
+    a.sc = c->sc;
+    a.partials = c->partials;
+    a.counter = c->counters;
+    return a;
+}
+
+static int run_jcg(ecmg_ctx *c, int l, double tol_abs, int max_iter, int fixed, ecmg_level_info *info) {
+    Level &L = c->lv[l];
+    launch_jcg_reset(c->sc, tol_abs, max_iter, fixed, c->stream);
+    StencilArgs<double> a = stencil_args(c, L);
+    a.v = L.x;
+    a.r = c->r;
+    a.q = c->q;
+    a.x = L.x;
+    a.p0 = c->p0;
+    a.p1 = c->p1;
+    size_t slot = 0;
+    CHK(rec_begin(c, l, 2, 0, &slot));
+    launch_stencil<double>(MODE_INIT, a, c->stream);
+    CHK(rec_end(c, slot));
+    HIPCHK(c, hipGetLastError());
+
+    PassBArgs<double> b{};
+    b.n = L.g.nnodes;
+    b.r = c->r;
+    b.q = c->q;
+    b.dinv = L.dinv;
+    b.sc = c->sc;
+    b.partials = c->partials;
+    b.counter = c->counters + 1;
+    const int nbB = reduce_blocks(L.g.nnodes);
+
+    int done_iters = 0;
+    int chunk = c->opt.chunk > 0 ? c->opt.chunk : 2;
+    if (fixed >= 0) chunk = std::max(fixed, 1);
+    for (;;) {
+        HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(JcgScalars), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        if (c->sc_host->done) break;
+        done_iters = c->sc_host->iter;
+        for (int t = 0; t < chunk; ++t) {
+            CHK(rec_begin(c, l, 0, done_iters + t, &slot));
+            launch_stencil<double>(MODE_PASSA, a, c->stream);
+            CHK(rec_end(c, slot));
+            CHK(rec_begin(c, l, 1, done_iters + t, &slot));
+            launch_passB<double>(b, nbB, c->stream);
+            CHK(rec_end(c, slot));
+        }
+        HIPCHK(c, hipGetLastError());
+        if (c->opt.chunk <= 0 && fixed < 0) chunk = std::min(chunk * 2, 64);
+    }
+    const JcgScalars s = *c->sc_host;
+    if (s.pending) launch_final_x(L.g, L.x, c->p0, c->p1, c->sc, c->stream);
+    HIPCHK(c, hipGetLastError());
+    CHK(rec_flush(c, s.iter));
+    if (info) {
+        info->iters = s.iter;
+        info->rre = (L.nf > 0) ? std::sqrt(s.rr) / L.nf : 0.0;
+        info->nf = L.nf;
+        info->status = (s.done == DONE_BREAKDOWN) ? ECMG_EBREAKDOWN
+                       : (s.done == DONE_MAXITER) ? ECMG_ENOTCONV : ECMG_OK;
+    }
+    if (s.done == DONE_BREAKDOWN) return fail(c, ECMG_EBREAKDOWN, "JCG breakdown on level %d (p.q = %g)", l, s.pq);
+    if (s.done == DONE_MAXITER)
+        return fail(c, ECMG_ENOTCONV, "JCG reached max_iter = %d on level %d (rre %g)", max_iter, l,
+                    std::sqrt(s.rr) / L.nf);
+    return ECMG_OK;
+}
+
+static int do_exp_finite(ecmg_ctx *c, int l) {
+    Level &L = c->lv[l];
+    size_t slot = 0;
+    CHK(rec_begin(c, l, 3, 0, &slot));
+    launch_exp_finite(L.g, c->lv[l - 1].x, c->lv[l - 2].x, L.x, L.W, c->opt.interp, c->stream);
+    CHK(rec_end(c, slot));
+    HIPCHK(c, hipGetLastError());
+    return ECMG_OK;
+}
+
+static int do_exp_true(ecmg_ctx *c, int l) {
+    Level &L = c->lv[l];
+    if (!L.Ut) CHK(dalloc_n(c, &L.Ut, L.g.nnodes));
+    size_t slot = 0;
+    CHK(rec_begin(c, l, 4, 0, &slot));
+    launch_exp_true(L.g, L.x, c->lv[l - 1].x, L.Ut, c->stream);
+    CHK(rec_end(c, slot));
+    HIPCHK(c, hipGetLastError());
+    return ECMG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// context lifetime
+// ---------------------------------------------------------------------------
+static void free_levels(ecmg_ctx *c) {
+    for (auto &L : c->lv) {
+        dfree(L.beta);
+        dfree(L.F);
+        dfree(L.x);
+        dfree(L.dinv);
+        dfree(L.W);
+        dfree(L.Ut);
+        dfree(L.beta32);
+        dfree(L.dinv32);
+        for (int f = 0; f < 6; ++f) {
+            dfree(L.alpha[f]);
+            dfree(L.alpha32[f]);
+        }
+    }
+    c->lv.clear();
+    dfree(c->r);
+    dfree(c->p0);
+    dfree(c->p1);
+    dfree(c->q);
+    dfree(c->partials);
+    c->r = c->p0 = c->p1 = c->q = c->partials = nullptr;
+    c->scratch_n = 0;
+    c->partials_n = 0;
+    c->nlev = 0;
+    c->ready = c->solved = false;
+}
+
+extern "C" {
+
+void ecmg_default_options(ecmg_options *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->precision = ECMG_FP64;
+    o->max_iter = 20000;
+    o->interp = ECMG_SERENDIPITY20;
+    o->keep_w = 1;
+    o->inner_tol = 1e-4;
+    o->dsolve_tol = 1e-14;
+    o->chunk = 0;
+    o->timing = 0;
+    o->hip_stream = nullptr;
+}
+
+int ecmg_create(const ecmg_options *opt, ecmg_ctx **out) {
+    if (!out) return fail(nullptr, ECMG_EINVAL, "ecmg_create: out is NULL");
+    *out = nullptr;
+    ecmg_options o;
+    ecmg_default_options(&o);
+    if (opt) o = *opt;
+    if (o.precision != ECMG_FP64 && o.precision != ECMG_MIXED)
+        return fail(nullptr, ECMG_EINVAL, "unknown precision %d", o.precision);
+    if (o.interp != ECMG_SERENDIPITY20 && o.interp != ECMG_LAGRANGE27)
+        return fail(nullptr, ECMG_EINVAL, "unknown interpolation %d", o.interp);
+    if (o.max_iter < 0) return fail(nullptr, ECMG_EINVAL, "max_iter < 0");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+        return fail(nullptr, ECMG_EDEVICE, "no HIP device available");
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(nullptr, ECMG_EDEVICE, "hipGetDevice failed");
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return fail(nullptr, ECMG_EDEVICE, "hipGetDeviceProperties failed");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(nullptr, ECMG_EDEVICE, "device %d is %s; this library is built for gfx950", dev,
+                    prop.gcnArchName);
+    ecmg_ctx *c = new ecmg_ctx();
+    c->opt = o;
+    if (const char *kz = std::getenv("ECMG_KZ")) c->KZ = std::max(1, std::atoi(kz));
+    if (o.hip_stream) {
+        c->stream = (hipStream_t)o.hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return fail(nullptr, ECMG_EDEVICE, "hipStreamCreate failed");
+        }
+        c->own_stream = true;
+    }
+    int rc = ECMG_OK;
+    if ((rc = dalloc(c, (void **)&c->sc, sizeof(JcgScalars))) != ECMG_OK ||
+        (rc = dalloc(c, (void **)&c->counters, 16 * sizeof(unsigned))) != ECMG_OK ||
+        (rc = dalloc(c, (void **)&c->dres, 8 * sizeof(double))) != ECMG_OK) {
+        ecmg_destroy(c);
+        return rc;
+    }
+    if (hipMemset(c->counters, 0, 16 * sizeof(unsigned)) != hipSuccess ||
+        hipHostMalloc((void **)&c->sc_host, sizeof(JcgScalars), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&c->hres, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+        hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+        ecmg_destroy(c);
+        return fail(nullptr, ECMG_EDEVICE, "context initialisation failed");
+    }
+    *out = c;
+    return ECMG_OK;
+}
+
+void ecmg_destroy(ecmg_ctx *c) {
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    free_levels(c);
+    dfree(c->sc);
+    dfree(c->counters);
+    dfree(c->dres);
+    dfree(c->dstage);
+    if (c->hstage) (void)hipHostFree(c->hstage);
+    if (c->sc_host) (void)hipHostFree(c->sc_host);
+    if (c->hres) (void)hipHostFree(c->hres);
+    for (auto e : c->evpool) (void)hipEventDestroy(e);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+const char *ecmg_last_error(const ecmg_ctx *c) {
+    if (c) return c->err.c_str();
+    return g_thread_error.c_str();
+}
+
+static int validate(ecmg_ctx *c, const ecmg_problem *p) {
+    if (!p) return fail(c, ECMG_EINVAL, "problem is NULL");
+    for (int d = 0; d < 3; ++d) {
+        if (!(p->lo[d] < p->hi[d]) || !std::isfinite(p->lo[d]) || !std::isfinite(p->hi[d]))
+            return fail(c, ECMG_EINVAL, "box: lo[%d] = %g must be < hi[%d] = %g", d, p->lo[d], d, p->hi[d]);
+        if (p->n0[d] < 1) return fail(c, ECMG_EINVAL, "n0[%d] = %d must be >= 1", d, p->n0[d]);
+    }
+    if (p->levels < 2 || p->levels > 16) return fail(c, ECMG_EINVAL, "levels = %d must be in [2, 16]", p->levels);
+    for (int d = 0; d < 3; ++d) {
+        const int64_t n = (int64_t)p->n0[d] << (p->levels - 1);
+        if (n > (int64_t)1 << 20) return fail(c, ECMG_EINVAL, "finest grid too large on axis %d", d);
+    }
+    bool anyD = false;
+    for (int f = 0; f < 6; ++f) {
+        if (p->face_type[f] != ECMG_DIRICHLET && p->face_type[f] != ECMG_ROBIN)
+            return fail(c, ECMG_EINVAL, "face_type[%d] = %d is neither Dirichlet nor Robin", f, p->face_type[f]);
+        anyD |= p->face_type[f] == ECMG_DIRICHLET;
+    }
+    if (!anyD && !p->alpha.host && !p->alpha.device && !(p->alpha.value > 0))
+        return fail(c, ECMG_EINVAL, "no Dirichlet face and alpha == 0: the system is singular");
+    return ECMG_OK;
+}
+
+int ecmg_plan_bytes(const ecmg_problem *p, int32_t precision, size_t *bytes) {
+    if (!bytes) return fail(nullptr, ECMG_EINVAL, "bytes is NULL");
+    int rc = validate(nullptr, p);
+    if (rc != ECMG_OK) return rc;
+    size_t tot = 0;
+    int64_t finest = 0;
+    for (int l = 0; l < p->levels; ++l) {
+        double lo[3];
+        Geom g = make_geom(p, l, lo);
+        const int64_t ne = (int64_t)g.nx * g.ny * g.nz;
+        tot += 8 * (size_t)(5 * g.nnodes + ne);     // F, x, dinv, W, U~ + beta
+        if (precision == ECMG_MIXED) tot += 4 * (size_t)(g.nnodes + ne);
+        finest = g.nnodes;
+    }
+    tot += 8 * (size_t)(4 * finest);                // r, p0, p1, q
+    if (precision == ECMG_MIXED) tot += 4 * (size_t)(5 * finest);
+    *bytes = tot;
+    return ECMG_OK;
+}
+
+int ecmg_setup(ecmg_ctx *c, const ecmg_problem *p) {
+    if (!c) return fail(nullptr, ECMG_EINVAL, "ctx is NULL");
+    CHK(validate(c, p));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    free_levels(c);
+    c->nlev = p->levels;
+    for (int f = 0; f < 6; ++f) c->face_type[f] = p->face_type[f];
+    c->lv.resize(p->levels);
+    // scratch for the finest level and reduction partials
+    {
+        double lo[3];
+        Geom gf = make_geom(p, p->levels - 1, lo);
+        c->scratch_n = gf.nnodes;
+        CHK(dalloc_n(c, &c->r, gf.nnodes));
+        CHK(dalloc_n(c, &c->p0, gf.nnodes));
+        CHK(dalloc_n(c, &c->p1, gf.nnodes));
+        CHK(dalloc_n(c, &c->q, gf.nnodes));
+        int64_t pn = 2 * 4096;
+        for (int l = 0; l < p->levels; ++l) {
+            Geom g = make_geom(p, l, lo);
+            int a, b, d;
+            pn = std::max<int64_t>(pn, 2 * (int64_t)stencil_blocks(g, c->KZ, &a, &b, &d));
+        }
+        c->partials_n = pn;
+        CHK(dalloc_n(c, &c->partials, pn));
+    }
+    for (int l = 0; l < p->levels; ++l) {
+        Level &L = c->lv[l];
+        L.g = make_geom(p, l, L.lo);
+        const Geom &g = L.g;
+        L.nelem = (int64_t)g.nx * g.ny * g.nz;
+        CHK(dalloc_n(c, &L.beta, L.nelem));
+        CHK(dalloc_n(c, &L.F, g.nnodes));
+        CHK(dalloc_n(c, &L.x, g.nnodes));
+        CHK(dalloc_n(c, &L.dinv, g.nnodes));
+        if (c->opt.keep_w && l >= 2) CHK(dalloc_n(c, &L.W, g.nnodes));
+        const std::vector<double> cx = centroid_coords(g, L.lo, 0), cy = centroid_coords(g, L.lo, 1),
+                                  cz = centroid_coords(g, L.lo, 2);
+        const std::vector<double> gx = gauss_coords(g, L.lo, 0), gy = gauss_coords(g, L.lo, 1),
+                                  gz = gauss_coords(g, L.lo, 2);
+        const std::vector<double> nx = node_coords(g, L.lo, 0), ny = node_coords(g, L.lo, 1),
+                                  nz = node_coords(g, L.lo, 2);
+        // beta at element centroids, in slabs of element layers
+        {
+            const int64_t per = (int64_t)g.nx * g.ny;
+            const int step = (int)std::max<int64_t>(1, kBatchPoints / per);
+            for (int k0 = 0; k0 < g.nz; k0 += step) {
+                const int k1 = std::min(g.nz, k0 + step);
+                std::vector<double> zz(cz.begin() + k0, cz.begin() + k1);
+                CHK(sample(c, p->beta, "beta", -1, cx, cy, zz, L.beta + per * k0, 1));
+            }
+        }
+        // load vector: f at 2x2x2 Gauss points, slab by slab
+        launch_fill(L.F, g.nnodes, 0.0, c->stream);
+        {
+            const int64_t per = 8 * (int64_t)g.nx * g.ny;   // Gauss points per element layer
+            const int step = (int)std::max<int64_t>(1, kBatchPoints / per);
+            double *dbuf = nullptr;
+            CHK(dalloc_n(c, &dbuf, per * std::min(step, g.nz)));
+            for (int e0 = 0; e0 < g.nz; e0 += step) {
+                const int e1 = std::min(g.nz, e0 + step);
+                std::vector<double> zz(gz.begin() + 2 * e0, gz.begin() + 2 * e1);
+                int rc = sample(c, p->f, "f", -1, gx, gy, zz, dbuf, 0);
+                if (rc != ECMG_OK) { dfree(dbuf); return rc; }
+                launch_load_volume(g, e0, e1, dbuf, L.F, c->stream);
+                HIPCHK(c, hipStreamSynchronize(c->stream));
+            }
+            dfree(dbuf);
+        }
+        // Robin faces: alpha at face-element centroids, g_R at face Gauss points
+        launch_fill(L.x, g.nnodes, 0.0, c->stream);
+        const int n3[3] = {g.nx, g.ny, g.nz};
+        for (int f = 0; f < 6; ++f) {
+            int pax, qax;
+            face_axes_h(f, pax, qax);
+            const int ax = f / 2;
+            const double plane = (f & 1) ? p->hi[ax] : p->lo[ax];
+            if (p->face_type[f] == ECMG_ROBIN) {
+                L.nface[f] = (int64_t)n3[pax] * n3[qax];
+                CHK(dalloc_n(c, &L.alpha[f], L.nface[f]));
+                std::vector<double> s[3];
+                s[ax] = {plane};
+                s[pax] = centroid_coords(g, L.lo, pax);
+                s[qax] = centroid_coords(g, L.lo, qax);
+                CHK(sample(c, p->alpha, "alpha", f, s[0], s[1], s[2], L.alpha[f], 2));
+                s[pax] = gauss_coords(g, L.lo, pax);
+                s[qax] = gauss_coords(g, L.lo, qax);
+                double *dbuf = nullptr;
+                CHK(dalloc_n(c, &dbuf, 4 * L.nface[f]));
+                int rc = sample(c, p->g_R, "g_R", f, s[0], s[1], s[2], dbuf, 0);
+                if (rc != ECMG_OK) { dfree(dbuf); return rc; }
+                launch_load_face(g, f, dbuf, L.F, c->stream);
+                HIPCHK(c, hipStreamSynchronize(c->stream));
+                dfree(dbuf);
+            }
+        }
+        // Dirichlet data at the nodes of Dirichlet faces
+        for (int f = 0; f < 6; ++f) {
+            if (p->face_type[f] != ECMG_DIRICHLET) continue;
+            int pax, qax;
+            face_axes_h(f, pax, qax);
+            const int ax = f / 2;
+            const std::vector<double> &nc = (ax == 0) ? nx : (ax == 1) ? ny : nz;
+            std::vector<double> s[3];
+            s[ax] = {(f & 1) ? nc.back() : nc.front()};
+            s[pax] = node_coords(g, L.lo, pax);
+            s[qax] = node_coords(g, L.lo, qax);
+            double *dbuf = nullptr;
+            CHK(dalloc_n(c, &dbuf, (int64_t)s[pax].size() * s[qax].size()));
+            int rc = sample(c, p->g_D, "g_D", f, s[0], s[1], s[2], dbuf, 0);
+            if (rc != ECMG_OK) { dfree(dbuf); return rc; }
+            launch_scatter_face(g, f, dbuf, L.x, c->stream);
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            dfree(dbuf);
+        }
+        const double *al[6];
+        for (int f = 0; f < 6; ++f) al[f] = L.alpha[f];
+        launch_dinv(g, L.beta, al, L.dinv, c->stream);
+        // ||f_h||: b = F - A x0 on free nodes (x0 = g_D on Dirichlet nodes, 0 elsewhere)
+        StencilArgs<double> a = stencil_args(c, L);
+        a.v = L.x;
+        a.q = c->q;
+        launch_stencil<double>(MODE_APPLY, a, c->stream);
+        launch_rhs_norm(g, L.F, c->q, L.x, c->partials, c->counters + 2, c->dres, c->stream);
+        HIPCHK(c, hipGetLastError());
+        HIPCHK(c, hipMemcpyAsync(c->hres, c->dres, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        L.nf = std::sqrt(c->hres[1]);
+    }
+    c->ready = true;
+    c->solved = false;
+    return ECMG_OK;
+}
+
+static int solve_impl(ecmg_ctx *c, double rel_tol, const int32_t *fixed, ecmg_level_info *info) {
+    if (!c) return fail(nullptr, ECMG_EINVAL, "ctx is NULL");
+    if (!c->ready) return fail(c, ECMG_ESTATE, "ecmg_solve before ecmg_setup");
+    if (!fixed && !(rel_tol >= 0.0)) return fail(c, ECMG_EINVAL, "rel_tol = %g must be >= 0", rel_tol);
+    int worst = ECMG_OK;
+    for (int l = 0; l < c->nlev; ++l) {
+        Level &L = c->lv[l];
+        ecmg_level_info li{};
+        li.level = l;
+        li.nx = L.g.nx;
+        li.ny = L.g.ny;
+        li.nz = L.g.nz;
+        HIPCHK(c, hipEventRecord(c->ev0, c->stream));
+        int rc;
+        if (l < 2) {
+            launch_zero_free(L.g, L.x, c->stream);
+            rc = run_jcg(c, l, c->opt.dsolve_tol * L.nf, 100000, -1, &li);
+            if (rc == ECMG_ENOTCONV) rc = ECMG_OK;  // DSOLVE: the iterate at the cap is kept
+        } else {
+            CHK(do_exp_finite(c, l));
+            rc = run_jcg(c, l, rel_tol * L.nf, c->opt.max_iter, fixed ? fixed[l] : -1, &li);
+        }
+        HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+        HIPCHK(c, hipEventSynchronize(c->ev1));
+        float ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+        li.ms = ms;
+        if (info) info[l] = li;
+        if (rc == ECMG_EDEVICE) return rc;
+        if (rc != ECMG_OK && worst == ECMG_OK) worst = rc;
+    }
+    c->solved = true;
+    return worst;
+}
+
+int ecmg_solve(ecmg_ctx *c, double rel_tol, ecmg_level_info *info) { return solve_impl(c, rel_tol, nullptr, info); }
+
+int ecmg_solve_fixed(ecmg_ctx *c, const int32_t *iters, ecmg_level_info *info) {
+    if (!iters) return fail(c, ECMG_EINVAL, "iters is NULL");
+    return solve_impl(c, 0.0, iters, info);
+}
+
+static int check_level(ecmg_ctx *c, int32_t *level, int min_level) {
+    if (!c) return fail(nullptr, ECMG_EINVAL, "ctx is NULL");
+    if (!c->ready) return fail(c, ECMG_ESTATE, "call before ecmg_setup");
+    if (*level < 0) *level = c->nlev - 1;
+    if (*level < min_level || *level >= c->nlev)
+        return fail(c, ECMG_EINVAL, "level %d out of range [%d, %d)", *level, min_level, c->nlev);
+    return ECMG_OK;
+}
+
+int ecmg_extrapolate(ecmg_ctx *c, int32_t level, double *host_out) {
+    CHK(check_level(c, &level, 1));
+    CHK(do_exp_true(c, level));
+    CHK(rec_flush(c, 1));
+    Level &L = c->lv[level];
+    if (host_out) {
+        HIPCHK(c, hipMemcpyAsync(host_out, L.Ut, 8 * (size_t)L.g.nnodes, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    return ECMG_OK;
+}
+
+int ecmg_prolongate(ecmg_ctx *c, int32_t level) {
+    CHK(check_level(c, &level, 2));
+    CHK(do_exp_finite(c, level));
+    CHK(rec_flush(c, 1));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return ECMG_OK;
+}
+
+int ecmg_jcg(ecmg_ctx *c, int32_t level, double rel_tol, int32_t fixed_iters, ecmg_level_info *info) {
+    CHK(check_level(c, &level, 0));
+    Level &L = c->lv[level];
+    ecmg_level_info li{};
+    li.level = level;
+    li.nx = L.g.nx;
+    li.ny = L.g.ny;
+    li.nz = L.g.nz;
+    const int rc = run_jcg(c, level, rel_tol * L.nf, c->opt.max_iter, fixed_iters, &li);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (info) *info = li;
+    return rc;
+}
+
+static double *vec_ptr(ecmg_ctx *c, Level &L, int which) {
+    switch (which) {
+        case ECMG_VEC_U: return L.x;
+        case ECMG_VEC_W: return L.W;
+        case ECMG_VEC_UTILDE: return L.Ut;
+        case ECMG_VEC_F: return L.F;
+        case ECMG_VEC_DINV: return L.dinv;
+        default: return nullptr;
+    }
+}
+
+int ecmg_get(ecmg_ctx *c, int32_t level, int32_t which, double *host_out) {
+    CHK(check_level(c, &level, 0));
+    if (!host_out) return fail(c, ECMG_EINVAL, "host_out is NULL");
+    Level &L = c->lv[level];
+    double *d = vec_ptr(c, L, which);
+    if (!d) return fail(c, ECMG_EINVAL, "vector %d is not available on level %d", which, level);
+    HIPCHK(c, hipMemcpyAsync(host_out, d, 8 * (size_t)L.g.nnodes, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return ECMG_OK;
+}
+
+int ecmg_set(ecmg_ctx *c, int32_t level, int32_t which, const double *host_in) {
+    CHK(check_level(c, &level, 0));
+    if (!host_in) return fail(c, ECMG_EINVAL, "host_in is NULL");
+    Level &L = c->lv[level];
+    if (which == ECMG_VEC_UTILDE && !L.Ut) CHK(dalloc_n(c, &L.Ut, L.g.nnodes));
+    if (which == ECMG_VEC_W && !L.W) CHK(dalloc_n(c, &L.W, L.g.nnodes));
+    double *d = vec_ptr(c, L, which);
+    if (!d || which == ECMG_VEC_F || which == ECMG_VEC_DINV)
+        return fail(c, ECMG_EINVAL, "vector %d cannot be set", which);
+    HIPCHK(c, hipMemcpyAsync(d, host_in, 8 * (size_t)L.g.nnodes, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return ECMG_OK;
+}
+
+int ecmg_device_view(ecmg_ctx *c, int32_t level, int32_t which, void **dptr, int64_t dims[3]) {
+    CHK(check_level(c, &level, 0));
+    if (!dptr) return fail(c, ECMG_EINVAL, "dptr is NULL");
+    Level &L = c->lv[level];
+    double *d = vec_ptr(c, L, which);
+    if (!d) return fail(c, ECMG_EINVAL, "vector %d is not available on level %d", which, level);
+    *dptr = d;
+    if (dims) {
+        dims[0] = L.g.nx + 1;
+        dims[1] = L.g.ny + 1;
+        dims[2] = L.g.nz + 1;
+    }
+    return ECMG_OK;
+}
+
+int ecmg_apply(ecmg_ctx *c, int32_t level, const double *host_in, double *host_out) {
+    CHK(check_level(c, &level, 0));
+    if (!host_in || !host_out) return fail(c, ECMG_EINVAL, "NULL buffer");
+    Level &L = c->lv[level];
+    HIPCHK(c, hipMemcpyAsync(c->p0, host_in, 8 * (size_t)L.g.nnodes, hipMemcpyHostToDevice, c->stream));
+    StencilArgs<double> a = stencil_args(c, L);
+    a.v = c->p0;
+    a.q = c->q;
+    launch_stencil<double>(MODE_APPLY, a, c->stream);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(host_out, c->q, 8 * (size_t)L.g.nnodes, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return ECMG_OK;
+}
+
+int ecmg_norms(ecmg_ctx *c, int32_t level, int32_t which, int32_t minus_which, const double *minus_host,
+               double out[2]) {
+    CHK(check_level(c, &level, 0));
+    if (!out) return fail(c, ECMG_EINVAL, "out is NULL");
+    Level &L = c->lv[level];
+    const double *a = vec_ptr(c, L, which);
+    if (!a) return fail(c, ECMG_EINVAL, "vector %d is not available on level %d", which, level);
+    const double *b = nullptr;
+    if (minus_which != ECMG_VEC_NONE) {
+        b = vec_ptr(c, L, minus_which);
+        if (!b) return fail(c, ECMG_EINVAL, "vector %d is not available on level %d", minus_which, level);
+    }
+    const double *h = nullptr;
+    if (minus_host) {
+        HIPCHK(c, hipMemcpyAsync(c->q, minus_host, 8 * (size_t)L.g.nnodes, hipMemcpyHostToDevice, c->stream));
+        h = c->q;
+    }
+    launch_norms(L.g.nnodes, a, b, h, c->partials, c->counters + 2, c->dres, c->stream);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(c->hres, c->dres, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    out[0] = c->hres[0];
+    out[1] = std::sqrt(c->hres[1] / (double)L.g.nnodes);
+    return ECMG_OK;
+}
+
+int ecmg_level_dims(ecmg_ctx *c, int32_t level, int64_t n[3]) {
+    CHK(check_level(c, &level, 0));
+    if (!n) return fail(c, ECMG_EINVAL, "n is NULL");
+    n[0] = c->lv[level].g.nx;
+    n[1] = c->lv[level].g.ny;
+    n[2] = c->lv[level].g.nz;
+    return ECMG_OK;
+}
+
+int ecmg_kernel_times(ecmg_ctx *c, int32_t level, int32_t k, double out[2]) {
+    CHK(check_level(c, &level, 0));
+    if (k < 0 || k >= 8 || !out) return fail(c, ECMG_EINVAL, "bad kernel class %d", k);
+    out[0] = c->lv[level].kt_ms[k];
+    out[1] = (double)c->lv[level].kt_n[k];
+    return ECMG_OK;
+}
+
+int ecmg_reset_kernel_times(ecmg_ctx *c) {
+    if (!c) return fail(nullptr, ECMG_EINVAL, "ctx is NULL");
+    for (auto &L : c->lv)
+        for (int k = 0; k < 8; ++k) {
+            L.kt_ms[k] = 0.0;
+            L.kt_n[k] = 0;
+        }
+    return ECMG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,147 @@
+// Internal declarations of the MI355X ECMG_jcg library: level geometry, device
+// argument blocks, kernel launchers.  Host code and kernels include this; the
+// public interface is include/ecmg.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "ecmg.h"
+
+namespace ecmg {
+
+// ---- stencil tile shape ------------------------------------------------------
+// A block of TX x TY threads owns a TX x (TY*RY) tile of an x-y node plane and
+// marches through KZ planes in z.  Lanes run along x (one 64-wide wavefront per
+// row: coalesced, each z-plane contiguous in HBM); each wave handles RY rows.
+constexpr int TX = 64;
+constexpr int TY = 4;
+constexpr int RY = 4;
+constexpr int TYT = TY * RY;          // tile height in nodes
+constexpr int NT = TX * TY;           // threads per block
+constexpr int NXCD = 8;               // MI355X: 8 XCDs, each with its own L2
+
+// Geometry of one level, passed to kernels by value.
+struct Geom {
+    int nx, ny, nz;                   // elements per axis
+    int sx, sy;                       // nodes per row / rows per plane (nx+1, ny+1)
+    int64_t nnodes;                   // (nx+1)(ny+1)(nz+1)
+    double h[3];
+    int ft[6];                        // face types (0 Dirichlet, 1 Robin)
+    // Q1 stiffness entry / beta between local nodes differing on the axes of
+    // mask m (bit 0 = x, 1 = y, 2 = z): tensor products of the 1-D stiffness
+    // (1,-1)/h and mass h(1/3, 1/6) (Section 2, bilinear form a(u,v)).
+    double C[8];
+    // Robin face mass / alpha for face f between face nodes differing on c in-
+    // face axes: hp*hq*(1/9, 1/18, 1/36).
+    double M[6][3];
+};
+
+// Device-side JCG state: scalars of the current iteration and stop control.
+struct JcgScalars {
+    double rho;        // r.z of the current residual
+    double rr;         // ||r||^2
+    double alpha;      // step length of the last completed pass A
+    double beta;       // rho_k / rho_{k-1} for the next search direction
+    double pq;         // p.q of the last pass A
+    double tol;        // eps * ||f_h|| (stop when !(||r|| > tol))
+    int iter;          // completed iterations
+    int done;          // 0 running, 1 converged, 2 max_iter, 3 breakdown
+    int max_iter;
+    int fixed;         // >= 0: run exactly this many iterations
+    int pending;       // x += alpha p of the last iteration still to apply
+    int pad;
+};
+
+enum { DONE_RUNNING = 0, DONE_CONVERGED = 1, DONE_MAXITER = 2, DONE_BREAKDOWN = 3 };
+
+// Arguments of the tiled stencil kernels (apply, JCG init, JCG pass A).
+template <typename T>
+struct StencilArgs {
+    Geom g;
+    int ntx, nty, nkz, KZ;            // tiles in x, y; z-chunks and planes per chunk
+    const T *beta;                    // element coefficients
+    const T *alpha[6];                // Robin face-element coefficients (or null)
+    const T *v;                       // apply/init: input vector
+    T *q;                             // apply: output; pass A: q = A p
+    const T *F;                       // init: load vector
+    const T *dinv;                    // init / pass A: 1/diag, 0 on Dirichlet nodes
+    T *r;                             // init: output residual; pass A: input
+    double *x;                        // pass A: iterate (deferred update)
+    T *p0, *p1;                       // pass A: search directions (ping-pong)
+    JcgScalars *sc;
+    double *partials;                 // per-block partial sums
+    unsigned *counter;                // last-block counter
+};
+
+template <typename T>
+struct PassBArgs {
+    int64_t n;
+    T *r;
+    const T *q;
+    const T *dinv;
+    JcgScalars *sc;
+    double *partials;
+    unsigned *counter;
+};
+
+// Modes of the tiled stencil kernel.
+enum { MODE_APPLY = 0, MODE_INIT = 1, MODE_PASSA = 2 };
+
+// ---- host-side level and context -------------------------------------------------
+struct Level {
+    Geom g;
+    double lo[3];
+    int64_t nelem;
+    int64_t nface[6];                 // face elements per face (0 if not Robin)
+    double *beta = nullptr;           // [nelem]
+    double *alpha[6] = {};            // Robin faces
+    double *F = nullptr;              // load vector
+    double *x = nullptr;              // u_l (g_D on Dirichlet nodes)
+    double *dinv = nullptr;
+    double *W = nullptr;              // EXP_finite output (optional)
+    double *Ut = nullptr;             // EXP_true output (lazy)
+    float *beta32 = nullptr;          // mixed precision copies (lazy)
+    float *alpha32[6] = {};
+    float *dinv32 = nullptr;
+    double nf = 0.0;                  // ||f_h||_2 of the stopping test
+    // timing accumulators per kernel class
+    double kt_ms[8] = {};
+    int64_t kt_n[8] = {};
+};
+
+struct Ctx;
+
+// ---- launchers (kernels.hip / extrap.hip / setup.hip) ---------------------------
+int stencil_blocks(const Geom &g, int KZ, int *ntx, int *nty, int *nkz);
+
+template <typename T>
+void launch_stencil(int mode, const StencilArgs<T> &a, hipStream_t s);
+template <typename T>
+void launch_passB(const PassBArgs<T> &a, int nblocks, hipStream_t s);
+void launch_final_x(const Geom &g, double *x, const double *p0, const double *p1, const JcgScalars *sc,
+                    hipStream_t s);
+void launch_jcg_reset(JcgScalars *sc, double tol, int max_iter, int fixed, hipStream_t s);
+
+void launch_exp_finite(const Geom &gf, const double *U1, const double *U0, double *x, double *W, int variant,
+                       hipStream_t s);
+void launch_exp_true(const Geom &gf, const double *U1, const double *U0, double *Ut, hipStream_t s);
+
+void launch_fill(double *p, int64_t n, double v, hipStream_t s);
+void launch_zero_free(const Geom &g, double *x, hipStream_t s);
+void launch_load_volume(const Geom &g, int e0, int e1, const double *fg, double *F, hipStream_t s);
+void launch_load_face(const Geom &g, int face, const double *gR, double *F, hipStream_t s);
+void launch_scatter_face(const Geom &g, int face, const double *vals, double *x, hipStream_t s);
+void launch_dinv(const Geom &g, const double *beta, const double *const *alpha, double *dinv, hipStream_t s);
+void launch_rhs_norm(const Geom &g, const double *F, const double *Ax0, const double *x0, double *partials,
+                     unsigned *counter, double *out, hipStream_t s);
+void launch_norms(int64_t n, const double *a, const double *b, const double *c, double *partials,
+                  unsigned *counter, double *out, hipStream_t s);
+
+// Block count of the 1-D reduction kernels (fixed so reductions are deterministic).
+int reduce_blocks(int64_t n);
+
+}  // namespace ecmg
