@@ -1,0 +1,243 @@
+#!/usr/bin/env python3
+"""ECMG_jcg benchmark on one MI355X.
+
+One step = the whole hot path on the workload: Algorithm 4 (DSOLVE on the two
+coarsest grids, EXP_finite + JCG on every finer grid) plus the final EXP_true on
+the finest grid, with every input already resident in HBM (setup is timed
+separately).  value = finest-grid unknowns (all nodes, as the paper counts them)
+per second of wall time of that step.
+
+Prints one JSON line.  Kernel durations for the roofline come from HIP events
+recorded by the library on its own stream around each launch inside the timed
+region; algorithmic bytes per launch follow the per-node traffic model of each
+kernel.  The CPU baseline times the oracle on a bounded sample
+of the same workload (fewer levels) on the host cores.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "unknowns/s to 4th-order accuracy (FP64 vs mixed); JCG HBM GB/s; serve p50/p99"
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+KIND_NAMES = {0: "jcg_pass_a", 1: "jcg_pass_b", 2: "jcg_init", 3: "exp_finite", 4: "exp_true",
+              5: "jcg_pass_a_fp32", 6: "jcg_pass_b_fp32"}
+KERNEL_SYMBOL = {0: "k_stencil<double, 2>", 1: "k_passB<double>", 2: "k_stencil<double, 1>",
+                 3: "k_exp_finite", 4: "k_exp_true", 5: "k_stencil<float, 2>", 6: "k_passB<float>"}
+
+
+def workload(name):
+    import workloads
+    if name == "variable-beta-robin-513":
+        return (workloads.variable_beta_robin_cube(levels=7, eps=1e-8),
+                "variable-beta Robin cube, beta=1+0.5 sin(pi x)sin(pi y)sin(pi z), u=S+xyz, Dirichlet x-faces, "
+                "Robin alpha=1 elsewhere; 8^3 -> 512^3 elements (7 levels, 513^3 = 135,005,697 nodes); eps=1e-8")
+    if name == "smooth-dirichlet-33":
+        return (workloads.smooth_dirichlet_cube(levels=4, eps=1e-10),
+                "beta=1, u=exp(x+y+z), Dirichlet cube; 4^3 -> 32^3 elements (35,937 nodes); eps=1e-10")
+    if name == "high-contrast-513x257x257":
+        return (workloads.high_contrast_singular_box(levels=6, eps=1e-8),
+                "box [0,2]x[0,1]^2, beta=exp(4 sin 2pi x cos 2pi y), u=r^(2/3), Dirichlet; 16x8x8 -> 512x256x256 "
+                "(6 levels, 33,883,137 nodes); eps=1e-8")
+    raise SystemExit("unknown workload %s" % name)
+
+
+def algorithmic_bytes(kind, n, e, n1, n0):
+    """HBM bytes a launch must move at minimum (8-byte values; n nodes, e
+    elements of the level; n1, n0 nodes of the two coarser levels)."""
+    if kind == 0:
+        return 8 * (6 * n + e)          # read r, p_old, x, beta; write p, q, x
+    if kind == 1:
+        return 8 * 4 * n                # read r, q, 1/D; write r
+    if kind == 2:
+        return 8 * (4 * n + e)          # read x, F, 1/D, beta; write r
+    if kind == 3:
+        return 8 * (2 * n + n1 + n0)    # write x and W; read u_{l-1}, u_{l-2}
+    if kind == 4:
+        return 8 * (2 * n + n1)         # read u_l, u_{l-1}; write U~
+    if kind == 5:
+        return 4 * (6 * n + e)
+    if kind == 6:
+        return 4 * 4 * n
+    return 0
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("jcg_kernels.hip", "ecmg_internal.h"):
+        with open(os.path.join(ROOT, "paper_1506_02983_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kind_name, level_nodes):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    k = t.get("kernels", {}).get(kind_name)
+    if not k or int(k.get("nodes", -1)) != int(level_nodes):
+        return None
+    return float(k["bytes_per_launch"])
+
+
+def exact_on_device(problem, n):
+    import torch
+    lo, hi = problem.lo, problem.hi
+    ax = [lo[d] + torch.arange(n[d] + 1, dtype=torch.float64, device="cuda") * ((hi[d] - lo[d]) / n[d])
+          for d in range(3)]
+    v = problem.u(ax[0][None, None, :], ax[1][None, :, None], ax[2][:, None, None], -1)
+    return torch.as_tensor(v, dtype=torch.float64, device="cuda").expand(n[2] + 1, n[1] + 1, n[0] + 1).contiguous()
+
+
+def cpu_baseline(problem, levels, precision_interp=0):
+    import oracle
+    p = problem.with_(levels=levels)
+    lvls = [oracle.discretize(p, l) for l in range(levels)]
+    t0 = time.perf_counter()
+    res = oracle.cascade(p, levels=lvls, errors=False, keep_vectors=False, variant=precision_interp)
+    dt = time.perf_counter() - t0
+    nodes = p.nodes_at(levels - 1)
+    return {"value": nodes / dt, "unit": "unknowns/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": "same workload on %d levels (finest %s elements, %d nodes): oracle DSOLVE + EXP_finite + "
+                      "JCG + EXP_true region, %.1f s, iterations %s" % (
+                          levels, "x".join(map(str, p.n_at(levels - 1))), nodes, dt, [r.iters for r in res])}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="variable-beta-robin-513")
+    ap.add_argument("--eps", type=float, default=None)
+    ap.add_argument("--interp", type=int, default=0)
+    ap.add_argument("--host-fields", action="store_true", help="sample fields with numpy on the host")
+    ap.add_argument("--cpu-levels", type=int, default=6, help="levels of the oracle CPU-baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-errors", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (the solver is single-device); "
+              "--gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1506_02983_amd as E
+
+    problem, desc = workload(args.workload)
+    eps = problem.eps if args.eps is None else args.eps
+    torch.cuda.init()
+    L = problem.levels - 1
+    n = problem.n_at(L)
+    nodes = problem.nodes_at(L)
+    elems = n[0] * n[1] * n[2]
+
+    s = E.Solver(interp=args.interp, timing=True)
+    t0 = time.perf_counter()
+    s.setup(problem, device_fields=not args.host_fields)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    print("bench: setup %.2f s (%s fields)" % (setup_s, "host" if args.host_fields else "device"),
+          file=sys.stderr, flush=True)
+
+    for _ in range(args.warmup):
+        s.solve(eps)
+        s.extrapolate(L, out=False)
+    torch.cuda.synchronize()
+    s.reset_kernel_times()
+    infos = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        infos = s.solve(eps)
+        s.extrapolate(L, out=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = 1e3 * dt / args.steps
+    value = nodes * args.steps / dt
+    print("bench: %.3f ms/step, %.3e unknowns/s" % (ms_per_step, value), file=sys.stderr, flush=True)
+
+    # per-kernel times inside the timed region
+    kernels = []
+    for l in range(problem.levels):
+        nl = problem.n_at(l)
+        nn = problem.nodes_at(l)
+        ee = nl[0] * nl[1] * nl[2]
+        n1 = problem.nodes_at(l - 1) if l >= 1 else 0
+        n0 = problem.nodes_at(l - 2) if l >= 2 else 0
+        for k in range(7):
+            ms, cnt = s.kernel_times(l, k)
+            if cnt == 0:
+                continue
+            b = algorithmic_bytes(k, nn, ee, n1, n0)
+            kernels.append({"level": l, "kernel": KIND_NAMES[k], "kind": k, "launches": cnt, "total_ms": ms,
+                            "avg_us": 1e3 * ms / cnt, "bytes_per_launch": b,
+                            "gbs": b / (ms / cnt * 1e-3) / 1e9, "nodes": nn})
+    dom = max(kernels, key=lambda r: r["total_ms"])
+    achieved = dom["gbs"]
+    traffic = measured_traffic(dom["kernel"], dom["nodes"])
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": KERNEL_SYMBOL[dom["kind"]], "level": dom["level"], "nodes": dom["nodes"],
+                "launches": dom["launches"], "avg_us": round(dom["avg_us"], 2),
+                "bytes_per_launch": dom["bytes_per_launch"]}
+    jcg_fin = [r for r in kernels if r["level"] == L and r["kind"] in (0, 1)]
+    jcg_gbs = None
+    if jcg_fin:
+        tb = sum(r["bytes_per_launch"] * r["launches"] for r in jcg_fin)
+        tt = sum(r["total_ms"] for r in jcg_fin) * 1e-3
+        jcg_gbs = tb / tt / 1e9
+
+    errors = {}
+    if not args.no_errors:
+        for l in (L - 1, L):
+            ue = exact_on_device(problem, problem.n_at(l))
+            errors["U_max_L%d" % l], errors["U_l2_L%d" % l] = s.norms(l, E.VEC_U, minus=ue)
+            s.extrapolate(l, out=False)
+            errors["Ut_max_L%d" % l], errors["Ut_l2_L%d" % l] = s.norms(l, E.VEC_UTILDE, minus=ue)
+            del ue
+        errors["U_order_max"] = math.log2(errors["U_max_L%d" % (L - 1)] / errors["U_max_L%d" % L])
+        errors["Ut_order_max"] = math.log2(errors["Ut_max_L%d" % (L - 1)] / errors["Ut_max_L%d" % L])
+        torch.cuda.empty_cache()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(problem.with_(eps=eps), min(args.cpu_levels, problem.levels), args.interp)
+        print("bench: cpu baseline %.3e unknowns/s on %d threads" % (cpu["value"], cpu["cores"]),
+              file=sys.stderr, flush=True)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "unknowns/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic (closed-form manufactured solution)",
+        "config": {"workload": desc, "levels": problem.levels, "finest_elements": list(n), "finest_nodes": nodes,
+                   "eps": eps, "precision": "fp64",
+                   "interp": "lagrange27" if args.interp else "serendipity20", "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "jcg_hbm_gbs_finest": jcg_gbs,
+        "setup_s": setup_s,
+        "levels": [{"level": i["level"], "n": [i["nx"], i["ny"], i["nz"]], "iters": i["iters"],
+                    "rre": i["rre"], "ms": i["ms"]} for i in infos],
+        "errors": errors,
+        "kernels": [{k: (round(v, 3) if isinstance(v, float) else v) for k, v in r.items()} for r in kernels],
+    }
+    s.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

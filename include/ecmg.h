@@ -187,16 +187,22 @@ int ecmg_apply(ecmg_ctx *ctx, int32_t level, const double *host_in, double *host
 int ecmg_get(ecmg_ctx *ctx, int32_t level, int32_t which, double *host_out);
 int ecmg_set(ecmg_ctx *ctx, int32_t level, int32_t which, const double *host_in);
 
-/* Device pointer of a vector (FP64, node layout above) for zero-copy use.
- * dims receives (nx+1, ny+1, nz+1).  The pointer stays valid until the next
- * ecmg_setup or ecmg_destroy. */
-int ecmg_device_view(ecmg_ctx *ctx, int32_t level, int32_t which, void **dptr, int64_t dims[3]);
+/* Device pointer of a vector (FP64) for zero-copy use.  On the device, rows
+ * are padded: node (i,j,k) is at i + row_pitch*(j + (ny+1)*k) with row_pitch
+ * >= nx+1 (a multiple of 16, so rows start on 128-byte lines); padding entries
+ * are zero.  dims receives (nx+1, ny+1, nz+1), *row_pitch (if not NULL) the
+ * pitch in elements.  The pointer stays valid until the next ecmg_setup or
+ * ecmg_destroy. */
+int ecmg_device_view(ecmg_ctx *ctx, int32_t level, int32_t which, void **dptr, int64_t dims[3],
+                     int64_t *row_pitch);
 
 /* Error norms of the tables of Section 5 on a level: v = vec[which]
- * - vec[minus_which] (ECMG_VEC_NONE = 0) - minus_host (NULL = 0);
- * out[0] = max |v|, out[1] = (sum v^2 / N)^(1/2) over all N nodes. */
+ * - vec[minus_which] (ECMG_VEC_NONE = 0) - minus (NULL = 0), where minus is a
+ * node array in host memory, or in device memory when minus_on_device != 0;
+ * out[0] = max |v|, out[1] = (sum v^2 / N)^(1/2) over all N nodes (the tables'
+ * L2 norm). */
 int ecmg_norms(ecmg_ctx *ctx, int32_t level, int32_t which, int32_t minus_which,
-               const double *minus_host, double out[2]);
+               const double *minus, int32_t minus_on_device, double out[2]);
 
 /* Elements per axis of a level. */
 int ecmg_level_dims(ecmg_ctx *ctx, int32_t level, int64_t n[3]);

@@ -81,6 +81,13 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError("libecmg.so not built at %s: run __graft_entry__.build()" % path)
+    # torch bundles its own HIP runtime.  Load it first so that libecmg.so binds
+    # to the same runtime (its libamdhip64.so.7 dependency is then already
+    # resolved): one process, one HIP runtime, shared device memory and streams.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(path)
     P, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
     L.ecmg_default_options.argtypes = [ctypes.POINTER(Options)]
@@ -95,8 +102,8 @@ def load_library(path: str = LIB_PATH):
     L.ecmg_apply.argtypes = [P, i32, P, P]
     L.ecmg_get.argtypes = [P, i32, i32, P]
     L.ecmg_set.argtypes = [P, i32, i32, P]
-    L.ecmg_device_view.argtypes = [P, i32, i32, ctypes.POINTER(P), P]
-    L.ecmg_norms.argtypes = [P, i32, i32, i32, P, P]
+    L.ecmg_device_view.argtypes = [P, i32, i32, ctypes.POINTER(P), P, P]
+    L.ecmg_norms.argtypes = [P, i32, i32, i32, P, i32, P]
     L.ecmg_level_dims.argtypes = [P, i32, P]
     L.ecmg_plan_bytes.argtypes = [ctypes.POINTER(ProblemC), i32, ctypes.POINTER(ctypes.c_size_t)]
     L.ecmg_kernel_times.argtypes = [P, i32, i32, P]
@@ -152,7 +159,9 @@ def _device_callback(fn):
 
     def cb(face, nx, ny, nz, px, py, pz, pout, stream, user):
         try:
-            with torch.cuda.stream(torch.cuda.ExternalStream(int(stream))):
+            torch.cuda.init()
+            dev = torch.device("cuda", torch.cuda.current_device())
+            with torch.cuda.stream(torch.cuda.ExternalStream(int(stream), device=dev)):
                 x = torch.as_tensor(_DevArray(px, (nx,)), device="cuda")
                 y = torch.as_tensor(_DevArray(py, (ny,)), device="cuda")
                 z = torch.as_tensor(_DevArray(pz, (nz,)), device="cuda")
@@ -320,16 +329,29 @@ class Solver:
         self._check(self.L.ecmg_set(self.h, int(level), int(which), v.ctypes.data))
 
     def device_view(self, level: int, which: int = VEC_U):
+        """(device pointer, (nx+1, ny+1, nz+1), row pitch in elements)."""
         ptr = ctypes.c_void_p()
         dims = (ctypes.c_int64 * 3)()
-        self._check(self.L.ecmg_device_view(self.h, int(level), int(which), ctypes.byref(ptr), dims))
-        return int(ptr.value), tuple(int(v) for v in dims)
+        pitch = ctypes.c_int64()
+        self._check(self.L.ecmg_device_view(self.h, int(level), int(which), ctypes.byref(ptr), dims,
+                                            ctypes.byref(pitch)))
+        return int(ptr.value), tuple(int(v) for v in dims), int(pitch.value)
 
-    def norms(self, level: int, which: int, minus_which: int = VEC_NONE, minus: Optional[np.ndarray] = None):
+    def norms(self, level: int, which: int, minus_which: int = VEC_NONE, minus=None):
+        """(max, RMS) of vec[which] - vec[minus_which] - minus; ``minus`` is a
+        numpy array or a contiguous float64 torch tensor on the device."""
         out = (ctypes.c_double * 2)()
-        m = None if minus is None else np.ascontiguousarray(minus, dtype=np.float64)
-        self._check(self.L.ecmg_norms(self.h, int(level), int(which), int(minus_which),
-                                      None if m is None else m.ctypes.data, out))
+        on_dev, ptr = 0, None
+        if minus is not None and type(minus).__module__.startswith("torch"):
+            import torch
+            assert minus.is_cuda and minus.dtype == torch.float64 and minus.is_contiguous()
+            assert minus.numel() == self.nodes(level if level >= 0 else self.levels - 1)
+            torch.cuda.current_stream().synchronize()   # the library works on its own stream
+            on_dev, ptr = 1, minus.data_ptr()
+        elif minus is not None:
+            m = np.ascontiguousarray(minus, dtype=np.float64)
+            ptr = m.ctypes.data
+        self._check(self.L.ecmg_norms(self.h, int(level), int(which), int(minus_which), ptr, on_dev, out))
         return float(out[0]), float(out[1])
 
     def kernel_times(self, level: int, kind: int) -> tuple:

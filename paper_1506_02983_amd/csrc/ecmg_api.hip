@@ -91,7 +91,23 @@ static int dalloc(ecmg_ctx *c, void **p, size_t bytes) {
 }
 template <typename T>
 static int dalloc_n(ecmg_ctx *c, T **p, int64_t n) {
-    return dalloc(c, (void **)p, sizeof(T) * (size_t)std::max<int64_t>(n, 1));
+    const size_t bytes = sizeof(T) * (size_t)std::max<int64_t>(n, 1);
+    int rc = dalloc(c, (void **)p, bytes);
+    if (rc != ECMG_OK) return rc;
+    // every array starts zeroed (row padding must read as zero); ordered on the
+    // library stream, which does not synchronise with the null stream
+    if (hipMemsetAsync(*p, 0, bytes, c->stream) != hipSuccess) return fail(c, ECMG_EDEVICE, "hipMemsetAsync failed");
+    return ECMG_OK;
+}
+
+// dense host node array <-> padded device node array of level geometry g
+static hipError_t copy_in(const Geom &g, double *dev, const double *host, hipStream_t s, hipMemcpyKind kind) {
+    return hipMemcpy2DAsync(dev, 8 * (size_t)g.sx, host, 8 * (size_t)(g.nx + 1), 8 * (size_t)(g.nx + 1),
+                            (size_t)g.sy * (g.nz + 1), kind, s);
+}
+static hipError_t copy_out(const Geom &g, double *host, const double *dev, hipStream_t s) {
+    return hipMemcpy2DAsync(host, 8 * (size_t)(g.nx + 1), dev, 8 * (size_t)g.sx, 8 * (size_t)(g.nx + 1),
+                            (size_t)g.sy * (g.nz + 1), hipMemcpyDeviceToHost, s);
 }
 static void dfree(void *p) {
     if (p) (void)hipFree(p);
@@ -105,9 +121,10 @@ static Geom make_geom(const ecmg_problem *p, int l, double lo[3]) {
     g.nx = p->n0[0] << l;
     g.ny = p->n0[1] << l;
     g.nz = p->n0[2] << l;
-    g.sx = g.nx + 1;
+    g.sx = row_pitch(g.nx + 1);
     g.sy = g.ny + 1;
     g.nnodes = (int64_t)g.sx * g.sy * (g.nz + 1);
+    g.nreal = (int64_t)(g.nx + 1) * g.sy * (g.nz + 1);
     const int n[3] = {g.nx, g.ny, g.nz};
     for (int d = 0; d < 3; ++d) {
         g.h[d] = (p->hi[d] - p->lo[d]) / (double)n[d];
@@ -281,8 +298,8 @@ static int rec_flush(ecmg_ctx *c, int iter_limit) {
 static StencilArgs<double> stencil_args(ecmg_ctx *c, Level &L) {
     StencilArgs<double> a{};
     a.g = L.g;
-    a.KZ = c->KZ;
-    stencil_blocks(L.g, c->KZ, &a.ntx, &a.nty, &a.nkz);
+    a.KZ = stencil_kz(L.g, c->KZ);
+    stencil_blocks(L.g, a.KZ, &a.ntx, &a.nty, &a.nkz);
     a.beta = L.beta;
     for (int f = 0; f < 6; ++f) a.alpha[f] = L.alpha[f];
     a.dinv = L.dinv;
@@ -296,6 +313,7 @@ static StencilArgs<double> stencil_args(ecmg_ctx *c, Level &L) {
 static int run_jcg(ecmg_ctx *c, int l, double tol_abs, int max_iter, int fixed, ecmg_level_info *info) {
     Level &L = c->lv[l];
     launch_jcg_reset(c->sc, tol_abs, max_iter, fixed, c->stream);
+    launch_zero_pad(L.g, c->r, c->q, c->p0, c->p1, c->stream);
     StencilArgs<double> a = stencil_args(c, L);
     a.v = L.x;
     a.r = c->r;
@@ -360,7 +378,9 @@ static int do_exp_finite(ecmg_ctx *c, int l) {
     Level &L = c->lv[l];
     size_t slot = 0;
     CHK(rec_begin(c, l, 3, 0, &slot));
-    launch_exp_finite(L.g, c->lv[l - 1].x, c->lv[l - 2].x, L.x, L.W, c->opt.interp, c->stream);
+    // phase 1 writes the 27-point nodal values on level l-1 into the q scratch
+    launch_exp_finite(L.g, c->lv[l - 1].g, c->lv[l - 1].x, c->lv[l - 2].x, c->q, L.x, L.W, c->opt.interp,
+                      c->stream);
     CHK(rec_end(c, slot));
     HIPCHK(c, hipGetLastError());
     return ECMG_OK;
@@ -465,7 +485,8 @@ int ecmg_create(const ecmg_options *opt, ecmg_ctx **out) {
         ecmg_destroy(c);
         return rc;
     }
-    if (hipMemset(c->counters, 0, 16 * sizeof(unsigned)) != hipSuccess ||
+    if (hipMemsetAsync(c->counters, 0, 16 * sizeof(unsigned), c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess ||
         hipHostMalloc((void **)&c->sc_host, sizeof(JcgScalars), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&c->hres, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
         hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
@@ -563,7 +584,7 @@ int ecmg_setup(ecmg_ctx *c, const ecmg_problem *p) {
         for (int l = 0; l < p->levels; ++l) {
             Geom g = make_geom(p, l, lo);
             int a, b, d;
-            pn = std::max<int64_t>(pn, 2 * (int64_t)stencil_blocks(g, c->KZ, &a, &b, &d));
+            pn = std::max<int64_t>(pn, 2 * (int64_t)stencil_blocks(g, stencil_kz(g, c->KZ), &a, &b, &d));
         }
         c->partials_n = pn;
         CHK(dalloc_n(c, &c->partials, pn));
@@ -733,7 +754,7 @@ int ecmg_extrapolate(ecmg_ctx *c, int32_t level, double *host_out) {
     CHK(rec_flush(c, 1));
     Level &L = c->lv[level];
     if (host_out) {
-        HIPCHK(c, hipMemcpyAsync(host_out, L.Ut, 8 * (size_t)L.g.nnodes, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, copy_out(L.g, host_out, L.Ut, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }
     return ECMG_OK;
@@ -778,7 +799,7 @@ int ecmg_get(ecmg_ctx *c, int32_t level, int32_t which, double *host_out) {
     Level &L = c->lv[level];
     double *d = vec_ptr(c, L, which);
     if (!d) return fail(c, ECMG_EINVAL, "vector %d is not available on level %d", which, level);
-    HIPCHK(c, hipMemcpyAsync(host_out, d, 8 * (size_t)L.g.nnodes, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, copy_out(L.g, host_out, d, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return ECMG_OK;
 }
@@ -792,12 +813,13 @@ int ecmg_set(ecmg_ctx *c, int32_t level, int32_t which, const double *host_in) {
     double *d = vec_ptr(c, L, which);
     if (!d || which == ECMG_VEC_F || which == ECMG_VEC_DINV)
         return fail(c, ECMG_EINVAL, "vector %d cannot be set", which);
-    HIPCHK(c, hipMemcpyAsync(d, host_in, 8 * (size_t)L.g.nnodes, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, copy_in(L.g, d, host_in, c->stream, hipMemcpyHostToDevice));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return ECMG_OK;
 }
 
-int ecmg_device_view(ecmg_ctx *c, int32_t level, int32_t which, void **dptr, int64_t dims[3]) {
+int ecmg_device_view(ecmg_ctx *c, int32_t level, int32_t which, void **dptr, int64_t dims[3],
+                     int64_t *row_pitch_out) {
     CHK(check_level(c, &level, 0));
     if (!dptr) return fail(c, ECMG_EINVAL, "dptr is NULL");
     Level &L = c->lv[level];
@@ -809,6 +831,7 @@ int ecmg_device_view(ecmg_ctx *c, int32_t level, int32_t which, void **dptr, int
         dims[1] = L.g.ny + 1;
         dims[2] = L.g.nz + 1;
     }
+    if (row_pitch_out) *row_pitch_out = L.g.sx;
     return ECMG_OK;
 }
 
@@ -816,19 +839,19 @@ int ecmg_apply(ecmg_ctx *c, int32_t level, const double *host_in, double *host_o
     CHK(check_level(c, &level, 0));
     if (!host_in || !host_out) return fail(c, ECMG_EINVAL, "NULL buffer");
     Level &L = c->lv[level];
-    HIPCHK(c, hipMemcpyAsync(c->p0, host_in, 8 * (size_t)L.g.nnodes, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, copy_in(L.g, c->p0, host_in, c->stream, hipMemcpyHostToDevice));
     StencilArgs<double> a = stencil_args(c, L);
     a.v = c->p0;
     a.q = c->q;
     launch_stencil<double>(MODE_APPLY, a, c->stream);
     HIPCHK(c, hipGetLastError());
-    HIPCHK(c, hipMemcpyAsync(host_out, c->q, 8 * (size_t)L.g.nnodes, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, copy_out(L.g, host_out, c->q, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return ECMG_OK;
 }
 
-int ecmg_norms(ecmg_ctx *c, int32_t level, int32_t which, int32_t minus_which, const double *minus_host,
-               double out[2]) {
+int ecmg_norms(ecmg_ctx *c, int32_t level, int32_t which, int32_t minus_which, const double *minus,
+               int32_t minus_on_device, double out[2]) {
     CHK(check_level(c, &level, 0));
     if (!out) return fail(c, ECMG_EINVAL, "out is NULL");
     Level &L = c->lv[level];
@@ -840,16 +863,17 @@ int ecmg_norms(ecmg_ctx *c, int32_t level, int32_t which, int32_t minus_which, c
         if (!b) return fail(c, ECMG_EINVAL, "vector %d is not available on level %d", minus_which, level);
     }
     const double *h = nullptr;
-    if (minus_host) {
-        HIPCHK(c, hipMemcpyAsync(c->q, minus_host, 8 * (size_t)L.g.nnodes, hipMemcpyHostToDevice, c->stream));
+    if (minus) {   // dense node array (host or device) into the padded layout
+        HIPCHK(c, copy_in(L.g, c->q, minus, c->stream,
+                          minus_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice));
         h = c->q;
     }
-    launch_norms(L.g.nnodes, a, b, h, c->partials, c->counters + 2, c->dres, c->stream);
+    launch_norms(L.g, a, b, h, c->partials, c->counters + 2, c->dres, c->stream);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipMemcpyAsync(c->hres, c->dres, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     out[0] = c->hres[0];
-    out[1] = std::sqrt(c->hres[1] / (double)L.g.nnodes);
+    out[1] = std::sqrt(c->hres[1] / (double)L.g.nreal);
     return ECMG_OK;
 }
 

@@ -17,18 +17,35 @@ namespace ecmg {
 // A block of TX x TY threads owns a TX x (TY*RY) tile of an x-y node plane and
 // marches through KZ planes in z.  Lanes run along x (one 64-wide wavefront per
 // row: coalesced, each z-plane contiguous in HBM); each wave handles RY rows.
+#ifndef ECMG_TILE_TY
+#define ECMG_TILE_TY 16
+#endif
+#ifndef ECMG_TILE_RY
+#define ECMG_TILE_RY 1
+#endif
+#ifndef ECMG_PREFETCH
+#define ECMG_PREFETCH 1
+#endif
 constexpr int TX = 64;
-constexpr int TY = 4;
-constexpr int RY = 4;
+constexpr int TY = ECMG_TILE_TY;
+constexpr int RY = ECMG_TILE_RY;
 constexpr int TYT = TY * RY;          // tile height in nodes
 constexpr int NT = TX * TY;           // threads per block
+constexpr int PF = ECMG_PREFETCH;     // z-steps between issuing a plane's loads and using them
 constexpr int NXCD = 8;               // MI355X: 8 XCDs, each with its own L2
 
 // Geometry of one level, passed to kernels by value.
+// Node arrays in HBM: node (i,j,k) at i + sx*(j + sy*k), rows padded to a
+// multiple of 16 doubles (128 bytes) so every tile row starts on a cache-line
+// boundary; padding entries (i > nx) hold zeros.
+constexpr int ROW_ALIGN = 16;
+__host__ __device__ inline int row_pitch(int nodes_x) { return (nodes_x + ROW_ALIGN - 1) / ROW_ALIGN * ROW_ALIGN; }
+
 struct Geom {
     int nx, ny, nz;                   // elements per axis
-    int sx, sy;                       // nodes per row / rows per plane (nx+1, ny+1)
-    int64_t nnodes;                   // (nx+1)(ny+1)(nz+1)
+    int sx, sy;                       // row pitch (>= nx+1, padded) / rows per plane (ny+1)
+    int64_t nnodes;                   // allocated entries sx*sy*(nz+1)
+    int64_t nreal;                    // nodes (nx+1)(ny+1)(nz+1)
     double h[3];
     int ft[6];                        // face types (0 Dirichlet, 1 Robin)
     // Q1 stiffness entry / beta between local nodes differing on the axes of
@@ -117,6 +134,7 @@ struct Ctx;
 
 // ---- launchers (kernels.hip / extrap.hip / setup.hip) ---------------------------
 int stencil_blocks(const Geom &g, int KZ, int *ntx, int *nty, int *nkz);
+int stencil_kz(const Geom &g, int kz_max);
 
 template <typename T>
 void launch_stencil(int mode, const StencilArgs<T> &a, hipStream_t s);
@@ -126,9 +144,10 @@ void launch_final_x(const Geom &g, double *x, const double *p0, const double *p1
                     hipStream_t s);
 void launch_jcg_reset(JcgScalars *sc, double tol, int max_iter, int fixed, hipStream_t s);
 
-void launch_exp_finite(const Geom &gf, const double *U1, const double *U0, double *x, double *W, int variant,
-                       hipStream_t s);
+void launch_exp_finite(const Geom &gf, const Geom &g1, const double *U1, const double *U0, double *V, double *x,
+                       double *W, int variant, hipStream_t s);
 void launch_exp_true(const Geom &gf, const double *U1, const double *U0, double *Ut, hipStream_t s);
+void launch_zero_pad(const Geom &g, double *a, double *b, double *c, double *d, hipStream_t s);
 
 void launch_fill(double *p, int64_t n, double v, hipStream_t s);
 void launch_zero_free(const Geom &g, double *x, hipStream_t s);
@@ -138,7 +157,7 @@ void launch_scatter_face(const Geom &g, int face, const double *vals, double *x,
 void launch_dinv(const Geom &g, const double *beta, const double *const *alpha, double *dinv, hipStream_t s);
 void launch_rhs_norm(const Geom &g, const double *F, const double *Ax0, const double *x0, double *partials,
                      unsigned *counter, double *out, hipStream_t s);
-void launch_norms(int64_t n, const double *a, const double *b, const double *c, double *partials,
+void launch_norms(const Geom &g, const double *a, const double *b, const double *c, double *partials,
                   unsigned *counter, double *out, hipStream_t s);
 
 // Block count of the 1-D reduction kernels (fixed so reductions are deterministic).

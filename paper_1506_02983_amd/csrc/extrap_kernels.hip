@@ -17,9 +17,13 @@
 // values.  For the serendipity form this equals eq. inter exactly, because the
 // serendipity interpolant is itself tri-quadratic and so is reproduced by
 // 27-node Lagrange interpolation of its own values; the tensor-product form
-// costs 39 multiply-adds per node instead of 20 three-dimensional shape
-// functions.  A fine node on a face shared by two coarse elements belongs to
-// the lower-index element (both give the same value up to rounding).
+// skips the vanishing 1-D weights instead of evaluating 20 three-dimensional
+// shape functions.  A fine node on a face shared by two coarse elements belongs
+// to the lower-index element (both give the same value up to rounding).
+//
+// The 27 nodal values sit on level l-1 nodes and each depends only on its own
+// edge, face or element, so phase 1 computes them once per level l-1 node (into
+// scratch) and phase 2 interpolates every fine node from them.
 #include "ecmg_internal.h"
 
 namespace ecmg {
@@ -42,120 +46,128 @@ __device__ __forceinline__ bool is_dir(const Geom &g, int i, int j, int k) {
            (k == 0 && g.ft[4] == ECMG_DIRICHLET) || (k == g.nz && g.ft[5] == ECMG_DIRICHLET);
 }
 
-__global__ void __launch_bounds__(256) k_exp_finite(const Geom gf, const double *__restrict__ U1,
-                                                    const double *__restrict__ U0, double *__restrict__ x,
-                                                    double *__restrict__ W, int variant) {
-    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= gf.nnodes) return;
-    const int i = (int)(id % gf.sx);
-    const int64_t t = id / gf.sx;
-    const int j = (int)(t % gf.sy);
-    const int k = (int)(t / gf.sy);
+// Phase 1 of EXP_finite, on the level l-1 grid (node (p,q,r), level l-2 nodes
+// at even indices): the 27-point nodal value V of the level l-2 element(s)
+// containing the node.  Every such value depends only on the node's own edge,
+// face or element, so it is single-valued across neighbouring coarse elements.
+__device__ __forceinline__ double u_at(const double *U, int64_t sx, int64_t sxy, int p, int q, int r) {
+    return U[p + sx * q + sxy * r];
+}
+
+__global__ void __launch_bounds__(256) k_exp_finite_nodal(const Geom g1, const double *__restrict__ U1,
+                                                          const double *__restrict__ U0, double *__restrict__ V,
+                                                          int variant) {
+    const int p = blockIdx.x * 64 + threadIdx.x;
+    const int64_t row = (int64_t)blockIdx.y * 4 + threadIdx.y;
+    if (p > g1.nx || row >= (int64_t)g1.sy * (g1.nz + 1)) return;
+    const int q = (int)(row % g1.sy), r = (int)(row / g1.sy);
+    const int64_t s1 = g1.sx, s1y = (int64_t)g1.sx * g1.sy;
+    const int64_t s0 = row_pitch(g1.nx / 2 + 1), s0y = s0 * (g1.ny / 2 + 1);
+    // eq. jiedian at a level l-2 node (all indices even)
+    auto Wc = [&](int pp, int qq, int rr) {
+        return (5.0 * u_at(U1, s1, s1y, pp, qq, rr) - u_at(U0, s0, s0y, pp >> 1, qq >> 1, rr >> 1)) / 4.0;
+    };
+    auto del = [&](int pp, int qq, int rr) {
+        return u_at(U1, s1, s1y, pp, qq, rr) - u_at(U0, s0, s0y, pp >> 1, qq >> 1, rr >> 1);
+    };
+    // eq. zhongdian at the midpoint (pp,qq,rr) of the edge along axis ax
+    auto Wm = [&](int pp, int qq, int rr, int ax) {
+        const int dp = ax == 0, dq = ax == 1, dr = ax == 2;
+        return u_at(U1, s1, s1y, pp, qq, rr) + (del(pp - dp, qq - dq, rr - dr) + del(pp + dp, qq + dq, rr + dr)) / 8.0;
+    };
+    const int op = p & 1, oq = q & 1, orr = r & 1;
+    const int nodd = op + oq + orr;
+    double v;
+    if (nodd == 0) {
+        v = Wc(p, q, r);
+    } else if (nodd == 1) {
+        v = Wm(p, q, r, op ? 0 : (oq ? 1 : 2));
+    } else if (nodd == 2) {
+        // face centre; in-face axes A < B (the two odd ones)
+        const int A = op ? 0 : 1, B = orr ? 2 : 1;
+        auto at = [&](int sa, int sb) {                  // offset sa along A, sb along B
+            int3 c = make_int3(p, q, r);
+            if (A == 0) c.x += sa; else c.y += sa;
+            if (B == 1) c.y += sb; else c.z += sb;
+            return c;
+        };
+        if (variant == ECMG_SERENDIPITY20) {
+            // value of the face's 8-node serendipity interpolant at its centre:
+            // -1/4 (4 corners) + 1/2 (4 mid-edges)
+            double sc = 0.0, sm = 0.0;
+            for (int sb = -1; sb <= 1; sb += 2)
+                for (int sa = -1; sa <= 1; sa += 2) {
+                    const int3 c = at(sa, sb);
+                    sc += Wc(c.x, c.y, c.z);
+                }
+            for (int s = -1; s <= 1; s += 2) {
+                const int3 ea = at(0, s);                // edge along A at B offset s
+                const int3 eb = at(s, 0);                // edge along B at A offset s
+                sm += Wm(ea.x, ea.y, ea.z, A) + Wm(eb.x, eb.y, eb.z, B);
+            }
+            v = -0.25 * sc + 0.5 * sm;
+        } else {
+            // mean of eq. zhongdian along the two face diagonals
+            const double u = u_at(U1, s1, s1y, p, q, r);
+            const int3 a0 = at(-1, -1), a1 = at(1, 1), b0 = at(-1, 1), b1 = at(1, -1);
+            v = ((u + (del(a0.x, a0.y, a0.z) + del(a1.x, a1.y, a1.z)) / 8.0) +
+                 (u + (del(b0.x, b0.y, b0.z) + del(b1.x, b1.y, b1.z)) / 8.0)) / 2.0;
+        }
+    } else {
+        if (variant == ECMG_SERENDIPITY20) {
+            // -1/4 (8 corners) + 1/4 (12 mid-edges)
+            double sc = 0.0, sm = 0.0;
+            for (int c = -1; c <= 1; c += 2)
+                for (int b = -1; b <= 1; b += 2)
+                    for (int a = -1; a <= 1; a += 2) sc += Wc(p + a, q + b, r + c);
+            for (int t = -1; t <= 1; t += 2)
+                for (int u2 = -1; u2 <= 1; u2 += 2)
+                    sm += Wm(p, q + t, r + u2, 0) + Wm(p + t, q, r + u2, 1) + Wm(p + t, q + u2, r, 2);
+            v = -0.25 * sc + 0.25 * sm;
+        } else {
+            // mean of eq. zhongdian along the 4 space diagonals
+            const double m = u_at(U1, s1, s1y, p, q, r);
+            double sum = 0.0;
+            for (int b = -1; b <= 1; b += 2)
+                for (int c = -1; c <= 1; c += 2)
+                    sum += m + (del(p - 1, q - b, r - c) + del(p + 1, q + b, r + c)) / 8.0;
+            v = sum / 4.0;
+        }
+    }
+    V[p + s1 * q + s1y * r] = v;
+}
+
+// Phase 2: every fine node of level l is the tri-quadratic Lagrange
+// interpolant of the 27 nodal values of its owner coarse element.  One 64-lane
+// row per wave, so the y and z offsets (and which 1-D weights vanish) are
+// uniform across the wave.
+__global__ void __launch_bounds__(256) k_exp_finite_interp(const Geom gf, const double *__restrict__ V,
+                                                           double *__restrict__ x, double *__restrict__ W) {
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    const int64_t row = (int64_t)blockIdx.y * 4 + threadIdx.y;
+    if (i > gf.nx || row >= (int64_t)gf.sy * (gf.nz + 1)) return;
+    const int j = (int)(row % gf.sy), k = (int)(row / gf.sy);
     const int NX = gf.nx / 4, NY = gf.ny / 4, NZ = gf.nz / 4;
     const int I = min(i / 4, NX - 1), J = min(j / 4, NY - 1), K = min(k / 4, NZ - 1);
     const int a = i - 4 * I, b = j - 4 * J, c = k - 4 * K;
-    const int64_t n1x = gf.nx / 2 + 1, n1y = gf.ny / 2 + 1;
-    const int64_t n0x = NX + 1, n0y = NY + 1;
-
-    double u1[3][3][3];
-#pragma unroll
-    for (int cc = 0; cc < 3; ++cc)
-#pragma unroll
-        for (int bb = 0; bb < 3; ++bb)
-#pragma unroll
-            for (int aa = 0; aa < 3; ++aa)
-                u1[cc][bb][aa] = U1[(2 * I + aa) + n1x * ((2 * J + bb) + n1y * (int64_t)(2 * K + cc))];
-    double u0[2][2][2], d[2][2][2];
-#pragma unroll
-    for (int cc = 0; cc < 2; ++cc)
-#pragma unroll
-        for (int bb = 0; bb < 2; ++bb)
-#pragma unroll
-            for (int aa = 0; aa < 2; ++aa) {
-                u0[cc][bb][aa] = U0[(I + aa) + n0x * ((J + bb) + n0y * (int64_t)(K + cc))];
-                d[cc][bb][aa] = u1[2 * cc][2 * bb][2 * aa] - u0[cc][bb][aa];
-            }
-
-    double V[3][3][3];
-    // corners (eq. jiedian)
-#pragma unroll
-    for (int cc = 0; cc < 2; ++cc)
-#pragma unroll
-        for (int bb = 0; bb < 2; ++bb)
-#pragma unroll
-            for (int aa = 0; aa < 2; ++aa)
-                V[2 * cc][2 * bb][2 * aa] = (5.0 * u1[2 * cc][2 * bb][2 * aa] - u0[cc][bb][aa]) / 4.0;
-    // mid-edges (eq. zhongdian)
-#pragma unroll
-    for (int p = 0; p < 2; ++p)
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            V[2 * q][2 * p][1] = u1[2 * q][2 * p][1] + (d[q][p][0] + d[q][p][1]) / 8.0;   // along x
-            V[2 * q][1][2 * p] = u1[2 * q][1][2 * p] + (d[q][0][p] + d[q][1][p]) / 8.0;   // along y
-            V[1][2 * q][2 * p] = u1[1][2 * q][2 * p] + (d[0][q][p] + d[1][q][p]) / 8.0;   // along z
+    const int64_t s1 = row_pitch(gf.nx / 2 + 1), s1y = s1 * (gf.ny / 2 + 1);
+    double Lx[3], Ly[3], Lz[3];
+    lagrange3(a, Lx);
+    lagrange3(b, Ly);
+    lagrange3(c, Lz);
+    const double *Vb = V + (2 * I) + s1 * (2 * J) + s1y * (2 * K);
+    double w = 0.0;
+    for (int cc = 0; cc < 3; ++cc) {
+        if (Lz[cc] == 0.0) continue;                      // uniform over the wave
+        double sy = 0.0;
+        for (int bb = 0; bb < 3; ++bb) {
+            if (Ly[bb] == 0.0) continue;                  // uniform over the wave
+            const double *Vr = Vb + s1 * bb + s1y * cc;
+            sy += Ly[bb] * (Lx[0] * Vr[0] + Lx[1] * Vr[1] + Lx[2] * Vr[2]);
         }
-    if (variant == ECMG_SERENDIPITY20) {
-        // face centres: -1/4 (4 face corners) + 1/2 (4 face mid-edges)
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            const int e = 2 * s;
-            V[1][1][e] = -0.25 * (V[0][0][e] + V[0][2][e] + V[2][0][e] + V[2][2][e]) +
-                         0.5 * (V[0][1][e] + V[2][1][e] + V[1][0][e] + V[1][2][e]);
-            V[1][e][1] = -0.25 * (V[0][e][0] + V[0][e][2] + V[2][e][0] + V[2][e][2]) +
-                         0.5 * (V[0][e][1] + V[2][e][1] + V[1][e][0] + V[1][e][2]);
-            V[e][1][1] = -0.25 * (V[e][0][0] + V[e][0][2] + V[e][2][0] + V[e][2][2]) +
-                         0.5 * (V[e][0][1] + V[e][2][1] + V[e][1][0] + V[e][1][2]);
-        }
-        double sc = 0.0, sm = 0.0;
-#pragma unroll
-        for (int cc = 0; cc < 2; ++cc)
-#pragma unroll
-            for (int bb = 0; bb < 2; ++bb)
-#pragma unroll
-                for (int aa = 0; aa < 2; ++aa) sc += V[2 * cc][2 * bb][2 * aa];
-#pragma unroll
-        for (int p = 0; p < 2; ++p)
-#pragma unroll
-            for (int q = 0; q < 2; ++q) sm += V[2 * q][2 * p][1] + V[2 * q][1][2 * p] + V[1][2 * q][2 * p];
-        V[1][1][1] = -0.25 * sc + 0.25 * sm;
-    } else {
-        // face centres: mean of eq. zhongdian along the two face diagonals
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            const int e = 2 * s;
-            V[1][1][e] = ((u1[1][1][e] + (d[0][0][s] + d[1][1][s]) / 8.0) +
-                          (u1[1][1][e] + (d[0][1][s] + d[1][0][s]) / 8.0)) / 2.0;
-            V[1][e][1] = ((u1[1][e][1] + (d[0][s][0] + d[1][s][1]) / 8.0) +
-                          (u1[1][e][1] + (d[0][s][1] + d[1][s][0]) / 8.0)) / 2.0;
-            V[e][1][1] = ((u1[e][1][1] + (d[s][0][0] + d[s][1][1]) / 8.0) +
-                          (u1[e][1][1] + (d[s][0][1] + d[s][1][0]) / 8.0)) / 2.0;
-        }
-        // body centre: mean along the 4 space diagonals
-        const double m = u1[1][1][1];
-        V[1][1][1] = ((m + (d[0][0][0] + d[1][1][1]) / 8.0) + (m + (d[0][0][1] + d[1][1][0]) / 8.0) +
-                      (m + (d[0][1][0] + d[1][0][1]) / 8.0) + (m + (d[0][1][1] + d[1][0][0]) / 8.0)) / 4.0;
+        w += Lz[cc] * sy;
     }
-
-    double w;
-    if (!(a & 1) && !(b & 1) && !(c & 1)) {
-        w = V[c >> 1][b >> 1][a >> 1];
-    } else {
-        double Lx[3], Ly[3], Lz[3];
-        lagrange3(a, Lx);
-        lagrange3(b, Ly);
-        lagrange3(c, Lz);
-        w = 0.0;
-#pragma unroll
-        for (int cc = 0; cc < 3; ++cc) {
-            double sy = 0.0;
-#pragma unroll
-            for (int bb = 0; bb < 3; ++bb) {
-                const double sxv = Lx[0] * V[cc][bb][0] + Lx[1] * V[cc][bb][1] + Lx[2] * V[cc][bb][2];
-                sy += Ly[bb] * sxv;
-            }
-            w += Lz[cc] * sy;
-        }
-    }
+    const int64_t id = i + (int64_t)gf.sx * j + (int64_t)gf.sx * gf.sy * k;
     if (W) W[id] = w;
     if (!is_dir(gf, i, j, k)) x[id] = w;
 }
@@ -163,17 +175,17 @@ __global__ void __launch_bounds__(256) k_exp_finite(const Geom gf, const double 
 // U~ = U1 + (1/3) T[U1 - U0]: eq. t1 at coarse nodes ((4 U1 - U0)/3), eq.
 // chenlin at edge midpoints (U1 + (d_a + d_b)/6), and the mean of chenlin along
 // the 2 face diagonals (U1 + sum(4 d)/12) or the 4 space diagonals (U1 +
-// sum(8 d)/24) at face and body centres.
+// sum(8 d)/24) at face and body centres.  One 64-lane row per wave: the y and
+// z parities, hence the number of coarse differences, are wave-uniform.
 __global__ void __launch_bounds__(256) k_exp_true(const Geom gf, const double *__restrict__ U1,
                                                   const double *__restrict__ U0, double *__restrict__ Ut) {
-    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= gf.nnodes) return;
-    const int i = (int)(id % gf.sx);
-    const int64_t t = id / gf.sx;
-    const int j = (int)(t % gf.sy);
-    const int k = (int)(t / gf.sy);
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    const int64_t row = (int64_t)blockIdx.y * 4 + threadIdx.y;
+    if (i > gf.nx || row >= (int64_t)gf.sy * (gf.nz + 1)) return;
+    const int j = (int)(row % gf.sy), k = (int)(row / gf.sy);
     const int64_t sx = gf.sx, sxy = (int64_t)gf.sx * gf.sy;
-    const int64_t cx = gf.nx / 2 + 1, cxy = cx * (gf.ny / 2 + 1);
+    const int64_t cx = row_pitch(gf.nx / 2 + 1), cxy = cx * (gf.ny / 2 + 1);
+    const int64_t id = i + sx * j + sxy * k;
     const double u1 = U1[id];
     const int oi = i & 1, oj = j & 1, ok = k & 1;
     if (!(oi | oj | ok)) {
@@ -181,17 +193,11 @@ __global__ void __launch_bounds__(256) k_exp_true(const Geom gf, const double *_
         return;
     }
     double s = 0.0;
-#pragma unroll
-    for (int dk = 0; dk < 2; ++dk) {
-        if (dk && !ok) break;
+    for (int dk = 0; dk <= ok; ++dk) {
         const int kk = k - ok + 2 * dk;
-#pragma unroll
-        for (int dj = 0; dj < 2; ++dj) {
-            if (dj && !oj) break;
+        for (int dj = 0; dj <= oj; ++dj) {
             const int jj = j - oj + 2 * dj;
-#pragma unroll
-            for (int di = 0; di < 2; ++di) {
-                if (di && !oi) break;
+            for (int di = 0; di <= oi; ++di) {
                 const int ii = i - oi + 2 * di;
                 s += U1[ii + sx * jj + sxy * kk] - U0[(ii >> 1) + cx * (jj >> 1) + cxy * (kk >> 1)];
             }
@@ -202,15 +208,39 @@ __global__ void __launch_bounds__(256) k_exp_true(const Geom gf, const double *_
     Ut[id] = u1 + s / denom;
 }
 
-void launch_exp_finite(const Geom &gf, const double *U1, const double *U0, double *x, double *W, int variant,
-                       hipStream_t s) {
-    const int64_t nb = (gf.nnodes + 255) / 256;
-    hipLaunchKernelGGL(k_exp_finite, dim3((unsigned)nb), dim3(256), 0, s, gf, U1, U0, x, W, variant);
+void launch_exp_finite(const Geom &gf, const Geom &g1, const double *U1, const double *U0, double *V, double *x,
+                       double *W, int variant, hipStream_t s) {
+    const dim3 blk(64, 4);
+    const dim3 g1grid((g1.nx + 1 + 63) / 64, (unsigned)(((int64_t)g1.sy * (g1.nz + 1) + 3) / 4));
+    hipLaunchKernelGGL(k_exp_finite_nodal, g1grid, blk, 0, s, g1, U1, U0, V, variant);
+    const dim3 gfgrid((gf.nx + 1 + 63) / 64, (unsigned)(((int64_t)gf.sy * (gf.nz + 1) + 3) / 4));
+    hipLaunchKernelGGL(k_exp_finite_interp, gfgrid, blk, 0, s, gf, V, x, W);
+}
+
+// Zero the row padding (i > nx) of up to four node arrays of a level; the JCG
+// scratch arrays are shared by all levels, so padding left over from another
+// level's layout is cleared before a level's streaming passes read it.
+__global__ void k_zero_pad(const Geom g, double *a, double *b, double *c, double *d) {
+    const int pad = g.sx - g.nx - 1;
+    const int64_t rows = (int64_t)g.sy * (g.nz + 1);
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pad <= 0 || t >= rows * pad) return;
+    const int64_t id = (t / pad) * g.sx + g.nx + 1 + (t % pad);
+    if (a) a[id] = 0.0;
+    if (b) b[id] = 0.0;
+    if (c) c[id] = 0.0;
+    if (d) d[id] = 0.0;
+}
+
+void launch_zero_pad(const Geom &g, double *a, double *b, double *c, double *d, hipStream_t s) {
+    const int64_t n = (int64_t)g.sy * (g.nz + 1) * (g.sx - g.nx - 1);
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_zero_pad, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, a, b, c, d);
 }
 
 void launch_exp_true(const Geom &gf, const double *U1, const double *U0, double *Ut, hipStream_t s) {
-    const int64_t nb = (gf.nnodes + 255) / 256;
-    hipLaunchKernelGGL(k_exp_true, dim3((unsigned)nb), dim3(256), 0, s, gf, U1, U0, Ut);
+    const dim3 grid((gf.nx + 1 + 63) / 64, (unsigned)(((int64_t)gf.sy * (gf.nz + 1) + 3) / 4));
+    hipLaunchKernelGGL(k_exp_true, grid, dim3(64, 4), 0, s, gf, U1, U0, Ut);
 }
 
 }  // namespace ecmg

@@ -119,35 +119,31 @@ __device__ __forceinline__ bool is_dirichlet(const Geom &g, int i, int j, int k)
 }
 
 // Robin face-mass term of face F (axis AX = F/2) at a node whose in-face
-// coordinates are (pi, qi), using the 3x3x3 neighbourhood v (index [oz][oy][ox]).
-// Face elements around the node: (ep, eq) = (pi-1+dp, qi-1+dq); the node sits
-// at local corner (1-dp, 1-dq) of each; the face mass couples it to the face
-// element's 4 corners with hp*hq*(1/9, 1/18, 1/36) by the number of differing
-// in-face axes.
-template <int AX, typename T>
+// coordinates are (pi, qi); neighbours come from the LDS planes (slots s0, s1,
+// s2 = planes k-1, k, k+1) around LDS position (lj, li).  Face elements around
+// the node: (ep, eq) = (pi-1+dp, qi-1+dq); the node sits at local corner
+// (1-dp, 1-dq) of each; the face mass couples it to the face element's 4
+// corners with hp*hq*(1/9, 1/18, 1/36) by the number of differing in-face axes.
+template <int AX, typename T, typename Planes>
 __device__ __forceinline__ T robin_term(const Geom &g, int face, const T *al, int pi, int qi, int np, int nq,
-                                        const T (&v)[3][3][3]) {
+                                     Planes sv, int s0, int s1, int s2, int lj, int li) {
     T s = 0;
-#pragma unroll
     for (int dq = 0; dq < 2; ++dq) {
         const int eq = qi - 1 + dq;
         if (eq < 0 || eq >= nq) continue;
-#pragma unroll
         for (int dp = 0; dp < 2; ++dp) {
             const int ep = pi - 1 + dp;
             if (ep < 0 || ep >= np) continue;
             const T a = al[ep + (int64_t)np * eq];
             T t = 0;
-#pragma unroll
             for (int bq = 0; bq < 2; ++bq)
-#pragma unroll
                 for (int bp = 0; bp < 2; ++bp) {
                     const int op = dp - 1 + bp, oq = dq - 1 + bq;
                     const int c = (bp != 1 - dp) + (bq != 1 - dq);
                     T vv;
-                    if (AX == 0) vv = v[oq + 1][op + 1][1];
-                    else if (AX == 1) vv = v[oq + 1][1][op + 1];
-                    else vv = v[1][oq + 1][op + 1];
+                    if (AX == 0) vv = sv[oq < 0 ? s0 : (oq > 0 ? s2 : s1)][lj + op][li];        // (p,q) = (y,z)
+                    else if (AX == 1) vv = sv[oq < 0 ? s0 : (oq > 0 ? s2 : s1)][lj][li + op];   // (p,q) = (x,z)
+                    else vv = sv[s1][lj + oq][li + op];                                         // (p,q) = (x,y)
                     t += (T)g.M[face][c] * vv;
                 }
             s += a * t;
@@ -163,10 +159,16 @@ __device__ __forceinline__ T robin_term(const Geom &g, int face, const T *al, in
 
 template <typename T, int MODE>
 __global__ void __launch_bounds__(NT) k_stencil(const StencilArgs<T> a) {
-    __shared__ T sv[3][TYT + 2][TX + 2];   // input vector, planes k-1, k, k+1 (+ halo)
-    __shared__ T sb[2][TYT + 1][TX + 1];   // beta of element layers k-1, k (+ halo)
+    // Rolling LDS buffers: 4 node planes and 3 element layers, so the plane
+    // being filled never aliases the three planes being read and one barrier per
+    // z-step suffices.
+    __shared__ T sv[4][TYT + 2][TX + 2];
+    __shared__ T sb[3][TYT + 1][TX + 1];
     __shared__ double red[2][NT / 64];
     __shared__ int s_last;
+    constexpr int NH = 2 * (TX + 2) + 2 * TYT;   // halo nodes of a plane tile
+    constexpr int NHB = (TX + 1) + TYT;          // halo elements of a layer tile
+    static_assert(NH <= NT && NHB <= NT, "one halo value per thread");
 
     const Geom &g = a.g;
     const int tid = threadIdx.x, tx = tid & (TX - 1), ty = tid / TX;
@@ -193,66 +195,106 @@ __global__ void __launch_bounds__(NT) k_stencil(const StencilArgs<T> a) {
         pin = (it & 1) ? a.p1 : a.p0;
         pout = (it & 1) ? a.p0 : a.p1;
     }
+    const int64_t sxy = (int64_t)g.sx * g.sy;
+    const int64_t exy = (int64_t)g.nx * g.ny;
+    const int i = i0 + tx;
 
-    const int64_t sx = g.sx, sxy = (int64_t)g.sx * g.sy;
-    T pold_next[RY], pold_cur[RY];
+    // Per-thread positions, fixed for the whole z-march: in-plane offsets of
+    // this thread's RY interior nodes and elements and of its halo node and
+    // halo element (-1 when outside the grid).
+    int off[RY], eoff[RY];
 #pragma unroll
-    for (int r = 0; r < RY; ++r) pold_next[r] = pold_cur[r] = 0;
+    for (int r = 0; r < RY; ++r) {
+        const int j = j0 + ty + TY * r;
+        off[r] = (i <= g.nx && j <= g.ny) ? i + g.sx * j : -1;
+        eoff[r] = (i < g.nx && j < g.ny) ? i + g.nx * j : -1;
+    }
+    int hli = 0, hlj = 0, hoff = -1, bli = 0, blj = 0, beoff = -1;
+    if (tid < NH) {
+        const int h = tid;
+        if (h < TX + 2) { hlj = 0; hli = h; }
+        else if (h < 2 * (TX + 2)) { hlj = TYT + 1; hli = h - (TX + 2); }
+        else if (h < 2 * (TX + 2) + TYT) { hli = 0; hlj = 1 + h - 2 * (TX + 2); }
+        else { hli = TX + 1; hlj = 1 + h - 2 * (TX + 2) - TYT; }
+        const int ii = i0 + hli - 1, jj = j0 + hlj - 1;
+        if (ii >= 0 && ii <= g.nx && jj >= 0 && jj <= g.ny) hoff = ii + g.sx * jj;
+    }
+    if (tid < NHB) {
+        if (tid < TX + 1) { blj = 0; bli = tid; }
+        else { bli = 0; blj = 1 + tid - (TX + 1); }
+        const int ie = i0 + bli - 1, je = j0 + blj - 1;
+        if (ie >= 0 && ie < g.nx && je >= 0 && je < g.ny) beoff = ie + g.nx * je;
+    }
 
-    // value of the stencil input at node (i,j,k): v, or for pass A the new
-    // search direction D^-1 r + beta p_old; 0 outside the grid
-    auto node_val = [&](int i, int j, int k, T &pold) -> T {
-        if (i < 0 || i > g.nx || j < 0 || j > g.ny || k < 0 || k > g.nz) { pold = 0; return 0; }
-        const int64_t id = i + sx * j + sxy * k;
+    // ---- raw loads into registers, issued PF z-steps before they are used ----
+    // A register set holds, for one z-step k: the raw inputs of plane k+1 (pass
+    // A: 1/D, r, p_old; apply/init: v) for this thread's interior and halo
+    // nodes, beta of element layer k, and the epilogue inputs of output plane k
+    // (pass A: x; init: F and 1/D).  With PF = 1 the loads of step k+1 are in
+    // flight while step k computes; PF = 2 alternates two sets.
+    struct RegSet {
+        T ra[RY], rb[RY], rc[RY], ha, hb, hc, bb[RY], bh, ea[RY], eb[RY];
+    };
+    RegSet SA, SB;
+    auto fetch_node = [&](int o, int kk, T &va, T &vb, T &vc) {
+        va = vb = vc = 0;
+        if (o < 0 || kk < 0 || kk > g.nz) return;
+        const int64_t id = (int64_t)o + sxy * kk;
         if (MODE == MODE_PASSA) {
-            const T z = a.dinv[id] * a.r[id];
-            if (first) { pold = 0; return z; }
-            pold = pin[id];
-            return z + betak * pold;
+            va = a.dinv[id];
+            vb = a.r[id];
+            if (!first) vc = pin[id];
         } else {
-            pold = 0;
-            return a.v[id];
+            va = a.v[id];
         }
     };
-    auto load_plane = [&](int k, int slot) {
+    // fill set S for z-step k: plane k+1, layer k, epilogue of plane k
+    auto fetch_set = [&](RegSet &S, int k) {
+#pragma unroll
+        for (int r = 0; r < RY; ++r) fetch_node(off[r], k + 1, S.ra[r], S.rb[r], S.rc[r]);
+        fetch_node(hoff, k + 1, S.ha, S.hb, S.hc);
+        const bool ok = k >= 0 && k < g.nz;
+#pragma unroll
+        for (int r = 0; r < RY; ++r) S.bb[r] = (ok && eoff[r] >= 0) ? a.beta[eoff[r] + exy * k] : (T)0;
+        S.bh = (ok && beoff >= 0) ? a.beta[beoff + exy * k] : (T)0;
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
-            const int jj = ty + TY * r;
-            T po;
-            sv[slot][jj + 1][tx + 1] = node_val(i0 + tx, j0 + jj, k, po);
-            pold_next[r] = po;
-        }
-        constexpr int NH = 2 * (TX + 2) + 2 * TYT;
-        for (int h = tid; h < NH; h += NT) {
-            int li, lj;
-            if (h < TX + 2) { lj = 0; li = h; }
-            else if (h < 2 * (TX + 2)) { lj = TYT + 1; li = h - (TX + 2); }
-            else if (h < 2 * (TX + 2) + TYT) { li = 0; lj = 1 + h - 2 * (TX + 2); }
-            else { li = TX + 1; lj = 1 + h - 2 * (TX + 2) - TYT; }
-            T po;
-            sv[slot][lj][li] = node_val(i0 + li - 1, j0 + lj - 1, k, po);
+            S.ea[r] = S.eb[r] = 0;
+            if (MODE == MODE_APPLY || off[r] < 0 || k < 0 || k > g.nz) continue;
+            const int64_t id = (int64_t)off[r] + sxy * k;
+            if (MODE == MODE_PASSA) {
+                if (!first) S.ea[r] = a.x[id];
+            } else {
+                S.ea[r] = a.F[id];
+                S.eb[r] = a.dinv[id];
+            }
         }
     };
-    auto elem_val = [&](int ie, int je, int ke) -> T {
-        if (ie < 0 || ie >= g.nx || je < 0 || je >= g.ny || ke < 0 || ke >= g.nz) return 0;
-        return a.beta[ie + (int64_t)g.nx * (je + (int64_t)g.ny * ke)];
+    // value stored in LDS: v, or the pass-A search direction D^-1 r + beta p_old
+    auto node_value = [&](T va, T vb, T vc) -> T {
+        if (MODE == MODE_PASSA) {
+            const T z = va * vb;
+            return first ? z : z + betak * vc;
+        }
+        return va;
     };
-    auto load_beta = [&](int ke, int slot) {
+    auto vslot = [](int k) { return (k + 4) & 3; };
+    auto bslot = [](int k) { return (k + 3) % 3; };
+    T pold_next[RY], pold_cur[RY], xa_cur[RY], xb_cur[RY];
+    // plane k+1 and layer k of set S into LDS
+    auto commit_set = [&](const RegSet &S, int k) {
+        const int slot = vslot(k + 1);
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
-            const int jj = ty + TY * r;
-            sb[slot][jj + 1][tx + 1] = elem_val(i0 + tx, j0 + jj, ke);
+            sv[slot][ty + TY * r + 1][tx + 1] = node_value(S.ra[r], S.rb[r], S.rc[r]);
+            pold_next[r] = S.rc[r];
         }
-        constexpr int NHB = (TX + 1) + TYT;
-        for (int h = tid; h < NHB; h += NT) {
-            int li, lj;
-            if (h < TX + 1) { lj = 0; li = h; }
-            else { li = 0; lj = 1 + h - (TX + 1); }
-            sb[slot][lj][li] = elem_val(i0 + li - 1, j0 + lj - 1, ke);
-        }
+        if (tid < NH) sv[slot][hlj][hli] = node_value(S.ha, S.hb, S.hc);
+        const int bs = bslot(k);
+#pragma unroll
+        for (int r = 0; r < RY; ++r) sb[bs][ty + TY * r + 1][tx + 1] = S.bb[r];
+        if (tid < NHB) sb[bs][blj][bli] = S.bh;
     };
-    auto vslot = [](int k) { return (k + 3) % 3; };
-    auto bslot = [](int k) { return (k + 2) & 1; };
 
     T C[8];
 #pragma unroll
@@ -260,88 +302,103 @@ __global__ void __launch_bounds__(NT) k_stencil(const StencilArgs<T> a) {
 
     double acc0 = 0.0, acc1 = 0.0;
 
-    load_plane(k0 - 1, vslot(k0 - 1));
-    load_plane(k0, vslot(k0));
-    load_beta(k0 - 1, bslot(k0 - 1));
+    // prologue: plane k0-1 (set SA as step k0-2's plane k0-1 ... built by hand)
+    {
+        fetch_set(SA, k0 - 2);       // plane k0-1, layer k0-2 (unused), epilogue k0-2 (unused)
+        commit_set(SA, k0 - 2);
+        fetch_set(SB, k0 - 1);       // plane k0, layer k0-1
+        commit_set(SB, k0 - 1);
+    }
+    fetch_set(SA, k0);
+    if (PF == 2) fetch_set(SB, k0 + 1);
 
-    for (int k = k0; k < k1; ++k) {
+    // one z-step: output plane k from planes k-1, k, k+1 (S holds plane k+1)
+    auto step = [&](RegSet &S, int k) {
 #pragma unroll
-        for (int r = 0; r < RY; ++r) pold_cur[r] = pold_next[r];
-        load_plane(k + 1, vslot(k + 1));
-        load_beta(k, bslot(k));
+        for (int r = 0; r < RY; ++r) {
+            pold_cur[r] = pold_next[r];
+            xa_cur[r] = S.ea[r];
+            xb_cur[r] = S.eb[r];
+        }
+        commit_set(S, k);
         __syncthreads();
+        if (k + PF < k1) fetch_set(S, k + PF);
 
         const int s0 = vslot(k - 1), s1 = vslot(k), s2 = vslot(k + 1);
         const int b0 = bslot(k - 1), b1 = bslot(k);
-        const int i = i0 + tx;
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
             const int jj = ty + TY * r;
             const int j = j0 + jj;
             const int li = tx + 1, lj = jj + 1;
-            T v[3][3][3];
-#pragma unroll
-            for (int oy = 0; oy < 3; ++oy)
-#pragma unroll
-                for (int ox = 0; ox < 3; ++ox) {
-                    v[0][oy][ox] = sv[s0][lj - 1 + oy][li - 1 + ox];
-                    v[1][oy][ox] = sv[s1][lj - 1 + oy][li - 1 + ox];
-                    v[2][oy][ox] = sv[s2][lj - 1 + oy][li - 1 + ox];
-                }
-            T b[2][2][2];
-#pragma unroll
-            for (int dy = 0; dy < 2; ++dy)
-#pragma unroll
-                for (int dx = 0; dx < 2; ++dx) {
-                    b[0][dy][dx] = sb[b0][lj - 1 + dy][li - 1 + dx];
-                    b[1][dy][dx] = sb[b1][lj - 1 + dy][li - 1 + dx];
-                }
-            // partial sums of beta over x, then y (elements sharing an edge/face)
+            // beta of the 8 elements around the node: layer below (k-1) and
+            // above (k), in-plane offsets [dy][dx] (element i-1+dx, j-1+dy)
+            const T l00 = sb[b0][lj - 1][li - 1], l01 = sb[b0][lj - 1][li];
+            const T l10 = sb[b0][lj][li - 1], l11 = sb[b0][lj][li];
+            const T u00 = sb[b1][lj - 1][li - 1], u01 = sb[b1][lj - 1][li];
+            const T u10 = sb[b1][lj][li - 1], u11 = sb[b1][lj][li];
+            // For in-plane neighbour offset (oy, ox), the elements of one layer
+            // that contain both the node and the neighbour column: one element
+            // (diagonal), two (edge) or all four (centre).
             T q = 0;
 #pragma unroll
-            for (int oz = -1; oz <= 1; ++oz)
+            for (int oy = -1; oy <= 1; ++oy)
 #pragma unroll
-                for (int oy = -1; oy <= 1; ++oy)
-#pragma unroll
-                    for (int ox = -1; ox <= 1; ++ox) {
-                        T wsum = 0;
-#pragma unroll
-                        for (int dz = (oz > 0); dz <= (oz < 0 ? 0 : 1); ++dz)
-#pragma unroll
-                            for (int dy = (oy > 0); dy <= (oy < 0 ? 0 : 1); ++dy)
-#pragma unroll
-                                for (int dx = (ox > 0); dx <= (ox < 0 ? 0 : 1); ++dx) wsum += b[dz][dy][dx];
-                        const int m = (ox != 0) | ((oy != 0) << 1) | ((oz != 0) << 2);
-                        q += C[m] * wsum * v[oz + 1][oy + 1][ox + 1];
-                    }
+                for (int ox = -1; ox <= 1; ++ox) {
+                    T sl, su;
+                    if (oy < 0 && ox < 0) { sl = l00; su = u00; }
+                    else if (oy < 0 && ox > 0) { sl = l01; su = u01; }
+                    else if (oy > 0 && ox < 0) { sl = l10; su = u10; }
+                    else if (oy > 0 && ox > 0) { sl = l11; su = u11; }
+                    else if (oy < 0) { sl = l00 + l01; su = u00 + u01; }
+                    else if (oy > 0) { sl = l10 + l11; su = u10 + u11; }
+                    else if (ox < 0) { sl = l00 + l10; su = u00 + u10; }
+                    else if (ox > 0) { sl = l01 + l11; su = u01 + u11; }
+                    else { sl = (l00 + l01) + (l10 + l11); su = (u00 + u01) + (u10 + u11); }
+                    const int m = (ox != 0) | ((oy != 0) << 1);
+                    const T vm = sv[s0][lj + oy][li + ox];
+                    const T v0 = sv[s1][lj + oy][li + ox];
+                    const T vp = sv[s2][lj + oy][li + ox];
+                    // neighbours in planes k-1 / k+1 share only the layer between;
+                    // neighbours in plane k are shared by both layers
+                    q += C[m | 4] * (sl * vm + su * vp) + C[m] * ((sl + su) * v0);
+                }
             if (i > g.nx || j > g.ny) continue;
-            // Robin faces
-            if (i == 0 && g.ft[0] == ECMG_ROBIN) q += robin_term<0>(g, 0, a.alpha[0], j, k, g.ny, g.nz, v);
-            if (i == g.nx && g.ft[1] == ECMG_ROBIN) q += robin_term<0>(g, 1, a.alpha[1], j, k, g.ny, g.nz, v);
-            if (j == 0 && g.ft[2] == ECMG_ROBIN) q += robin_term<1>(g, 2, a.alpha[2], i, k, g.nx, g.nz, v);
-            if (j == g.ny && g.ft[3] == ECMG_ROBIN) q += robin_term<1>(g, 3, a.alpha[3], i, k, g.nx, g.nz, v);
-            if (k == 0 && g.ft[4] == ECMG_ROBIN) q += robin_term<2>(g, 4, a.alpha[4], i, j, g.nx, g.ny, v);
-            if (k == g.nz && g.ft[5] == ECMG_ROBIN) q += robin_term<2>(g, 5, a.alpha[5], i, j, g.nx, g.ny, v);
+            // Robin faces (face-mass terms, rare: boundary nodes only)
+            if (i == 0 && g.ft[0] == ECMG_ROBIN) q += robin_term<0>(g, 0, a.alpha[0], j, k, g.ny, g.nz, sv, s0, s1, s2, lj, li);
+            if (i == g.nx && g.ft[1] == ECMG_ROBIN) q += robin_term<0>(g, 1, a.alpha[1], j, k, g.ny, g.nz, sv, s0, s1, s2, lj, li);
+            if (j == 0 && g.ft[2] == ECMG_ROBIN) q += robin_term<1>(g, 2, a.alpha[2], i, k, g.nx, g.nz, sv, s0, s1, s2, lj, li);
+            if (j == g.ny && g.ft[3] == ECMG_ROBIN) q += robin_term<1>(g, 3, a.alpha[3], i, k, g.nx, g.nz, sv, s0, s1, s2, lj, li);
+            if (k == 0 && g.ft[4] == ECMG_ROBIN) q += robin_term<2>(g, 4, a.alpha[4], i, j, g.nx, g.ny, sv, s0, s1, s2, lj, li);
+            if (k == g.nz && g.ft[5] == ECMG_ROBIN) q += robin_term<2>(g, 5, a.alpha[5], i, j, g.nx, g.ny, sv, s0, s1, s2, lj, li);
             const bool dir = is_dirichlet(g, i, j, k);
-            const int64_t id = i + sx * j + sxy * k;
+            const int64_t id = (int64_t)off[r] + sxy * k;
             if (MODE == MODE_APPLY) {
                 a.q[id] = dir ? (T)0 : q;
             } else if (MODE == MODE_INIT) {
-                const T rv = dir ? (T)0 : a.F[id] - q;
+                const T rv = dir ? (T)0 : xa_cur[r] - q;
                 a.r[id] = rv;
-                const T z = a.dinv[id] * rv;
+                const T z = xb_cur[r] * rv;
                 acc0 += (double)rv * (double)z;
                 acc1 += (double)rv * (double)rv;
             } else {
-                const T pc = v[1][1][1];
+                const T pc = sv[s1][lj][li];
                 const T qv = dir ? (T)0 : q;
                 pout[id] = pc;
                 a.q[id] = qv;
-                if (!first) a.x[id] += alpha_prev * pold_cur[r];
+                if (!first) a.x[id] = xa_cur[r] + alpha_prev * pold_cur[r];
                 acc0 += (double)pc * (double)qv;
             }
         }
-        __syncthreads();
+    };
+
+    if (PF == 1) {
+        for (int k = k0; k < k1; ++k) step(SA, k);
+    } else {
+        for (int k = k0; k < k1; k += 2) {
+            step(SA, k);
+            if (k + 1 < k1) step(SB, k + 1);
+        }
     }
 
     if (MODE == MODE_APPLY) return;
@@ -390,12 +447,32 @@ __global__ void __launch_bounds__(NTB) k_passB(const PassBArgs<T> a) {
     const T al = (T)sc->alpha;
     const int64_t stride = (int64_t)gridDim.x * NTB;
     double rz = 0.0, rr = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * NTB + threadIdx.x; i < a.n; i += stride) {
-        const T rv = a.r[i] - al * a.q[i];
-        a.r[i] = rv;
-        const T z = a.dinv[i] * rv;
-        rz += (double)rv * (double)z;
-        rr += (double)rv * (double)rv;
+    // U nodes per thread and trip, all loads issued before any is used (more
+    // bytes in flight per thread hides HBM latency)
+    constexpr int U = 1;
+    for (int64_t base = (int64_t)blockIdx.x * NTB + threadIdx.x; base < a.n; base += stride * U) {
+        T rv[U], qv[U], dv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = base + u * stride;
+            rv[u] = qv[u] = dv[u] = 0;
+            if (i < a.n) {
+                rv[u] = a.r[i];
+                qv[u] = a.q[i];
+                dv[u] = a.dinv[i];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = base + u * stride;
+            if (i < a.n) {
+                const T x = rv[u] - al * qv[u];
+                a.r[i] = x;
+                const T z = dv[u] * x;
+                rz += (double)x * (double)z;
+                rr += (double)x * (double)x;
+            }
+        }
     }
     double acc[2] = {rz, rr}, tot[2];
     if (last_block_total<2, NTB>(acc, red, &s_last, a.partials, a.counter, blockIdx.x, gridDim.x, tot) &&
@@ -446,6 +523,17 @@ int stencil_blocks(const Geom &g, int KZ, int *ntx, int *nty, int *nkz) {
     *nty = (g.sy + TYT - 1) / TYT;
     *nkz = (g.nz + 1 + KZ - 1) / KZ;
     return (*ntx) * (*nty) * (*nkz);
+}
+
+int stencil_kz(const Geom &g, int kz_max) {
+    // Planes per z-chunk: long chunks amortise the two halo planes, but small
+    // grids need short chunks so that enough blocks run concurrently (the
+    // planes of one chunk are processed in sequence by one block).
+    const int64_t tiles = (int64_t)((g.sx + TX - 1) / TX) * ((g.sy + TYT - 1) / TYT);
+    int64_t kz = tiles * (g.nz + 1) / 2048;
+    if (kz < 1) kz = 1;
+    if (kz > kz_max) kz = kz_max;
+    return (int)kz;
 }
 
 template <typename T>

@@ -36,6 +36,7 @@ __global__ void k_zero_free(const Geom g, double *x) {
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= g.nnodes) return;
     const int i = (int)(id % g.sx);
+    if (i > g.nx) return;
     const int64_t t = id / g.sx;
     const int j = (int)(t % g.sy), k = (int)(t / g.sy);
     if (!dir_node(g, i, j, k)) x[id] = 0.0;
@@ -131,7 +132,7 @@ __global__ void k_dinv(const Geom g, const double *__restrict__ beta, const Alph
     const int i = (int)(id % g.sx);
     const int64_t t = id / g.sx;
     const int j = (int)(t % g.sy), k = (int)(t / g.sy);
-    if (dir_node(g, i, j, k)) { dinv[id] = 0.0; return; }
+    if (i > g.nx || dir_node(g, i, j, k)) { dinv[id] = 0.0; return; }
     double s8 = 0.0;
     for (int ke = k - 1; ke <= k; ++ke) {
         if (ke < 0 || ke >= g.nz) continue;
@@ -230,6 +231,7 @@ __global__ void __launch_bounds__(256) k_rhs_norm(const Geom g, const double *F,
                                                   double *out) {
     auto val = [&](int64_t id) -> double {
         const int i = (int)(id % g.sx);
+        if (i > g.nx) return 0.0;
         const int64_t t = id / g.sx;
         const int j = (int)(t % g.sy), k = (int)(t / g.sy);
         return dir_node(g, i, j, k) ? x0[id] : F[id] - Ax0[id];
@@ -237,15 +239,16 @@ __global__ void __launch_bounds__(256) k_rhs_norm(const Geom g, const double *F,
     reduce_max_sum(val, g.nnodes, partials, counter, out);
 }
 
-__global__ void __launch_bounds__(256) k_norms(int64_t n, const double *a, const double *b, const double *c,
+__global__ void __launch_bounds__(256) k_norms(const Geom g, const double *a, const double *b, const double *c,
                                                double *partials, unsigned *counter, double *out) {
     auto val = [&](int64_t i) -> double {
+        if ((int)(i % g.sx) > g.nx) return 0.0;
         double v = a[i];
         if (b) v -= b[i];
         if (c) v -= c[i];
         return v;
     };
-    reduce_max_sum(val, n, partials, counter, out);
+    reduce_max_sum(val, g.nnodes, partials, counter, out);
 }
 
 // ---- launchers ----------------------------------------------------------------
@@ -293,9 +296,9 @@ void launch_rhs_norm(const Geom &g, const double *F, const double *Ax0, const do
                        counter, out);
 }
 
-void launch_norms(int64_t n, const double *a, const double *b, const double *c, double *partials,
+void launch_norms(const Geom &g, const double *a, const double *b, const double *c, double *partials,
                   unsigned *counter, double *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_norms, dim3(reduce_blocks(n)), dim3(256), 0, s, n, a, b, c, partials, counter, out);
+    hipLaunchKernelGGL(k_norms, dim3(reduce_blocks(g.nnodes)), dim3(256), 0, s, g, a, b, c, partials, counter, out);
 }
 
 }  // namespace ecmg

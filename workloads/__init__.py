@@ -7,8 +7,8 @@ hierarchy, face types, tolerance) and the seeded generators for the batched and
 serving mixes.  It holds none of the solver's arithmetic and is the only code
 shared by the CPU oracle and the GPU library's tests and benchmark.
 
-Every field is a numpy function ``fn(x, y, z, face)`` evaluated with numpy
-broadcasting; ``face`` is -1 for volume points and 0..5 (x-lo, x-hi, y-lo,
+Every field is a function ``fn(x, y, z, face)`` evaluated with broadcasting on
+numpy arrays or, unchanged, on torch tensors (any device); ``face`` is -1 for volume points and 0..5 (x-lo, x-hi, y-lo,
 y-hi, z-lo, z-hi) when all points lie on that face, which Robin data needs for
 the outward normal.  ``tensor_eval`` turns such a function into the
 tensor-product sampling convention of the C interfaces: ``out[k, j, i] =
@@ -32,9 +32,19 @@ FACE_NORMAL = ((0, -1.0), (0, 1.0), (1, -1.0), (1, 1.0), (2, -1.0), (2, 1.0))
 Field = Callable[[np.ndarray, np.ndarray, np.ndarray, int], np.ndarray]
 
 
+def _xp(*arrays):
+    """The array module of the inputs: numpy, or torch for torch tensors (fields
+    are then evaluated on whatever device the tensors live on)."""
+    for a in arrays:
+        if type(a).__module__.startswith("torch"):
+            import torch
+            return torch
+    return np
+
+
 def _const(c: float) -> Field:
     def fn(x, y, z, face=-1):
-        return np.full(np.broadcast_shapes(np.shape(x), np.shape(y), np.shape(z)), float(c))
+        return 0.0 * x + 0.0 * y + 0.0 * z + float(c)
     fn.constant = float(c)  # type: ignore[attr-defined]
     return fn
 
@@ -102,11 +112,13 @@ def paper_problem1(levels: int = 3, eps: float = 1e-9) -> Problem:
     h = 0.5 * math.pi
 
     def u(x, y, z, face=-1):
-        return np.sin(h * x) * np.sin(h * y) * np.sin(h * z)
+        xp = _xp(x, y, z)
+        return xp.sin(h * x) * xp.sin(h * y) * xp.sin(h * z)
 
     def grad_u(x, y, z):
-        sx, sy, sz = np.sin(h * x), np.sin(h * y), np.sin(h * z)
-        cx, cy, cz = np.cos(h * x), np.cos(h * y), np.cos(h * z)
+        xp = _xp(x, y, z)
+        sx, sy, sz = xp.sin(h * x), xp.sin(h * y), xp.sin(h * z)
+        cx, cy, cz = xp.cos(h * x), xp.cos(h * y), xp.cos(h * z)
         return (h * cx * sy * sz, h * sx * cy * sz, h * sx * sy * cz)
 
     def f(x, y, z, face=-1):
@@ -124,12 +136,14 @@ def paper_problem2(levels: int = 3, eps: float = 1e-12) -> Problem:
     a, b = 1.5 * math.pi, 0.5 * math.pi
 
     def u(x, y, z, face=-1):
-        return np.exp(z) * np.sin(a * x) * np.sin(b * y)
+        xp = _xp(x, y, z)
+        return xp.exp(z) * xp.sin(a * x) * xp.sin(b * y)
 
     def grad_u(x, y, z):
-        e = np.exp(z)
-        return (e * a * np.cos(a * x) * np.sin(b * y), e * b * np.sin(a * x) * np.cos(b * y),
-                e * np.sin(a * x) * np.sin(b * y))
+        xp = _xp(x, y, z)
+        e = xp.exp(z)
+        return (e * a * xp.cos(a * x) * xp.sin(b * y), e * b * xp.sin(a * x) * xp.cos(b * y),
+                e * xp.sin(a * x) * xp.sin(b * y))
 
     def f(x, y, z, face=-1):
         return (2.5 * math.pi ** 2 - 1.0) * u(x, y, z)
@@ -147,24 +161,25 @@ def paper_problem3(levels: int = 3, eps: float = 1e-11) -> Problem:
         return x * x + y * y + z * z
 
     def u(x, y, z, face=-1):
+        xp = _xp(x, y, z)
         s = r2(x, y, z)
-        with np.errstate(invalid="ignore", divide="ignore"):
-            v = x * y * z / np.power(s, 0.75)
-        return np.where(s > 0, v, 0.0)
+        ss = xp.where(s > 0, s, 1.0)
+        return xp.where(s > 0, x * y * z / ss ** 0.75, 0.0)
 
     def grad_u(x, y, z):
+        xp = _xp(x, y, z)
         s = r2(x, y, z)
-        with np.errstate(invalid="ignore", divide="ignore"):
-            p = np.power(s, -0.75)
-            q = -1.5 * x * y * z * np.power(s, -1.75)
-        return (np.where(s > 0, y * z * p + q * x, 0.0), np.where(s > 0, x * z * p + q * y, 0.0),
-                np.where(s > 0, x * y * p + q * z, 0.0))
+        ss = xp.where(s > 0, s, 1.0)
+        p = ss ** -0.75
+        q = -1.5 * x * y * z * ss ** -1.75
+        return (xp.where(s > 0, y * z * p + q * x, 0.0), xp.where(s > 0, x * z * p + q * y, 0.0),
+                xp.where(s > 0, x * y * p + q * z, 0.0))
 
     def f(x, y, z, face=-1):
+        xp = _xp(x, y, z)
         s = r2(x, y, z)
-        with np.errstate(invalid="ignore", divide="ignore"):
-            v = 33.0 * x * y * z / (4.0 * np.power(s, 1.75))
-        return np.where(s > 0, v, 0.0)
+        ss = xp.where(s > 0, s, 1.0)
+        return xp.where(s > 0, 33.0 * x * y * z / (4.0 * ss ** 1.75), 0.0)
 
     return Problem("paper-problem-3", (0, 0, 0), (1, 1, 1), (8, 8, 8), levels,
                    (DIRICHLET,) * 6, beta=_const(1.0), f=f, u=u, grad_u=grad_u, eps=eps)
@@ -179,14 +194,17 @@ def smooth_dirichlet_cube(levels: int = 4, eps: float = 1e-10) -> Problem:
     4 levels end at 32^3 elements (35,937 nodes)."""
 
     def u(x, y, z, face=-1):
-        return np.exp(x + y + z)
+        xp = _xp(x, y, z)
+        return xp.exp(x + y + z)
 
     def grad_u(x, y, z):
-        e = np.exp(x + y + z)
+        xp = _xp(x, y, z)
+        e = xp.exp(x + y + z)
         return (e, e, e)
 
     def f(x, y, z, face=-1):
-        return -3.0 * np.exp(x + y + z)
+        xp = _xp(x, y, z)
+        return -3.0 * xp.exp(x + y + z)
 
     return Problem("smooth-dirichlet-cube-4^3", (0, 0, 0), (1, 1, 1), (4, 4, 4), levels,
                    (DIRICHLET,) * 6, beta=_const(1.0), f=f, u=u, grad_u=grad_u, eps=eps)
@@ -199,11 +217,13 @@ def variable_beta_robin_cube(levels: int = 7, eps: float = 1e-8) -> Problem:
     pi = math.pi
 
     def S(x, y, z):
-        return np.sin(pi * x) * np.sin(pi * y) * np.sin(pi * z)
+        xp = _xp(x, y, z)
+        return xp.sin(pi * x) * xp.sin(pi * y) * xp.sin(pi * z)
 
     def gradS(x, y, z):
-        sx, sy, sz = np.sin(pi * x), np.sin(pi * y), np.sin(pi * z)
-        cx, cy, cz = np.cos(pi * x), np.cos(pi * y), np.cos(pi * z)
+        xp = _xp(x, y, z)
+        sx, sy, sz = xp.sin(pi * x), xp.sin(pi * y), xp.sin(pi * z)
+        cx, cy, cz = xp.cos(pi * x), xp.cos(pi * y), xp.cos(pi * z)
         return (pi * cx * sy * sz, pi * sx * cy * sz, pi * sx * sy * cz)
 
     def beta(x, y, z, face=-1):
@@ -235,26 +255,29 @@ def high_contrast_singular_box(levels: int = 6, eps: float = 1e-8) -> Problem:
     tp = 2.0 * math.pi
 
     def beta(x, y, z, face=-1):
-        return np.exp(4.0 * np.sin(tp * x) * np.cos(tp * y)) + 0.0 * z
+        xp = _xp(x, y, z)
+        return xp.exp(4.0 * xp.sin(tp * x) * xp.cos(tp * y)) + 0.0 * z
 
     def grad_beta(x, y, z):
+        xp = _xp(x, y, z)
         b = beta(x, y, z)
-        return (4.0 * tp * b * np.cos(tp * x) * np.cos(tp * y),
-                -4.0 * tp * b * np.sin(tp * x) * np.sin(tp * y), 0.0 * b)
+        return (4.0 * tp * b * xp.cos(tp * x) * xp.cos(tp * y),
+                -4.0 * tp * b * xp.sin(tp * x) * xp.sin(tp * y), 0.0 * b)
 
     def u(x, y, z, face=-1):
-        return np.cbrt(x * x + y * y + z * z)
+        return (x * x + y * y + z * z) ** (1.0 / 3.0)
 
     def grad_u(x, y, z):
+        xp = _xp(x, y, z)
         s = x * x + y * y + z * z
-        with np.errstate(invalid="ignore", divide="ignore"):
-            c = np.where(s > 0, (2.0 / 3.0) / np.power(np.where(s > 0, s, 1.0), 2.0 / 3.0), 0.0)
+        c = xp.where(s > 0, (2.0 / 3.0) / xp.where(s > 0, s, 1.0) ** (2.0 / 3.0), 0.0)
         return (c * x, c * y, c * z)
 
     def f(x, y, z, face=-1):
+        xp = _xp(x, y, z)
         s = x * x + y * y + z * z
-        ss = np.where(s > 0, s, 1.0)
-        m = np.where(s > 0, np.power(ss, -2.0 / 3.0), 0.0)  # r^(-4/3)
+        ss = xp.where(s > 0, s, 1.0)
+        m = xp.where(s > 0, ss ** (-2.0 / 3.0), 0.0)  # r^(-4/3)
         bx, by, bz = grad_beta(x, y, z)
         return -(10.0 / 9.0) * beta(x, y, z) * m - (2.0 / 3.0) * m * (x * bx + y * by + z * bz)
 
@@ -277,19 +300,22 @@ def batched_box(side, n_fine, phi, a, eps: float = 1e-8) -> Problem:
     a2 = a[0] ** 2 + a[1] ** 2 + a[2] ** 2
 
     def beta(x, y, z, face=-1):
-        return 1.0 + 0.5 * np.sin(tp * (x + p1)) * np.sin(tp * (y + p2)) + 0.0 * z
+        xp = _xp(x, y, z)
+        return 1.0 + 0.5 * xp.sin(tp * (x + p1)) * xp.sin(tp * (y + p2)) + 0.0 * z
 
     def u(x, y, z, face=-1):
-        return np.exp(a[0] * x + a[1] * y + a[2] * z)
+        xp = _xp(x, y, z)
+        return xp.exp(a[0] * x + a[1] * y + a[2] * z)
 
     def grad_u(x, y, z):
         e = u(x, y, z)
         return (a[0] * e, a[1] * e, a[2] * e)
 
     def f(x, y, z, face=-1):
+        xp = _xp(x, y, z)
         e = u(x, y, z)
-        bx = 0.5 * tp * np.cos(tp * (x + p1)) * np.sin(tp * (y + p2))
-        by = 0.5 * tp * np.sin(tp * (x + p1)) * np.cos(tp * (y + p2))
+        bx = 0.5 * tp * xp.cos(tp * (x + p1)) * xp.sin(tp * (y + p2))
+        by = 0.5 * tp * xp.sin(tp * (x + p1)) * xp.cos(tp * (y + p2))
         return -e * (beta(x, y, z) * a2 + a[0] * bx + a[1] * by)
 
     n0 = tuple(int(n) // 4 for n in n_fine)
@@ -321,8 +347,9 @@ def serving_request(n_fine: int, phi, k, faces, eps: float = 1e-8) -> Problem:
     k = [float(v) for v in k]
 
     def sb(x, y, z):
-        return (np.sin(tp * (x + p[0])), np.sin(tp * (y + p[1])), np.sin(tp * (z + p[2])),
-                np.cos(tp * (x + p[0])), np.cos(tp * (y + p[1])), np.cos(tp * (z + p[2])))
+        xp = _xp(x, y, z)
+        return (xp.sin(tp * (x + p[0])), xp.sin(tp * (y + p[1])), xp.sin(tp * (z + p[2])),
+                xp.cos(tp * (x + p[0])), xp.cos(tp * (y + p[1])), xp.cos(tp * (z + p[2])))
 
     def beta(x, y, z, face=-1):
         s1, s2, s3, _, _, _ = sb(x, y, z)
@@ -333,15 +360,18 @@ def serving_request(n_fine: int, phi, k, faces, eps: float = 1e-8) -> Problem:
         return (0.75 * tp * c1 * s2 * s3, 0.75 * tp * s1 * c2 * s3, 0.75 * tp * s1 * s2 * c3)
 
     def u(x, y, z, face=-1):
-        return np.sin(k[0] * x + k[1] * y + k[2] * z)
+        xp = _xp(x, y, z)
+        return xp.sin(k[0] * x + k[1] * y + k[2] * z)
 
     def grad_u(x, y, z):
-        c = np.cos(k[0] * x + k[1] * y + k[2] * z)
+        xp = _xp(x, y, z)
+        c = xp.cos(k[0] * x + k[1] * y + k[2] * z)
         return (k[0] * c, k[1] * c, k[2] * c)
 
     def f(x, y, z, face=-1):
+        xp = _xp(x, y, z)
         ph = k[0] * x + k[1] * y + k[2] * z
-        s, c = np.sin(ph), np.cos(ph)
+        s, c = xp.sin(ph), xp.cos(ph)
         bx, by, bz = grad_beta(x, y, z)
         kk = k[0] ** 2 + k[1] ** 2 + k[2] ** 2
         return beta(x, y, z) * kk * s - c * (k[0] * bx + k[1] * by + k[2] * bz)
