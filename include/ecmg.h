@@ -119,6 +119,8 @@ typedef struct {
     int32_t chunk;             /* JCG iterations between host status reads (0 = auto)    */
     int32_t timing;            /* 1 = time kernels with HIP events (ecmg_kernel_times)   */
     void *hip_stream;          /* hipStream_t to order all work on; NULL = own stream    */
+    int64_t persistent_nodes;  /* grids of at most this many nodes run the whole JCG loop
+                                  in one persistent launch; 0 = never, -1 = default     */
 } ecmg_options;
 
 /* Per-level report (Algorithm 4 and the "Iters"/"RRe" columns of Section 5). */
@@ -213,7 +215,8 @@ int ecmg_plan_bytes(const ecmg_problem *problem, int32_t precision, size_t *byte
 
 /* Kernel timing (options.timing = 1): for level `level` and kernel class k
  * (0 = JCG pass A, 1 = JCG pass B, 2 = JCG init, 3 = EXP_finite, 4 = EXP_true,
- * 5 = mixed-precision pass A, 6 = mixed-precision pass B),
+ * 5 = mixed-precision pass A, 6 = mixed-precision pass B, 7 = whole-level
+ * persistent JCG used for small grids),
  * out[0] = total milliseconds and out[1] = launches that did work since the
  * last ecmg_reset_kernel_times.  Measured with HIP events on the library's
  * stream around each launch. */

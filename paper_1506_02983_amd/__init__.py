@@ -27,7 +27,7 @@ DIRICHLET, ROBIN = 0, 1
 FP64, MIXED = 0, 1
 SERENDIPITY20, LAGRANGE27 = 0, 1
 VEC_U, VEC_W, VEC_UTILDE, VEC_F, VEC_DINV, VEC_NONE = 0, 1, 2, 3, 4, -1
-K_PASSA, K_PASSB, K_INIT, K_EXPF, K_EXPT, K_PASSA32, K_PASSB32 = range(7)
+K_PASSA, K_PASSB, K_INIT, K_EXPF, K_EXPT, K_PASSA32, K_PASSB32, K_PERSIST = range(8)
 
 _STATUS = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", ENOTCONV: "ENOTCONV", EBREAKDOWN: "EBREAKDOWN",
            EDEVICE: "EDEVICE", ESTATE: "ESTATE", ECALLBACK: "ECALLBACK"}
@@ -52,7 +52,8 @@ class ProblemC(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("interp", ctypes.c_int32),
                 ("keep_w", ctypes.c_int32), ("inner_tol", ctypes.c_double), ("dsolve_tol", ctypes.c_double),
-                ("chunk", ctypes.c_int32), ("timing", ctypes.c_int32), ("hip_stream", ctypes.c_void_p)]
+                ("chunk", ctypes.c_int32), ("timing", ctypes.c_int32), ("hip_stream", ctypes.c_void_p),
+                ("persistent_nodes", ctypes.c_int64)]
 
 
 class LevelInfo(ctypes.Structure):
@@ -220,13 +221,14 @@ class Solver:
 
     def __init__(self, precision: int = FP64, interp: int = SERENDIPITY20, keep_w: bool = True,
                  max_iter: int = 20000, dsolve_tol: float = 1e-14, inner_tol: float = 1e-4,
-                 chunk: int = 0, timing: bool = False, stream=None):
+                 chunk: int = 0, timing: bool = False, stream=None, persistent_nodes: int = -1):
         self.L = load_library()
         o = Options()
         self.L.ecmg_default_options(ctypes.byref(o))
         o.precision, o.interp, o.keep_w, o.max_iter = precision, interp, int(keep_w), max_iter
         o.dsolve_tol, o.inner_tol, o.chunk, o.timing = dsolve_tol, inner_tol, chunk, int(timing)
         o.hip_stream = stream
+        o.persistent_nodes = persistent_nodes
         self.opt = o
         h = ctypes.c_void_p()
         self._check(self.L.ecmg_create(ctypes.byref(o), ctypes.byref(h)), None)

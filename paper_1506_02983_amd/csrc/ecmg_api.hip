@@ -44,6 +44,11 @@ struct ecmg_ctx {
     double *dstage = nullptr;       // device staging
     int64_t stage_n = 0;
     int KZ = 32;
+    // persistent JCG for grids of at most persist_max nodes
+    int64_t persist_max = 2400000;
+    int persist_blocks = 0;                    // co-resident workgroups (0 = unavailable)
+    PersistentTask *d_task = nullptr;          // device copy of one task
+    unsigned *d_bar = nullptr;                 // barrier words + error flag
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     // kernel timing (options.timing)
     struct Rec { hipEvent_t a, b; int level, kind, iter; };
@@ -374,6 +379,59 @@ static int run_jcg(ecmg_ctx *c, int l, double tol_abs, int max_iter, int fixed, 
     return ECMG_OK;
 }
 
+// Whole JCG loop of one level in one cooperative launch (small grids).
+static int run_jcg_persistent(ecmg_ctx *c, int l, double tol_abs, int max_iter, int fixed, ecmg_level_info *info) {
+    Level &L = c->lv[l];
+    PersistentTask t{};
+    t.g = L.g;
+    t.beta = L.beta;
+    for (int f = 0; f < 6; ++f) t.alpha[f] = L.alpha[f];
+    t.F = L.F;
+    t.dinv = L.dinv;
+    t.x = L.x;
+    t.r = c->r;
+    t.p = c->p0;
+    t.q = c->q;
+    t.partials = c->partials;
+    t.bar = c->d_bar;
+    t.err = (int *)(c->d_bar + 2);
+    t.sc = c->sc;
+    t.tol = tol_abs;
+    t.max_iter = max_iter;
+    t.fixed = fixed;
+    t.wg0 = 0;
+    // about 4 nodes per thread, as many workgroups as stay resident
+    t.nwg = (int)std::min<int64_t>(std::max<int64_t>(1, L.g.nreal / 4096), c->persist_blocks);
+    HIPCHK(c, hipMemsetAsync(c->d_bar, 0, 4 * sizeof(unsigned), c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d_task, &t, sizeof(t), hipMemcpyHostToDevice, c->stream));
+    size_t slot = 0;
+    CHK(rec_begin(c, l, 7, 0, &slot));
+    HIPCHK(c, launch_jcg_persistent(c->d_task, 1, t.nwg, c->stream));
+    CHK(rec_end(c, slot));
+    HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(JcgScalars), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const JcgScalars s = *c->sc_host;
+    CHK(rec_flush(c, 1));
+    if (info) {
+        info->iters = s.iter;
+        info->rre = (L.nf > 0) ? std::sqrt(s.rr) / L.nf : 0.0;
+        info->nf = L.nf;
+        info->status = (s.done == DONE_BREAKDOWN) ? ECMG_EBREAKDOWN
+                       : (s.done == DONE_MAXITER) ? ECMG_ENOTCONV : ECMG_OK;
+    }
+    if (s.done == DONE_BREAKDOWN) return fail(c, ECMG_EBREAKDOWN, "JCG breakdown on level %d", l);
+    if (s.done == DONE_MAXITER)
+        return fail(c, ECMG_ENOTCONV, "JCG reached max_iter = %d on level %d (rre %g)", max_iter, l,
+                    std::sqrt(s.rr) / L.nf);
+    return ECMG_OK;
+}
+
+static int run_level_jcg(ecmg_ctx *c, int l, double tol_abs, int max_iter, int fixed, ecmg_level_info *info) {
+    if (c->persist_blocks > 0 && c->lv[l].g.nreal <= c->persist_max)
+        return run_jcg_persistent(c, l, tol_abs, max_iter, fixed, info);
+    return run_jcg(c, l, tol_abs, max_iter, fixed, info);
+}
+
 static int do_exp_finite(ecmg_ctx *c, int l) {
     Level &L = c->lv[l];
     size_t slot = 0;
@@ -442,6 +500,7 @@ void ecmg_default_options(ecmg_options *o) {
     o->chunk = 0;
     o->timing = 0;
     o->hip_stream = nullptr;
+    o->persistent_nodes = -1;
 }
 
 int ecmg_create(const ecmg_options *opt, ecmg_ctx **out) {
@@ -485,6 +544,17 @@ int ecmg_create(const ecmg_options *opt, ecmg_ctx **out) {
         ecmg_destroy(c);
         return rc;
     }
+    if ((rc = dalloc(c, (void **)&c->d_task, sizeof(PersistentTask))) != ECMG_OK ||
+        (rc = dalloc(c, (void **)&c->d_bar, 4 * sizeof(unsigned))) != ECMG_OK) {
+        ecmg_destroy(c);
+        return rc;
+    }
+    {
+        int per_cu = 0, cus = 0;
+        const int mb = persistent_max_blocks(&per_cu, &cus);
+        c->persist_blocks = mb > 0 ? mb : 0;
+        if (o.persistent_nodes >= 0) c->persist_max = o.persistent_nodes;
+    }
     if (hipMemsetAsync(c->counters, 0, 16 * sizeof(unsigned), c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess ||
         hipHostMalloc((void **)&c->sc_host, sizeof(JcgScalars), hipHostMallocDefault) != hipSuccess ||
@@ -502,6 +572,8 @@ void ecmg_destroy(ecmg_ctx *c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     free_levels(c);
     dfree(c->sc);
+    dfree(c->d_task);
+    dfree(c->d_bar);
     dfree(c->counters);
     dfree(c->dres);
     dfree(c->dstage);
@@ -580,7 +652,7 @@ int ecmg_setup(ecmg_ctx *c, const ecmg_problem *p) {
         CHK(dalloc_n(c, &c->p0, gf.nnodes));
         CHK(dalloc_n(c, &c->p1, gf.nnodes));
         CHK(dalloc_n(c, &c->q, gf.nnodes));
-        int64_t pn = 2 * 4096;
+        int64_t pn = std::max<int64_t>(2 * 4096, 3 * (int64_t)c->persist_blocks);
         for (int l = 0; l < p->levels; ++l) {
             Geom g = make_geom(p, l, lo);
             int a, b, d;
@@ -713,11 +785,11 @@ static int solve_impl(ecmg_ctx *c, double rel_tol, const int32_t *fixed, ecmg_le
         int rc;
         if (l < 2) {
             launch_zero_free(L.g, L.x, c->stream);
-            rc = run_jcg(c, l, c->opt.dsolve_tol * L.nf, 100000, -1, &li);
+            rc = run_level_jcg(c, l, c->opt.dsolve_tol * L.nf, 100000, -1, &li);
             if (rc == ECMG_ENOTCONV) rc = ECMG_OK;  // DSOLVE: the iterate at the cap is kept
         } else {
             CHK(do_exp_finite(c, l));
-            rc = run_jcg(c, l, rel_tol * L.nf, c->opt.max_iter, fixed ? fixed[l] : -1, &li);
+            rc = run_level_jcg(c, l, rel_tol * L.nf, c->opt.max_iter, fixed ? fixed[l] : -1, &li);
         }
         HIPCHK(c, hipEventRecord(c->ev1, c->stream));
         HIPCHK(c, hipEventSynchronize(c->ev1));
@@ -776,7 +848,7 @@ int ecmg_jcg(ecmg_ctx *c, int32_t level, double rel_tol, int32_t fixed_iters, ec
     li.nx = L.g.nx;
     li.ny = L.g.ny;
     li.nz = L.g.nz;
-    const int rc = run_jcg(c, level, rel_tol * L.nf, c->opt.max_iter, fixed_iters, &li);
+    const int rc = run_level_jcg(c, level, rel_tol * L.nf, c->opt.max_iter, fixed_iters, &li);
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (info) *info = li;
     return rc;

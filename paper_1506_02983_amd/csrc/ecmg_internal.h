@@ -105,6 +105,24 @@ struct PassBArgs {
     unsigned *counter;
 };
 
+// One independent JCG solve inside the persistent kernel: a grid, its arrays,
+// its stop control, and the contiguous range of workgroups that works on it.
+struct PersistentTask {
+    Geom g;
+    const double *beta;
+    const double *alpha[6];
+    const double *F;
+    const double *dinv;
+    double *x, *r, *p, *q;
+    double *partials;                 // 3 * nwg
+    unsigned *bar;                    // [count, generation], zero before launch
+    int *err;                         // set when a barrier wait exceeds its budget
+    JcgScalars *sc;                   // result: iterations, ||r||^2, status
+    double tol;                       // stop when !(||r|| > tol)
+    int max_iter, fixed;
+    int wg0, nwg;
+};
+
 // Modes of the tiled stencil kernel.
 enum { MODE_APPLY = 0, MODE_INIT = 1, MODE_PASSA = 2 };
 
@@ -159,6 +177,9 @@ void launch_rhs_norm(const Geom &g, const double *F, const double *Ax0, const do
                      unsigned *counter, double *out, hipStream_t s);
 void launch_norms(const Geom &g, const double *a, const double *b, const double *c, double *partials,
                   unsigned *counter, double *out, hipStream_t s);
+
+int persistent_max_blocks(int *per_cu, int *cus);
+hipError_t launch_jcg_persistent(const PersistentTask *d_tasks, int ntasks, int total_wg, hipStream_t s);
 
 // Block count of the 1-D reduction kernels (fixed so reductions are deterministic).
 int reduce_blocks(int64_t n);

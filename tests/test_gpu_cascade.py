@@ -27,11 +27,12 @@ def _rel(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
-def test_jcg_fixed_iterations_single_level(orc, ecmg):
+@pytest.mark.parametrize("persistent", [-1, 0], ids=["persistent", "tiled"])
+def test_jcg_fixed_iterations_single_level(orc, ecmg, persistent):
     p = workloads.variable_beta_robin_cube(levels=3)
     lv = orc.discretize(p, 2)
     x0 = np.where(lv.dmask == 1, lv.gD, workloads.random_vector(lv.grid.num_nodes, seed=5))
-    with ecmg.Solver() as s:
+    with ecmg.Solver(persistent_nodes=persistent) as s:
         s.setup(p)
         for k in (1, 2, 7, 25):
             s.set(2, ecmg.VEC_U, x0)
@@ -55,13 +56,16 @@ CASES = {
 }
 
 
+@pytest.mark.parametrize("persistent", [-1, 0], ids=["persistent", "tiled"])
 @pytest.mark.parametrize("name", list(CASES))
-def test_cascade_fixed_iterations(orc, ecmg, name):
+def test_cascade_fixed_iterations(orc, ecmg, name, persistent):
+    """Both JCG drivers: the whole-loop persistent kernel (default on these
+    grid sizes) and the tiled two-pass kernels with device-side stop control."""
     p, variant, bound = CASES[name]()
     ref = orc.cascade(p, variant=variant)
     iters = [r.iters for r in ref]
     rows = []
-    with ecmg.Solver(interp=variant) as s:
+    with ecmg.Solver(interp=variant, persistent_nodes=persistent) as s:
         s.setup(p)
         s.solve_fixed(iters)
         for l in range(p.levels):
@@ -78,11 +82,12 @@ def test_cascade_fixed_iterations(orc, ecmg, name):
                 assert row[k] <= bound, (name, row)
 
 
+@pytest.mark.parametrize("persistent", [-1, 0], ids=["persistent", "tiled"])
 @pytest.mark.parametrize("name", list(CASES))
-def test_cascade_normal_mode(orc, ecmg, name):
+def test_cascade_normal_mode(orc, ecmg, name, persistent):
     p, variant, bound = CASES[name]()
     ref = orc.cascade(p, variant=variant)
-    with ecmg.Solver(interp=variant) as s:
+    with ecmg.Solver(interp=variant, persistent_nodes=persistent) as s:
         s.setup(p)
         infos = s.solve(p.eps)
         for l in range(2, p.levels):
@@ -119,9 +124,10 @@ def test_paper_iteration_counts_on_gpu(ecmg):
                 assert info["iters"] == row["iters"], (case["cite"], row["mesh"], info["iters"])
 
 
-def test_deterministic(ecmg):
+@pytest.mark.parametrize("persistent", [-1, 0], ids=["persistent", "tiled"])
+def test_deterministic(ecmg, persistent):
     p = workloads.variable_beta_robin_cube(levels=4)
-    with ecmg.Solver() as s:
+    with ecmg.Solver(persistent_nodes=persistent) as s:
         s.setup(p)
         s.solve(p.eps)
         a = s.extrapolate()
@@ -130,9 +136,10 @@ def test_deterministic(ecmg):
         assert np.array_equal(a, b)
 
 
-def test_not_converged_and_errors(ecmg):
+@pytest.mark.parametrize("persistent", [-1, 0], ids=["persistent", "tiled"])
+def test_not_converged_and_errors(ecmg, persistent):
     p = workloads.smooth_dirichlet_cube(levels=3)
-    with ecmg.Solver(max_iter=1) as s:
+    with ecmg.Solver(max_iter=1, persistent_nodes=persistent) as s:
         s.setup(p)
         infos = s.solve(1e-12, allow_fail=True)
         assert infos[2]["status"] == ecmg.ENOTCONV and infos[2]["iters"] == 1
