@@ -28,9 +28,10 @@ if ROOT not in sys.path:
 METRIC = "unknowns/s to 4th-order accuracy (FP64 vs mixed); JCG HBM GB/s; serve p50/p99"
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 KIND_NAMES = {0: "jcg_pass_a", 1: "jcg_pass_b", 2: "jcg_init", 3: "exp_finite", 4: "exp_true",
-              5: "jcg_pass_a_fp32", 6: "jcg_pass_b_fp32"}
+              5: "jcg_pass_a_fp32", 6: "jcg_pass_b_fp32", 7: "jcg_persistent"}
 KERNEL_SYMBOL = {0: "k_stencil<double, 2>", 1: "k_passB<double>", 2: "k_stencil<double, 1>",
-                 3: "k_exp_finite", 4: "k_exp_true", 5: "k_stencil<float, 2>", 6: "k_passB<float>"}
+                 3: "k_exp_finite", 4: "k_exp_true", 5: "k_stencil<float, 2>", 6: "k_passB<float>",
+                 7: "k_jcg_persistent"}
 
 
 def workload(name):
@@ -49,9 +50,10 @@ def workload(name):
     raise SystemExit("unknown workload %s" % name)
 
 
-def algorithmic_bytes(kind, n, e, n1, n0):
+def algorithmic_bytes(kind, n, e, n1, n0, iters=0):
     """HBM bytes a launch must move at minimum (8-byte values; n nodes, e
-    elements of the level; n1, n0 nodes of the two coarser levels)."""
+    elements of the level; n1, n0 nodes of the two coarser levels; iters JCG
+    iterations inside one persistent launch)."""
     if kind == 0:
         return 8 * (6 * n + e)          # read r, p_old, x, beta; write p, q, x
     if kind == 1:
@@ -59,19 +61,24 @@ def algorithmic_bytes(kind, n, e, n1, n0):
     if kind == 2:
         return 8 * (4 * n + e)          # read x, F, 1/D, beta; write r
     if kind == 3:
-        return 8 * (2 * n + n1 + n0)    # write x and W; read u_{l-1}, u_{l-2}
+        return 8 * (n + n1 + n0)        # write x; read u_{l-1}, u_{l-2} (the W copy is off when timed)
     if kind == 4:
         return 8 * (2 * n + n1)         # read u_l, u_{l-1}; write U~
     if kind == 5:
         return 4 * (6 * n + e)
     if kind == 6:
         return 4 * 4 * n
+    if kind == 7:
+        # init: read x, F, 1/D, beta, write r; per iteration: read r, 1/D, x,
+        # p_old, write x, p (own-node pass), read p, beta, write q (stencil),
+        # read r, q, 1/D, write r; final x update: read x, p, write x
+        return 8 * ((4 * n + e) + iters * (12 * n + e) + 3 * n)
     return 0
 
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("jcg_kernels.hip", "ecmg_internal.h"):
+    for f in ("jcg_kernels.hip", "persistent_kernels.hip", "extrap_kernels.hip", "ecmg_internal.h"):
         with open(os.path.join(ROOT, "paper_1506_02983_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -145,7 +152,7 @@ def main():
     nodes = problem.nodes_at(L)
     elems = n[0] * n[1] * n[2]
 
-    s = E.Solver(interp=args.interp, timing=True)
+    s = E.Solver(interp=args.interp, timing=True, keep_w=False)
     t0 = time.perf_counter()
     s.setup(problem, device_fields=not args.host_fields)
     torch.cuda.synchronize()
@@ -178,11 +185,11 @@ def main():
         ee = nl[0] * nl[1] * nl[2]
         n1 = problem.nodes_at(l - 1) if l >= 1 else 0
         n0 = problem.nodes_at(l - 2) if l >= 2 else 0
-        for k in range(7):
+        for k in range(8):
             ms, cnt = s.kernel_times(l, k)
             if cnt == 0:
                 continue
-            b = algorithmic_bytes(k, nn, ee, n1, n0)
+            b = algorithmic_bytes(k, nn, ee, n1, n0, infos[l]["iters"])
             kernels.append({"level": l, "kernel": KIND_NAMES[k], "kind": k, "launches": cnt, "total_ms": ms,
                             "avg_us": 1e3 * ms / cnt, "bytes_per_launch": b,
                             "gbs": b / (ms / cnt * 1e-3) / 1e9, "nodes": nn})

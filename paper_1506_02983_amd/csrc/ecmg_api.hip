@@ -47,6 +47,8 @@ struct ecmg_ctx {
     // persistent JCG for grids of at most persist_max nodes
     int64_t persist_max = 2400000;
     int persist_blocks = 0;                    // co-resident workgroups (0 = unavailable)
+    int persist_seglen = 0;                    // persistent kernel: nodes per thread along z (0 = by size)
+    int persist_nwg = 256;                     // persistent kernel: most workgroups per task
     PersistentTask *d_task = nullptr;          // device copy of one task
     unsigned *d_bar = nullptr;                 // barrier words + error flag
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -390,19 +392,29 @@ static int run_jcg_persistent(ecmg_ctx *c, int l, double tol_abs, int max_iter, 
     t.dinv = L.dinv;
     t.x = L.x;
     t.r = c->r;
-    t.p = c->p0;
     t.q = c->q;
+    t.p[0] = c->p0;
+    t.p[1] = c->p1;
     t.partials = c->partials;
-    t.bar = c->d_bar;
-    t.err = (int *)(c->d_bar + 2);
+    t.err = (int *)c->d_bar;
+    t.bar = c->d_bar + 16;
     t.sc = c->sc;
     t.tol = tol_abs;
     t.max_iter = max_iter;
     t.fixed = fixed;
     t.wg0 = 0;
-    // about 4 nodes per thread, as many workgroups as stay resident
-    t.nwg = (int)std::min<int64_t>(std::max<int64_t>(1, L.g.nreal / 4096), c->persist_blocks);
-    HIPCHK(c, hipMemsetAsync(c->d_bar, 0, 4 * sizeof(unsigned), c->stream));
+    // one thread per column segment (2 nodes below 131072 nodes, else 4: short
+    // segments spread small grids over more lanes, longer ones save halo
+    // loads), at most persist_nwg workgroups (every barrier costs more with
+    // more of them)
+    const int seg = c->persist_seglen > 0 ? c->persist_seglen : (L.g.nreal < 131072 ? 2 : 4);
+    t.seglen = std::max(1, std::min(seg, L.g.nz + 1));
+    const int64_t nseg = (L.g.nz + t.seglen) / t.seglen;
+    const int64_t units = (int64_t)(L.g.nx + 1) * (L.g.ny + 1) * nseg;
+    t.nwg = (int)std::max<int64_t>(
+        1, std::min<int64_t>({(units + PERSIST_NTP - 1) / PERSIST_NTP, (int64_t)c->persist_nwg,
+                              (int64_t)c->persist_blocks}));
+    HIPCHK(c, hipMemsetAsync(c->d_bar, 0, 32 * sizeof(unsigned), c->stream));
     HIPCHK(c, hipMemcpyAsync(c->d_task, &t, sizeof(t), hipMemcpyHostToDevice, c->stream));
     size_t slot = 0;
     CHK(rec_begin(c, l, 7, 0, &slot));
@@ -427,7 +439,9 @@ static int run_jcg_persistent(ecmg_ctx *c, int l, double tol_abs, int max_iter, 
 }
 
 static int run_level_jcg(ecmg_ctx *c, int l, double tol_abs, int max_iter, int fixed, ecmg_level_info *info) {
-    if (c->persist_blocks > 0 && c->lv[l].g.nreal <= c->persist_max)
+    // the persistent kernel indexes with 32-bit integers
+    if (c->persist_blocks > 0 && c->lv[l].g.nreal <= c->persist_max && c->lv[l].g.nnodes < ((int64_t)1 << 31) &&
+        (int64_t)c->lv[l].g.nx * c->lv[l].g.ny * c->lv[l].g.nz < ((int64_t)1 << 31))
         return run_jcg_persistent(c, l, tol_abs, max_iter, fixed, info);
     return run_jcg(c, l, tol_abs, max_iter, fixed, info);
 }
@@ -528,6 +542,8 @@ int ecmg_create(const ecmg_options *opt, ecmg_ctx **out) {
     ecmg_ctx *c = new ecmg_ctx();
     c->opt = o;
     if (const char *kz = std::getenv("ECMG_KZ")) c->KZ = std::max(1, std::atoi(kz));
+    if (const char *v = std::getenv("ECMG_PERSIST_SEG")) c->persist_seglen = std::max(1, std::atoi(v));
+    if (const char *v = std::getenv("ECMG_PERSIST_NWG")) c->persist_nwg = std::max(1, std::atoi(v));
     if (o.hip_stream) {
         c->stream = (hipStream_t)o.hip_stream;
     } else {
@@ -544,16 +560,17 @@ int ecmg_create(const ecmg_options *opt, ecmg_ctx **out) {
         ecmg_destroy(c);
         return rc;
     }
-    if ((rc = dalloc(c, (void **)&c->d_task, sizeof(PersistentTask))) != ECMG_OK ||
-        (rc = dalloc(c, (void **)&c->d_bar, 4 * sizeof(unsigned))) != ECMG_OK) {
-        ecmg_destroy(c);
-        return rc;
-    }
     {
         int per_cu = 0, cus = 0;
         const int mb = persistent_max_blocks(&per_cu, &cus);
         c->persist_blocks = mb > 0 ? mb : 0;
         if (o.persistent_nodes >= 0) c->persist_max = o.persistent_nodes;
+    }
+    // barrier words: error flag at 0, arrival counter at 16 (its own cache line)
+    if ((rc = dalloc(c, (void **)&c->d_task, sizeof(PersistentTask))) != ECMG_OK ||
+        (rc = dalloc(c, (void **)&c->d_bar, 32 * sizeof(unsigned))) != ECMG_OK) {
+        ecmg_destroy(c);
+        return rc;
     }
     if (hipMemsetAsync(c->counters, 0, 16 * sizeof(unsigned), c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess ||

@@ -113,14 +113,16 @@ struct PersistentTask {
     const double *alpha[6];
     const double *F;
     const double *dinv;
-    double *x, *r, *p, *q;
+    double *x, *r, *q;
+    double *p[2];                     // search directions, ping-pong: iteration k writes p[(k+1)&1]
     double *partials;                 // 3 * nwg
-    unsigned *bar;                    // [count, generation], zero before launch
+    unsigned *bar;                    // arrival counter, zero before launch
     int *err;                         // set when a barrier wait exceeds its budget
     JcgScalars *sc;                   // result: iterations, ||r||^2, status
     double tol;                       // stop when !(||r|| > tol)
     int max_iter, fixed;
     int wg0, nwg;
+    int seglen;                       // z-march length: the nodes of a column are cut into segments
 };
 
 // Modes of the tiled stencil kernel.
@@ -178,6 +180,10 @@ void launch_rhs_norm(const Geom &g, const double *F, const double *Ax0, const do
 void launch_norms(const Geom &g, const double *a, const double *b, const double *c, double *partials,
                   unsigned *counter, double *out, hipStream_t s);
 
+#ifndef ECMG_PERSIST_NTP
+#define ECMG_PERSIST_NTP 512
+#endif
+constexpr int PERSIST_NTP = ECMG_PERSIST_NTP;  // threads per workgroup of the persistent kernel
 int persistent_max_blocks(int *per_cu, int *cus);
 hipError_t launch_jcg_persistent(const PersistentTask *d_tasks, int ntasks, int total_wg, hipStream_t s);
 

@@ -4,11 +4,17 @@
 // Small grids (the DSOLVE levels, coarse JCG levels, and the boxes of a
 // batched solve) are latency-bound when every iteration costs kernel launches
 // and host round trips.  Here each task owns a fixed set of workgroups that
-// stay resident for the whole solve; the phases of one iteration are separated
-// by a task-local barrier (a single workgroup uses __syncthreads only):
-//   A1  x += alpha_{k-1} p_{k-1};  p = D^-1 r + beta_k p          (own nodes)
-//   A2  q = A p (27-point gather from L2), partial p.q  -> alpha_k
-//   B   r -= alpha_k q;  z = D^-1 r;  partials r.z, r.r  -> beta_{k+1}, stop test
+// stay resident for the whole solve; the phases of an iteration are separated
+// by task-wide barriers:
+//   A  x += alpha_{k-1} p_{k-1};  p_k = D^-1 r + beta_k p_{k-1};  q = A p_k;
+//      partial p.q                                      -> alpha_k
+//   B  r -= alpha_k q;  partials r.D^-1 r, r.r          -> beta_{k+1}, stop test
+// Work is cut into column segments (x-y column (i,j), planes k0..k1-1); in the
+// stencil pass a thread marches up its segment holding three planes of the
+// 3x3 neighbourhood in registers.  p ping-pongs between two arrays.  Phase A
+// either stores p_k in an own-node pass and applies the stencil after a
+// barrier, or (ECMG_PERSIST_FUSED) forms the neighbours' p_k on the fly from
+// r, D^-1 and p_{k-1} with the owner's fused multiply-add.
 // Every workgroup of a task sums the per-workgroup partials itself in the same
 // fixed order, so all of them take the same decision and the result does not
 // depend on which other tasks share the launch (batch invariance).
@@ -21,123 +27,201 @@
 
 namespace ecmg {
 
-__device__ __forceinline__ bool pdir(const Geom &g, int i, int j, int k) {
-    return (i == 0 && g.ft[0] == ECMG_DIRICHLET) || (i == g.nx && g.ft[1] == ECMG_DIRICHLET) ||
-           (j == 0 && g.ft[2] == ECMG_DIRICHLET) || (j == g.ny && g.ft[3] == ECMG_DIRICHLET) ||
-           (k == 0 && g.ft[4] == ECMG_DIRICHLET) || (k == g.nz && g.ft[5] == ECMG_DIRICHLET);
+// The integers of a task's grid that the march needs; face types as bit masks
+// (bit f = face f) so that few scalar registers hold them.
+struct PGeom {
+    int nx, ny, nz, sx, sxy, nxy;
+    unsigned dir, robin;
+};
+
+__device__ __forceinline__ bool pdir(const PGeom &g, int i, int j, int k) {
+    return (i == 0 && (g.dir & 1u)) || (i == g.nx && (g.dir & 2u)) || (j == 0 && (g.dir & 4u)) ||
+           (j == g.ny && (g.dir & 8u)) || (k == 0 && (g.dir & 16u)) || (k == g.nz && (g.dir & 32u));
 }
 
-// (A v)_i for node (i,j,k) (not Dirichlet) with neighbours read from global
-// memory: the same Q1 stencil as the tiled kernels (beta per element, Robin
-// face mass), for grids that live in L2 / the Infinity Cache.  Out-of-grid
-// neighbours are read at clamped addresses and masked, so all 35 loads of a
-// node are independent and in flight together.
-__device__ double stencil_gather(const Geom &g, const double *__restrict__ v, const double *__restrict__ beta,
-                                 const double *const *alpha, int i, int j, int k) {
-    const int64_t sx = g.sx, sxy = (int64_t)g.sx * g.sy;
-    const int64_t ex = g.nx, exy = (int64_t)g.nx * g.ny;
-    double b[2][2][2];                                   // [dz][dy][dx]: element (i-1+dx, j-1+dy, k-1+dz)
+constexpr int NTP = PERSIST_NTP;
+constexpr long SPIN_LIMIT = 1L << 22; // polls of the arrival counter before giving up
+
+// Global-memory (address space 1) doubles: the task pointers are loaded from
+// memory, so without this the compiler can only emit flat accesses.
+typedef __attribute__((address_space(1))) double gdouble;
+
+// Barrier over the nwg workgroups of one task: a monotonic arrival counter
+// (zero at launch); barrier number gen completes when it reaches gen * nwg.
+// The comparison is wrap-safe.
+__device__ __forceinline__ void task_barrier(const PersistentTask &t, int nwg, unsigned gen, int *s_err) {
+    __syncthreads();
+    if (nwg > 1 && threadIdx.x == 0) {
+        __threadfence();
+        atomicAdd(t.bar, 1u);
+        const unsigned target = gen * (unsigned)nwg;
+        long n = 0;
+        while ((int)(__hip_atomic_load(t.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) < 0) {
+            __builtin_amdgcn_s_sleep(1);
+            if ((++n & 63) == 0 &&
+                (n > SPIN_LIMIT || __hip_atomic_load(t.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+                *s_err = 1;
+                __hip_atomic_store(t.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+        }
+        __threadfence();
+    }
+    __syncthreads();
+}
+
+// Arrays of one task as global-memory pointers.
+struct TaskArrays {
+    gdouble *X, *R, *Q, *PO, *PN;     // PO = p_{k-1} (read), PN = p_k (written)
+    const gdouble *F, *DI, *BE;
+    const gdouble *AL[6];
+};
+
+enum { MARCH_INIT = 0, MARCH_ITER = 1, MARCH_APPLY = 2 };
+
+// ECMG_PERSIST_FUSED = 1: p_k is formed on the fly inside the stencil pass
+// (two barriers per iteration, three times the loads and about 200 VGPRs);
+// 0 (default, faster on gfx950): an own-node pass stores p_k first and the
+// stencil pass reads it (three barriers per iteration).
+#ifndef ECMG_PERSIST_FUSED
+#define ECMG_PERSIST_FUSED 0
+#endif
+
+// One column segment: node (i, j, k) for k in [k0, k1).
+//   MARCH_INIT: r = F - A x on free nodes (0 on Dirichlet); acc += (r.D^-1 r, r.r)
+//   MARCH_APPLY: q = A p_k with p_k stored; acc[0] += p_k.q
+//   MARCH_ITER: x += alpha p_{k-1} (it > 0); p_k = D^-1 r + beta p_{k-1};
+//               q = A p_k on free nodes (0 on Dirichlet); acc[0] += p_k.q
+// The Q1 stencil is written per plane offset: the elements of the slab below
+// (sm) and above (sp) the node, summed over the 2x2 element columns that hold
+// both the node and each of the 3x3 in-plane neighbours.
+template <int MODE>
+__device__ __forceinline__ void march(const PGeom &g, const double *sC, const double (*sM)[3], const TaskArrays &A,
+                                      int i, int j, int k0, int k1, int it, double alpha, double beta,
+                                      double (&acc)[2]) {
+    const int sx = g.sx, sxy = g.sxy;
+    const int nx = g.nx, ny = g.ny, nz = g.nz, nxy = g.nxy;
+    const int ox[3] = {i > 0 ? -1 : 0, 0, i < nx ? 1 : 0};
+    const int oy[3] = {j > 0 ? -sx : 0, 0, j < ny ? sx : 0};
+    const int base = i + sx * j;
+    const bool ex[2] = {i > 0, i < nx}, ey[2] = {j > 0, j < ny};
+    const int bx[2] = {max(i - 1, 0), min(i, nx - 1)};
+    const int by[2] = {nx * max(j - 1, 0), nx * min(j, ny - 1)};
+
+    auto value = [&](int id) -> double {
+        if (MODE == MARCH_INIT) return A.X[id];
+        if (MODE == MARCH_APPLY) return A.PN[id];
+        const double z = A.DI[id] * A.R[id];
+        return it == 0 ? z : fma(beta, A.PO[id], z);
+    };
+    auto plane = [&](int k, double(&v)[9]) {
+        const int b = base + sxy * k;
 #pragma unroll
-    for (int dz = 0; dz < 2; ++dz)
+        for (int cy = 0; cy < 3; ++cy)
+#pragma unroll
+            for (int cx = 0; cx < 3; ++cx) v[3 * cy + cx] = value(b + ox[cx] + oy[cy]);
+    };
+    // beta of the 2x2 elements between planes kz and kz+1 (0 outside the grid)
+    auto slab = [&](int kz, double(&b)[4]) {
+        const bool okz = kz >= 0 && kz < nz;
+        const int bz = nxy * min(max(kz, 0), nz - 1);
 #pragma unroll
         for (int dy = 0; dy < 2; ++dy)
 #pragma unroll
             for (int dx = 0; dx < 2; ++dx) {
-                const int ie = i - 1 + dx, je = j - 1 + dy, ke = k - 1 + dz;
-                const bool ok = ie >= 0 && ie < g.nx && je >= 0 && je < g.ny && ke >= 0 && ke < g.nz;
-                const double val = beta[min(max(ie, 0), g.nx - 1) + ex * min(max(je, 0), g.ny - 1) +
-                                        exy * min(max(ke, 0), g.nz - 1)];
-                b[dz][dy][dx] = ok ? val : 0.0;
+                const double v = A.BE[bx[dx] + by[dy] + bz];
+                b[2 * dy + dx] = (okz && ex[dx] && ey[dy]) ? v : 0.0;
             }
-    double q = 0.0;
+    };
+    // sum of a slab's elements that hold both the node and in-plane neighbour (cx, cy)
+    auto wsum2 = [](const double(&b)[4], int cx, int cy) -> double {
+        double w = 0.0;
 #pragma unroll
-    for (int oz = -1; oz <= 1; ++oz) {
-        const int kk = min(max(k + oz, 0), g.nz);
+        for (int dy = (cy == 2); dy <= (cy == 0 ? 0 : 1); ++dy)
 #pragma unroll
-        for (int oy = -1; oy <= 1; ++oy) {
-            const int jj = min(max(j + oy, 0), g.ny);
+            for (int dx = (cx == 2); dx <= (cx == 0 ? 0 : 1); ++dx) w += b[2 * dy + dx];
+        return w;
+    };
+    // Robin face mass of face f over the 2x2 face elements around the node;
+    // the in-face neighbour (cp, cq) is read by vat(cp, cq).
+    auto robin = [&](int f, int pi, int np, int qi, int nq, auto vat) -> double {
+        const bool fp[2] = {pi > 0, pi < np}, fq[2] = {qi > 0, qi < nq};
+        const int ap[2] = {max(pi - 1, 0), min(pi, np - 1)};
+        const int aq[2] = {np * max(qi - 1, 0), np * min(qi, nq - 1)};
+        double a[2][2];
 #pragma unroll
-            for (int ox = -1; ox <= 1; ++ox) {
-                const int ii = min(max(i + ox, 0), g.nx);
+        for (int dq = 0; dq < 2; ++dq)
+#pragma unroll
+            for (int dp = 0; dp < 2; ++dp) {
+                const double v = A.AL[f][ap[dp] + aq[dq]];
+                a[dq][dp] = (fp[dp] && fq[dq]) ? v : 0.0;
+            }
+        double s = 0.0;
+#pragma unroll
+        for (int cq = 0; cq < 3; ++cq)
+#pragma unroll
+            for (int cp = 0; cp < 3; ++cp) {
                 double w = 0.0;
 #pragma unroll
-                for (int dz = (oz > 0); dz <= (oz < 0 ? 0 : 1); ++dz)
+                for (int dq = (cq == 2); dq <= (cq == 0 ? 0 : 1); ++dq)
 #pragma unroll
-                    for (int dy = (oy > 0); dy <= (oy < 0 ? 0 : 1); ++dy)
+                    for (int dp = (cp == 2); dp <= (cp == 0 ? 0 : 1); ++dp) w += a[dq][dp];
+                s += sM[f][(cp != 1) + (cq != 1)] * w * vat(cp, cq);
+            }
+        return s;
+    };
+
+    double vm[9], v0[9], vp[9], sm[4], sp[4];
+    plane(max(k0 - 1, 0), vm);
+    plane(k0, v0);
+    slab(k0 - 1, sm);
+    for (int k = k0; k < k1; ++k) {
+        plane(min(k + 1, nz), vp);
+        slab(k, sp);
+        const int id = base + sxy * k;
+        double q = 0.0;
+        if (!pdir(g, i, j, k)) {
 #pragma unroll
-                        for (int dx = (ox > 0); dx <= (ox < 0 ? 0 : 1); ++dx) w += b[dz][dy][dx];
-                // a neighbour outside the grid only meets elements outside the
-                // grid, whose beta is 0: w == 0 there, so the clamped value is
-                // multiplied by zero
-                const int m = (ox != 0) | ((oy != 0) << 1) | ((oz != 0) << 2);
-                q += g.C[m] * w * v[ii + sx * jj + sxy * kk];
+            for (int c = 0; c < 9; ++c) {
+                const int m = ((c % 3) != 1) | (((c / 3) != 1) << 1);
+                const double wm = wsum2(sm, c % 3, c / 3), wp = wsum2(sp, c % 3, c / 3);
+                q += sC[m | 4] * (wm * vm[c] + wp * vp[c]) + sC[m] * ((wm + wp) * v0[c]);
             }
+            // x faces: in-face axes (y, z); y faces: (x, z); z faces: (x, y)
+            auto vyz = [&](int cp, int cq) {
+                return cq == 0 ? vm[3 * cp + 1] : cq == 1 ? v0[3 * cp + 1] : vp[3 * cp + 1];
+            };
+            auto vxz = [&](int cp, int cq) { return cq == 0 ? vm[3 + cp] : cq == 1 ? v0[3 + cp] : vp[3 + cp]; };
+            auto vxy = [&](int cp, int cq) { return v0[3 * cq + cp]; };
+            if (i == 0 && (g.robin & 1u)) q += robin(0, j, ny, k, nz, vyz);
+            if (i == nx && (g.robin & 2u)) q += robin(1, j, ny, k, nz, vyz);
+            if (j == 0 && (g.robin & 4u)) q += robin(2, i, nx, k, nz, vxz);
+            if (j == ny && (g.robin & 8u)) q += robin(3, i, nx, k, nz, vxz);
+            if (k == 0 && (g.robin & 16u)) q += robin(4, i, nx, j, ny, vxy);
+            if (k == nz && (g.robin & 32u)) q += robin(5, i, nx, j, ny, vxy);
         }
-    }
-    // Robin faces through the node
-    const int idx[3] = {i, j, k};
-    const int n[3] = {g.nx, g.ny, g.nz};
-    for (int f = 0; f < 6; ++f) {
-        if (g.ft[f] != ECMG_ROBIN) continue;
-        const int ax = f / 2;
-        if (idx[ax] != ((f & 1) ? n[ax] : 0)) continue;
-        const int pax = (ax == 0) ? 1 : 0, qax = (ax == 2) ? 1 : 2;
-        const int pi = idx[pax], qi = idx[qax], np = n[pax], nq = n[qax];
-        double s = 0.0;
-        for (int dq = 0; dq < 2; ++dq) {
-            const int eq = qi - 1 + dq;
-            if (eq < 0 || eq >= nq) continue;
-            for (int dp = 0; dp < 2; ++dp) {
-                const int ep = pi - 1 + dp;
-                if (ep < 0 || ep >= np) continue;
-                const double a = alpha[f][ep + (int64_t)np * eq];
-                double t = 0.0;
-                for (int bq = 0; bq < 2; ++bq)
-                    for (int bp = 0; bp < 2; ++bp) {
-                        int c3[3] = {i, j, k};
-                        c3[pax] = ep + bp;
-                        c3[qax] = eq + bq;
-                        const int c = (bp != 1 - dp) + (bq != 1 - dq);
-                        t += g.M[f][c] * v[c3[0] + sx * c3[1] + sxy * c3[2]];
-                    }
-                s += a * t;
-            }
-        }
-        q += s;
-    }
-    return q;
-}
-
-constexpr int NTP = 1024;             // threads per workgroup
-constexpr long SPIN_LIMIT = 1L << 24; // polls of a barrier before giving up
-
-// Barrier over the nwg workgroups of one task: sense by generation count.
-__device__ __forceinline__ void task_barrier(const PersistentTask &t, int nwg, int *s_err) {
-    __syncthreads();
-    if (nwg > 1 && threadIdx.x == 0) {
-        unsigned *cnt = t.bar, *gen = t.bar + 1;
-        __threadfence();
-        const unsigned g0 = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned arrived = atomicAdd(cnt, 1u);
-        if (arrived == (unsigned)(nwg - 1)) {
-            __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __threadfence();
-            atomicAdd(gen, 1u);
+        if (MODE == MARCH_INIT) {
+            const double rv = pdir(g, i, j, k) ? 0.0 : A.F[id] - q;
+            A.R[id] = rv;
+            acc[0] += rv * (A.DI[id] * rv);
+            acc[1] += rv * rv;
+        } else if (MODE == MARCH_APPLY) {
+            A.Q[id] = q;
+            acc[0] += v0[4] * q;
         } else {
-            long n = 0;
-            while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g0) {
-                __builtin_amdgcn_s_sleep(2);
-                if (++n > SPIN_LIMIT) {
-                    *s_err = 1;
-                    __hip_atomic_store(t.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    break;
-                }
-            }
+            if (it > 0) A.X[id] += alpha * A.PO[id];
+            A.PN[id] = v0[4];
+            A.Q[id] = q;
+            acc[0] += v0[4] * q;
         }
-        __threadfence();
-        if (__hip_atomic_load(t.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) *s_err = 1;
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+            vm[c] = v0[c];
+            v0[c] = vp[c];
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sm[c] = sp[c];
     }
-    __syncthreads();
 }
 
 __device__ __forceinline__ double wsum(double v) {
@@ -169,8 +253,8 @@ __device__ __forceinline__ void wg_sum(double (&v)[NV], double (*red)[NTP / 64])
 // Task total of NV values: workgroup sums, exchange through the task's partial
 // slots [slot .. slot+NV) x nwg, then the same fixed-order sum in every workgroup.
 template <int NV>
-__device__ __forceinline__ void task_sum(const PersistentTask &t, int w, int nwg, int slot, double (&v)[NV],
-                                         double (*red)[NTP / 64], int *s_err) {
+__device__ __forceinline__ void task_sum(const PersistentTask &t, int w, int nwg, unsigned &gen, int slot,
+                                         double (&v)[NV], double (*red)[NTP / 64], int *s_err) {
     wg_sum<NV>(v, red);
     if (nwg == 1) return;
     if (threadIdx.x == 0) {
@@ -179,7 +263,7 @@ __device__ __forceinline__ void task_sum(const PersistentTask &t, int w, int nwg
             __hip_atomic_store(t.partials + (int64_t)(slot + i) * nwg + w, v[i], __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
     }
-    task_barrier(t, nwg, s_err);
+    task_barrier(t, nwg, ++gen, s_err);
     double s[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) s[i] = 0.0;
@@ -204,32 +288,60 @@ __global__ void __launch_bounds__(NTP) k_jcg_persistent(const PersistentTask *__
         const int mid = (lo + hi + 1) / 2;
         if (tasks[mid].wg0 <= bid) lo = mid; else hi = mid - 1;
     }
-    const PersistentTask t = tasks[lo];
+    const PersistentTask &t = tasks[lo];
     const int w = bid - t.wg0, nwg = t.nwg;
-    const Geom &g = t.g;
+    // stencil and face-mass coefficients in LDS (uniform reads), the rest of
+    // the grid as a few integers
+    __shared__ double sC[8], sM[6][3];
+    if (threadIdx.x < 8) sC[threadIdx.x] = t.g.C[threadIdx.x];
+    if (threadIdx.x < 18) sM[threadIdx.x / 3][threadIdx.x % 3] = t.g.M[threadIdx.x / 3][threadIdx.x % 3];
+    PGeom g;
+    g.nx = t.g.nx;
+    g.ny = t.g.ny;
+    g.nz = t.g.nz;
+    g.sx = t.g.sx;
+    g.sxy = t.g.sx * t.g.sy;
+    g.nxy = t.g.nx * t.g.ny;
+    g.dir = 0;
+    g.robin = 0;
+    for (int f = 0; f < 6; ++f) {
+        if (t.g.ft[f] == ECMG_DIRICHLET) g.dir |= 1u << f;
+        if (t.g.ft[f] == ECMG_ROBIN) g.robin |= 1u << f;
+    }
     if (threadIdx.x == 0) s_err = 0;
     __syncthreads();
 
-    // rows [r0, r1) of this workgroup; row = j + sy*k
-    const int64_t rows = (int64_t)g.sy * (g.nz + 1);
-    const int64_t r0 = rows * w / nwg, r1 = rows * (w + 1) / nwg;
-    const int64_t sx = g.sx;
-    const int width = g.nx + 1;
-    const int64_t n_own = (r1 - r0) * width;
+    TaskArrays A;
+    A.X = (gdouble *)t.x;
+    A.R = (gdouble *)t.r;
+    A.Q = (gdouble *)t.q;
+    A.F = (const gdouble *)t.F;
+    A.DI = (const gdouble *)t.dinv;
+    A.BE = (const gdouble *)t.beta;
+#pragma unroll
+    for (int f = 0; f < 6; ++f) A.AL[f] = (const gdouble *)t.alpha[f];
 
-    // init: r = F - A x on free nodes, z = D^-1 r; rho = r.z, rr = r.r
-    double acc[2] = {0.0, 0.0};
-    for (int64_t e = threadIdx.x; e < n_own; e += NTP) {
-        const int64_t row = r0 + e / width;
-        const int i = (int)(e % width), j = (int)(row % g.sy), k = (int)(row / g.sy);
-        const int64_t id = i + sx * row;
-        double rv = 0.0;
-        if (!pdir(g, i, j, k)) rv = t.F[id] - stencil_gather(g, t.x, t.beta, t.alpha, i, j, k);
-        t.r[id] = rv;
-        acc[0] += rv * (t.dinv[id] * rv);
-        acc[1] += rv * rv;
+    // work units: (column, segment), columns fastest so that neighbouring
+    // lanes take neighbouring x
+    const int width = g.nx + 1;
+    const int ncol = width * (g.ny + 1);
+    const int seglen = t.seglen;
+    const int nseg = (g.nz + seglen) / seglen;
+    const int nunits = ncol * nseg;
+    const int stride = nwg * NTP;
+    const int sx = g.sx, sxy = g.sxy;
+#define FOR_UNITS(body)                                                                   \
+    for (int u = w * NTP + (int)threadIdx.x; u < nunits; u += stride) {                   \
+        const int c = u % ncol, sg = u / ncol;                                            \
+        const int i = c % width, j = c / width;                                           \
+        const int k0 = sg * seglen, k1 = min(k0 + seglen, g.nz + 1);                      \
+        body                                                                              \
     }
-    task_sum<2>(t, w, nwg, 1, acc, red, &s_err);
+
+    unsigned gen = 0;                  // barriers passed by this workgroup
+    double acc[2] = {0.0, 0.0};
+    FOR_UNITS(march<MARCH_INIT>(g, sC, sM, A, i, j, k0, k1, 0, 0.0, 0.0, acc);)
+    task_sum<2>(t, w, nwg, gen, 1, acc, red, &s_err);
     double rho = acc[0], rr = acc[1], alpha = 0.0, beta = 0.0;
     int it = 0, done = 0;
     const int fixed = t.fixed, max_iter = t.max_iter;
@@ -240,62 +352,69 @@ __global__ void __launch_bounds__(NTP) k_jcg_persistent(const PersistentTask *__
         return it >= max_iter ? DONE_MAXITER : DONE_RUNNING;
     };
     done = stop(rr);
-    int pending = 0;
     while (!done && !s_err) {
-        // A1: deferred x update and the new search direction, own nodes
-        for (int64_t e = threadIdx.x; e < n_own; e += NTP) {
-            const int64_t row = r0 + e / width;
-            const int64_t id = (e % width) + sx * row;
-            const double z = t.dinv[id] * t.r[id];
-            if (it == 0) {
-                t.p[id] = z;
-            } else {
-                const double po = t.p[id];
-                t.x[id] += alpha * po;
-                t.p[id] = z + beta * po;
+        // A: x, p, q = A p, p.q
+        // (a select, not an index: indexing would put the task copy in scratch)
+        A.PO = (gdouble *)((it & 1) ? t.p[1] : t.p[0]);
+        A.PN = (gdouble *)((it & 1) ? t.p[0] : t.p[1]);
+        double pq[2] = {0.0, 0.0};
+#if ECMG_PERSIST_FUSED
+        FOR_UNITS(march<MARCH_ITER>(g, sC, sM, A, i, j, k0, k1, it, alpha, beta, pq);)
+#else
+        FOR_UNITS({
+            gdouble *__restrict__ Xr = A.X;
+            gdouble *__restrict__ Pn = A.PN;
+            const gdouble *__restrict__ Po = A.PO;
+            const gdouble *__restrict__ Rr = A.R;
+            const gdouble *__restrict__ Dr = A.DI;
+            int id = i + sx * j + sxy * k0;
+            for (int k = k0; k < k1; ++k, id += sxy) {
+                const double z = Dr[id] * Rr[id];
+                if (it == 0) {
+                    Pn[id] = z;
+                } else {
+                    const double po = Po[id];
+                    Xr[id] += alpha * po;
+                    Pn[id] = fma(beta, po, z);
+                }
             }
-        }
-        pending = 0;
-        task_barrier(t, nwg, &s_err);
-        // A2: q = A p, p.q
-        double pq[1] = {0.0};
-        for (int64_t e = threadIdx.x; e < n_own; e += NTP) {
-            const int64_t row = r0 + e / width;
-            const int i = (int)(e % width), j = (int)(row % g.sy), k = (int)(row / g.sy);
-            const int64_t id = i + sx * row;
-            double qv = 0.0;
-            if (!pdir(g, i, j, k)) qv = stencil_gather(g, t.p, t.beta, t.alpha, i, j, k);
-            t.q[id] = qv;
-            pq[0] += t.p[id] * qv;
-        }
-        task_sum<1>(t, w, nwg, 0, pq, red, &s_err);
-        if (!(pq[0] > 0.0) || !isfinite(pq[0])) { done = DONE_BREAKDOWN; break; }
-        alpha = rho / pq[0];
-        // B: r -= alpha q; z = D^-1 r; r.z, r.r
+        })
+        task_barrier(t, nwg, ++gen, &s_err);
+        FOR_UNITS(march<MARCH_APPLY>(g, sC, sM, A, i, j, k0, k1, it, alpha, beta, pq);)
+#endif
+        double pqs[1] = {pq[0]};
+        task_sum<1>(t, w, nwg, gen, 0, pqs, red, &s_err);
+        if (!(pqs[0] > 0.0) || !isfinite(pqs[0])) { done = DONE_BREAKDOWN; break; }
+        alpha = rho / pqs[0];
+        // B: r -= alpha q; r.D^-1 r, r.r
         double s2[2] = {0.0, 0.0};
-        for (int64_t e = threadIdx.x; e < n_own; e += NTP) {
-            const int64_t row = r0 + e / width;
-            const int64_t id = (e % width) + sx * row;
-            const double rv = t.r[id] - alpha * t.q[id];
-            t.r[id] = rv;
-            s2[0] += rv * (t.dinv[id] * rv);
-            s2[1] += rv * rv;
-        }
-        task_sum<2>(t, w, nwg, 1, s2, red, &s_err);
+        FOR_UNITS({
+            gdouble *__restrict__ Rr = A.R;
+            const gdouble *__restrict__ Qr = A.Q;
+            const gdouble *__restrict__ Dr = A.DI;
+            int id = i + sx * j + sxy * k0;
+            for (int k = k0; k < k1; ++k, id += sxy) {
+                const double rv = Rr[id] - alpha * Qr[id];
+                Rr[id] = rv;
+                s2[0] += rv * (Dr[id] * rv);
+                s2[1] += rv * rv;
+            }
+        })
+        task_sum<2>(t, w, nwg, gen, 1, s2, red, &s_err);
         ++it;
         beta = s2[0] / rho;
         rho = s2[0];
         rr = s2[1];
-        pending = 1;
         done = stop(rr);
     }
-    if (pending) {                     // x += alpha p of the last iteration
-        for (int64_t e = threadIdx.x; e < n_own; e += NTP) {
-            const int64_t row = r0 + e / width;
-            const int64_t id = (e % width) + sx * row;
-            t.x[id] += alpha * t.p[id];
-        }
+    if (it > 0 && done != DONE_BREAKDOWN) {   // x += alpha p of the last completed iteration
+        const gdouble *PL = (const gdouble *)((it & 1) ? t.p[1] : t.p[0]);
+        FOR_UNITS({
+            int id = i + sx * j + sxy * k0;
+            for (int k = k0; k < k1; ++k, id += sxy) A.X[id] += alpha * PL[id];
+        })
     }
+#undef FOR_UNITS
     if (w == 0 && threadIdx.x == 0) {
         JcgScalars *sc = t.sc;
         sc->iter = it;
