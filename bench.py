@@ -124,6 +124,41 @@ def cpu_baseline(problem, levels, precision_interp=0):
                           levels, "x".join(map(str, p.n_at(levels - 1))), nodes, dt, [r.iters for r in res])}
 
 
+def precision_comparison(E, torch, name="high-contrast-513x257x257", steps=3):
+    """FP64 and mixed precision on the same GPU and workload: ms per step
+    (solve + finest EXP_true) and max-norm errors of U and U~ vs the exact
+    solution on the finest grid."""
+    problem, desc = workload(name)
+    L = problem.levels - 1
+    nodes = problem.nodes_at(L)
+    res = {"workload": desc}
+    for prec, tag in ((E.FP64, "fp64"), (E.MIXED, "mixed")):
+        with E.Solver(precision=prec, keep_w=False) as s:
+            s.setup(problem, device_fields=True)
+            s.solve(problem.eps)
+            s.extrapolate(L, out=False)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                infos = s.solve(problem.eps)
+                s.extrapolate(L, out=False)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            ue = exact_on_device(problem, problem.n_at(L))
+            eu, _ = s.norms(L, E.VEC_U, minus=ue)
+            et, _ = s.norms(L, E.VEC_UTILDE, minus=ue)
+            del ue
+            res[tag] = {"ms_per_step": 1e3 * dt, "value": nodes / dt, "U_max": eu, "Ut_max": et,
+                        "iters": [i["iters"] for i in infos], "outer_steps": [i["outer_steps"] for i in infos]}
+        torch.cuda.empty_cache()
+        print("bench: %s on %s: %.2f ms/step, |U-u| %.3e, |U~-u| %.3e" % (tag, name, 1e3 * dt, eu, et),
+              file=sys.stderr, flush=True)
+    res["speedup_mixed"] = res["fp64"]["ms_per_step"] / res["mixed"]["ms_per_step"]
+    res["error_ratio_U"] = res["mixed"]["U_max"] / res["fp64"]["U_max"]
+    res["error_ratio_Ut"] = res["mixed"]["Ut_max"] / res["fp64"]["Ut_max"]
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -139,6 +174,8 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run one device copy kernel (read BYTES, write BYTES) and exit: the reference "
                          "for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE")
+    ap.add_argument("--no-precision-comparison", action="store_true",
+                    help="skip the FP64 vs mixed comparison on the high-contrast workload")
     ap.add_argument("--no-fourth-order", action="store_true",
                     help="skip the search for the eps that keeps the extrapolation fourth order")
     args = ap.parse_args()
@@ -274,6 +311,12 @@ def main():
                 break
         torch.cuda.empty_cache()
 
+    s.close()
+    torch.cuda.empty_cache()
+    prec_cmp = None
+    if not args.no_precision_comparison:
+        prec_cmp = precision_comparison(E, torch)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(problem.with_(eps=eps), min(args.cpu_levels, problem.levels), args.interp)
@@ -291,13 +334,13 @@ def main():
         "cpu_baseline": cpu,
         "jcg_hbm_gbs_finest": jcg_gbs,
         "fourth_order": fourth,
+        "precision_comparison": prec_cmp,
         "setup_s": setup_s,
         "levels": [{"level": i["level"], "n": [i["nx"], i["ny"], i["nz"]], "iters": i["iters"],
                     "rre": i["rre"], "ms": i["ms"]} for i in infos],
         "errors": errors,
         "kernels": [{k: (round(v, 3) if isinstance(v, float) else v) for k, v in r.items()} for r in kernels],
     }
-    s.close()
     print(json.dumps(out))
 
 

@@ -55,7 +55,13 @@ extern "C" {
 #define ECMG_FP64  0   /* everything in FP64                                          */
 #define ECMG_MIXED 1   /* FP32 stencil and CG vectors inside an FP64 residual /
                           iterative-refinement loop; dots, stopping test, DSOLVE,
-                          EXP_finite and EXP_true stay FP64                         */
+                          EXP_finite and EXP_true stay FP64.  Per JCG level solved
+                          by the tiled kernels: r = F - A x in FP64 (the stop
+                          test of Algorithm 4 is taken on it), FP32 JCG on
+                          A d = r / ||r|| from d = 0 until its residual falls by
+                          max(inner_tol, eps ||f_h|| / (2 ||r||)), x += ||r|| d in
+                          FP64, repeated.  Levels solved by the persistent kernel
+                          (small grids) run in FP64.                                */
 
 /* ---- EXP_finite interpolation (Section 4.3) --------------------------- */
 #define ECMG_SERENDIPITY20 0   /* 8 corners (eq. jiedian) + 12 mid-edges (eq. zhongdian)
@@ -171,6 +177,23 @@ int ecmg_solve_fixed(ecmg_ctx *ctx, const int32_t *iters, ecmg_level_info *info)
  * receives U~_l. */
 int ecmg_extrapolate(ecmg_ctx *ctx, int32_t level, double *host_out);
 
+/* Algorithm 4 for n independent problems at once (each context set up with
+ * its own problem, all on one device, none repeated).  Level by level over all
+ * contexts: DSOLVE / EXP_finite per box, then the JCG of every box on that
+ * level in one launch, one workgroup per box, boxes with more nodes first.
+ * Per box the arithmetic is that of ecmg_solve with the persistent kernel on a
+ * single workgroup, so a box's result does not depend on the other boxes of
+ * the batch (it equals a batch of that box alone bit for bit).  Work runs on
+ * ctxs[0]'s stream (the other contexts' streams are synchronised first).
+ * infos: NULL, or sum(levels of ctxs[i]) entries, box after box in input
+ * order.  FP64 only (options.precision is ignored).  Returns ECMG_ENOTCONV /
+ * ECMG_EBREAKDOWN if some box failed (all boxes still run; see infos). */
+int ecmg_solve_batch(ecmg_ctx *const *ctxs, int32_t n, double rel_tol, ecmg_level_info *infos);
+
+/* EXP_true on the finest level of n contexts, enqueued on ctxs[0]'s stream
+ * without a host round trip per box; returns when all are done. */
+int ecmg_extrapolate_batch(ecmg_ctx *const *ctxs, int32_t n);
+
 /* EXP_finite alone: W_l from the current u_{l-1} and u_{l-2} (2 <= level);
  * writes W_l into u_l on free nodes (Dirichlet nodes keep g_D) and into the W
  * vector when kept.  Used for testing and for resuming a cascade. */
@@ -216,7 +239,8 @@ int ecmg_plan_bytes(const ecmg_problem *problem, int32_t precision, size_t *byte
 /* Kernel timing (options.timing = 1): for level `level` and kernel class k
  * (0 = JCG pass A, 1 = JCG pass B, 2 = JCG init, 3 = EXP_finite, 4 = EXP_true,
  * 5 = mixed-precision pass A, 6 = mixed-precision pass B, 7 = whole-level
- * persistent JCG used for small grids),
+ * persistent JCG used for small grids, 8 = mixed-precision start (r / ||r||
+ * to FP32), 9 = mixed-precision update x += ||r|| d),
  * out[0] = total milliseconds and out[1] = launches that did work since the
  * last ecmg_reset_kernel_times.  Measured with HIP events on the library's
  * stream around each launch. */

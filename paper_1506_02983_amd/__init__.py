@@ -27,7 +27,7 @@ DIRICHLET, ROBIN = 0, 1
 FP64, MIXED = 0, 1
 SERENDIPITY20, LAGRANGE27 = 0, 1
 VEC_U, VEC_W, VEC_UTILDE, VEC_F, VEC_DINV, VEC_NONE = 0, 1, 2, 3, 4, -1
-K_PASSA, K_PASSB, K_INIT, K_EXPF, K_EXPT, K_PASSA32, K_PASSB32, K_PERSIST = range(8)
+K_PASSA, K_PASSB, K_INIT, K_EXPF, K_EXPT, K_PASSA32, K_PASSB32, K_PERSIST, K_MIXSTART, K_MIXUPDATE = range(10)
 
 _STATUS = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", ENOTCONV: "ENOTCONV", EBREAKDOWN: "EBREAKDOWN",
            EDEVICE: "EDEVICE", ESTATE: "ESTATE", ECALLBACK: "ECALLBACK"}
@@ -70,7 +70,8 @@ class LevelInfo(ctypes.Structure):
 EXPORTS = ["ecmg_default_options", "ecmg_create", "ecmg_setup", "ecmg_solve", "ecmg_solve_fixed",
            "ecmg_extrapolate", "ecmg_prolongate", "ecmg_jcg", "ecmg_apply", "ecmg_get", "ecmg_set",
            "ecmg_device_view", "ecmg_norms", "ecmg_level_dims", "ecmg_plan_bytes", "ecmg_kernel_times",
-           "ecmg_reset_kernel_times", "ecmg_last_error", "ecmg_destroy"]
+           "ecmg_reset_kernel_times", "ecmg_last_error", "ecmg_destroy", "ecmg_solve_batch",
+           "ecmg_extrapolate_batch"]
 
 _lib = None
 
@@ -113,6 +114,8 @@ def load_library(path: str = LIB_PATH):
     L.ecmg_last_error.restype = ctypes.c_char_p
     L.ecmg_destroy.argtypes = [P]
     L.ecmg_destroy.restype = None
+    L.ecmg_solve_batch.argtypes = [P, i32, dbl, P]
+    L.ecmg_extrapolate_batch.argtypes = [P, i32]
     for name in EXPORTS:
         getattr(L, name)
     _lib = L
@@ -363,6 +366,35 @@ class Solver:
 
     def reset_kernel_times(self):
         self._check(self.L.ecmg_reset_kernel_times(self.h))
+
+
+def solve_batch(solvers: Sequence["Solver"], rel_tol: float, allow_fail: bool = False) -> List[List[dict]]:
+    """ecmg_solve_batch over set-up solvers; returns each box's level infos."""
+    L = load_library()
+    n = len(solvers)
+    handles = (ctypes.c_void_p * n)(*[s.h for s in solvers])
+    total = sum(s.levels for s in solvers)
+    info = (LevelInfo * total)()
+    rc = L.ecmg_solve_batch(handles, n, float(rel_tol), info)
+    if rc != OK and not allow_fail:
+        msg = L.ecmg_last_error(solvers[0].h)
+        raise EcmgError(rc, (msg or b"").decode())
+    out, k = [], 0
+    for s in solvers:
+        out.append([info[k + l].as_dict() for l in range(s.levels)])
+        k += s.levels
+    return out
+
+
+def extrapolate_batch(solvers: Sequence["Solver"]) -> None:
+    """ecmg_extrapolate_batch: EXP_true on the finest level of every solver."""
+    L = load_library()
+    n = len(solvers)
+    handles = (ctypes.c_void_p * n)(*[s.h for s in solvers])
+    rc = L.ecmg_extrapolate_batch(handles, n)
+    if rc != OK:
+        msg = L.ecmg_last_error(solvers[0].h)
+        raise EcmgError(rc, (msg or b"").decode())
 
 
 def plan_bytes(problem, precision: int = FP64) -> int:

@@ -24,6 +24,14 @@ struct ecmg_ctx {
     ecmg_options opt{};
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    int device = 0;
+    // batched solves led by this context: task and scalar arrays for the queue kernel
+    PersistentTask *bt_tasks = nullptr;
+    JcgScalars *bt_sc = nullptr, *bt_sc_host = nullptr;
+    unsigned *bt_next = nullptr;              // queue counter
+    unsigned *bt_bar = nullptr;               // 32 barrier words per box (error flag, counter)
+    ExpTask *bt_exp = nullptr;                // batched EXP_finite / EXP_true boxes
+    int bt_cap = 0;
     std::string err;
     std::vector<Level> lv;
     int nlev = 0;
@@ -32,6 +40,9 @@ struct ecmg_ctx {
     bool solved = false;       // u of every level available
     // shared JCG scratch, sized for the finest level
     double *r = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr;
+    // mixed precision: FP32 work vectors of the inner JCG (finest size) and its scalars
+    float *r32 = nullptr, *p32a = nullptr, *p32b = nullptr, *q32 = nullptr, *d32 = nullptr;
+    JcgScalars *sc32 = nullptr;
     int64_t scratch_n = 0;
     JcgScalars *sc = nullptr;  // device
     JcgScalars *sc_host = nullptr;  // pinned
@@ -49,6 +60,8 @@ struct ecmg_ctx {
     int persist_blocks = 0;                    // co-resident workgroups (0 = unavailable)
     int persist_seglen = 0;                    // persistent kernel: nodes per thread along z (0 = by size)
     int persist_nwg = 256;                     // persistent kernel: most workgroups per task
+    int queue_blocks = 0;                      // co-resident workgroups of the queue kernel
+    int batch_npw = 8192;                      // batched solves: nodes per workgroup of a box
     PersistentTask *d_task = nullptr;          // device copy of one task
     unsigned *d_bar = nullptr;                 // barrier words + error flag
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -317,6 +330,135 @@ static StencilArgs<double> stencil_args(ecmg_ctx *c, Level &L) {
     return a;
 }
 
+// Enqueue JCG iterations (pass A, pass B) in chunks until the device sets
+// `done`: one status read per chunk; the chunk doubles up to 64 (fixed-
+// iteration mode enqueues all iterations at once).  Leaves the final scalars in
+// c->sc_host.  kind_a / kind_b name the timing classes.
+template <typename T>
+static int jcg_chunks(ecmg_ctx *c, int l, const StencilArgs<T> &a, const PassBArgs<T> &b, int nbB, JcgScalars *sc,
+                      int fixed, int kind_a, int kind_b) {
+    int done_iters = 0;
+    int chunk = c->opt.chunk > 0 ? c->opt.chunk : 2;
+    if (fixed >= 0) chunk = std::max(fixed, 1);
+    size_t slot = 0;
+    for (;;) {
+        HIPCHK(c, hipMemcpyAsync(c->sc_host, sc, sizeof(JcgScalars), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        if (c->sc_host->done) break;
+        done_iters = c->sc_host->iter;
+        for (int t = 0; t < chunk; ++t) {
+            CHK(rec_begin(c, l, kind_a, done_iters + t, &slot));
+            launch_stencil<T>(MODE_PASSA, a, c->stream);
+            CHK(rec_end(c, slot));
+            CHK(rec_begin(c, l, kind_b, done_iters + t, &slot));
+            launch_passB<T>(b, nbB, c->stream);
+            CHK(rec_end(c, slot));
+        }
+        HIPCHK(c, hipGetLastError());
+        if (c->opt.chunk <= 0 && fixed < 0) chunk = std::min(chunk * 2, 64);
+    }
+    return ECMG_OK;
+}
+
+// Mixed precision (FP32 stencil and CG vectors, FP64 dot products, FP64
+// residual and iterate): iterative refinement around an FP32 JCG.
+//   r = F - A x in FP64 (the stop test of Algorithm 4 is taken on it);
+//   s = ||r||_2;  FP32 JCG on A d = r / s from d = 0 until its residual is
+//   below max(inner_tol, tol / (2 ||r||)) of the start;  x += s d in FP64.
+static int run_jcg_mixed(ecmg_ctx *c, int l, double tol_abs, int max_iter, ecmg_level_info *info) {
+    Level &L = c->lv[l];
+    StencilArgs<double> a = stencil_args(c, L);
+    a.v = L.x;
+    a.r = c->r;
+    StencilArgs<float> a32{};
+    a32.g = L.g;
+    a32.KZ = a.KZ;
+    a32.ntx = a.ntx;
+    a32.nty = a.nty;
+    a32.nkz = a.nkz;
+    a32.beta = L.beta32;
+    for (int f = 0; f < 6; ++f) a32.alpha[f] = L.alpha32[f];
+    a32.dinv = L.dinv32;
+    a32.r = c->r32;
+    a32.q = c->q32;
+    a32.x = c->d32;
+    a32.p0 = c->p32a;
+    a32.p1 = c->p32b;
+    a32.sc = c->sc32;
+    a32.partials = c->partials;
+    a32.counter = c->counters;
+    PassBArgs<float> b32{};
+    b32.n = L.g.nnodes;
+    b32.r = c->r32;
+    b32.q = c->q32;
+    b32.dinv = L.dinv32;
+    b32.sc = c->sc32;
+    b32.partials = c->partials;
+    b32.counter = c->counters + 1;
+    const int nbB = reduce_blocks(L.g.nnodes);
+    const int max_outer = 100;
+    int inner_total = 0, outer = 0, status = ECMG_OK;
+    double rn = 0.0;
+    size_t slot = 0;
+    launch_zero_pad(L.g, c->r, nullptr, nullptr, nullptr, c->stream);
+    launch_zero_pad_f32(L.g, c->q32, c->p32a, c->p32b, c->stream);
+    for (;;) {
+        launch_jcg_reset(c->sc, tol_abs, 0, -1, c->stream);
+        CHK(rec_begin(c, l, 2, 0, &slot));
+        launch_stencil<double>(MODE_INIT, a, c->stream);
+        CHK(rec_end(c, slot));
+        HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(JcgScalars), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        rn = std::sqrt(c->sc_host->rr);
+        if (!(rn > tol_abs)) break;
+        if (!std::isfinite(rn)) {
+            status = ECMG_EBREAKDOWN;
+            break;
+        }
+        if (outer >= max_outer || inner_total >= max_iter) {
+            status = ECMG_ENOTCONV;
+            break;
+        }
+        const double tol_in = std::max(c->opt.inner_tol, 0.5 * tol_abs / rn);
+        launch_jcg_reset(c->sc32, tol_in, max_iter - inner_total, -1, c->stream);
+        CHK(rec_begin(c, l, 8, 0, &slot));
+        launch_mixed_start(L.g, c->r, 1.0 / rn, L.dinv32, c->r32, c->d32, c->sc32, c->partials, c->counters + 3,
+                           c->stream);
+        CHK(rec_end(c, slot));
+        HIPCHK(c, hipGetLastError());
+        CHK(jcg_chunks<float>(c, l, a32, b32, nbB, c->sc32, -1, 5, 6));
+        const JcgScalars s = *c->sc_host;
+        CHK(rec_begin(c, l, 9, 0, &slot));
+        launch_mixed_update(L.g, L.x, rn, c->d32, c->p32a, c->p32b, c->sc32, c->stream);
+        CHK(rec_end(c, slot));
+        HIPCHK(c, hipGetLastError());
+        CHK(rec_flush(c, s.iter));
+        inner_total += s.iter;
+        ++outer;
+        if (s.done == DONE_BREAKDOWN) {
+            status = ECMG_EBREAKDOWN;
+            break;
+        }
+        if (s.iter == 0) {               // FP32 cannot reduce this residual further
+            status = ECMG_ENOTCONV;
+            break;
+        }
+    }
+    CHK(rec_flush(c, 1));
+    if (info) {
+        info->iters = inner_total;
+        info->outer_steps = outer;
+        info->rre = (L.nf > 0) ? rn / L.nf : 0.0;
+        info->nf = L.nf;
+        info->status = status;
+    }
+    if (status == ECMG_EBREAKDOWN) return fail(c, status, "mixed JCG breakdown on level %d", l);
+    if (status == ECMG_ENOTCONV)
+        return fail(c, status, "mixed JCG did not reach the tolerance on level %d (rre %g after %d outer steps)", l,
+                    rn / L.nf, outer);
+    return ECMG_OK;
+}
+
 static int run_jcg(ecmg_ctx *c, int l, double tol_abs, int max_iter, int fixed, ecmg_level_info *info) {
     Level &L = c->lv[l];
     launch_jcg_reset(c->sc, tol_abs, max_iter, fixed, c->stream);
@@ -344,25 +486,7 @@ static int run_jcg(ecmg_ctx *c, int l, double tol_abs, int max_iter, int fixed, 
     b.counter = c->counters + 1;
     const int nbB = reduce_blocks(L.g.nnodes);
 
-    int done_iters = 0;
-    int chunk = c->opt.chunk > 0 ? c->opt.chunk : 2;
-    if (fixed >= 0) chunk = std::max(fixed, 1);
-    for (;;) {
-        HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(JcgScalars), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        if (c->sc_host->done) break;
-        done_iters = c->sc_host->iter;
-        for (int t = 0; t < chunk; ++t) {
-            CHK(rec_begin(c, l, 0, done_iters + t, &slot));
-            launch_stencil<double>(MODE_PASSA, a, c->stream);
-            CHK(rec_end(c, slot));
-            CHK(rec_begin(c, l, 1, done_iters + t, &slot));
-            launch_passB<double>(b, nbB, c->stream);
-            CHK(rec_end(c, slot));
-        }
-        HIPCHK(c, hipGetLastError());
-        if (c->opt.chunk <= 0 && fixed < 0) chunk = std::min(chunk * 2, 64);
-    }
+    CHK(jcg_chunks(c, l, a, b, nbB, c->sc, fixed, 0, 1));
     const JcgScalars s = *c->sc_host;
     if (s.pending) launch_final_x(L.g, L.x, c->p0, c->p1, c->sc, c->stream);
     HIPCHK(c, hipGetLastError());
@@ -438,11 +562,22 @@ static int run_jcg_persistent(ecmg_ctx *c, int l, double tol_abs, int max_iter, 
     return ECMG_OK;
 }
 
-static int run_level_jcg(ecmg_ctx *c, int l, double tol_abs, int max_iter, int fixed, ecmg_level_info *info) {
+static bool uses_persistent(const ecmg_ctx *c, int l) {
+    const Geom &g = c->lv[l].g;
     // the persistent kernel indexes with 32-bit integers
-    if (c->persist_blocks > 0 && c->lv[l].g.nreal <= c->persist_max && c->lv[l].g.nnodes < ((int64_t)1 << 31) &&
-        (int64_t)c->lv[l].g.nx * c->lv[l].g.ny * c->lv[l].g.nz < ((int64_t)1 << 31))
-        return run_jcg_persistent(c, l, tol_abs, max_iter, fixed, info);
+    return c->persist_blocks > 0 && g.nreal <= c->persist_max && g.nnodes < ((int64_t)1 << 31) &&
+           (int64_t)g.nx * g.ny * g.nz < ((int64_t)1 << 31);
+}
+
+// Mixed precision applies to JCG levels (not DSOLVE) solved by the tiled
+// kernels; the persistent coarse levels are latency-bound and stay FP64.
+static bool uses_mixed(const ecmg_ctx *c, int l) {
+    return c->opt.precision == ECMG_MIXED && l >= 2 && !uses_persistent(c, l);
+}
+
+static int run_level_jcg(ecmg_ctx *c, int l, double tol_abs, int max_iter, int fixed, ecmg_level_info *info) {
+    if (uses_mixed(c, l) && fixed < 0) return run_jcg_mixed(c, l, tol_abs, max_iter, info);
+    if (uses_persistent(c, l)) return run_jcg_persistent(c, l, tol_abs, max_iter, fixed, info);
     return run_jcg(c, l, tol_abs, max_iter, fixed, info);
 }
 
@@ -494,6 +629,12 @@ static void free_levels(ecmg_ctx *c) {
     dfree(c->q);
     dfree(c->partials);
     c->r = c->p0 = c->p1 = c->q = c->partials = nullptr;
+    dfree(c->r32);
+    dfree(c->p32a);
+    dfree(c->p32b);
+    dfree(c->q32);
+    dfree(c->d32);
+    c->r32 = c->p32a = c->p32b = c->q32 = c->d32 = nullptr;
     c->scratch_n = 0;
     c->partials_n = 0;
     c->nlev = 0;
@@ -540,10 +681,12 @@ int ecmg_create(const ecmg_options *opt, ecmg_ctx **out) {
         return fail(nullptr, ECMG_EDEVICE, "device %d is %s; this library is built for gfx950", dev,
                     prop.gcnArchName);
     ecmg_ctx *c = new ecmg_ctx();
+    c->device = dev;
     c->opt = o;
     if (const char *kz = std::getenv("ECMG_KZ")) c->KZ = std::max(1, std::atoi(kz));
     if (const char *v = std::getenv("ECMG_PERSIST_SEG")) c->persist_seglen = std::max(1, std::atoi(v));
     if (const char *v = std::getenv("ECMG_PERSIST_NWG")) c->persist_nwg = std::max(1, std::atoi(v));
+    if (const char *v = std::getenv("ECMG_BATCH_NPW")) c->batch_npw = std::max(64, std::atoi(v));
     if (o.hip_stream) {
         c->stream = (hipStream_t)o.hip_stream;
     } else {
@@ -555,6 +698,7 @@ int ecmg_create(const ecmg_options *opt, ecmg_ctx **out) {
     }
     int rc = ECMG_OK;
     if ((rc = dalloc(c, (void **)&c->sc, sizeof(JcgScalars))) != ECMG_OK ||
+        (rc = dalloc(c, (void **)&c->sc32, sizeof(JcgScalars))) != ECMG_OK ||
         (rc = dalloc(c, (void **)&c->counters, 16 * sizeof(unsigned))) != ECMG_OK ||
         (rc = dalloc(c, (void **)&c->dres, 8 * sizeof(double))) != ECMG_OK) {
         ecmg_destroy(c);
@@ -564,6 +708,8 @@ int ecmg_create(const ecmg_options *opt, ecmg_ctx **out) {
         int per_cu = 0, cus = 0;
         const int mb = persistent_max_blocks(&per_cu, &cus);
         c->persist_blocks = mb > 0 ? mb : 0;
+        const int qb = queue_max_blocks();
+        c->queue_blocks = qb > 0 ? qb : 0;
         if (o.persistent_nodes >= 0) c->persist_max = o.persistent_nodes;
     }
     // barrier words: error flag at 0, arrival counter at 16 (its own cache line)
@@ -589,6 +735,13 @@ void ecmg_destroy(ecmg_ctx *c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     free_levels(c);
     dfree(c->sc);
+    dfree(c->sc32);
+    dfree(c->bt_tasks);
+    dfree(c->bt_sc);
+    dfree(c->bt_next);
+    dfree(c->bt_bar);
+    dfree(c->bt_exp);
+    if (c->bt_sc_host) (void)hipHostFree(c->bt_sc_host);
     dfree(c->d_task);
     dfree(c->d_bar);
     dfree(c->counters);
@@ -669,6 +822,13 @@ int ecmg_setup(ecmg_ctx *c, const ecmg_problem *p) {
         CHK(dalloc_n(c, &c->p0, gf.nnodes));
         CHK(dalloc_n(c, &c->p1, gf.nnodes));
         CHK(dalloc_n(c, &c->q, gf.nnodes));
+        if (c->opt.precision == ECMG_MIXED) {
+            CHK(dalloc_n(c, &c->r32, gf.nnodes));
+            CHK(dalloc_n(c, &c->p32a, gf.nnodes));
+            CHK(dalloc_n(c, &c->p32b, gf.nnodes));
+            CHK(dalloc_n(c, &c->q32, gf.nnodes));
+            CHK(dalloc_n(c, &c->d32, gf.nnodes));
+        }
         int64_t pn = std::max<int64_t>(2 * 4096, 3 * (int64_t)c->persist_blocks);
         for (int l = 0; l < p->levels; ++l) {
             Geom g = make_geom(p, l, lo);
@@ -770,6 +930,17 @@ int ecmg_setup(ecmg_ctx *c, const ecmg_problem *p) {
         const double *al[6];
         for (int f = 0; f < 6; ++f) al[f] = L.alpha[f];
         launch_dinv(g, L.beta, al, L.dinv, c->stream);
+        if (uses_mixed(c, l)) {           // FP32 copies for the inner JCG of the mixed form
+            CHK(dalloc_n(c, &L.beta32, L.nelem));
+            CHK(dalloc_n(c, &L.dinv32, g.nnodes));
+            launch_to_f32(L.beta, L.beta32, L.nelem, c->stream);
+            launch_to_f32(L.dinv, L.dinv32, g.nnodes, c->stream);
+            for (int f = 0; f < 6; ++f) {
+                if (!L.alpha[f]) continue;
+                CHK(dalloc_n(c, &L.alpha32[f], L.nface[f]));
+                launch_to_f32(L.alpha[f], L.alpha32[f], L.nface[f], c->stream);
+            }
+        }
         // ||f_h||: b = F - A x0 on free nodes (x0 = g_D on Dirichlet nodes, 0 elsewhere)
         StencilArgs<double> a = stencil_args(c, L);
         a.v = L.x;
@@ -819,6 +990,240 @@ static int solve_impl(ecmg_ctx *c, double rel_tol, const int32_t *fixed, ecmg_le
     }
     c->solved = true;
     return worst;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batched solves: many independent hierarchies, level by level, with the JCG
+// of every box on one level in a single launch of the queue kernel
+// ---------------------------------------------------------------------------
+static int batch_reserve(ecmg_ctx *c, int n) {
+    if (c->bt_cap >= n) return ECMG_OK;
+    dfree(c->bt_tasks);
+    dfree(c->bt_sc);
+    if (c->bt_sc_host) (void)hipHostFree(c->bt_sc_host);
+    c->bt_tasks = nullptr;
+    c->bt_sc = c->bt_sc_host = nullptr;
+    c->bt_cap = 0;
+    if (!c->bt_next) CHK(dalloc(c, (void **)&c->bt_next, 64));
+    dfree(c->bt_bar);
+    c->bt_bar = nullptr;
+    CHK(dalloc(c, (void **)&c->bt_bar, 32 * sizeof(unsigned) * (size_t)n));
+    dfree(c->bt_exp);
+    c->bt_exp = nullptr;
+    CHK(dalloc(c, (void **)&c->bt_exp, sizeof(ExpTask) * (size_t)n));
+    CHK(dalloc(c, (void **)&c->bt_tasks, sizeof(PersistentTask) * (size_t)n));
+    CHK(dalloc(c, (void **)&c->bt_sc, sizeof(JcgScalars) * (size_t)n));
+    if (hipHostMalloc((void **)&c->bt_sc_host, sizeof(JcgScalars) * (size_t)n, hipHostMallocDefault) != hipSuccess)
+        return fail(c, ECMG_ENOMEM, "pinned host allocation of %d scalars failed", n);
+    c->bt_cap = n;
+    return ECMG_OK;
+}
+
+// The task of level l of context c as one workgroup of the queue kernel.
+static PersistentTask batch_task(ecmg_ctx *c, int l, double tol_abs, int max_iter, JcgScalars *sc) {
+    Level &L = c->lv[l];
+    PersistentTask t{};
+    t.g = L.g;
+    t.beta = L.beta;
+    for (int f = 0; f < 6; ++f) t.alpha[f] = L.alpha[f];
+    t.F = L.F;
+    t.dinv = L.dinv;
+    t.x = L.x;
+    t.r = c->r;
+    t.q = c->q;
+    t.p[0] = c->p0;
+    t.p[1] = c->p1;
+    t.partials = c->partials;
+    t.err = (int *)c->d_bar;
+    t.bar = c->d_bar + 16;
+    t.sc = sc;
+    t.tol = tol_abs;
+    t.max_iter = max_iter;
+    t.fixed = -1;
+    t.wg0 = 0;
+    // about batch_npw nodes per workgroup, at most 16 workgroups per box
+    t.nwg = (int)std::max<int64_t>(1, std::min<int64_t>(L.g.nreal / c->batch_npw, 16));
+    const int seg = c->persist_seglen > 0 ? c->persist_seglen : (L.g.nreal < 131072 ? 2 : 4);
+    t.seglen = std::max(1, std::min(seg, L.g.nz + 1));
+    return t;
+}
+
+// Runs fn(ctx) with ctx's work redirected to stream s.
+template <typename Fn>
+static int on_stream(ecmg_ctx *c, hipStream_t s, Fn fn) {
+    hipStream_t keep = c->stream;
+    c->stream = s;
+    const int rc = fn(c);
+    c->stream = keep;
+    return rc;
+}
+
+extern "C" {
+
+int ecmg_solve_batch(ecmg_ctx *const *ctxs, int32_t n, double rel_tol, ecmg_level_info *infos) {
+    if (!ctxs || n < 1) return fail(nullptr, ECMG_EINVAL, "ctxs is NULL or n = %d < 1", n);
+    ecmg_ctx *c0 = ctxs[0];
+    if (!c0) return fail(nullptr, ECMG_EINVAL, "ctxs[0] is NULL");
+    if (!(rel_tol >= 0.0)) return fail(c0, ECMG_EINVAL, "rel_tol = %g must be >= 0", rel_tol);
+    int maxlev = 0;
+    std::vector<int64_t> info_off(n);
+    int64_t off = 0;
+    for (int i = 0; i < n; ++i) {
+        ecmg_ctx *c = ctxs[i];
+        if (!c) return fail(c0, ECMG_EINVAL, "ctxs[%d] is NULL", i);
+        if (!c->ready) return fail(c0, ECMG_ESTATE, "ctxs[%d]: ecmg_solve_batch before ecmg_setup", i);
+        if (c->device != c0->device) return fail(c0, ECMG_EINVAL, "ctxs[%d] is on another device", i);
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == c) return fail(c0, ECMG_EINVAL, "ctxs[%d] repeats ctxs[%d]", i, j);
+        maxlev = std::max(maxlev, c->nlev);
+        info_off[i] = off;
+        off += c->nlev;
+    }
+    hipStream_t s = c0->stream;
+    for (int i = 1; i < n; ++i)
+        if (ctxs[i]->stream != s) HIPCHK(c0, hipStreamSynchronize(ctxs[i]->stream));
+    CHK(batch_reserve(c0, n));
+    std::vector<PersistentTask> tasks;
+    std::vector<int> owner;
+    tasks.reserve(n);
+    owner.reserve(n);
+    int worst = ECMG_OK;
+    for (int l = 0; l < maxlev; ++l) {
+        HIPCHK(c0, hipEventRecord(c0->ev0, s));
+        tasks.clear();
+        owner.clear();
+        std::vector<ExpTask> ex;
+        int64_t nb0 = 0, nb1 = 0;
+        for (int i = 0; i < n; ++i) {
+            ecmg_ctx *c = ctxs[i];
+            if (l >= c->nlev) continue;
+            Level &L = c->lv[l];
+            if (l >= 2) {                 // EXP_finite of every box in one pair of launches
+                ExpTask e{};
+                e.gf = L.g;
+                e.g1 = c->lv[l - 1].g;
+                e.U1 = c->lv[l - 1].x;
+                e.U0 = c->lv[l - 2].x;
+                e.V = c->q;
+                e.x = L.x;
+                e.W = L.W;
+                e.variant = c->opt.interp;
+                exp_task_blocks(e);
+                e.b0[0] = nb0;
+                e.b0[1] = nb1;
+                nb0 += e.nb[0];
+                nb1 += e.nb[1];
+                ex.push_back(e);
+            }
+            const double tol = (l < 2 ? c->opt.dsolve_tol : rel_tol) * L.nf;
+            const int max_iter = l < 2 ? 100000 : c->opt.max_iter;
+            tasks.push_back(batch_task(c, l, tol, max_iter, nullptr));
+            tasks.back().zero_x = l < 2;
+            owner.push_back(i);
+        }
+        if (!ex.empty()) {
+            if (nb0 >= ((int64_t)1 << 31) || nb1 >= ((int64_t)1 << 31))
+                return fail(c0, ECMG_EINVAL, "batched EXP_finite grid too large");
+            HIPCHK(c0, hipMemcpyAsync(c0->bt_exp, ex.data(), sizeof(ExpTask) * ex.size(), hipMemcpyHostToDevice, s));
+            launch_exp_finite_batch(c0->bt_exp, (int)ex.size(), nb0, nb1, s);
+            HIPCHK(c0, hipGetLastError());
+        }
+        // longest first: order by node count, then by input position
+        std::vector<int> order(tasks.size());
+        for (size_t k = 0; k < order.size(); ++k) order[k] = (int)k;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int a, int b) { return tasks[a].g.nreal > tasks[b].g.nreal; });
+        std::vector<PersistentTask> sorted(tasks.size());
+        std::vector<int> sorted_owner(tasks.size());
+        if (c0->queue_blocks < 1) return fail(c0, ECMG_EDEVICE, "the queue kernel cannot be resident");
+        int items = 0;
+        for (size_t k = 0; k < order.size(); ++k) {
+            sorted[k] = tasks[order[k]];
+            sorted[k].sc = c0->bt_sc + k;
+            sorted[k].err = (int *)(c0->bt_bar + 32 * k);
+            sorted[k].bar = c0->bt_bar + 32 * k + 16;
+            sorted[k].nwg = std::min(sorted[k].nwg, c0->queue_blocks);
+            sorted[k].wg0 = items;
+            items += sorted[k].nwg;
+            sorted_owner[k] = owner[order[k]];
+        }
+        const int nt = (int)sorted.size();
+        // every box's barrier words start at zero
+        HIPCHK(c0, hipMemsetAsync(c0->bt_bar, 0, 32 * sizeof(unsigned) * (size_t)nt, s));
+        HIPCHK(c0, hipMemcpyAsync(c0->bt_tasks, sorted.data(), sizeof(PersistentTask) * nt, hipMemcpyHostToDevice, s));
+        HIPCHK(c0, hipMemsetAsync(c0->bt_next, 0, sizeof(unsigned), s));
+        const int nwg = std::max(1, std::min(items, c0->queue_blocks));
+        HIPCHK(c0, launch_jcg_queue(c0->bt_tasks, nt, items, nwg, c0->bt_next, s));
+        HIPCHK(c0, hipMemcpyAsync(c0->bt_sc_host, c0->bt_sc, sizeof(JcgScalars) * nt, hipMemcpyDeviceToHost, s));
+        HIPCHK(c0, hipEventRecord(c0->ev1, s));
+        HIPCHK(c0, hipStreamSynchronize(s));
+        float ms = 0.f;
+        HIPCHK(c0, hipEventElapsedTime(&ms, c0->ev0, c0->ev1));
+        for (int k = 0; k < nt; ++k) {
+            ecmg_ctx *c = ctxs[sorted_owner[k]];
+            const Level &L = c->lv[l];
+            const JcgScalars &sc = c0->bt_sc_host[k];
+            ecmg_level_info li{};
+            li.level = l;
+            li.nx = L.g.nx;
+            li.ny = L.g.ny;
+            li.nz = L.g.nz;
+            li.iters = sc.iter;
+            li.rre = (L.nf > 0) ? std::sqrt(sc.rr) / L.nf : 0.0;
+            li.nf = L.nf;
+            li.ms = ms;
+            int st = (sc.done == DONE_BREAKDOWN) ? ECMG_EBREAKDOWN : (sc.done == DONE_MAXITER) ? ECMG_ENOTCONV : ECMG_OK;
+            if (l < 2 && st == ECMG_ENOTCONV) st = ECMG_OK;   // DSOLVE: the iterate at the cap is kept
+            li.status = st;
+            if (infos) infos[info_off[sorted_owner[k]] + l] = li;
+            if (st != ECMG_OK && worst == ECMG_OK) worst = st;
+        }
+    }
+    for (int i = 0; i < n; ++i) {
+        ctxs[i]->solved = true;
+        CHK(on_stream(ctxs[i], s, [&](ecmg_ctx *cc) { return rec_flush(cc, 1); }));
+    }
+    if (worst != ECMG_OK) return fail(c0, worst, "batched solve: some box did not converge (see infos)");
+    return ECMG_OK;
+}
+
+int ecmg_extrapolate_batch(ecmg_ctx *const *ctxs, int32_t n) {
+    if (!ctxs || n < 1) return fail(nullptr, ECMG_EINVAL, "ctxs is NULL or n = %d < 1", n);
+    ecmg_ctx *c0 = ctxs[0];
+    if (!c0) return fail(nullptr, ECMG_EINVAL, "ctxs[0] is NULL");
+    hipStream_t s = c0->stream;
+    for (int i = 0; i < n; ++i) {
+        ecmg_ctx *c = ctxs[i];
+        if (!c || !c->ready) return fail(c0, ECMG_ESTATE, "ctxs[%d] is NULL or not set up", i);
+        if (c->device != c0->device) return fail(c0, ECMG_EINVAL, "ctxs[%d] is on another device", i);
+        if (c->nlev < 2) return fail(c0, ECMG_EINVAL, "ctxs[%d] has fewer than 2 levels", i);
+        if (c->stream != s) HIPCHK(c0, hipStreamSynchronize(c->stream));
+    }
+    CHK(batch_reserve(c0, n));
+    std::vector<ExpTask> ex(n);
+    int64_t nb1 = 0;
+    for (int i = 0; i < n; ++i) {
+        ecmg_ctx *c = ctxs[i];
+        Level &L = c->lv[c->nlev - 1];
+        if (!L.Ut) CHK(dalloc_n(c, &L.Ut, L.g.nnodes));
+        ExpTask &e = ex[i];
+        e.gf = L.g;
+        e.g1 = c->lv[c->nlev - 2].g;
+        e.U1 = L.x;
+        e.U0 = c->lv[c->nlev - 2].x;
+        e.x = L.Ut;
+        exp_task_blocks(e);
+        e.b0[1] = nb1;
+        nb1 += e.nb[1];
+    }
+    if (nb1 >= ((int64_t)1 << 31)) return fail(c0, ECMG_EINVAL, "batched EXP_true grid too large");
+    HIPCHK(c0, hipMemcpyAsync(c0->bt_exp, ex.data(), sizeof(ExpTask) * n, hipMemcpyHostToDevice, s));
+    launch_exp_true_batch(c0->bt_exp, n, nb1, s);
+    HIPCHK(c0, hipGetLastError());
+    HIPCHK(c0, hipStreamSynchronize(s));
+    return ECMG_OK;
 }
 
 int ecmg_solve(ecmg_ctx *c, double rel_tol, ecmg_level_info *info) { return solve_impl(c, rel_tol, nullptr, info); }
@@ -977,7 +1382,7 @@ int ecmg_level_dims(ecmg_ctx *c, int32_t level, int64_t n[3]) {
 
 int ecmg_kernel_times(ecmg_ctx *c, int32_t level, int32_t k, double out[2]) {
     CHK(check_level(c, &level, 0));
-    if (k < 0 || k >= 8 || !out) return fail(c, ECMG_EINVAL, "bad kernel class %d", k);
+    if (k < 0 || k >= NKIND || !out) return fail(c, ECMG_EINVAL, "bad kernel class %d", k);
     out[0] = c->lv[level].kt_ms[k];
     out[1] = (double)c->lv[level].kt_n[k];
     return ECMG_OK;
@@ -986,7 +1391,7 @@ int ecmg_kernel_times(ecmg_ctx *c, int32_t level, int32_t k, double out[2]) {
 int ecmg_reset_kernel_times(ecmg_ctx *c) {
     if (!c) return fail(nullptr, ECMG_EINVAL, "ctx is NULL");
     for (auto &L : c->lv)
-        for (int k = 0; k < 8; ++k) {
+        for (int k = 0; k < NKIND; ++k) {
             L.kt_ms[k] = 0.0;
             L.kt_n[k] = 0;
         }

@@ -87,7 +87,7 @@ struct StencilArgs {
     const T *F;                       // init: load vector
     const T *dinv;                    // init / pass A: 1/diag, 0 on Dirichlet nodes
     T *r;                             // init: output residual; pass A: input
-    double *x;                        // pass A: iterate (deferred update)
+    T *x;                             // pass A: iterate (deferred update)
     T *p0, *p1;                       // pass A: search directions (ping-pong)
     JcgScalars *sc;
     double *partials;                 // per-block partial sums
@@ -123,12 +123,18 @@ struct PersistentTask {
     int max_iter, fixed;
     int wg0, nwg;
     int seglen;                       // z-march length: the nodes of a column are cut into segments
+    int zero_x;                       // 1: start from x = 0 on free nodes (DSOLVE), keep g_D
 };
 
 // Modes of the tiled stencil kernel.
 enum { MODE_APPLY = 0, MODE_INIT = 1, MODE_PASSA = 2 };
 
 // ---- host-side level and context -------------------------------------------------
+// kernel classes timed per level: 0 pass A, 1 pass B, 2 JCG init, 3 EXP_finite,
+// 4 EXP_true, 5 pass A FP32, 6 pass B FP32, 7 persistent JCG, 8 mixed start,
+// 9 mixed update
+constexpr int NKIND = 10;
+
 struct Level {
     Geom g;
     double lo[3];
@@ -146,8 +152,8 @@ struct Level {
     float *dinv32 = nullptr;
     double nf = 0.0;                  // ||f_h||_2 of the stopping test
     // timing accumulators per kernel class
-    double kt_ms[8] = {};
-    int64_t kt_n[8] = {};
+    double kt_ms[NKIND] = {};
+    int64_t kt_n[NKIND] = {};
 };
 
 struct Ctx;
@@ -162,12 +168,36 @@ template <typename T>
 void launch_passB(const PassBArgs<T> &a, int nblocks, hipStream_t s);
 void launch_final_x(const Geom &g, double *x, const double *p0, const double *p1, const JcgScalars *sc,
                     hipStream_t s);
+// mixed precision: r32 = r64 / s, d32 = 0, JCG start scalars (FP64 sums)
+void launch_mixed_start(const Geom &g, const double *r64, double inv_s, const float *dinv32, float *r32, float *d32,
+                        JcgScalars *sc, double *partials, unsigned *counter, hipStream_t s);
+// mixed precision: x64 += s * (d32 + alpha p_last) (the deferred last update included)
+void launch_mixed_update(const Geom &g, double *x, double sc_s, const float *d32, const float *p0, const float *p1,
+                         const JcgScalars *sc, hipStream_t s);
+void launch_to_f32(const double *a, float *b, int64_t n, hipStream_t s);
 void launch_jcg_reset(JcgScalars *sc, double tol, int max_iter, int fixed, hipStream_t s);
 
 void launch_exp_finite(const Geom &gf, const Geom &g1, const double *U1, const double *U0, double *V, double *x,
                        double *W, int variant, hipStream_t s);
 void launch_exp_true(const Geom &gf, const double *U1, const double *U0, double *Ut, hipStream_t s);
+
+// One box of a batched EXP_finite (U1 = u_{l-1}, U0 = u_{l-2}, V scratch on
+// level l-1, x and optional W on level l) or EXP_true (U1 = u_l, U0 = u_{l-1},
+// result into x).  b0 / nb / gx: first flat block, block count and blocks per
+// row chunk of phase 0 (level l-1 grid) and phase 1 (fine grid).
+struct ExpTask {
+    Geom gf, g1;
+    const double *U1, *U0;
+    double *V, *x, *W;
+    int variant;
+    int gx[2];
+    int64_t nb[2], b0[2];
+};
+void exp_task_blocks(ExpTask &t);
+void launch_exp_finite_batch(const ExpTask *d_tasks, int n, int64_t nb0, int64_t nb1, hipStream_t s);
+void launch_exp_true_batch(const ExpTask *d_tasks, int n, int64_t nb1, hipStream_t s);
 void launch_zero_pad(const Geom &g, double *a, double *b, double *c, double *d, hipStream_t s);
+void launch_zero_pad_f32(const Geom &g, float *a, float *b, float *c, hipStream_t s);
 
 void launch_fill(double *p, int64_t n, double v, hipStream_t s);
 void launch_zero_free(const Geom &g, double *x, hipStream_t s);
@@ -186,6 +216,11 @@ void launch_norms(const Geom &g, const double *a, const double *b, const double 
 constexpr int PERSIST_NTP = ECMG_PERSIST_NTP;  // threads per workgroup of the persistent kernel
 int persistent_max_blocks(int *per_cu, int *cus);
 hipError_t launch_jcg_persistent(const PersistentTask *d_tasks, int ntasks, int total_wg, hipStream_t s);
+// tasks with their own workgroup ranges [wg0, wg0 + nwg) over nitems work items,
+// taken from the queue counter *next (zero at launch) by nwg resident workgroups
+int queue_max_blocks();
+hipError_t launch_jcg_queue(const PersistentTask *d_tasks, int ntasks, int nitems, int nwg, unsigned *next,
+                            hipStream_t s);
 
 // Block count of the 1-D reduction kernels (fixed so reductions are deterministic).
 int reduce_blocks(int64_t n);

@@ -54,11 +54,11 @@ __device__ __forceinline__ double u_at(const double *U, int64_t sx, int64_t sxy,
     return U[p + sx * q + sxy * r];
 }
 
-__global__ void __launch_bounds__(256) k_exp_finite_nodal(const Geom g1, const double *__restrict__ U1,
-                                                          const double *__restrict__ U0, double *__restrict__ V,
-                                                          int variant) {
-    const int p = blockIdx.x * 64 + threadIdx.x;
-    const int64_t row = (int64_t)blockIdx.y * 4 + threadIdx.y;
+__device__ __forceinline__ void exp_finite_nodal_block(const Geom &g1, const double *__restrict__ U1,
+                                                       const double *__restrict__ U0, double *__restrict__ V,
+                                                       int variant, int bx, int64_t by) {
+    const int p = bx * 64 + threadIdx.x;
+    const int64_t row = by * 4 + threadIdx.y;
     if (p > g1.nx || row >= (int64_t)g1.sy * (g1.nz + 1)) return;
     const int q = (int)(row % g1.sy), r = (int)(row / g1.sy);
     const int64_t s1 = g1.sx, s1y = (int64_t)g1.sx * g1.sy;
@@ -137,14 +137,21 @@ __global__ void __launch_bounds__(256) k_exp_finite_nodal(const Geom g1, const d
     V[p + s1 * q + s1y * r] = v;
 }
 
+__global__ void __launch_bounds__(256) k_exp_finite_nodal(const Geom g1, const double *__restrict__ U1,
+                                                          const double *__restrict__ U0, double *__restrict__ V,
+                                                          int variant) {
+    exp_finite_nodal_block(g1, U1, U0, V, variant, blockIdx.x, blockIdx.y);
+}
+
 // Phase 2: every fine node of level l is the tri-quadratic Lagrange
 // interpolant of the 27 nodal values of its owner coarse element.  One 64-lane
 // row per wave, so the y and z offsets (and which 1-D weights vanish) are
 // uniform across the wave.
-__global__ void __launch_bounds__(256) k_exp_finite_interp(const Geom gf, const double *__restrict__ V,
-                                                           double *__restrict__ x, double *__restrict__ W) {
-    const int i = blockIdx.x * 64 + threadIdx.x;
-    const int64_t row = (int64_t)blockIdx.y * 4 + threadIdx.y;
+__device__ __forceinline__ void exp_finite_interp_block(const Geom &gf, const double *__restrict__ V,
+                                                        double *__restrict__ x, double *__restrict__ W, int bx,
+                                                        int64_t by) {
+    const int i = bx * 64 + threadIdx.x;
+    const int64_t row = by * 4 + threadIdx.y;
     if (i > gf.nx || row >= (int64_t)gf.sy * (gf.nz + 1)) return;
     const int j = (int)(row % gf.sy), k = (int)(row / gf.sy);
     const int NX = gf.nx / 4, NY = gf.ny / 4, NZ = gf.nz / 4;
@@ -172,15 +179,21 @@ __global__ void __launch_bounds__(256) k_exp_finite_interp(const Geom gf, const 
     if (!is_dir(gf, i, j, k)) x[id] = w;
 }
 
+__global__ void __launch_bounds__(256) k_exp_finite_interp(const Geom gf, const double *__restrict__ V,
+                                                           double *__restrict__ x, double *__restrict__ W) {
+    exp_finite_interp_block(gf, V, x, W, blockIdx.x, blockIdx.y);
+}
+
 // U~ = U1 + (1/3) T[U1 - U0]: eq. t1 at coarse nodes ((4 U1 - U0)/3), eq.
 // chenlin at edge midpoints (U1 + (d_a + d_b)/6), and the mean of chenlin along
 // the 2 face diagonals (U1 + sum(4 d)/12) or the 4 space diagonals (U1 +
 // sum(8 d)/24) at face and body centres.  One 64-lane row per wave: the y and
 // z parities, hence the number of coarse differences, are wave-uniform.
-__global__ void __launch_bounds__(256) k_exp_true(const Geom gf, const double *__restrict__ U1,
-                                                  const double *__restrict__ U0, double *__restrict__ Ut) {
-    const int i = blockIdx.x * 64 + threadIdx.x;
-    const int64_t row = (int64_t)blockIdx.y * 4 + threadIdx.y;
+__device__ __forceinline__ void exp_true_block(const Geom &gf, const double *__restrict__ U1,
+                                               const double *__restrict__ U0, double *__restrict__ Ut, int bx,
+                                               int64_t by) {
+    const int i = bx * 64 + threadIdx.x;
+    const int64_t row = by * 4 + threadIdx.y;
     if (i > gf.nx || row >= (int64_t)gf.sy * (gf.nz + 1)) return;
     const int j = (int)(row % gf.sy), k = (int)(row / gf.sy);
     const int64_t sx = gf.sx, sxy = (int64_t)gf.sx * gf.sy;
@@ -206,6 +219,63 @@ __global__ void __launch_bounds__(256) k_exp_true(const Geom gf, const double *_
     const int nodd = oi + oj + ok;
     const double denom = nodd == 1 ? 6.0 : (nodd == 2 ? 12.0 : 24.0);
     Ut[id] = u1 + s / denom;
+}
+
+__global__ void __launch_bounds__(256) k_exp_true(const Geom gf, const double *__restrict__ U1,
+                                                  const double *__restrict__ U0, double *__restrict__ Ut) {
+    exp_true_block(gf, U1, U0, Ut, blockIdx.x, blockIdx.y);
+}
+
+// ---------------------------------------------------------------------------
+// batched forms: one launch covers the grids of many boxes; box t owns the
+// flat blocks [b0, b0 + gx * gy) of the launch (tasks in order of b0)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int find_box(const ExpTask *__restrict__ t, int n, int64_t b, int phase) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (t[mid].b0[phase] <= b) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(256) k_exp_finite_nodal_batch(const ExpTask *__restrict__ tasks, int n) {
+    const int64_t b = blockIdx.x;
+    const ExpTask &t = tasks[find_box(tasks, n, b, 0)];
+    const int64_t lb = b - t.b0[0];
+    exp_finite_nodal_block(t.g1, t.U1, t.U0, t.V, t.variant, (int)(lb % t.gx[0]), lb / t.gx[0]);
+}
+
+__global__ void __launch_bounds__(256) k_exp_finite_interp_batch(const ExpTask *__restrict__ tasks, int n) {
+    const int64_t b = blockIdx.x;
+    const ExpTask &t = tasks[find_box(tasks, n, b, 1)];
+    const int64_t lb = b - t.b0[1];
+    exp_finite_interp_block(t.gf, t.V, t.x, t.W, (int)(lb % t.gx[1]), lb / t.gx[1]);
+}
+
+__global__ void __launch_bounds__(256) k_exp_true_batch(const ExpTask *__restrict__ tasks, int n) {
+    const int64_t b = blockIdx.x;
+    const ExpTask &t = tasks[find_box(tasks, n, b, 1)];
+    const int64_t lb = b - t.b0[1];
+    exp_true_block(t.gf, t.U1, t.U0, t.x, (int)(lb % t.gx[1]), lb / t.gx[1]);
+}
+
+// Block counts of a box: phase 0 over the level l-1 grid g1, phase 1 over the
+// fine grid gf (64 x 4 nodes per block).
+void exp_task_blocks(ExpTask &t) {
+    t.gx[0] = (t.g1.nx + 1 + 63) / 64;
+    t.gx[1] = (t.gf.nx + 1 + 63) / 64;
+    t.nb[0] = (int64_t)t.gx[0] * (((int64_t)t.g1.sy * (t.g1.nz + 1) + 3) / 4);
+    t.nb[1] = (int64_t)t.gx[1] * (((int64_t)t.gf.sy * (t.gf.nz + 1) + 3) / 4);
+}
+
+void launch_exp_finite_batch(const ExpTask *d_tasks, int n, int64_t nb0, int64_t nb1, hipStream_t s) {
+    if (nb0 > 0) hipLaunchKernelGGL(k_exp_finite_nodal_batch, dim3((unsigned)nb0), dim3(64, 4), 0, s, d_tasks, n);
+    if (nb1 > 0) hipLaunchKernelGGL(k_exp_finite_interp_batch, dim3((unsigned)nb1), dim3(64, 4), 0, s, d_tasks, n);
+}
+
+void launch_exp_true_batch(const ExpTask *d_tasks, int n, int64_t nb1, hipStream_t s) {
+    if (nb1 > 0) hipLaunchKernelGGL(k_exp_true_batch, dim3((unsigned)nb1), dim3(64, 4), 0, s, d_tasks, n);
 }
 
 void launch_exp_finite(const Geom &gf, const Geom &g1, const double *U1, const double *U0, double *V, double *x,
@@ -236,6 +306,23 @@ void launch_zero_pad(const Geom &g, double *a, double *b, double *c, double *d, 
     const int64_t n = (int64_t)g.sy * (g.nz + 1) * (g.sx - g.nx - 1);
     if (n <= 0) return;
     hipLaunchKernelGGL(k_zero_pad, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, a, b, c, d);
+}
+
+__global__ void k_zero_pad_f32(const Geom g, float *a, float *b, float *c) {
+    const int pad = g.sx - g.nx - 1;
+    const int64_t rows = (int64_t)g.sy * (g.nz + 1);
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pad <= 0 || t >= rows * pad) return;
+    const int64_t id = (t / pad) * g.sx + g.nx + 1 + (t % pad);
+    if (a) a[id] = 0.0f;
+    if (b) b[id] = 0.0f;
+    if (c) c[id] = 0.0f;
+}
+
+void launch_zero_pad_f32(const Geom &g, float *a, float *b, float *c, hipStream_t s) {
+    const int64_t n = (int64_t)g.sy * (g.nz + 1) * (g.sx - g.nx - 1);
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_zero_pad_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, a, b, c);
 }
 
 void launch_exp_true(const Geom &gf, const double *U1, const double *U0, double *Ut, hipStream_t s) {

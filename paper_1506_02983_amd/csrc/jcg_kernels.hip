@@ -567,7 +567,74 @@ int reduce_blocks(int64_t n) {
     return (int)nb;
 }
 
+// ---------------------------------------------------------------------------
+// mixed precision (outer FP64 residual / iterative refinement around an FP32
+// JCG on the correction)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(NTB) k_mixed_start(int64_t n, const double *r64, double inv_s, const float *dinv32,
+                                                     float *r32, float *d32, JcgScalars *sc, double *partials,
+                                                     unsigned *counter) {
+    __shared__ double red[2][NTB / 64];
+    __shared__ int s_last;
+    const int64_t stride = (int64_t)gridDim.x * NTB;
+    double rz = 0.0, rr = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * NTB + threadIdx.x; i < n; i += stride) {
+        const float rv = (float)(r64[i] * inv_s);
+        r32[i] = rv;
+        d32[i] = 0.0f;
+        const float z = dinv32[i] * rv;
+        rz += (double)rv * (double)z;
+        rr += (double)rv * (double)rv;
+    }
+    double acc[2] = {rz, rr}, tot[2];
+    if (last_block_total<2, NTB>(acc, red, &s_last, partials, counter, blockIdx.x, gridDim.x, tot) &&
+        threadIdx.x == 0) {
+        sc->rho = tot[0];
+        sc->rr = tot[1];
+        sc->iter = 0;
+        sc->alpha = 0.0;
+        sc->beta = 0.0;
+        sc->pending = 0;
+        const double rn = sqrt(tot[1]);
+        if (!(rn > sc->tol)) sc->done = DONE_CONVERGED;
+        else sc->done = (sc->max_iter <= 0) ? DONE_MAXITER : DONE_RUNNING;
+    }
+}
+
+__global__ void k_mixed_update(int64_t n, int sx, int width, double *x, double s, const float *d32, const float *p0,
+                               const float *p1, const JcgScalars *sc) {
+    const float al = sc->pending ? (float)sc->alpha : 0.0f;
+    const float *p = (sc->iter & 1) ? p1 : p0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        if ((int)(i % sx) < width) x[i] += s * (double)(d32[i] + al * p[i]);
+}
+
+__global__ void k_to_f32(const double *a, float *b, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) b[i] = (float)a[i];
+}
+
+void launch_mixed_start(const Geom &g, const double *r64, double inv_s, const float *dinv32, float *r32, float *d32,
+                        JcgScalars *sc, double *partials, unsigned *counter, hipStream_t s) {
+    hipLaunchKernelGGL(k_mixed_start, dim3(reduce_blocks(g.nnodes)), dim3(NTB), 0, s, g.nnodes, r64, inv_s, dinv32,
+                       r32, d32, sc, partials, counter);
+}
+
+void launch_mixed_update(const Geom &g, double *x, double sc_s, const float *d32, const float *p0, const float *p1,
+                         const JcgScalars *sc, hipStream_t s) {
+    const int64_t nb = std::min<int64_t>((g.nnodes + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_mixed_update, dim3(nb), dim3(256), 0, s, g.nnodes, g.sx, g.nx + 1, x, sc_s, d32, p0, p1, sc);
+}
+
+void launch_to_f32(const double *a, float *b, int64_t n, hipStream_t s) {
+    const int64_t nb = std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192));
+    hipLaunchKernelGGL(k_to_f32, dim3(nb), dim3(256), 0, s, a, b, n);
+}
+
 template void launch_stencil<double>(int, const StencilArgs<double> &, hipStream_t);
 template void launch_passB<double>(const PassBArgs<double> &, int, hipStream_t);
+template void launch_stencil<float>(int, const StencilArgs<float> &, hipStream_t);
+template void launch_passB<float>(const PassBArgs<float> &, int, hipStream_t);
 
 }  // namespace ecmg

@@ -278,21 +278,12 @@ __device__ __forceinline__ void task_sum(const PersistentTask &t, int w, int nwg
     for (int i = 0; i < NV; ++i) v[i] = s[i];
 }
 
-__global__ void __launch_bounds__(NTP) k_jcg_persistent(const PersistentTask *__restrict__ tasks, int ntasks) {
-    __shared__ double red[3][NTP / 64];
-    __shared__ int s_err;
-    // locate this workgroup's task (tasks hold contiguous workgroup ranges)
-    int lo = 0, hi = ntasks - 1;
-    const int bid = blockIdx.x;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) / 2;
-        if (tasks[mid].wg0 <= bid) lo = mid; else hi = mid - 1;
-    }
-    const PersistentTask &t = tasks[lo];
-    const int w = bid - t.wg0, nwg = t.nwg;
+// The JCG solve of one task by workgroup w of its nwg workgroups.  LDS: red
+// (reductions), s_err (barrier failure), sC / sM (coefficients).
+__device__ __forceinline__ void jcg_task(const PersistentTask &t, int w, int nwg, double (*red)[NTP / 64],
+                                         int &s_err, double *sC, double (*sM)[3]) {
     // stencil and face-mass coefficients in LDS (uniform reads), the rest of
     // the grid as a few integers
-    __shared__ double sC[8], sM[6][3];
     if (threadIdx.x < 8) sC[threadIdx.x] = t.g.C[threadIdx.x];
     if (threadIdx.x < 18) sM[threadIdx.x / 3][threadIdx.x % 3] = t.g.M[threadIdx.x / 3][threadIdx.x % 3];
     PGeom g;
@@ -339,6 +330,13 @@ __global__ void __launch_bounds__(NTP) k_jcg_persistent(const PersistentTask *__
     }
 
     unsigned gen = 0;                  // barriers passed by this workgroup
+    if (t.zero_x) {                    // x = 0 on free nodes, g_D stays on Dirichlet nodes
+        FOR_UNITS({
+            for (int k = k0; k < k1; ++k)
+                if (!pdir(g, i, j, k)) A.X[i + sx * j + sxy * k] = 0.0;
+        })
+        task_barrier(t, nwg, ++gen, &s_err);
+    }
     double acc[2] = {0.0, 0.0};
     FOR_UNITS(march<MARCH_INIT>(g, sC, sM, A, i, j, k0, k1, 0, 0.0, 0.0, acc);)
     task_sum<2>(t, w, nwg, gen, 1, acc, red, &s_err);
@@ -425,6 +423,55 @@ __global__ void __launch_bounds__(NTP) k_jcg_persistent(const PersistentTask *__
         sc->pending = 0;
         sc->tol = t.tol;
     }
+    __syncthreads();                   // LDS is reused by the next task of this workgroup
+}
+
+// One or more tasks, each on its own contiguous range of workgroups
+// (cooperative launch: all workgroups of a task must be resident together).
+__global__ void __launch_bounds__(NTP) k_jcg_persistent(const PersistentTask *__restrict__ tasks, int ntasks) {
+    __shared__ double red[3][NTP / 64];
+    __shared__ int s_err;
+    __shared__ double sC[8], sM[6][3];
+    // locate this workgroup's task (tasks hold contiguous workgroup ranges)
+    int lo = 0, hi = ntasks - 1;
+    const int bid = blockIdx.x;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (tasks[mid].wg0 <= bid) lo = mid; else hi = mid - 1;
+    }
+    const PersistentTask &t = tasks[lo];
+    jcg_task(t, bid - t.wg0, t.nwg, red, s_err, sC, sM);
+}
+
+// Many tasks taken from a queue.  Task i owns the work items [wg0, wg0 + nwg)
+// (contiguous, tasks in order); every workgroup takes the next item from an
+// atomic counter (zero at launch), works on its task as workgroup
+// item - wg0 of nwg, and takes another until none is left.  Deadlock-free when
+// every workgroup of the launch is resident (cooperative launch) and no task
+// has more workgroups than the launch: items are taken in order, so when a
+// workgroup waits at a task barrier, every item before its partners' has been
+// taken by a workgroup whose own task can complete.  Tasks sorted by
+// decreasing work keep the longest ones from starting last.
+__global__ void __launch_bounds__(NTP) k_jcg_queue(const PersistentTask *__restrict__ tasks, int ntasks,
+                                                   int nitems, unsigned *next) {
+    __shared__ double red[3][NTP / 64];
+    __shared__ int s_err;
+    __shared__ double sC[8], sM[6][3];
+    __shared__ int s_item;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(next, 1u);
+        __syncthreads();
+        const int item = s_item;
+        __syncthreads();
+        if (item >= nitems) break;
+        int lo = 0, hi = ntasks - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) / 2;
+            if (tasks[mid].wg0 <= item) lo = mid; else hi = mid - 1;
+        }
+        const PersistentTask &t = tasks[lo];
+        jcg_task(t, item - t.wg0, t.nwg, red, s_err, sC, sM);
+    }
 }
 
 int persistent_max_blocks(int *per_cu, int *cus) {
@@ -442,6 +489,22 @@ int persistent_max_blocks(int *per_cu, int *cus) {
 hipError_t launch_jcg_persistent(const PersistentTask *d_tasks, int ntasks, int total_wg, hipStream_t s) {
     void *args[] = {(void *)&d_tasks, (void *)&ntasks};
     return hipLaunchCooperativeKernel((const void *)k_jcg_persistent, dim3(total_wg), dim3(NTP), args, 0, s);
+}
+
+int queue_max_blocks() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return -1;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return -1;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_jcg_queue, NTP, 0) != hipSuccess) return -1;
+    return nb * prop.multiProcessorCount;
+}
+
+hipError_t launch_jcg_queue(const PersistentTask *d_tasks, int ntasks, int nitems, int nwg, unsigned *next,
+                            hipStream_t s) {
+    void *args[] = {(void *)&d_tasks, (void *)&ntasks, (void *)&nitems, (void *)&next};
+    return hipLaunchCooperativeKernel((const void *)k_jcg_queue, dim3(nwg), dim3(NTP), args, 0, s);
 }
 
 }  // namespace ecmg

@@ -1,0 +1,89 @@
+"""GPU mixed-precision form (FP32 stencil and CG vectors inside an FP64
+residual / iterative-refinement loop) against FP64 and the oracle.
+
+The mixed form is accepted on properties that do not depend on the GPU path:
+the oracle recomputes, in FP64 from its own assembled matrix, the residual
+||b - A u|| of every JCG level's GPU solution, which must satisfy the stopping
+test of Algorithm 4 (<= eps ||f_h||); and the errors against the exact
+solution must stay within 1.05x of the FP64 solver's on the same GPU."""
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ecmg():
+    import paper_1506_02983_amd as E
+    E.load_library()
+    return E
+
+
+def _exact_err(orc, p, l, v):
+    ue = orc.exact_nodes(p, orc.grid_of(p, l))
+    return float(np.abs(v - ue).max())
+
+
+CASES = {
+    # (problem, eps); the tiled kernels are forced on every level (persistent
+    # off) so the mixed form runs on all JCG levels at these sizes
+    "variable-beta-robin": lambda: (workloads.variable_beta_robin_cube(levels=4), 1e-10),
+    "singular-contrast": lambda: (workloads.high_contrast_singular_box(levels=4), 1e-8),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_mixed_meets_fp64_stop_test_and_accuracy(orc, ecmg, name):
+    p, eps = CASES[name]()
+    L = p.levels - 1
+    out = {}
+    for prec in (ecmg.FP64, ecmg.MIXED):
+        with ecmg.Solver(precision=prec, persistent_nodes=0) as s:
+            s.setup(p)
+            infos = s.solve(eps)
+            U = {l: s.get(l, ecmg.VEC_U) for l in range(2, p.levels)}
+            s.extrapolate(L, out=False)
+            Ut = s.get(L, ecmg.VEC_UTILDE)
+            out[prec] = (infos, U, Ut)
+    infos, U, Ut = out[ecmg.MIXED]
+    for l in range(2, p.levels):
+        assert infos[l]["status"] == 0
+        assert infos[l]["outer_steps"] >= 1 or infos[l]["iters"] == 0, infos[l]
+        lv = orc.discretize(p, l)
+        free = lv.dmask == 0
+        r = (lv.F - orc.spmv(lv, U[l]))[free]
+        rre_true = float(np.linalg.norm(r)) / lv.nf
+        assert rre_true <= eps * 1.001 + 1e-15, (l, rre_true, infos[l])
+        # Dirichlet values are exact
+        assert np.array_equal(U[l][lv.dmask == 1], lv.gD[lv.dmask == 1])
+    e_mixed = _exact_err(orc, p, L, U[L])
+    e_fp64 = _exact_err(orc, p, L, out[ecmg.FP64][1][L])
+    assert e_mixed <= 1.05 * e_fp64, (e_mixed, e_fp64)
+    et_mixed = _exact_err(orc, p, L, Ut)
+    et_fp64 = _exact_err(orc, p, L, out[ecmg.FP64][2])
+    assert et_mixed <= 1.05 * et_fp64 + 1e-13, (et_mixed, et_fp64)
+
+
+def test_mixed_default_levels_and_fixed_mode(orc, ecmg):
+    """With the persistent kernel on, small levels stay FP64 (outer_steps 0);
+    fixed-iteration mode (parity) always runs FP64."""
+    p = workloads.variable_beta_robin_cube(levels=4)
+    with ecmg.Solver(precision=ecmg.MIXED) as s:
+        s.setup(p)
+        infos = s.solve(1e-10)
+        assert all(i["outer_steps"] == 0 for i in infos)
+    with ecmg.Solver(precision=ecmg.MIXED, persistent_nodes=0) as s:
+        s.setup(p)
+        infos = s.solve_fixed([0, 0, 3, 2])
+        assert [i["iters"] for i in infos[2:]] == [3, 2]
+        assert all(i["outer_steps"] == 0 for i in infos)
+
+
+def test_mixed_not_converged_reports(ecmg):
+    p = workloads.variable_beta_robin_cube(levels=4)
+    with ecmg.Solver(precision=ecmg.MIXED, persistent_nodes=0, max_iter=3) as s:
+        s.setup(p)
+        infos = s.solve(1e-12, allow_fail=True)
+        assert any(i["status"] == ecmg.ENOTCONV for i in infos[2:])
