@@ -159,6 +159,50 @@ def precision_comparison(E, torch, name="high-contrast-513x257x257", steps=3):
     return res
 
 
+def serving(E, n_measured=200, n_warmup=20, rate=50.0, budget=200 * 10 ** 9):
+    """Replay a seeded Poisson stream of requests (finest 32^3..256^3,
+    random coefficients and faces) against the serving loop; latency is from
+    each request's scheduled arrival to its U~ on the host."""
+    import workloads
+    stream = workloads.serving_stream(n_measured + n_warmup, rate, seed=1)
+    lat, sizes = [], []
+    with E.Server(budget) as srv:
+        t0 = time.perf_counter()
+        nxt, live, t_first = 0, {}, None
+        while nxt < len(stream) or live:
+            now = time.perf_counter() - t0
+            while nxt < len(stream) and stream[nxt].arrival_s <= now:
+                live[srv.submit(stream[nxt].problem, stream[nxt].problem.eps)] = nxt
+                nxt += 1
+            if not live:
+                time.sleep(max(0.0, stream[nxt].arrival_s - (time.perf_counter() - t0)))
+                continue
+            srv.step()
+            tnow = time.perf_counter() - t0
+            for t, k in list(live.items()):
+                st, _ = srv.poll(t)
+                if st == 2 or st < 0:
+                    if st < 0:
+                        raise RuntimeError("request %d failed with status %d" % (k, st))
+                    if k >= n_warmup:
+                        lat.append(1e3 * (tnow - stream[k].arrival_s))
+                        sizes.append(stream[k].problem.nodes_at(stream[k].problem.levels - 1))
+                        if t_first is None:
+                            t_first = stream[k].arrival_s
+                    srv.release(t)
+                    del live[t]
+        t_end = time.perf_counter() - t0
+        internal = srv.stats()
+    lat = sorted(lat)
+    pct = lambda q: lat[min(len(lat) - 1, max(0, int(math.ceil(q * len(lat))) - 1))]
+    span = t_end - t_first
+    return {"requests": n_measured, "warmup": n_warmup, "rate_per_s": rate, "budget_bytes": budget,
+            "p50_ms": pct(0.5), "p99_ms": pct(0.99), "max_ms": lat[-1],
+            "solves_per_s": n_measured / span, "unknowns_per_s": sum(sizes) / span,
+            "latency_from": "scheduled arrival to U~ on the host (setup included)",
+            "server_internal": internal}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -176,6 +220,8 @@ def main():
                          "for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE")
     ap.add_argument("--no-precision-comparison", action="store_true",
                     help="skip the FP64 vs mixed comparison on the high-contrast workload")
+    ap.add_argument("--serve-requests", type=int, default=200,
+                    help="measured requests of the serving replay (0 = skip), after 20 warm-up requests")
     ap.add_argument("--no-fourth-order", action="store_true",
                     help="skip the search for the eps that keeps the extrapolation fourth order")
     args = ap.parse_args()
@@ -317,6 +363,14 @@ def main():
     if not args.no_precision_comparison:
         prec_cmp = precision_comparison(E, torch)
 
+    serve = None
+    if args.serve_requests > 0:
+        serve = serving(E, n_measured=args.serve_requests)
+        print("bench: serving p50 %.1f ms, p99 %.1f ms, %.1f solves/s" % (serve["p50_ms"], serve["p99_ms"],
+                                                                          serve["solves_per_s"]),
+              file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(problem.with_(eps=eps), min(args.cpu_levels, problem.levels), args.interp)
@@ -335,6 +389,7 @@ def main():
         "jcg_hbm_gbs_finest": jcg_gbs,
         "fourth_order": fourth,
         "precision_comparison": prec_cmp,
+        "serving": serve,
         "setup_s": setup_s,
         "levels": [{"level": i["level"], "n": [i["nx"], i["ny"], i["nz"]], "iters": i["iters"],
                     "rre": i["rre"], "ms": i["ms"]} for i in infos],

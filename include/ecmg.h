@@ -194,6 +194,45 @@ int ecmg_solve_batch(ecmg_ctx *const *ctxs, int32_t n, double rel_tol, ecmg_leve
  * without a host round trip per box; returns when all are done. */
 int ecmg_extrapolate_batch(ecmg_ctx *const *ctxs, int32_t n);
 
+/* ---- serving: continuous batching of independent requests ----------------
+ * A server solves requests (each a problem of eq. bvp run through Algorithm 4
+ * and EXP_true on its finest level) as they arrive.  The caller drives it:
+ * ecmg_server_step admits queued requests first come first served while the
+ * device bytes of their hierarchies (ecmg_plan_bytes) fit the budget, sets
+ * them up (callbacks run on the calling thread), then advances every admitted
+ * request by one level: the levels small enough for the persistent kernel of
+ * all requests share one launch (one workgroup range per request), larger
+ * levels run the tiled kernels; finished requests get EXP_true, their U~ copied
+ * to the caller's buffer and their device memory freed.  A request's result
+ * does not depend on which other requests share its steps.  FP64 only. */
+typedef struct ecmg_server ecmg_server;
+
+/* opt: NULL = defaults (precision must be ECMG_FP64); the server's work runs
+ * on opt->hip_stream or a stream of its own. */
+int ecmg_server_create(const ecmg_options *opt, size_t hbm_budget_bytes, ecmg_server **out);
+
+/* Queue a request.  problem and everything it points to (callbacks and their
+ * user data) must stay valid until the request is admitted; host_out (NULL or
+ * a dense array of the finest level's nodes, caller-owned) receives U~ and must
+ * stay valid until the request is done.  ECMG_ENOMEM if its hierarchy alone
+ * exceeds the budget. */
+int ecmg_server_submit(ecmg_server *srv, const ecmg_problem *problem, double rel_tol, double *host_out,
+                       uint64_t *ticket);
+
+/* Admit what fits, run one level of every admitted request, finish completed
+ * ones.  n_done: NULL or the number completed in this step. */
+int ecmg_server_step(ecmg_server *srv, int32_t *n_done);
+
+/* state: 0 queued, 1 running, 2 done, < 0 the error status of a failed request;
+ * info (NULL or `levels` entries) is filled once done. */
+int ecmg_server_poll(ecmg_server *srv, uint64_t ticket, int32_t *state, ecmg_level_info *info);
+
+/* Latency from submit to U~ on the host over completed requests (p50, p99, in
+ * ms), completed requests per second since creation or the last reset. */
+int ecmg_server_stats(ecmg_server *srv, double *p50_ms, double *p99_ms, double *solves_per_s, int64_t *done);
+int ecmg_server_reset_stats(ecmg_server *srv);
+void ecmg_server_destroy(ecmg_server *srv);
+
 /* EXP_finite alone: W_l from the current u_{l-1} and u_{l-2} (2 <= level);
  * writes W_l into u_l on free nodes (Dirichlet nodes keep g_D) and into the W
  * vector when kept.  Used for testing and for resuming a cascade. */

@@ -71,7 +71,8 @@ EXPORTS = ["ecmg_default_options", "ecmg_create", "ecmg_setup", "ecmg_solve", "e
            "ecmg_extrapolate", "ecmg_prolongate", "ecmg_jcg", "ecmg_apply", "ecmg_get", "ecmg_set",
            "ecmg_device_view", "ecmg_norms", "ecmg_level_dims", "ecmg_plan_bytes", "ecmg_kernel_times",
            "ecmg_reset_kernel_times", "ecmg_last_error", "ecmg_destroy", "ecmg_solve_batch",
-           "ecmg_extrapolate_batch"]
+           "ecmg_extrapolate_batch", "ecmg_server_create", "ecmg_server_submit", "ecmg_server_step",
+           "ecmg_server_poll", "ecmg_server_stats", "ecmg_server_reset_stats", "ecmg_server_destroy"]
 
 _lib = None
 
@@ -116,6 +117,15 @@ def load_library(path: str = LIB_PATH):
     L.ecmg_destroy.restype = None
     L.ecmg_solve_batch.argtypes = [P, i32, dbl, P]
     L.ecmg_extrapolate_batch.argtypes = [P, i32]
+    L.ecmg_server_create.argtypes = [ctypes.POINTER(Options), ctypes.c_size_t, ctypes.POINTER(P)]
+    L.ecmg_server_submit.argtypes = [P, ctypes.POINTER(ProblemC), dbl, P, ctypes.POINTER(ctypes.c_uint64)]
+    L.ecmg_server_step.argtypes = [P, ctypes.POINTER(i32)]
+    L.ecmg_server_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(i32), P]
+    L.ecmg_server_stats.argtypes = [P, ctypes.POINTER(dbl), ctypes.POINTER(dbl), ctypes.POINTER(dbl),
+                                    ctypes.POINTER(ctypes.c_int64)]
+    L.ecmg_server_reset_stats.argtypes = [P]
+    L.ecmg_server_destroy.argtypes = [P]
+    L.ecmg_server_destroy.restype = None
     for name in EXPORTS:
         getattr(L, name)
     _lib = L
@@ -395,6 +405,82 @@ def extrapolate_batch(solvers: Sequence["Solver"]) -> None:
     if rc != OK:
         msg = L.ecmg_last_error(solvers[0].h)
         raise EcmgError(rc, (msg or b"").decode())
+
+
+class Server:
+    """ecmg_server: continuous batching of independent requests (FP64).
+
+    submit() queues a problem (its field structures are kept alive here until
+    the request is done); step() admits, advances every admitted request by one
+    level and finishes completed ones; result() returns U~ on the finest grid."""
+
+    def __init__(self, hbm_budget_bytes: int, device_fields: bool = True, **opts):
+        self.L = load_library()
+        o = Options()
+        self.L.ecmg_default_options(ctypes.byref(o))
+        for k, v in opts.items():
+            setattr(o, k, v)
+        self.h = ctypes.c_void_p()
+        rc = self.L.ecmg_server_create(ctypes.byref(o), int(hbm_budget_bytes), ctypes.byref(self.h))
+        if rc != OK:
+            raise EcmgError(rc, (self.L.ecmg_last_error(None) or b"").decode())
+        self.device_fields = device_fields
+        self._req = {}
+
+    def _check(self, rc):
+        if rc != OK:
+            raise EcmgError(rc, (self.L.ecmg_last_error(None) or b"").decode())
+
+    def submit(self, problem, rel_tol: float, want_result: bool = True) -> int:
+        p, keep = problem_struct(problem, self.device_fields)
+        n = [int(v) << (problem.levels - 1) for v in problem.n0]
+        out = np.empty((n[2] + 1, n[1] + 1, n[0] + 1)) if want_result else None
+        t = ctypes.c_uint64()
+        self._check(self.L.ecmg_server_submit(self.h, ctypes.byref(p), float(rel_tol),
+                                              out.ctypes.data if out is not None else None, ctypes.byref(t)))
+        self._req[t.value] = (p, keep, out, problem.levels)
+        return t.value
+
+    def step(self) -> int:
+        d = ctypes.c_int32()
+        self._check(self.L.ecmg_server_step(self.h, ctypes.byref(d)))
+        return d.value
+
+    def poll(self, ticket: int):
+        """(state, infos): state 0 queued, 1 running, 2 done, < 0 error."""
+        st = ctypes.c_int32()
+        levels = self._req[ticket][3]
+        info = (LevelInfo * levels)()
+        self._check(self.L.ecmg_server_poll(self.h, ticket, ctypes.byref(st), info))
+        return st.value, ([i.as_dict() for i in info] if st.value == 2 else None)
+
+    def result(self, ticket: int):
+        return self._req[ticket][2]
+
+    def release(self, ticket: int):
+        """Drop the kept problem structures and result of a finished request."""
+        self._req.pop(ticket, None)
+
+    def stats(self) -> dict:
+        p50, p99, sps = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        done = ctypes.c_int64()
+        self._check(self.L.ecmg_server_stats(self.h, ctypes.byref(p50), ctypes.byref(p99), ctypes.byref(sps),
+                                             ctypes.byref(done)))
+        return {"p50_ms": p50.value, "p99_ms": p99.value, "solves_per_s": sps.value, "done": done.value}
+
+    def reset_stats(self):
+        self._check(self.L.ecmg_server_reset_stats(self.h))
+
+    def close(self):
+        if self.h:
+            self.L.ecmg_server_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 def plan_bytes(problem, precision: int = FP64) -> int:

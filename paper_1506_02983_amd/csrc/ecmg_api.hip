@@ -4,7 +4,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <deque>
+#include <mutex>
+#include <unordered_map>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -120,14 +124,21 @@ static int dalloc_n(ecmg_ctx *c, T **p, int64_t n) {
     return ECMG_OK;
 }
 
-// dense host node array <-> padded device node array of level geometry g
-static hipError_t copy_in(const Geom &g, double *dev, const double *host, hipStream_t s, hipMemcpyKind kind) {
-    return hipMemcpy2DAsync(dev, 8 * (size_t)g.sx, host, 8 * (size_t)(g.nx + 1), 8 * (size_t)(g.nx + 1),
-                            (size_t)g.sy * (g.nz + 1), kind, s);
+// dense host node array <-> padded device node array of level geometry g,
+// through the dense device buffer `dense` (one contiguous transfer, the row
+// padding handled by a pack kernel: a pitched copy with short rows is slow)
+static hipError_t copy_in(const Geom &g, double *dev, const double *host, double *dense, hipStream_t s,
+                          hipMemcpyKind kind) {
+    const hipError_t e = hipMemcpyAsync(dense, host, 8 * (size_t)g.nreal, kind, s);
+    if (e != hipSuccess) return e;
+    launch_unpack(g, dense, dev, s);
+    return hipGetLastError();
 }
-static hipError_t copy_out(const Geom &g, double *host, const double *dev, hipStream_t s) {
-    return hipMemcpy2DAsync(host, 8 * (size_t)(g.nx + 1), dev, 8 * (size_t)g.sx, 8 * (size_t)(g.nx + 1),
-                            (size_t)g.sy * (g.nz + 1), hipMemcpyDeviceToHost, s);
+static hipError_t copy_out(const Geom &g, double *host, const double *dev, double *dense, hipStream_t s) {
+    launch_pack(g, dev, dense, s);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return hipMemcpyAsync(host, dense, 8 * (size_t)g.nreal, hipMemcpyDeviceToHost, s);
 }
 static void dfree(void *p) {
     if (p) (void)hipFree(p);
@@ -1248,7 +1259,7 @@ int ecmg_extrapolate(ecmg_ctx *c, int32_t level, double *host_out) {
     CHK(rec_flush(c, 1));
     Level &L = c->lv[level];
     if (host_out) {
-        HIPCHK(c, copy_out(L.g, host_out, L.Ut, c->stream));
+        HIPCHK(c, copy_out(L.g, host_out, L.Ut, c->r, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }
     return ECMG_OK;
@@ -1293,7 +1304,7 @@ int ecmg_get(ecmg_ctx *c, int32_t level, int32_t which, double *host_out) {
     Level &L = c->lv[level];
     double *d = vec_ptr(c, L, which);
     if (!d) return fail(c, ECMG_EINVAL, "vector %d is not available on level %d", which, level);
-    HIPCHK(c, copy_out(L.g, host_out, d, c->stream));
+    HIPCHK(c, copy_out(L.g, host_out, d, c->r, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return ECMG_OK;
 }
@@ -1307,7 +1318,7 @@ int ecmg_set(ecmg_ctx *c, int32_t level, int32_t which, const double *host_in) {
     double *d = vec_ptr(c, L, which);
     if (!d || which == ECMG_VEC_F || which == ECMG_VEC_DINV)
         return fail(c, ECMG_EINVAL, "vector %d cannot be set", which);
-    HIPCHK(c, copy_in(L.g, d, host_in, c->stream, hipMemcpyHostToDevice));
+    HIPCHK(c, copy_in(L.g, d, host_in, c->r, c->stream, hipMemcpyHostToDevice));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return ECMG_OK;
 }
@@ -1333,13 +1344,13 @@ int ecmg_apply(ecmg_ctx *c, int32_t level, const double *host_in, double *host_o
     CHK(check_level(c, &level, 0));
     if (!host_in || !host_out) return fail(c, ECMG_EINVAL, "NULL buffer");
     Level &L = c->lv[level];
-    HIPCHK(c, copy_in(L.g, c->p0, host_in, c->stream, hipMemcpyHostToDevice));
+    HIPCHK(c, copy_in(L.g, c->p0, host_in, c->r, c->stream, hipMemcpyHostToDevice));
     StencilArgs<double> a = stencil_args(c, L);
     a.v = c->p0;
     a.q = c->q;
     launch_stencil<double>(MODE_APPLY, a, c->stream);
     HIPCHK(c, hipGetLastError());
-    HIPCHK(c, copy_out(L.g, host_out, c->q, c->stream));
+    HIPCHK(c, copy_out(L.g, host_out, c->q, c->r, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return ECMG_OK;
 }
@@ -1358,7 +1369,7 @@ int ecmg_norms(ecmg_ctx *c, int32_t level, int32_t which, int32_t minus_which, c
     }
     const double *h = nullptr;
     if (minus) {   // dense node array (host or device) into the padded layout
-        HIPCHK(c, copy_in(L.g, c->q, minus, c->stream,
+        HIPCHK(c, copy_in(L.g, c->q, minus, c->r, c->stream,
                           minus_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice));
         h = c->q;
     }
@@ -1396,6 +1407,353 @@ int ecmg_reset_kernel_times(ecmg_ctx *c) {
             L.kt_n[k] = 0;
         }
     return ECMG_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// serving loop: continuous batching of independent requests
+// ---------------------------------------------------------------------------
+namespace {
+using Clock = std::chrono::steady_clock;
+
+struct ServerReq {
+    uint64_t ticket = 0;
+    ecmg_problem prob{};
+    double rel_tol = 0.0;
+    double *host_out = nullptr;
+    size_t bytes = 0;
+    ecmg_ctx *ctx = nullptr;
+    int level = 0;                     // next level to solve
+    int state = 0;                     // 0 queued, 1 running, 2 done, < 0 error status
+    std::vector<ecmg_level_info> info;
+    Clock::time_point t_submit, t_done;
+};
+}  // namespace
+
+struct ecmg_server {
+    ecmg_options opt{};
+    size_t budget = 0, used = 0;
+    hipStream_t stream = nullptr;
+    ecmg_ctx *lead = nullptr;          // holds the queue-kernel buffers
+    std::mutex mu;                     // guards queue, tickets and statistics
+    std::deque<ServerReq *> queue;
+    std::vector<ServerReq *> active;
+    std::unordered_map<uint64_t, ServerReq *> reqs;
+    uint64_t next_ticket = 1;
+    std::vector<double> lat_ms;
+    bool have_t0 = false;
+    Clock::time_point t0, t_last;
+    int64_t ndone = 0;
+};
+
+// Finish a request: EXP_true on its finest level, U~ to the caller's buffer,
+// hierarchy freed.
+static int server_complete(ecmg_server *S, ServerReq *r) {
+    ecmg_ctx *c = r->ctx;
+    const int L = c->nlev - 1;
+    int rc = ECMG_OK;
+    if (L >= 1) rc = do_exp_true(c, L);
+    if (rc == ECMG_OK && r->host_out) {
+        const Level &F = c->lv[L];
+        if (copy_out(F.g, r->host_out, F.Ut, c->r, c->stream) != hipSuccess)
+            rc = fail(c, ECMG_EDEVICE, "copy of U~ failed");
+    }
+    if (rc == ECMG_OK && hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(c, ECMG_EDEVICE, "sync failed");
+    ecmg_destroy(c);
+    r->ctx = nullptr;
+    std::lock_guard<std::mutex> g(S->mu);
+    r->t_done = Clock::now();
+    r->state = rc == ECMG_OK ? 2 : rc;
+    S->used -= r->bytes;
+    if (rc == ECMG_OK) {
+        S->lat_ms.push_back(std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count());
+        ++S->ndone;
+        S->t_last = r->t_done;
+    }
+    return rc;
+}
+
+// One tick: the current level of every active request.  Levels the persistent
+// kernel handles (small grids) of all requests run together in one launch of
+// the queue kernel, after one batched EXP_finite launch; larger levels run the
+// tiled JCG of their own request on the same stream.
+static int server_tick(ecmg_server *S) {
+    ecmg_ctx *c0 = S->lead;
+    hipStream_t s = S->stream;
+    std::vector<ServerReq *> small, big;
+    for (ServerReq *r : S->active) (uses_persistent(r->ctx, r->level) ? small : big).push_back(r);
+    const auto t_start = Clock::now();
+    const int n = (int)small.size();
+    std::vector<int> order(n);
+    if (n > 0) {
+        CHK(batch_reserve(c0, n));
+        std::vector<PersistentTask> tasks(n);
+        std::vector<ExpTask> ex;
+        int64_t nb0 = 0, nb1 = 0;
+        for (int k = 0; k < n; ++k) {
+            ServerReq *r = small[k];
+            ecmg_ctx *c = r->ctx;
+            const int l = r->level;
+            Level &L = c->lv[l];
+            if (l >= 2) {
+                ExpTask e{};
+                e.gf = L.g;
+                e.g1 = c->lv[l - 1].g;
+                e.U1 = c->lv[l - 1].x;
+                e.U0 = c->lv[l - 2].x;
+                e.V = c->q;
+                e.x = L.x;
+                e.W = L.W;
+                e.variant = c->opt.interp;
+                exp_task_blocks(e);
+                e.b0[0] = nb0;
+                e.b0[1] = nb1;
+                nb0 += e.nb[0];
+                nb1 += e.nb[1];
+                ex.push_back(e);
+            }
+            const double tol = (l < 2 ? c->opt.dsolve_tol : r->rel_tol) * L.nf;
+            tasks[k] = batch_task(c, l, tol, l < 2 ? 100000 : c->opt.max_iter, nullptr);
+            tasks[k].zero_x = l < 2;
+        }
+        for (int k = 0; k < n; ++k) order[k] = k;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int x, int y) { return tasks[x].g.nreal > tasks[y].g.nreal; });
+        std::vector<PersistentTask> sorted(n);
+        int items = 0;
+        for (int k = 0; k < n; ++k) {
+            sorted[k] = tasks[order[k]];
+            sorted[k].sc = c0->bt_sc + k;
+            sorted[k].err = (int *)(c0->bt_bar + 32 * k);
+            sorted[k].bar = c0->bt_bar + 32 * k + 16;
+            sorted[k].nwg = std::min(sorted[k].nwg, c0->queue_blocks);
+            sorted[k].wg0 = items;
+            items += sorted[k].nwg;
+        }
+        if (!ex.empty()) {
+            if (nb0 >= ((int64_t)1 << 31) || nb1 >= ((int64_t)1 << 31))
+                return fail(c0, ECMG_EINVAL, "batched EXP_finite grid too large");
+            HIPCHK(c0, hipMemcpyAsync(c0->bt_exp, ex.data(), sizeof(ExpTask) * ex.size(), hipMemcpyHostToDevice, s));
+            launch_exp_finite_batch(c0->bt_exp, (int)ex.size(), nb0, nb1, s);
+            HIPCHK(c0, hipGetLastError());
+        }
+        HIPCHK(c0, hipMemsetAsync(c0->bt_bar, 0, 32 * sizeof(unsigned) * (size_t)n, s));
+        HIPCHK(c0, hipMemcpyAsync(c0->bt_tasks, sorted.data(), sizeof(PersistentTask) * n, hipMemcpyHostToDevice, s));
+        HIPCHK(c0, hipMemsetAsync(c0->bt_next, 0, sizeof(unsigned), s));
+        HIPCHK(c0, launch_jcg_queue(c0->bt_tasks, n, items, std::max(1, std::min(items, c0->queue_blocks)),
+                                    c0->bt_next, s));
+        HIPCHK(c0, hipMemcpyAsync(c0->bt_sc_host, c0->bt_sc, sizeof(JcgScalars) * n, hipMemcpyDeviceToHost, s));
+    }
+    // larger levels: the tiled path of each request (on the same stream)
+    for (ServerReq *r : big) {
+        ecmg_ctx *c = r->ctx;
+        const int l = r->level;
+        ecmg_level_info li{};
+        li.level = l;
+        li.nx = c->lv[l].g.nx;
+        li.ny = c->lv[l].g.ny;
+        li.nz = c->lv[l].g.nz;
+        int rc;
+        if (l >= 2) {
+            CHK(do_exp_finite(c, l));
+            rc = run_level_jcg(c, l, r->rel_tol * c->lv[l].nf, c->opt.max_iter, -1, &li);
+        } else {
+            launch_zero_free(c->lv[l].g, c->lv[l].x, s);
+            rc = run_level_jcg(c, l, c->opt.dsolve_tol * c->lv[l].nf, 100000, -1, &li);
+            if (rc == ECMG_ENOTCONV) rc = ECMG_OK;
+        }
+        if (rc == ECMG_EDEVICE) return rc;
+        li.status = rc;
+        r->info[l] = li;
+    }
+    HIPCHK(c0, hipStreamSynchronize(s));
+    const float ms = (float)std::chrono::duration<double, std::milli>(Clock::now() - t_start).count();
+    for (int k = 0; k < n; ++k) {
+        ServerReq *r = small[order[k]];
+        ecmg_ctx *c = r->ctx;
+        const int l = r->level;
+        const Level &L = c->lv[l];
+        const JcgScalars &sc = c0->bt_sc_host[k];
+        ecmg_level_info li{};
+        li.level = l;
+        li.nx = L.g.nx;
+        li.ny = L.g.ny;
+        li.nz = L.g.nz;
+        li.iters = sc.iter;
+        li.rre = (L.nf > 0) ? std::sqrt(sc.rr) / L.nf : 0.0;
+        li.nf = L.nf;
+        int st = (sc.done == DONE_BREAKDOWN) ? ECMG_EBREAKDOWN : (sc.done == DONE_MAXITER) ? ECMG_ENOTCONV : ECMG_OK;
+        if (l < 2 && st == ECMG_ENOTCONV) st = ECMG_OK;
+        li.status = st;
+        r->info[l] = li;
+    }
+    for (ServerReq *r : S->active) {
+        r->info[r->level].ms = ms;
+        ++r->level;
+    }
+    return ECMG_OK;
+}
+
+extern "C" {
+
+int ecmg_server_create(const ecmg_options *opt, size_t hbm_budget_bytes, ecmg_server **out) {
+    if (!out) return fail(nullptr, ECMG_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (hbm_budget_bytes == 0) return fail(nullptr, ECMG_EINVAL, "hbm_budget_bytes is 0");
+    ecmg_server *S = new ecmg_server();
+    if (opt) S->opt = *opt;
+    else ecmg_default_options(&S->opt);
+    if (S->opt.precision != ECMG_FP64) {
+        delete S;
+        return fail(nullptr, ECMG_EINVAL, "the server runs FP64 only");
+    }
+    S->opt.keep_w = 0;
+    S->opt.timing = 0;
+    S->budget = hbm_budget_bytes;
+    if (S->opt.hip_stream) {
+        S->stream = (hipStream_t)S->opt.hip_stream;
+    } else if (hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess) {
+        delete S;
+        return fail(nullptr, ECMG_EDEVICE, "hipStreamCreate failed");
+    }
+    ecmg_options lo = S->opt;
+    lo.hip_stream = S->stream;
+    const int rc = ecmg_create(&lo, &S->lead);
+    if (rc != ECMG_OK) {
+        if (!S->opt.hip_stream) (void)hipStreamDestroy(S->stream);
+        delete S;
+        return rc;
+    }
+    *out = S;
+    return ECMG_OK;
+}
+
+int ecmg_server_submit(ecmg_server *S, const ecmg_problem *problem, double rel_tol, double *host_out,
+                       uint64_t *ticket) {
+    if (!S || !problem || !ticket) return fail(nullptr, ECMG_EINVAL, "NULL argument");
+    if (!(rel_tol >= 0.0)) return fail(S->lead, ECMG_EINVAL, "rel_tol = %g must be >= 0", rel_tol);
+    CHK(validate(S->lead, problem));
+    size_t bytes = 0;
+    CHK(ecmg_plan_bytes(problem, ECMG_FP64, &bytes));
+    if (bytes > S->budget)
+        return fail(S->lead, ECMG_ENOMEM, "request needs %zu bytes, above the budget of %zu", bytes, S->budget);
+    ServerReq *r = new ServerReq();
+    r->prob = *problem;
+    r->rel_tol = rel_tol;
+    r->host_out = host_out;
+    r->bytes = bytes;
+    r->info.assign(problem->levels, ecmg_level_info{});
+    std::lock_guard<std::mutex> g(S->mu);
+    r->t_submit = Clock::now();
+    if (!S->have_t0) {
+        S->t0 = r->t_submit;
+        S->have_t0 = true;
+    }
+    r->ticket = S->next_ticket++;
+    S->queue.push_back(r);
+    S->reqs[r->ticket] = r;
+    *ticket = r->ticket;
+    return ECMG_OK;
+}
+
+int ecmg_server_step(ecmg_server *S, int32_t *n_done) {
+    if (!S) return fail(nullptr, ECMG_EINVAL, "server is NULL");
+    if (n_done) *n_done = 0;
+    // admission, first come first served, while the hierarchy fits the budget
+    for (;;) {
+        ServerReq *r = nullptr;
+        {
+            std::lock_guard<std::mutex> g(S->mu);
+            if (S->queue.empty()) break;
+            if (S->used + S->queue.front()->bytes > S->budget) break;
+            r = S->queue.front();
+            S->queue.pop_front();
+            S->used += r->bytes;
+        }
+        ecmg_options o = S->opt;
+        o.hip_stream = S->stream;
+        int rc = ecmg_create(&o, &r->ctx);
+        if (rc == ECMG_OK) rc = ecmg_setup(r->ctx, &r->prob);
+        if (rc != ECMG_OK) {
+            if (r->ctx) ecmg_destroy(r->ctx);
+            r->ctx = nullptr;
+            std::lock_guard<std::mutex> g(S->mu);
+            r->state = rc;
+            S->used -= r->bytes;
+            continue;
+        }
+        r->state = 1;
+        S->active.push_back(r);
+    }
+    if (S->active.empty()) return ECMG_OK;
+    CHK(server_tick(S));
+    int32_t done = 0;
+    std::vector<ServerReq *> keep;
+    for (ServerReq *r : S->active) {
+        if (r->level < r->ctx->nlev) {
+            keep.push_back(r);
+            continue;
+        }
+        const int rc = server_complete(S, r);
+        if (rc == ECMG_EDEVICE) return rc;
+        ++done;
+    }
+    S->active.swap(keep);
+    if (n_done) *n_done = done;
+    return ECMG_OK;
+}
+
+int ecmg_server_poll(ecmg_server *S, uint64_t ticket, int32_t *state, ecmg_level_info *info) {
+    if (!S || !state) return fail(nullptr, ECMG_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> g(S->mu);
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end()) return fail(S->lead, ECMG_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    ServerReq *r = it->second;
+    *state = r->state;
+    if (info && r->state == 2)
+        for (size_t l = 0; l < r->info.size(); ++l) info[l] = r->info[l];
+    return ECMG_OK;
+}
+
+int ecmg_server_stats(ecmg_server *S, double *p50_ms, double *p99_ms, double *solves_per_s, int64_t *done) {
+    if (!S) return fail(nullptr, ECMG_EINVAL, "server is NULL");
+    std::lock_guard<std::mutex> g(S->mu);
+    std::vector<double> v = S->lat_ms;
+    std::sort(v.begin(), v.end());
+    auto pct = [&](double p) {
+        if (v.empty()) return 0.0;
+        const size_t k = (size_t)std::min<double>((double)v.size() - 1, std::ceil(p * (double)v.size()) - 1);
+        return v[k];
+    };
+    if (p50_ms) *p50_ms = pct(0.50);
+    if (p99_ms) *p99_ms = pct(0.99);
+    if (solves_per_s) {
+        const double s = S->ndone > 0 ? std::chrono::duration<double>(S->t_last - S->t0).count() : 0.0;
+        *solves_per_s = s > 0 ? (double)S->ndone / s : 0.0;
+    }
+    if (done) *done = S->ndone;
+    return ECMG_OK;
+}
+
+int ecmg_server_reset_stats(ecmg_server *S) {
+    if (!S) return fail(nullptr, ECMG_EINVAL, "server is NULL");
+    std::lock_guard<std::mutex> g(S->mu);
+    S->lat_ms.clear();
+    S->ndone = 0;
+    S->have_t0 = true;
+    S->t0 = Clock::now();
+    return ECMG_OK;
+}
+
+void ecmg_server_destroy(ecmg_server *S) {
+    if (!S) return;
+    for (ServerReq *r : S->active)
+        if (r->ctx) ecmg_destroy(r->ctx);
+    for (auto &kv : S->reqs) delete kv.second;
+    if (S->lead) ecmg_destroy(S->lead);
+    if (!S->opt.hip_stream && S->stream) (void)hipStreamDestroy(S->stream);
+    delete S;
 }
 
 }  // extern "C"

@@ -200,6 +200,9 @@ void launch_zero_pad(const Geom &g, double *a, double *b, double *c, double *d, 
 void launch_zero_pad_f32(const Geom &g, float *a, float *b, float *c, hipStream_t s);
 
 void launch_fill(double *p, int64_t n, double v, hipStream_t s);
+// dense (n_x+1)(n_y+1)(n_z+1) node array <-> padded level layout
+void launch_pack(const Geom &g, const double *padded, double *dense, hipStream_t s);
+void launch_unpack(const Geom &g, const double *dense, double *padded, hipStream_t s);
 void launch_zero_free(const Geom &g, double *x, hipStream_t s);
 void launch_load_volume(const Geom &g, int e0, int e1, const double *fg, double *F, hipStream_t s);
 void launch_load_face(const Geom &g, int face, const double *gR, double *F, hipStream_t s);

@@ -301,4 +301,27 @@ void launch_norms(const Geom &g, const double *a, const double *b, const double 
     hipLaunchKernelGGL(k_norms, dim3(reduce_blocks(g.nnodes)), dim3(256), 0, s, g, a, b, c, partials, counter, out);
 }
 
+// dense node array (x fastest, no padding) <-> padded level layout
+__global__ void k_pack(const Geom g, const double *__restrict__ padded, double *__restrict__ dense, int unpack) {
+    const int w = g.nx + 1;
+    const int64_t rows = (int64_t)g.sy * (g.nz + 1);
+    for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
+        const int64_t d0 = row * w, p0 = row * g.sx;
+        for (int i = threadIdx.x; i < w; i += blockDim.x) {
+            if (unpack) ((double *)padded)[p0 + i] = dense[d0 + i];
+            else dense[d0 + i] = padded[p0 + i];
+        }
+    }
+}
+
+void launch_pack(const Geom &g, const double *padded, double *dense, hipStream_t s) {
+    const int64_t nb = std::max<int64_t>(1, std::min<int64_t>((int64_t)g.sy * (g.nz + 1), 65536));
+    hipLaunchKernelGGL(k_pack, dim3((unsigned)nb), dim3(256), 0, s, g, padded, dense, 0);
+}
+
+void launch_unpack(const Geom &g, const double *dense, double *padded, hipStream_t s) {
+    const int64_t nb = std::max<int64_t>(1, std::min<int64_t>((int64_t)g.sy * (g.nz + 1), 65536));
+    hipLaunchKernelGGL(k_pack, dim3((unsigned)nb), dim3(256), 0, s, g, (const double *)padded, (double *)dense, 1);
+}
+
 }  // namespace ecmg
