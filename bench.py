@@ -159,6 +159,43 @@ def precision_comparison(E, torch, name="high-contrast-513x257x257", steps=3):
     return res
 
 
+def batched(E, torch, n_boxes=512, steps=3):
+    """512 independent three-level solves (uneven boxes) through the batched
+    API: one step = ecmg_solve_batch + ecmg_extrapolate_batch over all boxes."""
+    import workloads
+    probs = workloads.batched_mix(n_boxes, seed=0)
+    t0 = time.perf_counter()
+    solvers = [E.Solver(keep_w=False).setup(p, device_fields=True) for p in probs]
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    nodes = sum(p.nodes_at(p.levels - 1) for p in probs)
+    eps = probs[0].eps
+    E.solve_batch(solvers, eps)
+    E.extrapolate_batch(solvers)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        infos = E.solve_batch(solvers, eps)
+        E.extrapolate_batch(solvers)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    # the same boxes one by one through ecmg_solve (a sample of 64) for context
+    t0 = time.perf_counter()
+    for sv in solvers[:64]:
+        sv.solve(eps)
+        sv.extrapolate(sv.levels - 1, out=False)
+    torch.cuda.synchronize()
+    seq = (time.perf_counter() - t0) * n_boxes / 64
+    it = [i[-1]["iters"] for i in infos]
+    for sv in solvers:
+        sv.close()
+    return {"boxes": n_boxes, "finest_nodes_total": nodes, "setup_s": setup_s, "ms_per_step": 1e3 * dt,
+            "boxes_per_s": n_boxes / dt, "unknowns_per_s": nodes / dt,
+            "level_ms": [infos[0][l]["ms"] for l in range(3)],
+            "finest_iters_mean": sum(it) / len(it), "finest_iters_max": max(it),
+            "sequential_ms_estimate": 1e3 * seq, "speedup_vs_sequential": seq / dt}
+
+
 def serving(E, n_measured=200, n_warmup=20, rate=50.0, budget=200 * 10 ** 9):
     """Replay a seeded Poisson stream of requests (finest 32^3..256^3,
     random coefficients and faces) against the serving loop; latency is from
@@ -220,6 +257,7 @@ def main():
                          "for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE")
     ap.add_argument("--no-precision-comparison", action="store_true",
                     help="skip the FP64 vs mixed comparison on the high-contrast workload")
+    ap.add_argument("--batch-boxes", type=int, default=512, help="boxes of the batched workload (0 = skip)")
     ap.add_argument("--serve-requests", type=int, default=200,
                     help="measured requests of the serving replay (0 = skip), after 20 warm-up requests")
     ap.add_argument("--no-fourth-order", action="store_true",
@@ -363,6 +401,14 @@ def main():
     if not args.no_precision_comparison:
         prec_cmp = precision_comparison(E, torch)
 
+    batch = None
+    if args.batch_boxes > 0:
+        batch = batched(E, torch, args.batch_boxes)
+        print("bench: batched %d boxes: %.2f ms/step, %.0f boxes/s" % (batch["boxes"], batch["ms_per_step"],
+                                                                     batch["boxes_per_s"]),
+              file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+
     serve = None
     if args.serve_requests > 0:
         serve = serving(E, n_measured=args.serve_requests)
@@ -389,6 +435,7 @@ def main():
         "jcg_hbm_gbs_finest": jcg_gbs,
         "fourth_order": fourth,
         "precision_comparison": prec_cmp,
+        "batched": batch,
         "serving": serve,
         "setup_s": setup_s,
         "levels": [{"level": i["level"], "n": [i["nx"], i["ny"], i["nz"]], "iters": i["iters"],

@@ -183,14 +183,15 @@ void launch_exp_true(const Geom &gf, const double *U1, const double *U0, double 
 
 // One box of a batched EXP_finite (U1 = u_{l-1}, U0 = u_{l-2}, V scratch on
 // level l-1, x and optional W on level l) or EXP_true (U1 = u_l, U0 = u_{l-1},
-// result into x).  b0 / nb / gx: first flat block, block count and blocks per
-// row chunk of phase 0 (level l-1 grid) and phase 1 (fine grid).
+// result into x).  b0 / nb / gx / gy: first flat block, block count, blocks
+// along x and along y of phase 0 (level l-1 grid) and phase 1 (fine grid);
+// a block is 64 x-nodes by 4 y-rows of one z-plane.
 struct ExpTask {
     Geom gf, g1;
     const double *U1, *U0;
     double *V, *x, *W;
     int variant;
-    int gx[2];
+    int gx[2], gy[2];
     int64_t nb[2], b0[2];
 };
 void exp_task_blocks(ExpTask &t);

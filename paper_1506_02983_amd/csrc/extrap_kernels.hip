@@ -56,11 +56,10 @@ __device__ __forceinline__ double u_at(const double *U, int64_t sx, int64_t sxy,
 
 __device__ __forceinline__ void exp_finite_nodal_block(const Geom &g1, const double *__restrict__ U1,
                                                        const double *__restrict__ U0, double *__restrict__ V,
-                                                       int variant, int bx, int64_t by) {
+                                                       int variant, int bx, int by, int bz) {
     const int p = bx * 64 + threadIdx.x;
-    const int64_t row = by * 4 + threadIdx.y;
-    if (p > g1.nx || row >= (int64_t)g1.sy * (g1.nz + 1)) return;
-    const int q = (int)(row % g1.sy), r = (int)(row / g1.sy);
+    const int q = by * 4 + threadIdx.y, r = bz;
+    if (p > g1.nx || q > g1.ny || r > g1.nz) return;
     const int64_t s1 = g1.sx, s1y = (int64_t)g1.sx * g1.sy;
     const int64_t s0 = row_pitch(g1.nx / 2 + 1), s0y = s0 * (g1.ny / 2 + 1);
     // eq. jiedian at a level l-2 node (all indices even)
@@ -140,7 +139,7 @@ __device__ __forceinline__ void exp_finite_nodal_block(const Geom &g1, const dou
 __global__ void __launch_bounds__(256) k_exp_finite_nodal(const Geom g1, const double *__restrict__ U1,
                                                           const double *__restrict__ U0, double *__restrict__ V,
                                                           int variant) {
-    exp_finite_nodal_block(g1, U1, U0, V, variant, blockIdx.x, blockIdx.y);
+    exp_finite_nodal_block(g1, U1, U0, V, variant, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 // Phase 2: every fine node of level l is the tri-quadratic Lagrange
@@ -149,11 +148,10 @@ __global__ void __launch_bounds__(256) k_exp_finite_nodal(const Geom g1, const d
 // uniform across the wave.
 __device__ __forceinline__ void exp_finite_interp_block(const Geom &gf, const double *__restrict__ V,
                                                         double *__restrict__ x, double *__restrict__ W, int bx,
-                                                        int64_t by) {
+                                                        int by, int bz) {
     const int i = bx * 64 + threadIdx.x;
-    const int64_t row = by * 4 + threadIdx.y;
-    if (i > gf.nx || row >= (int64_t)gf.sy * (gf.nz + 1)) return;
-    const int j = (int)(row % gf.sy), k = (int)(row / gf.sy);
+    const int j = by * 4 + threadIdx.y, k = bz;
+    if (i > gf.nx || j > gf.ny || k > gf.nz) return;
     const int NX = gf.nx / 4, NY = gf.ny / 4, NZ = gf.nz / 4;
     const int I = min(i / 4, NX - 1), J = min(j / 4, NY - 1), K = min(k / 4, NZ - 1);
     const int a = i - 4 * I, b = j - 4 * J, c = k - 4 * K;
@@ -181,7 +179,7 @@ __device__ __forceinline__ void exp_finite_interp_block(const Geom &gf, const do
 
 __global__ void __launch_bounds__(256) k_exp_finite_interp(const Geom gf, const double *__restrict__ V,
                                                            double *__restrict__ x, double *__restrict__ W) {
-    exp_finite_interp_block(gf, V, x, W, blockIdx.x, blockIdx.y);
+    exp_finite_interp_block(gf, V, x, W, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 // U~ = U1 + (1/3) T[U1 - U0]: eq. t1 at coarse nodes ((4 U1 - U0)/3), eq.
@@ -191,11 +189,10 @@ __global__ void __launch_bounds__(256) k_exp_finite_interp(const Geom gf, const 
 // z parities, hence the number of coarse differences, are wave-uniform.
 __device__ __forceinline__ void exp_true_block(const Geom &gf, const double *__restrict__ U1,
                                                const double *__restrict__ U0, double *__restrict__ Ut, int bx,
-                                               int64_t by) {
+                                               int by, int bz) {
     const int i = bx * 64 + threadIdx.x;
-    const int64_t row = by * 4 + threadIdx.y;
-    if (i > gf.nx || row >= (int64_t)gf.sy * (gf.nz + 1)) return;
-    const int j = (int)(row % gf.sy), k = (int)(row / gf.sy);
+    const int j = by * 4 + threadIdx.y, k = bz;
+    if (i > gf.nx || j > gf.ny || k > gf.nz) return;
     const int64_t sx = gf.sx, sxy = (int64_t)gf.sx * gf.sy;
     const int64_t cx = row_pitch(gf.nx / 2 + 1), cxy = cx * (gf.ny / 2 + 1);
     const int64_t id = i + sx * j + sxy * k;
@@ -223,7 +220,7 @@ __device__ __forceinline__ void exp_true_block(const Geom &gf, const double *__r
 
 __global__ void __launch_bounds__(256) k_exp_true(const Geom gf, const double *__restrict__ U1,
                                                   const double *__restrict__ U0, double *__restrict__ Ut) {
-    exp_true_block(gf, U1, U0, Ut, blockIdx.x, blockIdx.y);
+    exp_true_block(gf, U1, U0, Ut, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 // ---------------------------------------------------------------------------
@@ -243,21 +240,24 @@ __global__ void __launch_bounds__(256) k_exp_finite_nodal_batch(const ExpTask *_
     const int64_t b = blockIdx.x;
     const ExpTask &t = tasks[find_box(tasks, n, b, 0)];
     const int64_t lb = b - t.b0[0];
-    exp_finite_nodal_block(t.g1, t.U1, t.U0, t.V, t.variant, (int)(lb % t.gx[0]), lb / t.gx[0]);
+    const int64_t pl = lb / t.gx[0];
+    exp_finite_nodal_block(t.g1, t.U1, t.U0, t.V, t.variant, (int)(lb - pl * t.gx[0]), (int)(pl % t.gy[0]), (int)(pl / t.gy[0]));
 }
 
 __global__ void __launch_bounds__(256) k_exp_finite_interp_batch(const ExpTask *__restrict__ tasks, int n) {
     const int64_t b = blockIdx.x;
     const ExpTask &t = tasks[find_box(tasks, n, b, 1)];
     const int64_t lb = b - t.b0[1];
-    exp_finite_interp_block(t.gf, t.V, t.x, t.W, (int)(lb % t.gx[1]), lb / t.gx[1]);
+    const int64_t pl = lb / t.gx[1];
+    exp_finite_interp_block(t.gf, t.V, t.x, t.W, (int)(lb - pl * t.gx[1]), (int)(pl % t.gy[1]), (int)(pl / t.gy[1]));
 }
 
 __global__ void __launch_bounds__(256) k_exp_true_batch(const ExpTask *__restrict__ tasks, int n) {
     const int64_t b = blockIdx.x;
     const ExpTask &t = tasks[find_box(tasks, n, b, 1)];
     const int64_t lb = b - t.b0[1];
-    exp_true_block(t.gf, t.U1, t.U0, t.x, (int)(lb % t.gx[1]), lb / t.gx[1]);
+    const int64_t pl = lb / t.gx[1];
+    exp_true_block(t.gf, t.U1, t.U0, t.x, (int)(lb - pl * t.gx[1]), (int)(pl % t.gy[1]), (int)(pl / t.gy[1]));
 }
 
 // Block counts of a box: phase 0 over the level l-1 grid g1, phase 1 over the
@@ -265,8 +265,10 @@ __global__ void __launch_bounds__(256) k_exp_true_batch(const ExpTask *__restric
 void exp_task_blocks(ExpTask &t) {
     t.gx[0] = (t.g1.nx + 1 + 63) / 64;
     t.gx[1] = (t.gf.nx + 1 + 63) / 64;
-    t.nb[0] = (int64_t)t.gx[0] * (((int64_t)t.g1.sy * (t.g1.nz + 1) + 3) / 4);
-    t.nb[1] = (int64_t)t.gx[1] * (((int64_t)t.gf.sy * (t.gf.nz + 1) + 3) / 4);
+    t.gy[0] = (t.g1.ny + 1 + 3) / 4;
+    t.gy[1] = (t.gf.ny + 1 + 3) / 4;
+    t.nb[0] = (int64_t)t.gx[0] * t.gy[0] * (t.g1.nz + 1);
+    t.nb[1] = (int64_t)t.gx[1] * t.gy[1] * (t.gf.nz + 1);
 }
 
 void launch_exp_finite_batch(const ExpTask *d_tasks, int n, int64_t nb0, int64_t nb1, hipStream_t s) {
@@ -281,9 +283,9 @@ void launch_exp_true_batch(const ExpTask *d_tasks, int n, int64_t nb1, hipStream
 void launch_exp_finite(const Geom &gf, const Geom &g1, const double *U1, const double *U0, double *V, double *x,
                        double *W, int variant, hipStream_t s) {
     const dim3 blk(64, 4);
-    const dim3 g1grid((g1.nx + 1 + 63) / 64, (unsigned)(((int64_t)g1.sy * (g1.nz + 1) + 3) / 4));
+    const dim3 g1grid((g1.nx + 1 + 63) / 64, (g1.ny + 1 + 3) / 4, g1.nz + 1);
     hipLaunchKernelGGL(k_exp_finite_nodal, g1grid, blk, 0, s, g1, U1, U0, V, variant);
-    const dim3 gfgrid((gf.nx + 1 + 63) / 64, (unsigned)(((int64_t)gf.sy * (gf.nz + 1) + 3) / 4));
+    const dim3 gfgrid((gf.nx + 1 + 63) / 64, (gf.ny + 1 + 3) / 4, gf.nz + 1);
     hipLaunchKernelGGL(k_exp_finite_interp, gfgrid, blk, 0, s, gf, V, x, W);
 }
 
@@ -326,7 +328,7 @@ void launch_zero_pad_f32(const Geom &g, float *a, float *b, float *c, hipStream_
 }
 
 void launch_exp_true(const Geom &gf, const double *U1, const double *U0, double *Ut, hipStream_t s) {
-    const dim3 grid((gf.nx + 1 + 63) / 64, (unsigned)(((int64_t)gf.sy * (gf.nz + 1) + 3) / 4));
+    const dim3 grid((gf.nx + 1 + 63) / 64, (gf.ny + 1 + 3) / 4, gf.nz + 1);
     hipLaunchKernelGGL(k_exp_true, grid, dim3(64, 4), 0, s, gf, U1, U0, Ut);
 }
 
