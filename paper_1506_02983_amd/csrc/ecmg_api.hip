@@ -543,7 +543,7 @@ static int run_jcg_persistent(ecmg_ctx *c, int l, double tol_abs, int max_iter, 
     // loads), at most persist_nwg workgroups (every barrier costs more with
     // more of them)
     const int seg = c->persist_seglen > 0 ? c->persist_seglen : (L.g.nreal < 131072 ? 2 : 4);
-    t.seglen = std::max(1, std::min(seg, L.g.nz + 1));
+    t.seglen = seg >= 4 ? 4 : (seg >= 2 ? 2 : 1);         // the kernel's instantiations
     const int64_t nseg = (L.g.nz + t.seglen) / t.seglen;
     const int64_t units = (int64_t)(L.g.nx + 1) * (L.g.ny + 1) * nseg;
     t.nwg = (int)std::max<int64_t>(
@@ -1057,7 +1057,7 @@ static PersistentTask batch_task(ecmg_ctx *c, int l, double tol_abs, int max_ite
     // about batch_npw nodes per workgroup, at most 16 workgroups per box
     t.nwg = (int)std::max<int64_t>(1, std::min<int64_t>(L.g.nreal / c->batch_npw, 16));
     const int seg = c->persist_seglen > 0 ? c->persist_seglen : (L.g.nreal < 131072 ? 2 : 4);
-    t.seglen = std::max(1, std::min(seg, L.g.nz + 1));
+    t.seglen = seg >= 4 ? 4 : (seg >= 2 ? 2 : 1);         // the kernel's instantiations
     return t;
 }
 

@@ -13,8 +13,8 @@
 // stencil pass a thread marches up its segment holding three planes of the
 // 3x3 neighbourhood in registers.  p ping-pongs between two arrays.  Phase A
 // either stores p_k in an own-node pass and applies the stencil after a
-// barrier, or (ECMG_PERSIST_FUSED) forms the neighbours' p_k on the fly from
-// r, D^-1 and p_{k-1} with the owner's fused multiply-add.
+// barrier.  Segments are 1, 2 or 4 nodes long (a template parameter), and every
+// pass issues all loads of a segment before using any.
 // Every workgroup of a task sums the per-workgroup partials itself in the same
 // fixed order, so all of them take the same decision and the result does not
 // depend on which other tasks share the launch (batch invariance).
@@ -70,6 +70,13 @@ __device__ __forceinline__ void task_barrier(const PersistentTask &t, int nwg, u
     __syncthreads();
 }
 
+// Load element idx of a uniform base pointer with a 32-bit byte offset, the
+// form the SGPR-base global load takes: one VGPR per address instead of two.
+// The caller guarantees idx * 8 < 2^32.
+__device__ __forceinline__ double ldg(const gdouble *base, int idx) {
+    return *(const gdouble *)((const __attribute__((address_space(1))) char *)base + (unsigned)idx * 8u);
+}
+
 // Arrays of one task as global-memory pointers.
 struct TaskArrays {
     gdouble *X, *R, *Q, *PO, *PN;     // PO = p_{k-1} (read), PN = p_k (written)
@@ -77,28 +84,25 @@ struct TaskArrays {
     const gdouble *AL[6];
 };
 
-enum { MARCH_INIT = 0, MARCH_ITER = 1, MARCH_APPLY = 2 };
+enum { MARCH_INIT = 0, MARCH_APPLY = 2 };
 
-// ECMG_PERSIST_FUSED = 1: p_k is formed on the fly inside the stencil pass
-// (two barriers per iteration, three times the loads and about 200 VGPRs);
-// 0 (default, faster on gfx950): an own-node pass stores p_k first and the
-// stencil pass reads it (three barriers per iteration).
-#ifndef ECMG_PERSIST_FUSED
-#define ECMG_PERSIST_FUSED 0
-#endif
-
-// One column segment: node (i, j, k) for k in [k0, k1).
+// One column segment of SEG nodes: node (i, j, k) for k in [k0, k0 + SEG),
+// those above the grid (k > nz, last segment of a column) skipped.
 //   MARCH_INIT: r = F - A x on free nodes (0 on Dirichlet); acc += (r.D^-1 r, r.r)
-//   MARCH_APPLY: q = A p_k with p_k stored; acc[0] += p_k.q
-//   MARCH_ITER: x += alpha p_{k-1} (it > 0); p_k = D^-1 r + beta p_{k-1};
-//               q = A p_k on free nodes (0 on Dirichlet); acc[0] += p_k.q
-// The Q1 stencil is written per plane offset: the elements of the slab below
-// (sm) and above (sp) the node, summed over the 2x2 element columns that hold
-// both the node and each of the 3x3 in-plane neighbours.
-template <int MODE>
-__device__ __forceinline__ void march(const PGeom &g, const double *sC, const double (*sM)[3], const TaskArrays &A,
-                                      int i, int j, int k0, int k1, int it, double alpha, double beta,
-                                      double (&acc)[2]) {
+//   MARCH_APPLY: q = A p_k on free nodes (0 on Dirichlet); acc[0] += p_k.q
+// Every load of the segment (SEG + 2 planes of the 3x3 neighbourhood, SEG + 1
+// element slabs, the epilogue inputs) is issued before the first value is
+// used, so a segment costs one memory latency rather than one per node.  The
+// Q1 stencil is written per plane offset: the elements of the slab below and
+// above the node, summed over the 2x2 element columns that hold both the node
+// and each of the 3x3 in-plane neighbours.
+template <int MODE, int SEG>
+__device__ __forceinline__ void march(const PGeom &g, const double *sC_, const double (*sM_)[3], const TaskArrays &A,
+                                      int i, int j, int k0, double (&acc)[2]) {
+    // coefficients re-read from LDS at each use (a broadcast read) rather than
+    // held in 26 register pairs for the whole kernel
+    const volatile double *sC = sC_;
+    const volatile double(*sM)[3] = sM_;
     const int sx = g.sx, sxy = g.sxy;
     const int nx = g.nx, ny = g.ny, nz = g.nz, nxy = g.nxy;
     const int ox[3] = {i > 0 ? -1 : 0, 0, i < nx ? 1 : 0};
@@ -107,32 +111,41 @@ __device__ __forceinline__ void march(const PGeom &g, const double *sC, const do
     const bool ex[2] = {i > 0, i < nx}, ey[2] = {j > 0, j < ny};
     const int bx[2] = {max(i - 1, 0), min(i, nx - 1)};
     const int by[2] = {nx * max(j - 1, 0), nx * min(j, ny - 1)};
+    const gdouble *__restrict__ V = (MODE == MARCH_INIT) ? A.X : A.PN;
 
-    auto value = [&](int id) -> double {
-        if (MODE == MARCH_INIT) return A.X[id];
-        if (MODE == MARCH_APPLY) return A.PN[id];
-        const double z = A.DI[id] * A.R[id];
-        return it == 0 ? z : fma(beta, A.PO[id], z);
-    };
-    auto plane = [&](int k, double(&v)[9]) {
-        const int b = base + sxy * k;
+    // planes k0-1 .. k0+SEG (clamped into the grid; out-of-grid neighbours get
+    // zero weight) and slabs k0-1 .. k0+SEG-1 (zero outside 0..nz-1)
+    double P[SEG + 2][9], Bt[SEG + 1][4];
+#pragma unroll
+    for (int pl = 0; pl < SEG + 2; ++pl) {
+        const int b = base + sxy * min(max(k0 - 1 + pl, 0), nz);
 #pragma unroll
         for (int cy = 0; cy < 3; ++cy)
 #pragma unroll
-            for (int cx = 0; cx < 3; ++cx) v[3 * cy + cx] = value(b + ox[cx] + oy[cy]);
-    };
-    // beta of the 2x2 elements between planes kz and kz+1 (0 outside the grid)
-    auto slab = [&](int kz, double(&b)[4]) {
+            for (int cx = 0; cx < 3; ++cx) P[pl][3 * cy + cx] = ldg(V, b + ox[cx] + oy[cy]);
+    }
+#pragma unroll
+    for (int sl = 0; sl < SEG + 1; ++sl) {
+        const int kz = k0 - 1 + sl;
         const bool okz = kz >= 0 && kz < nz;
         const int bz = nxy * min(max(kz, 0), nz - 1);
 #pragma unroll
         for (int dy = 0; dy < 2; ++dy)
 #pragma unroll
             for (int dx = 0; dx < 2; ++dx) {
-                const double v = A.BE[bx[dx] + by[dy] + bz];
-                b[2 * dy + dx] = (okz && ex[dx] && ey[dy]) ? v : 0.0;
+                const double v = ldg(A.BE, bx[dx] + by[dy] + bz);
+                Bt[sl][2 * dy + dx] = (okz && ex[dx] && ey[dy]) ? v : 0.0;
             }
-    };
+    }
+    double E0[SEG], E1[SEG];                    // init: F and 1/D of the segment's nodes
+    if (MODE == MARCH_INIT) {
+#pragma unroll
+        for (int kk = 0; kk < SEG; ++kk) {
+            const int id = base + sxy * min(k0 + kk, nz);
+            E0[kk] = ldg(A.F, id);
+            E1[kk] = ldg(A.DI, id);
+        }
+    }
     // sum of a slab's elements that hold both the node and in-plane neighbour (cx, cy)
     auto wsum2 = [](const double(&b)[4], int cx, int cy) -> double {
         double w = 0.0;
@@ -171,20 +184,21 @@ __device__ __forceinline__ void march(const PGeom &g, const double *sC, const do
         return s;
     };
 
-    double vm[9], v0[9], vp[9], sm[4], sp[4];
-    plane(max(k0 - 1, 0), vm);
-    plane(k0, v0);
-    slab(k0 - 1, sm);
-    for (int k = k0; k < k1; ++k) {
-        plane(min(k + 1, nz), vp);
-        slab(k, sp);
+#pragma unroll
+    for (int kk = 0; kk < SEG; ++kk) {
+        const int k = k0 + kk;
+        if (k > nz) break;
+        const double(&vm)[9] = P[kk];
+        const double(&v0)[9] = P[kk + 1];
+        const double(&vp)[9] = P[kk + 2];
         const int id = base + sxy * k;
         double q = 0.0;
-        if (!pdir(g, i, j, k)) {
+        const bool dir = pdir(g, i, j, k);
+        if (!dir) {
 #pragma unroll
             for (int c = 0; c < 9; ++c) {
                 const int m = ((c % 3) != 1) | (((c / 3) != 1) << 1);
-                const double wm = wsum2(sm, c % 3, c / 3), wp = wsum2(sp, c % 3, c / 3);
+                const double wm = wsum2(Bt[kk], c % 3, c / 3), wp = wsum2(Bt[kk + 1], c % 3, c / 3);
                 q += sC[m | 4] * (wm * vm[c] + wp * vp[c]) + sC[m] * ((wm + wp) * v0[c]);
             }
             // x faces: in-face axes (y, z); y faces: (x, z); z faces: (x, y)
@@ -201,26 +215,14 @@ __device__ __forceinline__ void march(const PGeom &g, const double *sC, const do
             if (k == nz && (g.robin & 32u)) q += robin(5, i, nx, j, ny, vxy);
         }
         if (MODE == MARCH_INIT) {
-            const double rv = pdir(g, i, j, k) ? 0.0 : A.F[id] - q;
+            const double rv = dir ? 0.0 : E0[kk] - q;
             A.R[id] = rv;
-            acc[0] += rv * (A.DI[id] * rv);
+            acc[0] += rv * (E1[kk] * rv);
             acc[1] += rv * rv;
-        } else if (MODE == MARCH_APPLY) {
-            A.Q[id] = q;
-            acc[0] += v0[4] * q;
         } else {
-            if (it > 0) A.X[id] += alpha * A.PO[id];
-            A.PN[id] = v0[4];
             A.Q[id] = q;
             acc[0] += v0[4] * q;
         }
-#pragma unroll
-        for (int c = 0; c < 9; ++c) {
-            vm[c] = v0[c];
-            v0[c] = vp[c];
-        }
-#pragma unroll
-        for (int c = 0; c < 4; ++c) sm[c] = sp[c];
     }
 }
 
@@ -280,6 +282,7 @@ __device__ __forceinline__ void task_sum(const PersistentTask &t, int w, int nwg
 
 // The JCG solve of one task by workgroup w of its nwg workgroups.  LDS: red
 // (reductions), s_err (barrier failure), sC / sM (coefficients).
+template <int SEG>
 __device__ __forceinline__ void jcg_task(const PersistentTask &t, int w, int nwg, double (*red)[NTP / 64],
                                          int &s_err, double *sC, double (*sM)[3]) {
     // stencil and face-mass coefficients in LDS (uniform reads), the rest of
@@ -316,29 +319,32 @@ __device__ __forceinline__ void jcg_task(const PersistentTask &t, int w, int nwg
     // lanes take neighbouring x
     const int width = g.nx + 1;
     const int ncol = width * (g.ny + 1);
-    const int seglen = t.seglen;
-    const int nseg = (g.nz + seglen) / seglen;
+    const int nseg = (g.nz + SEG) / SEG;
     const int nunits = ncol * nseg;
     const int stride = nwg * NTP;
     const int sx = g.sx, sxy = g.sxy;
-#define FOR_UNITS(body)                                                                   \
+#define FOR_UNITS(...)                                                                    \
     for (int u = w * NTP + (int)threadIdx.x; u < nunits; u += stride) {                   \
         const int c = u % ncol, sg = u / ncol;                                            \
         const int i = c % width, j = c / width;                                           \
-        const int k0 = sg * seglen, k1 = min(k0 + seglen, g.nz + 1);                      \
-        body                                                                              \
+        const int k0 = sg * SEG;                                                          \
+        __VA_ARGS__                                                                       \
     }
 
+    // own-node loops over a segment: loads of all its nodes first
+#define FOR_SEG(kk) _Pragma("unroll") for (int kk = 0; kk < SEG; ++kk)
     unsigned gen = 0;                  // barriers passed by this workgroup
     if (t.zero_x) {                    // x = 0 on free nodes, g_D stays on Dirichlet nodes
         FOR_UNITS({
-            for (int k = k0; k < k1; ++k)
-                if (!pdir(g, i, j, k)) A.X[i + sx * j + sxy * k] = 0.0;
+            FOR_SEG(kk) {
+                const int k = k0 + kk;
+                if (k <= g.nz && !pdir(g, i, j, k)) A.X[i + sx * j + sxy * k] = 0.0;
+            }
         })
         task_barrier(t, nwg, ++gen, &s_err);
     }
     double acc[2] = {0.0, 0.0};
-    FOR_UNITS(march<MARCH_INIT>(g, sC, sM, A, i, j, k0, k1, 0, 0.0, 0.0, acc);)
+    FOR_UNITS(march<MARCH_INIT, SEG>(g, sC, sM, A, i, j, k0, acc);)
     task_sum<2>(t, w, nwg, gen, 1, acc, red, &s_err);
     double rho = acc[0], rr = acc[1], alpha = 0.0, beta = 0.0;
     int it = 0, done = 0;
@@ -351,35 +357,40 @@ __device__ __forceinline__ void jcg_task(const PersistentTask &t, int w, int nwg
     };
     done = stop(rr);
     while (!done && !s_err) {
-        // A: x, p, q = A p, p.q
+        // A: x, p (own nodes), then q = A p, p.q
         // (a select, not an index: indexing would put the task copy in scratch)
         A.PO = (gdouble *)((it & 1) ? t.p[1] : t.p[0]);
         A.PN = (gdouble *)((it & 1) ? t.p[0] : t.p[1]);
         double pq[2] = {0.0, 0.0};
-#if ECMG_PERSIST_FUSED
-        FOR_UNITS(march<MARCH_ITER>(g, sC, sM, A, i, j, k0, k1, it, alpha, beta, pq);)
-#else
         FOR_UNITS({
             gdouble *__restrict__ Xr = A.X;
             gdouble *__restrict__ Pn = A.PN;
             const gdouble *__restrict__ Po = A.PO;
             const gdouble *__restrict__ Rr = A.R;
             const gdouble *__restrict__ Dr = A.DI;
-            int id = i + sx * j + sxy * k0;
-            for (int k = k0; k < k1; ++k, id += sxy) {
-                const double z = Dr[id] * Rr[id];
+            const int id0 = i + sx * j + sxy * k0;
+            double z[SEG], po[SEG], xv[SEG];
+            FOR_SEG(kk) {
+                const int id = id0 + sxy * min(kk, g.nz - k0);
+                z[kk] = ldg(Dr, id) * ldg(Rr, id);
+                if (it > 0) {
+                    po[kk] = ldg(Po, id);
+                    xv[kk] = ldg(Xr, id);
+                }
+            }
+            FOR_SEG(kk) {
+                if (k0 + kk > g.nz) break;
+                const int id = id0 + sxy * kk;
                 if (it == 0) {
-                    Pn[id] = z;
+                    Pn[id] = z[kk];
                 } else {
-                    const double po = Po[id];
-                    Xr[id] += alpha * po;
-                    Pn[id] = fma(beta, po, z);
+                    Xr[id] = xv[kk] + alpha * po[kk];
+                    Pn[id] = fma(beta, po[kk], z[kk]);
                 }
             }
         })
         task_barrier(t, nwg, ++gen, &s_err);
-        FOR_UNITS(march<MARCH_APPLY>(g, sC, sM, A, i, j, k0, k1, it, alpha, beta, pq);)
-#endif
+        FOR_UNITS(march<MARCH_APPLY, SEG>(g, sC, sM, A, i, j, k0, pq);)
         double pqs[1] = {pq[0]};
         task_sum<1>(t, w, nwg, gen, 0, pqs, red, &s_err);
         if (!(pqs[0] > 0.0) || !isfinite(pqs[0])) { done = DONE_BREAKDOWN; break; }
@@ -390,12 +401,20 @@ __device__ __forceinline__ void jcg_task(const PersistentTask &t, int w, int nwg
             gdouble *__restrict__ Rr = A.R;
             const gdouble *__restrict__ Qr = A.Q;
             const gdouble *__restrict__ Dr = A.DI;
-            int id = i + sx * j + sxy * k0;
-            for (int k = k0; k < k1; ++k, id += sxy) {
-                const double rv = Rr[id] - alpha * Qr[id];
-                Rr[id] = rv;
-                s2[0] += rv * (Dr[id] * rv);
-                s2[1] += rv * rv;
+            const int id0 = i + sx * j + sxy * k0;
+            double rv[SEG], qv[SEG], dv[SEG];
+            FOR_SEG(kk) {
+                const int id = id0 + sxy * min(kk, g.nz - k0);
+                rv[kk] = ldg(Rr, id);
+                qv[kk] = ldg(Qr, id);
+                dv[kk] = ldg(Dr, id);
+            }
+            FOR_SEG(kk) {
+                if (k0 + kk > g.nz) break;
+                const double r1 = rv[kk] - alpha * qv[kk];
+                Rr[id0 + sxy * kk] = r1;
+                s2[0] += r1 * (dv[kk] * r1);
+                s2[1] += r1 * r1;
             }
         })
         task_sum<2>(t, w, nwg, gen, 1, s2, red, &s_err);
@@ -406,12 +425,23 @@ __device__ __forceinline__ void jcg_task(const PersistentTask &t, int w, int nwg
         done = stop(rr);
     }
     if (it > 0 && done != DONE_BREAKDOWN) {   // x += alpha p of the last completed iteration
-        const gdouble *PL = (const gdouble *)((it & 1) ? t.p[1] : t.p[0]);
+        const gdouble *__restrict__ PL = (const gdouble *)((it & 1) ? t.p[1] : t.p[0]);
         FOR_UNITS({
-            int id = i + sx * j + sxy * k0;
-            for (int k = k0; k < k1; ++k, id += sxy) A.X[id] += alpha * PL[id];
+            gdouble *__restrict__ Xr = A.X;
+            const int id0 = i + sx * j + sxy * k0;
+            double pv[SEG], xv[SEG];
+            FOR_SEG(kk) {
+                const int id = id0 + sxy * min(kk, g.nz - k0);
+                pv[kk] = ldg(PL, id);
+                xv[kk] = ldg(Xr, id);
+            }
+            FOR_SEG(kk) {
+                if (k0 + kk > g.nz) break;
+                Xr[id0 + sxy * kk] = xv[kk] + alpha * pv[kk];
+            }
         })
     }
+#undef FOR_SEG
 #undef FOR_UNITS
     if (w == 0 && threadIdx.x == 0) {
         JcgScalars *sc = t.sc;
@@ -424,6 +454,14 @@ __device__ __forceinline__ void jcg_task(const PersistentTask &t, int w, int nwg
         sc->tol = t.tol;
     }
     __syncthreads();                   // LDS is reused by the next task of this workgroup
+}
+
+// The task's segment length selects the instantiation (1, 2 or 4 nodes).
+__device__ __forceinline__ void run_task(const PersistentTask &t, int w, int nwg, double (*red)[NTP / 64], int &s_err,
+                                         double *sC, double (*sM)[3]) {
+    if (t.seglen >= 4) jcg_task<4>(t, w, nwg, red, s_err, sC, sM);
+    else if (t.seglen == 2) jcg_task<2>(t, w, nwg, red, s_err, sC, sM);
+    else jcg_task<1>(t, w, nwg, red, s_err, sC, sM);
 }
 
 // One or more tasks, each on its own contiguous range of workgroups
@@ -440,7 +478,7 @@ __global__ void __launch_bounds__(NTP) k_jcg_persistent(const PersistentTask *__
         if (tasks[mid].wg0 <= bid) lo = mid; else hi = mid - 1;
     }
     const PersistentTask &t = tasks[lo];
-    jcg_task(t, bid - t.wg0, t.nwg, red, s_err, sC, sM);
+    run_task(t, bid - t.wg0, t.nwg, red, s_err, sC, sM);
 }
 
 // Many tasks taken from a queue.  Task i owns the work items [wg0, wg0 + nwg)
@@ -470,7 +508,7 @@ __global__ void __launch_bounds__(NTP) k_jcg_queue(const PersistentTask *__restr
             if (tasks[mid].wg0 <= item) lo = mid; else hi = mid - 1;
         }
         const PersistentTask &t = tasks[lo];
-        jcg_task(t, item - t.wg0, t.nwg, red, s_err, sC, sM);
+        run_task(t, item - t.wg0, t.nwg, red, s_err, sC, sM);
     }
 }
 
