@@ -1121,7 +1121,7 @@ int ecmg_solve_batch(ecmg_ctx *const *ctxs, int32_t n, double rel_tol, ecmg_leve
                 e.x = L.x;
                 e.W = L.W;
                 e.variant = c->opt.interp;
-                exp_task_blocks(e);
+                exp_task_blocks(e, 0);
                 e.b0[0] = nb0;
                 e.b0[1] = nb1;
                 nb0 += e.nb[0];
@@ -1225,7 +1225,7 @@ int ecmg_extrapolate_batch(ecmg_ctx *const *ctxs, int32_t n) {
         e.U1 = L.x;
         e.U0 = c->lv[c->nlev - 2].x;
         e.x = L.Ut;
-        exp_task_blocks(e);
+        exp_task_blocks(e, 1);
         e.b0[1] = nb1;
         nb1 += e.nb[1];
     }
@@ -1506,7 +1506,7 @@ static int server_tick(ecmg_server *S) {
                 e.x = L.x;
                 e.W = L.W;
                 e.variant = c->opt.interp;
-                exp_task_blocks(e);
+                exp_task_blocks(e, 0);
                 e.b0[0] = nb0;
                 e.b0[1] = nb1;
                 nb0 += e.nb[0];

@@ -194,7 +194,9 @@ struct ExpTask {
     int gx[2], gy[2];
     int64_t nb[2], b0[2];
 };
-void exp_task_blocks(ExpTask &t);
+// kind 0: EXP_finite (phase 1 one thread per coarse element of a fine row),
+// 1: EXP_true (63 node pairs per 64-lane row block)
+void exp_task_blocks(ExpTask &t, int kind);
 void launch_exp_finite_batch(const ExpTask *d_tasks, int n, int64_t nb0, int64_t nb1, hipStream_t s);
 void launch_exp_true_batch(const ExpTask *d_tasks, int n, int64_t nb1, hipStream_t s);
 void launch_zero_pad(const Geom &g, double *a, double *b, double *c, double *d, hipStream_t s);

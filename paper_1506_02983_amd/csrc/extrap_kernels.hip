@@ -143,38 +143,73 @@ __global__ void __launch_bounds__(256) k_exp_finite_nodal(const Geom g1, const d
 }
 
 // Phase 2: every fine node of level l is the tri-quadratic Lagrange
-// interpolant of the 27 nodal values of its owner coarse element.  One 64-lane
-// row per wave, so the y and z offsets (and which 1-D weights vanish) are
-// uniform across the wave.
+// interpolant of the 27 nodal values of its owner coarse element.  A thread
+// takes one coarse element I along x and one fine row (j, k): the 4 fine
+// nodes 4I..4I+3 (and 4I+4 at the end of the row).  For each coarse row with a
+// nonzero y / z weight (1, 3 or 9 of them, uniform over the wave) it loads the
+// element's 3 nodal values with one 16-byte and one 8-byte load and folds
+// them into 3 x-column sums; the fine nodes are then fixed combinations of the
+// column sums, written as 16-byte stores.  Few wide loads per node matter:
+// the inter-level kernels are bound by address processing, not bytes.
 __device__ __forceinline__ void exp_finite_interp_block(const Geom &gf, const double *__restrict__ V,
                                                         double *__restrict__ x, double *__restrict__ W, int bx,
                                                         int by, int bz) {
-    const int i = bx * 64 + threadIdx.x;
-    const int j = by * 4 + threadIdx.y, k = bz;
-    if (i > gf.nx || j > gf.ny || k > gf.nz) return;
     const int NX = gf.nx / 4, NY = gf.ny / 4, NZ = gf.nz / 4;
-    const int I = min(i / 4, NX - 1), J = min(j / 4, NY - 1), K = min(k / 4, NZ - 1);
-    const int a = i - 4 * I, b = j - 4 * J, c = k - 4 * K;
+    const int I = bx * 64 + threadIdx.x;
+    const int j = by * 4 + threadIdx.y, k = bz;
+    if (I >= NX || j > gf.ny || k > gf.nz) return;
+    const int J = min(j / 4, NY - 1), K = min(k / 4, NZ - 1);
+    const int b = j - 4 * J, c = k - 4 * K;
     const int64_t s1 = row_pitch(gf.nx / 2 + 1), s1y = s1 * (gf.ny / 2 + 1);
-    double Lx[3], Ly[3], Lz[3];
-    lagrange3(a, Lx);
+    double Ly[3], Lz[3];
     lagrange3(b, Ly);
     lagrange3(c, Lz);
     const double *Vb = V + (2 * I) + s1 * (2 * J) + s1y * (2 * K);
-    double w = 0.0;
+    double w0 = 0.0, w1 = 0.0, w2 = 0.0;                  // weighted sums of the 3 x-columns
     for (int cc = 0; cc < 3; ++cc) {
         if (Lz[cc] == 0.0) continue;                      // uniform over the wave
-        double sy = 0.0;
+        double t0 = 0.0, t1 = 0.0, t2 = 0.0;
         for (int bb = 0; bb < 3; ++bb) {
             if (Ly[bb] == 0.0) continue;                  // uniform over the wave
             const double *Vr = Vb + s1 * bb + s1y * cc;
-            sy += Ly[bb] * (Lx[0] * Vr[0] + Lx[1] * Vr[1] + Lx[2] * Vr[2]);
+            const double2 v01 = *(const double2 *)Vr;     // 2I is even: 16-byte aligned
+            const double v2 = Vr[2];
+            t0 += Ly[bb] * v01.x;
+            t1 += Ly[bb] * v01.y;
+            t2 += Ly[bb] * v2;
         }
-        w += Lz[cc] * sy;
+        w0 += Lz[cc] * t0;
+        w1 += Lz[cc] * t1;
+        w2 += Lz[cc] * t2;
     }
-    const int64_t id = i + (int64_t)gf.sx * j + (int64_t)gf.sx * gf.sy * k;
-    if (W) W[id] = w;
-    if (!is_dir(gf, i, j, k)) x[id] = w;
+    // x weights at a = 0..4 (natural coordinate a/2 - 1): (1,0,0), (3/8,3/4,-1/8),
+    // (0,1,0), (-1/8,3/4,3/8), (0,0,1)
+    double out[5];
+    out[0] = w0;
+    out[1] = 0.375 * w0 + 0.75 * w1 - 0.125 * w2;
+    out[2] = w1;
+    out[3] = -0.125 * w0 + 0.75 * w1 + 0.375 * w2;
+    out[4] = w2;
+    const int i0 = 4 * I;
+    const int64_t id = i0 + (int64_t)gf.sx * j + (int64_t)gf.sx * gf.sy * k;
+    const bool dj = (j == 0 && gf.ft[2] == ECMG_DIRICHLET) || (j == gf.ny && gf.ft[3] == ECMG_DIRICHLET) ||
+                    (k == 0 && gf.ft[4] == ECMG_DIRICHLET) || (k == gf.nz && gf.ft[5] == ECMG_DIRICHLET);
+    const int na = (I == NX - 1) ? 5 : 4;
+    if (W) {
+        *(double2 *)(W + id) = make_double2(out[0], out[1]);   // 4I: 32-byte aligned
+        *(double2 *)(W + id + 2) = make_double2(out[2], out[3]);
+        if (na == 5) W[id + 4] = out[4];
+    }
+    if (dj) return;                                       // the whole row is Dirichlet
+    const bool d0 = (i0 == 0 && gf.ft[0] == ECMG_DIRICHLET);
+    const bool d4 = (i0 + 4 == gf.nx && gf.ft[1] == ECMG_DIRICHLET);
+    if (!d0) {
+        *(double2 *)(x + id) = make_double2(out[0], out[1]);
+    } else {
+        x[id + 1] = out[1];
+    }
+    *(double2 *)(x + id + 2) = make_double2(out[2], out[3]);
+    if (na == 5 && !d4) x[id + 4] = out[4];
 }
 
 __global__ void __launch_bounds__(256) k_exp_finite_interp(const Geom gf, const double *__restrict__ V,
@@ -185,37 +220,59 @@ __global__ void __launch_bounds__(256) k_exp_finite_interp(const Geom gf, const 
 // U~ = U1 + (1/3) T[U1 - U0]: eq. t1 at coarse nodes ((4 U1 - U0)/3), eq.
 // chenlin at edge midpoints (U1 + (d_a + d_b)/6), and the mean of chenlin along
 // the 2 face diagonals (U1 + sum(4 d)/12) or the 4 space diagonals (U1 +
-// sum(8 d)/24) at face and body centres.  One 64-lane row per wave: the y and
-// z parities, hence the number of coarse differences, are wave-uniform.
+// sum(8 d)/24) at face and body centres.  A thread takes a pair of fine nodes
+// (2p, 2p+1) of one row; the coarse differences d = U1 - U0 at the even x
+// positions of the 1, 2 or 4 contributing rows (row parities are uniform over
+// the wave) are loaded once per lane, and the odd node takes the difference at
+// 2p+2 from the next lane.  A wave covers 63 pairs: its last lane only supplies
+// that neighbour value.
 __device__ __forceinline__ void exp_true_block(const Geom &gf, const double *__restrict__ U1,
                                                const double *__restrict__ U0, double *__restrict__ Ut, int bx,
                                                int by, int bz) {
-    const int i = bx * 64 + threadIdx.x;
+    const int lane = threadIdx.x;                         // one wave per row (blockDim.x == 64)
+    const int npair = gf.nx / 2 + 1;                      // pair p: nodes 2p and 2p + 1 <= nx
+    const int p = bx * 63 + lane;
     const int j = by * 4 + threadIdx.y, k = bz;
-    if (i > gf.nx || j > gf.ny || k > gf.nz) return;
+    if (j > gf.ny || k > gf.nz) return;                   // whole rows only: the shuffles below stay wave-wide
+    const int pc = min(p, npair - 1);                     // clamped for the loads
+    const int i0 = 2 * pc;
     const int64_t sx = gf.sx, sxy = (int64_t)gf.sx * gf.sy;
     const int64_t cx = row_pitch(gf.nx / 2 + 1), cxy = cx * (gf.ny / 2 + 1);
-    const int64_t id = i + sx * j + sxy * k;
-    const double u1 = U1[id];
-    const int oi = i & 1, oj = j & 1, ok = k & 1;
-    if (!(oi | oj | ok)) {
-        Ut[id] = (4.0 * u1 - U0[(i >> 1) + cx * (j >> 1) + cxy * (k >> 1)]) / 3.0;
-        return;
+    const int64_t id = i0 + sx * j + sxy * k;
+    const bool has_odd = i0 + 1 <= gf.nx;
+    double u_e, u_o = 0.0;
+    if (has_odd) {
+        const double2 v = *(const double2 *)(U1 + id);    // i0 even, rows 16-byte aligned
+        u_e = v.x;
+        u_o = v.y;
+    } else {
+        u_e = U1[id];
     }
-    double s = 0.0;
+    const int oj = j & 1, ok = k & 1;
+    double se = 0.0, so = 0.0, c_own = 0.0;
     for (int dk = 0; dk <= ok; ++dk) {
         const int kk = k - ok + 2 * dk;
         for (int dj = 0; dj <= oj; ++dj) {
             const int jj = j - oj + 2 * dj;
-            for (int di = 0; di <= oi; ++di) {
-                const int ii = i - oi + 2 * di;
-                s += U1[ii + sx * jj + sxy * kk] - U0[(ii >> 1) + cx * (jj >> 1) + cxy * (kk >> 1)];
-            }
+            const double c0 = U0[pc + cx * (jj >> 1) + cxy * (kk >> 1)];
+            const double d0 = U1[i0 + sx * jj + sxy * kk] - c0;
+            const double d2 = __shfl_down(d0, 1, 64);     // the difference at 2p + 2
+            c_own = c0;
+            se += d0;
+            so += d0 + d2;
         }
     }
-    const int nodd = oi + oj + ok;
-    const double denom = nodd == 1 ? 6.0 : (nodd == 2 ? 12.0 : 24.0);
-    Ut[id] = u1 + s / denom;
+    if (lane == 63 || p >= npair) return;
+    const int ne = oj + ok;
+    double ve;
+    if (ne == 0) ve = (4.0 * u_e - c_own) / 3.0;
+    else ve = u_e + se / (ne == 1 ? 6.0 : 12.0);
+    if (has_odd) {
+        const double vo = u_o + so / (ne == 0 ? 6.0 : (ne == 1 ? 12.0 : 24.0));
+        *(double2 *)(Ut + id) = make_double2(ve, vo);
+    } else {
+        Ut[id] = ve;
+    }
 }
 
 __global__ void __launch_bounds__(256) k_exp_true(const Geom gf, const double *__restrict__ U1,
@@ -262,9 +319,12 @@ __global__ void __launch_bounds__(256) k_exp_true_batch(const ExpTask *__restric
 
 // Block counts of a box: phase 0 over the level l-1 grid g1, phase 1 over the
 // fine grid gf (64 x 4 nodes per block).
-void exp_task_blocks(ExpTask &t) {
+int exp_interp_gx(const Geom &gf) { return (gf.nx / 4 + 63) / 64; }
+int exp_true_gx(const Geom &gf) { return (gf.nx / 2 + 1 + 62) / 63; }
+
+void exp_task_blocks(ExpTask &t, int kind) {
     t.gx[0] = (t.g1.nx + 1 + 63) / 64;
-    t.gx[1] = (t.gf.nx + 1 + 63) / 64;
+    t.gx[1] = kind == 0 ? exp_interp_gx(t.gf) : exp_true_gx(t.gf);
     t.gy[0] = (t.g1.ny + 1 + 3) / 4;
     t.gy[1] = (t.gf.ny + 1 + 3) / 4;
     t.nb[0] = (int64_t)t.gx[0] * t.gy[0] * (t.g1.nz + 1);
@@ -285,7 +345,7 @@ void launch_exp_finite(const Geom &gf, const Geom &g1, const double *U1, const d
     const dim3 blk(64, 4);
     const dim3 g1grid((g1.nx + 1 + 63) / 64, (g1.ny + 1 + 3) / 4, g1.nz + 1);
     hipLaunchKernelGGL(k_exp_finite_nodal, g1grid, blk, 0, s, g1, U1, U0, V, variant);
-    const dim3 gfgrid((gf.nx + 1 + 63) / 64, (gf.ny + 1 + 3) / 4, gf.nz + 1);
+    const dim3 gfgrid(exp_interp_gx(gf), (gf.ny + 1 + 3) / 4, gf.nz + 1);
     hipLaunchKernelGGL(k_exp_finite_interp, gfgrid, blk, 0, s, gf, V, x, W);
 }
 
@@ -328,7 +388,7 @@ void launch_zero_pad_f32(const Geom &g, float *a, float *b, float *c, hipStream_
 }
 
 void launch_exp_true(const Geom &gf, const double *U1, const double *U0, double *Ut, hipStream_t s) {
-    const dim3 grid((gf.nx + 1 + 63) / 64, (gf.ny + 1 + 3) / 4, gf.nz + 1);
+    const dim3 grid(exp_true_gx(gf), (gf.ny + 1 + 3) / 4, gf.nz + 1);
     hipLaunchKernelGGL(k_exp_true, grid, dim3(64, 4), 0, s, gf, U1, U0, Ut);
 }
 
