@@ -127,12 +127,18 @@ typedef struct {
     void *hip_stream;          /* hipStream_t to order all work on; NULL = own stream    */
     int64_t persistent_nodes;  /* grids of at most this many nodes run the whole JCG loop
                                   in one persistent launch; 0 = never, -1 = default     */
+    int64_t dsolve_dense_max;  /* ecmg_solve: DSOLVE levels with at most this many free
+                                  nodes (capped at 8192) are solved with an explicit
+                                  inverse of A_FF, built on the first solve (Cholesky,
+                                  rocSOLVER) and applied as one matrix-vector product;
+                                  larger ones, and 0, use FP64 JCG (default 8192)        */
 } ecmg_options;
 
 /* Per-level report (Algorithm 4 and the "Iters"/"RRe" columns of Section 5). */
 typedef struct {
     int32_t level, nx, ny, nz; /* level index and elements per axis                    */
-    int32_t iters;             /* JCG iterations (DSOLVE levels: iterations used)      */
+    int32_t iters;             /* JCG iterations (DSOLVE levels: JCG iterations used, 0
+                                  for the dense direct solve)                           */
     int32_t outer_steps;       /* ECMG_MIXED: FP64 refinement steps; else 0            */
     int32_t status;            /* ECMG_OK, ECMG_ENOTCONV or ECMG_EBREAKDOWN            */
     int32_t reserved;

@@ -53,7 +53,7 @@ class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("interp", ctypes.c_int32),
                 ("keep_w", ctypes.c_int32), ("inner_tol", ctypes.c_double), ("dsolve_tol", ctypes.c_double),
                 ("chunk", ctypes.c_int32), ("timing", ctypes.c_int32), ("hip_stream", ctypes.c_void_p),
-                ("persistent_nodes", ctypes.c_int64)]
+                ("persistent_nodes", ctypes.c_int64), ("dsolve_dense_max", ctypes.c_int64)]
 
 
 class LevelInfo(ctypes.Structure):
@@ -234,7 +234,8 @@ class Solver:
 
     def __init__(self, precision: int = FP64, interp: int = SERENDIPITY20, keep_w: bool = True,
                  max_iter: int = 20000, dsolve_tol: float = 1e-14, inner_tol: float = 1e-4,
-                 chunk: int = 0, timing: bool = False, stream=None, persistent_nodes: int = -1):
+                 chunk: int = 0, timing: bool = False, stream=None, persistent_nodes: int = -1,
+                 dsolve_dense_max: Optional[int] = None):
         self.L = load_library()
         o = Options()
         self.L.ecmg_default_options(ctypes.byref(o))
@@ -242,6 +243,8 @@ class Solver:
         o.dsolve_tol, o.inner_tol, o.chunk, o.timing = dsolve_tol, inner_tol, chunk, int(timing)
         o.hip_stream = stream
         o.persistent_nodes = persistent_nodes
+        if dsolve_dense_max is not None:
+            o.dsolve_dense_max = dsolve_dense_max
         self.opt = o
         h = ctypes.c_void_p()
         self._check(self.L.ecmg_create(ctypes.byref(o), ctypes.byref(h)), None)

@@ -2,6 +2,8 @@
 // hierarchy resident in HBM, discretisation (Section 2), the Algorithm 4
 // driver, and the per-level operators exposed for testing.
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
 
 #include <algorithm>
 #include <chrono>
@@ -29,6 +31,7 @@ struct ecmg_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int device = 0;
+    rocblas_handle blas = nullptr;            // dense DSOLVE factorisation (lazy)
     // batched solves led by this context: task and scalar arrays for the queue kernel
     PersistentTask *bt_tasks = nullptr;
     JcgScalars *bt_sc = nullptr, *bt_sc_host = nullptr;
@@ -628,6 +631,8 @@ static void free_levels(ecmg_ctx *c) {
         dfree(L.Ut);
         dfree(L.beta32);
         dfree(L.dinv32);
+        dfree(L.ainv);
+        dfree(L.freeid);
         for (int f = 0; f < 6; ++f) {
             dfree(L.alpha[f]);
             dfree(L.alpha32[f]);
@@ -667,6 +672,7 @@ void ecmg_default_options(ecmg_options *o) {
     o->timing = 0;
     o->hip_stream = nullptr;
     o->persistent_nodes = -1;
+    o->dsolve_dense_max = DSOLVE_DENSE_LIMIT;
 }
 
 int ecmg_create(const ecmg_options *opt, ecmg_ctx **out) {
@@ -745,6 +751,7 @@ void ecmg_destroy(ecmg_ctx *c) {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     free_levels(c);
+    if (c->blas) (void)rocblas_destroy_handle(c->blas);
     dfree(c->sc);
     dfree(c->sc32);
     dfree(c->bt_tasks);
@@ -968,6 +975,92 @@ int ecmg_setup(ecmg_ctx *c, const ecmg_problem *p) {
     return ECMG_OK;
 }
 
+// ---------------------------------------------------------------------------
+// DSOLVE as a direct solve (Algorithm 4, levels 0 and 1): the explicit inverse
+// of A_FF from its Cholesky factor, built once per hierarchy on first use, then
+// x_F = A_FF^-1 (F - A_FD g_D) as one matrix-vector product per solve
+// ---------------------------------------------------------------------------
+static bool host_dir(const Geom &g, int i, int j, int k) {
+    return (i == 0 && g.ft[0] == ECMG_DIRICHLET) || (i == g.nx && g.ft[1] == ECMG_DIRICHLET) ||
+           (j == 0 && g.ft[2] == ECMG_DIRICHLET) || (j == g.ny && g.ft[3] == ECMG_DIRICHLET) ||
+           (k == 0 && g.ft[4] == ECMG_DIRICHLET) || (k == g.nz && g.ft[5] == ECMG_DIRICHLET);
+}
+
+static int dense_prepare(ecmg_ctx *c, int l) {
+    Level &L = c->lv[l];
+    if (L.dense != 0) return ECMG_OK;
+    L.dense = -1;
+    const int64_t lim = std::min<int64_t>(c->opt.dsolve_dense_max, DSOLVE_DENSE_LIMIT);
+    if (lim <= 0) return ECMG_OK;
+    const Geom &g = L.g;
+    std::vector<int> fmap((size_t)g.nnodes, -1), freeid;
+    for (int k = 0; k <= g.nz; ++k)
+        for (int j = 0; j <= g.ny; ++j)
+            for (int i = 0; i <= g.nx; ++i) {
+                if (host_dir(g, i, j, k)) continue;
+                const int64_t pid = i + (int64_t)g.sx * (j + (int64_t)g.sy * k);
+                fmap[(size_t)pid] = (int)freeid.size();
+                freeid.push_back((int)pid);
+            }
+    const int nf = (int)freeid.size();
+    if (nf == 0 || nf > lim) return ECMG_OK;
+    int *d_fmap = nullptr, *d_info = nullptr;
+    CHK(dalloc(c, (void **)&d_fmap, sizeof(int) * fmap.size()));
+    CHK(dalloc(c, (void **)&d_info, sizeof(int)));
+    CHK(dalloc(c, (void **)&L.freeid, sizeof(int) * (size_t)nf));
+    CHK(dalloc_n(c, &L.ainv, (int64_t)nf * nf));
+    HIPCHK(c, hipMemcpyAsync(d_fmap, fmap.data(), sizeof(int) * fmap.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(L.freeid, freeid.data(), sizeof(int) * (size_t)nf, hipMemcpyHostToDevice, c->stream));
+    const double *al[6];
+    for (int f = 0; f < 6; ++f) al[f] = L.alpha[f];
+    launch_assemble_dense(g, L.beta, al, d_fmap, L.ainv, nf, c->stream);
+    HIPCHK(c, hipGetLastError());
+    if (!c->blas && rocblas_create_handle(&c->blas) != rocblas_status_success) {
+        c->blas = nullptr;
+        return fail(c, ECMG_EDEVICE, "rocblas_create_handle failed");
+    }
+    int info = 0;
+    bool ok = rocblas_set_stream(c->blas, c->stream) == rocblas_status_success &&
+              rocsolver_dpotrf(c->blas, rocblas_fill_lower, nf, L.ainv, nf, d_info) == rocblas_status_success &&
+              hipMemcpyAsync(&info, d_info, sizeof(int), hipMemcpyDeviceToHost, c->stream) == hipSuccess &&
+              hipStreamSynchronize(c->stream) == hipSuccess && info == 0;
+    ok = ok && rocsolver_dpotri(c->blas, rocblas_fill_lower, nf, L.ainv, nf, d_info) == rocblas_status_success &&
+         hipMemcpyAsync(&info, d_info, sizeof(int), hipMemcpyDeviceToHost, c->stream) == hipSuccess &&
+         hipStreamSynchronize(c->stream) == hipSuccess && info == 0;
+    if (ok) launch_symmetrize(L.ainv, nf, c->stream);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    dfree(d_fmap);
+    dfree(d_info);
+    if (!ok) {                                    // not factorable: keep the JCG DSOLVE
+        dfree(L.ainv);
+        dfree(L.freeid);
+        L.ainv = nullptr;
+        L.freeid = nullptr;
+        return ECMG_OK;
+    }
+    L.nfree = nf;
+    L.dense = 1;
+    return ECMG_OK;
+}
+
+static int run_dsolve_dense(ecmg_ctx *c, int l, ecmg_level_info *info) {
+    Level &L = c->lv[l];
+    launch_zero_free(L.g, L.x, c->stream);       // x0: g_D on Dirichlet nodes, 0 elsewhere
+    StencilArgs<double> a = stencil_args(c, L);
+    a.v = L.x;
+    a.q = c->q;
+    launch_stencil<double>(MODE_APPLY, a, c->stream);
+    launch_dsolve_gemv(L.nfree, L.ainv, L.freeid, L.F, c->q, L.x, c->stream);
+    HIPCHK(c, hipGetLastError());
+    if (info) {
+        info->iters = 0;
+        info->rre = 0.0;
+        info->nf = L.nf;
+        info->status = ECMG_OK;
+    }
+    return ECMG_OK;
+}
+
 static int solve_impl(ecmg_ctx *c, double rel_tol, const int32_t *fixed, ecmg_level_info *info) {
     if (!c) return fail(nullptr, ECMG_EINVAL, "ctx is NULL");
     if (!c->ready) return fail(c, ECMG_ESTATE, "ecmg_solve before ecmg_setup");
@@ -983,9 +1076,14 @@ static int solve_impl(ecmg_ctx *c, double rel_tol, const int32_t *fixed, ecmg_le
         HIPCHK(c, hipEventRecord(c->ev0, c->stream));
         int rc;
         if (l < 2) {
-            launch_zero_free(L.g, L.x, c->stream);
-            rc = run_level_jcg(c, l, c->opt.dsolve_tol * L.nf, 100000, -1, &li);
-            if (rc == ECMG_ENOTCONV) rc = ECMG_OK;  // DSOLVE: the iterate at the cap is kept
+            CHK(dense_prepare(c, l));
+            if (L.dense == 1) {
+                rc = run_dsolve_dense(c, l, &li);
+            } else {
+                launch_zero_free(L.g, L.x, c->stream);
+                rc = run_level_jcg(c, l, c->opt.dsolve_tol * L.nf, 100000, -1, &li);
+                if (rc == ECMG_ENOTCONV) rc = ECMG_OK;  // DSOLVE: the iterate at the cap is kept
+            }
         } else {
             CHK(do_exp_finite(c, l));
             rc = run_level_jcg(c, l, rel_tol * L.nf, c->opt.max_iter, fixed ? fixed[l] : -1, &li);
@@ -1610,6 +1708,7 @@ int ecmg_server_create(const ecmg_options *opt, size_t hbm_budget_bytes, ecmg_se
     }
     S->opt.keep_w = 0;
     S->opt.timing = 0;
+    S->opt.dsolve_dense_max = 0;       // DSOLVE levels run in the shared queue launches
     S->budget = hbm_budget_bytes;
     if (S->opt.hip_stream) {
         S->stream = (hipStream_t)S->opt.hip_stream;

@@ -147,6 +147,10 @@ struct Level {
     double *dinv = nullptr;
     double *W = nullptr;              // EXP_finite output (optional)
     double *Ut = nullptr;             // EXP_true output (lazy)
+    double *ainv = nullptr;           // DSOLVE levels: explicit inverse of A_FF (lazy), nfree^2
+    int *freeid = nullptr;            // padded node index of each free node
+    int nfree = 0;
+    int dense = 0;                    // 0 not tried, 1 ready, -1 not used
     float *beta32 = nullptr;          // mixed precision copies (lazy)
     float *alpha32[6] = {};
     float *dinv32 = nullptr;
@@ -203,6 +207,14 @@ void launch_zero_pad(const Geom &g, double *a, double *b, double *c, double *d, 
 void launch_zero_pad_f32(const Geom &g, float *a, float *b, float *c, hipStream_t s);
 
 void launch_fill(double *p, int64_t n, double v, hipStream_t s);
+// dense DSOLVE: A_FF (row-major, free nodes numbered by fmap), its inverse made
+// full after the Cholesky routines, and x_F = A_FF^-1 (F - q) at the free nodes
+constexpr int DSOLVE_DENSE_LIMIT = 8192;   // right-hand side in 64 KB of LDS
+void launch_assemble_dense(const Geom &g, const double *beta, const double *const *alpha, const int *fmap,
+                           double *A, int nf, hipStream_t s);
+void launch_symmetrize(double *A, int n, hipStream_t s);
+void launch_dsolve_gemv(int nf, const double *Ainv, const int *freeid, const double *F, const double *q, double *x,
+                        hipStream_t s);
 // dense (n_x+1)(n_y+1)(n_z+1) node array <-> padded level layout
 void launch_pack(const Geom &g, const double *padded, double *dense, hipStream_t s);
 void launch_unpack(const Geom &g, const double *dense, double *padded, hipStream_t s);

@@ -46,6 +46,11 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
     return b;
 }
 
+// 2-vector of T for 16-byte (double) / 8-byte (float) accesses
+template <typename T> struct Vec2;
+template <> struct Vec2<double> { using type = double2; };
+template <> struct Vec2<float> { using type = float2; };
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -447,32 +452,23 @@ __global__ void __launch_bounds__(NTB) k_passB(const PassBArgs<T> a) {
     const T al = (T)sc->alpha;
     const int64_t stride = (int64_t)gridDim.x * NTB;
     double rz = 0.0, rr = 0.0;
-    // U nodes per thread and trip, all loads issued before any is used (more
-    // bytes in flight per thread hides HBM latency)
-    constexpr int U = 1;
-    for (int64_t base = (int64_t)blockIdx.x * NTB + threadIdx.x; base < a.n; base += stride * U) {
-        T rv[U], qv[U], dv[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t i = base + u * stride;
-            rv[u] = qv[u] = dv[u] = 0;
-            if (i < a.n) {
-                rv[u] = a.r[i];
-                qv[u] = a.q[i];
-                dv[u] = a.dinv[i];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t i = base + u * stride;
-            if (i < a.n) {
-                const T x = rv[u] - al * qv[u];
-                a.r[i] = x;
-                const T z = dv[u] * x;
-                rz += (double)x * (double)z;
-                rr += (double)x * (double)x;
-            }
-        }
+    // two nodes per thread and trip with 16-byte accesses (node arrays have an
+    // even length and 16-byte alignment): fewer memory instructions per byte
+    using V2 = typename Vec2<T>::type;
+    const int64_t n2 = a.n / 2;
+    const V2 *__restrict__ r2 = (const V2 *)a.r;
+    const V2 *__restrict__ q2 = (const V2 *)a.q;
+    const V2 *__restrict__ d2 = (const V2 *)a.dinv;
+    V2 *__restrict__ w2 = (V2 *)a.r;
+    for (int64_t i = (int64_t)blockIdx.x * NTB + threadIdx.x; i < n2; i += stride) {
+        const V2 rv = r2[i], qv = q2[i], dv = d2[i];
+        V2 x;
+        x.x = rv.x - al * qv.x;
+        x.y = rv.y - al * qv.y;
+        w2[i] = x;
+        const T z0 = dv.x * x.x, z1 = dv.y * x.y;
+        rz += (double)x.x * (double)z0 + (double)x.y * (double)z1;
+        rr += (double)x.x * (double)x.x + (double)x.y * (double)x.y;
     }
     double acc[2] = {rz, rr}, tot[2];
     if (last_block_total<2, NTB>(acc, red, &s_last, a.partials, a.counter, blockIdx.x, gridDim.x, tot) &&
@@ -491,14 +487,23 @@ __global__ void __launch_bounds__(NTB) k_passB(const PassBArgs<T> a) {
     }
 }
 
-// x += alpha p of the last iteration (after the host has seen `done`).
+// x += alpha p of the last iteration (after the host has seen `done`), two
+// nodes per thread with 16-byte accesses.
 template <typename T>
 __global__ void k_final_x(int64_t n, T *x, const T *p0, const T *p1, const JcgScalars *sc) {
     if (!sc->pending) return;
+    using V2 = typename Vec2<T>::type;
     const T al = (T)sc->alpha;
-    const T *p = (sc->iter & 1) ? p1 : p0;
+    const V2 *__restrict__ p = (const V2 *)((sc->iter & 1) ? p1 : p0);
+    V2 *__restrict__ x2 = (V2 *)x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) x[i] += al * p[i];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n / 2; i += stride) {
+        V2 v = x2[i];
+        const V2 pv = p[i];
+        v.x += al * pv.x;
+        v.y += al * pv.y;
+        x2[i] = v;
+    }
 }
 
 __global__ void k_jcg_reset(JcgScalars *sc, double tol, int max_iter, int fixed) {

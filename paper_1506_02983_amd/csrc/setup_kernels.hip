@@ -166,6 +166,125 @@ __global__ void k_dinv(const Geom g, const double *__restrict__ beta, const Alph
     dinv[id] = 1.0 / d;
 }
 
+__device__ __forceinline__ double wsum_dense(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// ---- dense direct solve of the coarse levels (DSOLVE) -------------------------
+// Row fi of A_FF (free node `id`): for every free neighbour, the Q1 stiffness
+// class coefficient times the sum of beta over the elements holding both nodes,
+// plus the Robin face mass times the sum of alpha over the face elements holding
+// both (when both lie on a Robin face).  Row-major, A[fi * nf + fj].
+__device__ __forceinline__ void elem_range(int i, int d, int n, int &lo, int &hi) {
+    lo = d > 0 ? i : i - 1;                      // elements along one axis holding i and i + d
+    hi = d < 0 ? i - 1 : i;
+    lo = max(lo, 0);
+    hi = min(hi, n - 1);
+}
+
+__global__ void k_assemble_dense(const Geom g, const double *__restrict__ beta, const AlphaPtrs al,
+                                 const int *__restrict__ fmap, double *__restrict__ A, int nf) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= g.nnodes) return;
+    const int fi = fmap[id];
+    if (fi < 0) return;
+    const int i = (int)(id % g.sx);
+    const int64_t t = id / g.sx;
+    const int j = (int)(t % g.sy), k = (int)(t / g.sy);
+    const int idx[3] = {i, j, k};
+    const int n[3] = {g.nx, g.ny, g.nz};
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int d[3] = {dx, dy, dz};
+                const int ii = i + dx, jj = j + dy, kk = k + dz;
+                if (ii < 0 || ii > g.nx || jj < 0 || jj > g.ny || kk < 0 || kk > g.nz) continue;
+                const int fj = fmap[ii + (int64_t)g.sx * (jj + (int64_t)g.sy * kk)];
+                if (fj < 0) continue;
+                int lo[3], hi[3];
+                for (int a = 0; a < 3; ++a) elem_range(idx[a], d[a], n[a], lo[a], hi[a]);
+                double wb = 0.0;
+                for (int ez = lo[2]; ez <= hi[2]; ++ez)
+                    for (int ey = lo[1]; ey <= hi[1]; ++ey)
+                        for (int ex = lo[0]; ex <= hi[0]; ++ex)
+                            wb += beta[ex + (int64_t)g.nx * (ey + (int64_t)g.ny * ez)];
+                const int m = (dx != 0) | ((dy != 0) << 1) | ((dz != 0) << 2);
+                double v = g.C[m] * wb;
+                for (int f = 0; f < 6; ++f) {
+                    if (g.ft[f] != ECMG_ROBIN) continue;
+                    const int ax = f / 2;
+                    if (idx[ax] != ((f & 1) ? n[ax] : 0) || d[ax] != 0) continue;
+                    int pax, qax;
+                    face_axes(f, pax, qax);
+                    int plo, phi, qlo, qhi;
+                    elem_range(idx[pax], d[pax], n[pax], plo, phi);
+                    elem_range(idx[qax], d[qax], n[qax], qlo, qhi);
+                    double wa = 0.0;
+                    for (int eq = qlo; eq <= qhi; ++eq)
+                        for (int ep = plo; ep <= phi; ++ep) wa += al.a[f][ep + (int64_t)n[pax] * eq];
+                    v += g.M[f][(d[pax] != 0) + (d[qax] != 0)] * wa;
+                }
+                A[(int64_t)fi * nf + fj] = v;
+            }
+}
+
+// Copy the lower triangle (column-major: element (r, c), r > c, at r + c n) to
+// the upper one, making the explicit inverse of the Cholesky routines full.
+__global__ void k_symmetrize(double *A, int n) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n * n) return;
+    const int r = (int)(t % n), c = (int)(t / n);
+    if (r < c) A[t] = A[c + (int64_t)r * n];
+}
+
+// x at the free nodes = A_FF^-1 (F - A x0) (x0 = g_D on Dirichlet nodes, 0 on
+// free ones; q = A x0 on free rows).  Each workgroup gathers the right-hand
+// side into LDS; a wave per row, lanes across the (symmetric, so row-major)
+// inverse, fixed-order reduction.
+constexpr int GEMV_NT = 512;
+
+__global__ void __launch_bounds__(GEMV_NT) k_dsolve_gemv(int nf, const double *__restrict__ Ainv,
+                                                         const int *__restrict__ freeid,
+                                                         const double *__restrict__ F, const double *__restrict__ q,
+                                                         double *__restrict__ x) {
+    extern __shared__ double rhs[];
+    for (int c = threadIdx.x; c < nf; c += GEMV_NT) {
+        const int id = freeid[c];
+        rhs[c] = F[id] - q[id];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int row = blockIdx.x * (GEMV_NT / 64) + wave; row < nf; row += gridDim.x * (GEMV_NT / 64)) {
+        const double *Ar = Ainv + (int64_t)row * nf;
+        double s = 0.0;
+        for (int c = lane; c < nf; c += 64) s += Ar[c] * rhs[c];
+        s = wsum_dense(s);
+        if (lane == 0) x[freeid[row]] = s;
+    }
+}
+
+void launch_assemble_dense(const Geom &g, const double *beta, const double *const *alpha, const int *fmap,
+                           double *A, int nf, hipStream_t s) {
+    AlphaPtrs al;
+    for (int f = 0; f < 6; ++f) al.a[f] = alpha[f];
+    hipLaunchKernelGGL(k_assemble_dense, dim3((unsigned)((g.nnodes + 255) / 256)), dim3(256), 0, s, g, beta, al, fmap,
+                       A, nf);
+}
+
+void launch_symmetrize(double *A, int n, hipStream_t s) {
+    const int64_t t = (int64_t)n * n;
+    hipLaunchKernelGGL(k_symmetrize, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, s, A, n);
+}
+
+void launch_dsolve_gemv(int nf, const double *Ainv, const int *freeid, const double *F, const double *q, double *x,
+                        hipStream_t s) {
+    const int rows_per_block = GEMV_NT / 64;
+    const int nb = std::max(1, std::min((nf + rows_per_block - 1) / rows_per_block, 1024));
+    hipLaunchKernelGGL(k_dsolve_gemv, dim3(nb), dim3(GEMV_NT), sizeof(double) * nf, s, nf, Ainv, freeid, F, q, x);
+}
+
 // ---- reductions over node arrays (deterministic, last block finalises) ----------
 __device__ __forceinline__ double wsum(double v) {
 #pragma unroll

@@ -151,3 +151,22 @@ def test_not_converged_and_errors(ecmg, persistent):
         with pytest.raises(ecmg.EcmgError) as e:
             s.setup(bad)
         assert e.value.code == ecmg.EINVAL
+
+
+def test_dsolve_dense_matches_jcg_dsolve(orc, ecmg):
+    """The direct DSOLVE (explicit inverse of A_FF) and the FP64-JCG DSOLVE give
+    the same coarse solutions and the same cascade (both are held to the
+    oracle's banded Cholesky above)."""
+    p = workloads.variable_beta_robin_cube(levels=4)
+    out = {}
+    for dense in (8192, 0):
+        with ecmg.Solver(dsolve_dense_max=dense) as s:
+            s.setup(p)
+            infos = s.solve(1e-10)
+            out[dense] = ([i["iters"] for i in infos], [s.get(l, ecmg.VEC_U) for l in range(p.levels)])
+    assert out[8192][0][:2] == [0, 0] and min(out[0][0][:2]) > 0
+    assert out[8192][0][2:] == out[0][0][2:]
+    for l in range(p.levels):
+        assert _rel(out[8192][1][l], out[0][1][l]) <= 1e-12, l
+    ref = orc.dsolve(orc.discretize(p, 1))
+    assert _rel(out[8192][1][1], ref) <= 1e-12
