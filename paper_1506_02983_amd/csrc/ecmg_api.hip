@@ -349,7 +349,7 @@ static StencilArgs<double> stencil_args(ecmg_ctx *c, Level &L) {
 // iteration mode enqueues all iterations at once).  Leaves the final scalars in
 // c->sc_host.  kind_a / kind_b name the timing classes.
 template <typename T>
-static int jcg_chunks(ecmg_ctx *c, int l, const StencilArgs<T> &a, const PassBArgs<T> &b, int nbB, JcgScalars *sc,
+static int jcg_chunks(ecmg_ctx *c, int l, const StencilArgs<T> &a, const PassBArgs<T> &b, JcgScalars *sc,
                       int fixed, int kind_a, int kind_b) {
     int done_iters = 0;
     int chunk = c->opt.chunk > 0 ? c->opt.chunk : 2;
@@ -365,7 +365,7 @@ static int jcg_chunks(ecmg_ctx *c, int l, const StencilArgs<T> &a, const PassBAr
             launch_stencil<T>(MODE_PASSA, a, c->stream);
             CHK(rec_end(c, slot));
             CHK(rec_begin(c, l, kind_b, done_iters + t, &slot));
-            launch_passB<T>(b, nbB, c->stream);
+            launch_passB<T>(b, c->stream);
             CHK(rec_end(c, slot));
         }
         HIPCHK(c, hipGetLastError());
@@ -408,8 +408,6 @@ static int run_jcg_mixed(ecmg_ctx *c, int l, double tol_abs, int max_iter, ecmg_
     b32.dinv = L.dinv32;
     b32.sc = c->sc32;
     b32.partials = c->partials;
-    b32.counter = c->counters + 1;
-    const int nbB = reduce_blocks(L.g.nnodes);
     const int max_outer = 100;
     int inner_total = 0, outer = 0, status = ECMG_OK;
     double rn = 0.0;
@@ -440,7 +438,7 @@ static int run_jcg_mixed(ecmg_ctx *c, int l, double tol_abs, int max_iter, ecmg_
                            c->stream);
         CHK(rec_end(c, slot));
         HIPCHK(c, hipGetLastError());
-        CHK(jcg_chunks<float>(c, l, a32, b32, nbB, c->sc32, -1, 5, 6));
+        CHK(jcg_chunks<float>(c, l, a32, b32, c->sc32, -1, 5, 6));
         const JcgScalars s = *c->sc_host;
         CHK(rec_begin(c, l, 9, 0, &slot));
         launch_mixed_update(L.g, L.x, rn, c->d32, c->p32a, c->p32b, c->sc32, c->stream);
@@ -497,10 +495,8 @@ static int run_jcg(ecmg_ctx *c, int l, double tol_abs, int max_iter, int fixed, 
     b.dinv = L.dinv;
     b.sc = c->sc;
     b.partials = c->partials;
-    b.counter = c->counters + 1;
-    const int nbB = reduce_blocks(L.g.nnodes);
 
-    CHK(jcg_chunks(c, l, a, b, nbB, c->sc, fixed, 0, 1));
+    CHK(jcg_chunks(c, l, a, b, c->sc, fixed, 0, 1));
     const JcgScalars s = *c->sc_host;
     if (s.pending) launch_final_x(L.g, L.x, c->p0, c->p1, c->sc, c->stream);
     HIPCHK(c, hipGetLastError());
@@ -852,6 +848,7 @@ int ecmg_setup(ecmg_ctx *c, const ecmg_problem *p) {
             Geom g = make_geom(p, l, lo);
             int a, b, d;
             pn = std::max<int64_t>(pn, 2 * (int64_t)stencil_blocks(g, stencil_kz(g, c->KZ), &a, &b, &d));
+            pn = std::max<int64_t>(pn, 2 * passB_blocks(g.nnodes));
         }
         c->partials_n = pn;
         CHK(dalloc_n(c, &c->partials, pn));

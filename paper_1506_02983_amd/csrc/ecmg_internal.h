@@ -101,8 +101,7 @@ struct PassBArgs {
     const T *q;
     const T *dinv;
     JcgScalars *sc;
-    double *partials;
-    unsigned *counter;
+    double *partials;                 // 2 * passB_blocks(n)
 };
 
 // One independent JCG solve inside the persistent kernel: a grid, its arrays,
@@ -169,7 +168,9 @@ int stencil_kz(const Geom &g, int kz_max);
 template <typename T>
 void launch_stencil(int mode, const StencilArgs<T> &a, hipStream_t s);
 template <typename T>
-void launch_passB(const PassBArgs<T> &a, int nblocks, hipStream_t s);
+void launch_passB(const PassBArgs<T> &a, hipStream_t s);
+// blocks of pass B for n nodes (its partial slots: twice as many)
+int64_t passB_blocks(int64_t n);
 void launch_final_x(const Geom &g, double *x, const double *p0, const double *p1, const JcgScalars *sc,
                     hipStream_t s);
 // mixed precision: r32 = r64 / s, d32 = 0, JCG start scalars (FP64 sums)

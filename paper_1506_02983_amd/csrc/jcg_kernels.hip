@@ -441,38 +441,73 @@ __global__ void __launch_bounds__(NT) k_stencil(const StencilArgs<T> a) {
 // ---------------------------------------------------------------------------
 // pass B: r -= alpha q; z = D^-1 r; r.z, r.r; stop test
 // ---------------------------------------------------------------------------
+// A streaming kernel in which every block takes one contiguous chunk of UB x NTB
+// node pairs (16-byte accesses; node arrays have an even length and 16-byte
+// alignment) and stores its two partial sums, then a one-block kernel that sums
+// the partials in block order and takes the scalar step.  Many short-lived
+// blocks with contiguous chunks stream faster than a grid-stride loop, and
+// plain partial stores avoid a device-scope fence and atomic per block.
 constexpr int NTB = 256;
+constexpr int UB = 4;
+constexpr int NTF = 1024;              // threads of the finishing block
 
 template <typename T>
 __global__ void __launch_bounds__(NTB) k_passB(const PassBArgs<T> a) {
     __shared__ double red[2][NTB / 64];
-    __shared__ int s_last;
-    JcgScalars *sc = a.sc;
+    const JcgScalars *sc = a.sc;
     if (sc->done) return;
     const T al = (T)sc->alpha;
-    const int64_t stride = (int64_t)gridDim.x * NTB;
-    double rz = 0.0, rr = 0.0;
-    // two nodes per thread and trip with 16-byte accesses (node arrays have an
-    // even length and 16-byte alignment): fewer memory instructions per byte
     using V2 = typename Vec2<T>::type;
     const int64_t n2 = a.n / 2;
     const V2 *__restrict__ r2 = (const V2 *)a.r;
     const V2 *__restrict__ q2 = (const V2 *)a.q;
     const V2 *__restrict__ d2 = (const V2 *)a.dinv;
     V2 *__restrict__ w2 = (V2 *)a.r;
-    for (int64_t i = (int64_t)blockIdx.x * NTB + threadIdx.x; i < n2; i += stride) {
-        const V2 rv = r2[i], qv = q2[i], dv = d2[i];
-        V2 x;
-        x.x = rv.x - al * qv.x;
-        x.y = rv.y - al * qv.y;
-        w2[i] = x;
-        const T z0 = dv.x * x.x, z1 = dv.y * x.y;
-        rz += (double)x.x * (double)z0 + (double)x.y * (double)z1;
-        rr += (double)x.x * (double)x.x + (double)x.y * (double)x.y;
+    const int64_t base = (int64_t)blockIdx.x * (UB * NTB) + threadIdx.x;
+    V2 rv[UB], qv[UB], dv[UB];
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+        const int64_t i = base + u * NTB;
+        if (i < n2) {
+            rv[u] = r2[i];
+            qv[u] = q2[i];
+            dv[u] = d2[i];
+        }
     }
-    double acc[2] = {rz, rr}, tot[2];
-    if (last_block_total<2, NTB>(acc, red, &s_last, a.partials, a.counter, blockIdx.x, gridDim.x, tot) &&
-        threadIdx.x == 0) {
+    double rz = 0.0, rr = 0.0;
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+        const int64_t i = base + u * NTB;
+        if (i < n2) {
+            V2 x;
+            x.x = rv[u].x - al * qv[u].x;
+            x.y = rv[u].y - al * qv[u].y;
+            w2[i] = x;
+            const T z0 = dv[u].x * x.x, z1 = dv[u].y * x.y;
+            rz += (double)x.x * (double)z0 + (double)x.y * (double)z1;
+            rr += (double)x.x * (double)x.x + (double)x.y * (double)x.y;
+        }
+    }
+    double acc[2] = {rz, rr};
+    block_sum<2, NTB>(acc, red);
+    if (threadIdx.x == 0) {
+        a.partials[2 * (int64_t)blockIdx.x] = acc[0];
+        a.partials[2 * (int64_t)blockIdx.x + 1] = acc[1];
+    }
+}
+
+// Totals of pass B's nb block partials (fixed order), then beta, rho, ||r||^2
+// and the stop test.
+__global__ void __launch_bounds__(NTF) k_passB_finish(JcgScalars *sc, const double *__restrict__ partials, int nb) {
+    __shared__ double red[2][NTF / 64];
+    if (sc->done) return;
+    double tot[2] = {0.0, 0.0};
+    for (int b = threadIdx.x; b < nb; b += NTF) {
+        tot[0] += partials[2 * (int64_t)b];
+        tot[1] += partials[2 * (int64_t)b + 1];
+    }
+    block_sum<2, NTF>(tot, red);
+    if (threadIdx.x == 0) {
         const int it = sc->iter + 1;
         sc->iter = it;
         const double rho_old = sc->rho;
@@ -487,22 +522,34 @@ __global__ void __launch_bounds__(NTB) k_passB(const PassBArgs<T> a) {
     }
 }
 
-// x += alpha p of the last iteration (after the host has seen `done`), two
-// nodes per thread with 16-byte accesses.
+// x += alpha p of the last iteration (after the host has seen `done`): one
+// contiguous chunk of UB x 256 node pairs per block, 16-byte accesses.
 template <typename T>
-__global__ void k_final_x(int64_t n, T *x, const T *p0, const T *p1, const JcgScalars *sc) {
+__global__ void __launch_bounds__(256) k_final_x(int64_t n, T *x, const T *p0, const T *p1, const JcgScalars *sc) {
     if (!sc->pending) return;
     using V2 = typename Vec2<T>::type;
     const T al = (T)sc->alpha;
     const V2 *__restrict__ p = (const V2 *)((sc->iter & 1) ? p1 : p0);
     V2 *__restrict__ x2 = (V2 *)x;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n / 2; i += stride) {
-        V2 v = x2[i];
-        const V2 pv = p[i];
-        v.x += al * pv.x;
-        v.y += al * pv.y;
-        x2[i] = v;
+    const int64_t n2 = n / 2;
+    const int64_t base = (int64_t)blockIdx.x * (UB * 256) + threadIdx.x;
+    V2 xv[UB], pv[UB];
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+        const int64_t i = base + u * 256;
+        if (i < n2) {
+            xv[u] = x2[i];
+            pv[u] = p[i];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+        const int64_t i = base + u * 256;
+        if (i < n2) {
+            xv[u].x += al * pv[u].x;
+            xv[u].y += al * pv[u].y;
+            x2[i] = xv[u];
+        }
     }
 }
 
@@ -549,15 +596,19 @@ void launch_stencil(int mode, const StencilArgs<T> &a, hipStream_t s) {
     else hipLaunchKernelGGL((k_stencil<T, MODE_PASSA>), dim3(nb), dim3(NT), 0, s, a);
 }
 
+int64_t passB_blocks(int64_t n) { return std::max<int64_t>(1, (n / 2 + UB * NTB - 1) / (UB * NTB)); }
+
 template <typename T>
-void launch_passB(const PassBArgs<T> &a, int nblocks, hipStream_t s) {
-    hipLaunchKernelGGL((k_passB<T>), dim3(nblocks), dim3(NTB), 0, s, a);
+void launch_passB(const PassBArgs<T> &a, hipStream_t s) {
+    const int64_t nb = passB_blocks(a.n);
+    hipLaunchKernelGGL((k_passB<T>), dim3((unsigned)nb), dim3(NTB), 0, s, a);
+    hipLaunchKernelGGL(k_passB_finish, dim3(1), dim3(NTF), 0, s, a.sc, (const double *)a.partials, (int)nb);
 }
 
 void launch_final_x(const Geom &g, double *x, const double *p0, const double *p1, const JcgScalars *sc,
                     hipStream_t s) {
-    const int nb = (int)std::min<int64_t>((g.nnodes + 255) / 256, 4096);
-    hipLaunchKernelGGL((k_final_x<double>), dim3(nb), dim3(256), 0, s, g.nnodes, x, p0, p1, sc);
+    const int64_t nb = std::max<int64_t>(1, (g.nnodes / 2 + UB * 256 - 1) / (UB * 256));
+    hipLaunchKernelGGL((k_final_x<double>), dim3((unsigned)nb), dim3(256), 0, s, g.nnodes, x, p0, p1, sc);
 }
 
 void launch_jcg_reset(JcgScalars *sc, double tol, int max_iter, int fixed, hipStream_t s) {
@@ -638,8 +689,8 @@ void launch_to_f32(const double *a, float *b, int64_t n, hipStream_t s) {
 }
 
 template void launch_stencil<double>(int, const StencilArgs<double> &, hipStream_t);
-template void launch_passB<double>(const PassBArgs<double> &, int, hipStream_t);
+template void launch_passB<double>(const PassBArgs<double> &, hipStream_t);
 template void launch_stencil<float>(int, const StencilArgs<float> &, hipStream_t);
-template void launch_passB<float>(const PassBArgs<float> &, int, hipStream_t);
+template void launch_passB<float>(const PassBArgs<float> &, hipStream_t);
 
 }  // namespace ecmg
