@@ -340,7 +340,6 @@ static StencilArgs<double> stencil_args(ecmg_ctx *c, Level &L) {
     a.F = L.F;
     a.sc = c->sc;
     a.partials = c->partials;
-    a.counter = c->counters;
     return a;
 }
 
@@ -400,7 +399,6 @@ static int run_jcg_mixed(ecmg_ctx *c, int l, double tol_abs, int max_iter, ecmg_
     a32.p1 = c->p32b;
     a32.sc = c->sc32;
     a32.partials = c->partials;
-    a32.counter = c->counters;
     PassBArgs<float> b32{};
     b32.n = L.g.nnodes;
     b32.r = c->r32;

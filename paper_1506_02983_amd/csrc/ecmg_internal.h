@@ -90,8 +90,7 @@ struct StencilArgs {
     T *x;                             // pass A: iterate (deferred update)
     T *p0, *p1;                       // pass A: search directions (ping-pong)
     JcgScalars *sc;
-    double *partials;                 // per-block partial sums
-    unsigned *counter;                // last-block counter
+    double *partials;                 // per-block partial sums (2 per block)
 };
 
 template <typename T>

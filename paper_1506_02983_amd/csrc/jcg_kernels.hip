@@ -46,6 +46,8 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
     return b;
 }
 
+constexpr int NTF = 1024;              // threads of a one-block finishing kernel
+
 // 2-vector of T for 16-byte (double) / 8-byte (float) accesses
 template <typename T> struct Vec2;
 template <> struct Vec2<double> { using type = double2; };
@@ -170,7 +172,6 @@ __global__ void __launch_bounds__(NT) k_stencil(const StencilArgs<T> a) {
     __shared__ T sv[4][TYT + 2][TX + 2];
     __shared__ T sb[3][TYT + 1][TX + 1];
     __shared__ double red[2][NT / 64];
-    __shared__ int s_last;
     constexpr int NH = 2 * (TX + 2) + 2 * TYT;   // halo nodes of a plane tile
     constexpr int NHB = (TX + 1) + TYT;          // halo elements of a layer tile
     static_assert(NH <= NT && NHB <= NT, "one halo value per thread");
@@ -408,33 +409,46 @@ __global__ void __launch_bounds__(NT) k_stencil(const StencilArgs<T> a) {
 
     if (MODE == MODE_APPLY) return;
 
+    // block partials, plain stores: a one-block kernel takes the totals
+    double acc[2] = {acc0, acc1};
+    block_sum<2, NT>(acc, red);
+    if (tid == 0) {
+        a.partials[2 * (int64_t)blockIdx.x] = acc[0];
+        if (MODE == MODE_INIT) a.partials[2 * (int64_t)blockIdx.x + 1] = acc[1];
+    }
+}
+
+// Totals of the stencil pass's nb block partials (fixed order), then the
+// scalar step: init sets rho = r.z, ||r||^2 and the first stop test; pass A
+// sets p.q and alpha = rho / p.q (or flags a breakdown).
+template <int MODE>
+__global__ void __launch_bounds__(NTF) k_stencil_finish(JcgScalars *sc, const double *__restrict__ partials, int nb) {
+    __shared__ double red[2][NTF / 64];
+    if (MODE == MODE_PASSA && sc->done) return;
+    double tot[2] = {0.0, 0.0};
+    for (int b = threadIdx.x; b < nb; b += NTF) {
+        tot[0] += partials[2 * (int64_t)b];
+        if (MODE == MODE_INIT) tot[1] += partials[2 * (int64_t)b + 1];
+    }
+    block_sum<2, NTF>(tot, red);
+    if (threadIdx.x != 0) return;
     if (MODE == MODE_INIT) {
-        double acc[2] = {acc0, acc1}, tot[2];
-        if (last_block_total<2, NT>(acc, red, &s_last, a.partials, a.counter, blockIdx.x, gridDim.x, tot) &&
-            tid == 0) {
-            JcgScalars *sc = a.sc;
-            sc->rho = tot[0];
-            sc->rr = tot[1];
-            sc->iter = 0;
-            sc->alpha = 0.0;
-            sc->beta = 0.0;
-            sc->pending = 0;
-            const double rn = sqrt(tot[1]);
-            if (sc->fixed >= 0) sc->done = (sc->fixed == 0) ? DONE_CONVERGED : DONE_RUNNING;
-            else if (!(rn > sc->tol)) sc->done = DONE_CONVERGED;
-            else sc->done = (sc->max_iter <= 0) ? DONE_MAXITER : DONE_RUNNING;
-        }
+        sc->rho = tot[0];
+        sc->rr = tot[1];
+        sc->iter = 0;
+        sc->alpha = 0.0;
+        sc->beta = 0.0;
+        sc->pending = 0;
+        const double rn = sqrt(tot[1]);
+        if (sc->fixed >= 0) sc->done = (sc->fixed == 0) ? DONE_CONVERGED : DONE_RUNNING;
+        else if (!(rn > sc->tol)) sc->done = DONE_CONVERGED;
+        else sc->done = (sc->max_iter <= 0) ? DONE_MAXITER : DONE_RUNNING;
     } else {
-        double acc[1] = {acc0}, tot[1];
-        if (last_block_total<1, NT>(acc, red, &s_last, a.partials, a.counter, blockIdx.x, gridDim.x, tot) &&
-            tid == 0) {
-            JcgScalars *sc = a.sc;
-            const double pq = tot[0];
-            sc->pq = pq;
-            sc->pending = 0;
-            if (!(pq > 0.0) || !isfinite(pq)) sc->done = DONE_BREAKDOWN;
-            else sc->alpha = sc->rho / pq;
-        }
+        const double pq = tot[0];
+        sc->pq = pq;
+        sc->pending = 0;
+        if (!(pq > 0.0) || !isfinite(pq)) sc->done = DONE_BREAKDOWN;
+        else sc->alpha = sc->rho / pq;
     }
 }
 
@@ -449,7 +463,6 @@ __global__ void __launch_bounds__(NT) k_stencil(const StencilArgs<T> a) {
 // plain partial stores avoid a device-scope fence and atomic per block.
 constexpr int NTB = 256;
 constexpr int UB = 4;
-constexpr int NTF = 1024;              // threads of the finishing block
 
 template <typename T>
 __global__ void __launch_bounds__(NTB) k_passB(const PassBArgs<T> a) {
@@ -591,9 +604,15 @@ int stencil_kz(const Geom &g, int kz_max) {
 template <typename T>
 void launch_stencil(int mode, const StencilArgs<T> &a, hipStream_t s) {
     const int nb = a.ntx * a.nty * a.nkz;
-    if (mode == MODE_APPLY) hipLaunchKernelGGL((k_stencil<T, MODE_APPLY>), dim3(nb), dim3(NT), 0, s, a);
-    else if (mode == MODE_INIT) hipLaunchKernelGGL((k_stencil<T, MODE_INIT>), dim3(nb), dim3(NT), 0, s, a);
-    else hipLaunchKernelGGL((k_stencil<T, MODE_PASSA>), dim3(nb), dim3(NT), 0, s, a);
+    if (mode == MODE_APPLY) {
+        hipLaunchKernelGGL((k_stencil<T, MODE_APPLY>), dim3(nb), dim3(NT), 0, s, a);
+    } else if (mode == MODE_INIT) {
+        hipLaunchKernelGGL((k_stencil<T, MODE_INIT>), dim3(nb), dim3(NT), 0, s, a);
+        hipLaunchKernelGGL(k_stencil_finish<MODE_INIT>, dim3(1), dim3(NTF), 0, s, a.sc, (const double *)a.partials, nb);
+    } else {
+        hipLaunchKernelGGL((k_stencil<T, MODE_PASSA>), dim3(nb), dim3(NT), 0, s, a);
+        hipLaunchKernelGGL(k_stencil_finish<MODE_PASSA>, dim3(1), dim3(NTF), 0, s, a.sc, (const double *)a.partials, nb);
+    }
 }
 
 int64_t passB_blocks(int64_t n) { return std::max<int64_t>(1, (n / 2 + UB * NTB - 1) / (UB * NTB)); }
