@@ -593,9 +593,7 @@ static int do_exp_finite(ecmg_ctx *c, int l) {
     Level &L = c->lv[l];
     size_t slot = 0;
     CHK(rec_begin(c, l, 3, 0, &slot));
-    // phase 1 writes the 27-point nodal values on level l-1 into the q scratch
-    launch_exp_finite(L.g, c->lv[l - 1].g, c->lv[l - 1].x, c->lv[l - 2].x, c->q, L.x, L.W, c->opt.interp,
-                      c->stream);
+    launch_exp_finite(L.g, c->lv[l - 1].g, c->lv[l - 1].x, c->lv[l - 2].x, L.x, L.W, c->opt.interp, c->stream);
     CHK(rec_end(c, slot));
     HIPCHK(c, hipGetLastError());
     return ECMG_OK;
@@ -1199,26 +1197,23 @@ int ecmg_solve_batch(ecmg_ctx *const *ctxs, int32_t n, double rel_tol, ecmg_leve
         tasks.clear();
         owner.clear();
         std::vector<ExpTask> ex;
-        int64_t nb0 = 0, nb1 = 0;
+        int64_t nb0 = 0;
         for (int i = 0; i < n; ++i) {
             ecmg_ctx *c = ctxs[i];
             if (l >= c->nlev) continue;
             Level &L = c->lv[l];
-            if (l >= 2) {                 // EXP_finite of every box in one pair of launches
+            if (l >= 2) {                 // EXP_finite of every box in one launch
                 ExpTask e{};
                 e.gf = L.g;
                 e.g1 = c->lv[l - 1].g;
                 e.U1 = c->lv[l - 1].x;
                 e.U0 = c->lv[l - 2].x;
-                e.V = c->q;
                 e.x = L.x;
                 e.W = L.W;
                 e.variant = c->opt.interp;
                 exp_task_blocks(e, 0);
                 e.b0[0] = nb0;
-                e.b0[1] = nb1;
                 nb0 += e.nb[0];
-                nb1 += e.nb[1];
                 ex.push_back(e);
             }
             const double tol = (l < 2 ? c->opt.dsolve_tol : rel_tol) * L.nf;
@@ -1228,10 +1223,10 @@ int ecmg_solve_batch(ecmg_ctx *const *ctxs, int32_t n, double rel_tol, ecmg_leve
             owner.push_back(i);
         }
         if (!ex.empty()) {
-            if (nb0 >= ((int64_t)1 << 31) || nb1 >= ((int64_t)1 << 31))
+            if (nb0 >= ((int64_t)1 << 31))
                 return fail(c0, ECMG_EINVAL, "batched EXP_finite grid too large");
             HIPCHK(c0, hipMemcpyAsync(c0->bt_exp, ex.data(), sizeof(ExpTask) * ex.size(), hipMemcpyHostToDevice, s));
-            launch_exp_finite_batch(c0->bt_exp, (int)ex.size(), nb0, nb1, s);
+            launch_exp_finite_batch(c0->bt_exp, (int)ex.size(), nb0, s);
             HIPCHK(c0, hipGetLastError());
         }
         // longest first: order by node count, then by input position
@@ -1583,7 +1578,7 @@ static int server_tick(ecmg_server *S) {
         CHK(batch_reserve(c0, n));
         std::vector<PersistentTask> tasks(n);
         std::vector<ExpTask> ex;
-        int64_t nb0 = 0, nb1 = 0;
+        int64_t nb0 = 0;
         for (int k = 0; k < n; ++k) {
             ServerReq *r = small[k];
             ecmg_ctx *c = r->ctx;
@@ -1595,15 +1590,12 @@ static int server_tick(ecmg_server *S) {
                 e.g1 = c->lv[l - 1].g;
                 e.U1 = c->lv[l - 1].x;
                 e.U0 = c->lv[l - 2].x;
-                e.V = c->q;
                 e.x = L.x;
                 e.W = L.W;
                 e.variant = c->opt.interp;
                 exp_task_blocks(e, 0);
                 e.b0[0] = nb0;
-                e.b0[1] = nb1;
                 nb0 += e.nb[0];
-                nb1 += e.nb[1];
                 ex.push_back(e);
             }
             const double tol = (l < 2 ? c->opt.dsolve_tol : r->rel_tol) * L.nf;
@@ -1625,10 +1617,10 @@ static int server_tick(ecmg_server *S) {
             items += sorted[k].nwg;
         }
         if (!ex.empty()) {
-            if (nb0 >= ((int64_t)1 << 31) || nb1 >= ((int64_t)1 << 31))
+            if (nb0 >= ((int64_t)1 << 31))
                 return fail(c0, ECMG_EINVAL, "batched EXP_finite grid too large");
             HIPCHK(c0, hipMemcpyAsync(c0->bt_exp, ex.data(), sizeof(ExpTask) * ex.size(), hipMemcpyHostToDevice, s));
-            launch_exp_finite_batch(c0->bt_exp, (int)ex.size(), nb0, nb1, s);
+            launch_exp_finite_batch(c0->bt_exp, (int)ex.size(), nb0, s);
             HIPCHK(c0, hipGetLastError());
         }
         HIPCHK(c0, hipMemsetAsync(c0->bt_bar, 0, 32 * sizeof(unsigned) * (size_t)n, s));

@@ -181,27 +181,27 @@ void launch_mixed_update(const Geom &g, double *x, double sc_s, const float *d32
 void launch_to_f32(const double *a, float *b, int64_t n, hipStream_t s);
 void launch_jcg_reset(JcgScalars *sc, double tol, int max_iter, int fixed, hipStream_t s);
 
-void launch_exp_finite(const Geom &gf, const Geom &g1, const double *U1, const double *U0, double *V, double *x,
-                       double *W, int variant, hipStream_t s);
+void launch_exp_finite(const Geom &gf, const Geom &g1, const double *U1, const double *U0, double *x, double *W,
+                       int variant, hipStream_t s);
 void launch_exp_true(const Geom &gf, const double *U1, const double *U0, double *Ut, hipStream_t s);
 
-// One box of a batched EXP_finite (U1 = u_{l-1}, U0 = u_{l-2}, V scratch on
-// level l-1, x and optional W on level l) or EXP_true (U1 = u_l, U0 = u_{l-1},
-// result into x).  b0 / nb / gx / gy: first flat block, block count, blocks
-// along x and along y of phase 0 (level l-1 grid) and phase 1 (fine grid);
-// a block is 64 x-nodes by 4 y-rows of one z-plane.
+// One box of a batched EXP_finite (U1 = u_{l-1}, U0 = u_{l-2}, x and optional
+// W on level l) or EXP_true (U1 = u_l, U0 = u_{l-1}, result into x).  b0 / nb:
+// first flat block and block count of the box ([0] EXP_finite, [1] EXP_true);
+// gx / gy: EXP_true blocks along x and y (a block is 63 node pairs by 4 rows
+// of one z-plane).
 struct ExpTask {
     Geom gf, g1;
     const double *U1, *U0;
-    double *V, *x, *W;
+    double *x, *W;
     int variant;
     int gx[2], gy[2];
     int64_t nb[2], b0[2];
 };
-// kind 0: EXP_finite (phase 1 one thread per coarse element of a fine row),
-// 1: EXP_true (63 node pairs per 64-lane row block)
+// kind 0: EXP_finite (one thread per coarse element; blocks in nb[0], b0[0]),
+// 1: EXP_true (63 node pairs per 64-lane row block; nb[1], b0[1])
 void exp_task_blocks(ExpTask &t, int kind);
-void launch_exp_finite_batch(const ExpTask *d_tasks, int n, int64_t nb0, int64_t nb1, hipStream_t s);
+void launch_exp_finite_batch(const ExpTask *d_tasks, int n, int64_t nb, hipStream_t s);
 void launch_exp_true_batch(const ExpTask *d_tasks, int n, int64_t nb1, hipStream_t s);
 void launch_zero_pad(const Geom &g, double *a, double *b, double *c, double *d, hipStream_t s);
 void launch_zero_pad_f32(const Geom &g, float *a, float *b, float *c, hipStream_t s);

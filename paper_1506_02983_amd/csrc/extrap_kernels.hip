@@ -21,9 +21,13 @@
 // shape functions.  A fine node on a face shared by two coarse elements belongs
 // to the lower-index element (both give the same value up to rounding).
 //
-// The 27 nodal values sit on level l-1 nodes and each depends only on its own
-// edge, face or element, so phase 1 computes them once per level l-1 node (into
-// scratch) and phase 2 interpolates every fine node from them.
+// Each of the 27 nodal values of a coarse element depends only on that
+// element's own 27 level l-1 values and 8 level l-2 corner values (its edge,
+// face or the element itself), so one thread per coarse element loads those 35
+// values, forms the 27 nodal values in registers and writes the element's 4x4x4
+// fine nodes (one more layer on the grid's upper faces).  A nodal value on a
+// face or edge shared with a neighbouring element is computed by both from the
+// same inputs with the same expression, so it is single-valued.
 #include "ecmg_internal.h"
 
 namespace ecmg {
@@ -46,175 +50,195 @@ __device__ __forceinline__ bool is_dir(const Geom &g, int i, int j, int k) {
            (k == 0 && g.ft[4] == ECMG_DIRICHLET) || (k == g.nz && g.ft[5] == ECMG_DIRICHLET);
 }
 
-// Phase 1 of EXP_finite, on the level l-1 grid (node (p,q,r), level l-2 nodes
-// at even indices): the 27-point nodal value V of the level l-2 element(s)
-// containing the node.  Every such value depends only on the node's own edge,
-// face or element, so it is single-valued across neighbouring coarse elements.
-__device__ __forceinline__ double u_at(const double *U, int64_t sx, int64_t sxy, int p, int q, int r) {
-    return U[p + sx * q + sxy * r];
-}
-
-__device__ __forceinline__ void exp_finite_nodal_block(const Geom &g1, const double *__restrict__ U1,
-                                                       const double *__restrict__ U0, double *__restrict__ V,
-                                                       int variant, int bx, int by, int bz) {
-    const int p = bx * 64 + threadIdx.x;
-    const int q = by * 4 + threadIdx.y, r = bz;
-    if (p > g1.nx || q > g1.ny || r > g1.nz) return;
+// EXP_finite of coarse (level l-2) element e = I + NX (J + NY K) of the fine
+// grid gf (NX = nx/4 ...): local level l-1 nodes (a,b,c) in {0,1,2}^3 are the
+// global ones (2I+a, 2J+b, 2K+c); level l-2 corners (a/2, b/2, c/2).  Fine rows
+// are written with 16-byte stores (4I is a multiple of 4 and rows are 16-byte
+// aligned); lanes take consecutive I, so a wave writes contiguous row segments.
+__device__ __forceinline__ void exp_finite_elem(const Geom &gf, const Geom &g1, const double *__restrict__ U1,
+                                                const double *__restrict__ U0, double *__restrict__ x,
+                                                double *__restrict__ W, int variant, int64_t e) {
+    const int NX = gf.nx / 4, NY = gf.ny / 4, NZ = gf.nz / 4;
+    if (e >= (int64_t)NX * NY * NZ) return;
+    const int I = (int)(e % NX);
+    const int64_t ejk = e / NX;
+    const int J = (int)(ejk % NY), K = (int)(ejk / NY);
     const int64_t s1 = g1.sx, s1y = (int64_t)g1.sx * g1.sy;
     const int64_t s0 = row_pitch(g1.nx / 2 + 1), s0y = s0 * (g1.ny / 2 + 1);
-    // eq. jiedian at a level l-2 node (all indices even)
-    auto Wc = [&](int pp, int qq, int rr) {
-        return (5.0 * u_at(U1, s1, s1y, pp, qq, rr) - u_at(U0, s0, s0y, pp >> 1, qq >> 1, rr >> 1)) / 4.0;
+
+    // the element's level l-1 values u[c][b][a] and level l-2 corners u0[c][b][a]
+    double u[3][3][3], u0[2][2][2];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const double *row = U1 + 2 * I + s1 * (2 * J + b) + s1y * (2 * K + c);
+            const double2 v01 = *(const double2 *)row;   // 2I is even: 16-byte aligned
+            u[c][b][0] = v01.x;
+            u[c][b][1] = v01.y;
+            u[c][b][2] = row[2];
+        }
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int a = 0; a < 2; ++a) u0[c][b][a] = U0[(I + a) + s0 * (J + b) + s0y * (K + c)];
+
+    // nodal values N[c][b][a]
+    double N[3][3][3];
+    auto del = [&](int a, int b, int c) { return u[c][b][a] - u0[c >> 1][b >> 1][a >> 1]; };
+#pragma unroll
+    for (int c = 0; c < 3; c += 2)                     // corners: eq. jiedian
+#pragma unroll
+        for (int b = 0; b < 3; b += 2)
+#pragma unroll
+            for (int a = 0; a < 3; a += 2) N[c][b][a] = (5.0 * u[c][b][a] - u0[c >> 1][b >> 1][a >> 1]) / 4.0;
+    // mid-edges along axis ax: eq. zhongdian
+    auto Wm = [&](int a, int b, int c, int ax) {
+        const int da = ax == 0, db = ax == 1, dc = ax == 2;
+        return u[c][b][a] + (del(a - da, b - db, c - dc) + del(a + da, b + db, c + dc)) / 8.0;
     };
-    auto del = [&](int pp, int qq, int rr) {
-        return u_at(U1, s1, s1y, pp, qq, rr) - u_at(U0, s0, s0y, pp >> 1, qq >> 1, rr >> 1);
-    };
-    // eq. zhongdian at the midpoint (pp,qq,rr) of the edge along axis ax
-    auto Wm = [&](int pp, int qq, int rr, int ax) {
-        const int dp = ax == 0, dq = ax == 1, dr = ax == 2;
-        return u_at(U1, s1, s1y, pp, qq, rr) + (del(pp - dp, qq - dq, rr - dr) + del(pp + dp, qq + dq, rr + dr)) / 8.0;
-    };
-    const int op = p & 1, oq = q & 1, orr = r & 1;
-    const int nodd = op + oq + orr;
-    double v;
-    if (nodd == 0) {
-        v = Wc(p, q, r);
-    } else if (nodd == 1) {
-        v = Wm(p, q, r, op ? 0 : (oq ? 1 : 2));
-    } else if (nodd == 2) {
-        // face centre; in-face axes A < B (the two odd ones)
-        const int A = op ? 0 : 1, B = orr ? 2 : 1;
-        auto at = [&](int sa, int sb) {                  // offset sa along A, sb along B
-            int3 c = make_int3(p, q, r);
-            if (A == 0) c.x += sa; else c.y += sa;
-            if (B == 1) c.y += sb; else c.z += sb;
-            return c;
-        };
-        if (variant == ECMG_SERENDIPITY20) {
-            // value of the face's 8-node serendipity interpolant at its centre:
-            // -1/4 (4 corners) + 1/2 (4 mid-edges)
-            double sc = 0.0, sm = 0.0;
-            for (int sb = -1; sb <= 1; sb += 2)
-                for (int sa = -1; sa <= 1; sa += 2) {
-                    const int3 c = at(sa, sb);
-                    sc += Wc(c.x, c.y, c.z);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                if ((a & 1) + (b & 1) + (c & 1) == 1) N[c][b][a] = Wm(a, b, c, (a & 1) ? 0 : ((b & 1) ? 1 : 2));
+    // face centres: in-face axes A < B (the two odd ones); offset (sa, sb)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                if ((a & 1) + (b & 1) + (c & 1) != 2) continue;
+                const int A = (a & 1) ? 0 : 1, B = (c & 1) ? 2 : 1;
+                auto at = [&](int sa, int sb, int &pa, int &pb, int &pc) {
+                    pa = a + (A == 0 ? sa : 0);
+                    pb = b + (A == 1 ? sa : 0) + (B == 1 ? sb : 0);
+                    pc = c + (B == 2 ? sb : 0);
+                };
+                int xa, xb, xc, ya, yb, yc;
+                double v;
+                if (variant == ECMG_SERENDIPITY20) {
+                    // the face's 8-node serendipity interpolant at its centre:
+                    // -1/4 (4 corners) + 1/2 (4 mid-edges)
+                    double sc = 0.0, sm = 0.0;
+#pragma unroll
+                    for (int sb = -1; sb <= 1; sb += 2)
+#pragma unroll
+                        for (int sa = -1; sa <= 1; sa += 2) {
+                            at(sa, sb, xa, xb, xc);
+                            sc += N[xc][xb][xa];
+                        }
+#pragma unroll
+                    for (int s2 = -1; s2 <= 1; s2 += 2) {
+                        at(0, s2, xa, xb, xc);           // edge along A at B offset s2
+                        at(s2, 0, ya, yb, yc);           // edge along B at A offset s2
+                        sm += N[xc][xb][xa] + N[yc][yb][ya];
+                    }
+                    v = -0.25 * sc + 0.5 * sm;
+                } else {
+                    // mean of eq. zhongdian along the two face diagonals
+                    const double um = u[c][b][a];
+                    int pa, pb, pc, qa, qb, qc;
+                    at(-1, -1, xa, xb, xc);
+                    at(1, 1, ya, yb, yc);
+                    at(-1, 1, pa, pb, pc);
+                    at(1, -1, qa, qb, qc);
+                    v = ((um + (del(xa, xb, xc) + del(ya, yb, yc)) / 8.0) +
+                         (um + (del(pa, pb, pc) + del(qa, qb, qc)) / 8.0)) / 2.0;
                 }
-            for (int s = -1; s <= 1; s += 2) {
-                const int3 ea = at(0, s);                // edge along A at B offset s
-                const int3 eb = at(s, 0);                // edge along B at A offset s
-                sm += Wm(ea.x, ea.y, ea.z, A) + Wm(eb.x, eb.y, eb.z, B);
+                N[c][b][a] = v;
             }
-            v = -0.25 * sc + 0.5 * sm;
-        } else {
-            // mean of eq. zhongdian along the two face diagonals
-            const double u = u_at(U1, s1, s1y, p, q, r);
-            const int3 a0 = at(-1, -1), a1 = at(1, 1), b0 = at(-1, 1), b1 = at(1, -1);
-            v = ((u + (del(a0.x, a0.y, a0.z) + del(a1.x, a1.y, a1.z)) / 8.0) +
-                 (u + (del(b0.x, b0.y, b0.z) + del(b1.x, b1.y, b1.z)) / 8.0)) / 2.0;
-        }
-    } else {
-        if (variant == ECMG_SERENDIPITY20) {
-            // -1/4 (8 corners) + 1/4 (12 mid-edges)
-            double sc = 0.0, sm = 0.0;
-            for (int c = -1; c <= 1; c += 2)
-                for (int b = -1; b <= 1; b += 2)
-                    for (int a = -1; a <= 1; a += 2) sc += Wc(p + a, q + b, r + c);
-            for (int t = -1; t <= 1; t += 2)
-                for (int u2 = -1; u2 <= 1; u2 += 2)
-                    sm += Wm(p, q + t, r + u2, 0) + Wm(p + t, q, r + u2, 1) + Wm(p + t, q + u2, r, 2);
-            v = -0.25 * sc + 0.25 * sm;
-        } else {
-            // mean of eq. zhongdian along the 4 space diagonals
-            const double m = u_at(U1, s1, s1y, p, q, r);
-            double sum = 0.0;
+    // element centre
+    if (variant == ECMG_SERENDIPITY20) {
+        // -1/4 (8 corners) + 1/4 (12 mid-edges)
+        double sc = 0.0, sm = 0.0;
+#pragma unroll
+        for (int c = -1; c <= 1; c += 2)
+#pragma unroll
             for (int b = -1; b <= 1; b += 2)
-                for (int c = -1; c <= 1; c += 2)
-                    sum += m + (del(p - 1, q - b, r - c) + del(p + 1, q + b, r + c)) / 8.0;
-            v = sum / 4.0;
-        }
-    }
-    V[p + s1 * q + s1y * r] = v;
-}
-
-__global__ void __launch_bounds__(256) k_exp_finite_nodal(const Geom g1, const double *__restrict__ U1,
-                                                          const double *__restrict__ U0, double *__restrict__ V,
-                                                          int variant) {
-    exp_finite_nodal_block(g1, U1, U0, V, variant, blockIdx.x, blockIdx.y, blockIdx.z);
-}
-
-// Phase 2: every fine node of level l is the tri-quadratic Lagrange
-// interpolant of the 27 nodal values of its owner coarse element.  A thread
-// takes one coarse element I along x and one fine row (j, k): the 4 fine
-// nodes 4I..4I+3 (and 4I+4 at the end of the row).  For each coarse row with a
-// nonzero y / z weight (1, 3 or 9 of them, uniform over the wave) it loads the
-// element's 3 nodal values with one 16-byte and one 8-byte load and folds
-// them into 3 x-column sums; the fine nodes are then fixed combinations of the
-// column sums, written as 16-byte stores.  Few wide loads per node matter:
-// the inter-level kernels are bound by address processing, not bytes.
-__device__ __forceinline__ void exp_finite_interp_block(const Geom &gf, const double *__restrict__ V,
-                                                        double *__restrict__ x, double *__restrict__ W, int bx,
-                                                        int by, int bz) {
-    const int NX = gf.nx / 4, NY = gf.ny / 4, NZ = gf.nz / 4;
-    const int I = bx * 64 + threadIdx.x;
-    const int j = by * 4 + threadIdx.y, k = bz;
-    if (I >= NX || j > gf.ny || k > gf.nz) return;
-    const int J = min(j / 4, NY - 1), K = min(k / 4, NZ - 1);
-    const int b = j - 4 * J, c = k - 4 * K;
-    const int64_t s1 = row_pitch(gf.nx / 2 + 1), s1y = s1 * (gf.ny / 2 + 1);
-    double Ly[3], Lz[3];
-    lagrange3(b, Ly);
-    lagrange3(c, Lz);
-    const double *Vb = V + (2 * I) + s1 * (2 * J) + s1y * (2 * K);
-    double w0 = 0.0, w1 = 0.0, w2 = 0.0;                  // weighted sums of the 3 x-columns
-    for (int cc = 0; cc < 3; ++cc) {
-        if (Lz[cc] == 0.0) continue;                      // uniform over the wave
-        double t0 = 0.0, t1 = 0.0, t2 = 0.0;
-        for (int bb = 0; bb < 3; ++bb) {
-            if (Ly[bb] == 0.0) continue;                  // uniform over the wave
-            const double *Vr = Vb + s1 * bb + s1y * cc;
-            const double2 v01 = *(const double2 *)Vr;     // 2I is even: 16-byte aligned
-            const double v2 = Vr[2];
-            t0 += Ly[bb] * v01.x;
-            t1 += Ly[bb] * v01.y;
-            t2 += Ly[bb] * v2;
-        }
-        w0 += Lz[cc] * t0;
-        w1 += Lz[cc] * t1;
-        w2 += Lz[cc] * t2;
-    }
-    // x weights at a = 0..4 (natural coordinate a/2 - 1): (1,0,0), (3/8,3/4,-1/8),
-    // (0,1,0), (-1/8,3/4,3/8), (0,0,1)
-    double out[5];
-    out[0] = w0;
-    out[1] = 0.375 * w0 + 0.75 * w1 - 0.125 * w2;
-    out[2] = w1;
-    out[3] = -0.125 * w0 + 0.75 * w1 + 0.375 * w2;
-    out[4] = w2;
-    const int i0 = 4 * I;
-    const int64_t id = i0 + (int64_t)gf.sx * j + (int64_t)gf.sx * gf.sy * k;
-    const bool dj = (j == 0 && gf.ft[2] == ECMG_DIRICHLET) || (j == gf.ny && gf.ft[3] == ECMG_DIRICHLET) ||
-                    (k == 0 && gf.ft[4] == ECMG_DIRICHLET) || (k == gf.nz && gf.ft[5] == ECMG_DIRICHLET);
-    const int na = (I == NX - 1) ? 5 : 4;
-    if (W) {
-        *(double2 *)(W + id) = make_double2(out[0], out[1]);   // 4I: 32-byte aligned
-        *(double2 *)(W + id + 2) = make_double2(out[2], out[3]);
-        if (na == 5) W[id + 4] = out[4];
-    }
-    if (dj) return;                                       // the whole row is Dirichlet
-    const bool d0 = (i0 == 0 && gf.ft[0] == ECMG_DIRICHLET);
-    const bool d4 = (i0 + 4 == gf.nx && gf.ft[1] == ECMG_DIRICHLET);
-    if (!d0) {
-        *(double2 *)(x + id) = make_double2(out[0], out[1]);
+#pragma unroll
+                for (int a = -1; a <= 1; a += 2) sc += N[1 + c][1 + b][1 + a];
+#pragma unroll
+        for (int t = -1; t <= 1; t += 2)
+#pragma unroll
+            for (int u2 = -1; u2 <= 1; u2 += 2)
+                sm += N[1 + u2][1 + t][1] + N[1 + u2][1][1 + t] + N[1][1 + u2][1 + t];
+        N[1][1][1] = -0.25 * sc + 0.25 * sm;
     } else {
-        x[id + 1] = out[1];
+        // mean of eq. zhongdian along the 4 space diagonals
+        const double m = u[1][1][1];
+        double sum = 0.0;
+#pragma unroll
+        for (int b = -1; b <= 1; b += 2)
+#pragma unroll
+            for (int c = -1; c <= 1; c += 2) sum += m + (del(0, 1 - b, 1 - c) + del(2, 1 + b, 1 + c)) / 8.0;
+        N[1][1][1] = sum / 4.0;
     }
-    *(double2 *)(x + id + 2) = make_double2(out[2], out[3]);
-    if (na == 5 && !d4) x[id + 4] = out[4];
+
+    // fine rows (j, k) = (4J + bf, 4K + cf): tensor-product quadratic
+    // interpolation, z then y weights folded into 3 x-column sums
+    const bool lastx = I == NX - 1, lasty = J == NY - 1, lastz = K == NZ - 1;
+    const bool d0 = I == 0 && gf.ft[0] == ECMG_DIRICHLET;
+    const bool d4 = lastx && gf.ft[1] == ECMG_DIRICHLET;
+    const int64_t sx = gf.sx, sxy = (int64_t)gf.sx * gf.sy;
+#pragma unroll
+    for (int cf = 0; cf < 5; ++cf) {
+        if (cf == 4 && !lastz) break;
+        double Lz[3];
+        lagrange3(cf, Lz);
+        const int k = 4 * K + cf;
+#pragma unroll
+        for (int bf = 0; bf < 5; ++bf) {
+            if (bf == 4 && !lasty) break;
+            double Ly[3];
+            lagrange3(bf, Ly);
+            const int j = 4 * J + bf;
+            double w0 = 0.0, w1 = 0.0, w2 = 0.0;
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+                if (Lz[cc] == 0.0) continue;
+                double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+#pragma unroll
+                for (int bb = 0; bb < 3; ++bb) {
+                    if (Ly[bb] == 0.0) continue;
+                    t0 += Ly[bb] * N[cc][bb][0];
+                    t1 += Ly[bb] * N[cc][bb][1];
+                    t2 += Ly[bb] * N[cc][bb][2];
+                }
+                w0 += Lz[cc] * t0;
+                w1 += Lz[cc] * t1;
+                w2 += Lz[cc] * t2;
+            }
+            // x weights at a = 0..4: (1,0,0), (3/8,3/4,-1/8), (0,1,0),
+            // (-1/8,3/4,3/8), (0,0,1)
+            const double o1 = 0.375 * w0 + 0.75 * w1 - 0.125 * w2;
+            const double o3 = -0.125 * w0 + 0.75 * w1 + 0.375 * w2;
+            const int64_t id = 4 * I + sx * j + sxy * k;
+            if (W) {
+                *(double2 *)(W + id) = make_double2(w0, o1);
+                *(double2 *)(W + id + 2) = make_double2(w1, o3);
+                if (lastx) W[id + 4] = w2;
+            }
+            const bool drow = (j == 0 && gf.ft[2] == ECMG_DIRICHLET) || (j == gf.ny && gf.ft[3] == ECMG_DIRICHLET) ||
+                              (k == 0 && gf.ft[4] == ECMG_DIRICHLET) || (k == gf.nz && gf.ft[5] == ECMG_DIRICHLET);
+            if (drow) continue;                               // the whole row is Dirichlet (g_D stays)
+            if (!d0) *(double2 *)(x + id) = make_double2(w0, o1);
+            else x[id + 1] = o1;
+            *(double2 *)(x + id + 2) = make_double2(w1, o3);
+            if (lastx && !d4) x[id + 4] = w2;
+        }
+    }
 }
 
-__global__ void __launch_bounds__(256) k_exp_finite_interp(const Geom gf, const double *__restrict__ V,
-                                                           double *__restrict__ x, double *__restrict__ W) {
-    exp_finite_interp_block(gf, V, x, W, blockIdx.x, blockIdx.y, blockIdx.z);
+__global__ void __launch_bounds__(256) k_exp_finite(const Geom gf, const Geom g1, const double *__restrict__ U1,
+                                                    const double *__restrict__ U0, double *__restrict__ x,
+                                                    double *__restrict__ W, int variant) {
+    exp_finite_elem(gf, g1, U1, U0, x, W, variant, (int64_t)blockIdx.x * 256 + threadIdx.x);
 }
 
 // U~ = U1 + (1/3) T[U1 - U0]: eq. t1 at coarse nodes ((4 U1 - U0)/3), eq.
@@ -293,20 +317,10 @@ __device__ __forceinline__ int find_box(const ExpTask *__restrict__ t, int n, in
     return lo;
 }
 
-__global__ void __launch_bounds__(256) k_exp_finite_nodal_batch(const ExpTask *__restrict__ tasks, int n) {
+__global__ void __launch_bounds__(256) k_exp_finite_batch(const ExpTask *__restrict__ tasks, int n) {
     const int64_t b = blockIdx.x;
     const ExpTask &t = tasks[find_box(tasks, n, b, 0)];
-    const int64_t lb = b - t.b0[0];
-    const int64_t pl = lb / t.gx[0];
-    exp_finite_nodal_block(t.g1, t.U1, t.U0, t.V, t.variant, (int)(lb - pl * t.gx[0]), (int)(pl % t.gy[0]), (int)(pl / t.gy[0]));
-}
-
-__global__ void __launch_bounds__(256) k_exp_finite_interp_batch(const ExpTask *__restrict__ tasks, int n) {
-    const int64_t b = blockIdx.x;
-    const ExpTask &t = tasks[find_box(tasks, n, b, 1)];
-    const int64_t lb = b - t.b0[1];
-    const int64_t pl = lb / t.gx[1];
-    exp_finite_interp_block(t.gf, t.V, t.x, t.W, (int)(lb - pl * t.gx[1]), (int)(pl % t.gy[1]), (int)(pl / t.gy[1]));
+    exp_finite_elem(t.gf, t.g1, t.U1, t.U0, t.x, t.W, t.variant, (b - t.b0[0]) * 256 + threadIdx.x);
 }
 
 __global__ void __launch_bounds__(256) k_exp_true_batch(const ExpTask *__restrict__ tasks, int n) {
@@ -317,36 +331,38 @@ __global__ void __launch_bounds__(256) k_exp_true_batch(const ExpTask *__restric
     exp_true_block(t.gf, t.U1, t.U0, t.x, (int)(lb - pl * t.gx[1]), (int)(pl % t.gy[1]), (int)(pl / t.gy[1]));
 }
 
-// Block counts of a box: phase 0 over the level l-1 grid g1, phase 1 over the
-// fine grid gf (64 x 4 nodes per block).
-int exp_interp_gx(const Geom &gf) { return (gf.nx / 4 + 63) / 64; }
+// Block counts of a box: EXP_finite one thread per coarse element (256 per
+// block, [0]); EXP_true 63 node pairs x 4 rows per block ([1]).
 int exp_true_gx(const Geom &gf) { return (gf.nx / 2 + 1 + 62) / 63; }
 
 void exp_task_blocks(ExpTask &t, int kind) {
-    t.gx[0] = (t.g1.nx + 1 + 63) / 64;
-    t.gx[1] = kind == 0 ? exp_interp_gx(t.gf) : exp_true_gx(t.gf);
-    t.gy[0] = (t.g1.ny + 1 + 3) / 4;
-    t.gy[1] = (t.gf.ny + 1 + 3) / 4;
-    t.nb[0] = (int64_t)t.gx[0] * t.gy[0] * (t.g1.nz + 1);
-    t.nb[1] = (int64_t)t.gx[1] * t.gy[1] * (t.gf.nz + 1);
+    t.gx[0] = t.gy[0] = 0;
+    t.nb[0] = 0;
+    t.gx[1] = t.gy[1] = 0;
+    t.nb[1] = 0;
+    if (kind == 0) {
+        t.nb[0] = ((int64_t)(t.gf.nx / 4) * (t.gf.ny / 4) * (t.gf.nz / 4) + 255) / 256;
+    } else {
+        t.gx[1] = exp_true_gx(t.gf);
+        t.gy[1] = (t.gf.ny + 1 + 3) / 4;
+        t.nb[1] = (int64_t)t.gx[1] * t.gy[1] * (t.gf.nz + 1);
+    }
 }
 
-void launch_exp_finite_batch(const ExpTask *d_tasks, int n, int64_t nb0, int64_t nb1, hipStream_t s) {
-    if (nb0 > 0) hipLaunchKernelGGL(k_exp_finite_nodal_batch, dim3((unsigned)nb0), dim3(64, 4), 0, s, d_tasks, n);
-    if (nb1 > 0) hipLaunchKernelGGL(k_exp_finite_interp_batch, dim3((unsigned)nb1), dim3(64, 4), 0, s, d_tasks, n);
+void launch_exp_finite_batch(const ExpTask *d_tasks, int n, int64_t nb, hipStream_t s) {
+    if (nb > 0) hipLaunchKernelGGL(k_exp_finite_batch, dim3((unsigned)nb), dim3(256), 0, s, d_tasks, n);
 }
 
 void launch_exp_true_batch(const ExpTask *d_tasks, int n, int64_t nb1, hipStream_t s) {
     if (nb1 > 0) hipLaunchKernelGGL(k_exp_true_batch, dim3((unsigned)nb1), dim3(64, 4), 0, s, d_tasks, n);
 }
 
-void launch_exp_finite(const Geom &gf, const Geom &g1, const double *U1, const double *U0, double *V, double *x,
-                       double *W, int variant, hipStream_t s) {
-    const dim3 blk(64, 4);
-    const dim3 g1grid((g1.nx + 1 + 63) / 64, (g1.ny + 1 + 3) / 4, g1.nz + 1);
-    hipLaunchKernelGGL(k_exp_finite_nodal, g1grid, blk, 0, s, g1, U1, U0, V, variant);
-    const dim3 gfgrid(exp_interp_gx(gf), (gf.ny + 1 + 3) / 4, gf.nz + 1);
-    hipLaunchKernelGGL(k_exp_finite_interp, gfgrid, blk, 0, s, gf, V, x, W);
+void launch_exp_finite(const Geom &gf, const Geom &g1, const double *U1, const double *U0, double *x, double *W,
+                       int variant, hipStream_t s) {
+    const int64_t ne = (int64_t)(gf.nx / 4) * (gf.ny / 4) * (gf.nz / 4);
+    if (ne <= 0) return;
+    hipLaunchKernelGGL(k_exp_finite, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s, gf, g1, U1, U0, x, W,
+                       variant);
 }
 
 // Zero the row padding (i > nx) of up to four node arrays of a level; the JCG
