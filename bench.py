@@ -55,7 +55,12 @@ def algorithmic_bytes(kind, n, e, n1, n0, iters=0):
     elements of the level; n1, n0 nodes of the two coarser levels; iters JCG
     iterations inside one persistent launch)."""
     if kind == 0:
-        return 8 * (6 * n + e)          # read r, p_old, x, beta; write p, q, x
+        # read r, p_old, x, beta; write p, q, x -- the first iteration has no
+        # p_old and no x update (read r, beta; write p, q): the mean over the
+        # iters launches of one solve
+        if iters <= 0:
+            return 8 * (6 * n + e)
+        return 8 * ((3 * n + e) + (iters - 1) * (6 * n + e)) / iters
     if kind == 1:
         return 8 * 4 * n                # read r, q, 1/D; write r
     if kind == 2:
@@ -70,9 +75,12 @@ def algorithmic_bytes(kind, n, e, n1, n0, iters=0):
         return 4 * 4 * n
     if kind == 7:
         # init: read x, F, 1/D, beta, write r; per iteration: read r, 1/D, x,
-        # p_old, write x, p (own-node pass), read p, beta, write q (stencil),
-        # read r, q, 1/D, write r; final x update: read x, p, write x
-        return 8 * ((4 * n + e) + iters * (12 * n + e) + 3 * n)
+        # p_old, write x, p (own-node pass; the first iteration reads neither
+        # x nor p_old and writes no x), read p, beta, write q (stencil), read
+        # r, q, 1/D, write r; final x update: read x, p, write x
+        if iters <= 0:
+            return 8 * (4 * n + e)
+        return 8 * ((4 * n + e) + (9 * n + e) + (iters - 1) * (12 * n + e) + 3 * n)
     return 0
 
 
