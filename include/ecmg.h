@@ -126,7 +126,8 @@ typedef struct {
     int32_t timing;            /* 1 = time kernels with HIP events (ecmg_kernel_times)   */
     void *hip_stream;          /* hipStream_t to order all work on; NULL = own stream    */
     int64_t persistent_nodes;  /* grids of at most this many nodes run the whole JCG loop
-                                  in one persistent launch; 0 = never, -1 = default     */
+                                  in one persistent launch; 0 = never, -1 = default
+                                  (300,000; 2,400,000 in the serving loop)             */
     int64_t dsolve_dense_max;  /* ecmg_solve: DSOLVE levels with at most this many free
                                   nodes (capped at 8192) are solved with an explicit
                                   inverse of A_FF, built on the first solve (Cholesky,

@@ -62,8 +62,11 @@ struct ecmg_ctx {
     double *dstage = nullptr;       // device staging
     int64_t stage_n = 0;
     int KZ = 32;
-    // persistent JCG for grids of at most persist_max nodes
-    int64_t persist_max = 2400000;
+    int kz_target = 512;                       // tiled stencil: blocks aimed for per launch
+    // persistent JCG for grids of at most persist_max nodes (larger ones: the
+    // tiled passes, whose kernel boundaries synchronise more cheaply than the
+    // persistent kernel's device-wide barriers once a grid fills the chip)
+    int64_t persist_max = 300000;
     int persist_blocks = 0;                    // co-resident workgroups (0 = unavailable)
     int persist_seglen = 0;                    // persistent kernel: nodes per thread along z (0 = by size)
     int persist_nwg = 256;                     // persistent kernel: most workgroups per task
@@ -332,7 +335,7 @@ static int rec_flush(ecmg_ctx *c, int iter_limit) {
 static StencilArgs<double> stencil_args(ecmg_ctx *c, Level &L) {
     StencilArgs<double> a{};
     a.g = L.g;
-    a.KZ = stencil_kz(L.g, c->KZ);
+    a.KZ = stencil_kz(L.g, c->KZ, c->kz_target);
     stencil_blocks(L.g, a.KZ, &a.ntx, &a.nty, &a.nkz);
     a.beta = L.beta;
     for (int f = 0; f < 6; ++f) a.alpha[f] = L.alpha[f];
@@ -693,6 +696,7 @@ int ecmg_create(const ecmg_options *opt, ecmg_ctx **out) {
     c->device = dev;
     c->opt = o;
     if (const char *kz = std::getenv("ECMG_KZ")) c->KZ = std::max(1, std::atoi(kz));
+    if (const char *kt = std::getenv("ECMG_KZ_TARGET")) c->kz_target = std::max(1, std::atoi(kt));
     if (const char *v = std::getenv("ECMG_PERSIST_SEG")) c->persist_seglen = std::max(1, std::atoi(v));
     if (const char *v = std::getenv("ECMG_PERSIST_NWG")) c->persist_nwg = std::max(1, std::atoi(v));
     if (const char *v = std::getenv("ECMG_BATCH_NPW")) c->batch_npw = std::max(64, std::atoi(v));
@@ -843,7 +847,7 @@ int ecmg_setup(ecmg_ctx *c, const ecmg_problem *p) {
         for (int l = 0; l < p->levels; ++l) {
             Geom g = make_geom(p, l, lo);
             int a, b, d;
-            pn = std::max<int64_t>(pn, 2 * (int64_t)stencil_blocks(g, stencil_kz(g, c->KZ), &a, &b, &d));
+            pn = std::max<int64_t>(pn, 2 * (int64_t)stencil_blocks(g, stencil_kz(g, c->KZ, c->kz_target), &a, &b, &d));
             pn = std::max<int64_t>(pn, 2 * passB_blocks(g.nnodes));
         }
         c->partials_n = pn;
@@ -1696,6 +1700,9 @@ int ecmg_server_create(const ecmg_options *opt, size_t hbm_budget_bytes, ecmg_se
     S->opt.keep_w = 0;
     S->opt.timing = 0;
     S->opt.dsolve_dense_max = 0;       // DSOLVE levels run in the shared queue launches
+    // coarse levels of all active requests share one queue launch: the
+    // persistent form pays off up to larger grids there
+    if (S->opt.persistent_nodes < 0) S->opt.persistent_nodes = 2400000;
     S->budget = hbm_budget_bytes;
     if (S->opt.hip_stream) {
         S->stream = (hipStream_t)S->opt.hip_stream;

@@ -162,7 +162,8 @@ struct Ctx;
 
 // ---- launchers (kernels.hip / extrap.hip / setup.hip) ---------------------------
 int stencil_blocks(const Geom &g, int KZ, int *ntx, int *nty, int *nkz);
-int stencil_kz(const Geom &g, int kz_max);
+// planes per z-chunk of the tiled stencil: about target_blocks blocks, at most kz_max
+int stencil_kz(const Geom &g, int kz_max, int target_blocks);
 
 template <typename T>
 void launch_stencil(int mode, const StencilArgs<T> &a, hipStream_t s);

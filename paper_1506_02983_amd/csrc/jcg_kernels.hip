@@ -590,12 +590,12 @@ int stencil_blocks(const Geom &g, int KZ, int *ntx, int *nty, int *nkz) {
     return (*ntx) * (*nty) * (*nkz);
 }
 
-int stencil_kz(const Geom &g, int kz_max) {
+int stencil_kz(const Geom &g, int kz_max, int target_blocks) {
     // Planes per z-chunk: long chunks amortise the two halo planes, but small
     // grids need short chunks so that enough blocks run concurrently (the
     // planes of one chunk are processed in sequence by one block).
     const int64_t tiles = (int64_t)((g.sx + TX - 1) / TX) * ((g.sy + TYT - 1) / TYT);
-    int64_t kz = tiles * (g.nz + 1) / 2048;
+    int64_t kz = tiles * (g.nz + 1) / std::max(1, target_blocks);
     if (kz < 1) kz = 1;
     if (kz > kz_max) kz = kz_max;
     return (int)kz;
