@@ -62,7 +62,7 @@ struct ecmg_ctx {
     double *dstage = nullptr;       // device staging
     int64_t stage_n = 0;
     int KZ = 32;
-    int kz_target = 512;                       // tiled stencil: blocks aimed for per launch
+    int kz_target = 1024;                      // tiled stencil: blocks aimed for per launch
     // persistent JCG for grids of at most persist_max nodes (larger ones: the
     // tiled passes, whose kernel boundaries synchronise more cheaply than the
     // persistent kernel's device-wide barriers once a grid fills the chip)

@@ -17,8 +17,10 @@ namespace ecmg {
 // A block of TX x TY threads owns a TX x (TY*RY) tile of an x-y node plane and
 // marches through KZ planes in z.  Lanes run along x (one 64-wide wavefront per
 // row: coalesced, each z-plane contiguous in HBM); each wave handles RY rows.
+// 64 x 8 tiles of 512 threads: two blocks share a CU, so one computes while the
+// other waits at its per-plane barrier for the next plane's loads.
 #ifndef ECMG_TILE_TY
-#define ECMG_TILE_TY 16
+#define ECMG_TILE_TY 8
 #endif
 #ifndef ECMG_TILE_RY
 #define ECMG_TILE_RY 1
@@ -32,6 +34,10 @@ constexpr int RY = ECMG_TILE_RY;
 constexpr int TYT = TY * RY;          // tile height in nodes
 constexpr int NT = TX * TY;           // threads per block
 constexpr int PF = ECMG_PREFETCH;     // z-steps between issuing a plane's loads and using them
+// waves per SIMD the stencil kernel is compiled for: 4 x 64 lanes x 4 SIMDs =
+// 1024 threads per CU, one 1024-thread block or two 512-thread blocks (caps
+// registers at 128 per lane)
+constexpr int STENCIL_WAVES_PER_EU = 4;
 constexpr int NXCD = 8;               // MI355X: 8 XCDs, each with its own L2
 
 // Geometry of one level, passed to kernels by value.

@@ -165,7 +165,7 @@ __device__ __forceinline__ T robin_term(const Geom &g, int face, const T *al, in
 // ---------------------------------------------------------------------------
 
 template <typename T, int MODE>
-__global__ void __launch_bounds__(NT) k_stencil(const StencilArgs<T> a) {
+__global__ void __launch_bounds__(NT, STENCIL_WAVES_PER_EU) k_stencil(const StencilArgs<T> a) {
     // Rolling LDS buffers: 4 node planes and 3 element layers, so the plane
     // being filled never aliases the three planes being read and one barrier per
     // z-step suffices.
