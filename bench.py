@@ -55,16 +55,16 @@ def algorithmic_bytes(kind, n, e, n1, n0, iters=0):
     elements of the level; n1, n0 nodes of the two coarser levels; iters JCG
     iterations inside one persistent launch)."""
     if kind == 0:
-        # read r, p_old, x, beta; write p, q, x -- the first iteration has no
-        # p_old and no x update (read r, beta; write p, q): the mean over the
-        # iters launches of one solve
+        # read r, p_old, x, beta; write p, q, x -- the first iteration reads
+        # p_0 (stored by init) and beta and writes q: the mean over the iters
+        # launches of one solve
         if iters <= 0:
             return 8 * (6 * n + e)
-        return 8 * ((3 * n + e) + (iters - 1) * (6 * n + e)) / iters
+        return 8 * ((2 * n + e) + (iters - 1) * (6 * n + e)) / iters
     if kind == 1:
         return 8 * 4 * n                # read r, q, 1/D; write r
     if kind == 2:
-        return 8 * (4 * n + e)          # read x, F, 1/D, beta; write r
+        return 8 * (5 * n + e)          # read x, F, 1/D, beta; write r, p_0 = D^-1 r
     if kind == 3:
         return 8 * (n + n1 + n0)        # write x; read u_{l-1}, u_{l-2} (the W copy is off when timed)
     if kind == 4:

@@ -364,7 +364,8 @@ static int jcg_chunks(ecmg_ctx *c, int l, const StencilArgs<T> &a, const PassBAr
         done_iters = c->sc_host->iter;
         for (int t = 0; t < chunk; ++t) {
             CHK(rec_begin(c, l, kind_a, done_iters + t, &slot));
-            launch_stencil<T>(MODE_PASSA, a, c->stream);
+            // iteration 0 from the p_0 init stored, when it did
+            launch_stencil<T>((a.p_init && done_iters + t == 0) ? MODE_PASSA0 : MODE_PASSA, a, c->stream);
             CHK(rec_end(c, slot));
             CHK(rec_begin(c, l, kind_b, done_iters + t, &slot));
             launch_passB<T>(b, c->stream);
@@ -483,6 +484,7 @@ static int run_jcg(ecmg_ctx *c, int l, double tol_abs, int max_iter, int fixed, 
     a.x = L.x;
     a.p0 = c->p0;
     a.p1 = c->p1;
+    a.p_init = 1;
     size_t slot = 0;
     CHK(rec_begin(c, l, 2, 0, &slot));
     launch_stencil<double>(MODE_INIT, a, c->stream);

@@ -97,6 +97,8 @@ struct StencilArgs {
     T *p0, *p1;                       // pass A: search directions (ping-pong)
     JcgScalars *sc;
     double *partials;                 // per-block partial sums (2 per block)
+    int p_init;                       // init also stores p_0 = D^-1 r into p1, and pass A's
+                                      // iteration 0 (MODE_PASSA0) reads it there
 };
 
 template <typename T>
@@ -131,7 +133,7 @@ struct PersistentTask {
 };
 
 // Modes of the tiled stencil kernel.
-enum { MODE_APPLY = 0, MODE_INIT = 1, MODE_PASSA = 2 };
+enum { MODE_APPLY = 0, MODE_INIT = 1, MODE_PASSA = 2, MODE_PASSA0 = 3 };
 
 // ---- host-side level and context -------------------------------------------------
 // kernel classes timed per level: 0 pass A, 1 pass B, 2 JCG init, 3 EXP_finite,

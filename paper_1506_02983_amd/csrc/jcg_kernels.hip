@@ -161,7 +161,7 @@ __device__ __forceinline__ T robin_term(const Geom &g, int face, const T *al, in
 
 // ---------------------------------------------------------------------------
 // tiled stencil kernel: MODE_APPLY (q = A v), MODE_INIT (r = F - A x, r.z, r.r),
-// MODE_PASSA (fused JCG pass A)
+// MODE_PASSA (fused JCG pass A), MODE_PASSA0 (its iteration 0 from a stored p_0)
 // ---------------------------------------------------------------------------
 
 template <typename T, int MODE>
@@ -187,14 +187,17 @@ __global__ void __launch_bounds__(NT, STENCIL_WAVES_PER_EU) k_stencil(const Sten
     const int k0 = bz * a.KZ;
     const int k1 = min(k0 + a.KZ, g.nz + 1);
 
+    // MODE_PASSA0: pass A of iteration 0 when init has stored p_0 = D^-1 r_0
+    // in p1: the stencil input is p_0 itself (no r, 1/D loads, no p store)
+    constexpr bool PA = MODE == MODE_PASSA || MODE == MODE_PASSA0;
     bool first = true;
     T alpha_prev = 0, betak = 0;
     const T *pin = a.p0;
     T *pout = a.p1;
-    if (MODE == MODE_PASSA) {
+    if (PA) {
         const JcgScalars *sc = a.sc;
         if (sc->done) return;                     // uniform over the grid
-        const int it = sc->iter;
+        const int it = MODE == MODE_PASSA0 ? 0 : sc->iter;
         first = (it == 0);
         alpha_prev = (T)sc->alpha;
         betak = (T)sc->beta;
@@ -246,7 +249,9 @@ __global__ void __launch_bounds__(NT, STENCIL_WAVES_PER_EU) k_stencil(const Sten
         va = vb = vc = 0;
         if (o < 0 || kk < 0 || kk > g.nz) return;
         const int64_t id = (int64_t)o + sxy * kk;
-        if (MODE == MODE_PASSA) {
+        if (MODE == MODE_PASSA0) {
+            va = pout[id];
+        } else if (MODE == MODE_PASSA) {
             va = a.dinv[id];
             vb = a.r[id];
             if (!first) vc = pin[id];
@@ -266,7 +271,7 @@ __global__ void __launch_bounds__(NT, STENCIL_WAVES_PER_EU) k_stencil(const Sten
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
             S.ea[r] = S.eb[r] = 0;
-            if (MODE == MODE_APPLY || off[r] < 0 || k < 0 || k > g.nz) continue;
+            if (MODE == MODE_APPLY || MODE == MODE_PASSA0 || off[r] < 0 || k < 0 || k > g.nz) continue;
             const int64_t id = (int64_t)off[r] + sxy * k;
             if (MODE == MODE_PASSA) {
                 if (!first) S.ea[r] = a.x[id];
@@ -282,7 +287,7 @@ __global__ void __launch_bounds__(NT, STENCIL_WAVES_PER_EU) k_stencil(const Sten
             const T z = va * vb;
             return first ? z : z + betak * vc;
         }
-        return va;
+        return va;                                // apply / init: v; MODE_PASSA0: p_0
     };
     auto vslot = [](int k) { return (k + 4) & 3; };
     auto bslot = [](int k) { return (k + 3) % 3; };
@@ -385,14 +390,15 @@ __global__ void __launch_bounds__(NT, STENCIL_WAVES_PER_EU) k_stencil(const Sten
                 const T rv = dir ? (T)0 : xa_cur[r] - q;
                 a.r[id] = rv;
                 const T z = xb_cur[r] * rv;
+                if (a.p_init) a.p1[id] = z;           // p_0 for MODE_PASSA0
                 acc0 += (double)rv * (double)z;
                 acc1 += (double)rv * (double)rv;
             } else {
                 const T pc = sv[s1][lj][li];
                 const T qv = dir ? (T)0 : q;
-                pout[id] = pc;
+                if (MODE == MODE_PASSA) pout[id] = pc;
                 a.q[id] = qv;
-                if (!first) a.x[id] = xa_cur[r] + alpha_prev * pold_cur[r];
+                if (MODE == MODE_PASSA && !first) a.x[id] = xa_cur[r] + alpha_prev * pold_cur[r];
                 acc0 += (double)pc * (double)qv;
             }
         }
@@ -424,7 +430,7 @@ __global__ void __launch_bounds__(NT, STENCIL_WAVES_PER_EU) k_stencil(const Sten
 template <int MODE>
 __global__ void __launch_bounds__(NTF) k_stencil_finish(JcgScalars *sc, const double *__restrict__ partials, int nb) {
     __shared__ double red[2][NTF / 64];
-    if (MODE == MODE_PASSA && sc->done) return;
+    if (MODE != MODE_INIT && sc->done) return;
     double tot[2] = {0.0, 0.0};
     for (int b = threadIdx.x; b < nb; b += NTF) {
         tot[0] += partials[2 * (int64_t)b];
@@ -610,7 +616,8 @@ void launch_stencil(int mode, const StencilArgs<T> &a, hipStream_t s) {
         hipLaunchKernelGGL((k_stencil<T, MODE_INIT>), dim3(nb), dim3(NT), 0, s, a);
         hipLaunchKernelGGL(k_stencil_finish<MODE_INIT>, dim3(1), dim3(NTF), 0, s, a.sc, (const double *)a.partials, nb);
     } else {
-        hipLaunchKernelGGL((k_stencil<T, MODE_PASSA>), dim3(nb), dim3(NT), 0, s, a);
+        if (mode == MODE_PASSA0) hipLaunchKernelGGL((k_stencil<T, MODE_PASSA0>), dim3(nb), dim3(NT), 0, s, a);
+        else hipLaunchKernelGGL((k_stencil<T, MODE_PASSA>), dim3(nb), dim3(NT), 0, s, a);
         hipLaunchKernelGGL(k_stencil_finish<MODE_PASSA>, dim3(1), dim3(NTF), 0, s, a.sc, (const double *)a.partials, nb);
     }
 }
