@@ -10,8 +10,8 @@ per second of wall time of that step.
 Prints one JSON line.  Kernel durations for the roofline come from HIP events
 recorded by the library on its own stream around each launch inside the timed
 region; algorithmic bytes per launch follow the per-node traffic model of each
-kernel.  The CPU baseline times the oracle on a bounded sample
-of the same workload (fewer levels) on the host cores.
+kernel (algorithmic_bytes below).  The CPU baseline times the oracle on a
+bounded sample of the same workload (fewer levels) on the host cores.
 """
 import argparse
 import hashlib

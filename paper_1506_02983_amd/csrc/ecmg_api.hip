@@ -330,7 +330,7 @@ static int rec_flush(ecmg_ctx *c, int iter_limit) {
 }
 
 // ---------------------------------------------------------------------------
-// JCG on one level (the loop of Algorithm 4, lines 7-9)
+// JCG on one level (the JCG loop of Algorithm 4)
 // ---------------------------------------------------------------------------
 static StencilArgs<double> stencil_args(ecmg_ctx *c, Level &L) {
     StencilArgs<double> a{};

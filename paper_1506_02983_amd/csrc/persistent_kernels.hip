@@ -1,4 +1,4 @@
-// Persistent JCG: the whole JCG loop of Algorithm 4 (lines 7-9) for one or
+// Persistent JCG: the whole JCG loop of Algorithm 4 for one or
 // many independent grids ("tasks") in a single cooperative launch.
 //
 // Small grids (the DSOLVE levels, coarse JCG levels, and the boxes of a
