@@ -197,18 +197,19 @@ void launch_exp_true(const Geom &gf, const double *U1, const double *U0, double 
 // One box of a batched EXP_finite (U1 = u_{l-1}, U0 = u_{l-2}, x and optional
 // W on level l) or EXP_true (U1 = u_l, U0 = u_{l-1}, result into x).  b0 / nb:
 // first flat block and block count of the box ([0] EXP_finite, [1] EXP_true);
-// gx / gy: EXP_true blocks along x and y (a block is 63 node pairs by 4 rows
-// of one z-plane).
+// gx / gy: EXP_true blocks along x and y (a block is 64 node pairs by 4 row
+// pairs marching up a chunk of coarse planes).
 struct ExpTask {
     Geom gf, g1;
     const double *U1, *U0;
     double *x, *W;
     int variant;
     int gx[2], gy[2];
+    int tkz;                          // EXP_true: coarse planes per block
     int64_t nb[2], b0[2];
 };
 // kind 0: EXP_finite (one thread per coarse element; blocks in nb[0], b0[0]),
-// 1: EXP_true (63 node pairs per 64-lane row block; nb[1], b0[1])
+// 1: EXP_true (64 x 4 node-pair columns per block; nb[1], b0[1])
 void exp_task_blocks(ExpTask &t, int kind);
 void launch_exp_finite_batch(const ExpTask *d_tasks, int n, int64_t nb, hipStream_t s);
 void launch_exp_true_batch(const ExpTask *d_tasks, int n, int64_t nb1, hipStream_t s);

@@ -30,6 +30,8 @@
 // same inputs with the same expression, so it is single-valued.
 #include "ecmg_internal.h"
 
+#include <algorithm>
+
 namespace ecmg {
 
 // 1-D quadratic Lagrange weights at natural coordinate t = a/2 - 1, a in 0..4,
@@ -244,64 +246,97 @@ __global__ void __launch_bounds__(256) k_exp_finite(const Geom gf, const Geom g1
 // U~ = U1 + (1/3) T[U1 - U0]: eq. t1 at coarse nodes ((4 U1 - U0)/3), eq.
 // chenlin at edge midpoints (U1 + (d_a + d_b)/6), and the mean of chenlin along
 // the 2 face diagonals (U1 + sum(4 d)/12) or the 4 space diagonals (U1 +
-// sum(8 d)/24) at face and body centres.  A thread takes a pair of fine nodes
-// (2p, 2p+1) of one row; the coarse differences d = U1 - U0 at the even x
-// positions of the 1, 2 or 4 contributing rows (row parities are uniform over
-// the wave) are loaded once per lane, and the odd node takes the difference at
-// 2p+2 from the next lane.  A wave covers 63 pairs: its last lane only supplies
-// that neighbour value.
+// sum(8 d)/24) at face and body centres, d = U1 - U0 at the coarse nodes.
+// A thread takes node pair p (fine x = 2p, 2p+1) of row pair J (fine y = 2J,
+// 2J+1) and marches up tkz coarse planes K (fine z = 2K, 2K+1): the 4 coarse
+// differences on the upper plane 2K+2 are carried to the next step as its
+// lower plane, so every input is read about once.  The last pair / row pair /
+// plane of the grid has only its even node.  tkz (at most 16) leaves about
+// 2048 blocks per launch: small grids do not march, large ones amortise the
+// re-read chunk boundary.
+
 __device__ __forceinline__ void exp_true_block(const Geom &gf, const double *__restrict__ U1,
-                                               const double *__restrict__ U0, double *__restrict__ Ut, int bx,
-                                               int by, int bz) {
-    const int lane = threadIdx.x;                         // one wave per row (blockDim.x == 64)
-    const int npair = gf.nx / 2 + 1;                      // pair p: nodes 2p and 2p + 1 <= nx
-    const int p = bx * 63 + lane;
-    const int j = by * 4 + threadIdx.y, k = bz;
-    if (j > gf.ny || k > gf.nz) return;                   // whole rows only: the shuffles below stay wave-wide
-    const int pc = min(p, npair - 1);                     // clamped for the loads
-    const int i0 = 2 * pc;
+                                               const double *__restrict__ U0, double *__restrict__ Ut, int tkz,
+                                               int bx, int by, int bz) {
+    const int NX1 = gf.nx / 2, NY1 = gf.ny / 2, NZ1 = gf.nz / 2;   // coarse elements per axis
+    const int p = bx * 64 + threadIdx.x, J = by * 4 + threadIdx.y;
+    if (p > NX1 || J > NY1) return;
+    const int K0 = bz * tkz, K1 = min(K0 + tkz, NZ1 + 1);
     const int64_t sx = gf.sx, sxy = (int64_t)gf.sx * gf.sy;
-    const int64_t cx = row_pitch(gf.nx / 2 + 1), cxy = cx * (gf.ny / 2 + 1);
-    const int64_t id = i0 + sx * j + sxy * k;
-    const bool has_odd = i0 + 1 <= gf.nx;
-    double u_e, u_o = 0.0;
-    if (has_odd) {
-        const double2 v = *(const double2 *)(U1 + id);    // i0 even, rows 16-byte aligned
-        u_e = v.x;
-        u_o = v.y;
-    } else {
-        u_e = U1[id];
-    }
-    const int oj = j & 1, ok = k & 1;
-    double se = 0.0, so = 0.0, c_own = 0.0;
-    for (int dk = 0; dk <= ok; ++dk) {
-        const int kk = k - ok + 2 * dk;
-        for (int dj = 0; dj <= oj; ++dj) {
-            const int jj = j - oj + 2 * dj;
-            const double c0 = U0[pc + cx * (jj >> 1) + cxy * (kk >> 1)];
-            const double d0 = U1[i0 + sx * jj + sxy * kk] - c0;
-            const double d2 = __shfl_down(d0, 1, 64);     // the difference at 2p + 2
-            c_own = c0;
-            se += d0;
-            so += d0 + d2;
+    const int64_t cx = row_pitch(NX1 + 1), cxy = cx * (NY1 + 1);
+    const bool hx = p < NX1, hy = J < NY1;                        // odd x node / odd row exist
+    const int p2 = min(p + 1, NX1), J2 = min(J + 1, NY1);          // clamped: used only where they exist
+    // coarse differences d at x = 2p (dx 0) and 2p + 2 (dx 1) of rows 2J (dj 0)
+    // and 2J + 2 (dj 1) on one coarse plane kc, and U0 at (p, J, kc)
+    auto dplane = [&](int kc, double (&d)[2][2], double &c00) {
+        const int64_t f = sxy * (2 * (int64_t)kc), c = cxy * (int64_t)kc;
+#pragma unroll
+        for (int dj = 0; dj < 2; ++dj) {
+            const int jj = dj ? J2 : J;
+            const int64_t fr = f + sx * (2 * (int64_t)jj), cr = c + cx * jj;
+            const double c0 = U0[cr + p];
+            if (dj == 0) c00 = c0;
+            d[dj][0] = U1[fr + 2 * p] - c0;
+            d[dj][1] = U1[fr + 2 * p2] - U0[cr + p2];
         }
-    }
-    if (lane == 63 || p >= npair) return;
-    const int ne = oj + ok;
-    double ve;
-    if (ne == 0) ve = (4.0 * u_e - c_own) / 3.0;
-    else ve = u_e + se / (ne == 1 ? 6.0 : 12.0);
-    if (has_odd) {
-        const double vo = u_o + so / (ne == 0 ? 6.0 : (ne == 1 ? 12.0 : 24.0));
-        *(double2 *)(Ut + id) = make_double2(ve, vo);
-    } else {
-        Ut[id] = ve;
+    };
+    double dlo[2][2], dhi[2][2], clo, chi;
+    dplane(K0, dlo, clo);
+    for (int K = K0; K < K1; ++K) {
+        const bool hz = K < NZ1;
+        if (hz) dplane(K + 1, dhi, chi);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            if (c == 1 && !hz) break;
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                if (b == 1 && !hy) break;
+                const int64_t id = 2 * p + sx * (2 * (int64_t)J + b) + sxy * (2 * (int64_t)K + c);
+                double u_e, u_o = 0.0;
+                if (hx) {
+                    const double2 v = *(const double2 *)(U1 + id);   // 2p even, rows 16-byte aligned
+                    u_e = v.x;
+                    u_o = v.y;
+                } else {
+                    u_e = U1[id];
+                }
+                // sums over the contributing coarse rows (planes outer, rows inner)
+                double se = 0.0, so = 0.0;
+#pragma unroll
+                for (int dk = 0; dk <= c; ++dk)
+#pragma unroll
+                    for (int dj = 0; dj <= b; ++dj) {
+                        const double d0 = dk ? dhi[dj][0] : dlo[dj][0];
+                        const double d2 = dk ? dhi[dj][1] : dlo[dj][1];
+                        se += d0;
+                        so += d0 + d2;
+                    }
+                const int ne = b + c;
+                double ve;
+                if (ne == 0) ve = (4.0 * u_e - clo) / 3.0;
+                else ve = u_e + se / (ne == 1 ? 6.0 : 12.0);
+                if (hx) {
+                    const double vo = u_o + so / (ne == 0 ? 6.0 : (ne == 1 ? 12.0 : 24.0));
+                    *(double2 *)(Ut + id) = make_double2(ve, vo);
+                } else {
+                    Ut[id] = ve;
+                }
+            }
+        }
+        if (hz) {
+#pragma unroll
+            for (int dj = 0; dj < 2; ++dj) {
+                dlo[dj][0] = dhi[dj][0];
+                dlo[dj][1] = dhi[dj][1];
+            }
+            clo = chi;
+        }
     }
 }
 
 __global__ void __launch_bounds__(256) k_exp_true(const Geom gf, const double *__restrict__ U1,
-                                                  const double *__restrict__ U0, double *__restrict__ Ut) {
-    exp_true_block(gf, U1, U0, Ut, blockIdx.x, blockIdx.y, blockIdx.z);
+                                                  const double *__restrict__ U0, double *__restrict__ Ut, int tkz) {
+    exp_true_block(gf, U1, U0, Ut, tkz, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 // ---------------------------------------------------------------------------
@@ -328,12 +363,20 @@ __global__ void __launch_bounds__(256) k_exp_true_batch(const ExpTask *__restric
     const ExpTask &t = tasks[find_box(tasks, n, b, 1)];
     const int64_t lb = b - t.b0[1];
     const int64_t pl = lb / t.gx[1];
-    exp_true_block(t.gf, t.U1, t.U0, t.x, (int)(lb - pl * t.gx[1]), (int)(pl % t.gy[1]), (int)(pl / t.gy[1]));
+    exp_true_block(t.gf, t.U1, t.U0, t.x, t.tkz, (int)(lb - pl * t.gx[1]), (int)(pl % t.gy[1]),
+                   (int)(pl / t.gy[1]));
 }
 
 // Block counts of a box: EXP_finite one thread per coarse element (256 per
-// block, [0]); EXP_true 63 node pairs x 4 rows per block ([1]).
-int exp_true_gx(const Geom &gf) { return (gf.nx / 2 + 1 + 62) / 63; }
+// block, [0]); EXP_true 64 node pairs x 4 row pairs x tkz coarse planes per
+// block ([1]).
+int exp_true_gx(const Geom &gf) { return (gf.nx / 2 + 1 + 63) / 64; }
+int exp_true_gy(const Geom &gf) { return (gf.ny / 2 + 1 + 3) / 4; }
+int exp_true_tkz(const Geom &gf) {
+    const int64_t t = (int64_t)exp_true_gx(gf) * exp_true_gy(gf) * (gf.nz / 2 + 1) / 2048;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(16, t));
+}
+int exp_true_gz(const Geom &gf, int tkz) { return (gf.nz / 2 + 1 + tkz - 1) / tkz; }
 
 void exp_task_blocks(ExpTask &t, int kind) {
     t.gx[0] = t.gy[0] = 0;
@@ -344,8 +387,9 @@ void exp_task_blocks(ExpTask &t, int kind) {
         t.nb[0] = ((int64_t)(t.gf.nx / 4) * (t.gf.ny / 4) * (t.gf.nz / 4) + 255) / 256;
     } else {
         t.gx[1] = exp_true_gx(t.gf);
-        t.gy[1] = (t.gf.ny + 1 + 3) / 4;
-        t.nb[1] = (int64_t)t.gx[1] * t.gy[1] * (t.gf.nz + 1);
+        t.gy[1] = exp_true_gy(t.gf);
+        t.tkz = exp_true_tkz(t.gf);
+        t.nb[1] = (int64_t)t.gx[1] * t.gy[1] * exp_true_gz(t.gf, t.tkz);
     }
 }
 
@@ -404,8 +448,9 @@ void launch_zero_pad_f32(const Geom &g, float *a, float *b, float *c, hipStream_
 }
 
 void launch_exp_true(const Geom &gf, const double *U1, const double *U0, double *Ut, hipStream_t s) {
-    const dim3 grid(exp_true_gx(gf), (gf.ny + 1 + 3) / 4, gf.nz + 1);
-    hipLaunchKernelGGL(k_exp_true, grid, dim3(64, 4), 0, s, gf, U1, U0, Ut);
+    const int tkz = exp_true_tkz(gf);
+    const dim3 grid(exp_true_gx(gf), exp_true_gy(gf), exp_true_gz(gf, tkz));
+    hipLaunchKernelGGL(k_exp_true, grid, dim3(64, 4), 0, s, gf, U1, U0, Ut, tkz);
 }
 
 }  // namespace ecmg
