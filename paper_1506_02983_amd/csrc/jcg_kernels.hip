@@ -48,6 +48,7 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 
 constexpr int NTF = 1024;              // threads of a one-block finishing kernel
 
+
 // 2-vector of T for 16-byte (double) / 8-byte (float) accesses
 template <typename T> struct Vec2;
 template <> struct Vec2<double> { using type = double2; };
@@ -87,6 +88,38 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double (*red)[NTHREAD
         }
     }
     __syncthreads();
+}
+
+// Sum over blocks b < nb of partials[2 b + i] (i < NV) by one block of NTF
+// threads: 8 independent loads in flight per thread, then a fixed-order
+// combination, so the total does not depend on timing.  Result in thread 0.
+template <int NV>
+__device__ __forceinline__ void sum_partials(const double *__restrict__ partials, int nb, double (&tot)[NV],
+                                             double (*red)[NTF / 64]) {
+    constexpr int U = 8;
+    double acc[U][NV];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int i = 0; i < NV; ++i) acc[u][i] = 0.0;
+    int b = threadIdx.x;
+    for (; b + (U - 1) * NTF < nb; b += U * NTF) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int i = 0; i < NV; ++i) acc[u][i] += partials[2 * (int64_t)(b + u * NTF) + i];
+    }
+    for (; b < nb; b += NTF)
+#pragma unroll
+        for (int i = 0; i < NV; ++i) acc[0][i] += partials[2 * (int64_t)b + i];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        double t = acc[0][i];
+#pragma unroll
+        for (int u = 1; u < U; ++u) t += acc[u][i];
+        tot[i] = t;
+    }
+    block_sum<NV, NTF>(tot, red);
 }
 
 // Two-stage deterministic reduction: every block stores its partials, the last
@@ -432,11 +465,13 @@ __global__ void __launch_bounds__(NTF) k_stencil_finish(JcgScalars *sc, const do
     __shared__ double red[2][NTF / 64];
     if (MODE != MODE_INIT && sc->done) return;
     double tot[2] = {0.0, 0.0};
-    for (int b = threadIdx.x; b < nb; b += NTF) {
-        tot[0] += partials[2 * (int64_t)b];
-        if (MODE == MODE_INIT) tot[1] += partials[2 * (int64_t)b + 1];
+    if (MODE == MODE_INIT) {
+        sum_partials<2>(partials, nb, tot, red);
+    } else {
+        double t1[1];
+        sum_partials<1>(partials, nb, t1, red);
+        tot[0] = t1[0];
     }
-    block_sum<2, NTF>(tot, red);
     if (threadIdx.x != 0) return;
     if (MODE == MODE_INIT) {
         sc->rho = tot[0];
@@ -520,12 +555,8 @@ __global__ void __launch_bounds__(NTB) k_passB(const PassBArgs<T> a) {
 __global__ void __launch_bounds__(NTF) k_passB_finish(JcgScalars *sc, const double *__restrict__ partials, int nb) {
     __shared__ double red[2][NTF / 64];
     if (sc->done) return;
-    double tot[2] = {0.0, 0.0};
-    for (int b = threadIdx.x; b < nb; b += NTF) {
-        tot[0] += partials[2 * (int64_t)b];
-        tot[1] += partials[2 * (int64_t)b + 1];
-    }
-    block_sum<2, NTF>(tot, red);
+    double tot[2];
+    sum_partials<2>(partials, nb, tot, red);
     if (threadIdx.x == 0) {
         const int it = sc->iter + 1;
         sc->iter = it;
