@@ -75,6 +75,13 @@ struct ecmg_ctx {
     PersistentTask *d_task = nullptr;          // device copy of one task
     unsigned *d_bar = nullptr;                 // barrier words + error flag
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // a solve enqueues the levels without waiting for them: per level, its
+    // final JCG scalars and persistent task (pinned; the stream copies them
+    // when it gets there) and a start / end event pair
+    JcgScalars *sc_lv = nullptr;
+    PersistentTask *task_lv = nullptr;
+    int lv_cap = 0;
+    std::vector<hipEvent_t> lv_ev;
     // kernel timing (options.timing)
     struct Rec { hipEvent_t a, b; int level, kind, iter; };
     std::vector<hipEvent_t> evpool;
@@ -313,12 +320,16 @@ static int rec_end(ecmg_ctx *c, size_t slot) {
     HIPCHK(c, hipEventRecord(c->recs[slot].b, c->stream));
     return ECMG_OK;
 }
-// fold the records of a finished section; launches with iter >= iter_limit did no work
-static int rec_flush(ecmg_ctx *c, int iter_limit) {
+// Fold the finished records.  A JCG pass launch (classes 0, 1, 5, 6) whose
+// iteration index is at or beyond its level's limit (the iterations the level
+// ran) found the `done` flag set and did no work; it is not counted.
+static bool rec_is_pass(int kind) { return kind == 0 || kind == 1 || kind == 5 || kind == 6; }
+static int rec_flush_levels(ecmg_ctx *c, const std::vector<int> &limit) {
     if (!c->opt.timing) return ECMG_OK;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     for (auto &r : c->recs) {
-        if (r.iter >= iter_limit) continue;
+        const int lim = r.level < (int)limit.size() ? limit[r.level] : 0;
+        if (rec_is_pass(r.kind) && r.iter >= lim) continue;
         float ms = 0.f;
         HIPCHK(c, hipEventElapsedTime(&ms, r.a, r.b));
         c->lv[r.level].kt_ms[r.kind] += ms;
@@ -327,6 +338,10 @@ static int rec_flush(ecmg_ctx *c, int iter_limit) {
     c->recs.clear();
     c->evnext = 0;
     return ECMG_OK;
+}
+// the same with one limit for every level
+static int rec_flush(ecmg_ctx *c, int iter_limit) {
+    return rec_flush_levels(c, std::vector<int>(std::max(c->nlev, 1), iter_limit));
 }
 
 // ---------------------------------------------------------------------------
@@ -347,21 +362,32 @@ static StencilArgs<double> stencil_args(ecmg_ctx *c, Level &L) {
 }
 
 // Enqueue JCG iterations (pass A, pass B) in chunks until the device sets
-// `done`: one status read per chunk; the chunk doubles up to 64 (fixed-
-// iteration mode enqueues all iterations at once).  Leaves the final scalars in
-// c->sc_host.  kind_a / kind_b name the timing classes.
+// `done`, with one status read after each chunk.  The first chunk follows the
+// init pass without a status read (if init already met the tolerance its
+// launches return at once); it is `hint` iterations (the count the level needed
+// last time, so a repeated solve usually needs one status read) or 2; later
+// chunks double from 2 up to 64.  Fixed-iteration mode enqueues all iterations
+// at once.  Leaves the final scalars in c->sc_host.  kind_a / kind_b name the
+// timing classes.
 template <typename T>
 static int jcg_chunks(ecmg_ctx *c, int l, const StencilArgs<T> &a, const PassBArgs<T> &b, JcgScalars *sc,
-                      int fixed, int kind_a, int kind_b) {
+                      int fixed, int kind_a, int kind_b, int hint) {
     int done_iters = 0;
-    int chunk = c->opt.chunk > 0 ? c->opt.chunk : 2;
+    int next = 2;
+    int chunk = c->opt.chunk > 0 ? c->opt.chunk : (hint > 0 ? hint : 2);
     if (fixed >= 0) chunk = std::max(fixed, 1);
     size_t slot = 0;
-    for (;;) {
-        HIPCHK(c, hipMemcpyAsync(c->sc_host, sc, sizeof(JcgScalars), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        if (c->sc_host->done) break;
-        done_iters = c->sc_host->iter;
+    for (bool first = true;; first = false) {
+        if (!first) {
+            HIPCHK(c, hipMemcpyAsync(c->sc_host, sc, sizeof(JcgScalars), hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            if (c->sc_host->done) break;
+            done_iters = c->sc_host->iter;
+            if (c->opt.chunk <= 0 && fixed < 0) {
+                chunk = next;
+                next = std::min(next * 2, 64);
+            }
+        }
         for (int t = 0; t < chunk; ++t) {
             CHK(rec_begin(c, l, kind_a, done_iters + t, &slot));
             // iteration 0 from the p_0 init stored, when it did
@@ -372,7 +398,6 @@ static int jcg_chunks(ecmg_ctx *c, int l, const StencilArgs<T> &a, const PassBAr
             CHK(rec_end(c, slot));
         }
         HIPCHK(c, hipGetLastError());
-        if (c->opt.chunk <= 0 && fixed < 0) chunk = std::min(chunk * 2, 64);
     }
     return ECMG_OK;
 }
@@ -440,7 +465,7 @@ static int run_jcg_mixed(ecmg_ctx *c, int l, double tol_abs, int max_iter, ecmg_
                            c->stream);
         CHK(rec_end(c, slot));
         HIPCHK(c, hipGetLastError());
-        CHK(jcg_chunks<float>(c, l, a32, b32, c->sc32, -1, 5, 6));
+        CHK(jcg_chunks<float>(c, l, a32, b32, c->sc32, -1, 5, 6, 0));
         const JcgScalars s = *c->sc_host;
         CHK(rec_begin(c, l, 9, 0, &slot));
         launch_mixed_update(L.g, L.x, rn, c->d32, c->p32a, c->p32b, c->sc32, c->stream);
@@ -473,7 +498,30 @@ static int run_jcg_mixed(ecmg_ctx *c, int l, double tol_abs, int max_iter, ecmg_
     return ECMG_OK;
 }
 
-static int run_jcg(ecmg_ctx *c, int l, double tol_abs, int max_iter, int fixed, ecmg_level_info *info) {
+// The level's results from its final JCG scalars s: iterations, relative
+// residual, status (breakdown / iteration cap reported as errors).
+static int jcg_result(ecmg_ctx *c, int l, const JcgScalars &s, int max_iter, bool keep_hint, ecmg_level_info *info) {
+    Level &L = c->lv[l];
+    if (info) {
+        info->iters = s.iter;
+        info->rre = (L.nf > 0) ? std::sqrt(s.rr) / L.nf : 0.0;
+        info->nf = L.nf;
+        info->status = (s.done == DONE_BREAKDOWN) ? ECMG_EBREAKDOWN
+                       : (s.done == DONE_MAXITER) ? ECMG_ENOTCONV : ECMG_OK;
+    }
+    if (s.done == DONE_BREAKDOWN) return fail(c, ECMG_EBREAKDOWN, "JCG breakdown on level %d (p.q = %g)", l, s.pq);
+    if (s.done == DONE_MAXITER)
+        return fail(c, ECMG_ENOTCONV, "JCG reached max_iter = %d on level %d (rre %g)", max_iter, l,
+                    std::sqrt(s.rr) / L.nf);
+    if (keep_hint && s.done == DONE_CONVERGED) L.last_iters = s.iter;
+    return ECMG_OK;
+}
+
+// Tiled JCG of level l, enqueued: init, the iterations (status reads only
+// between chunks), the last x update (the kernel checks whether one is
+// pending) and a copy of the final scalars into the level's pinned slot,
+// which holds them once the stream has passed it.
+static int enqueue_jcg(ecmg_ctx *c, int l, double tol_abs, int max_iter, int fixed) {
     Level &L = c->lv[l];
     launch_jcg_reset(c->sc, tol_abs, max_iter, fixed, c->stream);
     launch_zero_pad(L.g, c->r, c->q, c->p0, c->p1, c->stream);
@@ -499,29 +547,28 @@ static int run_jcg(ecmg_ctx *c, int l, double tol_abs, int max_iter, int fixed, 
     b.sc = c->sc;
     b.partials = c->partials;
 
-    CHK(jcg_chunks(c, l, a, b, c->sc, fixed, 0, 1));
-    const JcgScalars s = *c->sc_host;
-    if (s.pending) launch_final_x(L.g, L.x, c->p0, c->p1, c->sc, c->stream);
+    CHK(jcg_chunks(c, l, a, b, c->sc, fixed, 0, 1, fixed < 0 ? L.last_iters : 0));
+    launch_final_x(L.g, L.x, c->p0, c->p1, c->sc, c->stream);
     HIPCHK(c, hipGetLastError());
-    CHK(rec_flush(c, s.iter));
-    if (info) {
-        info->iters = s.iter;
-        info->rre = (L.nf > 0) ? std::sqrt(s.rr) / L.nf : 0.0;
-        info->nf = L.nf;
-        info->status = (s.done == DONE_BREAKDOWN) ? ECMG_EBREAKDOWN
-                       : (s.done == DONE_MAXITER) ? ECMG_ENOTCONV : ECMG_OK;
-    }
-    if (s.done == DONE_BREAKDOWN) return fail(c, ECMG_EBREAKDOWN, "JCG breakdown on level %d (p.q = %g)", l, s.pq);
-    if (s.done == DONE_MAXITER)
-        return fail(c, ECMG_ENOTCONV, "JCG reached max_iter = %d on level %d (rre %g)", max_iter, l,
-                    std::sqrt(s.rr) / L.nf);
+    HIPCHK(c, hipMemcpyAsync(c->sc_lv + l, c->sc, sizeof(JcgScalars), hipMemcpyDeviceToHost, c->stream));
     return ECMG_OK;
 }
 
-// Whole JCG loop of one level in one cooperative launch (small grids).
-static int run_jcg_persistent(ecmg_ctx *c, int l, double tol_abs, int max_iter, int fixed, ecmg_level_info *info) {
+static int run_jcg(ecmg_ctx *c, int l, double tol_abs, int max_iter, int fixed, ecmg_level_info *info) {
+    CHK(enqueue_jcg(c, l, tol_abs, max_iter, fixed));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const JcgScalars s = c->sc_lv[l];
+    CHK(rec_flush(c, s.iter));
+    return jcg_result(c, l, s, max_iter, fixed < 0, info);
+}
+
+// Whole JCG loop of one level in one cooperative launch (small grids),
+// enqueued: the task goes from the level's pinned slot to the device, the final
+// scalars come back into the level's scalar slot.
+static int enqueue_jcg_persistent(ecmg_ctx *c, int l, double tol_abs, int max_iter, int fixed) {
     Level &L = c->lv[l];
-    PersistentTask t{};
+    PersistentTask &t = c->task_lv[l];
+    t = PersistentTask{};
     t.g = L.g;
     t.beta = L.beta;
     for (int f = 0; f < 6; ++f) t.alpha[f] = L.alpha[f];
@@ -557,22 +604,16 @@ static int run_jcg_persistent(ecmg_ctx *c, int l, double tol_abs, int max_iter, 
     CHK(rec_begin(c, l, 7, 0, &slot));
     HIPCHK(c, launch_jcg_persistent(c->d_task, 1, t.nwg, c->stream));
     CHK(rec_end(c, slot));
-    HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(JcgScalars), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    const JcgScalars s = *c->sc_host;
-    CHK(rec_flush(c, 1));
-    if (info) {
-        info->iters = s.iter;
-        info->rre = (L.nf > 0) ? std::sqrt(s.rr) / L.nf : 0.0;
-        info->nf = L.nf;
-        info->status = (s.done == DONE_BREAKDOWN) ? ECMG_EBREAKDOWN
-                       : (s.done == DONE_MAXITER) ? ECMG_ENOTCONV : ECMG_OK;
-    }
-    if (s.done == DONE_BREAKDOWN) return fail(c, ECMG_EBREAKDOWN, "JCG breakdown on level %d", l);
-    if (s.done == DONE_MAXITER)
-        return fail(c, ECMG_ENOTCONV, "JCG reached max_iter = %d on level %d (rre %g)", max_iter, l,
-                    std::sqrt(s.rr) / L.nf);
+    HIPCHK(c, hipMemcpyAsync(c->sc_lv + l, c->sc, sizeof(JcgScalars), hipMemcpyDeviceToHost, c->stream));
     return ECMG_OK;
+}
+
+static int run_jcg_persistent(ecmg_ctx *c, int l, double tol_abs, int max_iter, int fixed, ecmg_level_info *info) {
+    CHK(enqueue_jcg_persistent(c, l, tol_abs, max_iter, fixed));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const JcgScalars s = c->sc_lv[l];
+    CHK(rec_flush(c, 1));
+    return jcg_result(c, l, s, max_iter, false, info);
 }
 
 static bool uses_persistent(const ecmg_ctx *c, int l) {
@@ -769,6 +810,9 @@ void ecmg_destroy(ecmg_ctx *c) {
     for (auto e : c->evpool) (void)hipEventDestroy(e);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->sc_lv) (void)hipHostFree(c->sc_lv);
+    if (c->task_lv) (void)hipHostFree(c->task_lv);
+    for (auto e : c->lv_ev) (void)hipEventDestroy(e);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -829,6 +873,23 @@ int ecmg_setup(ecmg_ctx *c, const ecmg_problem *p) {
     c->nlev = p->levels;
     for (int f = 0; f < 6; ++f) c->face_type[f] = p->face_type[f];
     c->lv.resize(p->levels);
+    if (c->lv_cap < p->levels) {
+        if (c->sc_lv) (void)hipHostFree(c->sc_lv);
+        if (c->task_lv) (void)hipHostFree(c->task_lv);
+        c->sc_lv = nullptr;
+        c->task_lv = nullptr;
+        c->lv_cap = 0;
+        if (hipHostMalloc((void **)&c->sc_lv, sizeof(JcgScalars) * p->levels, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void **)&c->task_lv, sizeof(PersistentTask) * p->levels, hipHostMallocDefault) !=
+                hipSuccess)
+            return fail(c, ECMG_ENOMEM, "pinned host allocation of %d level slots failed", p->levels);
+        c->lv_cap = p->levels;
+    }
+    while (c->lv_ev.size() < 2 * (size_t)p->levels) {
+        hipEvent_t e;
+        HIPCHK(c, hipEventCreate(&e));
+        c->lv_ev.push_back(e);
+    }
     // scratch for the finest level and reduction partials
     {
         double lo[3];
@@ -1060,42 +1121,85 @@ static int run_dsolve_dense(ecmg_ctx *c, int l, ecmg_level_info *info) {
     return ECMG_OK;
 }
 
+// Algorithm 4 over all levels.  Every level is enqueued without waiting for
+// the one before (the stream orders them); the host waits only inside the
+// tiled JCG loop (one status read per chunk) and once at the end, when the
+// levels' results come out of their pinned slots.  A mixed-precision level
+// drives its outer refinement from the host, so the levels before it are
+// settled first.
 static int solve_impl(ecmg_ctx *c, double rel_tol, const int32_t *fixed, ecmg_level_info *info) {
     if (!c) return fail(nullptr, ECMG_EINVAL, "ctx is NULL");
     if (!c->ready) return fail(c, ECMG_ESTATE, "ecmg_solve before ecmg_setup");
     if (!fixed && !(rel_tol >= 0.0)) return fail(c, ECMG_EINVAL, "rel_tol = %g must be >= 0", rel_tol);
-    int worst = ECMG_OK;
-    for (int l = 0; l < c->nlev; ++l) {
+    const int n = c->nlev;
+    std::vector<ecmg_level_info> li(n);
+    std::vector<char> deferred(n, 0);        // JCG results still in the level's slot
+    std::vector<int> cap(n, 0);              // their iteration caps
+    std::vector<int> limit(n, 1 << 30);      // timing: iterations each level ran
+    int worst = ECMG_OK, settled = 0;
+    auto note = [&](int rc) {
+        if (rc != ECMG_OK && worst == ECMG_OK) worst = rc;
+    };
+    // wait for the stream; results and times of levels settled .. upto-1
+    auto settle = [&](int upto) -> int {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (int k = settled; k < upto; ++k) {
+            if (deferred[k]) {
+                int rc = jcg_result(c, k, c->sc_lv[k], cap[k], fixed == nullptr, &li[k]);
+                if (k < 2 && rc == ECMG_ENOTCONV) rc = ECMG_OK;   // DSOLVE: the iterate at the cap is kept
+                note(rc);
+                limit[k] = li[k].iters;
+            }
+            float ms = 0.f;
+            HIPCHK(c, hipEventElapsedTime(&ms, c->lv_ev[2 * k], c->lv_ev[2 * k + 1]));
+            li[k].ms = ms;
+        }
+        settled = upto;
+        return rec_flush_levels(c, limit);
+    };
+    for (int l = 0; l < n; ++l) {
         Level &L = c->lv[l];
-        ecmg_level_info li{};
-        li.level = l;
-        li.nx = L.g.nx;
-        li.ny = L.g.ny;
-        li.nz = L.g.nz;
-        HIPCHK(c, hipEventRecord(c->ev0, c->stream));
-        int rc;
+        li[l].level = l;
+        li[l].nx = L.g.nx;
+        li[l].ny = L.g.ny;
+        li[l].nz = L.g.nz;
+        HIPCHK(c, hipEventRecord(c->lv_ev[2 * l], c->stream));
+        int rc = ECMG_OK;
+        double tol = rel_tol * L.nf;
+        int max_iter = c->opt.max_iter, fx = fixed ? fixed[l] : -1;
+        bool jcg = true;
         if (l < 2) {
             CHK(dense_prepare(c, l));
             if (L.dense == 1) {
-                rc = run_dsolve_dense(c, l, &li);
+                rc = run_dsolve_dense(c, l, &li[l]);
+                jcg = false;
             } else {
                 launch_zero_free(L.g, L.x, c->stream);
-                rc = run_level_jcg(c, l, c->opt.dsolve_tol * L.nf, 100000, -1, &li);
-                if (rc == ECMG_ENOTCONV) rc = ECMG_OK;  // DSOLVE: the iterate at the cap is kept
+                tol = c->opt.dsolve_tol * L.nf;
+                max_iter = 100000;
+                fx = -1;
             }
         } else {
             CHK(do_exp_finite(c, l));
-            rc = run_level_jcg(c, l, rel_tol * L.nf, c->opt.max_iter, fixed ? fixed[l] : -1, &li);
+            if (uses_mixed(c, l) && fx < 0) {
+                CHK(settle(l));
+                rc = run_jcg_mixed(c, l, tol, max_iter, &li[l]);
+                jcg = false;
+            }
         }
-        HIPCHK(c, hipEventRecord(c->ev1, c->stream));
-        HIPCHK(c, hipEventSynchronize(c->ev1));
-        float ms = 0.f;
-        HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
-        li.ms = ms;
-        if (info) info[l] = li;
+        if (jcg) {
+            rc = uses_persistent(c, l) ? enqueue_jcg_persistent(c, l, tol, max_iter, fx)
+                                       : enqueue_jcg(c, l, tol, max_iter, fx);
+            deferred[l] = 1;
+            cap[l] = max_iter;
+        }
+        HIPCHK(c, hipEventRecord(c->lv_ev[2 * l + 1], c->stream));
         if (rc == ECMG_EDEVICE) return rc;
-        if (rc != ECMG_OK && worst == ECMG_OK) worst = rc;
+        note(rc);
     }
+    CHK(settle(n));
+    if (info)
+        for (int l = 0; l < n; ++l) info[l] = li[l];
     c->solved = true;
     return worst;
 }

@@ -161,6 +161,7 @@ struct Level {
     float *alpha32[6] = {};
     float *dinv32 = nullptr;
     double nf = 0.0;                  // ||f_h||_2 of the stopping test
+    int last_iters = -1;              // JCG iterations of the last converged solve (first chunk)
     // timing accumulators per kernel class
     double kt_ms[NKIND] = {};
     int64_t kt_n[NKIND] = {};
