@@ -180,8 +180,10 @@ int ecmg_solve_fixed(ecmg_ctx *ctx, const int32_t *iters, ecmg_level_info *info)
 
 /* EXP_true (Section 4.2.1, eqs. t1 and chenlin; face and body centres as the
  * mean along their diagonals): U~_l from u_l and u_{l-1}, for 1 <= level <
- * levels (-1 = finest).  host_out: NULL, or a node array of the level that
- * receives U~_l. */
+ * levels (-1 = finest).  host_out: NULL (the call returns once the work is
+ * enqueued on the library stream; later calls on the context are ordered
+ * after it), or a node array of the level that receives U~_l (the call
+ * returns when it is filled). */
 int ecmg_extrapolate(ecmg_ctx *ctx, int32_t level, double *host_out);
 
 /* Algorithm 4 for n independent problems at once (each context set up with
@@ -289,7 +291,8 @@ int ecmg_plan_bytes(const ecmg_problem *problem, int32_t precision, size_t *byte
  * to FP32), 9 = mixed-precision update x += ||r|| d),
  * out[0] = total milliseconds and out[1] = launches that did work since the
  * last ecmg_reset_kernel_times.  Measured with HIP events on the library's
- * stream around each launch. */
+ * stream around each launch; both calls wait for the stream to finish the
+ * launches they account. */
 int ecmg_kernel_times(ecmg_ctx *ctx, int32_t level, int32_t k, double out[2]);
 int ecmg_reset_kernel_times(ecmg_ctx *ctx);
 

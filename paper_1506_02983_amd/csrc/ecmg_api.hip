@@ -299,8 +299,12 @@ static const int64_t kBatchPoints = (int64_t)1 << 23;
 // ---------------------------------------------------------------------------
 // timing records
 // ---------------------------------------------------------------------------
+static int rec_flush(ecmg_ctx *c, int iter_limit);
 static int rec_begin(ecmg_ctx *c, int level, int kind, int iter, size_t *slot) {
     if (!c->opt.timing) return ECMG_OK;
+    // bound the pending records (a long run of calls that never reach a
+    // solve's final wait or a kernel-time query)
+    if (c->recs.size() >= 65536) CHK(rec_flush(c, 1 << 30));
     if (c->evnext + 2 > c->evpool.size()) {
         for (int t = 0; t < 256; ++t) {
             hipEvent_t e;
@@ -1453,8 +1457,7 @@ static int check_level(ecmg_ctx *c, int32_t *level, int min_level) {
 
 int ecmg_extrapolate(ecmg_ctx *c, int32_t level, double *host_out) {
     CHK(check_level(c, &level, 1));
-    CHK(do_exp_true(c, level));
-    CHK(rec_flush(c, 1));
+    CHK(do_exp_true(c, level));                   // its timing record is folded later (no wait here)
     Level &L = c->lv[level];
     if (host_out) {
         HIPCHK(c, copy_out(L.g, host_out, L.Ut, c->r, c->stream));
@@ -1592,6 +1595,7 @@ int ecmg_level_dims(ecmg_ctx *c, int32_t level, int64_t n[3]) {
 int ecmg_kernel_times(ecmg_ctx *c, int32_t level, int32_t k, double out[2]) {
     CHK(check_level(c, &level, 0));
     if (k < 0 || k >= NKIND || !out) return fail(c, ECMG_EINVAL, "bad kernel class %d", k);
+    CHK(rec_flush(c, 1 << 30));                   // records still pending (EXP_true, EXP_finite)
     out[0] = c->lv[level].kt_ms[k];
     out[1] = (double)c->lv[level].kt_n[k];
     return ECMG_OK;
@@ -1599,6 +1603,7 @@ int ecmg_kernel_times(ecmg_ctx *c, int32_t level, int32_t k, double out[2]) {
 
 int ecmg_reset_kernel_times(ecmg_ctx *c) {
     if (!c) return fail(nullptr, ECMG_EINVAL, "ctx is NULL");
+    CHK(rec_flush(c, 1 << 30));                   // pending records belong before the reset
     for (auto &L : c->lv)
         for (int k = 0; k < NKIND; ++k) {
             L.kt_ms[k] = 0.0;
