@@ -52,8 +52,10 @@ typedef __attribute__((address_space(1))) double gdouble;
 __device__ __forceinline__ void task_barrier(const PersistentTask &t, int nwg, unsigned gen, int *s_err) {
     __syncthreads();
     if (nwg > 1 && threadIdx.x == 0) {
-        __threadfence();
-        atomicAdd(t.bar, 1u);
+        // release on arrival (the workgroup's writes, ordered before this by
+        // the barrier above, become visible device-wide), acquire after the
+        // wait: one L2 write-back and one invalidate per barrier
+        __hip_atomic_fetch_add(t.bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         const unsigned target = gen * (unsigned)nwg;
         long n = 0;
         while ((int)(__hip_atomic_load(t.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) < 0) {
@@ -65,7 +67,7 @@ __device__ __forceinline__ void task_barrier(const PersistentTask &t, int nwg, u
                 break;
             }
         }
-        __threadfence();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
 }
