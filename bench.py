@@ -259,6 +259,10 @@ def main():
     ap.add_argument("--host-fields", action="store_true", help="sample fields with numpy on the host")
     ap.add_argument("--cpu-levels", type=int, default=6, help="levels of the oracle CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--autotune", type=int, default=1, choices=(0, 1),
+                    help="time the JCG configurations of every level after the warm-up (untimed) and keep the "
+                         "fastest; 0 = the built-in heuristics")
+    ap.add_argument("--tune-cache", default=None, help="JSON tuning cache to merge the choices into")
     ap.add_argument("--no-errors", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run one device copy kernel (read BYTES, write BYTES) and exit: the reference "
@@ -304,7 +308,17 @@ def main():
     print("bench: setup %.2f s (%s fields)" % (setup_s, "host" if args.host_fields else "device"),
           file=sys.stderr, flush=True)
 
-    for _ in range(args.warmup):
+    for _ in range(max(args.warmup, 1 if args.autotune else 0)):
+        s.solve(eps)
+        s.extrapolate(L, out=False)
+    tuned = None
+    if args.autotune:
+        # each level timed over its iteration count in the warm-up solve
+        t0 = time.perf_counter()
+        tuned = s.autotune(iters=0, cache=args.tune_cache)
+        print("bench: autotune %.2f s: %s" % (time.perf_counter() - t0, ", ".join(
+            "L%d %s" % (r["level"], ("kz=%d" % r["kz"]) if r["path"] == 0 else "seg=%d nwg=%d" % (r["seg"], r["nwg"]))
+            for r in tuned)), file=sys.stderr, flush=True)
         s.solve(eps)
         s.extrapolate(L, out=False)
     torch.cuda.synchronize()
@@ -437,7 +451,9 @@ def main():
         "vs_baseline": None, "dtype": "f64", "data": "synthetic (closed-form manufactured solution)",
         "config": {"workload": desc, "levels": problem.levels, "finest_elements": list(n), "finest_nodes": nodes,
                    "eps": eps, "precision": "fp64",
-                   "interp": "lagrange27" if args.interp else "serendipity20", "parallelism": "single GPU"},
+                   "interp": "lagrange27" if args.interp else "serendipity20", "parallelism": "single GPU",
+                   "jcg_configuration": "autotuned" if args.autotune else "built-in"},
+        "autotune": tuned,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "jcg_hbm_gbs_finest": jcg_gbs,

@@ -46,6 +46,7 @@ extern "C" {
 #define ECMG_EDEVICE     -5   /* a HIP runtime call failed                         */
 #define ECMG_ESTATE      -6   /* call out of order (e.g. solve before setup)       */
 #define ECMG_ECALLBACK   -7   /* a field callback returned nonzero                 */
+#define ECMG_ENOENT      -8   /* no tuning cache file, or no entry for the level   */
 
 /* ---- face types (Section 1: Neumann is Robin with alpha = 0) ---------- */
 #define ECMG_DIRICHLET 0
@@ -133,7 +134,26 @@ typedef struct {
                                   inverse of A_FF, built on the first solve (Cholesky,
                                   rocSOLVER) and applied as one matrix-vector product;
                                   larger ones, and 0, use FP64 JCG (default 8192)        */
+    int32_t autotune;          /* 0 (default): built-in JCG configuration per level; 1:
+                                  ecmg_setup applies the choices the tuning cache holds
+                                  for the hierarchy's JCG levels (a missing file or
+                                  entry leaves the built-in choice)                     */
+    const char *tune_cache;    /* JSON tuning cache path (see ecmg_autotune); NULL = the
+                                  ECMG_TUNE_CACHE environment variable, if set; the
+                                  string is read during ecmg_create only                */
 } ecmg_options;
+
+/* One JCG level's configuration chosen by the autotuner. */
+typedef struct {
+    int32_t level;             /* level (>= 2); -1 from ecmg_tune_lookup                */
+    int32_t path;              /* 0: tiled passes, 1: persistent kernel                  */
+    int32_t kz;                /* tiled: planes per z-chunk of a stencil block           */
+    int32_t seg;               /* persistent: nodes per thread segment (1, 2 or 4)       */
+    int32_t nwg;               /* persistent: most workgroups                            */
+    int32_t candidates;        /* configurations timed                                   */
+    double us_default;         /* microseconds per JCG iteration, built-in configuration */
+    double us_best;            /* microseconds per JCG iteration, chosen configuration   */
+} ecmg_tune_result;
 
 /* Per-level report (Algorithm 4 and the "Iters"/"RRe" columns of Section 5). */
 typedef struct {
@@ -295,6 +315,29 @@ int ecmg_plan_bytes(const ecmg_problem *problem, int32_t precision, size_t *byte
  * launches they account. */
 int ecmg_kernel_times(ecmg_ctx *ctx, int32_t level, int32_t k, double out[2]);
 int ecmg_reset_kernel_times(ecmg_ctx *ctx);
+
+/* Autotuner of the JCG configuration (how the loop of Algorithm 4 runs on each
+ * level; the iterates are those of the same recurrence whatever is chosen, up
+ * to summation order).  After ecmg_setup: for every JCG level (>= 2), times
+ * `iters` fixed JCG iterations (<= 0: the level's iteration count in the last
+ * converged solve on ctx, capped at 4000, or 8 before any) from the level's
+ * current iterate,
+ * which is restored, under the built-in configuration and each candidate
+ * (tiled passes with z-chunks of 4, 8, 16, 32 or 64 planes; the persistent
+ * kernel with segments of 2 or 4 nodes and at most 128 or 256 workgroups, for
+ * grids of at most 20,000,000 nodes), keeps the fastest for later solves on
+ * ctx and, if cache_path (or options.tune_cache, or $ECMG_TUNE_CACHE) names a
+ * file, merges the choices into that JSON cache keyed by precision and
+ * elements per axis (the file is replaced atomically).  out: NULL or
+ * levels - 2 entries.  Allocates one scratch array of the largest JCG level
+ * for the duration of the call; synchronous. */
+int ecmg_autotune(ecmg_ctx *ctx, int32_t iters, const char *cache_path, ecmg_tune_result *out);
+
+/* Host only (no device needed): the choice the tuning cache at `path` holds for
+ * a JCG level of nx x ny x nz elements at `precision`.  ECMG_ENOENT if the file
+ * or the entry does not exist, ECMG_EINVAL if the file is not a tuning cache. */
+int ecmg_tune_lookup(const char *path, int32_t precision, int32_t nx, int32_t ny, int32_t nz,
+                     ecmg_tune_result *out);
 
 /* The last error message of ctx (or of the calling thread when ctx is NULL). */
 const char *ecmg_last_error(const ecmg_ctx *ctx);

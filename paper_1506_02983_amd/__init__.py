@@ -22,7 +22,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libecmg.so")
 
-OK, EINVAL, ENOMEM, ENOTCONV, EBREAKDOWN, EDEVICE, ESTATE, ECALLBACK = 0, -1, -2, -3, -4, -5, -6, -7
+OK, EINVAL, ENOMEM, ENOTCONV, EBREAKDOWN, EDEVICE, ESTATE, ECALLBACK, ENOENT = 0, -1, -2, -3, -4, -5, -6, -7, -8
 DIRICHLET, ROBIN = 0, 1
 FP64, MIXED = 0, 1
 SERENDIPITY20, LAGRANGE27 = 0, 1
@@ -30,7 +30,7 @@ VEC_U, VEC_W, VEC_UTILDE, VEC_F, VEC_DINV, VEC_NONE = 0, 1, 2, 3, 4, -1
 K_PASSA, K_PASSB, K_INIT, K_EXPF, K_EXPT, K_PASSA32, K_PASSB32, K_PERSIST, K_MIXSTART, K_MIXUPDATE = range(10)
 
 _STATUS = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", ENOTCONV: "ENOTCONV", EBREAKDOWN: "EBREAKDOWN",
-           EDEVICE: "EDEVICE", ESTATE: "ESTATE", ECALLBACK: "ECALLBACK"}
+           EDEVICE: "EDEVICE", ESTATE: "ESTATE", ECALLBACK: "ECALLBACK", ENOENT: "ENOENT"}
 
 HOST_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
@@ -53,7 +53,19 @@ class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("interp", ctypes.c_int32),
                 ("keep_w", ctypes.c_int32), ("inner_tol", ctypes.c_double), ("dsolve_tol", ctypes.c_double),
                 ("chunk", ctypes.c_int32), ("timing", ctypes.c_int32), ("hip_stream", ctypes.c_void_p),
-                ("persistent_nodes", ctypes.c_int64), ("dsolve_dense_max", ctypes.c_int64)]
+                ("persistent_nodes", ctypes.c_int64), ("dsolve_dense_max", ctypes.c_int64),
+                ("autotune", ctypes.c_int32), ("tune_cache", ctypes.c_char_p)]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("level", ctypes.c_int32), ("path", ctypes.c_int32), ("kz", ctypes.c_int32), ("seg", ctypes.c_int32),
+                ("nwg", ctypes.c_int32), ("candidates", ctypes.c_int32), ("us_default", ctypes.c_double),
+                ("us_best", ctypes.c_double)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["path"] = "persistent" if self.path == 1 else "tiled"
+        return d
 
 
 class LevelInfo(ctypes.Structure):
@@ -72,7 +84,8 @@ EXPORTS = ["ecmg_default_options", "ecmg_create", "ecmg_setup", "ecmg_solve", "e
            "ecmg_device_view", "ecmg_norms", "ecmg_level_dims", "ecmg_plan_bytes", "ecmg_kernel_times",
            "ecmg_reset_kernel_times", "ecmg_last_error", "ecmg_destroy", "ecmg_solve_batch",
            "ecmg_extrapolate_batch", "ecmg_server_create", "ecmg_server_submit", "ecmg_server_step",
-           "ecmg_server_poll", "ecmg_server_stats", "ecmg_server_reset_stats", "ecmg_server_destroy"]
+           "ecmg_server_poll", "ecmg_server_stats", "ecmg_server_reset_stats", "ecmg_server_destroy",
+           "ecmg_autotune", "ecmg_tune_lookup"]
 
 _lib = None
 
@@ -126,10 +139,25 @@ def load_library(path: str = LIB_PATH):
     L.ecmg_server_reset_stats.argtypes = [P]
     L.ecmg_server_destroy.argtypes = [P]
     L.ecmg_server_destroy.restype = None
+    L.ecmg_autotune.argtypes = [P, i32, ctypes.c_char_p, P]
+    L.ecmg_tune_lookup.argtypes = [ctypes.c_char_p, i32, i32, i32, i32, P]
     for name in EXPORTS:
         getattr(L, name)
     _lib = L
     return L
+
+
+def tune_lookup(path: str, n, precision: int = FP64) -> Optional[dict]:
+    """The choice a tuning cache holds for a JCG level of n = (nx, ny, nz)
+    elements (host only; None if there is none)."""
+    L = load_library()
+    r = TuneResult()
+    rc = L.ecmg_tune_lookup(path.encode(), int(precision), int(n[0]), int(n[1]), int(n[2]), ctypes.byref(r))
+    if rc == ENOENT:
+        return None
+    if rc != OK:
+        raise EcmgError(rc, (L.ecmg_last_error(None) or b"").decode())
+    return r.as_dict()
 
 
 class EcmgError(RuntimeError):
@@ -235,7 +263,7 @@ class Solver:
     def __init__(self, precision: int = FP64, interp: int = SERENDIPITY20, keep_w: bool = True,
                  max_iter: int = 20000, dsolve_tol: float = 1e-14, inner_tol: float = 1e-4,
                  chunk: int = 0, timing: bool = False, stream=None, persistent_nodes: int = -1,
-                 dsolve_dense_max: Optional[int] = None):
+                 dsolve_dense_max: Optional[int] = None, autotune: int = 0, tune_cache: Optional[str] = None):
         self.L = load_library()
         o = Options()
         self.L.ecmg_default_options(ctypes.byref(o))
@@ -245,6 +273,8 @@ class Solver:
         o.persistent_nodes = persistent_nodes
         if dsolve_dense_max is not None:
             o.dsolve_dense_max = dsolve_dense_max
+        o.autotune = int(autotune)
+        o.tune_cache = tune_cache.encode() if tune_cache else None
         self.opt = o
         h = ctypes.c_void_p()
         self._check(self.L.ecmg_create(ctypes.byref(o), ctypes.byref(h)), None)
@@ -285,6 +315,14 @@ class Solver:
 
     def _infos(self):
         return (LevelInfo * self.levels)()
+
+    def autotune(self, iters: int = 8, cache: Optional[str] = None) -> List[dict]:
+        """Time the candidate JCG configurations of every JCG level (after setup),
+        keep the fastest for later solves, merge them into the JSON cache.
+        iters <= 0 times each level over its iteration count in the last solve."""
+        out = (TuneResult * max(self.levels - 2, 1))()
+        self._check(self.L.ecmg_autotune(self.h, int(iters), cache.encode() if cache else None, out))
+        return [r.as_dict() for r in out[:max(self.levels - 2, 0)]]
 
     def solve(self, rel_tol: float, allow_fail: bool = False) -> List[dict]:
         info = self._infos()
@@ -422,7 +460,7 @@ class Server:
         o = Options()
         self.L.ecmg_default_options(ctypes.byref(o))
         for k, v in opts.items():
-            setattr(o, k, v)
+            setattr(o, k, v.encode() if isinstance(v, str) else v)
         self.h = ctypes.c_void_p()
         rc = self.L.ecmg_server_create(ctypes.byref(o), int(hbm_budget_bytes), ctypes.byref(self.h))
         if rc != OK:

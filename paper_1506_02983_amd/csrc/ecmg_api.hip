@@ -73,6 +73,8 @@ struct ecmg_ctx {
     int queue_blocks = 0;                      // co-resident workgroups of the queue kernel
     int batch_npw = 8192;                      // batched solves: nodes per workgroup of a box
     PersistentTask *d_task = nullptr;          // device copy of one task
+    std::string tune_cache;                    // tuning cache path ("" = none)
+    std::string device_name;                   // "<arch> <CUs> CUs", recorded with tuning choices
     unsigned *d_bar = nullptr;                 // barrier words + error flag
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     // a solve enqueues the levels without waiting for them: per level, its
@@ -348,13 +350,15 @@ static int rec_flush(ecmg_ctx *c, int iter_limit) {
     return rec_flush_levels(c, std::vector<int>(std::max(c->nlev, 1), iter_limit));
 }
 
+static int apply_tune_cache(ecmg_ctx *c);
+
 // ---------------------------------------------------------------------------
 // JCG on one level (the JCG loop of Algorithm 4)
 // ---------------------------------------------------------------------------
 static StencilArgs<double> stencil_args(ecmg_ctx *c, Level &L) {
     StencilArgs<double> a{};
     a.g = L.g;
-    a.KZ = stencil_kz(L.g, c->KZ, c->kz_target);
+    a.KZ = (L.tune_path == 0 && L.tune_kz > 0) ? std::min(L.tune_kz, L.g.nz + 1) : stencil_kz(L.g, c->KZ, c->kz_target);
     stencil_blocks(L.g, a.KZ, &a.ntx, &a.nty, &a.nkz);
     a.beta = L.beta;
     for (int f = 0; f < 6; ++f) a.alpha[f] = L.alpha[f];
@@ -595,12 +599,13 @@ static int enqueue_jcg_persistent(ecmg_ctx *c, int l, double tol_abs, int max_it
     // segments spread small grids over more lanes, longer ones save halo
     // loads), at most persist_nwg workgroups (every barrier costs more with
     // more of them)
-    const int seg = c->persist_seglen > 0 ? c->persist_seglen : (L.g.nreal < 131072 ? 2 : 4);
+    const bool tuned = L.tune_path == 1 && L.tune_seg > 0 && L.tune_nwg > 0;
+    const int seg = tuned ? L.tune_seg : c->persist_seglen > 0 ? c->persist_seglen : (L.g.nreal < 131072 ? 2 : 4);
     t.seglen = seg >= 4 ? 4 : (seg >= 2 ? 2 : 1);         // the kernel's instantiations
     const int64_t nseg = (L.g.nz + t.seglen) / t.seglen;
     const int64_t units = (int64_t)(L.g.nx + 1) * (L.g.ny + 1) * nseg;
     t.nwg = (int)std::max<int64_t>(
-        1, std::min<int64_t>({(units + PERSIST_NTP - 1) / PERSIST_NTP, (int64_t)c->persist_nwg,
+        1, std::min<int64_t>({(units + PERSIST_NTP - 1) / PERSIST_NTP, (int64_t)(tuned ? L.tune_nwg : c->persist_nwg),
                               (int64_t)c->persist_blocks}));
     HIPCHK(c, hipMemsetAsync(c->d_bar, 0, 32 * sizeof(unsigned), c->stream));
     HIPCHK(c, hipMemcpyAsync(c->d_task, &t, sizeof(t), hipMemcpyHostToDevice, c->stream));
@@ -620,11 +625,19 @@ static int run_jcg_persistent(ecmg_ctx *c, int l, double tol_abs, int max_iter, 
     return jcg_result(c, l, s, max_iter, false, info);
 }
 
+// the persistent kernel can run the grid: co-resident workgroups exist and its
+// 32-bit indices reach every node and element
+static bool persist_possible(const ecmg_ctx *c, const Geom &g) {
+    return c->persist_blocks > 0 && g.nnodes < ((int64_t)1 << 31) && (int64_t)g.nx * g.ny * g.nz < ((int64_t)1 << 31);
+}
+
+// The level's JCG path: the autotuned one if there is one, else the persistent
+// kernel up to persist_max nodes.
 static bool uses_persistent(const ecmg_ctx *c, int l) {
-    const Geom &g = c->lv[l].g;
-    // the persistent kernel indexes with 32-bit integers
-    return c->persist_blocks > 0 && g.nreal <= c->persist_max && g.nnodes < ((int64_t)1 << 31) &&
-           (int64_t)g.nx * g.ny * g.nz < ((int64_t)1 << 31);
+    const Level &L = c->lv[l];
+    if (L.tune_path == 0) return false;
+    if (L.tune_path == 1) return persist_possible(c, L.g);
+    return persist_possible(c, L.g) && L.g.nreal <= c->persist_max;
 }
 
 // Mixed precision applies to JCG levels (not DSOLVE) solved by the tiled
@@ -715,6 +728,8 @@ void ecmg_default_options(ecmg_options *o) {
     o->hip_stream = nullptr;
     o->persistent_nodes = -1;
     o->dsolve_dense_max = DSOLVE_DENSE_LIMIT;
+    o->autotune = 0;
+    o->tune_cache = nullptr;
 }
 
 int ecmg_create(const ecmg_options *opt, ecmg_ctx **out) {
@@ -742,6 +757,10 @@ int ecmg_create(const ecmg_options *opt, ecmg_ctx **out) {
     ecmg_ctx *c = new ecmg_ctx();
     c->device = dev;
     c->opt = o;
+    if (o.tune_cache) c->tune_cache = o.tune_cache;
+    else if (const char *tc = std::getenv("ECMG_TUNE_CACHE")) c->tune_cache = tc;
+    c->opt.tune_cache = nullptr;              // the caller's string is not kept
+    c->device_name = std::string(prop.gcnArchName) + " " + std::to_string(prop.multiProcessorCount) + " CUs";
     if (const char *kz = std::getenv("ECMG_KZ")) c->KZ = std::max(1, std::atoi(kz));
     if (const char *kt = std::getenv("ECMG_KZ_TARGET")) c->kz_target = std::max(1, std::atoi(kt));
     if (const char *v = std::getenv("ECMG_PERSIST_SEG")) c->persist_seglen = std::max(1, std::atoi(v));
@@ -1034,6 +1053,7 @@ int ecmg_setup(ecmg_ctx *c, const ecmg_problem *p) {
         HIPCHK(c, hipStreamSynchronize(c->stream));
         L.nf = std::sqrt(c->hres[1]);
     }
+    if (c->opt.autotune == 1) CHK(apply_tune_cache(c));
     c->ready = true;
     c->solved = false;
     return ECMG_OK;
@@ -1121,6 +1141,71 @@ static int run_dsolve_dense(ecmg_ctx *c, int l, ecmg_level_info *info) {
         info->rre = 0.0;
         info->nf = L.nf;
         info->status = ECMG_OK;
+    }
+    return ECMG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner: per-level JCG configuration, timed on the device, cached in JSON
+// ---------------------------------------------------------------------------
+// partial-sum slots for at least n values (grown when a tuned z-chunk length
+// gives a stencil pass more blocks than the built-in one)
+static int ensure_partials(ecmg_ctx *c, int64_t n) {
+    if (n <= c->partials_n) return ECMG_OK;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    dfree(c->partials);
+    c->partials = nullptr;
+    c->partials_n = 0;
+    CHK(dalloc_n(c, &c->partials, n));
+    c->partials_n = n;
+    return ECMG_OK;
+}
+
+// the configuration the built-in rules give level l
+static TuneEntry builtin_choice(const ecmg_ctx *c, int l) {
+    const Level &L = c->lv[l];
+    TuneEntry e;
+    if (persist_possible(c, L.g) && L.g.nreal <= c->persist_max) {
+        const int seg = c->persist_seglen > 0 ? c->persist_seglen : (L.g.nreal < 131072 ? 2 : 4);
+        e.path = 1;
+        e.seg = seg >= 4 ? 4 : (seg >= 2 ? 2 : 1);
+        e.nwg = c->persist_nwg;
+    } else {
+        e.path = 0;
+        e.kz = stencil_kz(L.g, c->KZ, c->kz_target);
+    }
+    return e;
+}
+
+// level l runs configuration e from now on (path -1: the built-in rules)
+static int apply_choice(ecmg_ctx *c, int l, int path, int kz, int seg, int nwg) {
+    Level &L = c->lv[l];
+    if (path == 1 && !persist_possible(c, L.g)) path = -1;
+    L.tune_path = path;
+    L.tune_kz = path == 0 ? std::max(1, std::min(kz, L.g.nz + 1)) : 0;
+    L.tune_seg = path == 1 ? (seg >= 4 ? 4 : (seg >= 2 ? 2 : 1)) : 0;
+    L.tune_nwg = path == 1 ? std::max(1, nwg) : 0;
+    if (path == 0) {
+        int a, b, d;
+        CHK(ensure_partials(c, 2 * (int64_t)stencil_blocks(L.g, L.tune_kz, &a, &b, &d)));
+    }
+    return ECMG_OK;
+}
+
+// the cached choices for this hierarchy's JCG levels (ecmg_setup, autotune = 1)
+static int apply_tune_cache(ecmg_ctx *c) {
+    if (c->tune_cache.empty()) return ECMG_OK;
+    std::map<std::string, TuneEntry> entries;
+    std::string dev, err;
+    const int rc = tune_cache_read(c->tune_cache, &dev, &entries, &err);
+    if (rc == ECMG_ENOENT) return ECMG_OK;        // nothing tuned yet: built-in choices
+    if (rc != ECMG_OK) return fail(c, rc, "%s", err.c_str());
+    for (int l = 2; l < c->nlev; ++l) {
+        const Level &L = c->lv[l];
+        auto it = entries.find(tune_key(c->opt.precision, L.g.nx, L.g.ny, L.g.nz));
+        if (it == entries.end()) continue;
+        const TuneEntry &e = it->second;
+        CHK(apply_choice(c, l, e.path, e.kz, e.seg, e.nwg));
     }
     return ECMG_OK;
 }
@@ -1612,6 +1697,136 @@ int ecmg_reset_kernel_times(ecmg_ctx *c) {
     return ECMG_OK;
 }
 
+int ecmg_autotune(ecmg_ctx *c, int32_t iters, const char *cache_path, ecmg_tune_result *out) {
+    if (!c) return fail(nullptr, ECMG_EINVAL, "ctx is NULL");
+    if (!c->ready) return fail(c, ECMG_ESTATE, "ecmg_autotune before ecmg_setup");
+    const int fixed_iters = iters;
+    const std::string path = cache_path ? std::string(cache_path) : c->tune_cache;
+    std::map<std::string, TuneEntry> entries;
+    if (!path.empty()) {
+        std::string dev, err;
+        // an unreadable or foreign file is replaced; entries of another device are dropped
+        if (tune_cache_read(path, &dev, &entries, &err) != ECMG_OK || dev != c->device_name) entries.clear();
+    }
+    int64_t maxn = 0;
+    for (int l = 2; l < c->nlev; ++l) maxn = std::max<int64_t>(maxn, c->lv[l].g.nnodes);
+    double *save = nullptr;
+    CHK(dalloc_n(c, &save, std::max<int64_t>(maxn, 1)));
+    struct Cand { int path, kz, seg, nwg; };
+    int rc = ECMG_OK;
+    for (int l = 2; l < c->nlev && rc == ECMG_OK; ++l) {
+        Level &L = c->lv[l];
+        const size_t bytes = sizeof(double) * (size_t)L.g.nnodes;
+        if (hipMemcpyAsync(save, L.x, bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess) {
+            rc = fail(c, ECMG_EDEVICE, "autotune: copy of level %d failed", l);
+            break;
+        }
+        // the run length: as asked, else the level's iterations in the last solve, else 8
+        iters = fixed_iters > 0 ? fixed_iters : (L.last_iters > 0 ? std::min(L.last_iters, 4000) : 8);
+        std::vector<Cand> cands{{-1, 0, 0, 0}};   // the built-in configuration first
+        for (int kz : {4, 8, 16, 32, 64})
+            if (kz <= L.g.nz + 1) cands.push_back({0, kz, 0, 0});
+        if (persist_possible(c, L.g) && L.g.nreal <= 20000000)
+            for (int seg : {2, 4})
+                for (int nwg : {128, 256})
+                    if (nwg <= c->persist_blocks) cands.push_back({1, 0, seg, nwg});
+        double best = 0.0, us_default = 0.0;
+        int bi = -1;
+        for (size_t ci = 0; ci < cands.size() && rc == ECMG_OK; ++ci) {
+            const Cand &cd = cands[ci];
+            if ((rc = apply_choice(c, l, cd.path, cd.kz, cd.seg, cd.nwg)) != ECMG_OK) break;
+            double us = -1.0;
+            for (int rep = 0; rep < 2; ++rep) {       // one untimed run, one timed
+                if (hipMemcpyAsync(L.x, save, bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
+                    hipEventRecord(c->ev0, c->stream) != hipSuccess) {
+                    rc = fail(c, ECMG_EDEVICE, "autotune: restore of level %d failed", l);
+                    break;
+                }
+                ecmg_level_info li{};
+                const int jr = run_level_jcg(c, l, 0.0, iters + 1, iters, &li);
+                if (jr == ECMG_EDEVICE) {
+                    rc = jr;
+                    break;
+                }
+                float ms = 0.f;
+                if (hipEventRecord(c->ev1, c->stream) != hipSuccess || hipEventSynchronize(c->ev1) != hipSuccess ||
+                    hipEventElapsedTime(&ms, c->ev0, c->ev1) != hipSuccess) {
+                    rc = fail(c, ECMG_EDEVICE, "autotune: timing of level %d failed", l);
+                    break;
+                }
+                us = (jr == ECMG_OK && li.iters == iters) ? 1e3 * ms / iters : -1.0;   // breakdown: no time
+            }
+            if (rc != ECMG_OK) break;
+            if (ci == 0) us_default = us;
+            if (us > 0.0 && (bi < 0 || us < best)) {
+                best = us;
+                bi = (int)ci;
+            }
+        }
+        if (rc == ECMG_OK) {
+            // keep the fastest (as a concrete configuration); none timed: built-in
+            TuneEntry e = builtin_choice(c, l);
+            if (bi > 0) {
+                e.path = cands[bi].path;
+                e.kz = cands[bi].kz;
+                e.seg = cands[bi].seg;
+                e.nwg = cands[bi].nwg;
+            }
+            e.us_default = us_default;
+            e.us_best = bi >= 0 ? best : us_default;
+            rc = apply_choice(c, l, bi > 0 ? e.path : -1, e.kz, e.seg, e.nwg);
+            if (bi >= 0) entries[tune_key(c->opt.precision, L.g.nx, L.g.ny, L.g.nz)] = e;
+            if (out) {
+                ecmg_tune_result &r = out[l - 2];
+                r.level = l;
+                r.path = e.path;
+                r.kz = e.kz;
+                r.seg = e.seg;
+                r.nwg = e.nwg;
+                r.candidates = (int32_t)cands.size();
+                r.us_default = e.us_default;
+                r.us_best = e.us_best;
+            }
+        }
+        // the level's iterate as it was
+        if (hipMemcpyAsync(L.x, save, bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess && rc == ECMG_OK)
+            rc = fail(c, ECMG_EDEVICE, "autotune: restore of level %d failed", l);
+    }
+    if (hipStreamSynchronize(c->stream) != hipSuccess && rc == ECMG_OK)
+        rc = fail(c, ECMG_EDEVICE, "autotune: stream synchronisation failed");
+    dfree(save);
+    c->solved = false;
+    if (rc != ECMG_OK) return rc;
+    if (!path.empty()) {
+        std::string err;
+        const int wr = tune_cache_write(path, c->device_name, entries, &err);
+        if (wr != ECMG_OK) return fail(c, wr, "%s", err.c_str());
+    }
+    return ECMG_OK;
+}
+
+int ecmg_tune_lookup(const char *path, int32_t precision, int32_t nx, int32_t ny, int32_t nz,
+                     ecmg_tune_result *out) {
+    if (!path || !out) return fail(nullptr, ECMG_EINVAL, "ecmg_tune_lookup: path or out is NULL");
+    std::map<std::string, TuneEntry> entries;
+    std::string dev, err;
+    const int rc = tune_cache_read(path, &dev, &entries, &err);
+    if (rc != ECMG_OK) return fail(nullptr, rc, "%s", err.c_str());
+    auto it = entries.find(tune_key(precision, nx, ny, nz));
+    if (it == entries.end())
+        return fail(nullptr, ECMG_ENOENT, "no tuning entry for %s", tune_key(precision, nx, ny, nz).c_str());
+    const TuneEntry &e = it->second;
+    out->level = -1;
+    out->path = e.path;
+    out->kz = e.kz;
+    out->seg = e.seg;
+    out->nwg = e.nwg;
+    out->candidates = 0;
+    out->us_default = e.us_default;
+    out->us_best = e.us_best;
+    return ECMG_OK;
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
@@ -1636,6 +1851,7 @@ struct ServerReq {
 
 struct ecmg_server {
     ecmg_options opt{};
+    std::string tune_cache;            // owned copy of opt.tune_cache (request contexts are created later)
     size_t budget = 0, used = 0;
     hipStream_t stream = nullptr;
     ecmg_ctx *lead = nullptr;          // holds the queue-kernel buffers
@@ -1804,6 +2020,10 @@ int ecmg_server_create(const ecmg_options *opt, size_t hbm_budget_bytes, ecmg_se
     ecmg_server *S = new ecmg_server();
     if (opt) S->opt = *opt;
     else ecmg_default_options(&S->opt);
+    if (S->opt.tune_cache) {
+        S->tune_cache = S->opt.tune_cache;
+        S->opt.tune_cache = S->tune_cache.c_str();
+    }
     if (S->opt.precision != ECMG_FP64) {
         delete S;
         return fail(nullptr, ECMG_EINVAL, "the server runs FP64 only");

@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -162,12 +164,33 @@ struct Level {
     float *dinv32 = nullptr;
     double nf = 0.0;                  // ||f_h||_2 of the stopping test
     int last_iters = -1;              // JCG iterations of the last converged solve (first chunk)
+    // autotuned JCG configuration (tune_path -1: the built-in rules)
+    int tune_path = -1;               // 0 tiled passes, 1 persistent kernel
+    int tune_kz = 0;                  // tiled: planes per z-chunk
+    int tune_seg = 0, tune_nwg = 0;   // persistent: nodes per segment, most workgroups
     // timing accumulators per kernel class
     double kt_ms[NKIND] = {};
     int64_t kt_n[NKIND] = {};
 };
 
 struct Ctx;
+
+// ---- autotuner: per-level choices and their JSON cache (tune_cache.cpp) ----
+struct TuneEntry {
+    int path = 0;                     // 0 tiled passes, 1 persistent kernel
+    int kz = 0;                       // tiled: planes per z-chunk
+    int seg = 0, nwg = 0;             // persistent: nodes per segment, most workgroups
+    double us_default = 0.0;          // microseconds per JCG iteration, built-in choice
+    double us_best = 0.0;             // ... the chosen configuration
+};
+// cache key of a JCG level: precision and elements per axis
+std::string tune_key(int precision, int nx, int ny, int nz);
+// ECMG_OK, ECMG_ENOENT (no file) or ECMG_EINVAL (not a tuning cache); entries
+// are added to *out, the device string of the file goes to *device
+int tune_cache_read(const std::string &path, std::string *device, std::map<std::string, TuneEntry> *out,
+                    std::string *err);
+int tune_cache_write(const std::string &path, const std::string &device,
+                     const std::map<std::string, TuneEntry> &entries, std::string *err);
 
 // ---- launchers (kernels.hip / extrap.hip / setup.hip) ---------------------------
 int stencil_blocks(const Geom &g, int KZ, int *ntx, int *nty, int *nkz);
