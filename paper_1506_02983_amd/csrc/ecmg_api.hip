@@ -63,6 +63,7 @@ struct ecmg_ctx {
     int64_t stage_n = 0;
     int KZ = 32;
     int kz_target = 1024;                      // tiled stencil: blocks aimed for per launch
+    int fold_max = FOLD_MAX_BLOCKS;            // JCG scalar steps folded into the passes up to this many blocks
     // persistent JCG for grids of at most persist_max nodes (larger ones: the
     // tiled passes, whose kernel boundaries synchronise more cheaply than the
     // persistent kernel's device-wide barriers once a grid fills the chip)
@@ -410,6 +411,47 @@ static int jcg_chunks(ecmg_ctx *c, int l, const StencilArgs<T> &a, const PassBAr
     return ECMG_OK;
 }
 
+// The same with folded scalars (no finishing kernels): the launches form the
+// sequence A0 B0 A1 B1 ..., each with its iteration index, and every chunk ends
+// on a pass A, which takes the stop test of the pass B before it.  Pass A sums
+// init's partials (nb_init pairs) at iteration 0 and pass B's after.
+static int jcg_chunks_folded(ecmg_ctx *c, int l, StencilArgs<double> a, PassBArgs<double> b, int fixed, int hint,
+                             int nb_init, int nb_b) {
+    int next = 2;
+    int chunk = c->opt.chunk > 0 ? c->opt.chunk : (hint > 0 ? hint : 2);
+    if (fixed >= 0) chunk = std::max(fixed, 1);
+    int64_t seq = 0;                     // next launch: even = pass A of seq / 2, odd = pass B
+    size_t slot = 0;
+    for (bool first = true;; first = false) {
+        if (!first) {
+            HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(JcgScalars), hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            if (c->sc_host->done) break;
+            if (c->opt.chunk <= 0 && fixed < 0) {
+                chunk = next;
+                next = std::min(next * 2, 64);
+            }
+        }
+        const int64_t last = 2 * (seq / 2 + chunk);
+        for (; seq <= last; ++seq) {
+            const int it = (int)(seq / 2);
+            if ((seq & 1) == 0) {
+                a.it = it;
+                a.fold_nb = it == 0 ? nb_init : nb_b;
+                CHK(rec_begin(c, l, 0, it, &slot));
+                launch_stencil<double>((a.p_init && it == 0) ? MODE_PASSA0 : MODE_PASSA, a, c->stream);
+            } else {
+                b.it = it;
+                CHK(rec_begin(c, l, 1, it, &slot));
+                launch_passB<double>(b, c->stream);
+            }
+            CHK(rec_end(c, slot));
+        }
+        HIPCHK(c, hipGetLastError());
+    }
+    return ECMG_OK;
+}
+
 // Mixed precision (FP32 stencil and CG vectors, FP64 dot products, FP64
 // residual and iterate): iterative refinement around an FP32 JCG.
 //   r = F - A x in FP64 (the stop test of Algorithm 4 is taken on it);
@@ -541,12 +583,6 @@ static int enqueue_jcg(ecmg_ctx *c, int l, double tol_abs, int max_iter, int fix
     a.p0 = c->p0;
     a.p1 = c->p1;
     a.p_init = 1;
-    size_t slot = 0;
-    CHK(rec_begin(c, l, 2, 0, &slot));
-    launch_stencil<double>(MODE_INIT, a, c->stream);
-    CHK(rec_end(c, slot));
-    HIPCHK(c, hipGetLastError());
-
     PassBArgs<double> b{};
     b.n = L.g.nnodes;
     b.r = c->r;
@@ -554,8 +590,26 @@ static int enqueue_jcg(ecmg_ctx *c, int l, double tol_abs, int max_iter, int fix
     b.dinv = L.dinv;
     b.sc = c->sc;
     b.partials = c->partials;
+    // folded scalars when both passes have few blocks: pass A's p.q partials
+    // at the start of the buffer, init's and pass B's (r.z, r.r) pairs after
+    const int64_t nb_a = (int64_t)a.ntx * a.nty * a.nkz, nb_b = passB_blocks(L.g.nnodes);
+    const bool fold = nb_a <= c->fold_max && nb_b <= c->fold_max &&
+                      2 * nb_a + 2 * std::max(nb_a, nb_b) <= c->partials_n;
+    if (fold) {
+        a.fold = b.fold = 1;
+        a.partials2 = c->partials + 2 * nb_a;
+        b.partials = a.partials2;
+        b.pq_partials = c->partials;
+        b.nb_a = (int)nb_a;
+    }
+    size_t slot = 0;
+    CHK(rec_begin(c, l, 2, 0, &slot));
+    launch_stencil<double>(MODE_INIT, a, c->stream);
+    CHK(rec_end(c, slot));
+    HIPCHK(c, hipGetLastError());
 
-    CHK(jcg_chunks(c, l, a, b, c->sc, fixed, 0, 1, fixed < 0 ? L.last_iters : 0));
+    if (fold) CHK(jcg_chunks_folded(c, l, a, b, fixed, fixed < 0 ? L.last_iters : 0, (int)nb_a, (int)nb_b));
+    else CHK(jcg_chunks(c, l, a, b, c->sc, fixed, 0, 1, fixed < 0 ? L.last_iters : 0));
     launch_final_x(L.g, L.x, c->p0, c->p1, c->sc, c->stream);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipMemcpyAsync(c->sc_lv + l, c->sc, sizeof(JcgScalars), hipMemcpyDeviceToHost, c->stream));
@@ -763,6 +817,7 @@ int ecmg_create(const ecmg_options *opt, ecmg_ctx **out) {
     c->device_name = std::string(prop.gcnArchName) + " " + std::to_string(prop.multiProcessorCount) + " CUs";
     if (const char *kz = std::getenv("ECMG_KZ")) c->KZ = std::max(1, std::atoi(kz));
     if (const char *kt = std::getenv("ECMG_KZ_TARGET")) c->kz_target = std::max(1, std::atoi(kt));
+    if (const char *v = std::getenv("ECMG_FOLD_BLOCKS")) c->fold_max = std::max(0, std::min(std::atoi(v), FOLD_MAX_BLOCKS));
     if (const char *v = std::getenv("ECMG_PERSIST_SEG")) c->persist_seglen = std::max(1, std::atoi(v));
     if (const char *v = std::getenv("ECMG_PERSIST_NWG")) c->persist_nwg = std::max(1, std::atoi(v));
     if (const char *v = std::getenv("ECMG_BATCH_NPW")) c->batch_npw = std::max(64, std::atoi(v));
@@ -929,7 +984,9 @@ int ecmg_setup(ecmg_ctx *c, const ecmg_problem *p) {
             CHK(dalloc_n(c, &c->q32, gf.nnodes));
             CHK(dalloc_n(c, &c->d32, gf.nnodes));
         }
-        int64_t pn = std::max<int64_t>(2 * 4096, 3 * (int64_t)c->persist_blocks);
+        // at least the two regions of folded scalar steps (pass A: 2 per block,
+        // then init / pass B: 2 per block, each pass up to FOLD_MAX_BLOCKS)
+        int64_t pn = std::max<int64_t>(4 * (int64_t)FOLD_MAX_BLOCKS, 3 * (int64_t)c->persist_blocks);
         for (int l = 0; l < p->levels; ++l) {
             Geom g = make_geom(p, l, lo);
             int a, b, d;

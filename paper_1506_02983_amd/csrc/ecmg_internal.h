@@ -78,7 +78,8 @@ struct JcgScalars {
     int max_iter;
     int fixed;         // >= 0: run exactly this many iterations
     int pending;       // x += alpha p of the last iteration still to apply
-    int pad;
+    int brk;           // folded scalars: pass B found p.q <= 0 (the next pass A sets done)
+    double rho_f[2];   // folded scalars: rho of iteration k in slot k & 1
 };
 
 enum { DONE_RUNNING = 0, DONE_CONVERGED = 1, DONE_MAXITER = 2, DONE_BREAKDOWN = 3 };
@@ -101,6 +102,12 @@ struct StencilArgs {
     double *partials;                 // per-block partial sums (2 per block)
     int p_init;                       // init also stores p_0 = D^-1 r into p1, and pass A's
                                       // iteration 0 (MODE_PASSA0) reads it there
+    // Folded scalars (no finishing kernels): init stores its (r.z, r.r) block
+    // partials in partials2; pass A of iteration `it` sums the fold_nb pairs
+    // there (init's or pass B's) itself, takes the stop test and beta, and
+    // stores its p.q partials in partials.
+    int fold, it, fold_nb;
+    double *partials2;
 };
 
 template <typename T>
@@ -111,7 +118,15 @@ struct PassBArgs {
     const T *dinv;
     JcgScalars *sc;
     double *partials;                 // 2 * passB_blocks(n)
+    // folded scalars: pass B of iteration `it` sums pass A's nb_a p.q partials
+    // (stride 2) itself and takes alpha = rho_it / p.q
+    int fold, it, nb_a;
+    const double *pq_partials;
 };
+
+// Largest pass (blocks) whose partials every block of the next pass sums
+// itself instead of a one-block finishing kernel.
+constexpr int FOLD_MAX_BLOCKS = 4096;
 
 // One independent JCG solve inside the persistent kernel: a grid, its arrays,
 // its stop control, and the contiguous range of workgroups that works on it.

@@ -21,6 +21,16 @@
 // the host can enqueue iterations in chunks and the iterate freezes exactly at
 // the stopping iteration.
 //
+// The scalar steps run either in one-block finishing kernels after each pass,
+// or -- when a pass has few blocks, where launches rather than bytes set the
+// time -- folded into the next pass: every block of pass A sums the (r.z, r.r)
+// partials of pass B (or init) itself, in one fixed order, so all blocks take
+// the same stop decision and the same beta; every block of pass B likewise sums
+// pass A's p.q partials for alpha.  Block 0 publishes the scalars.  Values that
+// block 0 writes are never read by the other blocks of the same launch: the
+// iteration index is a launch argument, rho alternates between two slots, and
+// a breakdown found in pass B is handed to the next pass A.
+//
 // Data layout in HBM: node (i,j,k) at i + sx*(j + sy*k) (x fastest, each
 // z-plane contiguous); element arrays likewise over nx*ny*nz.  The stencil
 // kernels tile x-y planes (TX lanes along x, coalesced rows) and march through
@@ -205,6 +215,8 @@ __global__ void __launch_bounds__(NT, STENCIL_WAVES_PER_EU) k_stencil(const Sten
     __shared__ T sv[4][TYT + 2][TX + 2];
     __shared__ T sb[3][TYT + 1][TX + 1];
     __shared__ double red[2][NT / 64];
+    __shared__ double s_beta;
+    __shared__ int s_flag;
     constexpr int NH = 2 * (TX + 2) + 2 * TYT;   // halo nodes of a plane tile
     constexpr int NHB = (TX + 1) + TYT;          // halo elements of a layer tile
     static_assert(NH <= NT && NHB <= NT, "one halo value per thread");
@@ -227,7 +239,55 @@ __global__ void __launch_bounds__(NT, STENCIL_WAVES_PER_EU) k_stencil(const Sten
     T alpha_prev = 0, betak = 0;
     const T *pin = a.p0;
     T *pout = a.p1;
-    if (PA) {
+    if (PA && a.fold) {
+        // Folded scalar step of the previous pass B (or init).  Block 0 of this
+        // launch may set `done`, so each block reads it once, through LDS.
+        JcgScalars *sc = a.sc;
+        const int it = a.it;
+        double t[2] = {0.0, 0.0};
+        for (int b = tid; b < a.fold_nb; b += NT) {
+            t[0] += a.partials2[2 * b];
+            t[1] += a.partials2[2 * b + 1];
+        }
+        if (tid == 0) s_flag = sc->done ? -1 : (sc->brk ? -2 : 0);
+        __syncthreads();
+        const int pre = s_flag;
+        if (pre == -1) return;                    // stopped by an earlier launch
+        block_sum<2, NT>(t, red);
+        if (tid == 0) {
+            int dn;
+            double bk = 0.0;
+            if (pre == -2) {
+                dn = DONE_BREAKDOWN;              // the previous pass B found p.q <= 0
+            } else {
+                const double rz = t[0], rr = t[1], rn = sqrt(rr);
+                if (sc->fixed >= 0) dn = (it >= sc->fixed) ? DONE_CONVERGED : DONE_RUNNING;
+                else if (!(rn > sc->tol)) dn = DONE_CONVERGED;
+                else if (it >= sc->max_iter) dn = DONE_MAXITER;
+                else dn = DONE_RUNNING;
+                if (it > 0) bk = rz / sc->rho_f[(it - 1) & 1];
+                if (blockIdx.x == 0) {
+                    sc->iter = it;
+                    sc->rho = rz;
+                    sc->rho_f[it & 1] = rz;
+                    sc->rr = rr;
+                    sc->beta = bk;
+                    // stopping after a pass B leaves that iteration's x update
+                    sc->pending = (dn != DONE_RUNNING && it > 0) ? 1 : 0;
+                }
+            }
+            if (blockIdx.x == 0 && dn != DONE_RUNNING) sc->done = dn;
+            s_beta = bk;
+            s_flag = dn;
+        }
+        __syncthreads();
+        if (s_flag != DONE_RUNNING) return;
+        first = (it == 0);
+        alpha_prev = (T)sc->alpha;
+        betak = (T)s_beta;
+        pin = (it & 1) ? a.p1 : a.p0;
+        pout = (it & 1) ? a.p0 : a.p1;
+    } else if (PA) {
         const JcgScalars *sc = a.sc;
         if (sc->done) return;                     // uniform over the grid
         const int it = MODE == MODE_PASSA0 ? 0 : sc->iter;
@@ -452,8 +512,9 @@ __global__ void __launch_bounds__(NT, STENCIL_WAVES_PER_EU) k_stencil(const Sten
     double acc[2] = {acc0, acc1};
     block_sum<2, NT>(acc, red);
     if (tid == 0) {
-        a.partials[2 * (int64_t)blockIdx.x] = acc[0];
-        if (MODE == MODE_INIT) a.partials[2 * (int64_t)blockIdx.x + 1] = acc[1];
+        double *out = (MODE == MODE_INIT && a.fold) ? a.partials2 : a.partials;
+        out[2 * (int64_t)blockIdx.x] = acc[0];
+        if (MODE == MODE_INIT) out[2 * (int64_t)blockIdx.x + 1] = acc[1];
     }
 }
 
@@ -508,9 +569,10 @@ constexpr int UB = 4;
 template <typename T>
 __global__ void __launch_bounds__(NTB) k_passB(const PassBArgs<T> a) {
     __shared__ double red[2][NTB / 64];
-    const JcgScalars *sc = a.sc;
-    if (sc->done) return;
-    const T al = (T)sc->alpha;
+    __shared__ double s_alpha;
+    __shared__ int s_bad;
+    JcgScalars *sc = a.sc;
+    if (sc->done) return;                         // never set during a pass B
     using V2 = typename Vec2<T>::type;
     const int64_t n2 = a.n / 2;
     const V2 *__restrict__ r2 = (const V2 *)a.r;
@@ -527,6 +589,32 @@ __global__ void __launch_bounds__(NTB) k_passB(const PassBArgs<T> a) {
             qv[u] = q2[i];
             dv[u] = d2[i];
         }
+    }
+    T al;
+    if (a.fold) {
+        // folded: alpha = rho_it / p.q from pass A's partials (every block the
+        // same sum, while its own loads are in flight); a breakdown goes to
+        // `brk`, which the next pass A turns into `done`
+        double t[1] = {0.0};
+        for (int b = threadIdx.x; b < a.nb_a; b += NTB) t[0] += a.pq_partials[2 * b];
+        block_sum<1, NTB>(t, red);
+        if (threadIdx.x == 0) {
+            const double pq = t[0];
+            const bool bad = !(pq > 0.0) || !isfinite(pq);
+            const double alpha = bad ? 0.0 : sc->rho_f[a.it & 1] / pq;
+            if (blockIdx.x == 0) {
+                sc->pq = pq;
+                if (bad) sc->brk = 1;
+                else sc->alpha = alpha;
+            }
+            s_alpha = alpha;
+            s_bad = bad;
+        }
+        __syncthreads();
+        if (s_bad) return;
+        al = (T)s_alpha;
+    } else {
+        al = (T)sc->alpha;
     }
     double rz = 0.0, rr = 0.0;
 #pragma unroll
@@ -612,7 +700,8 @@ __global__ void k_jcg_reset(JcgScalars *sc, double tol, int max_iter, int fixed)
         sc->max_iter = max_iter;
         sc->fixed = fixed;
         sc->pending = 0;
-        sc->pad = 0;
+        sc->brk = 0;
+        sc->rho_f[0] = sc->rho_f[1] = 0.0;
     }
 }
 
@@ -645,11 +734,15 @@ void launch_stencil(int mode, const StencilArgs<T> &a, hipStream_t s) {
         hipLaunchKernelGGL((k_stencil<T, MODE_APPLY>), dim3(nb), dim3(NT), 0, s, a);
     } else if (mode == MODE_INIT) {
         hipLaunchKernelGGL((k_stencil<T, MODE_INIT>), dim3(nb), dim3(NT), 0, s, a);
-        hipLaunchKernelGGL(k_stencil_finish<MODE_INIT>, dim3(1), dim3(NTF), 0, s, a.sc, (const double *)a.partials, nb);
+        if (!a.fold)
+            hipLaunchKernelGGL(k_stencil_finish<MODE_INIT>, dim3(1), dim3(NTF), 0, s, a.sc,
+                               (const double *)a.partials, nb);
     } else {
         if (mode == MODE_PASSA0) hipLaunchKernelGGL((k_stencil<T, MODE_PASSA0>), dim3(nb), dim3(NT), 0, s, a);
         else hipLaunchKernelGGL((k_stencil<T, MODE_PASSA>), dim3(nb), dim3(NT), 0, s, a);
-        hipLaunchKernelGGL(k_stencil_finish<MODE_PASSA>, dim3(1), dim3(NTF), 0, s, a.sc, (const double *)a.partials, nb);
+        if (!a.fold)
+            hipLaunchKernelGGL(k_stencil_finish<MODE_PASSA>, dim3(1), dim3(NTF), 0, s, a.sc,
+                               (const double *)a.partials, nb);
     }
 }
 
@@ -659,7 +752,7 @@ template <typename T>
 void launch_passB(const PassBArgs<T> &a, hipStream_t s) {
     const int64_t nb = passB_blocks(a.n);
     hipLaunchKernelGGL((k_passB<T>), dim3((unsigned)nb), dim3(NTB), 0, s, a);
-    hipLaunchKernelGGL(k_passB_finish, dim3(1), dim3(NTF), 0, s, a.sc, (const double *)a.partials, (int)nb);
+    if (!a.fold) hipLaunchKernelGGL(k_passB_finish, dim3(1), dim3(NTF), 0, s, a.sc, (const double *)a.partials, (int)nb);
 }
 
 void launch_final_x(const Geom &g, double *x, const double *p0, const double *p1, const JcgScalars *sc,
