@@ -7,10 +7,14 @@ the finest grid, with every input already resident in HBM (setup is timed
 separately).  value = finest-grid unknowns (all nodes, as the paper counts them)
 per second of wall time of that step.
 
-Prints one JSON line.  Kernel durations for the roofline come from HIP events
-recorded by the library on its own stream around each launch inside the timed
-region; algorithmic bytes per launch follow the per-node traffic model of each
-kernel (algorithmic_bytes below).  The CPU baseline times the oracle on a
+Prints one JSON line.  After the warm-up (and the autotuner), two untimed steps
+with HIP events around every launch give the per-kernel breakdown and name the
+dominant kernel (largest total time); the timed steps run without events (a
+timed launch costs about 5 us more, which the launch-bound levels would add to
+the step); the same number of steps follows with events, stamped by each launch
+of the dominant kernel itself on the library's stream, around that kernel only,
+which give the roofline's average duration.  Algorithmic bytes per launch follow
+the per-node traffic model of each kernel (algorithmic_bytes below).  The CPU baseline times the oracle on a
 bounded sample of the same workload (fewer levels) on the host cores.
 """
 import argparse
@@ -28,10 +32,10 @@ if ROOT not in sys.path:
 METRIC = "unknowns/s to 4th-order accuracy (FP64 vs mixed); JCG HBM GB/s; serve p50/p99"
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 KIND_NAMES = {0: "jcg_pass_a", 1: "jcg_pass_b", 2: "jcg_init", 3: "exp_finite", 4: "exp_true",
-              5: "jcg_pass_a_fp32", 6: "jcg_pass_b_fp32", 7: "jcg_persistent"}
+              5: "jcg_pass_a_fp32", 6: "jcg_pass_b_fp32", 7: "jcg_persistent", 10: "jcg_pass_a0"}
 KERNEL_SYMBOL = {0: "k_stencil<double, 2>", 1: "k_passB<double>", 2: "k_stencil<double, 1>",
                  3: "k_exp_finite", 4: "k_exp_true", 5: "k_stencil<float, 2>", 6: "k_passB<float>",
-                 7: "k_jcg_persistent"}
+                 7: "k_jcg_persistent", 10: "k_stencil<double, 3>"}
 
 
 def workload(name):
@@ -55,12 +59,9 @@ def algorithmic_bytes(kind, n, e, n1, n0, iters=0):
     elements of the level; n1, n0 nodes of the two coarser levels; iters JCG
     iterations inside one persistent launch)."""
     if kind == 0:
-        # read r, p_old, x, beta; write p, q, x -- the first iteration reads
-        # p_0 (stored by init) and beta and writes q: the mean over the iters
-        # launches of one solve
-        if iters <= 0:
-            return 8 * (6 * n + e)
-        return 8 * ((2 * n + e) + (iters - 1) * (6 * n + e)) / iters
+        return 8 * (6 * n + e)          # iterations >= 1: read r, p_old, x, beta; write p, q, x
+    if kind == 10:
+        return 8 * (2 * n + e)          # iteration 0: read p_0 (stored by init), beta; write q
     if kind == 1:
         return 8 * 4 * n                # read r, q, 1/D; write r
     if kind == 2:
@@ -92,10 +93,12 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kind_name, launches):
-    """HBM bytes per launch (average over the kernel's launches in one step)
-    from the committed rocprofv3 counter summary, if it was taken on the
-    current kernel source; else None."""
+def measured_traffic(kind_name, launches_per_step):
+    """HBM bytes per launch: the kernel's HBM bytes per step from the committed
+    rocprofv3 counter summary (every dispatch of the kernel name; launches that
+    find the `done` flag set move next to nothing) over its working launches
+    per step, if the summary was taken on the current kernel source; else
+    None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -104,9 +107,9 @@ def measured_traffic(kind_name, launches):
     if t.get("kernel_source_hash") != kernel_source_hash():
         return None
     k = t.get("kernels", {}).get(kind_name)
-    if not k:
+    if not k or not launches_per_step:
         return None
-    return float(k["bytes_per_launch"])
+    return float(k["bytes_per_step"]) / launches_per_step
 
 
 def exact_on_device(problem, n):
@@ -263,6 +266,9 @@ def main():
                     help="time the JCG configurations of every level after the warm-up (untimed) and keep the "
                          "fastest; 0 = the built-in heuristics")
     ap.add_argument("--tune-cache", default=None, help="JSON tuning cache to merge the choices into")
+    ap.add_argument("--tuned-from", default=None, metavar="CACHE",
+                    help="apply the choices of an existing tuning cache at setup instead of tuning (profiled runs: "
+                         "no candidate launches)")
     ap.add_argument("--no-errors", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run one device copy kernel (read BYTES, write BYTES) and exit: the reference "
@@ -300,7 +306,11 @@ def main():
     nodes = problem.nodes_at(L)
     elems = n[0] * n[1] * n[2]
 
-    s = E.Solver(interp=args.interp, timing=True, keep_w=False)
+    if args.tuned_from:
+        args.autotune = 0
+        s = E.Solver(interp=args.interp, timing=True, keep_w=False, autotune=1, tune_cache=args.tuned_from)
+    else:
+        s = E.Solver(interp=args.interp, timing=True, keep_w=False)
     t0 = time.perf_counter()
     s.setup(problem, device_fields=not args.host_fields)
     torch.cuda.synchronize()
@@ -317,12 +327,45 @@ def main():
         t0 = time.perf_counter()
         tuned = s.autotune(iters=0, cache=args.tune_cache)
         print("bench: autotune %.2f s: %s" % (time.perf_counter() - t0, ", ".join(
-            "L%d %s" % (r["level"], ("kz=%d" % r["kz"]) if r["path"] == 0 else "seg=%d nwg=%d" % (r["seg"], r["nwg"]))
+            "L%d %s" % (r["level"], ("tiled kz=%d" % r["kz"]) if r["path"] == "tiled" else
+                        "persistent seg=%d nwg=%d" % (r["seg"], r["nwg"]))
             for r in tuned)), file=sys.stderr, flush=True)
         s.solve(eps)
         s.extrapolate(L, out=False)
+    # per-kernel breakdown: two untimed steps with every kernel class timed
+    # (HIP events around each launch, which lengthen the launch-bound levels)
+    s.set_timing(-1)
     torch.cuda.synchronize()
     s.reset_kernel_times()
+    for _ in range(2):
+        infos_b = s.solve(eps)
+        s.extrapolate(L, out=False)
+    kernels = []
+    for l in range(problem.levels):
+        nl = problem.n_at(l)
+        nn = problem.nodes_at(l)
+        ee = nl[0] * nl[1] * nl[2]
+        n1 = problem.nodes_at(l - 1) if l >= 1 else 0
+        n0 = problem.nodes_at(l - 2) if l >= 2 else 0
+        for k in sorted(KIND_NAMES):
+            ms, cnt = s.kernel_times(l, k)
+            if cnt == 0:
+                continue
+            b = algorithmic_bytes(k, nn, ee, n1, n0, infos_b[l]["iters"])
+            kernels.append({"level": l, "kernel": KIND_NAMES[k], "kind": k, "launches": cnt, "total_ms": ms,
+                            "avg_us": 1e3 * ms / cnt, "bytes_per_launch": b,
+                            "gbs": b / (ms / cnt * 1e-3) / 1e9, "nodes": nn})
+    # the dominant kernel: largest total time, summed over all its launches
+    # (every level), as rocprofv3 reports it per kernel name
+    by_kind = {}
+    for r in kernels:
+        by_kind[r["kind"]] = by_kind.get(r["kind"], 0.0) + r["total_ms"]
+    dkind = max(by_kind, key=by_kind.get)
+
+    # timed region: no events (a timed launch costs about 5 us more, which the
+    # launch-bound levels would add to the step)
+    s.set_timing(0)
+    torch.cuda.synchronize()
     infos = None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -335,40 +378,42 @@ def main():
     value = nodes * args.steps / dt
     print("bench: %.3f ms/step, %.3e unknowns/s" % (ms_per_step, value), file=sys.stderr, flush=True)
 
-    # per-kernel times inside the timed region
-    kernels = []
+    # roofline region: the same steps again with events (stamped by each
+    # launch of the dominant kernel itself) around that kernel only
+    s.set_timing([dkind])
+    s.reset_kernel_times()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        infos_r = s.solve(eps)
+        s.extrapolate(L, out=False)
+    torch.cuda.synchronize()
+    region_ms = 1e3 * (time.perf_counter() - t0) / args.steps
+
+    d = {"total_ms": 0.0, "launches": 0, "bytes": 0.0}
     for l in range(problem.levels):
+        ms, cnt = s.kernel_times(l, dkind)
+        if cnt == 0:
+            continue
         nl = problem.n_at(l)
-        nn = problem.nodes_at(l)
-        ee = nl[0] * nl[1] * nl[2]
-        n1 = problem.nodes_at(l - 1) if l >= 1 else 0
-        n0 = problem.nodes_at(l - 2) if l >= 2 else 0
-        for k in range(8):
-            ms, cnt = s.kernel_times(l, k)
-            if cnt == 0:
-                continue
-            b = algorithmic_bytes(k, nn, ee, n1, n0, infos[l]["iters"])
-            kernels.append({"level": l, "kernel": KIND_NAMES[k], "kind": k, "launches": cnt, "total_ms": ms,
-                            "avg_us": 1e3 * ms / cnt, "bytes_per_launch": b,
-                            "gbs": b / (ms / cnt * 1e-3) / 1e9, "nodes": nn})
-    # the dominant kernel: largest total time in the timed region, summed over
-    # all its launches (every level), as rocprofv3 reports it per kernel name
-    by_kind = {}
-    for r in kernels:
-        a = by_kind.setdefault(r["kind"], {"total_ms": 0.0, "launches": 0, "bytes": 0.0})
-        a["total_ms"] += r["total_ms"]
-        a["launches"] += r["launches"]
-        a["bytes"] += r["bytes_per_launch"] * r["launches"]
-    dkind = max(by_kind, key=lambda k: by_kind[k]["total_ms"])
-    d = by_kind[dkind]
+        b = algorithmic_bytes(dkind, problem.nodes_at(l), nl[0] * nl[1] * nl[2],
+                              problem.nodes_at(l - 1) if l >= 1 else 0, problem.nodes_at(l - 2) if l >= 2 else 0,
+                              infos_r[l]["iters"])
+        d["total_ms"] += ms
+        d["launches"] += cnt
+        d["bytes"] += b * cnt
+    s.set_timing(-1)
     achieved = d["bytes"] / (d["total_ms"] * 1e-3) / 1e9
-    traffic = measured_traffic(KIND_NAMES[dkind], d["launches"])
+    traffic = measured_traffic(KIND_NAMES[dkind], d["launches"] / args.steps)
+    traffic = round(traffic) if traffic else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": KERNEL_SYMBOL[dkind], "launches": d["launches"],
                 "avg_us": round(1e3 * d["total_ms"] / d["launches"], 2),
-                "bytes_per_launch": round(d["bytes"] / d["launches"])}
-    jcg_fin = [r for r in kernels if r["level"] == L and r["kind"] in (0, 1)]
+                "bytes_per_launch": round(d["bytes"] / d["launches"]),
+                "region": "%d steps after the timed ones, HIP events only around this kernel's launches "
+                          "(%.3f ms/step)" % (args.steps, region_ms)}
+    jcg_fin = [r for r in kernels if r["level"] == L and r["kind"] in (0, 1, 10)]
     jcg_gbs = None
     if jcg_fin:
         tb = sum(r["bytes_per_launch"] * r["launches"] for r in jcg_fin)
@@ -452,7 +497,8 @@ def main():
         "config": {"workload": desc, "levels": problem.levels, "finest_elements": list(n), "finest_nodes": nodes,
                    "eps": eps, "precision": "fp64",
                    "interp": "lagrange27" if args.interp else "serendipity20", "parallelism": "single GPU",
-                   "jcg_configuration": "autotuned" if args.autotune else "built-in"},
+                   "jcg_configuration": ("from tuning cache" if args.tuned_from else
+                                         "autotuned" if args.autotune else "built-in")},
         "autotune": tuned,
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -465,6 +511,8 @@ def main():
         "levels": [{"level": i["level"], "n": [i["nx"], i["ny"], i["nz"]], "iters": i["iters"],
                     "rre": i["rre"], "ms": i["ms"]} for i in infos],
         "errors": errors,
+        "kernels_note": "per-kernel breakdown from 2 untimed steps with every kernel class timed; the timed "
+                        "steps record no events, the roofline region's only around the roofline kernel",
         "kernels": [{k: (round(v, 3) if isinstance(v, float) else v) for k, v in r.items()} for r in kernels],
     }
     print(json.dumps(out))

@@ -61,8 +61,10 @@ extern "C" {
                           test of Algorithm 4 is taken on it), FP32 JCG on
                           A d = r / ||r|| from d = 0 until its residual falls by
                           max(inner_tol, eps ||f_h|| / (2 ||r||)), x += ||r|| d in
-                          FP64, repeated.  Levels solved by the persistent kernel
-                          (small grids) run in FP64.                                */
+                          FP64, repeated.  Small levels run in FP64: those the
+                          persistent kernel solves and, on the tiled kernels,
+                          those of at most persistent_nodes nodes (300,000 when
+                          persistent_nodes is -1).                                  */
 
 /* ---- EXP_finite interpolation (Section 4.3) --------------------------- */
 #define ECMG_SERENDIPITY20 0   /* 8 corners (eq. jiedian) + 12 mid-edges (eq. zhongdian)
@@ -128,7 +130,7 @@ typedef struct {
     void *hip_stream;          /* hipStream_t to order all work on; NULL = own stream    */
     int64_t persistent_nodes;  /* grids of at most this many nodes run the whole JCG loop
                                   in one persistent launch; 0 = never, -1 = default
-                                  (300,000; 2,400,000 in the serving loop)             */
+                                  (20,000; 2,400,000 in the serving loop)              */
     int64_t dsolve_dense_max;  /* ecmg_solve: DSOLVE levels with at most this many free
                                   nodes (capped at 8192) are solved with an explicit
                                   inverse of A_FF, built on the first solve (Cholesky,
@@ -308,13 +310,22 @@ int ecmg_plan_bytes(const ecmg_problem *problem, int32_t precision, size_t *byte
  * (0 = JCG pass A, 1 = JCG pass B, 2 = JCG init, 3 = EXP_finite, 4 = EXP_true,
  * 5 = mixed-precision pass A, 6 = mixed-precision pass B, 7 = whole-level
  * persistent JCG used for small grids, 8 = mixed-precision start (r / ||r||
- * to FP32), 9 = mixed-precision update x += ||r|| d),
+ * to FP32), 9 = mixed-precision update x += ||r|| d, 10 = JCG pass A of
+ * iteration 0, which reads the p_0 that init stored; class 0 counts the later
+ * iterations),
  * out[0] = total milliseconds and out[1] = launches that did work since the
  * last ecmg_reset_kernel_times.  Measured with HIP events on the library's
  * stream around each launch; both calls wait for the stream to finish the
  * launches they account. */
 int ecmg_kernel_times(ecmg_ctx *ctx, int32_t level, int32_t k, double out[2]);
 int ecmg_reset_kernel_times(ecmg_ctx *ctx);
+
+/* The kernel classes timed from now on: bit k = class k of ecmg_kernel_times,
+ * 0 = none, -1 = all (options.timing = 1 starts with all).  Records already
+ * made still count.  Timing a class records two HIP events around each of its
+ * launches, which lengthens launch-bound levels (the JCG passes of small
+ * grids); to measure a step's time, time only the classes needed. */
+int ecmg_set_timing(ecmg_ctx *ctx, int32_t mask);
 
 /* Autotuner of the JCG configuration (how the loop of Algorithm 4 runs on each
  * level; the iterates are those of the same recurrence whatever is chosen, up

@@ -85,7 +85,7 @@ EXPORTS = ["ecmg_default_options", "ecmg_create", "ecmg_setup", "ecmg_solve", "e
            "ecmg_reset_kernel_times", "ecmg_last_error", "ecmg_destroy", "ecmg_solve_batch",
            "ecmg_extrapolate_batch", "ecmg_server_create", "ecmg_server_submit", "ecmg_server_step",
            "ecmg_server_poll", "ecmg_server_stats", "ecmg_server_reset_stats", "ecmg_server_destroy",
-           "ecmg_autotune", "ecmg_tune_lookup"]
+           "ecmg_autotune", "ecmg_tune_lookup", "ecmg_set_timing"]
 
 _lib = None
 
@@ -124,6 +124,7 @@ def load_library(path: str = LIB_PATH):
     L.ecmg_plan_bytes.argtypes = [ctypes.POINTER(ProblemC), i32, ctypes.POINTER(ctypes.c_size_t)]
     L.ecmg_kernel_times.argtypes = [P, i32, i32, P]
     L.ecmg_reset_kernel_times.argtypes = [P]
+    L.ecmg_set_timing.argtypes = [P, i32]
     L.ecmg_last_error.argtypes = [P]
     L.ecmg_last_error.restype = ctypes.c_char_p
     L.ecmg_destroy.argtypes = [P]
@@ -417,6 +418,12 @@ class Solver:
 
     def reset_kernel_times(self):
         self._check(self.L.ecmg_reset_kernel_times(self.h))
+
+    def set_timing(self, classes) -> None:
+        """Time these kernel classes from now on (an iterable of class numbers,
+        or -1 for all, 0 for none)."""
+        mask = classes if isinstance(classes, int) else sum(1 << int(k) for k in classes)
+        self._check(self.L.ecmg_set_timing(self.h, int(mask)))
 
 
 def solve_batch(solvers: Sequence["Solver"], rel_tol: float, allow_fail: bool = False) -> List[List[dict]]:

@@ -64,10 +64,14 @@ struct ecmg_ctx {
     int KZ = 32;
     int kz_target = 1024;                      // tiled stencil: blocks aimed for per launch
     int fold_max = FOLD_MAX_BLOCKS;            // JCG scalar steps folded into the passes up to this many blocks
+    uint32_t timing_mask = 0;                  // kernel classes timed with HIP events (bit k = class k)
     // persistent JCG for grids of at most persist_max nodes (larger ones: the
-    // tiled passes, whose kernel boundaries synchronise more cheaply than the
-    // persistent kernel's device-wide barriers once a grid fills the chip)
-    int64_t persist_max = 300000;
+    // tiled passes with folded scalar steps -- two launches per iteration,
+    // whose boundaries cost about what one of the persistent kernel's three
+    // device-wide barriers per iteration costs)
+    int64_t persist_max = 20000;
+    int64_t mixed_min = 300000;                // ECMG_MIXED: levels up to this many nodes stay FP64
+                                               // (an explicit persistent_nodes sets it too)
     int persist_blocks = 0;                    // co-resident workgroups (0 = unavailable)
     int persist_seglen = 0;                    // persistent kernel: nodes per thread along z (0 = by size)
     int persist_nwg = 256;                     // persistent kernel: most workgroups per task
@@ -86,7 +90,7 @@ struct ecmg_ctx {
     int lv_cap = 0;
     std::vector<hipEvent_t> lv_ev;
     // kernel timing (options.timing)
-    struct Rec { hipEvent_t a, b; int level, kind, iter; };
+    struct Rec { hipEvent_t a, b; int level, kind, iter; bool ext, valid; };
     std::vector<hipEvent_t> evpool;
     std::vector<Rec> recs;
     size_t evnext = 0;
@@ -303,8 +307,12 @@ static const int64_t kBatchPoints = (int64_t)1 << 23;
 // timing records
 // ---------------------------------------------------------------------------
 static int rec_flush(ecmg_ctx *c, int iter_limit);
+thread_local ecmg::PendingTiming ecmg::g_pending_timing;
+
+constexpr size_t NO_REC = ~(size_t)0;
 static int rec_begin(ecmg_ctx *c, int level, int kind, int iter, size_t *slot) {
-    if (!c->opt.timing) return ECMG_OK;
+    *slot = NO_REC;
+    if (!((c->timing_mask >> kind) & 1u)) return ECMG_OK;
     // bound the pending records (a long run of calls that never reach a
     // solve's final wait or a kernel-time query)
     if (c->recs.size() >= 65536) CHK(rec_flush(c, 1 << 30));
@@ -315,28 +323,38 @@ static int rec_begin(ecmg_ctx *c, int level, int kind, int iter, size_t *slot) {
             c->evpool.push_back(e);
         }
     }
-    ecmg_ctx::Rec r{c->evpool[c->evnext], c->evpool[c->evnext + 1], level, kind, iter};
+    // the kernel's own start and end through the extended launch; the
+    // cooperative launch of the persistent kernel (class 7) between markers
+    const bool ext = kind != 7;
+    ecmg_ctx::Rec r{c->evpool[c->evnext], c->evpool[c->evnext + 1], level, kind, iter, ext, true};
     c->evnext += 2;
-    HIPCHK(c, hipEventRecord(r.a, c->stream));
+    if (ext) g_pending_timing = PendingTiming{r.a, r.b};
+    else HIPCHK(c, hipEventRecord(r.a, c->stream));
     *slot = c->recs.size();
     c->recs.push_back(r);
     return ECMG_OK;
 }
 static int rec_end(ecmg_ctx *c, size_t slot) {
-    if (!c->opt.timing) return ECMG_OK;
-    HIPCHK(c, hipEventRecord(c->recs[slot].b, c->stream));
+    if (slot == NO_REC) return ECMG_OK;
+    ecmg_ctx::Rec &r = c->recs[slot];
+    if (!r.ext) {
+        HIPCHK(c, hipEventRecord(r.b, c->stream));
+    } else if (g_pending_timing.start) {         // nothing was launched: no record
+        g_pending_timing = PendingTiming{};
+        r.valid = false;
+    }
     return ECMG_OK;
 }
 // Fold the finished records.  A JCG pass launch (classes 0, 1, 5, 6) whose
 // iteration index is at or beyond its level's limit (the iterations the level
 // ran) found the `done` flag set and did no work; it is not counted.
-static bool rec_is_pass(int kind) { return kind == 0 || kind == 1 || kind == 5 || kind == 6; }
+static bool rec_is_pass(int kind) { return kind == 0 || kind == 1 || kind == 5 || kind == 6 || kind == 10; }
 static int rec_flush_levels(ecmg_ctx *c, const std::vector<int> &limit) {
-    if (!c->opt.timing) return ECMG_OK;
+    if (c->recs.empty()) return ECMG_OK;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     for (auto &r : c->recs) {
         const int lim = r.level < (int)limit.size() ? limit[r.level] : 0;
-        if (rec_is_pass(r.kind) && r.iter >= lim) continue;
+        if (!r.valid || (rec_is_pass(r.kind) && r.iter >= lim)) continue;
         float ms = 0.f;
         HIPCHK(c, hipEventElapsedTime(&ms, r.a, r.b));
         c->lv[r.level].kt_ms[r.kind] += ms;
@@ -398,9 +416,10 @@ static int jcg_chunks(ecmg_ctx *c, int l, const StencilArgs<T> &a, const PassBAr
             }
         }
         for (int t = 0; t < chunk; ++t) {
-            CHK(rec_begin(c, l, kind_a, done_iters + t, &slot));
-            // iteration 0 from the p_0 init stored, when it did
-            launch_stencil<T>((a.p_init && done_iters + t == 0) ? MODE_PASSA0 : MODE_PASSA, a, c->stream);
+            // iteration 0 from the p_0 init stored, when it did (its own timing class)
+            const bool a0 = a.p_init && done_iters + t == 0;
+            CHK(rec_begin(c, l, a0 ? 10 : kind_a, done_iters + t, &slot));
+            launch_stencil<T>(a0 ? MODE_PASSA0 : MODE_PASSA, a, c->stream);
             CHK(rec_end(c, slot));
             CHK(rec_begin(c, l, kind_b, done_iters + t, &slot));
             launch_passB<T>(b, c->stream);
@@ -438,8 +457,9 @@ static int jcg_chunks_folded(ecmg_ctx *c, int l, StencilArgs<double> a, PassBArg
             if ((seq & 1) == 0) {
                 a.it = it;
                 a.fold_nb = it == 0 ? nb_init : nb_b;
-                CHK(rec_begin(c, l, 0, it, &slot));
-                launch_stencil<double>((a.p_init && it == 0) ? MODE_PASSA0 : MODE_PASSA, a, c->stream);
+                const bool a0 = a.p_init && it == 0;
+                CHK(rec_begin(c, l, a0 ? 10 : 0, it, &slot));
+                launch_stencil<double>(a0 ? MODE_PASSA0 : MODE_PASSA, a, c->stream);
             } else {
                 b.it = it;
                 CHK(rec_begin(c, l, 1, it, &slot));
@@ -695,9 +715,11 @@ static bool uses_persistent(const ecmg_ctx *c, int l) {
 }
 
 // Mixed precision applies to JCG levels (not DSOLVE) solved by the tiled
-// kernels; the persistent coarse levels are latency-bound and stay FP64.
+// kernels above mixed_min nodes; smaller levels are latency-bound (FP32 saves
+// bytes they do not wait for, and the outer FP64 steps add host round trips)
+// and stay FP64, as do the persistent ones.
 static bool uses_mixed(const ecmg_ctx *c, int l) {
-    return c->opt.precision == ECMG_MIXED && l >= 2 && !uses_persistent(c, l);
+    return c->opt.precision == ECMG_MIXED && l >= 2 && !uses_persistent(c, l) && c->lv[l].g.nreal > c->mixed_min;
 }
 
 static int run_level_jcg(ecmg_ctx *c, int l, double tol_abs, int max_iter, int fixed, ecmg_level_info *info) {
@@ -811,6 +833,7 @@ int ecmg_create(const ecmg_options *opt, ecmg_ctx **out) {
     ecmg_ctx *c = new ecmg_ctx();
     c->device = dev;
     c->opt = o;
+    c->timing_mask = o.timing ? ((1u << NKIND) - 1u) : 0u;
     if (o.tune_cache) c->tune_cache = o.tune_cache;
     else if (const char *tc = std::getenv("ECMG_TUNE_CACHE")) c->tune_cache = tc;
     c->opt.tune_cache = nullptr;              // the caller's string is not kept
@@ -844,7 +867,7 @@ int ecmg_create(const ecmg_options *opt, ecmg_ctx **out) {
         c->persist_blocks = mb > 0 ? mb : 0;
         const int qb = queue_max_blocks();
         c->queue_blocks = qb > 0 ? qb : 0;
-        if (o.persistent_nodes >= 0) c->persist_max = o.persistent_nodes;
+        if (o.persistent_nodes >= 0) c->persist_max = c->mixed_min = o.persistent_nodes;
     }
     // barrier words: error flag at 0, arrival counter at 16 (its own cache line)
     if ((rc = dalloc(c, (void **)&c->d_task, sizeof(PersistentTask))) != ECMG_OK ||
@@ -1754,6 +1777,12 @@ int ecmg_reset_kernel_times(ecmg_ctx *c) {
     return ECMG_OK;
 }
 
+int ecmg_set_timing(ecmg_ctx *c, int32_t mask) {
+    if (!c) return fail(nullptr, ECMG_EINVAL, "ctx is NULL");
+    c->timing_mask = (uint32_t)mask & ((1u << NKIND) - 1u);
+    return ECMG_OK;
+}
+
 int ecmg_autotune(ecmg_ctx *c, int32_t iters, const char *cache_path, ecmg_tune_result *out) {
     if (!c) return fail(nullptr, ECMG_EINVAL, "ctx is NULL");
     if (!c->ready) return fail(c, ECMG_ESTATE, "ecmg_autotune before ecmg_setup");
@@ -1767,6 +1796,16 @@ int ecmg_autotune(ecmg_ctx *c, int32_t iters, const char *cache_path, ecmg_tune_
     }
     int64_t maxn = 0;
     for (int l = 2; l < c->nlev; ++l) maxn = std::max<int64_t>(maxn, c->lv[l].g.nnodes);
+    // no per-launch event records while tuning: they would lengthen the
+    // launch-bound candidates (and nothing the tuner runs is a solve to account)
+    const uint32_t saved_mask = c->timing_mask;
+    CHK(rec_flush(c, 1 << 30));
+    c->timing_mask = 0;
+    struct RestoreMask {
+        ecmg_ctx *c;
+        uint32_t m;
+        ~RestoreMask() { c->timing_mask = m; }
+    } restore_mask{c, saved_mask};
     double *save = nullptr;
     CHK(dalloc_n(c, &save, std::max<int64_t>(maxn, 1)));
     struct Cand { int path, kz, seg, nwg; };

@@ -3,6 +3,7 @@
 // public interface is include/ecmg.h.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -41,6 +42,21 @@ constexpr int PF = ECMG_PREFETCH;     // z-steps between issuing a plane's loads
 // registers at 128 per lane)
 constexpr int STENCIL_WAVES_PER_EU = 4;
 constexpr int NXCD = 8;               // MI355X: 8 XCDs, each with its own L2
+
+// HIP events for the next timed launch, set by the library's kernel-time
+// records.  launch_timed() hands them to the extended launch, which stamps
+// them with that kernel's own start and end (no marker packets between
+// kernels, so timing does not lengthen launch-bound levels), and clears them.
+struct PendingTiming {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+extern thread_local PendingTiming g_pending_timing;
+template <typename F, typename... Args>
+inline void launch_timed(F kernel, dim3 grid, dim3 block, uint32_t shmem, hipStream_t s, Args... args) {
+    const PendingTiming t = g_pending_timing;
+    g_pending_timing = PendingTiming{};
+    hipExtLaunchKernelGGL(kernel, grid, block, shmem, s, t.start, t.stop, 0u, args...);
+}
 
 // Geometry of one level, passed to kernels by value.
 // Node arrays in HBM: node (i,j,k) at i + sx*(j + sy*k), rows padded to a
@@ -156,7 +172,7 @@ enum { MODE_APPLY = 0, MODE_INIT = 1, MODE_PASSA = 2, MODE_PASSA0 = 3 };
 // kernel classes timed per level: 0 pass A, 1 pass B, 2 JCG init, 3 EXP_finite,
 // 4 EXP_true, 5 pass A FP32, 6 pass B FP32, 7 persistent JCG, 8 mixed start,
 // 9 mixed update
-constexpr int NKIND = 10;
+constexpr int NKIND = 11;
 
 struct Level {
     Geom g;

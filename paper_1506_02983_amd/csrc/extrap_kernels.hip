@@ -405,7 +405,7 @@ void launch_exp_finite(const Geom &gf, const Geom &g1, const double *U1, const d
                        int variant, hipStream_t s) {
     const int64_t ne = (int64_t)(gf.nx / 4) * (gf.ny / 4) * (gf.nz / 4);
     if (ne <= 0) return;
-    hipLaunchKernelGGL(k_exp_finite, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s, gf, g1, U1, U0, x, W,
+    launch_timed(k_exp_finite, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s, gf, g1, U1, U0, x, W,
                        variant);
 }
 
@@ -450,7 +450,7 @@ void launch_zero_pad_f32(const Geom &g, float *a, float *b, float *c, hipStream_
 void launch_exp_true(const Geom &gf, const double *U1, const double *U0, double *Ut, hipStream_t s) {
     const int tkz = exp_true_tkz(gf);
     const dim3 grid(exp_true_gx(gf), exp_true_gy(gf), exp_true_gz(gf, tkz));
-    hipLaunchKernelGGL(k_exp_true, grid, dim3(64, 4), 0, s, gf, U1, U0, Ut, tkz);
+    launch_timed(k_exp_true, grid, dim3(64, 4), 0, s, gf, U1, U0, Ut, tkz);
 }
 
 }  // namespace ecmg

@@ -719,27 +719,30 @@ int stencil_blocks(const Geom &g, int KZ, int *ntx, int *nty, int *nkz) {
 int stencil_kz(const Geom &g, int kz_max, int target_blocks) {
     // Planes per z-chunk: long chunks amortise the two halo planes, but small
     // grids need short chunks so that enough blocks run concurrently (the
-    // planes of one chunk are processed in sequence by one block).
+    // planes of one chunk are processed in sequence by one block).  At least 4:
+    // below that the halo planes dominate and the extra blocks of a small grid
+    // queue behind each other instead of overlapping.
     const int64_t tiles = (int64_t)((g.sx + TX - 1) / TX) * ((g.sy + TYT - 1) / TYT);
     int64_t kz = tiles * (g.nz + 1) / std::max(1, target_blocks);
-    if (kz < 1) kz = 1;
+    if (kz < 4) kz = 4;
     if (kz > kz_max) kz = kz_max;
-    return (int)kz;
+    if (kz > g.nz + 1) kz = g.nz + 1;
+    return (int)std::max<int64_t>(kz, 1);
 }
 
 template <typename T>
 void launch_stencil(int mode, const StencilArgs<T> &a, hipStream_t s) {
     const int nb = a.ntx * a.nty * a.nkz;
     if (mode == MODE_APPLY) {
-        hipLaunchKernelGGL((k_stencil<T, MODE_APPLY>), dim3(nb), dim3(NT), 0, s, a);
+        launch_timed(k_stencil<T, MODE_APPLY>, dim3(nb), dim3(NT), 0, s, a);
     } else if (mode == MODE_INIT) {
-        hipLaunchKernelGGL((k_stencil<T, MODE_INIT>), dim3(nb), dim3(NT), 0, s, a);
+        launch_timed(k_stencil<T, MODE_INIT>, dim3(nb), dim3(NT), 0, s, a);
         if (!a.fold)
             hipLaunchKernelGGL(k_stencil_finish<MODE_INIT>, dim3(1), dim3(NTF), 0, s, a.sc,
                                (const double *)a.partials, nb);
     } else {
-        if (mode == MODE_PASSA0) hipLaunchKernelGGL((k_stencil<T, MODE_PASSA0>), dim3(nb), dim3(NT), 0, s, a);
-        else hipLaunchKernelGGL((k_stencil<T, MODE_PASSA>), dim3(nb), dim3(NT), 0, s, a);
+        if (mode == MODE_PASSA0) launch_timed(k_stencil<T, MODE_PASSA0>, dim3(nb), dim3(NT), 0, s, a);
+        else launch_timed(k_stencil<T, MODE_PASSA>, dim3(nb), dim3(NT), 0, s, a);
         if (!a.fold)
             hipLaunchKernelGGL(k_stencil_finish<MODE_PASSA>, dim3(1), dim3(NTF), 0, s, a.sc,
                                (const double *)a.partials, nb);
@@ -751,7 +754,7 @@ int64_t passB_blocks(int64_t n) { return std::max<int64_t>(1, (n / 2 + UB * NTB 
 template <typename T>
 void launch_passB(const PassBArgs<T> &a, hipStream_t s) {
     const int64_t nb = passB_blocks(a.n);
-    hipLaunchKernelGGL((k_passB<T>), dim3((unsigned)nb), dim3(NTB), 0, s, a);
+    launch_timed(k_passB<T>, dim3((unsigned)nb), dim3(NTB), 0, s, a);
     if (!a.fold) hipLaunchKernelGGL(k_passB_finish, dim3(1), dim3(NTF), 0, s, a.sc, (const double *)a.partials, (int)nb);
 }
 
@@ -823,14 +826,14 @@ __global__ void k_to_f32(const double *a, float *b, int64_t n) {
 
 void launch_mixed_start(const Geom &g, const double *r64, double inv_s, const float *dinv32, float *r32, float *d32,
                         JcgScalars *sc, double *partials, unsigned *counter, hipStream_t s) {
-    hipLaunchKernelGGL(k_mixed_start, dim3(reduce_blocks(g.nnodes)), dim3(NTB), 0, s, g.nnodes, r64, inv_s, dinv32,
+    launch_timed(k_mixed_start, dim3(reduce_blocks(g.nnodes)), dim3(NTB), 0, s, g.nnodes, r64, inv_s, dinv32,
                        r32, d32, sc, partials, counter);
 }
 
 void launch_mixed_update(const Geom &g, double *x, double sc_s, const float *d32, const float *p0, const float *p1,
                          const JcgScalars *sc, hipStream_t s) {
     const int64_t nb = std::min<int64_t>((g.nnodes + 255) / 256, 8192);
-    hipLaunchKernelGGL(k_mixed_update, dim3(nb), dim3(256), 0, s, g.nnodes, g.sx, g.nx + 1, x, sc_s, d32, p0, p1, sc);
+    launch_timed(k_mixed_update, dim3(nb), dim3(256), 0, s, g.nnodes, g.sx, g.nx + 1, x, sc_s, d32, p0, p1, sc);
 }
 
 void launch_to_f32(const double *a, float *b, int64_t n, hipStream_t s) {

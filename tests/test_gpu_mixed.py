@@ -67,13 +67,18 @@ def test_mixed_meets_fp64_stop_test_and_accuracy(orc, ecmg, name):
 
 
 def test_mixed_default_levels_and_fixed_mode(orc, ecmg):
-    """With the persistent kernel on, small levels stay FP64 (outer_steps 0);
-    fixed-iteration mode (parity) always runs FP64."""
+    """By default, levels of at most 300,000 nodes stay FP64 (outer_steps 0)
+    whichever driver solves them; an explicit persistent_nodes moves that limit
+    (0: every JCG level mixed).  Fixed-iteration mode (parity) always runs FP64."""
     p = workloads.variable_beta_robin_cube(levels=4)
     with ecmg.Solver(precision=ecmg.MIXED) as s:
         s.setup(p)
         infos = s.solve(1e-10)
-        assert all(i["outer_steps"] == 0 for i in infos)
+        assert all(i["outer_steps"] == 0 for i in infos), infos
+    with ecmg.Solver(precision=ecmg.MIXED, persistent_nodes=0) as s:
+        s.setup(p)
+        infos = s.solve(1e-10)
+        assert all(i["outer_steps"] >= 1 for i in infos[2:]), infos
     with ecmg.Solver(precision=ecmg.MIXED, persistent_nodes=0) as s:
         s.setup(p)
         infos = s.solve_fixed([0, 0, 3, 2])

@@ -23,7 +23,7 @@ def _solve(ecmg, s, p, eps):
     return [i["iters"] for i in infos], {l: s.get(l, ecmg.VEC_U) for l in range(p.levels)}
 
 
-@pytest.mark.parametrize("persistent", [0, -1], ids=["tiled", "default"])
+@pytest.mark.parametrize("persistent", [0, -1, 300000], ids=["tiled", "default", "persistent"])
 def test_repeated_solves_match_fresh_context(ecmg, persistent):
     p = workloads.variable_beta_robin_cube(levels=5)
     fresh = {}
@@ -44,7 +44,7 @@ def test_repeated_solves_match_fresh_context(ecmg, persistent):
 def test_kernel_times_count_working_launches(ecmg):
     """Pass A / pass B launches that found `done` set are not counted: after a
     solve whose first chunk was too long, each tiled level counts exactly its
-    iterations."""
+    iterations (pass A: iteration 0 in class 10, the others in class 0)."""
     p = workloads.variable_beta_robin_cube(levels=5)
     with ecmg.Solver(persistent_nodes=0, timing=True) as s:
         s.setup(p)
@@ -52,6 +52,31 @@ def test_kernel_times_count_working_launches(ecmg):
         s.reset_kernel_times()
         infos = s.solve(1e-6)                                 # hints from the 1e-10 solve
         for l in range(2, p.levels):
-            for kind in (0, 1):
-                ms, cnt = s.kernel_times(l, kind)
-                assert cnt == infos[l]["iters"], (l, kind, cnt, infos[l]["iters"])
+            it = infos[l]["iters"]
+            counts = {k: s.kernel_times(l, k)[1] for k in (0, 1, 10)}
+            assert counts[10] == min(it, 1) and counts[0] == max(it - 1, 0), (l, counts, it)
+            assert counts[1] == it, (l, counts, it)
+
+
+def test_set_timing_selects_classes(ecmg):
+    """Only the selected kernel classes are timed; -1 times every class again."""
+    p = workloads.variable_beta_robin_cube(levels=5)
+    with ecmg.Solver(persistent_nodes=0, timing=True) as s:
+        s.setup(p)
+        s.solve(1e-8)
+        s.set_timing([2])                                     # JCG init only
+        s.reset_kernel_times()
+        infos = s.solve(1e-8)
+        for l in range(2, p.levels):
+            assert s.kernel_times(l, 2)[1] == 1, l
+            for k in (0, 1, 10):
+                assert s.kernel_times(l, k)[1] == 0, (l, k)
+        s.set_timing(-1)
+        s.reset_kernel_times()
+        infos = s.solve(1e-8)
+        for l in range(2, p.levels):
+            assert s.kernel_times(l, 1)[1] == infos[l]["iters"], l
+        s.set_timing(0)
+        s.reset_kernel_times()
+        s.solve(1e-8)
+        assert all(s.kernel_times(l, k)[1] == 0 for l in range(p.levels) for k in (0, 1, 2, 10))
