@@ -170,6 +170,38 @@ def precision_comparison(E, torch, name="high-contrast-513x257x257", steps=3):
     return res
 
 
+def method_comparison(E, torch, problem, desc, steps=3):
+    """ECMG_jcg and ECMG_cg (Algorithm 4 with plain CG, the comparison of the
+    paper's Tables iterations8-10) on the same workload and GPU: ms per step
+    (solve + finest EXP_true), CG iterations per level, finest-grid errors."""
+    L = problem.levels - 1
+    nodes = problem.nodes_at(L)
+    res = {"workload": desc}
+    for method, tag in ((E.JCG, "ecmg_jcg"), (E.CG, "ecmg_cg")):
+        with E.Solver(method=method, keep_w=False) as s:
+            s.setup(problem, device_fields=True)
+            s.solve(problem.eps)
+            s.extrapolate(L, out=False)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                infos = s.solve(problem.eps)
+                s.extrapolate(L, out=False)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            ue = exact_on_device(problem, problem.n_at(L))
+            eu, _ = s.norms(L, E.VEC_U, minus=ue)
+            et, _ = s.norms(L, E.VEC_UTILDE, minus=ue)
+            del ue
+            res[tag] = {"ms_per_step": 1e3 * dt, "value": nodes / dt, "U_max": eu, "Ut_max": et,
+                        "iters": [i["iters"] for i in infos]}
+        torch.cuda.empty_cache()
+        print("bench: %s: %.2f ms/step, iterations %s, |U~-u| %.3e" % (tag, 1e3 * dt, res[tag]["iters"], et),
+              file=sys.stderr, flush=True)
+    res["speedup_jcg"] = res["ecmg_cg"]["ms_per_step"] / res["ecmg_jcg"]["ms_per_step"]
+    return res
+
+
 def batched(E, torch, n_boxes=512, steps=3):
     """512 independent three-level solves (uneven boxes) through the batched
     API: one step = ecmg_solve_batch + ecmg_extrapolate_batch over all boxes."""
@@ -273,6 +305,8 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run one device copy kernel (read BYTES, write BYTES) and exit: the reference "
                          "for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE")
+    ap.add_argument("--no-method-comparison", action="store_true",
+                    help="skip ECMG_jcg vs ECMG_cg (plain CG) on the same workload")
     ap.add_argument("--no-precision-comparison", action="store_true",
                     help="skip the FP64 vs mixed comparison on the high-contrast workload")
     ap.add_argument("--batch-boxes", type=int, default=512, help="boxes of the batched workload (0 = skip)")
@@ -467,6 +501,9 @@ def main():
     prec_cmp = None
     if not args.no_precision_comparison:
         prec_cmp = precision_comparison(E, torch)
+    meth_cmp = None
+    if not args.no_method_comparison:
+        meth_cmp = method_comparison(E, torch, problem.with_(eps=eps), desc)
 
     batch = None
     if args.batch_boxes > 0:
@@ -505,6 +542,7 @@ def main():
         "jcg_hbm_gbs_finest": jcg_gbs,
         "fourth_order": fourth,
         "precision_comparison": prec_cmp,
+        "method_comparison": meth_cmp,
         "batched": batch,
         "serving": serve,
         "setup_s": setup_s,

@@ -73,13 +73,21 @@ extern "C" {
                                   means of eq. zhongdian along diagonals, then 27-node
                                   tri-quadratic Lagrange interpolation                 */
 
+/* ---- iteration on the levels above the two DSOLVE grids (Section 4.1) --- */
+#define ECMG_JCG 0   /* ECMG_jcg: CG preconditioned with M = diag(A) (Algorithm 4)   */
+#define ECMG_CG  1   /* ECMG_cg: Algorithm 4 with plain CG (M = I on free nodes), the
+                        variant Section 4.1 compares against; with ecmg_solve_fixed
+                        and ecmg_cascadic_schedule it is the original ECMG of
+                        Algorithm 3 (eq. ee)                                         */
+
 /* ---- vectors of a level (ecmg_get / ecmg_set / ecmg_device_view) ------ */
 #define ECMG_VEC_U      0   /* u_l: DSOLVE or JCG solution (g_D on Dirichlet nodes)    */
 #define ECMG_VEC_W      1   /* W_l: EXP_finite output on every node, before g_D is
                                imposed (kept only with options.keep_w)                  */
 #define ECMG_VEC_UTILDE 2   /* U~_l: EXP_true output (after ecmg_extrapolate)          */
 #define ECMG_VEC_F      3   /* load vector F = int f phi + int_R g_R phi (Section 2)   */
-#define ECMG_VEC_DINV   4   /* 1/diag(A) on free nodes, 0 on Dirichlet nodes           */
+#define ECMG_VEC_DINV   4   /* M^-1 on free nodes (1/diag(A); 1 with ECMG_CG), 0 on
+                               Dirichlet nodes                                            */
 #define ECMG_VEC_NONE  -1
 
 /* Field sampled on a tensor product of coordinates.  The library asks for
@@ -143,6 +151,7 @@ typedef struct {
     const char *tune_cache;    /* JSON tuning cache path (see ecmg_autotune); NULL = the
                                   ECMG_TUNE_CACHE environment variable, if set; the
                                   string is read during ecmg_create only                */
+    int32_t method;            /* ECMG_JCG (default) or ECMG_CG                          */
 } ecmg_options;
 
 /* One JCG level's configuration chosen by the autotuner. */
@@ -301,6 +310,15 @@ int ecmg_norms(ecmg_ctx *ctx, int32_t level, int32_t which, int32_t minus_which,
 
 /* Elements per axis of a level. */
 int ecmg_level_dims(ecmg_ctx *ctx, int32_t level, int64_t n[3]);
+
+/* Host only (no device needed): the per-level iteration counts of the
+ * original ECMG (Algorithm 3, eq. ee) for ecmg_solve_fixed.  iters[0] =
+ * iters[1] = 0 (the DSOLVE grids); fine grid j = 1 .. L (L = levels - 2, level
+ * j + 1) runs ceil(m_L * beta^(L - j)), so the finest runs m_L; e.g. m_L = 4,
+ * beta = 4 gives 4 * 4^(L - j).  iters: `levels` entries, caller-owned.
+ * ECMG_EINVAL for levels < 3, m_L < 1, beta < 1 (or not finite), or a count
+ * above 2^31 - 1. */
+int ecmg_cascadic_schedule(int32_t levels, int32_t m_L, double beta, int32_t *iters);
 
 /* Device bytes the hierarchy of `problem` needs at `precision` (no device
  * needed). */

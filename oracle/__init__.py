@@ -13,7 +13,9 @@ module marshals arguments and runs Algorithm 4 step by step:
                    test is the norm of (b on free nodes, g_D on Dirichlet nodes),
                    i.e. of the right-hand side with Dirichlet identity rows
   O6 DSOLVE        banded Cholesky on the two coarsest grids
-  O7 JCG           PCG with M = diag(A_FF) while ||r||_2 > eps ||f_h||_2
+  O7 JCG           PCG with M = diag(A_FF) while ||r||_2 > eps ||f_h||_2; ECMG_cg
+                   (Section 4.1) the same recurrence with M = I
+  O7b schedule     eq. ee: the fixed per-grid CG counts of Algorithm 3
   O8 EXP_finite    eqs. jiedian, zhongdian, inter (Section 4.3)
   O9 cascade       Algorithm 4
   O10 EXP_true     eqs. t1 and chenlin (Sections 4.2.1, 4.3)
@@ -310,16 +312,40 @@ class JCGResult:
     hist: np.ndarray
 
 
-def jcg(lv: Level, x0: np.ndarray, eps: float, max_iter: int = 20000, fixed_iters: int = -1) -> JCGResult:
+JCG_METHOD = 0      # Section 4.1: CG preconditioned with M = diag(A) (ECMG_jcg)
+CG_METHOD = 1       # Section 4.1: ECMG_cg, the same CG with M = I
+
+
+def jcg(lv: Level, x0: np.ndarray, eps: float, max_iter: int = 20000, fixed_iters: int = -1,
+        method: int = JCG_METHOD) -> JCGResult:
+    """Preconditioned CG of Algorithm 4 (M = diag(A)); with ``method=CG_METHOD``
+    plain CG, i.e. the same recurrence with M = I on the free nodes."""
     x = np.ascontiguousarray(x0, dtype=np.float64).copy()
+    D = lv.D if method == JCG_METHOD else np.ones_like(lv.D)
     it = ctypes.c_int64(0)
     rre = ctypes.c_double(0.0)
     rrt = ctypes.c_double(0.0)
     hist = np.zeros(max(max_iter, fixed_iters) + 2)
-    st = lib().orc_jcg(ctypes.byref(lv.csr()), _ptr(lv.dmask), _ptr(lv.D), _ptr(lv.F), _ptr(x),
+    st = lib().orc_jcg(ctypes.byref(lv.csr()), _ptr(lv.dmask), _ptr(D), _ptr(lv.F), _ptr(x),
                        float(eps), int(max_iter), int(fixed_iters), float(lv.nf),
                        ctypes.byref(it), ctypes.byref(rre), ctypes.byref(rrt), _ptr(hist))
     return JCGResult(x, int(it.value), float(rre.value), float(rrt.value), int(st), hist[: it.value + 1])
+
+
+def cascadic_schedule(levels: int, m_L: int, beta: float) -> List[int]:
+    """Eq. ee (Algorithm 3): with L = levels - 2 fine grids, grid j = 1..L
+    (hierarchy level j + 1) runs m_j = ceil(m_L * beta^(L - j)) CG steps; the
+    two DSOLVE grids run none.  The power is taken as repeated products."""
+    if levels < 3 or m_L < 1 or not (beta >= 1.0) or not math.isfinite(beta):
+        raise ValueError("need levels >= 3, m_L >= 1, beta >= 1")
+    L = levels - 2
+    out = [0, 0]
+    for j in range(1, L + 1):
+        m = float(m_L)
+        for _ in range(L - j):
+            m *= beta
+        out.append(int(math.ceil(m)))
+    return out
 
 
 SERENDIPITY20 = 0   # Section 4.3: 20 extrapolated nodes + serendipity (eq. inter)
@@ -419,11 +445,14 @@ class LevelResult:
 
 def cascade(problem: Problem, eps: Optional[float] = None, fixed_iters: Optional[Sequence[int]] = None,
             max_iter: int = 20000, keep_vectors: bool = True, errors: bool = True,
-            levels: Optional[Sequence[Level]] = None, variant: int = SERENDIPITY20) -> List[LevelResult]:
+            levels: Optional[Sequence[Level]] = None, variant: int = SERENDIPITY20,
+            method: int = JCG_METHOD) -> List[LevelResult]:
     """Algorithm 4: DSOLVE on levels 0 and 1, then for each finer level
     W = EXP_finite(u_{l-1}, u_{l-2}), JCG from W while ||A u - f|| > eps ||f||,
     and U~ = EXP_true(u_l, u_{l-1}).  ``fixed_iters[l]`` (l >= 2) replaces the
-    stopping test with an exact iteration count."""
+    stopping test with an exact iteration count.  ``method=CG_METHOD`` is
+    ECMG_cg (Section 4.1); with ``fixed_iters=cascadic_schedule(...)`` it is the
+    original ECMG of Algorithm 3."""
     eps = problem.eps if eps is None else eps
     Lt = problem.levels
     out: List[LevelResult] = []
@@ -437,7 +466,7 @@ def cascade(problem: Problem, eps: Optional[float] = None, fixed_iters: Optional
             W = exp_finite(lv.grid, us[l - 1], us[l - 2], variant)
             x0 = np.where(lv.dmask == 1, lv.gD, W)      # JCG starts from W with g_D imposed
             fi = -1 if fixed_iters is None else int(fixed_iters[l])
-            jr = jcg(lv, x0, eps, max_iter=max_iter, fixed_iters=fi)
+            jr = jcg(lv, x0, eps, max_iter=max_iter, fixed_iters=fi, method=method)
             if jr.status == -4:
                 raise RuntimeError("oracle JCG breakdown on level %d" % l)
             u = jr.x

@@ -26,6 +26,7 @@ OK, EINVAL, ENOMEM, ENOTCONV, EBREAKDOWN, EDEVICE, ESTATE, ECALLBACK, ENOENT = 0
 DIRICHLET, ROBIN = 0, 1
 FP64, MIXED = 0, 1
 SERENDIPITY20, LAGRANGE27 = 0, 1
+JCG, CG = 0, 1                      # iteration on the JCG levels: ECMG_jcg / ECMG_cg
 VEC_U, VEC_W, VEC_UTILDE, VEC_F, VEC_DINV, VEC_NONE = 0, 1, 2, 3, 4, -1
 K_PASSA, K_PASSB, K_INIT, K_EXPF, K_EXPT, K_PASSA32, K_PASSB32, K_PERSIST, K_MIXSTART, K_MIXUPDATE = range(10)
 
@@ -54,7 +55,7 @@ class Options(ctypes.Structure):
                 ("keep_w", ctypes.c_int32), ("inner_tol", ctypes.c_double), ("dsolve_tol", ctypes.c_double),
                 ("chunk", ctypes.c_int32), ("timing", ctypes.c_int32), ("hip_stream", ctypes.c_void_p),
                 ("persistent_nodes", ctypes.c_int64), ("dsolve_dense_max", ctypes.c_int64),
-                ("autotune", ctypes.c_int32), ("tune_cache", ctypes.c_char_p)]
+                ("autotune", ctypes.c_int32), ("tune_cache", ctypes.c_char_p), ("method", ctypes.c_int32)]
 
 
 class TuneResult(ctypes.Structure):
@@ -85,7 +86,7 @@ EXPORTS = ["ecmg_default_options", "ecmg_create", "ecmg_setup", "ecmg_solve", "e
            "ecmg_reset_kernel_times", "ecmg_last_error", "ecmg_destroy", "ecmg_solve_batch",
            "ecmg_extrapolate_batch", "ecmg_server_create", "ecmg_server_submit", "ecmg_server_step",
            "ecmg_server_poll", "ecmg_server_stats", "ecmg_server_reset_stats", "ecmg_server_destroy",
-           "ecmg_autotune", "ecmg_tune_lookup", "ecmg_set_timing"]
+           "ecmg_autotune", "ecmg_tune_lookup", "ecmg_set_timing", "ecmg_cascadic_schedule"]
 
 _lib = None
 
@@ -125,6 +126,7 @@ def load_library(path: str = LIB_PATH):
     L.ecmg_kernel_times.argtypes = [P, i32, i32, P]
     L.ecmg_reset_kernel_times.argtypes = [P]
     L.ecmg_set_timing.argtypes = [P, i32]
+    L.ecmg_cascadic_schedule.argtypes = [i32, i32, dbl, P]
     L.ecmg_last_error.argtypes = [P]
     L.ecmg_last_error.restype = ctypes.c_char_p
     L.ecmg_destroy.argtypes = [P]
@@ -159,6 +161,18 @@ def tune_lookup(path: str, n, precision: int = FP64) -> Optional[dict]:
     if rc != OK:
         raise EcmgError(rc, (L.ecmg_last_error(None) or b"").decode())
     return r.as_dict()
+
+
+def cascadic_schedule(levels: int, m_L: int, beta: float) -> List[int]:
+    """Per-level iteration counts of the original ECMG (Algorithm 3, eq. ee)
+    for Solver.solve_fixed: 0 on the two DSOLVE grids, ceil(m_L beta^(L-j)) on
+    fine grid j (host only)."""
+    L = load_library()
+    out = (ctypes.c_int32 * int(levels))()
+    rc = L.ecmg_cascadic_schedule(int(levels), int(m_L), float(beta), out)
+    if rc != OK:
+        raise EcmgError(rc, (L.ecmg_last_error(None) or b"").decode())
+    return list(out)
 
 
 class EcmgError(RuntimeError):
@@ -259,12 +273,14 @@ def problem_struct(problem, device_fields: bool = False):
 # ---------------------------------------------------------------------------
 
 class Solver:
-    """One ECMG_jcg context (one problem hierarchy resident on the device)."""
+    """One ECMG_jcg (or, with method=CG, ECMG_cg) context: one problem
+    hierarchy resident on the device."""
 
     def __init__(self, precision: int = FP64, interp: int = SERENDIPITY20, keep_w: bool = True,
                  max_iter: int = 20000, dsolve_tol: float = 1e-14, inner_tol: float = 1e-4,
                  chunk: int = 0, timing: bool = False, stream=None, persistent_nodes: int = -1,
-                 dsolve_dense_max: Optional[int] = None, autotune: int = 0, tune_cache: Optional[str] = None):
+                 dsolve_dense_max: Optional[int] = None, autotune: int = 0, tune_cache: Optional[str] = None,
+                 method: int = JCG):
         self.L = load_library()
         o = Options()
         self.L.ecmg_default_options(ctypes.byref(o))
@@ -276,6 +292,7 @@ class Solver:
             o.dsolve_dense_max = dsolve_dense_max
         o.autotune = int(autotune)
         o.tune_cache = tune_cache.encode() if tune_cache else None
+        o.method = int(method)
         self.opt = o
         h = ctypes.c_void_p()
         self._check(self.L.ecmg_create(ctypes.byref(o), ctypes.byref(h)), None)

@@ -806,6 +806,7 @@ void ecmg_default_options(ecmg_options *o) {
     o->dsolve_dense_max = DSOLVE_DENSE_LIMIT;
     o->autotune = 0;
     o->tune_cache = nullptr;
+    o->method = ECMG_JCG;
 }
 
 int ecmg_create(const ecmg_options *opt, ecmg_ctx **out) {
@@ -818,6 +819,7 @@ int ecmg_create(const ecmg_options *opt, ecmg_ctx **out) {
         return fail(nullptr, ECMG_EINVAL, "unknown precision %d", o.precision);
     if (o.interp != ECMG_SERENDIPITY20 && o.interp != ECMG_LAGRANGE27)
         return fail(nullptr, ECMG_EINVAL, "unknown interpolation %d", o.interp);
+    if (o.method != ECMG_JCG && o.method != ECMG_CG) return fail(nullptr, ECMG_EINVAL, "unknown method %d", o.method);
     if (o.max_iter < 0) return fail(nullptr, ECMG_EINVAL, "max_iter < 0");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
@@ -943,6 +945,24 @@ static int validate(ecmg_ctx *c, const ecmg_problem *p) {
     }
     if (!anyD && !p->alpha.host && !p->alpha.device && !(p->alpha.value > 0))
         return fail(c, ECMG_EINVAL, "no Dirichlet face and alpha == 0: the system is singular");
+    return ECMG_OK;
+}
+
+int ecmg_cascadic_schedule(int32_t levels, int32_t m_L, double beta, int32_t *iters) {
+    if (!iters) return fail(nullptr, ECMG_EINVAL, "ecmg_cascadic_schedule: iters is NULL");
+    if (levels < 3 || m_L < 1 || !(beta >= 1.0) || !std::isfinite(beta))
+        return fail(nullptr, ECMG_EINVAL, "ecmg_cascadic_schedule: need levels >= 3, m_L >= 1, beta >= 1");
+    // eq. ee: grid j of the L = levels - 2 fine grids (level j + 1) runs
+    // ceil(m_L * beta^(L - j)) iterations; the power as repeated products
+    const int L = levels - 2;
+    iters[0] = iters[1] = 0;
+    for (int j = 1; j <= L; ++j) {
+        double m = (double)m_L;
+        for (int e = 0; e < L - j; ++e) m *= beta;
+        const double c = std::ceil(m);
+        if (!(c <= 2147483647.0)) return fail(nullptr, ECMG_EINVAL, "ecmg_cascadic_schedule: count overflows");
+        iters[j + 1] = (int32_t)c;
+    }
     return ECMG_OK;
 }
 
@@ -1110,7 +1130,7 @@ int ecmg_setup(ecmg_ctx *c, const ecmg_problem *p) {
         }
         const double *al[6];
         for (int f = 0; f < 6; ++f) al[f] = L.alpha[f];
-        launch_dinv(g, L.beta, al, L.dinv, c->stream);
+        launch_dinv(g, L.beta, al, L.dinv, c->opt.method == ECMG_CG, c->stream);
         if (uses_mixed(c, l)) {           // FP32 copies for the inner JCG of the mixed form
             CHK(dalloc_n(c, &L.beta32, L.nelem));
             CHK(dalloc_n(c, &L.dinv32, g.nnodes));
@@ -1577,6 +1597,10 @@ int ecmg_extrapolate_batch(ecmg_ctx *const *ctxs, int32_t n) {
         if (!c || !c->ready) return fail(c0, ECMG_ESTATE, "ctxs[%d] is NULL or not set up", i);
         if (c->device != c0->device) return fail(c0, ECMG_EINVAL, "ctxs[%d] is on another device", i);
         if (c->nlev < 2) return fail(c0, ECMG_EINVAL, "ctxs[%d] has fewer than 2 levels", i);
+        // U~ is allocated (and zeroed on ctx's own stream) before that stream
+        // is waited for: the batched kernel below runs on ctxs[0]'s stream
+        Level &L = c->lv[c->nlev - 1];
+        if (!L.Ut) CHK(dalloc_n(c, &L.Ut, L.g.nnodes));
         if (c->stream != s) HIPCHK(c0, hipStreamSynchronize(c->stream));
     }
     CHK(batch_reserve(c0, n));
@@ -1585,7 +1609,6 @@ int ecmg_extrapolate_batch(ecmg_ctx *const *ctxs, int32_t n) {
     for (int i = 0; i < n; ++i) {
         ecmg_ctx *c = ctxs[i];
         Level &L = c->lv[c->nlev - 1];
-        if (!L.Ut) CHK(dalloc_n(c, &L.Ut, L.g.nnodes));
         ExpTask &e = ex[i];
         e.gf = L.g;
         e.g1 = c->lv[c->nlev - 2].g;

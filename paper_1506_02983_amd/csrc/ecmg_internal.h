@@ -287,7 +287,8 @@ void launch_zero_free(const Geom &g, double *x, hipStream_t s);
 void launch_load_volume(const Geom &g, int e0, int e1, const double *fg, double *F, hipStream_t s);
 void launch_load_face(const Geom &g, int face, const double *gR, double *F, hipStream_t s);
 void launch_scatter_face(const Geom &g, int face, const double *vals, double *x, hipStream_t s);
-void launch_dinv(const Geom &g, const double *beta, const double *const *alpha, double *dinv, hipStream_t s);
+void launch_dinv(const Geom &g, const double *beta, const double *const *alpha, double *dinv, int plain_cg,
+                 hipStream_t s);
 void launch_rhs_norm(const Geom &g, const double *F, const double *Ax0, const double *x0, double *partials,
                      unsigned *counter, double *out, hipStream_t s);
 void launch_norms(const Geom &g, const double *a, const double *b, const double *c, double *partials,

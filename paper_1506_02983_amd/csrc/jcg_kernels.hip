@@ -239,54 +239,20 @@ __global__ void __launch_bounds__(NT, STENCIL_WAVES_PER_EU) k_stencil(const Sten
     T alpha_prev = 0, betak = 0;
     const T *pin = a.p0;
     T *pout = a.p1;
+    // Folded scalar step (pass A): the iteration index and the buffers come
+    // with the launch; the sums of the previous pass's partials are loaded here
+    // and resolved after the first planes' loads are issued, so one memory
+    // round trip covers both.
+    double fold_t[2] = {0.0, 0.0};
     if (PA && a.fold) {
-        // Folded scalar step of the previous pass B (or init).  Block 0 of this
-        // launch may set `done`, so each block reads it once, through LDS.
-        JcgScalars *sc = a.sc;
         const int it = a.it;
-        double t[2] = {0.0, 0.0};
-        for (int b = tid; b < a.fold_nb; b += NT) {
-            t[0] += a.partials2[2 * b];
-            t[1] += a.partials2[2 * b + 1];
-        }
-        if (tid == 0) s_flag = sc->done ? -1 : (sc->brk ? -2 : 0);
-        __syncthreads();
-        const int pre = s_flag;
-        if (pre == -1) return;                    // stopped by an earlier launch
-        block_sum<2, NT>(t, red);
-        if (tid == 0) {
-            int dn;
-            double bk = 0.0;
-            if (pre == -2) {
-                dn = DONE_BREAKDOWN;              // the previous pass B found p.q <= 0
-            } else {
-                const double rz = t[0], rr = t[1], rn = sqrt(rr);
-                if (sc->fixed >= 0) dn = (it >= sc->fixed) ? DONE_CONVERGED : DONE_RUNNING;
-                else if (!(rn > sc->tol)) dn = DONE_CONVERGED;
-                else if (it >= sc->max_iter) dn = DONE_MAXITER;
-                else dn = DONE_RUNNING;
-                if (it > 0) bk = rz / sc->rho_f[(it - 1) & 1];
-                if (blockIdx.x == 0) {
-                    sc->iter = it;
-                    sc->rho = rz;
-                    sc->rho_f[it & 1] = rz;
-                    sc->rr = rr;
-                    sc->beta = bk;
-                    // stopping after a pass B leaves that iteration's x update
-                    sc->pending = (dn != DONE_RUNNING && it > 0) ? 1 : 0;
-                }
-            }
-            if (blockIdx.x == 0 && dn != DONE_RUNNING) sc->done = dn;
-            s_beta = bk;
-            s_flag = dn;
-        }
-        __syncthreads();
-        if (s_flag != DONE_RUNNING) return;
         first = (it == 0);
-        alpha_prev = (T)sc->alpha;
-        betak = (T)s_beta;
         pin = (it & 1) ? a.p1 : a.p0;
         pout = (it & 1) ? a.p0 : a.p1;
+        for (int b = tid; b < a.fold_nb; b += NT) {
+            fold_t[0] += a.partials2[2 * b];
+            fold_t[1] += a.partials2[2 * b + 1];
+        }
     } else if (PA) {
         const JcgScalars *sc = a.sc;
         if (sc->done) return;                     // uniform over the grid
@@ -406,13 +372,54 @@ __global__ void __launch_bounds__(NT, STENCIL_WAVES_PER_EU) k_stencil(const Sten
 
     double acc0 = 0.0, acc1 = 0.0;
 
-    // prologue: plane k0-1 (set SA as step k0-2's plane k0-1 ... built by hand)
-    {
-        fetch_set(SA, k0 - 2);       // plane k0-1, layer k0-2 (unused), epilogue k0-2 (unused)
-        commit_set(SA, k0 - 2);
-        fetch_set(SB, k0 - 1);       // plane k0, layer k0-1
-        commit_set(SB, k0 - 1);
+    // prologue: planes k0-1 and k0 (sets SA and SB as steps k0-2 and k0-1),
+    // both in flight together
+    fetch_set(SA, k0 - 2);           // plane k0-1, layer k0-2 (unused), epilogue k0-2 (unused)
+    fetch_set(SB, k0 - 1);           // plane k0, layer k0-1
+    if (PA && a.fold) {
+        // resolve the folded scalar step of the previous pass B (or init).
+        // Block 0 of this launch may set `done`, so each block reads it once,
+        // through LDS; every block sums the same partials in the same order.
+        JcgScalars *sc = a.sc;
+        const int it = a.it;
+        if (tid == 0) s_flag = sc->done ? -1 : (sc->brk ? -2 : 0);
+        __syncthreads();
+        const int pre = s_flag;
+        if (pre == -1) return;                    // stopped by an earlier launch
+        block_sum<2, NT>(fold_t, red);
+        if (tid == 0) {
+            int dn;
+            double bk = 0.0;
+            if (pre == -2) {
+                dn = DONE_BREAKDOWN;              // the previous pass B found p.q <= 0
+            } else {
+                const double rz = fold_t[0], rr = fold_t[1], rn = sqrt(rr);
+                if (sc->fixed >= 0) dn = (it >= sc->fixed) ? DONE_CONVERGED : DONE_RUNNING;
+                else if (!(rn > sc->tol)) dn = DONE_CONVERGED;
+                else if (it >= sc->max_iter) dn = DONE_MAXITER;
+                else dn = DONE_RUNNING;
+                if (it > 0) bk = rz / sc->rho_f[(it - 1) & 1];
+                if (blockIdx.x == 0) {
+                    sc->iter = it;
+                    sc->rho = rz;
+                    sc->rho_f[it & 1] = rz;
+                    sc->rr = rr;
+                    sc->beta = bk;
+                    // stopping after a pass B leaves that iteration's x update
+                    sc->pending = (dn != DONE_RUNNING && it > 0) ? 1 : 0;
+                }
+            }
+            if (blockIdx.x == 0 && dn != DONE_RUNNING) sc->done = dn;
+            s_beta = bk;
+            s_flag = dn;
+        }
+        __syncthreads();
+        if (s_flag != DONE_RUNNING) return;
+        alpha_prev = (T)sc->alpha;
+        betak = (T)s_beta;
     }
+    commit_set(SA, k0 - 2);
+    commit_set(SB, k0 - 1);
     fetch_set(SA, k0);
     if (PF == 2) fetch_set(SB, k0 + 1);
 

@@ -126,13 +126,19 @@ __global__ void k_scatter_face(const Geom g, int f, const double *__restrict__ v
 // hp*hq/9 * (sum of alpha over the face elements around i).
 struct AlphaPtrs { const double *a[6]; };
 
-__global__ void k_dinv(const Geom g, const double *__restrict__ beta, const AlphaPtrs al, double *dinv) {
+// The preconditioner M^-1 of the level's CG iterations, one value per node:
+// ECMG_jcg (Section 4.1) takes M = diag(A), so 1 / A_ii; ECMG_cg (plain CG,
+// the variant Section 4.1 names for comparison) takes M = I, so 1 on free
+// nodes.  Dirichlet nodes and row padding hold 0, which keeps them out of
+// every search direction.
+__global__ void k_dinv(const Geom g, const double *__restrict__ beta, const AlphaPtrs al, double *dinv, int plain_cg) {
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= g.nnodes) return;
     const int i = (int)(id % g.sx);
     const int64_t t = id / g.sx;
     const int j = (int)(t % g.sy), k = (int)(t / g.sy);
     if (i > g.nx || dir_node(g, i, j, k)) { dinv[id] = 0.0; return; }
+    if (plain_cg) { dinv[id] = 1.0; return; }
     double s8 = 0.0;
     for (int ke = k - 1; ke <= k; ++ke) {
         if (ke < 0 || ke >= g.nz) continue;
@@ -403,10 +409,11 @@ void launch_scatter_face(const Geom &g, int face, const double *vals, double *x,
                        vals, x);
 }
 
-void launch_dinv(const Geom &g, const double *beta, const double *const *alpha, double *dinv, hipStream_t s) {
+void launch_dinv(const Geom &g, const double *beta, const double *const *alpha, double *dinv, int plain_cg,
+                 hipStream_t s) {
     AlphaPtrs ap;
     for (int f = 0; f < 6; ++f) ap.a[f] = alpha[f];
-    hipLaunchKernelGGL(k_dinv, dim3(nblk(g.nnodes)), dim3(256), 0, s, g, beta, ap, dinv);
+    hipLaunchKernelGGL(k_dinv, dim3(nblk(g.nnodes)), dim3(256), 0, s, g, beta, ap, dinv, plain_cg);
 }
 
 void launch_rhs_norm(const Geom &g, const double *F, const double *Ax0, const double *x0, double *partials,

@@ -93,3 +93,48 @@ def test_smoothing_of_initial_error(orc):
         e.append(np.abs(orc.jcg(lv[2], x0, 0.0, fixed_iters=k).x - U).max())
     assert e[1] < 0.15 * e[0]
     assert e[2] < 1e-10
+
+
+def _cg_cases():
+    with open(GOLDEN) as fh:
+        return json.load(fh)["cg_cases"]
+
+
+@pytest.mark.parametrize("case", _cg_cases(), ids=lambda c: "P%d-cg-eps%g" % (c["problem"], c["eps"]))
+def test_ecmg_cg_matches_paper_tables(orc, case):
+    """ECMG_cg (Algorithm 4 with plain CG, Section 4.1): the oracle's CG with
+    M = I takes the iteration counts the paper prints in the ECMG_cg column,
+    on the same initial guesses that reproduce the ECMG_jcg column."""
+    res = orc.cascade(_problem(case), variant=orc.LAGRANGE27, method=orc.CG_METHOD, errors=False)
+    for row, r in zip(case["rows"], res[2:]):
+        assert list(r.n) == row["mesh"]
+        assert r.iters == row["iters"], (case["cite"], row["mesh"], r.iters)
+        assert r.rre <= case["eps"]
+
+
+def test_cascadic_schedule_eq_ee(orc):
+    """Eq. ee: m_j = ceil(m_L beta^(L-j)); the setting the paper quotes,
+    m_j = 4 * 4^(L-j), and a non-integer beta (ceil of the product)."""
+    assert orc.cascadic_schedule(5, 4, 4.0) == [0, 0, 64, 16, 4]
+    assert orc.cascadic_schedule(3, 7, 2.0) == [0, 0, 7]
+    # 3 * 1.5^3 = 10.125, 3 * 1.5^2 = 6.75, 3 * 1.5 = 4.5
+    assert orc.cascadic_schedule(6, 3, 1.5) == [0, 0, 11, 7, 5, 3]
+    with pytest.raises(ValueError):
+        orc.cascadic_schedule(2, 4, 4.0)
+    with pytest.raises(ValueError):
+        orc.cascadic_schedule(5, 4, 0.5)
+
+
+def test_cg_equals_jcg_when_the_diagonal_is_constant(orc):
+    """With M = c I, preconditioned CG takes exactly the iterates of plain CG
+    (the preconditioner only rescales z and cancels in alpha and p): on a level
+    whose diagonal the test makes constant, both methods agree to rounding."""
+    import numpy as np
+    p = workloads.paper_problem1(levels=3, eps=1e-10)
+    lv = orc.discretize(p, 2)
+    lv.D = np.where(lv.dmask == 1, lv.D, 2.5)
+    x0 = np.where(lv.dmask == 1, lv.gD, 0.0)
+    a = orc.jcg(lv, x0, 1e-10, method=orc.JCG_METHOD)
+    b = orc.jcg(lv, x0, 1e-10, method=orc.CG_METHOD)
+    assert a.iters == b.iters
+    assert np.abs(a.x - b.x).max() <= 1e-12 * np.abs(b.x).max()

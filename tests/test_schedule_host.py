@@ -1,0 +1,30 @@
+"""Host-only entry point of the C ABI (no device needed): the iteration counts
+of the original ECMG (Algorithm 3, eq. ee) that ecmg_solve_fixed runs."""
+import pytest
+
+import oracle
+
+
+@pytest.fixture(scope="module")
+def ecmg():
+    import paper_1506_02983_amd as E
+    E.load_library()
+    return E
+
+
+@pytest.mark.parametrize("levels,m_L,beta", [(5, 4, 4.0), (3, 7, 2.0), (6, 3, 1.5), (7, 1, 8.0), (4, 5, 1.0)])
+def test_schedule_matches_eq_ee(ecmg, levels, m_L, beta):
+    got = ecmg.cascadic_schedule(levels, m_L, beta)
+    assert got == oracle.cascadic_schedule(levels, m_L, beta)
+    assert got[:2] == [0, 0] and got[-1] == m_L
+
+
+def test_schedule_closed_form(ecmg):
+    """m_j = 4 * 4^(L - j), the setting the paper quotes for Algorithm 3."""
+    assert ecmg.cascadic_schedule(6, 4, 4.0) == [0, 0, 256, 64, 16, 4]
+
+
+@pytest.mark.parametrize("args", [(2, 4, 4.0), (5, 0, 4.0), (5, 4, 0.5), (5, 4, float("nan")), (40, 4, 8.0)])
+def test_schedule_rejects_bad_arguments(ecmg, args):
+    with pytest.raises(ecmg.EcmgError):
+        ecmg.cascadic_schedule(*args)
