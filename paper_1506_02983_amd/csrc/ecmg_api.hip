@@ -1847,7 +1847,7 @@ int ecmg_autotune(ecmg_ctx *c, int32_t iters, const char *cache_path, ecmg_tune_
             if (kz <= L.g.nz + 1) cands.push_back({0, kz, 0, 0});
         if (persist_possible(c, L.g) && L.g.nreal <= 20000000)
             for (int seg : {2, 4})
-                for (int nwg : {128, 256})
+                for (int nwg : {32, 64, 128, 256})
                     if (nwg <= c->persist_blocks) cands.push_back({1, 0, seg, nwg});
         double best = 0.0, us_default = 0.0;
         int bi = -1;

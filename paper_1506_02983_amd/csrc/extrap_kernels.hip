@@ -317,7 +317,7 @@ __device__ __forceinline__ void exp_true_block(const Geom &gf, const double *__r
                 else ve = u_e + se / (ne == 1 ? 6.0 : 12.0);
                 if (hx) {
                     const double vo = u_o + so / (ne == 0 ? 6.0 : (ne == 1 ? 12.0 : 24.0));
-                    *(double2 *)(Ut + id) = make_double2(ve, vo);
+                    nt_store2(make_double2(ve, vo), (double2 *)(Ut + id));   // streamed: read by nothing here
                 } else {
                     Ut[id] = ve;
                 }

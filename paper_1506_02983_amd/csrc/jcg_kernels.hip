@@ -565,8 +565,8 @@ __global__ void __launch_bounds__(NTF) k_stencil_finish(JcgScalars *sc, const do
 // pass B: r -= alpha q; z = D^-1 r; r.z, r.r; stop test
 // ---------------------------------------------------------------------------
 // A streaming kernel in which every block takes one contiguous chunk of UB x NTB
-// node pairs (16-byte accesses; node arrays have an even length and 16-byte
-// alignment) and stores its two partial sums, then a one-block kernel that sums
+// node pairs (16-byte non-temporal accesses; node arrays have an even length
+// and 16-byte alignment) and stores its two partial sums, then a one-block kernel that sums
 // the partials in block order and takes the scalar step.  Many short-lived
 // blocks with contiguous chunks stream faster than a grid-stride loop, and
 // plain partial stores avoid a device-scope fence and atomic per block.
@@ -592,9 +592,9 @@ __global__ void __launch_bounds__(NTB) k_passB(const PassBArgs<T> a) {
     for (int u = 0; u < UB; ++u) {
         const int64_t i = base + u * NTB;
         if (i < n2) {
-            rv[u] = r2[i];
-            qv[u] = q2[i];
-            dv[u] = d2[i];
+            rv[u] = nt_load2(r2 + i);
+            qv[u] = nt_load2(q2 + i);
+            dv[u] = nt_load2(d2 + i);
         }
     }
     T al;
@@ -631,7 +631,7 @@ __global__ void __launch_bounds__(NTB) k_passB(const PassBArgs<T> a) {
             V2 x;
             x.x = rv[u].x - al * qv[u].x;
             x.y = rv[u].y - al * qv[u].y;
-            w2[i] = x;
+            nt_store2(x, w2 + i);
             const T z0 = dv[u].x * x.x, z1 = dv[u].y * x.y;
             rz += (double)x.x * (double)z0 + (double)x.y * (double)z1;
             rr += (double)x.x * (double)x.x + (double)x.y * (double)x.y;
@@ -683,8 +683,8 @@ __global__ void __launch_bounds__(256) k_final_x(int64_t n, T *x, const T *p0, c
     for (int u = 0; u < UB; ++u) {
         const int64_t i = base + u * 256;
         if (i < n2) {
-            xv[u] = x2[i];
-            pv[u] = p[i];
+            xv[u] = nt_load2(x2 + i);
+            pv[u] = nt_load2(p + i);
         }
     }
 #pragma unroll
@@ -693,7 +693,7 @@ __global__ void __launch_bounds__(256) k_final_x(int64_t n, T *x, const T *p0, c
         if (i < n2) {
             xv[u].x += al * pv[u].x;
             xv[u].y += al * pv[u].y;
-            x2[i] = xv[u];
+            nt_store2(xv[u], x2 + i);
         }
     }
 }
