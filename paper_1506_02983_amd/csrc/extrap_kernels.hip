@@ -57,9 +57,16 @@ __device__ __forceinline__ bool is_dir(const Geom &g, int i, int j, int k) {
 // global ones (2I+a, 2J+b, 2K+c); level l-2 corners (a/2, b/2, c/2).  Fine rows
 // are written with 16-byte stores (4I is a multiple of 4 and rows are 16-byte
 // aligned); lanes take consecutive I, so a wave writes contiguous row segments.
+// WIDE: every wave holds 64 consecutive elements of one element row (the
+// caller guarantees NX % 64 == 0, 64-thread-aligned waves): each fine row's
+// 256 values go through the wave's LDS buffer `stage` (256 doubles), so that
+// every store instruction writes 1 KB contiguous instead of 16 bytes per
+// 32-byte chunk.
+template <bool WIDE>
 __device__ __forceinline__ void exp_finite_elem(const Geom &gf, const Geom &g1, const double *__restrict__ U1,
                                                 const double *__restrict__ U0, double *__restrict__ x,
-                                                double *__restrict__ W, int variant, int64_t e) {
+                                                double *__restrict__ W, int variant, int64_t e,
+                                                double *__restrict__ stage) {
     const int NX = gf.nx / 4, NY = gf.ny / 4, NZ = gf.nz / 4;
     if (e >= (int64_t)NX * NY * NZ) return;
     const int I = (int)(e % NX);
@@ -221,13 +228,42 @@ __device__ __forceinline__ void exp_finite_elem(const Geom &gf, const Geom &g1, 
             const double o1 = 0.375 * w0 + 0.75 * w1 - 0.125 * w2;
             const double o3 = -0.125 * w0 + 0.75 * w1 + 0.375 * w2;
             const int64_t id = 4 * I + sx * j + sxy * k;
+            const bool drow = (j == 0 && gf.ft[2] == ECMG_DIRICHLET) || (j == gf.ny && gf.ft[3] == ECMG_DIRICHLET) ||
+                              (k == 0 && gf.ft[4] == ECMG_DIRICHLET) || (k == gf.nz && gf.ft[5] == ECMG_DIRICHLET);
+            if (WIDE) {
+                // the wave's 256 fine nodes of this row start at 4 * (I - lane)
+                const int lane = (int)(threadIdx.x & 63);
+                const int64_t row0 = id - 4 * lane;
+                const bool dw = (I - lane) == 0 && gf.ft[0] == ECMG_DIRICHLET;   // node x = 0 keeps g_D
+                *(double2 *)(stage + 4 * lane) = make_double2(w0, o1);
+                *(double2 *)(stage + 4 * lane + 2) = make_double2(w1, o3);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                const double2 v0 = *(const double2 *)(stage + 2 * lane);
+                const double2 v1 = *(const double2 *)(stage + 128 + 2 * lane);
+                if (W) {
+                    *(double2 *)(W + row0 + 2 * lane) = v0;
+                    *(double2 *)(W + row0 + 128 + 2 * lane) = v1;
+                    if (lastx) W[id + 4] = w2;
+                }
+                if (!drow) {
+                    if (dw && lane == 0) x[row0 + 1] = v0.y;
+                    else *(double2 *)(x + row0 + 2 * lane) = v0;
+                    *(double2 *)(x + row0 + 128 + 2 * lane) = v1;
+                    if (lastx && !d4) x[id + 4] = w2;
+                }
+                // the buffer is rewritten by the next row
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                continue;
+            }
             if (W) {
                 *(double2 *)(W + id) = make_double2(w0, o1);
                 *(double2 *)(W + id + 2) = make_double2(w1, o3);
                 if (lastx) W[id + 4] = w2;
             }
-            const bool drow = (j == 0 && gf.ft[2] == ECMG_DIRICHLET) || (j == gf.ny && gf.ft[3] == ECMG_DIRICHLET) ||
-                              (k == 0 && gf.ft[4] == ECMG_DIRICHLET) || (k == gf.nz && gf.ft[5] == ECMG_DIRICHLET);
             if (drow) continue;                               // the whole row is Dirichlet (g_D stays)
             if (!d0) *(double2 *)(x + id) = make_double2(w0, o1);
             else x[id + 1] = o1;
@@ -237,10 +273,13 @@ __device__ __forceinline__ void exp_finite_elem(const Geom &gf, const Geom &g1, 
     }
 }
 
+template <bool WIDE>
 __global__ void __launch_bounds__(256) k_exp_finite(const Geom gf, const Geom g1, const double *__restrict__ U1,
                                                     const double *__restrict__ U0, double *__restrict__ x,
                                                     double *__restrict__ W, int variant) {
-    exp_finite_elem(gf, g1, U1, U0, x, W, variant, (int64_t)blockIdx.x * 256 + threadIdx.x);
+    __shared__ double stage[WIDE ? 4 : 1][WIDE ? 256 : 1];
+    exp_finite_elem<WIDE>(gf, g1, U1, U0, x, W, variant, (int64_t)blockIdx.x * 256 + threadIdx.x,
+                          stage[WIDE ? threadIdx.x / 64 : 0]);
 }
 
 // U~ = U1 + (1/3) T[U1 - U0]: eq. t1 at coarse nodes ((4 U1 - U0)/3), eq.
@@ -355,7 +394,7 @@ __device__ __forceinline__ int find_box(const ExpTask *__restrict__ t, int n, in
 __global__ void __launch_bounds__(256) k_exp_finite_batch(const ExpTask *__restrict__ tasks, int n) {
     const int64_t b = blockIdx.x;
     const ExpTask &t = tasks[find_box(tasks, n, b, 0)];
-    exp_finite_elem(t.gf, t.g1, t.U1, t.U0, t.x, t.W, t.variant, (b - t.b0[0]) * 256 + threadIdx.x);
+    exp_finite_elem<false>(t.gf, t.g1, t.U1, t.U0, t.x, t.W, t.variant, (b - t.b0[0]) * 256 + threadIdx.x, nullptr);
 }
 
 __global__ void __launch_bounds__(256) k_exp_true_batch(const ExpTask *__restrict__ tasks, int n) {
@@ -405,8 +444,14 @@ void launch_exp_finite(const Geom &gf, const Geom &g1, const double *U1, const d
                        int variant, hipStream_t s) {
     const int64_t ne = (int64_t)(gf.nx / 4) * (gf.ny / 4) * (gf.nz / 4);
     if (ne <= 0) return;
-    launch_timed(k_exp_finite, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s, gf, g1, U1, U0, x, W,
-                       variant);
+    // whole waves on one element row when NX is a multiple of 64 (then every
+    // 64-thread wave holds 64 consecutive elements of one row)
+    if ((gf.nx / 4) % 64 == 0)
+        launch_timed(k_exp_finite<true>, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s, gf, g1, U1, U0, x, W,
+                     variant);
+    else
+        launch_timed(k_exp_finite<false>, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s, gf, g1, U1, U0, x, W,
+                     variant);
 }
 
 // Zero the row padding (i > nx) of up to four node arrays of a level; the JCG

@@ -111,3 +111,32 @@ def test_fullsize_sampled_parity(orc, ecmg, name):
           (name, e_fine, e_coarse, float(np.abs(Ut - ue).max())), flush=True)
     if name == "variable-beta-robin-513":       # smooth u: second order; r^(2/3) is singular
         assert e_fine <= 0.5 * e_coarse
+
+
+@pytest.mark.parametrize("interp", ["serendipity", "lagrange"])
+def test_exp_finite_wide_rows_against_points(orc, ecmg, interp):
+    """EXP_finite on a grid whose element rows fill whole waves (257^3: 64 coarse
+    elements per row, the form that stages each row through LDS): with zero JCG
+    iterations u_L is EXP_finite's output with g_D on Dirichlet nodes, and W its
+    raw form; both at sampled nodes (row ends, the Dirichlet x faces) against the
+    oracle's point-wise formula on the GPU's own coarser solutions."""
+    p = workloads.variable_beta_robin_cube(levels=6)
+    L = p.levels - 1
+    n = p.n_at(L)
+    variant = ecmg.LAGRANGE27 if interp == "lagrange" else ecmg.SERENDIPITY20
+    with ecmg.Solver(keep_w=True, interp=variant) as s:
+        s.setup(p, device_fields=True)
+        s.solve_fixed([0] * p.levels)
+        u1, u0, uL = s.get(L - 1, ecmg.VEC_U), s.get(L - 2, ecmg.VEC_U), s.get(L, ecmg.VEC_U)
+        W = s.get(L, ecmg.VEC_W)
+    rng = np.random.default_rng(5)
+    pts = _sample(n, rng, extra=4000)
+    ovar = orc.LAGRANGE27 if interp == "lagrange" else orc.SERENDIPITY20
+    wref = orc.exp_finite_points(n, u1, u0, pts, variant=ovar)
+    assert _rel(W[pts], wref) <= 1e-14
+    grid = orc.grid_of(p, L)
+    dmask = orc.dirichlet_mask(grid)[pts] == 1
+    assert dmask.any() and (~dmask).any()
+    assert _rel(uL[pts][~dmask], wref[~dmask]) <= 1e-14
+    ue = orc.exact_nodes(p, grid)[pts][dmask]
+    assert np.all(np.abs(uL[pts][dmask] - ue) <= 8 * np.finfo(np.float64).eps * np.abs(ue) + 1e-300)
