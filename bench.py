@@ -121,18 +121,25 @@ def exact_on_device(problem, n):
     return torch.as_tensor(v, dtype=torch.float64, device="cuda").expand(n[2] + 1, n[1] + 1, n[0] + 1).contiguous()
 
 
-def cpu_baseline(problem, levels, precision_interp=0):
+def cpu_baseline(problem, levels, precision_interp=0, min_seconds=10.0):
+    """The oracle's cascade (discretisation excluded, as on the GPU) on the same
+    workload with fewer levels, repeated until at least min_seconds of CPU work
+    have been timed."""
     import oracle
     p = problem.with_(levels=levels)
     lvls = [oracle.discretize(p, l) for l in range(levels)]
-    t0 = time.perf_counter()
-    res = oracle.cascade(p, levels=lvls, errors=False, keep_vectors=False, variant=precision_interp)
-    dt = time.perf_counter() - t0
+    reps, dt, res = 0, 0.0, None
+    while reps == 0 or dt < min_seconds:
+        t0 = time.perf_counter()
+        res = oracle.cascade(p, levels=lvls, errors=False, keep_vectors=False, variant=precision_interp)
+        dt += time.perf_counter() - t0
+        reps += 1
     nodes = p.nodes_at(levels - 1)
-    return {"value": nodes / dt, "unit": "unknowns/s", "cores": oracle.num_threads(), "kind": "oracle",
+    return {"value": nodes * reps / dt, "unit": "unknowns/s", "cores": oracle.num_threads(), "kind": "oracle",
             "sample": "same workload on %d levels (finest %s elements, %d nodes): oracle DSOLVE + EXP_finite + "
-                      "JCG + EXP_true region, %.1f s, iterations %s" % (
-                          levels, "x".join(map(str, p.n_at(levels - 1))), nodes, dt, [r.iters for r in res])}
+                      "JCG + EXP_true region, %d repetitions, %.1f s, iterations %s" % (
+                          levels, "x".join(map(str, p.n_at(levels - 1))), nodes, reps, dt,
+                          [r.iters for r in res])}
 
 
 def precision_comparison(E, torch, name="high-contrast-513x257x257", steps=3):
