@@ -501,6 +501,29 @@ def main():
             print("bench: eps %g: %.2f ms/step, Ut order %.2f" % (e4, 1e3 * dt4, order), file=sys.stderr, flush=True)
             if order >= 3.8:
                 break
+        # the same finest tolerance as a per-level schedule, each coarser grid
+        # 16 times looser (ecmg_solve_levels): the coarse levels get cheap
+        sched = E.tolerance_schedule(problem.levels, fourth["eps"], 16.0)
+        s.solve_levels(sched)
+        s.extrapolate(L, out=False)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(2):
+            infs = s.solve_levels(sched)
+            s.extrapolate(L, out=False)
+        torch.cuda.synchronize()
+        dts = (time.perf_counter() - t1) / 2
+        errs = {}
+        for l in (L - 1, L):
+            ue = exact_on_device(problem, problem.n_at(l))
+            s.extrapolate(l, out=False)
+            errs["Ut_max_L%d" % l], _ = s.norms(l, E.VEC_UTILDE, minus=ue)
+            del ue
+        fourth["schedule16"] = {"rel_tol": sched, "ms_per_step": 1e3 * dts,
+                                "Ut_order_max": math.log2(errs["Ut_max_L%d" % (L - 1)] / errs["Ut_max_L%d" % L]),
+                                "iters": [i["iters"] for i in infs], **errs}
+        print("bench: schedule (finest eps %g, ratio 16): %.2f ms/step, Ut order %.2f" %
+              (fourth["eps"], 1e3 * dts, fourth["schedule16"]["Ut_order_max"]), file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
 
     s.close()

@@ -209,6 +209,20 @@ int ecmg_solve(ecmg_ctx *ctx, double rel_tol, ecmg_level_info *info);
  * (iters has `levels` entries; entries 0 and 1 are ignored). */
 int ecmg_solve_fixed(ecmg_ctx *ctx, const int32_t *iters, ecmg_level_info *info);
 
+/* As ecmg_solve with a tolerance per level: JCG on level l >= 2 stops when
+ * ||r||_2 <= rel_tol[l] ||f_h||_2 (rel_tol has `levels` entries, each >= 0;
+ * entries 0 and 1 are ignored).  Section 5 notes that a uniform tolerance lets
+ * U~ lose fourth order on fine grids, since it combines two second-order
+ * solutions that must both be accurate; a schedule tightened towards the finest
+ * grid (ecmg_tolerance_schedule) keeps the coarse levels cheap. */
+int ecmg_solve_levels(ecmg_ctx *ctx, const double *rel_tol, ecmg_level_info *info);
+
+/* Host only: rel_tol[l] = min(1, eps_finest * ratio^(levels - 1 - l)) for
+ * l >= 2 (repeated products), 0 for the two DSOLVE grids; ratio 1 is the
+ * uniform tolerance, ratio 16 loosens each coarser grid by the factor its h^4
+ * grows.  ECMG_EINVAL for levels < 3, eps_finest <= 0 or ratio < 1. */
+int ecmg_tolerance_schedule(int32_t levels, double eps_finest, double ratio, double *rel_tol);
+
 /* EXP_true (Section 4.2.1, eqs. t1 and chenlin; face and body centres as the
  * mean along their diagonals): U~_l from u_l and u_{l-1}, for 1 <= level <
  * levels (-1 = finest).  host_out: NULL (the call returns once the work is

@@ -348,6 +348,22 @@ def cascadic_schedule(levels: int, m_L: int, beta: float) -> List[int]:
     return out
 
 
+def tolerance_schedule(levels: int, eps_finest: float, ratio: float) -> List[float]:
+    """Per-level relative tolerances: eps_finest on the finest grid, each coarser
+    JCG grid ``ratio`` times looser (capped at 1), 0 on the DSOLVE grids.  The
+    paper fixes no schedule (Section 5 only says fine grids need a stricter
+    tolerance); this geometric one is the library's."""
+    if levels < 3 or not (eps_finest > 0.0) or not (ratio >= 1.0):
+        raise ValueError("need levels >= 3, eps_finest > 0, ratio >= 1")
+    out = [0.0, 0.0]
+    for l in range(2, levels):
+        e = float(eps_finest)
+        for _ in range(l, levels - 1):
+            e *= ratio
+        out.append(min(e, 1.0))
+    return out
+
+
 SERENDIPITY20 = 0   # Section 4.3: 20 extrapolated nodes + serendipity (eq. inter)
 LAGRANGE27 = 1      # the Remark after eq. inter: 27 nodes + tri-quadratic Lagrange
 
@@ -452,8 +468,10 @@ def cascade(problem: Problem, eps: Optional[float] = None, fixed_iters: Optional
     and U~ = EXP_true(u_l, u_{l-1}).  ``fixed_iters[l]`` (l >= 2) replaces the
     stopping test with an exact iteration count.  ``method=CG_METHOD`` is
     ECMG_cg (Section 4.1); with ``fixed_iters=cascadic_schedule(...)`` it is the
-    original ECMG of Algorithm 3."""
+    original ECMG of Algorithm 3.  ``eps`` may be a sequence, one relative
+    tolerance per level (the per-level schedule Section 5 motivates)."""
     eps = problem.eps if eps is None else eps
+    eps_at = (lambda l: float(eps[l])) if isinstance(eps, (list, tuple, np.ndarray)) else (lambda l: float(eps))
     Lt = problem.levels
     out: List[LevelResult] = []
     us: List[np.ndarray] = []
@@ -466,7 +484,7 @@ def cascade(problem: Problem, eps: Optional[float] = None, fixed_iters: Optional
             W = exp_finite(lv.grid, us[l - 1], us[l - 2], variant)
             x0 = np.where(lv.dmask == 1, lv.gD, W)      # JCG starts from W with g_D imposed
             fi = -1 if fixed_iters is None else int(fixed_iters[l])
-            jr = jcg(lv, x0, eps, max_iter=max_iter, fixed_iters=fi, method=method)
+            jr = jcg(lv, x0, eps_at(l), max_iter=max_iter, fixed_iters=fi, method=method)
             if jr.status == -4:
                 raise RuntimeError("oracle JCG breakdown on level %d" % l)
             u = jr.x

@@ -86,7 +86,8 @@ EXPORTS = ["ecmg_default_options", "ecmg_create", "ecmg_setup", "ecmg_solve", "e
            "ecmg_reset_kernel_times", "ecmg_last_error", "ecmg_destroy", "ecmg_solve_batch",
            "ecmg_extrapolate_batch", "ecmg_server_create", "ecmg_server_submit", "ecmg_server_step",
            "ecmg_server_poll", "ecmg_server_stats", "ecmg_server_reset_stats", "ecmg_server_destroy",
-           "ecmg_autotune", "ecmg_tune_lookup", "ecmg_set_timing", "ecmg_cascadic_schedule"]
+           "ecmg_autotune", "ecmg_tune_lookup", "ecmg_set_timing", "ecmg_cascadic_schedule",
+           "ecmg_solve_levels", "ecmg_tolerance_schedule"]
 
 _lib = None
 
@@ -127,6 +128,8 @@ def load_library(path: str = LIB_PATH):
     L.ecmg_reset_kernel_times.argtypes = [P]
     L.ecmg_set_timing.argtypes = [P, i32]
     L.ecmg_cascadic_schedule.argtypes = [i32, i32, dbl, P]
+    L.ecmg_solve_levels.argtypes = [P, P, P]
+    L.ecmg_tolerance_schedule.argtypes = [i32, dbl, dbl, P]
     L.ecmg_last_error.argtypes = [P]
     L.ecmg_last_error.restype = ctypes.c_char_p
     L.ecmg_destroy.argtypes = [P]
@@ -170,6 +173,17 @@ def cascadic_schedule(levels: int, m_L: int, beta: float) -> List[int]:
     L = load_library()
     out = (ctypes.c_int32 * int(levels))()
     rc = L.ecmg_cascadic_schedule(int(levels), int(m_L), float(beta), out)
+    if rc != OK:
+        raise EcmgError(rc, (L.ecmg_last_error(None) or b"").decode())
+    return list(out)
+
+
+def tolerance_schedule(levels: int, eps_finest: float, ratio: float) -> List[float]:
+    """Per-level relative tolerances for Solver.solve_levels: 0 on the two
+    DSOLVE grids, min(1, eps_finest * ratio^(levels-1-l)) on level l (host only)."""
+    L = load_library()
+    out = (ctypes.c_double * int(levels))()
+    rc = L.ecmg_tolerance_schedule(int(levels), float(eps_finest), float(ratio), out)
     if rc != OK:
         raise EcmgError(rc, (L.ecmg_last_error(None) or b"").decode())
     return list(out)
@@ -345,6 +359,15 @@ class Solver:
     def solve(self, rel_tol: float, allow_fail: bool = False) -> List[dict]:
         info = self._infos()
         rc = self.L.ecmg_solve(self.h, float(rel_tol), info)
+        if not allow_fail:
+            self._check(rc)
+        return [i.as_dict() for i in info]
+
+    def solve_levels(self, rel_tol: Sequence[float], allow_fail: bool = False) -> List[dict]:
+        """ecmg_solve with one relative tolerance per level (entries 0, 1 ignored)."""
+        info = self._infos()
+        arr = (ctypes.c_double * self.levels)(*[float(v) for v in rel_tol])
+        rc = self.L.ecmg_solve_levels(self.h, arr, info)
         if not allow_fail:
             self._check(rc)
         return [i.as_dict() for i in info]

@@ -1316,11 +1316,15 @@ static int apply_tune_cache(ecmg_ctx *c) {
 // levels' results come out of their pinned slots.  A mixed-precision level
 // drives its outer refinement from the host, so the levels before it are
 // settled first.
-static int solve_impl(ecmg_ctx *c, double rel_tol, const int32_t *fixed, ecmg_level_info *info) {
+static int solve_impl(ecmg_ctx *c, double rel_tol, const int32_t *fixed, ecmg_level_info *info,
+                      const double *level_tol = nullptr) {
     if (!c) return fail(nullptr, ECMG_EINVAL, "ctx is NULL");
     if (!c->ready) return fail(c, ECMG_ESTATE, "ecmg_solve before ecmg_setup");
-    if (!fixed && !(rel_tol >= 0.0)) return fail(c, ECMG_EINVAL, "rel_tol = %g must be >= 0", rel_tol);
+    if (!fixed && !level_tol && !(rel_tol >= 0.0)) return fail(c, ECMG_EINVAL, "rel_tol = %g must be >= 0", rel_tol);
     const int n = c->nlev;
+    if (level_tol)
+        for (int l = 2; l < n; ++l)
+            if (!(level_tol[l] >= 0.0)) return fail(c, ECMG_EINVAL, "rel_tol[%d] = %g must be >= 0", l, level_tol[l]);
     std::vector<ecmg_level_info> li(n);
     std::vector<char> deferred(n, 0);        // JCG results still in the level's slot
     std::vector<int> cap(n, 0);              // their iteration caps
@@ -1354,7 +1358,7 @@ static int solve_impl(ecmg_ctx *c, double rel_tol, const int32_t *fixed, ecmg_le
         li[l].nz = L.g.nz;
         HIPCHK(c, hipEventRecord(c->lv_ev[2 * l], c->stream));
         int rc = ECMG_OK;
-        double tol = rel_tol * L.nf;
+        double tol = (level_tol && l >= 2 ? level_tol[l] : rel_tol) * L.nf;
         int max_iter = c->opt.max_iter, fx = fixed ? fixed[l] : -1;
         bool jcg = true;
         if (l < 2) {
@@ -1632,6 +1636,24 @@ int ecmg_solve(ecmg_ctx *c, double rel_tol, ecmg_level_info *info) { return solv
 int ecmg_solve_fixed(ecmg_ctx *c, const int32_t *iters, ecmg_level_info *info) {
     if (!iters) return fail(c, ECMG_EINVAL, "iters is NULL");
     return solve_impl(c, 0.0, iters, info);
+}
+
+int ecmg_solve_levels(ecmg_ctx *c, const double *rel_tol, ecmg_level_info *info) {
+    if (!rel_tol) return fail(c, ECMG_EINVAL, "rel_tol is NULL");
+    return solve_impl(c, 0.0, nullptr, info, rel_tol);
+}
+
+int ecmg_tolerance_schedule(int32_t levels, double eps_finest, double ratio, double *rel_tol) {
+    if (!rel_tol) return fail(nullptr, ECMG_EINVAL, "ecmg_tolerance_schedule: rel_tol is NULL");
+    if (levels < 3 || !(eps_finest > 0.0) || !(ratio >= 1.0) || !std::isfinite(eps_finest) || !std::isfinite(ratio))
+        return fail(nullptr, ECMG_EINVAL, "ecmg_tolerance_schedule: need levels >= 3, eps_finest > 0, ratio >= 1");
+    rel_tol[0] = rel_tol[1] = 0.0;                // DSOLVE grids: options.dsolve_tol applies
+    for (int l = 2; l < levels; ++l) {
+        double e = eps_finest;
+        for (int k = l; k < levels - 1; ++k) e *= ratio;
+        rel_tol[l] = std::min(e, 1.0);
+    }
+    return ECMG_OK;
 }
 
 static int check_level(ecmg_ctx *c, int32_t *level, int min_level) {

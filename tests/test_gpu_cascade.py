@@ -171,3 +171,20 @@ def test_dsolve_dense_matches_jcg_dsolve(orc, ecmg):
         assert _rel(out[8192][1][l], out[0][1][l]) <= 1e-12, l
     ref = orc.dsolve(orc.discretize(p, 1))
     assert _rel(out[8192][1][1], ref) <= 1e-12
+
+
+@pytest.mark.parametrize("persistent", [300000, 0], ids=["persistent", "tiled"])
+def test_per_level_tolerance_schedule(orc, ecmg, persistent):
+    """ecmg_solve_levels with a schedule tightened towards the finest grid
+    takes the oracle's per-level iteration counts and iterates."""
+    p = workloads.variable_beta_robin_cube(levels=5)
+    sched = ecmg.tolerance_schedule(p.levels, 1e-11, 16.0)
+    ref = orc.cascade(p, eps=sched, errors=False)
+    with ecmg.Solver(persistent_nodes=persistent) as s:
+        s.setup(p)
+        infos = s.solve_levels(sched)
+        u = [s.get(l, ecmg.VEC_U) for l in range(p.levels)]
+    assert [i["iters"] for i in infos[2:]] == [r.iters for r in ref[2:]]
+    for l in range(2, p.levels):
+        assert infos[l]["rre"] <= sched[l]
+        assert _rel(u[l], ref[l].u) <= 1e-10, (l, _rel(u[l], ref[l].u))

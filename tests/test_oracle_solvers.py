@@ -84,3 +84,37 @@ def test_stopping_norm_includes_dirichlet_rows(orc):
     lv = orc.discretize(p, 0)
     want = np.sqrt(np.sum(lv.b[lv.dmask == 0] ** 2) + np.sum(lv.gD[lv.dmask == 1] ** 2))
     assert lv.nf == pytest.approx(want, rel=1e-14)
+
+
+def test_per_level_tolerance_reduces_to_uniform(orc):
+    """A per-level tolerance list with every entry equal is the uniform
+    tolerance of Algorithm 4: the same iterations and bit-identical iterates."""
+    import workloads as wl
+    p = wl.paper_problem1(levels=4, eps=1e-8)
+    a = orc.cascade(p, eps=1e-8, errors=False)
+    b = orc.cascade(p, eps=[1e-8] * p.levels, errors=False)
+    for ra, rb in zip(a, b):
+        assert ra.iters == rb.iters
+        assert np.array_equal(ra.u, rb.u)
+
+
+def test_per_level_tolerance_applies_per_level(orc):
+    """Tightening only the finest level's tolerance leaves the coarser levels
+    as they were and stops the finest at its own tolerance."""
+    import workloads as wl
+    p = wl.paper_problem1(levels=4, eps=1e-8)
+    a = orc.cascade(p, eps=1e-8, errors=False)
+    sched = orc.tolerance_schedule(p.levels, 1e-11, 1000.0)     # 1e-8 on level 2, 1e-11 on level 3
+    assert sched[2] == pytest.approx(1e-8) and sched[3] == 1e-11
+    b = orc.cascade(p, eps=sched, errors=False)
+    assert b[2].iters == a[2].iters and np.array_equal(b[2].u, a[2].u)
+    assert b[3].iters > a[3].iters
+    assert b[3].rre <= 1e-11 < a[3].rre
+
+
+def test_tolerance_schedule_closed_form(orc):
+    assert orc.tolerance_schedule(5, 1e-10, 16.0) == [0.0, 0.0, pytest.approx(2.56e-8), pytest.approx(1.6e-9), 1e-10]
+    assert orc.tolerance_schedule(4, 0.5, 4.0) == [0.0, 0.0, 1.0, 0.5]          # capped at 1
+    assert orc.tolerance_schedule(3, 1e-6, 1.0) == [0.0, 0.0, 1e-6]
+    with pytest.raises(ValueError):
+        orc.tolerance_schedule(4, 0.0, 2.0)

@@ -28,3 +28,14 @@ def test_schedule_closed_form(ecmg):
 def test_schedule_rejects_bad_arguments(ecmg, args):
     with pytest.raises(ecmg.EcmgError):
         ecmg.cascadic_schedule(*args)
+
+
+@pytest.mark.parametrize("levels,eps,ratio", [(5, 1e-10, 16.0), (4, 0.5, 4.0), (7, 1e-8, 1.0), (6, 3e-9, 2.5)])
+def test_tolerance_schedule_matches_oracle(ecmg, levels, eps, ratio):
+    assert ecmg.tolerance_schedule(levels, eps, ratio) == oracle.tolerance_schedule(levels, eps, ratio)
+
+
+@pytest.mark.parametrize("args", [(2, 1e-8, 2.0), (5, 0.0, 2.0), (5, 1e-8, 0.5), (5, float("inf"), 2.0)])
+def test_tolerance_schedule_rejects_bad_arguments(ecmg, args):
+    with pytest.raises(ecmg.EcmgError):
+        ecmg.tolerance_schedule(*args)
