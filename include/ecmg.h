@@ -366,7 +366,7 @@ int ecmg_set_timing(ecmg_ctx *ctx, int32_t mask);
  * converged solve on ctx, capped at 4000, or 8 before any) from the level's
  * current iterate,
  * which is restored, under the built-in configuration and each candidate
- * (tiled passes with z-chunks of 4, 8, 16, 32 or 64 planes; the persistent
+ * (tiled passes with z-chunks of 1, 2, 4, 8, 16, 32 or 64 planes; the persistent
  * kernel with segments of 2 or 4 nodes and at most 32, 64, 128 or 256 workgroups, for
  * grids of at most 20,000,000 nodes), keeps the fastest for later solves on
  * ctx and, if cache_path (or options.tune_cache, or $ECMG_TUNE_CACHE) names a

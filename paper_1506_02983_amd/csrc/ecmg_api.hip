@@ -1865,7 +1865,7 @@ int ecmg_autotune(ecmg_ctx *c, int32_t iters, const char *cache_path, ecmg_tune_
         // the run length: as asked, else the level's iterations in the last solve, else 8
         iters = fixed_iters > 0 ? fixed_iters : (L.last_iters > 0 ? std::min(L.last_iters, 4000) : 8);
         std::vector<Cand> cands{{-1, 0, 0, 0}};   // the built-in configuration first
-        for (int kz : {4, 8, 16, 32, 64})
+        for (int kz : {1, 2, 4, 8, 16, 32, 64})
             if (kz <= L.g.nz + 1) cands.push_back({0, kz, 0, 0});
         if (persist_possible(c, L.g) && L.g.nreal <= 20000000)
             for (int seg : {2, 4})
