@@ -332,11 +332,12 @@ __global__ void __launch_bounds__(NT, STENCIL_WAVES_PER_EU) k_stencil(const Sten
             S.ea[r] = S.eb[r] = 0;
             if (MODE == MODE_APPLY || MODE == MODE_PASSA0 || off[r] < 0 || k < 0 || k > g.nz) continue;
             const int64_t id = (int64_t)off[r] + sxy * k;
+            // epilogue inputs are read once: non-temporal
             if (MODE == MODE_PASSA) {
-                if (!first) S.ea[r] = a.x[id];
+                if (!first) S.ea[r] = __builtin_nontemporal_load(a.x + id);
             } else {
-                S.ea[r] = a.F[id];
-                S.eb[r] = a.dinv[id];
+                S.ea[r] = __builtin_nontemporal_load(a.F + id);
+                S.eb[r] = __builtin_nontemporal_load(a.dinv + id);
             }
         }
     };
@@ -484,21 +485,23 @@ __global__ void __launch_bounds__(NT, STENCIL_WAVES_PER_EU) k_stencil(const Sten
             if (k == g.nz && g.ft[5] == ECMG_ROBIN) q += robin_term<2>(g, 5, a.alpha[5], i, j, g.nx, g.ny, sv, s0, s1, s2, lj, li);
             const bool dir = is_dirichlet(g, i, j, k);
             const int64_t id = (int64_t)off[r] + sxy * k;
+            // outputs: coalesced rows, written once per pass (non-temporal)
             if (MODE == MODE_APPLY) {
-                a.q[id] = dir ? (T)0 : q;
+                __builtin_nontemporal_store(dir ? (T)0 : q, a.q + id);
             } else if (MODE == MODE_INIT) {
                 const T rv = dir ? (T)0 : xa_cur[r] - q;
-                a.r[id] = rv;
+                __builtin_nontemporal_store(rv, a.r + id);
                 const T z = xb_cur[r] * rv;
-                if (a.p_init) a.p1[id] = z;           // p_0 for MODE_PASSA0
+                if (a.p_init) __builtin_nontemporal_store(z, a.p1 + id);   // p_0 for MODE_PASSA0
                 acc0 += (double)rv * (double)z;
                 acc1 += (double)rv * (double)rv;
             } else {
                 const T pc = sv[s1][lj][li];
                 const T qv = dir ? (T)0 : q;
-                if (MODE == MODE_PASSA) pout[id] = pc;
-                a.q[id] = qv;
-                if (MODE == MODE_PASSA && !first) a.x[id] = xa_cur[r] + alpha_prev * pold_cur[r];
+                if (MODE == MODE_PASSA) __builtin_nontemporal_store(pc, pout + id);
+                __builtin_nontemporal_store(qv, a.q + id);
+                if (MODE == MODE_PASSA && !first)
+                    __builtin_nontemporal_store(xa_cur[r] + alpha_prev * pold_cur[r], a.x + id);
                 acc0 += (double)pc * (double)qv;
             }
         }
