@@ -220,6 +220,12 @@ def batched(E, torch, n_boxes=512, steps=3):
     setup_s = time.perf_counter() - t0
     nodes = sum(p.nodes_at(p.levels - 1) for p in probs)
     eps = probs[0].eps
+    t0 = time.perf_counter()
+    tuned = E.autotune_batch(solvers, eps)            # untimed: every box takes the fastest setting
+    tune_s = time.perf_counter() - t0
+    print("bench: batched autotune %.2f s: %d nodes per workgroup, segments of %d (%.1f -> %.1f ms)" % (
+        tune_s, tuned["nodes_per_workgroup"], tuned["seg"], tuned["us_default"] / 1e3, tuned["us_best"] / 1e3),
+        file=sys.stderr, flush=True)
     E.solve_batch(solvers, eps)
     E.extrapolate_batch(solvers)
     torch.cuda.synchronize()
@@ -243,7 +249,7 @@ def batched(E, torch, n_boxes=512, steps=3):
             "boxes_per_s": n_boxes / dt, "unknowns_per_s": nodes / dt,
             "level_ms": [infos[0][l]["ms"] for l in range(3)],
             "finest_iters_mean": sum(it) / len(it), "finest_iters_max": max(it),
-            "sequential_ms_estimate": 1e3 * seq, "speedup_vs_sequential": seq / dt}
+            "sequential_ms_estimate": 1e3 * seq, "speedup_vs_sequential": seq / dt, "autotune": tuned}
 
 
 def serving(E, n_measured=200, n_warmup=20, rate=50.0, budget=200 * 10 ** 9):

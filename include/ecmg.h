@@ -376,6 +376,18 @@ int ecmg_set_timing(ecmg_ctx *ctx, int32_t mask);
  * for the duration of the call; synchronous. */
 int ecmg_autotune(ecmg_ctx *ctx, int32_t iters, const char *cache_path, ecmg_tune_result *out);
 
+/* Autotuner of the batched form (ecmg_solve_batch): times a batch solve of the
+ * n set-up contexts (rel_tol as in ecmg_solve_batch; the solutions are those of
+ * the last candidate's solve) under their current configuration and under each
+ * candidate -- about 2048, 4096, 8192, 16384 or 32768 nodes per workgroup of a
+ * box (at most 16 workgroups) with segments of 2 or 4 nodes -- and gives every
+ * context the fastest.  If cache_path (or ctxs[0]'s options.tune_cache) names a
+ * file, the choice is merged into it under "batch <precision>", and a context
+ * created with options.autotune = 1 takes it at setup.  out: NULL or one entry
+ * (level -1, path 2, seg, nwg = nodes per workgroup).  Synchronous. */
+int ecmg_autotune_batch(ecmg_ctx *const *ctxs, int32_t n, double rel_tol, const char *cache_path,
+                        ecmg_tune_result *out);
+
 /* Host only (no device needed): the choice the tuning cache at `path` holds for
  * a JCG level of nx x ny x nz elements at `precision`.  ECMG_ENOENT if the file
  * or the entry does not exist, ECMG_EINVAL if the file is not a tuning cache. */

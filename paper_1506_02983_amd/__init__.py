@@ -87,7 +87,7 @@ EXPORTS = ["ecmg_default_options", "ecmg_create", "ecmg_setup", "ecmg_solve", "e
            "ecmg_extrapolate_batch", "ecmg_server_create", "ecmg_server_submit", "ecmg_server_step",
            "ecmg_server_poll", "ecmg_server_stats", "ecmg_server_reset_stats", "ecmg_server_destroy",
            "ecmg_autotune", "ecmg_tune_lookup", "ecmg_set_timing", "ecmg_cascadic_schedule",
-           "ecmg_solve_levels", "ecmg_tolerance_schedule"]
+           "ecmg_solve_levels", "ecmg_tolerance_schedule", "ecmg_autotune_batch"]
 
 _lib = None
 
@@ -129,6 +129,7 @@ def load_library(path: str = LIB_PATH):
     L.ecmg_set_timing.argtypes = [P, i32]
     L.ecmg_cascadic_schedule.argtypes = [i32, i32, dbl, P]
     L.ecmg_solve_levels.argtypes = [P, P, P]
+    L.ecmg_autotune_batch.argtypes = [P, i32, dbl, ctypes.c_char_p, P]
     L.ecmg_tolerance_schedule.argtypes = [i32, dbl, dbl, P]
     L.ecmg_last_error.argtypes = [P]
     L.ecmg_last_error.restype = ctypes.c_char_p
@@ -482,6 +483,24 @@ def solve_batch(solvers: Sequence["Solver"], rel_tol: float, allow_fail: bool = 
         out.append([info[k + l].as_dict() for l in range(s.levels)])
         k += s.levels
     return out
+
+
+def autotune_batch(solvers: Sequence["Solver"], rel_tol: float, cache: Optional[str] = None) -> dict:
+    """ecmg_autotune_batch: time the batched solve of these solvers under the
+    candidate nodes-per-workgroup and segment settings, keep the fastest on all
+    of them (and in the JSON cache)."""
+    L = load_library()
+    n = len(solvers)
+    handles = (ctypes.c_void_p * n)(*[s.h for s in solvers])
+    r = TuneResult()
+    rc = L.ecmg_autotune_batch(handles, n, float(rel_tol), cache.encode() if cache else None, ctypes.byref(r))
+    if rc != OK:
+        msg = L.ecmg_last_error(solvers[0].h)
+        raise EcmgError(rc, (msg or b"").decode())
+    d = r.as_dict()
+    d["path"] = "batch"
+    d["nodes_per_workgroup"] = d.pop("nwg")
+    return d
 
 
 def extrapolate_batch(solvers: Sequence["Solver"]) -> None:

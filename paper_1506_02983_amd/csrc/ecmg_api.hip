@@ -77,6 +77,7 @@ struct ecmg_ctx {
     int persist_nwg = 256;                     // persistent kernel: most workgroups per task
     int queue_blocks = 0;                      // co-resident workgroups of the queue kernel
     int batch_npw = 8192;                      // batched solves: nodes per workgroup of a box
+    int batch_seg = 0;                         // batched solves: nodes per segment (0 = by size)
     PersistentTask *d_task = nullptr;          // device copy of one task
     std::string tune_cache;                    // tuning cache path ("" = none)
     std::string device_name;                   // "<arch> <CUs> CUs", recorded with tuning choices
@@ -1303,9 +1304,14 @@ static int apply_tune_cache(ecmg_ctx *c) {
     for (int l = 2; l < c->nlev; ++l) {
         const Level &L = c->lv[l];
         auto it = entries.find(tune_key(c->opt.precision, L.g.nx, L.g.ny, L.g.nz));
-        if (it == entries.end()) continue;
+        if (it == entries.end() || it->second.path > 1) continue;
         const TuneEntry &e = it->second;
         CHK(apply_choice(c, l, e.path, e.kz, e.seg, e.nwg));
+    }
+    auto bt = entries.find(tune_key_batch(c->opt.precision));   // the batched solve's choice
+    if (bt != entries.end() && bt->second.path == 2) {
+        c->batch_npw = bt->second.nwg;
+        c->batch_seg = bt->second.seg;
     }
     return ECMG_OK;
 }
@@ -1450,7 +1456,8 @@ static PersistentTask batch_task(ecmg_ctx *c, int l, double tol_abs, int max_ite
     t.wg0 = 0;
     // about batch_npw nodes per workgroup, at most 16 workgroups per box
     t.nwg = (int)std::max<int64_t>(1, std::min<int64_t>(L.g.nreal / c->batch_npw, 16));
-    const int seg = c->persist_seglen > 0 ? c->persist_seglen : (L.g.nreal < 131072 ? 2 : 4);
+    const int seg = c->batch_seg > 0 ? c->batch_seg
+                    : c->persist_seglen > 0 ? c->persist_seglen : (L.g.nreal < 131072 ? 2 : 4);
     t.seglen = seg >= 4 ? 4 : (seg >= 2 ? 2 : 1);         // the kernel's instantiations
     return t;
 }
@@ -1942,6 +1949,75 @@ int ecmg_autotune(ecmg_ctx *c, int32_t iters, const char *cache_path, ecmg_tune_
         std::string err;
         const int wr = tune_cache_write(path, c->device_name, entries, &err);
         if (wr != ECMG_OK) return fail(c, wr, "%s", err.c_str());
+    }
+    return ECMG_OK;
+}
+
+int ecmg_autotune_batch(ecmg_ctx *const *ctxs, int32_t n, double rel_tol, const char *cache_path,
+                        ecmg_tune_result *out) {
+    if (!ctxs || n < 1 || !ctxs[0]) return fail(nullptr, ECMG_EINVAL, "ctxs is NULL or n = %d < 1", n);
+    ecmg_ctx *c0 = ctxs[0];
+    for (int i = 0; i < n; ++i)
+        if (!ctxs[i] || !ctxs[i]->ready) return fail(c0, ECMG_ESTATE, "ecmg_autotune_batch: ctxs[%d] not set up", i);
+    const std::string path = cache_path ? std::string(cache_path) : c0->tune_cache;
+    struct Cand { int npw, seg; };
+    std::vector<Cand> cands{{c0->batch_npw, c0->batch_seg}};   // the current configuration first
+    for (int npw : {2048, 4096, 8192, 16384, 32768})
+        for (int seg : {2, 4}) cands.push_back({npw, seg});
+    auto set_all = [&](const Cand &cd) {
+        for (int i = 0; i < n; ++i) {
+            ctxs[i]->batch_npw = cd.npw;
+            ctxs[i]->batch_seg = cd.seg;
+        }
+    };
+    double best = 0.0, us_default = 0.0;
+    int bi = -1, rc = ECMG_OK;
+    for (size_t ci = 0; ci < cands.size() && rc == ECMG_OK; ++ci) {
+        set_all(cands[ci]);
+        double us = -1.0;
+        for (int rep = 0; rep < 2; ++rep) {          // one untimed solve, one timed (synchronous)
+            const auto t0 = std::chrono::steady_clock::now();
+            const int sr = ecmg_solve_batch(ctxs, n, rel_tol, nullptr);
+            const auto t1 = std::chrono::steady_clock::now();
+            if (sr == ECMG_EDEVICE || sr == ECMG_EINVAL || sr == ECMG_ESTATE || sr == ECMG_ENOMEM) {
+                rc = sr;
+                break;
+            }
+            us = sr == ECMG_OK ? std::chrono::duration<double, std::micro>(t1 - t0).count() : -1.0;
+        }
+        if (rc != ECMG_OK) break;
+        if (ci == 0) us_default = us;
+        if (us > 0.0 && (bi < 0 || us < best)) {
+            best = us;
+            bi = (int)ci;
+        }
+    }
+    const Cand chosen = bi >= 0 ? cands[bi] : cands[0];
+    set_all(chosen);
+    if (rc != ECMG_OK) return rc;
+    if (out) {
+        *out = ecmg_tune_result{};
+        out->level = -1;
+        out->path = 2;
+        out->seg = chosen.seg;
+        out->nwg = chosen.npw;
+        out->candidates = (int32_t)cands.size();
+        out->us_default = us_default;
+        out->us_best = bi >= 0 ? best : us_default;
+    }
+    if (!path.empty() && bi >= 0) {
+        std::map<std::string, TuneEntry> entries;
+        std::string dev, err;
+        if (tune_cache_read(path, &dev, &entries, &err) != ECMG_OK || dev != c0->device_name) entries.clear();
+        TuneEntry e;
+        e.path = 2;
+        e.seg = chosen.seg > 0 ? chosen.seg : 2;
+        e.nwg = chosen.npw;
+        e.us_default = us_default;
+        e.us_best = best;
+        entries[tune_key_batch(c0->opt.precision)] = e;
+        const int wr = tune_cache_write(path, c0->device_name, entries, &err);
+        if (wr != ECMG_OK) return fail(c0, wr, "%s", err.c_str());
     }
     return ECMG_OK;
 }

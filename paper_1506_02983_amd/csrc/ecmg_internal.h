@@ -230,14 +230,17 @@ struct Ctx;
 
 // ---- autotuner: per-level choices and their JSON cache (tune_cache.cpp) ----
 struct TuneEntry {
-    int path = 0;                     // 0 tiled passes, 1 persistent kernel
+    int path = 0;                     // 0 tiled passes, 1 persistent kernel, 2 batched solve
     int kz = 0;                       // tiled: planes per z-chunk
-    int seg = 0, nwg = 0;             // persistent: nodes per segment, most workgroups
-    double us_default = 0.0;          // microseconds per JCG iteration, built-in choice
-    double us_best = 0.0;             // ... the chosen configuration
+    int seg = 0, nwg = 0;             // persistent: nodes per segment, most workgroups;
+                                      // batched: nodes per segment, nodes per workgroup
+    double us_default = 0.0;          // microseconds per JCG iteration (batched: per
+    double us_best = 0.0;             // batch solve), built-in and chosen configuration
 };
 // cache key of a JCG level: precision and elements per axis
 std::string tune_key(int precision, int nx, int ny, int nz);
+// cache key of the batched solve's configuration
+std::string tune_key_batch(int precision);
 // ECMG_OK, ECMG_ENOENT (no file) or ECMG_EINVAL (not a tuning cache); entries
 // are added to *out, the device string of the file goes to *device
 int tune_cache_read(const std::string &path, std::string *device, std::map<std::string, TuneEntry> *out,

@@ -3,8 +3,10 @@
 // The file holds one object:
 //   {"format": "ecmg-tune-1", "device": "<name> <compute units> CUs",
 //    "levels": {"<precision> <nx>x<ny>x<nz>": {"path": "tiled" | "persistent",
-//               "kz": K, "seg": S, "nwg": W, "us_default": D, "us_best": B}, ...}}
-// keyed by the level's precision and elements per axis.  The reader accepts any
+//               "kz": K, "seg": S, "nwg": W, "us_default": D, "us_best": B}, ...,
+//               "batch <precision>": {"path": "batch", "seg": S, "nwg": NPW, ...}}}
+// keyed by the level's precision and elements per axis (the batched solve's
+// entry: its segment length and nodes per workgroup).  The reader accepts any
 // JSON whose top level has that shape (other keys ignored); the writer replaces
 // the file through a temporary file and a rename, so a reader never sees half
 // of it.
@@ -144,6 +146,8 @@ double dbl_field(const JVal &o, const char *k) {
 
 }  // namespace
 
+std::string tune_key_batch(int precision) { return precision == ECMG_MIXED ? "batch mixed" : "batch fp64"; }
+
 std::string tune_key(int precision, int nx, int ny, int nz) {
     char b[96];
     std::snprintf(b, sizeof b, "%s %dx%dx%d", precision == ECMG_MIXED ? "mixed" : "fp64", nx, ny, nz);
@@ -182,7 +186,8 @@ int tune_cache_read(const std::string &path, std::string *device, std::map<std::
             const JVal &o = kv.second;
             const JVal *pth = o.get("path");
             TuneEntry e;
-            e.path = (pth && pth->kind == JVal::STR && pth->str == "persistent") ? 1 : 0;
+            const std::string pname = (pth && pth->kind == JVal::STR) ? pth->str : std::string();
+            e.path = pname == "persistent" ? 1 : (pname == "batch" ? 2 : 0);
             e.kz = num_field(o, "kz", 0);
             e.seg = num_field(o, "seg", 0);
             e.nwg = num_field(o, "nwg", 0);
@@ -190,6 +195,7 @@ int tune_cache_read(const std::string &path, std::string *device, std::map<std::
             e.us_best = dbl_field(o, "us_best");
             if (e.path == 0 && e.kz < 1) continue;            // not a usable choice
             if (e.path == 1 && (e.seg < 1 || e.nwg < 1)) continue;
+            if (e.path == 2 && (e.seg < 1 || e.nwg < 64)) continue;
             (*out)[kv.first] = e;
         }
     }
@@ -213,7 +219,8 @@ int tune_cache_write(const std::string &path, const std::string &device,
             std::snprintf(b, sizeof b,
                           "%s\n  \"%s\": {\"path\": \"%s\", \"kz\": %d, \"seg\": %d, \"nwg\": %d, "
                           "\"us_default\": %.3f, \"us_best\": %.3f}",
-                          first ? "" : ",", kv.first.c_str(), e.path == 1 ? "persistent" : "tiled", e.kz, e.seg,
+                          first ? "" : ",", kv.first.c_str(),
+                          e.path == 2 ? "batch" : (e.path == 1 ? "persistent" : "tiled"), e.kz, e.seg,
                           e.nwg, e.us_default, e.us_best);
             f << b;
             first = false;

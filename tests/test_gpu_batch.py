@@ -6,6 +6,8 @@ its own bit for bit (batch invariance); against the single-problem solver
 (multi-workgroup persistent kernel, different summation order) and the oracle
 the per-level iteration counts agree and the iterates match to 1e-12 relative
 in the max norm, the normal-mode parity rule."""
+import json
+
 import numpy as np
 import pytest
 
@@ -85,3 +87,34 @@ def test_batch_errors(ecmg, boxes):
     assert e.value.code == ecmg.EINVAL
     s.close()
     t.close()
+
+
+def test_batch_autotune_and_cache(ecmg, boxes, tmp_path):
+    """The batched autotuner keeps the fastest nodes-per-workgroup / segment
+    setting on every box; the iteration counts stay those of the untuned batch
+    (every setting runs the same recurrences), and boxes set up with
+    autotune = 1 from its cache solve bit for bit like the tuned ones."""
+    cache = str(tmp_path / "tune.json")
+    infos0, out0 = _solve_batch(ecmg, boxes, 1e-8)
+    solvers = [ecmg.Solver().setup(p) for p in boxes]
+    res = ecmg.autotune_batch(solvers, 1e-8, cache=cache)
+    assert res["path"] == "batch" and res["candidates"] >= 2
+    assert 0.0 < res["us_best"] <= res["us_default"]
+    assert res["nodes_per_workgroup"] in (2048, 4096, 8192, 16384, 32768)
+    infos = ecmg.solve_batch(solvers, 1e-8)
+    out = [s.get(p.levels - 1, ecmg.VEC_U) for s, p in zip(solvers, boxes)]
+    for s in solvers:
+        s.close()
+    for i in range(len(boxes)):
+        assert [x["iters"] for x in infos[i]][2:] == [x["iters"] for x in infos0[i]][2:], i
+        assert _rel(out[i], out0[i][0]) <= 1e-10, i
+    with open(cache) as fh:
+        entry = json.load(fh)["levels"]["batch fp64"]
+    assert entry["path"] == "batch" and entry["nwg"] == res["nodes_per_workgroup"]
+    again = [ecmg.Solver(autotune=1, tune_cache=cache).setup(p) for p in boxes]
+    ecmg.solve_batch(again, 1e-8)
+    out2 = [s.get(p.levels - 1, ecmg.VEC_U) for s, p in zip(again, boxes)]
+    for s in again:
+        s.close()
+    for i in range(len(boxes)):
+        assert np.array_equal(out2[i], out[i]), i

@@ -46,3 +46,15 @@ def test_lookup_rejects_non_cache(ecmg, tmp_path, text):
     with pytest.raises(ecmg.EcmgError) as e:
         ecmg.tune_lookup(path, (8, 8, 8))
     assert e.value.code == ecmg.EINVAL
+
+
+def test_batch_entry_is_kept_apart_from_levels(ecmg, tmp_path):
+    """A cache holding the batched solve's entry ("batch fp64", path "batch")
+    still serves level lookups, and the batch entry is not taken for a level."""
+    path = tmp_path / "tune.json"
+    path.write_text(json.dumps({"format": "ecmg-tune-1", "device": "x", "levels": {
+        "fp64 64x64x64": {"path": "tiled", "kz": 4, "seg": 0, "nwg": 0, "us_default": 2.0, "us_best": 1.0},
+        "batch fp64": {"path": "batch", "kz": 0, "seg": 2, "nwg": 4096, "us_default": 9.0, "us_best": 8.0}}}))
+    r = ecmg.tune_lookup(str(path), (64, 64, 64))
+    assert r["path"] == "tiled" and r["kz"] == 4
+    assert ecmg.tune_lookup(str(path), (8, 8, 8)) is None
