@@ -2011,7 +2011,7 @@ int ecmg_autotune_batch(ecmg_ctx *const *ctxs, int32_t n, double rel_tol, const 
         if (tune_cache_read(path, &dev, &entries, &err) != ECMG_OK || dev != c0->device_name) entries.clear();
         TuneEntry e;
         e.path = 2;
-        e.seg = chosen.seg > 0 ? chosen.seg : 2;
+        e.seg = chosen.seg;                            // 0: by box size
         e.nwg = chosen.npw;
         e.us_default = us_default;
         e.us_best = best;

@@ -233,7 +233,8 @@ struct TuneEntry {
     int path = 0;                     // 0 tiled passes, 1 persistent kernel, 2 batched solve
     int kz = 0;                       // tiled: planes per z-chunk
     int seg = 0, nwg = 0;             // persistent: nodes per segment, most workgroups;
-                                      // batched: nodes per segment, nodes per workgroup
+                                      // batched: nodes per segment (0: by box size),
+                                      // nodes per workgroup
     double us_default = 0.0;          // microseconds per JCG iteration (batched: per
     double us_best = 0.0;             // batch solve), built-in and chosen configuration
 };

@@ -195,7 +195,7 @@ int tune_cache_read(const std::string &path, std::string *device, std::map<std::
             e.us_best = dbl_field(o, "us_best");
             if (e.path == 0 && e.kz < 1) continue;            // not a usable choice
             if (e.path == 1 && (e.seg < 1 || e.nwg < 1)) continue;
-            if (e.path == 2 && (e.seg < 1 || e.nwg < 64)) continue;
+            if (e.path == 2 && (e.seg < 0 || e.nwg < 64)) continue;   // batch: seg 0 = by box size
             (*out)[kv.first] = e;
         }
     }
