@@ -329,7 +329,7 @@ def main():
                     help="skip the search for the eps that keeps the extrapolation fourth order")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the solver is single-device); "
+        print("bench.py: the solver runs on a single GPU (one device per context); "
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
