@@ -1,6 +1,6 @@
 """Parity at the benchmark's full sizes, in the configuration bench.py times
-(device-sampled fields, the same solver options), on outputs the oracle can
-compute one by one:
+(device-sampled fields, the same solver options, the autotuned per-level
+configuration), on outputs the oracle can compute one by one:
 
 * the operator (A u)_r at sampled rows of the finest level (tile edges, the
   ragged x-tail, z-chunk edges, faces, edges, corners, random rows) against the
@@ -62,6 +62,11 @@ def test_fullsize_sampled_parity(orc, ecmg, name):
     rng = np.random.default_rng(11)
     with ecmg.Solver(keep_w=True) as s:
         s.setup(p, device_fields=True)
+        # the configuration bench.py times: a warm-up solve, then the autotuner
+        # over each level's iteration count
+        s.solve(p.eps)
+        tuned = s.autotune(iters=0)
+        print("fullsize %s: tuned %s" % (name, [(r["level"], r["path"], r["kz"]) for r in tuned]), flush=True)
         infos = s.solve(p.eps)
         print("fullsize %s: iterations %s" % (name, [i["iters"] for i in infos]), flush=True)
         for l in range(2, p.levels):
