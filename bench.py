@@ -33,9 +33,11 @@ METRIC = "unknowns/s to 4th-order accuracy (FP64 vs mixed); JCG HBM GB/s; serve 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 KIND_NAMES = {0: "jcg_pass_a", 1: "jcg_pass_b", 2: "jcg_init", 3: "exp_finite", 4: "exp_true",
               5: "jcg_pass_a_fp32", 6: "jcg_pass_b_fp32", 7: "jcg_persistent", 10: "jcg_pass_a0"}
-KERNEL_SYMBOL = {0: "k_stencil<double, 2>", 1: "k_passB<double>", 2: "k_stencil<double, 1>",
-                 3: "k_exp_finite", 4: "k_exp_true", 5: "k_stencil<float, 2>", 6: "k_passB<float>",
-                 7: "k_jcg_persistent", 10: "k_stencil<double, 3>"}
+# kernel names as rocprofv3 reports them (stencil: <type, mode, rows of
+# threads, rows per thread, waves per SIMD>)
+KERNEL_SYMBOL = {0: "k_stencil<double, 2, 8, 1, 4>", 1: "k_passB<double>", 2: "k_stencil<double, 1, 8, 1, 4>",
+                 3: "k_exp_finite", 4: "k_exp_true", 5: "k_stencil<float, 2, 8, 1, 4>", 6: "k_passB<float>",
+                 7: "k_jcg_persistent", 10: "k_stencil<double, 3, 4, 2, 2>"}
 
 
 def workload(name):

@@ -207,19 +207,24 @@ __device__ __forceinline__ T robin_term(const Geom &g, int face, const T *al, in
 // MODE_PASSA (fused JCG pass A), MODE_PASSA0 (its iteration 0 from a stored p_0)
 // ---------------------------------------------------------------------------
 
-template <typename T, int MODE>
-__global__ void __launch_bounds__(NT, STENCIL_WAVES_PER_EU) k_stencil(const StencilArgs<T> a) {
+// Block shape per instantiation: TYv rows of TX threads, RYv node rows per
+// thread (TYv * RYv == TYT, so every shape tiles the plane alike and the host's
+// tile counts and partial slots do not depend on it), WPE waves per SIMD.
+template <typename T, int MODE, int TYv, int RYv, int WPE>
+__global__ void __launch_bounds__(TX * TYv, WPE) k_stencil(const StencilArgs<T> a) {
+    constexpr int NTv = TX * TYv;
+    static_assert(TYv * RYv == TYT, "a block shape covers the tile height");
     // Rolling LDS buffers: 4 node planes and 3 element layers, so the plane
     // being filled never aliases the three planes being read and one barrier per
     // z-step suffices.
     __shared__ T sv[4][TYT + 2][TX + 2];
     __shared__ T sb[3][TYT + 1][TX + 1];
-    __shared__ double red[2][NT / 64];
+    __shared__ double red[2][NTv / 64];
     __shared__ double s_beta;
     __shared__ int s_flag;
     constexpr int NH = 2 * (TX + 2) + 2 * TYT;   // halo nodes of a plane tile
     constexpr int NHB = (TX + 1) + TYT;          // halo elements of a layer tile
-    static_assert(NH <= NT && NHB <= NT, "one halo value per thread");
+    static_assert(NH <= NTv && NHB <= NTv, "one halo value per thread");
 
     const Geom &g = a.g;
     const int tid = threadIdx.x, tx = tid & (TX - 1), ty = tid / TX;
@@ -249,7 +254,7 @@ __global__ void __launch_bounds__(NT, STENCIL_WAVES_PER_EU) k_stencil(const Sten
         first = (it == 0);
         pin = (it & 1) ? a.p1 : a.p0;
         pout = (it & 1) ? a.p0 : a.p1;
-        for (int b = tid; b < a.fold_nb; b += NT) {
+        for (int b = tid; b < a.fold_nb; b += NTv) {
             fold_t[0] += a.partials2[2 * b];
             fold_t[1] += a.partials2[2 * b + 1];
         }
@@ -268,12 +273,12 @@ __global__ void __launch_bounds__(NT, STENCIL_WAVES_PER_EU) k_stencil(const Sten
     const int i = i0 + tx;
 
     // Per-thread positions, fixed for the whole z-march: in-plane offsets of
-    // this thread's RY interior nodes and elements and of its halo node and
+    // this thread's RYv interior nodes and elements and of its halo node and
     // halo element (-1 when outside the grid).
-    int off[RY], eoff[RY];
+    int off[RYv], eoff[RYv];
 #pragma unroll
-    for (int r = 0; r < RY; ++r) {
-        const int j = j0 + ty + TY * r;
+    for (int r = 0; r < RYv; ++r) {
+        const int j = j0 + ty + TYv * r;
         off[r] = (i <= g.nx && j <= g.ny) ? i + g.sx * j : -1;
         eoff[r] = (i < g.nx && j < g.ny) ? i + g.nx * j : -1;
     }
@@ -301,7 +306,7 @@ __global__ void __launch_bounds__(NT, STENCIL_WAVES_PER_EU) k_stencil(const Sten
     // (pass A: x; init: F and 1/D).  With PF = 1 the loads of step k+1 are in
     // flight while step k computes; PF = 2 alternates two sets.
     struct RegSet {
-        T ra[RY], rb[RY], rc[RY], ha, hb, hc, bb[RY], bh, ea[RY], eb[RY];
+        T ra[RYv], rb[RYv], rc[RYv], ha, hb, hc, bb[RYv], bh, ea[RYv], eb[RYv];
     };
     RegSet SA, SB;
     auto fetch_node = [&](int o, int kk, T &va, T &vb, T &vc) {
@@ -321,14 +326,14 @@ __global__ void __launch_bounds__(NT, STENCIL_WAVES_PER_EU) k_stencil(const Sten
     // fill set S for z-step k: plane k+1, layer k, epilogue of plane k
     auto fetch_set = [&](RegSet &S, int k) {
 #pragma unroll
-        for (int r = 0; r < RY; ++r) fetch_node(off[r], k + 1, S.ra[r], S.rb[r], S.rc[r]);
+        for (int r = 0; r < RYv; ++r) fetch_node(off[r], k + 1, S.ra[r], S.rb[r], S.rc[r]);
         fetch_node(hoff, k + 1, S.ha, S.hb, S.hc);
         const bool ok = k >= 0 && k < g.nz;
 #pragma unroll
-        for (int r = 0; r < RY; ++r) S.bb[r] = (ok && eoff[r] >= 0) ? a.beta[eoff[r] + exy * k] : (T)0;
+        for (int r = 0; r < RYv; ++r) S.bb[r] = (ok && eoff[r] >= 0) ? a.beta[eoff[r] + exy * k] : (T)0;
         S.bh = (ok && beoff >= 0) ? a.beta[beoff + exy * k] : (T)0;
 #pragma unroll
-        for (int r = 0; r < RY; ++r) {
+        for (int r = 0; r < RYv; ++r) {
             S.ea[r] = S.eb[r] = 0;
             if (MODE == MODE_APPLY || MODE == MODE_PASSA0 || off[r] < 0 || k < 0 || k > g.nz) continue;
             const int64_t id = (int64_t)off[r] + sxy * k;
@@ -351,19 +356,19 @@ __global__ void __launch_bounds__(NT, STENCIL_WAVES_PER_EU) k_stencil(const Sten
     };
     auto vslot = [](int k) { return (k + 4) & 3; };
     auto bslot = [](int k) { return (k + 3) % 3; };
-    T pold_next[RY], pold_cur[RY], xa_cur[RY], xb_cur[RY];
+    T pold_next[RYv], pold_cur[RYv], xa_cur[RYv], xb_cur[RYv];
     // plane k+1 and layer k of set S into LDS
     auto commit_set = [&](const RegSet &S, int k) {
         const int slot = vslot(k + 1);
 #pragma unroll
-        for (int r = 0; r < RY; ++r) {
-            sv[slot][ty + TY * r + 1][tx + 1] = node_value(S.ra[r], S.rb[r], S.rc[r]);
+        for (int r = 0; r < RYv; ++r) {
+            sv[slot][ty + TYv * r + 1][tx + 1] = node_value(S.ra[r], S.rb[r], S.rc[r]);
             pold_next[r] = S.rc[r];
         }
         if (tid < NH) sv[slot][hlj][hli] = node_value(S.ha, S.hb, S.hc);
         const int bs = bslot(k);
 #pragma unroll
-        for (int r = 0; r < RY; ++r) sb[bs][ty + TY * r + 1][tx + 1] = S.bb[r];
+        for (int r = 0; r < RYv; ++r) sb[bs][ty + TYv * r + 1][tx + 1] = S.bb[r];
         if (tid < NHB) sb[bs][blj][bli] = S.bh;
     };
 
@@ -387,7 +392,7 @@ __global__ void __launch_bounds__(NT, STENCIL_WAVES_PER_EU) k_stencil(const Sten
         __syncthreads();
         const int pre = s_flag;
         if (pre == -1) return;                    // stopped by an earlier launch
-        block_sum<2, NT>(fold_t, red);
+        block_sum<2, NTv>(fold_t, red);
         if (tid == 0) {
             int dn;
             double bk = 0.0;
@@ -427,7 +432,7 @@ __global__ void __launch_bounds__(NT, STENCIL_WAVES_PER_EU) k_stencil(const Sten
     // one z-step: output plane k from planes k-1, k, k+1 (S holds plane k+1)
     auto step = [&](RegSet &S, int k) {
 #pragma unroll
-        for (int r = 0; r < RY; ++r) {
+        for (int r = 0; r < RYv; ++r) {
             pold_cur[r] = pold_next[r];
             xa_cur[r] = S.ea[r];
             xb_cur[r] = S.eb[r];
@@ -439,8 +444,8 @@ __global__ void __launch_bounds__(NT, STENCIL_WAVES_PER_EU) k_stencil(const Sten
         const int s0 = vslot(k - 1), s1 = vslot(k), s2 = vslot(k + 1);
         const int b0 = bslot(k - 1), b1 = bslot(k);
 #pragma unroll
-        for (int r = 0; r < RY; ++r) {
-            const int jj = ty + TY * r;
+        for (int r = 0; r < RYv; ++r) {
+            const int jj = ty + TYv * r;
             const int j = j0 + jj;
             const int li = tx + 1, lj = jj + 1;
             // beta of the 8 elements around the node: layer below (k-1) and
@@ -520,7 +525,7 @@ __global__ void __launch_bounds__(NT, STENCIL_WAVES_PER_EU) k_stencil(const Sten
 
     // block partials, plain stores: a one-block kernel takes the totals
     double acc[2] = {acc0, acc1};
-    block_sum<2, NT>(acc, red);
+    block_sum<2, NTv>(acc, red);
     if (tid == 0) {
         double *out = (MODE == MODE_INIT && a.fold) ? a.partials2 : a.partials;
         out[2 * (int64_t)blockIdx.x] = acc[0];
@@ -740,19 +745,37 @@ int stencil_kz(const Geom &g, int kz_max, int target_blocks) {
     return (int)std::max<int64_t>(kz, 1);
 }
 
+// Block shape of pass A's iteration 0: it reads only p_0 and beta, so a z-step
+// carries little work for its memory latency; 256-thread blocks with two node
+// rows per thread at 2 waves per SIMD (164 registers, no spills) run it 8-11 %
+// faster on 513^3 than the 512-thread shape the other passes use (for them the
+// same shape was measured slower).
+#ifndef ECMG_PA0_TY
+#define ECMG_PA0_TY 4
+#endif
+#ifndef ECMG_PA0_RY
+#define ECMG_PA0_RY 2
+#endif
+#ifndef ECMG_PA0_WPE
+#define ECMG_PA0_WPE 2
+#endif
+
 template <typename T>
 void launch_stencil(int mode, const StencilArgs<T> &a, hipStream_t s) {
     const int nb = a.ntx * a.nty * a.nkz;
     if (mode == MODE_APPLY) {
-        launch_timed(k_stencil<T, MODE_APPLY>, dim3(nb), dim3(NT), 0, s, a);
+        launch_timed(k_stencil<T, MODE_APPLY, TY, RY, STENCIL_WAVES_PER_EU>, dim3(nb), dim3(NT), 0, s, a);
     } else if (mode == MODE_INIT) {
-        launch_timed(k_stencil<T, MODE_INIT>, dim3(nb), dim3(NT), 0, s, a);
+        launch_timed(k_stencil<T, MODE_INIT, TY, RY, STENCIL_WAVES_PER_EU>, dim3(nb), dim3(NT), 0, s, a);
         if (!a.fold)
             hipLaunchKernelGGL(k_stencil_finish<MODE_INIT>, dim3(1), dim3(NTF), 0, s, a.sc,
                                (const double *)a.partials, nb);
     } else {
-        if (mode == MODE_PASSA0) launch_timed(k_stencil<T, MODE_PASSA0>, dim3(nb), dim3(NT), 0, s, a);
-        else launch_timed(k_stencil<T, MODE_PASSA>, dim3(nb), dim3(NT), 0, s, a);
+        if (mode == MODE_PASSA0)
+            launch_timed(k_stencil<T, MODE_PASSA0, ECMG_PA0_TY, ECMG_PA0_RY, ECMG_PA0_WPE>, dim3(nb),
+                         dim3(TX * ECMG_PA0_TY), 0, s, a);
+        else
+            launch_timed(k_stencil<T, MODE_PASSA, TY, RY, STENCIL_WAVES_PER_EU>, dim3(nb), dim3(NT), 0, s, a);
         if (!a.fold)
             hipLaunchKernelGGL(k_stencil_finish<MODE_PASSA>, dim3(1), dim3(NTF), 0, s, a.sc,
                                (const double *)a.partials, nb);
