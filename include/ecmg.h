@@ -152,6 +152,14 @@ typedef struct {
                                   ECMG_TUNE_CACHE environment variable, if set; the
                                   string is read during ecmg_create only                */
     int32_t method;            /* ECMG_JCG (default) or ECMG_CG                          */
+    int32_t speculate;         /* 1 (default): in ecmg_solve / ecmg_solve_levels, a tiled
+                                  JCG level whose last two solves converged in the same
+                                  number of iterations enqueues that many iterations and
+                                  no status read, so the host does not wait between
+                                  levels; if it then falls short of the tolerance, that
+                                  level and every finer one are solved again from their
+                                  EXP_finite start with status reads (same results as
+                                  speculate = 0, at the cost of the repeated work)  */
 } ecmg_options;
 
 /* One JCG level's configuration chosen by the autotuner. */

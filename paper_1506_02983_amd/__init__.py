@@ -55,7 +55,8 @@ class Options(ctypes.Structure):
                 ("keep_w", ctypes.c_int32), ("inner_tol", ctypes.c_double), ("dsolve_tol", ctypes.c_double),
                 ("chunk", ctypes.c_int32), ("timing", ctypes.c_int32), ("hip_stream", ctypes.c_void_p),
                 ("persistent_nodes", ctypes.c_int64), ("dsolve_dense_max", ctypes.c_int64),
-                ("autotune", ctypes.c_int32), ("tune_cache", ctypes.c_char_p), ("method", ctypes.c_int32)]
+                ("autotune", ctypes.c_int32), ("tune_cache", ctypes.c_char_p), ("method", ctypes.c_int32),
+                ("speculate", ctypes.c_int32)]
 
 
 class TuneResult(ctypes.Structure):
@@ -295,7 +296,7 @@ class Solver:
                  max_iter: int = 20000, dsolve_tol: float = 1e-14, inner_tol: float = 1e-4,
                  chunk: int = 0, timing: bool = False, stream=None, persistent_nodes: int = -1,
                  dsolve_dense_max: Optional[int] = None, autotune: int = 0, tune_cache: Optional[str] = None,
-                 method: int = JCG):
+                 method: int = JCG, speculate: bool = True):
         self.L = load_library()
         o = Options()
         self.L.ecmg_default_options(ctypes.byref(o))
@@ -308,6 +309,7 @@ class Solver:
         o.autotune = int(autotune)
         o.tune_cache = tune_cache.encode() if tune_cache else None
         o.method = int(method)
+        o.speculate = int(speculate)
         self.opt = o
         h = ctypes.c_void_p()
         self._check(self.L.ecmg_create(ctypes.byref(o), ctypes.byref(h)), None)

@@ -87,6 +87,7 @@ struct ecmg_ctx {
     // final JCG scalars and persistent task (pinned; the stream copies them
     // when it gets there) and a start / end event pair
     JcgScalars *sc_lv = nullptr;
+    JcgScalars *sc_lv_dev = nullptr;           // the same slots as kernels address them
     PersistentTask *task_lv = nullptr;
     int lv_cap = 0;
     std::vector<hipEvent_t> lv_ev;
@@ -396,10 +397,11 @@ static StencilArgs<double> stencil_args(ecmg_ctx *c, Level &L) {
 // last time, so a repeated solve usually needs one status read) or 2; later
 // chunks double from 2 up to 64.  Fixed-iteration mode enqueues all iterations
 // at once.  Leaves the final scalars in c->sc_host.  kind_a / kind_b name the
-// timing classes.
+// timing classes.  nowait: the first chunk only, with no status read (the
+// caller checks `done` once the stream has run it).
 template <typename T>
 static int jcg_chunks(ecmg_ctx *c, int l, const StencilArgs<T> &a, const PassBArgs<T> &b, JcgScalars *sc,
-                      int fixed, int kind_a, int kind_b, int hint) {
+                      int fixed, int kind_a, int kind_b, int hint, bool nowait = false) {
     int done_iters = 0;
     int next = 2;
     int chunk = c->opt.chunk > 0 ? c->opt.chunk : (hint > 0 ? hint : 2);
@@ -427,6 +429,7 @@ static int jcg_chunks(ecmg_ctx *c, int l, const StencilArgs<T> &a, const PassBAr
             CHK(rec_end(c, slot));
         }
         HIPCHK(c, hipGetLastError());
+        if (nowait) break;
     }
     return ECMG_OK;
 }
@@ -436,7 +439,7 @@ static int jcg_chunks(ecmg_ctx *c, int l, const StencilArgs<T> &a, const PassBAr
 // on a pass A, which takes the stop test of the pass B before it.  Pass A sums
 // init's partials (nb_init pairs) at iteration 0 and pass B's after.
 static int jcg_chunks_folded(ecmg_ctx *c, int l, StencilArgs<double> a, PassBArgs<double> b, int fixed, int hint,
-                             int nb_init, int nb_b) {
+                             int nb_init, int nb_b, bool nowait) {
     int next = 2;
     int chunk = c->opt.chunk > 0 ? c->opt.chunk : (hint > 0 ? hint : 2);
     if (fixed >= 0) chunk = std::max(fixed, 1);
@@ -469,6 +472,7 @@ static int jcg_chunks_folded(ecmg_ctx *c, int l, StencilArgs<double> a, PassBArg
             CHK(rec_end(c, slot));
         }
         HIPCHK(c, hipGetLastError());
+        if (nowait) break;
     }
     return ECMG_OK;
 }
@@ -584,16 +588,23 @@ static int jcg_result(ecmg_ctx *c, int l, const JcgScalars &s, int max_iter, boo
     if (s.done == DONE_MAXITER)
         return fail(c, ECMG_ENOTCONV, "JCG reached max_iter = %d on level %d (rre %g)", max_iter, l,
                     std::sqrt(s.rr) / L.nf);
-    if (keep_hint && s.done == DONE_CONVERGED) L.last_iters = s.iter;
+    if (keep_hint && s.done == DONE_CONVERGED) {
+        L.spec_hits = s.iter == L.last_iters ? std::min(L.spec_hits + 1, 1 << 20) : 0;
+        L.last_iters = s.iter;
+    }
     return ECMG_OK;
 }
 
 // Tiled JCG of level l, enqueued: init, the iterations (status reads only
 // between chunks), the last x update (the kernel checks whether one is
-// pending) and a copy of the final scalars into the level's pinned slot,
-// which holds them once the stream has passed it.
-static int enqueue_jcg(ecmg_ctx *c, int l, double tol_abs, int max_iter, int fixed) {
+// pending), which also copies the final scalars into the level's pinned slot;
+// the slot holds them once the stream has passed it.  speculate: a level whose
+// last two solves converged in the same number of iterations enqueues that
+// many and reads no status (L.spec_live; the caller checks `done` in the slot).
+static int enqueue_jcg(ecmg_ctx *c, int l, double tol_abs, int max_iter, int fixed, bool speculate = false) {
     Level &L = c->lv[l];
+    L.spec_live = speculate && fixed < 0 && c->opt.chunk <= 0 && c->opt.speculate && L.last_iters > 0 &&
+                  L.spec_hits >= 1;
     launch_jcg_reset(c->sc, tol_abs, max_iter, fixed, c->stream);
     launch_zero_pad(L.g, c->r, c->q, c->p0, c->p1, c->stream);
     StencilArgs<double> a = stencil_args(c, L);
@@ -629,11 +640,11 @@ static int enqueue_jcg(ecmg_ctx *c, int l, double tol_abs, int max_iter, int fix
     CHK(rec_end(c, slot));
     HIPCHK(c, hipGetLastError());
 
-    if (fold) CHK(jcg_chunks_folded(c, l, a, b, fixed, fixed < 0 ? L.last_iters : 0, (int)nb_a, (int)nb_b));
-    else CHK(jcg_chunks(c, l, a, b, c->sc, fixed, 0, 1, fixed < 0 ? L.last_iters : 0));
-    launch_final_x(L.g, L.x, c->p0, c->p1, c->sc, c->stream);
+    const int hint = fixed < 0 ? L.last_iters : 0;
+    if (fold) CHK(jcg_chunks_folded(c, l, a, b, fixed, hint, (int)nb_a, (int)nb_b, L.spec_live));
+    else CHK(jcg_chunks(c, l, a, b, c->sc, fixed, 0, 1, hint, L.spec_live));
+    launch_final_x(L.g, L.x, c->p0, c->p1, c->sc, c->sc_lv_dev + l, c->stream);
     HIPCHK(c, hipGetLastError());
-    HIPCHK(c, hipMemcpyAsync(c->sc_lv + l, c->sc, sizeof(JcgScalars), hipMemcpyDeviceToHost, c->stream));
     return ECMG_OK;
 }
 
@@ -808,6 +819,7 @@ void ecmg_default_options(ecmg_options *o) {
     o->autotune = 0;
     o->tune_cache = nullptr;
     o->method = ECMG_JCG;
+    o->speculate = 1;
 }
 
 int ecmg_create(const ecmg_options *opt, ecmg_ctx **out) {
@@ -998,13 +1010,14 @@ int ecmg_setup(ecmg_ctx *c, const ecmg_problem *p) {
     if (c->lv_cap < p->levels) {
         if (c->sc_lv) (void)hipHostFree(c->sc_lv);
         if (c->task_lv) (void)hipHostFree(c->task_lv);
-        c->sc_lv = nullptr;
+        c->sc_lv = c->sc_lv_dev = nullptr;
         c->task_lv = nullptr;
         c->lv_cap = 0;
         if (hipHostMalloc((void **)&c->sc_lv, sizeof(JcgScalars) * p->levels, hipHostMallocDefault) != hipSuccess ||
             hipHostMalloc((void **)&c->task_lv, sizeof(PersistentTask) * p->levels, hipHostMallocDefault) !=
                 hipSuccess)
             return fail(c, ECMG_ENOMEM, "pinned host allocation of %d level slots failed", p->levels);
+        HIPCHK(c, hipHostGetDevicePointer((void **)&c->sc_lv_dev, c->sc_lv, 0));
         c->lv_cap = p->levels;
     }
     while (c->lv_ev.size() < 2 * (size_t)p->levels) {
@@ -1336,13 +1349,26 @@ static int solve_impl(ecmg_ctx *c, double rel_tol, const int32_t *fixed, ecmg_le
     std::vector<int> cap(n, 0);              // their iteration caps
     std::vector<int> limit(n, 1 << 30);      // timing: iterations each level ran
     int worst = ECMG_OK, settled = 0;
+    int redo = -1;                           // first level whose speculative chunk fell short
     auto note = [&](int rc) {
         if (rc != ECMG_OK && worst == ECMG_OK) worst = rc;
     };
-    // wait for the stream; results and times of levels settled .. upto-1
+    // wait for the stream; results and times of levels settled .. upto-1.  A
+    // level enqueued without status reads that is still running fell short:
+    // it and every level after it are discarded (with their timing records)
+    // and `redo` names it.
     auto settle = [&](int upto) -> int {
         HIPCHK(c, hipStreamSynchronize(c->stream));
         for (int k = settled; k < upto; ++k) {
+            if (deferred[k] && c->lv[k].spec_live && c->sc_lv[k].done == DONE_RUNNING) {
+                c->lv[k].spec_hits = 0;
+                redo = k;
+                upto = k;
+                c->recs.erase(std::remove_if(c->recs.begin(), c->recs.end(),
+                                             [k](const ecmg_ctx::Rec &r) { return r.level >= k; }),
+                              c->recs.end());
+                break;
+            }
             if (deferred[k]) {
                 int rc = jcg_result(c, k, c->sc_lv[k], cap[k], fixed == nullptr, &li[k]);
                 if (k < 2 && rc == ECMG_ENOTCONV) rc = ECMG_OK;   // DSOLVE: the iterate at the cap is kept
@@ -1356,7 +1382,13 @@ static int solve_impl(ecmg_ctx *c, double rel_tol, const int32_t *fixed, ecmg_le
         settled = upto;
         return rec_flush_levels(c, limit);
     };
-    for (int l = 0; l < n; ++l) {
+    for (int l = 0;; ++l) {
+        if (l == n) {
+            CHK(settle(n));
+            if (redo < 0) break;
+            l = redo;
+            redo = -1;
+        }
         Level &L = c->lv[l];
         li[l].level = l;
         li[l].nx = L.g.nx;
@@ -1382,13 +1414,19 @@ static int solve_impl(ecmg_ctx *c, double rel_tol, const int32_t *fixed, ecmg_le
             CHK(do_exp_finite(c, l));
             if (uses_mixed(c, l) && fx < 0) {
                 CHK(settle(l));
+                if (redo >= 0) {                 // a level before this one runs again first
+                    l = redo - 1;
+                    redo = -1;
+                    continue;
+                }
                 rc = run_jcg_mixed(c, l, tol, max_iter, &li[l]);
                 jcg = false;
             }
         }
+        c->lv[l].spec_live = false;
         if (jcg) {
             rc = uses_persistent(c, l) ? enqueue_jcg_persistent(c, l, tol, max_iter, fx)
-                                       : enqueue_jcg(c, l, tol, max_iter, fx);
+                                       : enqueue_jcg(c, l, tol, max_iter, fx, fixed == nullptr);
             deferred[l] = 1;
             cap[l] = max_iter;
         }
@@ -1396,7 +1434,6 @@ static int solve_impl(ecmg_ctx *c, double rel_tol, const int32_t *fixed, ecmg_le
         if (rc == ECMG_EDEVICE) return rc;
         note(rc);
     }
-    CHK(settle(n));
     if (info)
         for (int l = 0; l < n; ++l) info[l] = li[l];
     c->solved = true;

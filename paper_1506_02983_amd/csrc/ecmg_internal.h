@@ -217,6 +217,8 @@ struct Level {
     float *dinv32 = nullptr;
     double nf = 0.0;                  // ||f_h||_2 of the stopping test
     int last_iters = -1;              // JCG iterations of the last converged solve (first chunk)
+    int spec_hits = 0;                // consecutive solves that converged in exactly last_iters
+    bool spec_live = false;           // the enqueued solve reads no status (its chunk is last_iters)
     // autotuned JCG configuration (tune_path -1: the built-in rules)
     int tune_path = -1;               // 0 tiled passes, 1 persistent kernel
     int tune_kz = 0;                  // tiled: planes per z-chunk
@@ -261,7 +263,7 @@ void launch_passB(const PassBArgs<T> &a, hipStream_t s);
 // blocks of pass B for n nodes (its partial slots: twice as many)
 int64_t passB_blocks(int64_t n);
 void launch_final_x(const Geom &g, double *x, const double *p0, const double *p1, const JcgScalars *sc,
-                    hipStream_t s);
+                    JcgScalars *out, hipStream_t s);
 // mixed precision: r32 = r64 / s, d32 = 0, JCG start scalars (FP64 sums)
 void launch_mixed_start(const Geom &g, const double *r64, double inv_s, const float *dinv32, float *r32, float *d32,
                         JcgScalars *sc, double *partials, unsigned *counter, hipStream_t s);

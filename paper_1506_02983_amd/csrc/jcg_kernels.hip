@@ -675,10 +675,22 @@ __global__ void __launch_bounds__(NTF) k_passB_finish(JcgScalars *sc, const doub
     }
 }
 
-// x += alpha p of the last iteration (after the host has seen `done`): one
-// contiguous chunk of UB x 256 node pairs per block, 16-byte accesses.
+// x += alpha p of the last iteration (after the host has seen `done`, or
+// enqueued right behind the iterations): one contiguous chunk of UB x 256 node
+// pairs per block, 16-byte accesses.  Thread 0 of block 0 also copies the
+// final scalars to `out` (pinned host memory, read by the host once the stream
+// has passed this launch).
 template <typename T>
-__global__ void __launch_bounds__(256) k_final_x(int64_t n, T *x, const T *p0, const T *p1, const JcgScalars *sc) {
+__global__ void __launch_bounds__(256) k_final_x(int64_t n, T *x, const T *p0, const T *p1, const JcgScalars *sc,
+                                                 JcgScalars *out) {
+    static_assert(sizeof(JcgScalars) % 8 == 0, "scalars copied as 8-byte words");
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        // system-scope stores: the words reach host memory without an L2 write-back
+        const unsigned long long *src = (const unsigned long long *)sc;
+        unsigned long long *dst = (unsigned long long *)out;
+        for (int w = 0; w < (int)(sizeof(JcgScalars) / 8); ++w)
+            __hip_atomic_store(dst + w, src[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
     if (!sc->pending) return;
     using V2 = typename Vec2<T>::type;
     const T al = (T)sc->alpha;
@@ -792,9 +804,9 @@ void launch_passB(const PassBArgs<T> &a, hipStream_t s) {
 }
 
 void launch_final_x(const Geom &g, double *x, const double *p0, const double *p1, const JcgScalars *sc,
-                    hipStream_t s) {
+                    JcgScalars *out, hipStream_t s) {
     const int64_t nb = std::max<int64_t>(1, (g.nnodes / 2 + UB * 256 - 1) / (UB * 256));
-    hipLaunchKernelGGL((k_final_x<double>), dim3((unsigned)nb), dim3(256), 0, s, g.nnodes, x, p0, p1, sc);
+    hipLaunchKernelGGL((k_final_x<double>), dim3((unsigned)nb), dim3(256), 0, s, g.nnodes, x, p0, p1, sc, out);
 }
 
 void launch_jcg_reset(JcgScalars *sc, double tol, int max_iter, int fixed, hipStream_t s) {

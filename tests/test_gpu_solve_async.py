@@ -80,3 +80,73 @@ def test_set_timing_selects_classes(ecmg):
         s.reset_kernel_times()
         s.solve(1e-8)
         assert all(s.kernel_times(l, k)[1] == 0 for l in range(p.levels) for k in (0, 1, 2, 10))
+
+
+def _stable(ecmg, s, p, eps, times=3):
+    # the same solve a few times: every tiled level's iteration count repeats,
+    # so the next solve enqueues each of them without a status read
+    for _ in range(times):
+        s.solve(eps)
+
+
+@pytest.mark.parametrize("persistent", [0, -1], ids=["tiled", "default"])
+def test_speculative_chunk_shortfall_matches_fresh_context(ecmg, persistent):
+    """A level enqueued with its previous count and no status read that then
+    falls short of a tighter tolerance is solved again, with every finer level,
+    from its EXP_finite start: iterates and counts equal a fresh context's."""
+    p = workloads.variable_beta_robin_cube(levels=5)
+    with ecmg.Solver(persistent_nodes=persistent) as s:
+        s.setup(p)
+        fresh = _solve(ecmg, s, p, 1e-10)
+    with ecmg.Solver(persistent_nodes=persistent) as s:
+        s.setup(p)
+        _stable(ecmg, s, p, 1e-6)
+        for _ in range(2):                                    # short speculation, then no speculation
+            iters, u = _solve(ecmg, s, p, 1e-10)
+            assert iters == fresh[0], (iters, fresh[0])
+            for l in range(p.levels):
+                assert np.array_equal(u[l], fresh[1][l]), l
+
+
+def test_speculative_shortfall_on_a_middle_level(ecmg):
+    """Only level 3's tolerance tightens: level 2 keeps its speculative result,
+    levels 3 and 4 are solved again; the same as a fresh context."""
+    p = workloads.variable_beta_robin_cube(levels=5)
+    loose = [1e-6] * p.levels
+    tight = list(loose)
+    tight[3] = 1e-11
+    with ecmg.Solver(persistent_nodes=0) as s:
+        s.setup(p)
+        s.solve_levels(loose)
+        ref = s.solve_levels(tight)
+        ref_u = {l: s.get(l, ecmg.VEC_U) for l in range(p.levels)}
+    with ecmg.Solver(persistent_nodes=0, timing=True) as s:
+        s.setup(p)
+        for _ in range(3):
+            base = s.solve_levels(loose)
+        s.reset_kernel_times()
+        infos = s.solve_levels(tight)
+        assert [i["iters"] for i in infos] == [i["iters"] for i in ref]
+        assert infos[2]["iters"] == base[2]["iters"] and infos[3]["iters"] > base[3]["iters"]
+        for l in range(p.levels):
+            assert np.array_equal(s.get(l, ecmg.VEC_U), ref_u[l]), l
+        # the discarded attempt leaves no kernel times: each tiled level counts
+        # exactly the iterations of its kept solve
+        for l in range(2, p.levels):
+            it = infos[l]["iters"]
+            counts = {k: s.kernel_times(l, k)[1] for k in (0, 1, 10)}
+            assert counts[10] == min(it, 1) and counts[0] == max(it - 1, 0), (l, counts, it)
+            assert counts[1] == it, (l, counts, it)
+
+
+def test_speculation_off_gives_the_same_iterates(ecmg):
+    p = workloads.variable_beta_robin_cube(levels=5)
+    out = []
+    for spec in (True, False):
+        with ecmg.Solver(persistent_nodes=0, speculate=spec) as s:
+            s.setup(p)
+            _stable(ecmg, s, p, 1e-8)
+            out.append(_solve(ecmg, s, p, 1e-8))
+    assert out[0][0] == out[1][0]
+    for l in range(p.levels):
+        assert np.array_equal(out[0][1][l], out[1][1][l]), l
