@@ -249,11 +249,24 @@ __global__ void __launch_bounds__(TX * TYv, WPE) k_stencil(const StencilArgs<T> 
     // and resolved after the first planes' loads are issued, so one memory
     // round trip covers both.
     double fold_t[2] = {0.0, 0.0};
+    // the scalars the folded step reads, loaded here with the partials: no
+    // block of this launch writes them, except `done` (block 0 may set it),
+    // which each block takes from thread 0 through LDS below
+    int f_done = 0, f_brk = 0, f_fixed = 0, f_maxit = 0;
+    double f_tol = 0.0, f_rho_prev = 1.0, f_alpha = 0.0;
     if (PA && a.fold) {
         const int it = a.it;
         first = (it == 0);
         pin = (it & 1) ? a.p1 : a.p0;
         pout = (it & 1) ? a.p0 : a.p1;
+        const JcgScalars *scf = a.sc;
+        f_done = scf->done;
+        f_brk = scf->brk;
+        f_fixed = scf->fixed;
+        f_maxit = scf->max_iter;
+        f_tol = scf->tol;
+        f_alpha = scf->alpha;
+        if (it > 0) f_rho_prev = scf->rho_f[(it - 1) & 1];
         for (int b = tid; b < a.fold_nb; b += NTv) {
             fold_t[0] += a.partials2[2 * b];
             fold_t[1] += a.partials2[2 * b + 1];
@@ -388,7 +401,7 @@ __global__ void __launch_bounds__(TX * TYv, WPE) k_stencil(const StencilArgs<T> 
         // through LDS; every block sums the same partials in the same order.
         JcgScalars *sc = a.sc;
         const int it = a.it;
-        if (tid == 0) s_flag = sc->done ? -1 : (sc->brk ? -2 : 0);
+        if (tid == 0) s_flag = f_done ? -1 : (f_brk ? -2 : 0);
         __syncthreads();
         const int pre = s_flag;
         if (pre == -1) return;                    // stopped by an earlier launch
@@ -400,11 +413,11 @@ __global__ void __launch_bounds__(TX * TYv, WPE) k_stencil(const StencilArgs<T> 
                 dn = DONE_BREAKDOWN;              // the previous pass B found p.q <= 0
             } else {
                 const double rz = fold_t[0], rr = fold_t[1], rn = sqrt(rr);
-                if (sc->fixed >= 0) dn = (it >= sc->fixed) ? DONE_CONVERGED : DONE_RUNNING;
-                else if (!(rn > sc->tol)) dn = DONE_CONVERGED;
-                else if (it >= sc->max_iter) dn = DONE_MAXITER;
+                if (f_fixed >= 0) dn = (it >= f_fixed) ? DONE_CONVERGED : DONE_RUNNING;
+                else if (!(rn > f_tol)) dn = DONE_CONVERGED;
+                else if (it >= f_maxit) dn = DONE_MAXITER;
                 else dn = DONE_RUNNING;
-                if (it > 0) bk = rz / sc->rho_f[(it - 1) & 1];
+                if (it > 0) bk = rz / f_rho_prev;
                 if (blockIdx.x == 0) {
                     sc->iter = it;
                     sc->rho = rz;
@@ -421,7 +434,7 @@ __global__ void __launch_bounds__(TX * TYv, WPE) k_stencil(const StencilArgs<T> 
         }
         __syncthreads();
         if (s_flag != DONE_RUNNING) return;
-        alpha_prev = (T)sc->alpha;
+        alpha_prev = (T)f_alpha;
         betak = (T)s_beta;
     }
     commit_set(SA, k0 - 2);
@@ -587,7 +600,9 @@ __global__ void __launch_bounds__(NTB) k_passB(const PassBArgs<T> a) {
     __shared__ double s_alpha;
     __shared__ int s_bad;
     JcgScalars *sc = a.sc;
-    if (sc->done) return;                         // never set during a pass B
+    // never set during a pass B; folded, the check waits until the loads below
+    // are issued (a launch after `done` then only reads, on a small grid)
+    if (!a.fold && sc->done) return;
     using V2 = typename Vec2<T>::type;
     const int64_t n2 = a.n / 2;
     const V2 *__restrict__ r2 = (const V2 *)a.r;
@@ -610,13 +625,16 @@ __global__ void __launch_bounds__(NTB) k_passB(const PassBArgs<T> a) {
         // folded: alpha = rho_it / p.q from pass A's partials (every block the
         // same sum, while its own loads are in flight); a breakdown goes to
         // `brk`, which the next pass A turns into `done`
+        const int dn = sc->done;
+        const double rho_it = sc->rho_f[a.it & 1];
         double t[1] = {0.0};
         for (int b = threadIdx.x; b < a.nb_a; b += NTB) t[0] += a.pq_partials[2 * b];
+        if (dn) return;                           // uniform: no pass B writes it
         block_sum<1, NTB>(t, red);
         if (threadIdx.x == 0) {
             const double pq = t[0];
             const bool bad = !(pq > 0.0) || !isfinite(pq);
-            const double alpha = bad ? 0.0 : sc->rho_f[a.it & 1] / pq;
+            const double alpha = bad ? 0.0 : rho_it / pq;
             if (blockIdx.x == 0) {
                 sc->pq = pq;
                 if (bad) sc->brk = 1;
