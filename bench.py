@@ -155,13 +155,11 @@ def precision_comparison(E, torch, name="high-contrast-513x257x257", steps=3):
     for prec, tag in ((E.FP64, "fp64"), (E.MIXED, "mixed")):
         with E.Solver(precision=prec, keep_w=False) as s:
             s.setup(problem, device_fields=True)
-            s.solve(problem.eps)
-            s.extrapolate(L, out=False)
+            s.solve(problem.eps, extrapolate=True)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             for _ in range(steps):
-                infos = s.solve(problem.eps)
-                s.extrapolate(L, out=False)
+                infos = s.solve(problem.eps, extrapolate=True)
             torch.cuda.synchronize()
             dt = (time.perf_counter() - t0) / steps
             ue = exact_on_device(problem, problem.n_at(L))
@@ -189,13 +187,11 @@ def method_comparison(E, torch, problem, desc, steps=3):
     for method, tag in ((E.JCG, "ecmg_jcg"), (E.CG, "ecmg_cg")):
         with E.Solver(method=method, keep_w=False) as s:
             s.setup(problem, device_fields=True)
-            s.solve(problem.eps)
-            s.extrapolate(L, out=False)
+            s.solve(problem.eps, extrapolate=True)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             for _ in range(steps):
-                infos = s.solve(problem.eps)
-                s.extrapolate(L, out=False)
+                infos = s.solve(problem.eps, extrapolate=True)
             torch.cuda.synchronize()
             dt = (time.perf_counter() - t0) / steps
             ue = exact_on_device(problem, problem.n_at(L))
@@ -240,8 +236,7 @@ def batched(E, torch, n_boxes=512, steps=3):
     # the same boxes one by one through ecmg_solve (a sample of 64) for context
     t0 = time.perf_counter()
     for sv in solvers[:64]:
-        sv.solve(eps)
-        sv.extrapolate(sv.levels - 1, out=False)
+        sv.solve(eps, extrapolate=True)
     torch.cuda.synchronize()
     seq = (time.perf_counter() - t0) * n_boxes / 64
     it = [i[-1]["iters"] for i in infos]
@@ -368,8 +363,7 @@ def main():
           file=sys.stderr, flush=True)
 
     for _ in range(max(args.warmup, 1 if args.autotune else 0)):
-        s.solve(eps)
-        s.extrapolate(L, out=False)
+        s.solve(eps, extrapolate=True)
     tuned = None
     if args.autotune:
         # each level timed over its iteration count in the warm-up solve
@@ -379,16 +373,14 @@ def main():
             "L%d %s" % (r["level"], ("tiled kz=%d" % r["kz"]) if r["path"] == "tiled" else
                         "persistent seg=%d nwg=%d" % (r["seg"], r["nwg"]))
             for r in tuned)), file=sys.stderr, flush=True)
-        s.solve(eps)
-        s.extrapolate(L, out=False)
+        s.solve(eps, extrapolate=True)
     # per-kernel breakdown: two untimed steps with every kernel class timed
     # (HIP events around each launch, which lengthen the launch-bound levels)
     s.set_timing(-1)
     torch.cuda.synchronize()
     s.reset_kernel_times()
     for _ in range(2):
-        infos_b = s.solve(eps)
-        s.extrapolate(L, out=False)
+        infos_b = s.solve(eps, extrapolate=True)
     kernels = []
     for l in range(problem.levels):
         nl = problem.n_at(l)
@@ -419,8 +411,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        infos = s.solve(eps)
-        s.extrapolate(L, out=False)
+        infos = s.solve(eps, extrapolate=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms_per_step = 1e3 * dt / args.steps
@@ -434,8 +425,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        infos_r = s.solve(eps)
-        s.extrapolate(L, out=False)
+        infos_r = s.solve(eps, extrapolate=True)
     torch.cuda.synchronize()
     region_ms = 1e3 * (time.perf_counter() - t0) / args.steps
 
@@ -487,13 +477,11 @@ def main():
     fourth = None
     if not args.no_errors and errors.get("Ut_order_max", 0.0) < 3.8 and not args.no_fourth_order:
         for e4 in (1e-9, 1e-10, 1e-11, 1e-12, 1e-13):
-            s.solve(e4)
-            s.extrapolate(L, out=False)
+            s.solve(e4, extrapolate=True)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             for _ in range(2):
-                inf4 = s.solve(e4)
-                s.extrapolate(L, out=False)
+                inf4 = s.solve(e4, extrapolate=True)
             torch.cuda.synchronize()
             dt4 = (time.perf_counter() - t1) / 2
             err4 = {}

@@ -213,6 +213,13 @@ int ecmg_setup(ecmg_ctx *ctx, const ecmg_problem *problem);
  * failed (all levels still run; each entry has its own status). */
 int ecmg_solve(ecmg_ctx *ctx, double rel_tol, ecmg_level_info *info);
 
+/* Algorithm 4 in full: ecmg_solve, then EXP_true on the finest level, enqueued
+ * behind the cascade so that the call waits for the device once (U~ of the
+ * finest level as ecmg_extrapolate(ctx, -1, NULL) leaves it: read it with
+ * ecmg_get / ecmg_device_view / ecmg_norms).  Same arguments, results and
+ * errors as ecmg_solve. */
+int ecmg_solve_extrapolated(ecmg_ctx *ctx, double rel_tol, ecmg_level_info *info);
+
 /* As ecmg_solve, but JCG on level l >= 2 runs exactly iters[l] iterations
  * (iters has `levels` entries; entries 0 and 1 are ignored). */
 int ecmg_solve_fixed(ecmg_ctx *ctx, const int32_t *iters, ecmg_level_info *info);

@@ -81,7 +81,8 @@ class LevelInfo(ctypes.Structure):
 
 
 # Every symbol include/ecmg.h declares (checked by the CPU test suite).
-EXPORTS = ["ecmg_default_options", "ecmg_create", "ecmg_setup", "ecmg_solve", "ecmg_solve_fixed",
+EXPORTS = ["ecmg_default_options", "ecmg_create", "ecmg_setup", "ecmg_solve", "ecmg_solve_extrapolated",
+           "ecmg_solve_fixed",
            "ecmg_extrapolate", "ecmg_prolongate", "ecmg_jcg", "ecmg_apply", "ecmg_get", "ecmg_set",
            "ecmg_device_view", "ecmg_norms", "ecmg_level_dims", "ecmg_plan_bytes", "ecmg_kernel_times",
            "ecmg_reset_kernel_times", "ecmg_last_error", "ecmg_destroy", "ecmg_solve_batch",
@@ -114,6 +115,7 @@ def load_library(path: str = LIB_PATH):
     L.ecmg_create.argtypes = [ctypes.POINTER(Options), ctypes.POINTER(P)]
     L.ecmg_setup.argtypes = [P, ctypes.POINTER(ProblemC)]
     L.ecmg_solve.argtypes = [P, dbl, P]
+    L.ecmg_solve_extrapolated.argtypes = [P, dbl, P]
     L.ecmg_solve_fixed.argtypes = [P, P, P]
     L.ecmg_extrapolate.argtypes = [P, i32, P]
     L.ecmg_prolongate.argtypes = [P, i32]
@@ -359,9 +361,12 @@ class Solver:
         self._check(self.L.ecmg_autotune(self.h, int(iters), cache.encode() if cache else None, out))
         return [r.as_dict() for r in out[:max(self.levels - 2, 0)]]
 
-    def solve(self, rel_tol: float, allow_fail: bool = False) -> List[dict]:
+    def solve(self, rel_tol: float, allow_fail: bool = False, extrapolate: bool = False) -> List[dict]:
+        """ecmg_solve; extrapolate=True: ecmg_solve_extrapolated (EXP_true on
+        the finest level enqueued behind the cascade, one wait)."""
         info = self._infos()
-        rc = self.L.ecmg_solve(self.h, float(rel_tol), info)
+        fn = self.L.ecmg_solve_extrapolated if extrapolate else self.L.ecmg_solve
+        rc = fn(self.h, float(rel_tol), info)
         if not allow_fail:
             self._check(rc)
         return [i.as_dict() for i in info]

@@ -1336,7 +1336,7 @@ static int apply_tune_cache(ecmg_ctx *c) {
 // drives its outer refinement from the host, so the levels before it are
 // settled first.
 static int solve_impl(ecmg_ctx *c, double rel_tol, const int32_t *fixed, ecmg_level_info *info,
-                      const double *level_tol = nullptr) {
+                      const double *level_tol = nullptr, bool exp_true = false) {
     if (!c) return fail(nullptr, ECMG_EINVAL, "ctx is NULL");
     if (!c->ready) return fail(c, ECMG_ESTATE, "ecmg_solve before ecmg_setup");
     if (!fixed && !level_tol && !(rel_tol >= 0.0)) return fail(c, ECMG_EINVAL, "rel_tol = %g must be >= 0", rel_tol);
@@ -1384,6 +1384,9 @@ static int solve_impl(ecmg_ctx *c, double rel_tol, const int32_t *fixed, ecmg_le
     };
     for (int l = 0;; ++l) {
         if (l == n) {
+            // EXP_true on the finest level (the last step of Algorithm 4)
+            // behind the cascade, before the one wait; again after a re-solve
+            if (exp_true) CHK(do_exp_true(c, n - 1));
             CHK(settle(n));
             if (redo < 0) break;
             l = redo;
@@ -1676,6 +1679,10 @@ int ecmg_extrapolate_batch(ecmg_ctx *const *ctxs, int32_t n) {
 }
 
 int ecmg_solve(ecmg_ctx *c, double rel_tol, ecmg_level_info *info) { return solve_impl(c, rel_tol, nullptr, info); }
+
+int ecmg_solve_extrapolated(ecmg_ctx *c, double rel_tol, ecmg_level_info *info) {
+    return solve_impl(c, rel_tol, nullptr, info, nullptr, true);
+}
 
 int ecmg_solve_fixed(ecmg_ctx *c, const int32_t *iters, ecmg_level_info *info) {
     if (!iters) return fail(c, ECMG_EINVAL, "iters is NULL");

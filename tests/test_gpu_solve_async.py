@@ -150,3 +150,24 @@ def test_speculation_off_gives_the_same_iterates(ecmg):
     assert out[0][0] == out[1][0]
     for l in range(p.levels):
         assert np.array_equal(out[0][1][l], out[1][1][l]), l
+
+
+def test_solve_extrapolated_matches_solve_then_extrapolate(ecmg):
+    """ecmg_solve_extrapolated (EXP_true enqueued behind the cascade, one wait)
+    leaves the U~ of ecmg_solve + ecmg_extrapolate, also when a speculative
+    level falls short and the finest levels are solved again."""
+    p = workloads.variable_beta_robin_cube(levels=5)
+    L = p.levels - 1
+    ref = {}
+    with ecmg.Solver(persistent_nodes=0) as s:
+        s.setup(p)
+        for eps in (1e-6, 1e-10):
+            s.solve(eps)
+            s.extrapolate(L, out=False)
+            ref[eps] = s.get(L, ecmg.VEC_UTILDE)
+    with ecmg.Solver(persistent_nodes=0) as s:
+        s.setup(p)
+        for eps in (1e-6, 1e-6, 1e-6, 1e-10):                 # the last one falls short
+            infos = s.solve(eps, extrapolate=True)
+            assert all(i["status"] == ecmg.OK for i in infos)
+            assert np.array_equal(s.get(L, ecmg.VEC_UTILDE), ref[eps]), eps
