@@ -137,11 +137,46 @@ def cpu_baseline(problem, levels, precision_interp=0, min_seconds=10.0):
         dt += time.perf_counter() - t0
         reps += 1
     nodes = p.nodes_at(levels - 1)
-    return {"value": nodes * reps / dt, "unit": "unknowns/s", "cores": oracle.num_threads(), "kind": "oracle",
+    cores = oracle.num_threads()
+    # the same region on one core, on the small smooth Dirichlet workload
+    m1, m1_desc = workload("smooth-dirichlet-33")
+    lv1 = [oracle.discretize(m1, l) for l in range(m1.levels)]
+    reps1, dt1 = 0, 0.0
+    oracle.set_num_threads(1)
+    try:
+        while reps1 == 0 or dt1 < 1.0:
+            t0 = time.perf_counter()
+            oracle.cascade(m1, levels=lv1, errors=False, keep_vectors=False)
+            dt1 += time.perf_counter() - t0
+            reps1 += 1
+    finally:
+        oracle.set_num_threads(cores)
+    n1 = m1.nodes_at(m1.levels - 1)
+    return {"value": nodes * reps / dt, "unit": "unknowns/s", "cores": cores, "kind": "oracle",
             "sample": "same workload on %d levels (finest %s elements, %d nodes): oracle DSOLVE + EXP_finite + "
                       "JCG + EXP_true region, %d repetitions, %.1f s, iterations %s" % (
                           levels, "x".join(map(str, p.n_at(levels - 1))), nodes, reps, dt,
-                          [r.iters for r in res])}
+                          [r.iters for r in res]),
+            "host": host_cpu(),
+            "one_core": {"value": n1 * reps1 / dt1, "unit": "unknowns/s", "cores": 1,
+                         "sample": "%s: the same region, %d repetitions, %.2f s" % (m1_desc, reps1, dt1)}}
+
+
+def host_cpu():
+    """CPU model, sockets and logical CPUs of the host (and those this process may use)."""
+    model, sockets = "unknown", set()
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name") and model == "unknown":
+                    model = line.split(":", 1)[1].strip()
+                elif line.startswith("physical id"):
+                    sockets.add(line.split(":", 1)[1].strip())
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"model": model, "sockets": max(1, len(sockets)), "logical_cpus": os.cpu_count(),
+            "usable_cpus": usable}
 
 
 def precision_comparison(E, torch, name="high-contrast-513x257x257", steps=3):

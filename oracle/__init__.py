@@ -74,6 +74,7 @@ def lib():
         C = ctypes.POINTER(_CSR)
         i64, dbl = ctypes.c_int64, ctypes.c_double
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_set_num_threads.argtypes = [ctypes.c_int]
         L.orc_dirichlet_mask.argtypes = [G, P]
         L.orc_element_stiffness.argtypes = [dbl, dbl, dbl, P]
         L.orc_face_mass.argtypes = [dbl, dbl, P]
@@ -112,6 +113,11 @@ def _ptr(a: Optional[np.ndarray]):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's later parallel loops (timing of the baseline)."""
+    lib().orc_set_num_threads(int(n))
 
 
 # ---------------------------------------------------------------------------

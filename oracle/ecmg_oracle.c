@@ -64,6 +64,15 @@ int orc_num_threads(void) {
 #endif
 }
 
+/* threads of the following parallel regions (n >= 1); timing only */
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* Node (i,j,k) lies on a Dirichlet face (Dirichlet wins on shared edges). */
 static int is_dirichlet(const orc_grid *g, int64_t i, int64_t j, int64_t k) {
     const int32_t *t = g->face_type;

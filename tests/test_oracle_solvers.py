@@ -118,3 +118,19 @@ def test_tolerance_schedule_closed_form(orc):
     assert orc.tolerance_schedule(3, 1e-6, 1.0) == [0.0, 0.0, 1e-6]
     with pytest.raises(ValueError):
         orc.tolerance_schedule(4, 0.0, 2.0)
+
+
+def test_oracle_thread_count_is_settable(orc):
+    """The baseline's one-core timing sets the oracle's OpenMP threads; the
+    cascade takes the same iterations on one thread as on all of them."""
+    p = workloads.smooth_dirichlet_cube(levels=3, eps=1e-10)
+    full = orc.num_threads()
+    ref = [r.iters for r in orc.cascade(p)]
+    orc.set_num_threads(1)
+    try:
+        assert orc.num_threads() == 1
+        one = [r.iters for r in orc.cascade(p)]
+    finally:
+        orc.set_num_threads(full)
+    assert orc.num_threads() == full
+    assert one == ref
