@@ -248,7 +248,7 @@ def batched(E, torch, n_boxes=512, steps=3):
     import workloads
     probs = workloads.batched_mix(n_boxes, seed=0)
     t0 = time.perf_counter()
-    solvers = [E.Solver(keep_w=False).setup(p, device_fields=True) for p in probs]
+    solvers = [E.Solver(keep_w=False, dsolve_dense_max=0).setup(p, device_fields=True) for p in probs]
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     nodes = sum(p.nodes_at(p.levels - 1) for p in probs)

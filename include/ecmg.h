@@ -141,9 +141,12 @@ typedef struct {
                                   (20,000; 2,400,000 in the serving loop)              */
     int64_t dsolve_dense_max;  /* ecmg_solve: DSOLVE levels with at most this many free
                                   nodes (capped at 8192) are solved with an explicit
-                                  inverse of A_FF, built on the first solve (Cholesky,
-                                  rocSOLVER) and applied as one matrix-vector product;
-                                  larger ones, and 0, use FP64 JCG (default 8192)        */
+                                  inverse of A_FF, built by ecmg_setup (Cholesky and
+                                  inverse, rocSOLVER) and applied as one matrix-vector
+                                  product per solve; larger ones, and 0, use FP64 JCG
+                                  to dsolve_tol (default 8192).  The batched form and
+                                  the server always use FP64 JCG, so their contexts
+                                  are best created with 0 (no factorisation at setup) */
     int32_t autotune;          /* 0 (default): built-in JCG configuration per level; 1:
                                   ecmg_setup applies the choices the tuning cache holds
                                   for the hierarchy's JCG levels (a missing file or
@@ -160,6 +163,25 @@ typedef struct {
                                   level and every finer one are solved again from their
                                   EXP_finite start with status reads (same results as
                                   speculate = 0, at the cost of the repeated work)  */
+    int32_t fold_blocks;       /* tiled JCG levels whose two passes have at most this many
+                                  blocks each take the CG scalar steps inside the passes
+                                  (every block sums the previous pass's partials in one
+                                  fixed order); larger levels run a one-block finishing
+                                  kernel after each pass.  -1 = default (4096, also the
+                                  largest value honoured), 0 = never.  Both forms compute
+                                  the same recurrence; only the summation order differs */
+    int32_t true_residual;     /* 1: after each JCG level, recompute ||F - A u||_2 on the
+                                  free nodes from the final iterate (one more stencil
+                                  pass per level) and report it as info.rre_true; 0
+                                  (default): rre_true = -1                              */
+    /* Device allocator hook (NULL = hipMalloc / hipFree).  alloc returns `bytes` of
+     * device memory usable on hip_stream (the library's stream; hipStream_t as
+     * void*), or NULL on failure (ECMG_ENOMEM); free releases a pointer alloc
+     * returned, after every use of it enqueued on that stream so far.  Lets a
+     * caching allocator (e.g. PyTorch's) back the hierarchy.  Both or neither. */
+    void *(*alloc)(size_t bytes, void *hip_stream, void *user);
+    void (*free)(void *ptr, void *hip_stream, void *user);
+    void *alloc_user;
 } ecmg_options;
 
 /* One JCG level's configuration chosen by the autotuner. */
@@ -185,6 +207,9 @@ typedef struct {
     double rre;                /* ||r||_2 / ||f_h||_2 at exit (recurrence residual)     */
     double nf;                 /* ||f_h||_2 of the stopping test                        */
     double ms;                 /* wall time of the level on the device stream          */
+    double rre_true;           /* ||F - A u||_2 / ||f_h||_2 over the free nodes from the
+                                  final iterate (options.true_residual = 1; else -1);
+                                  rounding in the recurrence makes it differ from rre */
 } ecmg_level_info;
 
 typedef struct ecmg_ctx ecmg_ctx;
@@ -202,13 +227,15 @@ int ecmg_create(const ecmg_options *opt, ecmg_ctx **out);
  * diagonal, and ||f_h||_2 = ||(F - A_FD g_D on free nodes, g_D on Dirichlet
  * nodes)||_2.  Validates the problem: ECMG_EINVAL for lo >= hi, n0 < 1,
  * levels < 2, a bad face type, beta <= 0, alpha < 0, non-finite samples, or a
- * singular system (no Dirichlet face and alpha == 0 everywhere).  May be called
- * again; it frees the previous hierarchy first. */
+ * singular system (no Dirichlet face and alpha == 0 everywhere).  Also builds
+ * the direct DSOLVE of levels 0 and 1 (options.dsolve_dense_max).  May be
+ * called again; it frees the previous hierarchy first. */
 int ecmg_setup(ecmg_ctx *ctx, const ecmg_problem *problem);
 
-/* Algorithm 4: DSOLVE on levels 0 and 1 (FP64 JCG to options.dsolve_tol), then
- * for each finer level W = EXP_finite(u_{l-1}, u_{l-2}), JCG from W (with g_D
- * imposed) while ||r||_2 > rel_tol ||f_h||_2.  info: NULL or an array of
+/* Algorithm 4: DSOLVE on levels 0 and 1 (the explicit inverse of A_FF that
+ * ecmg_setup built, or FP64 JCG to options.dsolve_tol; see dsolve_dense_max),
+ * then for each finer level W = EXP_finite(u_{l-1}, u_{l-2}), JCG from W (with
+ * g_D imposed) while ||r||_2 > rel_tol ||f_h||_2.  info: NULL or an array of
  * `levels` entries.  Returns ECMG_ENOTCONV / ECMG_EBREAKDOWN if any level
  * failed (all levels still run; each entry has its own status). */
 int ecmg_solve(ecmg_ctx *ctx, double rel_tol, ecmg_level_info *info);

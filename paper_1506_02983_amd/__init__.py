@@ -12,9 +12,12 @@ the GPU through the library's device-callback interface.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import dataclasses
 import os
+import sys
+import weakref
 from typing import List, Optional, Sequence
 
 import numpy as np
@@ -50,13 +53,18 @@ class ProblemC(ctypes.Structure):
                 ("beta", Field), ("f", Field), ("g_D", Field), ("alpha", Field), ("g_R", Field)]
 
 
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("interp", ctypes.c_int32),
                 ("keep_w", ctypes.c_int32), ("inner_tol", ctypes.c_double), ("dsolve_tol", ctypes.c_double),
                 ("chunk", ctypes.c_int32), ("timing", ctypes.c_int32), ("hip_stream", ctypes.c_void_p),
                 ("persistent_nodes", ctypes.c_int64), ("dsolve_dense_max", ctypes.c_int64),
                 ("autotune", ctypes.c_int32), ("tune_cache", ctypes.c_char_p), ("method", ctypes.c_int32),
-                ("speculate", ctypes.c_int32)]
+                ("speculate", ctypes.c_int32), ("fold_blocks", ctypes.c_int32), ("true_residual", ctypes.c_int32),
+                ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_user", ctypes.c_void_p)]
 
 
 class TuneResult(ctypes.Structure):
@@ -74,7 +82,7 @@ class LevelInfo(ctypes.Structure):
     _fields_ = [("level", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("iters", ctypes.c_int32), ("outer_steps", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("rre", ctypes.c_double), ("nf", ctypes.c_double),
-                ("ms", ctypes.c_double)]
+                ("ms", ctypes.c_double), ("rre_true", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -93,6 +101,20 @@ EXPORTS = ["ecmg_default_options", "ecmg_create", "ecmg_setup", "ecmg_solve", "e
 
 _lib = None
 
+# Contexts and servers still open at interpreter exit are closed by an exit
+# handler registered after torch's (so it runs first, while the HIP runtime and
+# torch's allocator are still up); __del__ makes no library call once the
+# interpreter is finalizing.
+_live = weakref.WeakSet()
+
+
+def _close_live():
+    for obj in list(_live):
+        try:
+            obj.close()
+        except Exception:  # noqa: BLE001
+            pass
+
 
 def load_library(path: str = LIB_PATH):
     """Load libecmg.so; raises ImportError if it is missing (no fallback)."""
@@ -108,6 +130,7 @@ def load_library(path: str = LIB_PATH):
         import torch  # noqa: F401
     except ImportError:
         pass
+    atexit.register(_close_live)        # after torch's own exit handlers, so it runs before them
     L = ctypes.CDLL(path)
     P, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
     L.ecmg_default_options.argtypes = [ctypes.POINTER(Options)]
@@ -290,6 +313,24 @@ def problem_struct(problem, device_fields: bool = False):
 # context
 # ---------------------------------------------------------------------------
 
+def _torch_allocator_hooks():
+    """(alloc, free) callbacks that take the library's device memory from
+    PyTorch's caching allocator, on the library's stream."""
+    import torch
+
+    def alloc(nbytes, stream, user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device(),
+                                                      torch.cuda.ExternalStream(int(stream or 0)))
+        except Exception:                      # noqa: BLE001 - reported as ECMG_ENOMEM
+            return None
+
+    def free(ptr, stream, user):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    return ALLOC_FN(alloc), FREE_FN(free)
+
+
 class Solver:
     """One ECMG_jcg (or, with method=CG, ECMG_cg) context: one problem
     hierarchy resident on the device."""
@@ -298,7 +339,8 @@ class Solver:
                  max_iter: int = 20000, dsolve_tol: float = 1e-14, inner_tol: float = 1e-4,
                  chunk: int = 0, timing: bool = False, stream=None, persistent_nodes: int = -1,
                  dsolve_dense_max: Optional[int] = None, autotune: int = 0, tune_cache: Optional[str] = None,
-                 method: int = JCG, speculate: bool = True):
+                 method: int = JCG, speculate: bool = True, fold_blocks: int = -1, true_residual: bool = False,
+                 torch_allocator: bool = False):
         self.L = load_library()
         o = Options()
         self.L.ecmg_default_options(ctypes.byref(o))
@@ -312,12 +354,19 @@ class Solver:
         o.tune_cache = tune_cache.encode() if tune_cache else None
         o.method = int(method)
         o.speculate = int(speculate)
+        o.fold_blocks = int(fold_blocks)
+        o.true_residual = int(true_residual)
+        self._hooks = None
+        if torch_allocator:
+            self._hooks = _torch_allocator_hooks()
+            o.alloc, o.free = self._hooks
         self.opt = o
         h = ctypes.c_void_p()
         self._check(self.L.ecmg_create(ctypes.byref(o), ctypes.byref(h)), None)
         self.h = h
         self.levels = 0
         self._keep = None
+        _live.add(self)
 
     def _check(self, rc, h="self"):
         if rc != OK:
@@ -331,6 +380,8 @@ class Solver:
             self.h = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:  # noqa: BLE001
@@ -540,6 +591,7 @@ class Server:
             raise EcmgError(rc, (self.L.ecmg_last_error(None) or b"").decode())
         self.device_fields = device_fields
         self._req = {}
+        _live.add(self)
 
     def _check(self, rc):
         if rc != OK:
@@ -589,6 +641,14 @@ class Server:
         if self.h:
             self.L.ecmg_server_destroy(self.h)
             self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        if sys.is_finalizing():
+            return
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass
 
     def __enter__(self):
         return self

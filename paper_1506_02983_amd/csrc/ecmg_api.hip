@@ -88,6 +88,7 @@ struct ecmg_ctx {
     // when it gets there) and a start / end event pair
     JcgScalars *sc_lv = nullptr;
     JcgScalars *sc_lv_dev = nullptr;           // the same slots as kernels address them
+    double *rrt_lv = nullptr;                  // per level ||F - A u||^2 (options.true_residual), pinned
     PersistentTask *task_lv = nullptr;
     int lv_cap = 0;
     std::vector<hipEvent_t> lv_ev;
@@ -128,6 +129,16 @@ static int fail(ecmg_ctx *c, int code, const char *fmt, ...) {
 
 static int dalloc(ecmg_ctx *c, void **p, size_t bytes) {
     if (bytes == 0) bytes = 8;
+    if (c->opt.alloc) {                          // the caller's allocator (stream-ordered)
+        *p = c->opt.alloc(bytes, (void *)c->stream, c->opt.alloc_user);
+        if (!*p) return fail(c, ECMG_ENOMEM, "allocator hook returned NULL for %zu bytes", bytes);
+        if ((uintptr_t)*p % 256 != 0) {
+            c->opt.free(*p, (void *)c->stream, c->opt.alloc_user);
+            *p = nullptr;
+            return fail(c, ECMG_EINVAL, "allocator hook returned a pointer not aligned to 256 bytes");
+        }
+        return ECMG_OK;
+    }
     hipError_t e = hipMalloc(p, bytes);
     if (e != hipSuccess) {
         *p = nullptr;
@@ -162,8 +173,10 @@ static hipError_t copy_out(const Geom &g, double *host, const double *dev, doubl
     if (e != hipSuccess) return e;
     return hipMemcpyAsync(host, dense, 8 * (size_t)g.nreal, hipMemcpyDeviceToHost, s);
 }
-static void dfree(void *p) {
-    if (p) (void)hipFree(p);
+static void dfree(ecmg_ctx *c, void *p) {
+    if (!p) return;
+    if (c->opt.free) c->opt.free(p, (void *)c->stream, c->opt.alloc_user);
+    else (void)hipFree(p);
 }
 
 // ---------------------------------------------------------------------------
@@ -250,7 +263,7 @@ static std::vector<double> gauss_coords(const Geom &g, const double lo[3], int d
 static int ensure_stage(ecmg_ctx *c, int64_t n) {
     if (n <= c->stage_n) return ECMG_OK;
     if (c->hstage) (void)hipHostFree(c->hstage);
-    dfree(c->dstage);
+    dfree(c, c->dstage);
     c->hstage = nullptr;
     c->dstage = nullptr;
     c->stage_n = 0;
@@ -275,9 +288,9 @@ static int sample(ecmg_ctx *c, const ecmg_field &fld, const char *name, int face
         const int rc = fld.device(face, (int64_t)x.size(), (int64_t)y.size(), (int64_t)z.size(), dx, dy, dz, dout,
                                   (void *)c->stream, fld.user);
         HIPCHK(c, hipStreamSynchronize(c->stream));
-        dfree(dx);
-        dfree(dy);
-        dfree(dz);
+        dfree(c, dx);
+        dfree(c, dy);
+        dfree(c, dz);
         if (rc != 0) return fail(c, ECMG_ECALLBACK, "device callback for %s returned %d", name, rc);
         return ECMG_OK;
     }
@@ -372,6 +385,7 @@ static int rec_flush(ecmg_ctx *c, int iter_limit) {
 }
 
 static int apply_tune_cache(ecmg_ctx *c);
+static int dense_prepare(ecmg_ctx *c, int l);
 
 // ---------------------------------------------------------------------------
 // JCG on one level (the JCG loop of Algorithm 4)
@@ -734,6 +748,30 @@ static bool uses_mixed(const ecmg_ctx *c, int l) {
     return c->opt.precision == ECMG_MIXED && l >= 2 && !uses_persistent(c, l) && c->lv[l].g.nreal > c->mixed_min;
 }
 
+// ||F - A u_l||^2 over the free nodes of level l from its current iterate,
+// enqueued: a JCG init pass into the scratch residual (its finishing step
+// leaves the sum in the context's scalars, which the level no longer needs),
+// copied into the level's pinned slot once the stream gets there.
+static int enqueue_true_residual(ecmg_ctx *c, int l) {
+    Level &L = c->lv[l];
+    StencilArgs<double> a = stencil_args(c, L);
+    a.v = L.x;
+    a.r = c->r;
+    a.p_init = 0;
+    launch_stencil<double>(MODE_INIT, a, c->stream);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(c->rrt_lv + l, &c->sc->rr, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    return ECMG_OK;
+}
+
+// info->rre_true of level l from its pinned slot (after the stream has passed
+// enqueue_true_residual), -1 when not requested
+static void fill_true_residual(const ecmg_ctx *c, int l, ecmg_level_info *info) {
+    const Level &L = c->lv[l];
+    if (!c->opt.true_residual) info->rre_true = -1.0;
+    else info->rre_true = L.nf > 0 ? std::sqrt(c->rrt_lv[l]) / L.nf : 0.0;
+}
+
 static int run_level_jcg(ecmg_ctx *c, int l, double tol_abs, int max_iter, int fixed, ecmg_level_info *info) {
     if (uses_mixed(c, l) && fixed < 0) return run_jcg_mixed(c, l, tol_abs, max_iter, info);
     if (uses_persistent(c, l)) return run_jcg_persistent(c, l, tol_abs, max_iter, fixed, info);
@@ -766,33 +804,33 @@ static int do_exp_true(ecmg_ctx *c, int l) {
 // ---------------------------------------------------------------------------
 static void free_levels(ecmg_ctx *c) {
     for (auto &L : c->lv) {
-        dfree(L.beta);
-        dfree(L.F);
-        dfree(L.x);
-        dfree(L.dinv);
-        dfree(L.W);
-        dfree(L.Ut);
-        dfree(L.beta32);
-        dfree(L.dinv32);
-        dfree(L.ainv);
-        dfree(L.freeid);
+        dfree(c, L.beta);
+        dfree(c, L.F);
+        dfree(c, L.x);
+        dfree(c, L.dinv);
+        dfree(c, L.W);
+        dfree(c, L.Ut);
+        dfree(c, L.beta32);
+        dfree(c, L.dinv32);
+        dfree(c, L.ainv);
+        dfree(c, L.freeid);
         for (int f = 0; f < 6; ++f) {
-            dfree(L.alpha[f]);
-            dfree(L.alpha32[f]);
+            dfree(c, L.alpha[f]);
+            dfree(c, L.alpha32[f]);
         }
     }
     c->lv.clear();
-    dfree(c->r);
-    dfree(c->p0);
-    dfree(c->p1);
-    dfree(c->q);
-    dfree(c->partials);
+    dfree(c, c->r);
+    dfree(c, c->p0);
+    dfree(c, c->p1);
+    dfree(c, c->q);
+    dfree(c, c->partials);
     c->r = c->p0 = c->p1 = c->q = c->partials = nullptr;
-    dfree(c->r32);
-    dfree(c->p32a);
-    dfree(c->p32b);
-    dfree(c->q32);
-    dfree(c->d32);
+    dfree(c, c->r32);
+    dfree(c, c->p32a);
+    dfree(c, c->p32b);
+    dfree(c, c->q32);
+    dfree(c, c->d32);
     c->r32 = c->p32a = c->p32b = c->q32 = c->d32 = nullptr;
     c->scratch_n = 0;
     c->partials_n = 0;
@@ -820,6 +858,11 @@ void ecmg_default_options(ecmg_options *o) {
     o->tune_cache = nullptr;
     o->method = ECMG_JCG;
     o->speculate = 1;
+    o->fold_blocks = -1;
+    o->true_residual = 0;
+    o->alloc = nullptr;
+    o->free = nullptr;
+    o->alloc_user = nullptr;
 }
 
 int ecmg_create(const ecmg_options *opt, ecmg_ctx **out) {
@@ -834,6 +877,8 @@ int ecmg_create(const ecmg_options *opt, ecmg_ctx **out) {
         return fail(nullptr, ECMG_EINVAL, "unknown interpolation %d", o.interp);
     if (o.method != ECMG_JCG && o.method != ECMG_CG) return fail(nullptr, ECMG_EINVAL, "unknown method %d", o.method);
     if (o.max_iter < 0) return fail(nullptr, ECMG_EINVAL, "max_iter < 0");
+    if ((o.alloc == nullptr) != (o.free == nullptr))
+        return fail(nullptr, ECMG_EINVAL, "options.alloc and options.free must be given together");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
         return fail(nullptr, ECMG_EDEVICE, "no HIP device available");
@@ -855,7 +900,7 @@ int ecmg_create(const ecmg_options *opt, ecmg_ctx **out) {
     c->device_name = std::string(prop.gcnArchName) + " " + std::to_string(prop.multiProcessorCount) + " CUs";
     if (const char *kz = std::getenv("ECMG_KZ")) c->KZ = std::max(1, std::atoi(kz));
     if (const char *kt = std::getenv("ECMG_KZ_TARGET")) c->kz_target = std::max(1, std::atoi(kt));
-    if (const char *v = std::getenv("ECMG_FOLD_BLOCKS")) c->fold_max = std::max(0, std::min(std::atoi(v), FOLD_MAX_BLOCKS));
+    if (o.fold_blocks >= 0) c->fold_max = std::min<int>(o.fold_blocks, FOLD_MAX_BLOCKS);
     if (const char *v = std::getenv("ECMG_PERSIST_SEG")) c->persist_seglen = std::max(1, std::atoi(v));
     if (const char *v = std::getenv("ECMG_PERSIST_NWG")) c->persist_nwg = std::max(1, std::atoi(v));
     if (const char *v = std::getenv("ECMG_BATCH_NPW")) c->batch_npw = std::max(64, std::atoi(v));
@@ -907,19 +952,19 @@ void ecmg_destroy(ecmg_ctx *c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     free_levels(c);
     if (c->blas) (void)rocblas_destroy_handle(c->blas);
-    dfree(c->sc);
-    dfree(c->sc32);
-    dfree(c->bt_tasks);
-    dfree(c->bt_sc);
-    dfree(c->bt_next);
-    dfree(c->bt_bar);
-    dfree(c->bt_exp);
+    dfree(c, c->sc);
+    dfree(c, c->sc32);
+    dfree(c, c->bt_tasks);
+    dfree(c, c->bt_sc);
+    dfree(c, c->bt_next);
+    dfree(c, c->bt_bar);
+    dfree(c, c->bt_exp);
     if (c->bt_sc_host) (void)hipHostFree(c->bt_sc_host);
-    dfree(c->d_task);
-    dfree(c->d_bar);
-    dfree(c->counters);
-    dfree(c->dres);
-    dfree(c->dstage);
+    dfree(c, c->d_task);
+    dfree(c, c->d_bar);
+    dfree(c, c->counters);
+    dfree(c, c->dres);
+    dfree(c, c->dstage);
     if (c->hstage) (void)hipHostFree(c->hstage);
     if (c->sc_host) (void)hipHostFree(c->sc_host);
     if (c->hres) (void)hipHostFree(c->hres);
@@ -928,6 +973,7 @@ void ecmg_destroy(ecmg_ctx *c) {
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     if (c->sc_lv) (void)hipHostFree(c->sc_lv);
     if (c->task_lv) (void)hipHostFree(c->task_lv);
+    if (c->rrt_lv) (void)hipHostFree(c->rrt_lv);
     for (auto e : c->lv_ev) (void)hipEventDestroy(e);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
@@ -1010,12 +1056,15 @@ int ecmg_setup(ecmg_ctx *c, const ecmg_problem *p) {
     if (c->lv_cap < p->levels) {
         if (c->sc_lv) (void)hipHostFree(c->sc_lv);
         if (c->task_lv) (void)hipHostFree(c->task_lv);
+        if (c->rrt_lv) (void)hipHostFree(c->rrt_lv);
         c->sc_lv = c->sc_lv_dev = nullptr;
         c->task_lv = nullptr;
+        c->rrt_lv = nullptr;
         c->lv_cap = 0;
         if (hipHostMalloc((void **)&c->sc_lv, sizeof(JcgScalars) * p->levels, hipHostMallocDefault) != hipSuccess ||
             hipHostMalloc((void **)&c->task_lv, sizeof(PersistentTask) * p->levels, hipHostMallocDefault) !=
-                hipSuccess)
+                hipSuccess ||
+            hipHostMalloc((void **)&c->rrt_lv, sizeof(double) * p->levels, hipHostMallocDefault) != hipSuccess)
             return fail(c, ECMG_ENOMEM, "pinned host allocation of %d level slots failed", p->levels);
         HIPCHK(c, hipHostGetDevicePointer((void **)&c->sc_lv_dev, c->sc_lv, 0));
         c->lv_cap = p->levels;
@@ -1090,11 +1139,11 @@ int ecmg_setup(ecmg_ctx *c, const ecmg_problem *p) {
                 const int e1 = std::min(g.nz, e0 + step);
                 std::vector<double> zz(gz.begin() + 2 * e0, gz.begin() + 2 * e1);
                 int rc = sample(c, p->f, "f", -1, gx, gy, zz, dbuf, 0);
-                if (rc != ECMG_OK) { dfree(dbuf); return rc; }
+                if (rc != ECMG_OK) { dfree(c, dbuf); return rc; }
                 launch_load_volume(g, e0, e1, dbuf, L.F, c->stream);
                 HIPCHK(c, hipStreamSynchronize(c->stream));
             }
-            dfree(dbuf);
+            dfree(c, dbuf);
         }
         // Robin faces: alpha at face-element centroids, g_R at face Gauss points
         launch_fill(L.x, g.nnodes, 0.0, c->stream);
@@ -1117,10 +1166,10 @@ int ecmg_setup(ecmg_ctx *c, const ecmg_problem *p) {
                 double *dbuf = nullptr;
                 CHK(dalloc_n(c, &dbuf, 4 * L.nface[f]));
                 int rc = sample(c, p->g_R, "g_R", f, s[0], s[1], s[2], dbuf, 0);
-                if (rc != ECMG_OK) { dfree(dbuf); return rc; }
+                if (rc != ECMG_OK) { dfree(c, dbuf); return rc; }
                 launch_load_face(g, f, dbuf, L.F, c->stream);
                 HIPCHK(c, hipStreamSynchronize(c->stream));
-                dfree(dbuf);
+                dfree(c, dbuf);
             }
         }
         // Dirichlet data at the nodes of Dirichlet faces
@@ -1137,10 +1186,10 @@ int ecmg_setup(ecmg_ctx *c, const ecmg_problem *p) {
             double *dbuf = nullptr;
             CHK(dalloc_n(c, &dbuf, (int64_t)s[pax].size() * s[qax].size()));
             int rc = sample(c, p->g_D, "g_D", f, s[0], s[1], s[2], dbuf, 0);
-            if (rc != ECMG_OK) { dfree(dbuf); return rc; }
+            if (rc != ECMG_OK) { dfree(c, dbuf); return rc; }
             launch_scatter_face(g, f, dbuf, L.x, c->stream);
             HIPCHK(c, hipStreamSynchronize(c->stream));
-            dfree(dbuf);
+            dfree(c, dbuf);
         }
         const double *al[6];
         for (int f = 0; f < 6; ++f) al[f] = L.alpha[f];
@@ -1167,6 +1216,9 @@ int ecmg_setup(ecmg_ctx *c, const ecmg_problem *p) {
         HIPCHK(c, hipStreamSynchronize(c->stream));
         L.nf = std::sqrt(c->hres[1]);
     }
+    // DSOLVE (Algorithm 4, levels 0 and 1): the explicit inverse of A_FF is a
+    // setup product, so every solve only applies it
+    for (int l = 0; l < std::min(2, c->nlev); ++l) CHK(dense_prepare(c, l));
     if (c->opt.autotune == 1) CHK(apply_tune_cache(c));
     c->ready = true;
     c->solved = false;
@@ -1175,7 +1227,7 @@ int ecmg_setup(ecmg_ctx *c, const ecmg_problem *p) {
 
 // ---------------------------------------------------------------------------
 // DSOLVE as a direct solve (Algorithm 4, levels 0 and 1): the explicit inverse
-// of A_FF from its Cholesky factor, built once per hierarchy on first use, then
+// of A_FF from its Cholesky factor, built once per hierarchy by ecmg_setup, then
 // x_F = A_FF^-1 (F - A_FD g_D) as one matrix-vector product per solve
 // ---------------------------------------------------------------------------
 static bool host_dir(const Geom &g, int i, int j, int k) {
@@ -1227,11 +1279,11 @@ static int dense_prepare(ecmg_ctx *c, int l) {
          hipStreamSynchronize(c->stream) == hipSuccess && info == 0;
     if (ok) launch_symmetrize(L.ainv, nf, c->stream);
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    dfree(d_fmap);
-    dfree(d_info);
+    dfree(c, d_fmap);
+    dfree(c, d_info);
     if (!ok) {                                    // not factorable: keep the JCG DSOLVE
-        dfree(L.ainv);
-        dfree(L.freeid);
+        dfree(c, L.ainv);
+        dfree(c, L.freeid);
         L.ainv = nullptr;
         L.freeid = nullptr;
         return ECMG_OK;
@@ -1267,7 +1319,7 @@ static int run_dsolve_dense(ecmg_ctx *c, int l, ecmg_level_info *info) {
 static int ensure_partials(ecmg_ctx *c, int64_t n) {
     if (n <= c->partials_n) return ECMG_OK;
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    dfree(c->partials);
+    dfree(c, c->partials);
     c->partials = nullptr;
     c->partials_n = 0;
     CHK(dalloc_n(c, &c->partials, n));
@@ -1378,6 +1430,7 @@ static int solve_impl(ecmg_ctx *c, double rel_tol, const int32_t *fixed, ecmg_le
             float ms = 0.f;
             HIPCHK(c, hipEventElapsedTime(&ms, c->lv_ev[2 * k], c->lv_ev[2 * k + 1]));
             li[k].ms = ms;
+            fill_true_residual(c, k, &li[k]);
         }
         settled = upto;
         return rec_flush_levels(c, limit);
@@ -1435,6 +1488,7 @@ static int solve_impl(ecmg_ctx *c, double rel_tol, const int32_t *fixed, ecmg_le
         }
         HIPCHK(c, hipEventRecord(c->lv_ev[2 * l + 1], c->stream));
         if (rc == ECMG_EDEVICE) return rc;
+        if (c->opt.true_residual) CHK(enqueue_true_residual(c, l));
         note(rc);
     }
     if (info)
@@ -1451,17 +1505,17 @@ static int solve_impl(ecmg_ctx *c, double rel_tol, const int32_t *fixed, ecmg_le
 // ---------------------------------------------------------------------------
 static int batch_reserve(ecmg_ctx *c, int n) {
     if (c->bt_cap >= n) return ECMG_OK;
-    dfree(c->bt_tasks);
-    dfree(c->bt_sc);
+    dfree(c, c->bt_tasks);
+    dfree(c, c->bt_sc);
     if (c->bt_sc_host) (void)hipHostFree(c->bt_sc_host);
     c->bt_tasks = nullptr;
     c->bt_sc = c->bt_sc_host = nullptr;
     c->bt_cap = 0;
     if (!c->bt_next) CHK(dalloc(c, (void **)&c->bt_next, 64));
-    dfree(c->bt_bar);
+    dfree(c, c->bt_bar);
     c->bt_bar = nullptr;
     CHK(dalloc(c, (void **)&c->bt_bar, 32 * sizeof(unsigned) * (size_t)n));
-    dfree(c->bt_exp);
+    dfree(c, c->bt_exp);
     c->bt_exp = nullptr;
     CHK(dalloc(c, (void **)&c->bt_exp, sizeof(ExpTask) * (size_t)n));
     CHK(dalloc(c, (void **)&c->bt_tasks, sizeof(PersistentTask) * (size_t)n));
@@ -1615,6 +1669,7 @@ int ecmg_solve_batch(ecmg_ctx *const *ctxs, int32_t n, double rel_tol, ecmg_leve
             const Level &L = c->lv[l];
             const JcgScalars &sc = c0->bt_sc_host[k];
             ecmg_level_info li{};
+            li.rre_true = -1.0;              // not computed by the batched form
             li.level = l;
             li.nx = L.g.nx;
             li.ny = L.g.ny;
@@ -1744,7 +1799,10 @@ int ecmg_jcg(ecmg_ctx *c, int32_t level, double rel_tol, int32_t fixed_iters, ec
     li.ny = L.g.ny;
     li.nz = L.g.nz;
     const int rc = run_level_jcg(c, level, rel_tol * L.nf, c->opt.max_iter, fixed_iters, &li);
+    if (rc == ECMG_EDEVICE) return rc;
+    if (c->opt.true_residual) CHK(enqueue_true_residual(c, level));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    fill_true_residual(c, level, &li);
     if (info) *info = li;
     return rc;
 }
@@ -1935,6 +1993,7 @@ int ecmg_autotune(ecmg_ctx *c, int32_t iters, const char *cache_path, ecmg_tune_
                     break;
                 }
                 ecmg_level_info li{};
+            li.rre_true = -1.0;              // not computed by the batched form
                 const int jr = run_level_jcg(c, l, 0.0, iters + 1, iters, &li);
                 if (jr == ECMG_EDEVICE) {
                     rc = jr;
@@ -1986,7 +2045,7 @@ int ecmg_autotune(ecmg_ctx *c, int32_t iters, const char *cache_path, ecmg_tune_
     }
     if (hipStreamSynchronize(c->stream) != hipSuccess && rc == ECMG_OK)
         rc = fail(c, ECMG_EDEVICE, "autotune: stream synchronisation failed");
-    dfree(save);
+    dfree(c, save);
     c->solved = false;
     if (rc != ECMG_OK) return rc;
     if (!path.empty()) {
@@ -2227,6 +2286,7 @@ static int server_tick(ecmg_server *S) {
         ecmg_ctx *c = r->ctx;
         const int l = r->level;
         ecmg_level_info li{};
+        li.rre_true = -1.0;
         li.level = l;
         li.nx = c->lv[l].g.nx;
         li.ny = c->lv[l].g.ny;
@@ -2253,6 +2313,7 @@ static int server_tick(ecmg_server *S) {
         const Level &L = c->lv[l];
         const JcgScalars &sc = c0->bt_sc_host[k];
         ecmg_level_info li{};
+        li.rre_true = -1.0;
         li.level = l;
         li.nx = L.g.nx;
         li.ny = L.g.ny;

@@ -34,7 +34,7 @@ def boxes():
 
 
 def _solve_batch(ecmg, probs, eps):
-    solvers = [ecmg.Solver().setup(p) for p in probs]
+    solvers = [ecmg.Solver(dsolve_dense_max=0).setup(p) for p in probs]
     infos = ecmg.solve_batch(solvers, eps)
     ecmg.extrapolate_batch(solvers)
     out = [(s.get(p.levels - 1, ecmg.VEC_U), s.get(p.levels - 1, ecmg.VEC_UTILDE)) for s, p in zip(solvers, probs)]
@@ -96,7 +96,7 @@ def test_batch_autotune_and_cache(ecmg, boxes, tmp_path):
     autotune = 1 from its cache solve bit for bit like the tuned ones."""
     cache = str(tmp_path / "tune.json")
     infos0, out0 = _solve_batch(ecmg, boxes, 1e-8)
-    solvers = [ecmg.Solver().setup(p) for p in boxes]
+    solvers = [ecmg.Solver(dsolve_dense_max=0).setup(p) for p in boxes]
     res = ecmg.autotune_batch(solvers, 1e-8, cache=cache)
     assert res["path"] == "batch" and res["candidates"] >= 2
     assert 0.0 < res["us_best"] <= res["us_default"]
@@ -111,7 +111,7 @@ def test_batch_autotune_and_cache(ecmg, boxes, tmp_path):
     with open(cache) as fh:
         entry = json.load(fh)["levels"]["batch fp64"]
     assert entry["path"] == "batch" and entry["nwg"] == res["nodes_per_workgroup"]
-    again = [ecmg.Solver(autotune=1, tune_cache=cache).setup(p) for p in boxes]
+    again = [ecmg.Solver(autotune=1, tune_cache=cache, dsolve_dense_max=0).setup(p) for p in boxes]
     ecmg.solve_batch(again, 1e-8)
     out2 = [s.get(p.levels - 1, ecmg.VEC_U) for s, p in zip(again, boxes)]
     for s in again:
