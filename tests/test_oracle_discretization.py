@@ -155,3 +155,91 @@ def test_trilinear_solution_reproduced(orc, faces):
         x = orc.dsolve(lv)
         ue = orc.exact_nodes(p, lv.grid)
         assert np.abs(x - ue).max() < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Variable coefficients: beta per element at its centroid, alpha per Robin
+# face element at its centroid (the reading of the bilinear form of Section 2
+# for coefficients that vary; every problem of Section 5 has beta = 1)
+# ---------------------------------------------------------------------------
+
+def _indicator(c, r):
+    """A field that is 1 within half-widths r of the point c and 0 elsewhere."""
+    def fn(x, y, z, face=-1):
+        inside = (np.abs(x - c[0]) < r[0]) & (np.abs(y - c[1]) < r[1]) & (np.abs(z - c[2]) < r[2])
+        return np.where(inside, 1.0, 0.0) + 0.0 * x * y * z
+    return fn
+
+
+def _node(n, i, j, k):
+    return i + (n[0] + 1) * (j + (n[1] + 1) * k)
+
+
+@pytest.mark.parametrize("e", [(0, 0, 0), (2, 3, 1), (1, 0, 1), (2, 1, 0)])
+def test_beta_of_one_element_lands_on_its_nodes(orc, e):
+    """A beta that is 1 around one element's centroid and 0 elsewhere gives a
+    matrix that is that element's Q1 stiffness (the closed-form tensor product,
+    not the oracle's quadrature) on its 8 nodes and zero everywhere else: beta is
+    sampled at that centroid and multiplies that element's matrix only."""
+    n, h = (3, 4, 2), (0.3, 0.25, 0.5)
+    c = [(e[d] + 0.5) * h[d] for d in range(3)]
+    p = _robin_cube(n, h).with_(beta=_indicator(c, [0.25 * hh for hh in h]))
+    A = orc.discretize(p, 0).dense()
+    want = np.zeros_like(A)
+    for a, b in itertools.product(range(8), repeat=2):
+        na = _node(n, e[0] + (a & 1), e[1] + ((a >> 1) & 1), e[2] + ((a >> 2) & 1))
+        nb = _node(n, e[0] + (b & 1), e[1] + ((b >> 1) & 1), e[2] + ((b >> 2) & 1))
+        d = [((a >> s) & 1) ^ ((b >> s) & 1) for s in range(3)]
+        want[na, nb] = _class_coeff(h, *d)
+    assert np.abs(A - want).max() <= 1e-14
+
+
+@pytest.mark.parametrize("face, fe", [(0, (1, 0)), (1, (3, 1)), (3, (2, 1)), (4, (0, 3)), (5, (2, 2))])
+def test_alpha_of_one_face_element_lands_on_its_nodes(orc, face, fe):
+    """With beta = 0 and an alpha that is 1 around one Robin face element's
+    centroid, the matrix is that face element's mass, alpha hp hq (1/9, 1/18,
+    1/36) by the number of in-face axes on which two nodes differ, on its 4
+    nodes, and zero elsewhere."""
+    n, h = (3, 4, 2), (0.3, 0.25, 0.5)
+    ax = face // 2
+    pa, qa = [d for d in range(3) if d != ax]
+    plane = 0.0 if face % 2 == 0 else n[ax] * h[ax]
+    c = [0.0] * 3
+    c[ax] = plane
+    c[pa] = (fe[0] + 0.5) * h[pa]
+    c[qa] = (fe[1] + 0.5) * h[qa]
+    if fe[0] >= n[pa] or fe[1] >= n[qa]:
+        pytest.skip("face element outside this face")
+    r = [0.25 * hh for hh in h]
+    p = _robin_cube(n, h, beta=0.0).with_(alpha=_indicator(c, r))
+    A = orc.discretize(p, 0).dense()
+    want = np.zeros_like(A)
+    hp, hq = h[pa], h[qa]
+    cls = (hp * hq / 9.0, hp * hq / 18.0, hp * hq / 36.0)
+    k_face = 0 if face % 2 == 0 else n[ax]
+    for a, b in itertools.product(range(4), repeat=2):
+        def idx(m):
+            ijk = [0, 0, 0]
+            ijk[ax] = k_face
+            ijk[pa] = fe[0] + (m & 1)
+            ijk[qa] = fe[1] + ((m >> 1) & 1)
+            return _node(n, *ijk)
+        want[idx(a), idx(b)] = cls[bin(a ^ b).count("1")]
+    assert np.abs(A - want).max() <= 1e-15
+
+
+@pytest.mark.parametrize("mask", range(64))
+def test_apply_rows_equals_assembled_rows(orc, mask):
+    """The oracle's row-wise operator (used to check single rows at sizes where
+    nothing is assembled) equals the assembled CSR matrix on every row, for every
+    combination of Dirichlet and Robin faces, with variable beta and alpha."""
+    faces = tuple(ROBIN if (mask >> f) & 1 else DIRICHLET for f in range(6))
+    p = workloads.variable_beta_robin_cube(levels=1).with_(
+        n0=(3, 4, 2), hi=(0.9, 1.0, 0.5), face_type=faces,
+        alpha=lambda x, y, z, face=-1: 1.0 + 0.5 * x * x + 0.25 * y - 0.1 * z + 0.0 * x)
+    lv = orc.discretize(p, 0)
+    v = workloads.random_vector(lv.grid.num_nodes, seed=mask)
+    full = orc.spmv(lv, v)
+    rows = np.arange(lv.grid.num_nodes)
+    got = orc.apply_rows(lv.grid, lv.beta, lv.alpha, v, rows)
+    assert np.abs(got - full).max() <= 1e-14 * max(np.abs(full).max(), 1.0), mask
