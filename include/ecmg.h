@@ -364,6 +364,19 @@ int ecmg_device_view(ecmg_ctx *ctx, int32_t level, int32_t which, void **dptr, i
 int ecmg_norms(ecmg_ctx *ctx, int32_t level, int32_t which, int32_t minus_which,
                const double *minus, int32_t minus_on_device, double out[2]);
 
+/* ecmg_norms without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, serving loops that forbid hipMalloc):
+ * out[0] = max |v|, out[1] = (sum v^2 / N)^(1/2) for v = vec[which] -
+ * vec[minus_which] (ECMG_VEC_NONE = 0), the same kernel and summation order
+ * as ecmg_norms, so the same results bit for bit.  The reduction's block
+ * partials, arrival counter and totals (at most 2,048 blocks: 33 KB) live in
+ * a static device array of the library, one per GPU, held until the process
+ * ends; a level that needs more blocks is rejected with ECMG_EINVAL.  Every
+ * call on a GPU shares that GPU's array, so calls that overlap on one GPU
+ * (from several threads or contexts) race; calls on one context are ordered.
+ * Makes no hipMalloc, hipFree or other allocating call; waits for the result. */
+int ecmg_norms_noalloc(ecmg_ctx *ctx, int32_t level, int32_t which, int32_t minus_which, double out[2]);
+
 /* Elements per axis of a level. */
 int ecmg_level_dims(ecmg_ctx *ctx, int32_t level, int64_t n[3]);
 

@@ -97,7 +97,7 @@ EXPORTS = ["ecmg_default_options", "ecmg_create", "ecmg_setup", "ecmg_solve", "e
            "ecmg_extrapolate_batch", "ecmg_server_create", "ecmg_server_submit", "ecmg_server_step",
            "ecmg_server_poll", "ecmg_server_stats", "ecmg_server_reset_stats", "ecmg_server_destroy",
            "ecmg_autotune", "ecmg_tune_lookup", "ecmg_set_timing", "ecmg_cascadic_schedule",
-           "ecmg_solve_levels", "ecmg_tolerance_schedule", "ecmg_autotune_batch"]
+           "ecmg_solve_levels", "ecmg_tolerance_schedule", "ecmg_autotune_batch", "ecmg_norms_noalloc"]
 
 _lib = None
 
@@ -148,6 +148,7 @@ def load_library(path: str = LIB_PATH):
     L.ecmg_set.argtypes = [P, i32, i32, P]
     L.ecmg_device_view.argtypes = [P, i32, i32, ctypes.POINTER(P), P, P]
     L.ecmg_norms.argtypes = [P, i32, i32, i32, P, i32, P]
+    L.ecmg_norms_noalloc.argtypes = [P, i32, i32, i32, P]
     L.ecmg_level_dims.argtypes = [P, i32, P]
     L.ecmg_plan_bytes.argtypes = [ctypes.POINTER(ProblemC), i32, ctypes.POINTER(ctypes.c_size_t)]
     L.ecmg_kernel_times.argtypes = [P, i32, i32, P]
@@ -508,6 +509,13 @@ class Solver:
             m = np.ascontiguousarray(minus, dtype=np.float64)
             ptr = m.ctypes.data
         self._check(self.L.ecmg_norms(self.h, int(level), int(which), int(minus_which), ptr, on_dev, out))
+        return float(out[0]), float(out[1])
+
+    def norms_noalloc(self, level: int, which: int, minus_which: int = VEC_NONE):
+        """ecmg_norms_noalloc: (max, RMS) of vec[which] - vec[minus_which] with
+        the reduction's scratch in the library's static device array."""
+        out = (ctypes.c_double * 2)()
+        self._check(self.L.ecmg_norms_noalloc(self.h, int(level), int(which), int(minus_which), out))
         return float(out[0]), float(out[1])
 
     def kernel_times(self, level: int, kind: int) -> tuple:

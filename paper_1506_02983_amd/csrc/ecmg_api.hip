@@ -26,6 +26,27 @@ namespace {
 thread_local std::string g_thread_error;
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free reductions (ecmg_norms_noalloc): the block partials, the
+// arrival counter and the two totals of the norm kernel live in this
+// file-scope device array, one copy per GPU, held until the process ends.
+// Host code never passes `scratch` itself (in host code the name is only a
+// stand-in, not a device address): ecmg_create looks up each device's address
+// once with hipGetSymbolAddress and every later use goes through it.
+// ---------------------------------------------------------------------------
+constexpr int NOALLOC_BLOCKS = 2048;                       // the norm kernel's most blocks
+constexpr size_t NOALLOC_TOTALS = 2 * NOALLOC_BLOCKS;      // doubles: partials, then 2 totals
+constexpr size_t NOALLOC_COUNTER = NOALLOC_TOTALS + 32;    // doubles: counter on its own 256-byte line
+constexpr size_t NOALLOC_BYTES = 8 * (NOALLOC_COUNTER + 32);
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[NOALLOC_MAX_DEVICES];           // device address of `scratch`, per device
+
+__global__ void k_noalloc_clear(unsigned *counter) {
+    if (threadIdx.x == 0) *counter = 0u;
+}
+
 struct ecmg_ctx {
     ecmg_options opt{};
     hipStream_t stream = nullptr;
@@ -890,6 +911,18 @@ int ecmg_create(const ecmg_options *opt, ecmg_ctx **out) {
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         return fail(nullptr, ECMG_EDEVICE, "device %d is %s; this library is built for gfx950", dev,
                     prop.gcnArchName);
+    {
+        // the device address of this GPU's copy of `scratch` (ecmg_norms_noalloc)
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (dev >= NOALLOC_MAX_DEVICES) return fail(nullptr, ECMG_EDEVICE, "device %d: too many devices", dev);
+        if (!g_scratch_ptr[dev]) {
+            void *ptr = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !ptr)
+                return fail(nullptr, ECMG_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+            g_scratch_ptr[dev] = ptr;
+        }
+    }
     ecmg_ctx *c = new ecmg_ctx();
     c->device = dev;
     c->opt = o;
@@ -1896,6 +1929,34 @@ int ecmg_norms(ecmg_ctx *c, int32_t level, int32_t which, int32_t minus_which, c
     launch_norms(L.g, a, b, h, c->partials, c->counters + 2, c->dres, c->stream);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipMemcpyAsync(c->hres, c->dres, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    out[0] = c->hres[0];
+    out[1] = std::sqrt(c->hres[1] / (double)L.g.nreal);
+    return ECMG_OK;
+}
+
+int ecmg_norms_noalloc(ecmg_ctx *c, int32_t level, int32_t which, int32_t minus_which, double out[2]) {
+    CHK(check_level(c, &level, 0));
+    if (!out) return fail(c, ECMG_EINVAL, "out is NULL");
+    Level &L = c->lv[level];
+    const double *a = vec_ptr(c, L, which);
+    if (!a) return fail(c, ECMG_EINVAL, "vector %d is not available on level %d", which, level);
+    const double *b = nullptr;
+    if (minus_which != ECMG_VEC_NONE) {
+        b = vec_ptr(c, L, minus_which);
+        if (!b) return fail(c, ECMG_EINVAL, "vector %d is not available on level %d", minus_which, level);
+    }
+    if (reduce_blocks(L.g.nnodes) > NOALLOC_BLOCKS)
+        return fail(c, ECMG_EINVAL, "level %d: %d reduction blocks exceed the static scratch (%d)", level,
+                    reduce_blocks(L.g.nnodes), NOALLOC_BLOCKS);
+    unsigned char *base = (unsigned char *)g_scratch_ptr[c->device];   // set by ecmg_create
+    double *partials = (double *)base;
+    double *totals = partials + NOALLOC_TOTALS;
+    unsigned *counter = (unsigned *)(partials + NOALLOC_COUNTER);
+    hipLaunchKernelGGL(k_noalloc_clear, dim3(1), dim3(64), 0, c->stream, counter);
+    launch_norms(L.g, a, b, nullptr, partials, counter, totals, c->stream);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(c->hres, totals, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     out[0] = c->hres[0];
     out[1] = std::sqrt(c->hres[1] / (double)L.g.nreal);
