@@ -52,11 +52,14 @@ def test_jcg_fixed_iterations_single_level(orc, ecmg, driver):
             assert info["rre"] == pytest.approx(ref.rre, rel=1e-9)
 
 
-# (problem, EXP_finite form, iterate parity bound).  The bound is 1e-12 (the
-# target for the benchmark workloads, eps >= 1e-10); for the paper's Problem 2
-# at eps = 1e-12 the iterates are converged to the level where two FP64 CG runs
-# that differ only in summation order separate (~ eps times the amplification
-# of rounding through the iteration), so its bound is 5 eps.
+# (problem, EXP_finite form, iterate parity bound).  The bound is 1e-12; for
+# the paper's Problem 2 at eps = 1e-12 the iterates are converged to the level
+# where two FP64 runs of the same cascade separate when only their summation
+# order differs: the oracle against itself with reversed dot products and
+# reversed row sums separates by 7.5e-13 (55 iterations) and 9.2e-13 (81), the
+# GPU by 1.1e-12 and 1.3e-12, so its bound is 5e-12.  (The same experiment on
+# the other cases, including the per-level schedule, ECMG_cg and Algorithm 3,
+# separates by at most 3e-15, and their bound is 1e-12.)
 CASES = {
     "smooth-dirichlet": lambda: (workloads.smooth_dirichlet_cube(levels=4), 0, 1e-12),
     "variable-beta-robin": lambda: (workloads.variable_beta_robin_cube(levels=4), 0, 1e-12),
@@ -197,6 +200,8 @@ def test_per_level_tolerance_schedule(orc, ecmg, driver):
         infos = s.solve_levels(sched)
         u = [s.get(l, ecmg.VEC_U) for l in range(p.levels)]
     assert [i["iters"] for i in infos[2:]] == [r.iters for r in ref[2:]]
+    d = [_rel(u[l], ref[l].u) for l in range(2, p.levels)]
+    print("schedule: iterate differences per level", d)
     for l in range(2, p.levels):
         assert infos[l]["rre"] <= sched[l]
-        assert _rel(u[l], ref[l].u) <= 1e-10, (l, _rel(u[l], ref[l].u))
+    assert max(d) <= 1e-12, d

@@ -35,8 +35,9 @@ def test_ecmg_cg_paper_counts_and_oracle(orc, ecmg, persistent, eps, paper):
         u = [s.get(l, ecmg.VEC_U) for l in range(p.levels)]
         minv = s.get(p.levels - 1, ecmg.VEC_DINV)
     assert got[2:] == paper == [r.iters for r in ref[2:]], (got, paper)
-    for l in range(p.levels):
-        assert _rel(u[l], ref[l].u) <= 1e-10, (l, _rel(u[l], ref[l].u))
+    d = [_rel(u[l], ref[l].u) for l in range(p.levels)]
+    print("ECMG_cg eps %g: iterate differences per level %s" % (eps, d))
+    assert max(d) <= 1e-12, d
     # M^-1 of plain CG: 1 on free nodes, 0 on Dirichlet nodes
     assert set(np.unique(minv).tolist()) <= {0.0, 1.0}
 
@@ -55,8 +56,9 @@ def test_algorithm3_fixed_schedule(orc, ecmg, method):
         infos = s.solve_fixed(sched)
         u = [s.get(l, ecmg.VEC_U) for l in range(p.levels)]
     assert [i["iters"] for i in infos[2:]] == sched[2:]
-    for l in range(p.levels):
-        assert _rel(u[l], ref[l].u) <= 1e-11, (l, _rel(u[l], ref[l].u))
+    d = [_rel(u[l], ref[l].u) for l in range(p.levels)]
+    print("Algorithm 3 (%s): iterate differences per level %s" % (method, d))
+    assert max(d) <= 1e-12, d
 
 
 def test_unknown_method_is_rejected(ecmg):
