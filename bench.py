@@ -67,7 +67,7 @@ def algorithmic_bytes(kind, n, e, n1, n0, iters=0):
     if kind == 1:
         return 8 * 4 * n                # read r, q, 1/D; write r
     if kind == 2:
-        return 8 * (5 * n + e)          # read x, F, 1/D, beta; write r, p_0 = D^-1 r
+        return 8 * (4 * n + e)          # read x, F, beta; write r, p_0 = D^-1 r (D from beta: 40 B/node)
     if kind == 3:
         return 8 * (n + n1 + n0)        # write x; read u_{l-1}, u_{l-2} (the W copy is off when timed)
     if kind == 4:
@@ -179,6 +179,102 @@ def host_cpu():
             "usable_cpus": usable}
 
 
+def _finest_orders(E, s, problem, levels):
+    """Max-norm errors of U and U~ on the given levels and the observed orders."""
+    err = {}
+    for l in levels:
+        ue = exact_on_device(problem, problem.n_at(l))
+        err["U_max_L%d" % l], _ = s.norms(l, E.VEC_U, minus=ue)
+        s.extrapolate(l, out=False)
+        err["Ut_max_L%d" % l], _ = s.norms(l, E.VEC_UTILDE, minus=ue)
+        del ue
+    a, b = levels[-2], levels[-1]
+    return err, math.log2(err["Ut_max_L%d" % a] / err["Ut_max_L%d" % b])
+
+
+def _timed_solves(torch, fn, reps=2):
+    fn()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    out = None
+    for _ in range(reps):
+        out = fn()
+    torch.cuda.synchronize()
+    return out, (time.perf_counter() - t1) / reps
+
+
+def fourth_order_search(E, torch, s, problem, desc, nodes):
+    """Uniform eps from 1e-9 down to 1e-15 until U~ on the finest grid is fourth
+    order (log2 of the max-error ratio to the next coarser grid >= 3.8) or stops
+    changing (converged: the discretisation limits it); then the same finest
+    tolerance as per-level schedules (each coarser grid 4x and 16x looser)."""
+    L = problem.levels - 1
+    s.set_timing(0)                      # no kernel events in these timings
+    out = {"workload": desc, "uniform": []}
+    prev = None
+    for e4 in (1e-9, 1e-10, 1e-11, 1e-12, 1e-13, 1e-14, 1e-15):
+        inf4, dt4 = _timed_solves(torch, lambda: s.solve(e4, extrapolate=True))
+        err4, order = _finest_orders(E, s, problem, [L - 1, L])
+        row = {"eps": e4, "ms_per_step": 1e3 * dt4, "value": nodes / dt4, "Ut_order_max": order,
+               "iters": [i["iters"] for i in inf4], **err4}
+        out["uniform"].append(row)
+        print("bench: eps %g: %.2f ms/step, Ut order %.2f" % (e4, 1e3 * dt4, order), file=sys.stderr, flush=True)
+        ut = err4["Ut_max_L%d" % L]
+        if order >= 3.8:
+            out["reached"] = row
+            break
+        if prev is not None and abs(ut / prev - 1.0) < 1e-3:
+            out["converged"] = row          # U~ no longer moves with eps
+            break
+        prev = ut
+    last = out.get("reached") or out.get("converged") or out["uniform"][-1]
+    for ratio in (4.0, 16.0):
+        sched = E.tolerance_schedule(problem.levels, last["eps"], ratio)
+
+        def run():
+            r = s.solve_levels(sched)
+            s.extrapolate(L, out=False)
+            return r
+        infs, dts = _timed_solves(torch, run)
+        errs, order = _finest_orders(E, s, problem, [L - 1, L])
+        out["schedule%d" % ratio] = {"rel_tol": sched, "ms_per_step": 1e3 * dts, "value": nodes / dts,
+                                     "Ut_order_max": order, "iters": [i["iters"] for i in infs], **errs}
+        print("bench: schedule (finest eps %g, ratio %g): %.2f ms/step, Ut order %.2f" %
+              (last["eps"], ratio, 1e3 * dts, order), file=sys.stderr, flush=True)
+    torch.cuda.empty_cache()
+    return out
+
+
+def fourth_order_problem1(E, torch):
+    """The paper's Problem 1 (beta = 1, three Neumann faces) on its seven grids
+    8^3 .. 512^3 (Section 5): the loosest eps at which U~ is fourth order on the
+    512^3 grid, with unknowns/s at that eps (solve + EXP_true, device fields)."""
+    import workloads
+    p = workloads.paper_problem1(levels=7, eps=1e-10)
+    L = p.levels - 1
+    nodes = p.nodes_at(L)
+    out = {"workload": "Problem 1 of Section 5: -Laplace u = f, u = sin(pi x/2) sin(pi y/2) sin(pi z/2), "
+                       "Dirichlet on x=0, y=0, z=0, Neumann elsewhere; 8^3 -> 512^3 elements (7 levels)",
+           "uniform": []}
+    with E.Solver(keep_w=False) as s:
+        s.setup(p, device_fields=True)
+        s.solve(1e-10, extrapolate=True)
+        s.autotune(iters=0)
+        for e4 in (1e-10, 1e-11, 1e-12, 1e-13, 1e-14):
+            inf4, dt4 = _timed_solves(torch, lambda: s.solve(e4, extrapolate=True))
+            err4, order = _finest_orders(E, s, p, [L - 1, L])
+            row = {"eps": e4, "ms_per_step": 1e3 * dt4, "value": nodes / dt4, "Ut_order_max": order,
+                   "iters": [i["iters"] for i in inf4], **err4}
+            out["uniform"].append(row)
+            print("bench: problem 1 eps %g: %.2f ms/step, Ut order %.2f" % (e4, 1e3 * dt4, order),
+                  file=sys.stderr, flush=True)
+            if order >= 3.8:
+                out["reached"] = row
+                break
+    torch.cuda.empty_cache()
+    return out
+
+
 def precision_comparison(E, torch, name="high-contrast-513x257x257", steps=3):
     """FP64 and mixed precision on the same GPU and workload: ms per step
     (solve + finest EXP_true) and max-norm errors of U and U~ vs the exact
@@ -244,7 +340,11 @@ def method_comparison(E, torch, problem, desc, steps=3):
 
 def batched(E, torch, n_boxes=512, steps=3):
     """512 independent three-level solves (uneven boxes) through the batched
-    API: one step = ecmg_solve_batch + ecmg_extrapolate_batch over all boxes."""
+    API: one step = ecmg_solve_batch + ecmg_extrapolate_batch over all boxes,
+    replayed from the HIP graph the first solve captures; the same steps launch
+    by launch (a leading context with options.batch_graph = 0) for the per-level
+    device times."""
+    import tempfile
     import workloads
     probs = workloads.batched_mix(n_boxes, seed=0)
     t0 = time.perf_counter()
@@ -253,21 +353,31 @@ def batched(E, torch, n_boxes=512, steps=3):
     setup_s = time.perf_counter() - t0
     nodes = sum(p.nodes_at(p.levels - 1) for p in probs)
     eps = probs[0].eps
+    cache = os.path.join(tempfile.mkdtemp(prefix="ecmg_batch_"), "tune.json")
     t0 = time.perf_counter()
-    tuned = E.autotune_batch(solvers, eps)            # untimed: every box takes the fastest setting
+    tuned = E.autotune_batch(solvers, eps, cache=cache)   # untimed: every box takes the fastest setting
     tune_s = time.perf_counter() - t0
     print("bench: batched autotune %.2f s: %d nodes per workgroup, segments of %d (%.1f -> %.1f ms)" % (
         tune_s, tuned["nodes_per_workgroup"], tuned["seg"], tuned["us_default"] / 1e3, tuned["us_best"] / 1e3),
         file=sys.stderr, flush=True)
-    E.solve_batch(solvers, eps)
-    E.extrapolate_batch(solvers)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        infos = E.solve_batch(solvers, eps)
-        E.extrapolate_batch(solvers)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / steps
+
+    def timed(lst):
+        E.solve_batch(lst, eps)                          # captures the graph (or not) and warms up
+        E.extrapolate_batch(lst)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        inf = None
+        for _ in range(steps):
+            inf = E.solve_batch(lst, eps)
+            E.extrapolate_batch(lst)
+        torch.cuda.synchronize()
+        return inf, (time.perf_counter() - t1) / steps
+
+    infos, dt = timed(solvers)
+    lead = E.Solver(keep_w=False, dsolve_dense_max=0, batch_graph=False, autotune=1, tune_cache=cache)
+    lead.setup(probs[0], device_fields=True)
+    infos_e, dt_e = timed([lead] + solvers[1:])
+    lead.close()
     # the same boxes one by one through ecmg_solve (a sample of 64) for context
     t0 = time.perf_counter()
     for sv in solvers[:64]:
@@ -279,7 +389,9 @@ def batched(E, torch, n_boxes=512, steps=3):
         sv.close()
     return {"boxes": n_boxes, "finest_nodes_total": nodes, "setup_s": setup_s, "ms_per_step": 1e3 * dt,
             "boxes_per_s": n_boxes / dt, "unknowns_per_s": nodes / dt,
-            "level_ms": [infos[0][l]["ms"] for l in range(3)],
+            "graph": "replayed HIP graph of the whole batched cascade (captured by the first solve)",
+            "ms_per_step_launch_by_launch": 1e3 * dt_e,
+            "level_ms": [infos_e[0][l]["ms"] for l in range(3)],
             "finest_iters_mean": sum(it) / len(it), "finest_iters_max": max(it),
             "sequential_ms_estimate": 1e3 * seq, "speedup_vs_sequential": seq / dt, "autotune": tuned}
 
@@ -507,58 +619,19 @@ def main():
         torch.cuda.empty_cache()
 
     # if eps loses fourth order on the finest grid (the stop test is relative to
-    # ||f_h||, reading of Section 5), also report the smallest tighter eps that
-    # keeps it, with its throughput
+    # ||f_h||, reading of Section 5), search tighter tolerances: the first that
+    # keeps it, or the point where U~ stops changing (the algebraic error is
+    # gone and the discretisation sets the order)
     fourth = None
     if not args.no_errors and errors.get("Ut_order_max", 0.0) < 3.8 and not args.no_fourth_order:
-        for e4 in (1e-9, 1e-10, 1e-11, 1e-12, 1e-13):
-            s.solve(e4, extrapolate=True)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            for _ in range(2):
-                inf4 = s.solve(e4, extrapolate=True)
-            torch.cuda.synchronize()
-            dt4 = (time.perf_counter() - t1) / 2
-            err4 = {}
-            for l in (L - 1, L):
-                ue = exact_on_device(problem, problem.n_at(l))
-                err4["U_max_L%d" % l], _ = s.norms(l, E.VEC_U, minus=ue)
-                s.extrapolate(l, out=False)
-                err4["Ut_max_L%d" % l], _ = s.norms(l, E.VEC_UTILDE, minus=ue)
-                del ue
-            order = math.log2(err4["Ut_max_L%d" % (L - 1)] / err4["Ut_max_L%d" % L])
-            fourth = {"eps": e4, "ms_per_step": 1e3 * dt4, "value": nodes / dt4, "Ut_order_max": order,
-                      "iters": [i["iters"] for i in inf4], **err4}
-            print("bench: eps %g: %.2f ms/step, Ut order %.2f" % (e4, 1e3 * dt4, order), file=sys.stderr, flush=True)
-            if order >= 3.8:
-                break
-        # the same finest tolerance as a per-level schedule, each coarser grid
-        # 16 times looser (ecmg_solve_levels): the coarse levels get cheap
-        sched = E.tolerance_schedule(problem.levels, fourth["eps"], 16.0)
-        s.solve_levels(sched)
-        s.extrapolate(L, out=False)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for _ in range(2):
-            infs = s.solve_levels(sched)
-            s.extrapolate(L, out=False)
-        torch.cuda.synchronize()
-        dts = (time.perf_counter() - t1) / 2
-        errs = {}
-        for l in (L - 1, L):
-            ue = exact_on_device(problem, problem.n_at(l))
-            s.extrapolate(l, out=False)
-            errs["Ut_max_L%d" % l], _ = s.norms(l, E.VEC_UTILDE, minus=ue)
-            del ue
-        fourth["schedule16"] = {"rel_tol": sched, "ms_per_step": 1e3 * dts,
-                                "Ut_order_max": math.log2(errs["Ut_max_L%d" % (L - 1)] / errs["Ut_max_L%d" % L]),
-                                "iters": [i["iters"] for i in infs], **errs}
-        print("bench: schedule (finest eps %g, ratio 16): %.2f ms/step, Ut order %.2f" %
-              (fourth["eps"], 1e3 * dts, fourth["schedule16"]["Ut_order_max"]), file=sys.stderr, flush=True)
-        torch.cuda.empty_cache()
-
+        fourth = fourth_order_search(E, torch, s, problem, desc, nodes)
     s.close()
     torch.cuda.empty_cache()
+    if not args.no_errors and not args.no_fourth_order:
+        p1 = fourth_order_problem1(E, torch)
+        if fourth is None:
+            fourth = {}
+        fourth["problem1"] = p1
     prec_cmp = None
     if not args.no_precision_comparison:
         prec_cmp = precision_comparison(E, torch)

@@ -174,6 +174,12 @@ typedef struct {
                                   free nodes from the final iterate (one more stencil
                                   pass per level) and report it as info.rre_true; 0
                                   (default): rre_true = -1                              */
+    int32_t batch_graph;       /* ecmg_solve_batch (options of ctxs[0]): 1 (default) =
+                                  capture the batched cascade's launch sequence into a
+                                  HIP graph on the first solve of a set of boxes and
+                                  tolerance and replay it on later ones (launch by
+                                  launch if the runtime cannot capture it); 0 = launch
+                                  by launch.  Same results either way                  */
     /* Device allocator hook (NULL = hipMalloc / hipFree).  alloc returns `bytes` of
      * device memory usable on hip_stream (the library's stream; hipStream_t as
      * void*), or NULL on failure (ECMG_ENOMEM); free releases a pointer alloc
@@ -277,6 +283,10 @@ int ecmg_extrapolate(ecmg_ctx *ctx, int32_t level, double *host_out);
  * its own problem, all on one device, none repeated).  Level by level over all
  * contexts: DSOLVE / EXP_finite per box, then the JCG of every box on that
  * level in one launch, one workgroup per box, boxes with more nodes first.
+ * The whole sequence is enqueued at once and the call waits once; with
+ * options.batch_graph (of ctxs[0]) it is captured into a HIP graph on the first
+ * call for a set of contexts and rel_tol and replayed by later calls (a new
+ * setup, tuning or tolerance captures again).
  * Per box the arithmetic is that of ecmg_solve with the persistent kernel on a
  * single workgroup, so a box's result does not depend on the other boxes of
  * the batch (it equals a batch of that box alone bit for bit).  Work runs on

@@ -64,6 +64,7 @@ class Options(ctypes.Structure):
                 ("persistent_nodes", ctypes.c_int64), ("dsolve_dense_max", ctypes.c_int64),
                 ("autotune", ctypes.c_int32), ("tune_cache", ctypes.c_char_p), ("method", ctypes.c_int32),
                 ("speculate", ctypes.c_int32), ("fold_blocks", ctypes.c_int32), ("true_residual", ctypes.c_int32),
+                ("batch_graph", ctypes.c_int32),
                 ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_user", ctypes.c_void_p)]
 
 
@@ -106,6 +107,7 @@ _lib = None
 # torch's allocator are still up); __del__ makes no library call once the
 # interpreter is finalizing.
 _live = weakref.WeakSet()
+_finalizing = sys.is_finalizing       # kept: module globals may be gone when __del__ runs at exit
 
 
 def _close_live():
@@ -341,7 +343,7 @@ class Solver:
                  chunk: int = 0, timing: bool = False, stream=None, persistent_nodes: int = -1,
                  dsolve_dense_max: Optional[int] = None, autotune: int = 0, tune_cache: Optional[str] = None,
                  method: int = JCG, speculate: bool = True, fold_blocks: int = -1, true_residual: bool = False,
-                 torch_allocator: bool = False):
+                 batch_graph: bool = True, torch_allocator: bool = False):
         self.L = load_library()
         o = Options()
         self.L.ecmg_default_options(ctypes.byref(o))
@@ -357,6 +359,7 @@ class Solver:
         o.speculate = int(speculate)
         o.fold_blocks = int(fold_blocks)
         o.true_residual = int(true_residual)
+        o.batch_graph = int(batch_graph)
         self._hooks = None
         if torch_allocator:
             self._hooks = _torch_allocator_hooks()
@@ -381,7 +384,7 @@ class Solver:
             self.h = None
 
     def __del__(self):
-        if sys.is_finalizing():
+        if _finalizing is None or _finalizing():
             return
         try:
             self.close()
@@ -651,7 +654,7 @@ class Server:
             self.h = ctypes.c_void_p()
 
     def __del__(self):
-        if sys.is_finalizing():
+        if _finalizing is None or _finalizing():
             return
         try:
             self.close()

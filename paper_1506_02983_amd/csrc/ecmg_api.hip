@@ -6,6 +6,7 @@
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <deque>
@@ -25,6 +26,13 @@ using namespace ecmg;
 namespace {
 thread_local std::string g_thread_error;
 }
+
+struct BatchPlan;
+struct ecmg_ctx;
+static void batch_plan_free(ecmg_ctx *c0, BatchPlan *P);
+// generations are unique over all contexts of the process, so a plan never
+// matches a context that replaced a destroyed one at the same address
+static std::atomic<uint64_t> g_generation{0};
 
 // ---------------------------------------------------------------------------
 // Allocation-free reductions (ecmg_norms_noalloc): the block partials, the
@@ -60,6 +68,8 @@ struct ecmg_ctx {
     unsigned *bt_bar = nullptr;               // 32 barrier words per box (error flag, counter)
     ExpTask *bt_exp = nullptr;                // batched EXP_finite / EXP_true boxes
     int bt_cap = 0;
+    struct BatchPlan *bplan = nullptr;        // batched solves led by this context: plan and graph
+    uint64_t gen = 0;                         // changes whenever the hierarchy or its JCG configuration does
     std::string err;
     std::vector<Level> lv;
     int nlev = 0;
@@ -881,6 +891,7 @@ void ecmg_default_options(ecmg_options *o) {
     o->speculate = 1;
     o->fold_blocks = -1;
     o->true_residual = 0;
+    o->batch_graph = 1;
     o->alloc = nullptr;
     o->free = nullptr;
     o->alloc_user = nullptr;
@@ -985,6 +996,8 @@ void ecmg_destroy(ecmg_ctx *c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     free_levels(c);
     if (c->blas) (void)rocblas_destroy_handle(c->blas);
+    batch_plan_free(c, c->bplan);
+    c->bplan = nullptr;
     dfree(c, c->sc);
     dfree(c, c->sc32);
     dfree(c, c->bt_tasks);
@@ -1084,6 +1097,7 @@ int ecmg_setup(ecmg_ctx *c, const ecmg_problem *p) {
     HIPCHK(c, hipStreamSynchronize(c->stream));
     free_levels(c);
     c->nlev = p->levels;
+    c->gen = ++g_generation;
     for (int f = 0; f < 6; ++f) c->face_type[f] = p->face_type[f];
     c->lv.resize(p->levels);
     if (c->lv_cap < p->levels) {
@@ -1379,6 +1393,7 @@ static TuneEntry builtin_choice(const ecmg_ctx *c, int l) {
 // level l runs configuration e from now on (path -1: the built-in rules)
 static int apply_choice(ecmg_ctx *c, int l, int path, int kz, int seg, int nwg) {
     Level &L = c->lv[l];
+    c->gen = ++g_generation;
     if (path == 1 && !persist_possible(c, L.g)) path = -1;
     L.tune_path = path;
     L.tune_kz = path == 0 ? std::max(1, std::min(kz, L.g.nz + 1)) : 0;
@@ -1599,42 +1614,84 @@ static int on_stream(ecmg_ctx *c, hipStream_t s, Fn fn) {
     return rc;
 }
 
-extern "C" {
-
-int ecmg_solve_batch(ecmg_ctx *const *ctxs, int32_t n, double rel_tol, ecmg_level_info *infos) {
-    if (!ctxs || n < 1) return fail(nullptr, ECMG_EINVAL, "ctxs is NULL or n = %d < 1", n);
-    ecmg_ctx *c0 = ctxs[0];
-    if (!c0) return fail(nullptr, ECMG_EINVAL, "ctxs[0] is NULL");
-    if (!(rel_tol >= 0.0)) return fail(c0, ECMG_EINVAL, "rel_tol = %g must be >= 0", rel_tol);
-    int maxlev = 0;
-    std::vector<int64_t> info_off(n);
-    int64_t off = 0;
-    for (int i = 0; i < n; ++i) {
-        ecmg_ctx *c = ctxs[i];
-        if (!c) return fail(c0, ECMG_EINVAL, "ctxs[%d] is NULL", i);
-        if (!c->ready) return fail(c0, ECMG_ESTATE, "ctxs[%d]: ecmg_solve_batch before ecmg_setup", i);
-        if (c->device != c0->device) return fail(c0, ECMG_EINVAL, "ctxs[%d] is on another device", i);
-        for (int j = 0; j < i; ++j)
-            if (ctxs[j] == c) return fail(c0, ECMG_EINVAL, "ctxs[%d] repeats ctxs[%d]", i, j);
-        maxlev = std::max(maxlev, c->nlev);
-        info_off[i] = off;
-        off += c->nlev;
-    }
-    hipStream_t s = c0->stream;
-    for (int i = 1; i < n; ++i)
-        if (ctxs[i]->stream != s) HIPCHK(c0, hipStreamSynchronize(ctxs[i]->stream));
-    CHK(batch_reserve(c0, n));
-    std::vector<PersistentTask> tasks;
-    std::vector<int> owner;
-    tasks.reserve(n);
-    owner.reserve(n);
-    int worst = ECMG_OK;
-    for (int l = 0; l < maxlev; ++l) {
-        HIPCHK(c0, hipEventRecord(c0->ev0, s));
-        tasks.clear();
-        owner.clear();
-        std::vector<ExpTask> ex;
+// ---------------------------------------------------------------------------
+// Batched cascade plan: every level's EXP_finite tasks and queue-kernel tasks
+// (boxes sorted by node count, each with its own scalar slot and barrier
+// words) uploaded once per set of boxes and tolerance, so that a solve is one
+// fixed sequence of launches -- per level: a kernel that clears the barrier
+// words and queue counter, the batched EXP_finite, the cooperative queue
+// kernel -- and one copy of all scalars back to pinned memory.  That sequence
+// is captured once into a HIP graph and replayed by later solves.
+// ---------------------------------------------------------------------------
+struct BatchPlan {
+    struct Lv {
+        int nt = 0, items = 0, nwg = 0, nex = 0;
         int64_t nb0 = 0;
+        size_t task_off = 0, sc_off = 0, bar_off = 0, exp_off = 0;
+        std::vector<int> owner;                  // sorted task k -> input box
+    };
+    std::vector<ecmg_ctx *> ctxs;
+    std::vector<uint64_t> key;                   // per box: generation, batch_npw, batch_seg
+    double rel_tol = 0.0;
+    int n = 0, maxlev = 0;
+    std::vector<Lv> lv;
+    PersistentTask *d_tasks = nullptr;
+    JcgScalars *d_sc = nullptr;
+    JcgScalars *h_sc = nullptr;                  // pinned
+    unsigned *d_bar = nullptr;                   // per level: 32 words per box, then 16 words of queue counter
+    ExpTask *d_exp = nullptr;
+    size_t nsc = 0, nbar = 0;
+    std::vector<hipEvent_t> ev;                  // level boundaries
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int graph_state = 0;                         // 0 not tried, 1 captured, -1 not capturable (launch by launch)
+    bool timed = true;                           // per-level events in the launch sequence
+
+    bool matches(ecmg_ctx *const *cs, int m, double tol) const {
+        if (m != n || tol != rel_tol) return false;
+        for (int i = 0; i < m; ++i) {
+            if (cs[i] != ctxs[i] || key[3 * i] != cs[i]->gen || key[3 * i + 1] != (uint64_t)cs[i]->batch_npw ||
+                key[3 * i + 2] != (uint64_t)cs[i]->batch_seg)
+                return false;
+        }
+        return true;
+    }
+};
+
+static void batch_plan_free(ecmg_ctx *c0, BatchPlan *P) {
+    if (!P) return;
+    if (c0->stream) (void)hipStreamSynchronize(c0->stream);
+    if (P->exec) (void)hipGraphExecDestroy(P->exec);
+    if (P->graph) (void)hipGraphDestroy(P->graph);
+    dfree(c0, P->d_tasks);
+    dfree(c0, P->d_sc);
+    dfree(c0, P->d_bar);
+    dfree(c0, P->d_exp);
+    if (P->h_sc) (void)hipHostFree(P->h_sc);
+    for (auto e : P->ev) (void)hipEventDestroy(e);
+    delete P;
+}
+
+static int batch_plan_build(ecmg_ctx *c0, ecmg_ctx *const *ctxs, int n, double rel_tol, BatchPlan **out) {
+    BatchPlan *P = new BatchPlan();
+    P->n = n;
+    P->rel_tol = rel_tol;
+    P->ctxs.assign(ctxs, ctxs + n);
+    for (int i = 0; i < n; ++i) {
+        P->key.push_back(ctxs[i]->gen);
+        P->key.push_back((uint64_t)ctxs[i]->batch_npw);
+        P->key.push_back((uint64_t)ctxs[i]->batch_seg);
+        P->maxlev = std::max(P->maxlev, ctxs[i]->nlev);
+    }
+    P->lv.resize(P->maxlev);
+    std::vector<PersistentTask> all_tasks;
+    std::vector<ExpTask> all_exp;
+    size_t nbar = 0;
+    for (int l = 0; l < P->maxlev; ++l) {
+        BatchPlan::Lv &V = P->lv[l];
+        std::vector<PersistentTask> tasks;
+        std::vector<int> owner;
+        V.exp_off = all_exp.size();
         for (int i = 0; i < n; ++i) {
             ecmg_ctx *c = ctxs[i];
             if (l >= c->nlev) continue;
@@ -1649,9 +1706,10 @@ int ecmg_solve_batch(ecmg_ctx *const *ctxs, int32_t n, double rel_tol, ecmg_leve
                 e.W = L.W;
                 e.variant = c->opt.interp;
                 exp_task_blocks(e, 0);
-                e.b0[0] = nb0;
-                nb0 += e.nb[0];
-                ex.push_back(e);
+                e.b0[0] = V.nb0;
+                V.nb0 += e.nb[0];
+                all_exp.push_back(e);
+                ++V.nex;
             }
             const double tol = (l < 2 ? c->opt.dsolve_tol : rel_tol) * L.nf;
             const int max_iter = l < 2 ? 100000 : c->opt.max_iter;
@@ -1659,48 +1717,172 @@ int ecmg_solve_batch(ecmg_ctx *const *ctxs, int32_t n, double rel_tol, ecmg_leve
             tasks.back().zero_x = l < 2;
             owner.push_back(i);
         }
-        if (!ex.empty()) {
-            if (nb0 >= ((int64_t)1 << 31))
-                return fail(c0, ECMG_EINVAL, "batched EXP_finite grid too large");
-            HIPCHK(c0, hipMemcpyAsync(c0->bt_exp, ex.data(), sizeof(ExpTask) * ex.size(), hipMemcpyHostToDevice, s));
-            launch_exp_finite_batch(c0->bt_exp, (int)ex.size(), nb0, s);
-            HIPCHK(c0, hipGetLastError());
+        if (V.nb0 >= ((int64_t)1 << 31)) {
+            delete P;
+            return fail(c0, ECMG_EINVAL, "batched EXP_finite grid too large");
         }
         // longest first: order by node count, then by input position
         std::vector<int> order(tasks.size());
         for (size_t k = 0; k < order.size(); ++k) order[k] = (int)k;
         std::stable_sort(order.begin(), order.end(),
                          [&](int a, int b) { return tasks[a].g.nreal > tasks[b].g.nreal; });
-        std::vector<PersistentTask> sorted(tasks.size());
-        std::vector<int> sorted_owner(tasks.size());
-        if (c0->queue_blocks < 1) return fail(c0, ECMG_EDEVICE, "the queue kernel cannot be resident");
-        int items = 0;
+        V.nt = (int)tasks.size();
+        V.task_off = all_tasks.size();
+        V.sc_off = V.task_off;
+        V.bar_off = nbar;
         for (size_t k = 0; k < order.size(); ++k) {
-            sorted[k] = tasks[order[k]];
-            sorted[k].sc = c0->bt_sc + k;
-            sorted[k].err = (int *)(c0->bt_bar + 32 * k);
-            sorted[k].bar = c0->bt_bar + 32 * k + 16;
-            sorted[k].nwg = std::min(sorted[k].nwg, c0->queue_blocks);
-            sorted[k].wg0 = items;
-            items += sorted[k].nwg;
-            sorted_owner[k] = owner[order[k]];
+            PersistentTask t = tasks[order[k]];
+            t.nwg = std::min(t.nwg, c0->queue_blocks);
+            t.wg0 = V.items;
+            V.items += t.nwg;
+            all_tasks.push_back(t);
+            V.owner.push_back(owner[order[k]]);
         }
-        const int nt = (int)sorted.size();
-        // every box's barrier words start at zero
-        HIPCHK(c0, hipMemsetAsync(c0->bt_bar, 0, 32 * sizeof(unsigned) * (size_t)nt, s));
-        HIPCHK(c0, hipMemcpyAsync(c0->bt_tasks, sorted.data(), sizeof(PersistentTask) * nt, hipMemcpyHostToDevice, s));
-        HIPCHK(c0, hipMemsetAsync(c0->bt_next, 0, sizeof(unsigned), s));
-        const int nwg = std::max(1, std::min(items, c0->queue_blocks));
-        HIPCHK(c0, launch_jcg_queue(c0->bt_tasks, nt, items, nwg, c0->bt_next, s));
-        HIPCHK(c0, hipMemcpyAsync(c0->bt_sc_host, c0->bt_sc, sizeof(JcgScalars) * nt, hipMemcpyDeviceToHost, s));
-        HIPCHK(c0, hipEventRecord(c0->ev1, s));
-        HIPCHK(c0, hipStreamSynchronize(s));
-        float ms = 0.f;
-        HIPCHK(c0, hipEventElapsedTime(&ms, c0->ev0, c0->ev1));
-        for (int k = 0; k < nt; ++k) {
-            ecmg_ctx *c = ctxs[sorted_owner[k]];
+        V.nwg = std::max(1, std::min(V.items, c0->queue_blocks));
+        nbar += 32 * (size_t)V.nt + 16;
+    }
+    P->nsc = all_tasks.size();
+    P->nbar = nbar;
+    int rc = ECMG_OK;
+    if ((rc = dalloc(c0, (void **)&P->d_tasks, sizeof(PersistentTask) * std::max<size_t>(1, P->nsc))) != ECMG_OK ||
+        (rc = dalloc(c0, (void **)&P->d_sc, sizeof(JcgScalars) * std::max<size_t>(1, P->nsc))) != ECMG_OK ||
+        (rc = dalloc(c0, (void **)&P->d_bar, sizeof(unsigned) * std::max<size_t>(1, nbar))) != ECMG_OK ||
+        (rc = dalloc(c0, (void **)&P->d_exp, sizeof(ExpTask) * std::max<size_t>(1, all_exp.size()))) != ECMG_OK) {
+        batch_plan_free(c0, P);
+        return rc;
+    }
+    if (hipHostMalloc((void **)&P->h_sc, sizeof(JcgScalars) * std::max<size_t>(1, P->nsc), hipHostMallocDefault) !=
+        hipSuccess) {
+        P->h_sc = nullptr;
+        batch_plan_free(c0, P);
+        return fail(c0, ECMG_ENOMEM, "pinned host allocation of %zu scalars failed", P->nsc);
+    }
+    // every task's scalar slot and barrier words inside the plan's arrays
+    for (int l = 0; l < P->maxlev; ++l) {
+        const BatchPlan::Lv &V = P->lv[l];
+        for (int k = 0; k < V.nt; ++k) {
+            PersistentTask &t = all_tasks[V.task_off + k];
+            t.sc = P->d_sc + V.sc_off + k;
+            t.err = (int *)(P->d_bar + V.bar_off + 32 * (size_t)k);
+            t.bar = P->d_bar + V.bar_off + 32 * (size_t)k + 16;
+        }
+    }
+    for (int l = 0; l <= P->maxlev; ++l) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) {
+            batch_plan_free(c0, P);
+            return fail(c0, ECMG_EDEVICE, "hipEventCreate failed");
+        }
+        P->ev.push_back(e);
+    }
+    hipStream_t s = c0->stream;
+    if (hipMemcpyAsync(P->d_tasks, all_tasks.data(), sizeof(PersistentTask) * P->nsc, hipMemcpyHostToDevice, s) !=
+            hipSuccess ||
+        (!all_exp.empty() &&
+         hipMemcpyAsync(P->d_exp, all_exp.data(), sizeof(ExpTask) * all_exp.size(), hipMemcpyHostToDevice, s) !=
+             hipSuccess) ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        batch_plan_free(c0, P);
+        return fail(c0, ECMG_EDEVICE, "uploading the batched plan failed");
+    }
+    *out = P;
+    return ECMG_OK;
+}
+
+// The plan's launch sequence on stream s (eager: the cooperative launch
+// interface; under capture: the launch-attribute one, recorded as a kernel node
+// with the cooperative attribute).
+static int batch_enqueue(ecmg_ctx *c0, BatchPlan *P, hipStream_t s, bool eager) {
+    for (int l = 0; l < P->maxlev; ++l) {
+        const BatchPlan::Lv &V = P->lv[l];
+        unsigned *bar = P->d_bar + V.bar_off;
+        unsigned *next = bar + 32 * (size_t)V.nt;
+        launch_zero_u32(bar, 32 * (int64_t)V.nt + 16, s);       // barrier words and queue counter
+        if (V.nex > 0) launch_exp_finite_batch(P->d_exp + V.exp_off, V.nex, V.nb0, s);
+        HIPCHK(c0, hipGetLastError());
+        const PersistentTask *tk = P->d_tasks + V.task_off;
+        HIPCHK(c0, eager ? launch_jcg_queue(tk, V.nt, V.items, V.nwg, next, s)
+                         : launch_jcg_queue_attr(tk, V.nt, V.items, V.nwg, next, s));
+        if (P->timed) HIPCHK(c0, hipEventRecord(P->ev[l + 1], s));
+    }
+    HIPCHK(c0, hipMemcpyAsync(P->h_sc, P->d_sc, sizeof(JcgScalars) * P->nsc, hipMemcpyDeviceToHost, s));
+    return ECMG_OK;
+}
+
+// Capture the launch sequence into a graph (without the per-level events:
+// events recorded inside a captured graph cannot be timed); graph_state -1 if
+// it cannot be captured.
+static int batch_plan_capture(ecmg_ctx *c0, BatchPlan *P, hipStream_t s) {
+    P->timed = false;
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+        const int rc = batch_enqueue(c0, P, s, false);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(s, &g);
+        if (rc == ECMG_OK && e == hipSuccess && g) {
+            hipGraphExec_t x = nullptr;
+            if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) == hipSuccess && x) {
+                P->graph = g;
+                P->exec = x;
+                P->graph_state = 1;
+            }
+        }
+        if (P->graph_state != 1 && g) (void)hipGraphDestroy(g);
+    }
+    (void)hipGetLastError();                 // a refused capture leaves no error behind
+    if (P->graph_state != 1) {
+        P->graph_state = -1;
+        P->timed = true;
+        c0->err.clear();
+    }
+    return ECMG_OK;
+}
+
+extern "C" {
+
+int ecmg_solve_batch(ecmg_ctx *const *ctxs, int32_t n, double rel_tol, ecmg_level_info *infos) {
+    if (!ctxs || n < 1) return fail(nullptr, ECMG_EINVAL, "ctxs is NULL or n = %d < 1", n);
+    ecmg_ctx *c0 = ctxs[0];
+    if (!c0) return fail(nullptr, ECMG_EINVAL, "ctxs[0] is NULL");
+    if (!(rel_tol >= 0.0)) return fail(c0, ECMG_EINVAL, "rel_tol = %g must be >= 0", rel_tol);
+    std::vector<int64_t> info_off(n);
+    int64_t off = 0;
+    for (int i = 0; i < n; ++i) {
+        ecmg_ctx *c = ctxs[i];
+        if (!c) return fail(c0, ECMG_EINVAL, "ctxs[%d] is NULL", i);
+        if (!c->ready) return fail(c0, ECMG_ESTATE, "ctxs[%d]: ecmg_solve_batch before ecmg_setup", i);
+        if (c->device != c0->device) return fail(c0, ECMG_EINVAL, "ctxs[%d] is on another device", i);
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == c) return fail(c0, ECMG_EINVAL, "ctxs[%d] repeats ctxs[%d]", i, j);
+        info_off[i] = off;
+        off += c->nlev;
+    }
+    if (c0->queue_blocks < 1) return fail(c0, ECMG_EDEVICE, "the queue kernel cannot be resident");
+    hipStream_t s = c0->stream;
+    for (int i = 1; i < n; ++i)
+        if (ctxs[i]->stream != s) HIPCHK(c0, hipStreamSynchronize(ctxs[i]->stream));
+    BatchPlan *P = c0->bplan;
+    if (!P || !P->matches(ctxs, n, rel_tol)) {
+        if (P) batch_plan_free(c0, P);
+        c0->bplan = nullptr;
+        CHK(batch_plan_build(c0, ctxs, n, rel_tol, &P));
+        c0->bplan = P;
+    }
+    // the whole cascade is enqueued at once (one host wait): from the plan's
+    // graph when it could be captured, else launch by launch
+    HIPCHK(c0, hipEventRecord(P->ev[0], s));
+    if (c0->opt.batch_graph && P->graph_state == 0) CHK(batch_plan_capture(c0, P, s));
+    if (P->graph_state == 1) HIPCHK(c0, hipGraphLaunch(P->exec, s));
+    else CHK(batch_enqueue(c0, P, s, true));
+    HIPCHK(c0, hipStreamSynchronize(s));
+    int worst = ECMG_OK;
+    for (int l = 0; l < P->maxlev; ++l) {
+        const BatchPlan::Lv &V = P->lv[l];
+        float ms = -1.f;                     // a replayed graph: per-level device time not observable
+        if (P->timed) HIPCHK(c0, hipEventElapsedTime(&ms, P->ev[l], P->ev[l + 1]));
+        for (int k = 0; k < V.nt; ++k) {
+            ecmg_ctx *c = ctxs[V.owner[k]];
             const Level &L = c->lv[l];
-            const JcgScalars &sc = c0->bt_sc_host[k];
+            const JcgScalars &sc = P->h_sc[V.sc_off + k];
             ecmg_level_info li{};
             li.rre_true = -1.0;              // not computed by the batched form
             li.level = l;
@@ -1714,7 +1896,7 @@ int ecmg_solve_batch(ecmg_ctx *const *ctxs, int32_t n, double rel_tol, ecmg_leve
             int st = (sc.done == DONE_BREAKDOWN) ? ECMG_EBREAKDOWN : (sc.done == DONE_MAXITER) ? ECMG_ENOTCONV : ECMG_OK;
             if (l < 2 && st == ECMG_ENOTCONV) st = ECMG_OK;   // DSOLVE: the iterate at the cap is kept
             li.status = st;
-            if (infos) infos[info_off[sorted_owner[k]] + l] = li;
+            if (infos) infos[info_off[V.owner[k]] + l] = li;
             if (st != ECMG_OK && worst == ECMG_OK) worst = st;
         }
     }

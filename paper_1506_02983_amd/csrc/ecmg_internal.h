@@ -333,6 +333,11 @@ hipError_t launch_jcg_persistent(const PersistentTask *d_tasks, int ntasks, int 
 int queue_max_blocks();
 hipError_t launch_jcg_queue(const PersistentTask *d_tasks, int ntasks, int nitems, int nwg, unsigned *next,
                             hipStream_t s);
+// the same cooperative launch through hipLaunchKernelExC (recordable by stream capture)
+hipError_t launch_jcg_queue_attr(const PersistentTask *d_tasks, int ntasks, int nitems, int nwg, unsigned *next,
+                                 hipStream_t s);
+// zero n 32-bit words with a kernel (a fill kernel, not a memset node, when captured)
+void launch_zero_u32(unsigned *p, int64_t n, hipStream_t s);
 
 // Block count of the 1-D reduction kernels (fixed so reductions are deterministic).
 int reduce_blocks(int64_t n);

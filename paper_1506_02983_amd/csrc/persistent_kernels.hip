@@ -547,4 +547,22 @@ hipError_t launch_jcg_queue(const PersistentTask *d_tasks, int ntasks, int nitem
     return hipLaunchCooperativeKernel((const void *)k_jcg_queue, dim3(nwg), dim3(NTP), args, 0, s);
 }
 
+// The same launch through the launch-attribute interface (cooperative
+// attribute), which stream capture records into a graph kernel node.
+hipError_t launch_jcg_queue_attr(const PersistentTask *d_tasks, int ntasks, int nitems, int nwg, unsigned *next,
+                                 hipStream_t s) {
+    void *args[] = {(void *)&d_tasks, (void *)&ntasks, (void *)&nitems, (void *)&next};
+    hipLaunchAttribute attr[1];
+    attr[0].id = hipLaunchAttributeCooperative;
+    attr[0].val.cooperative = 1;
+    hipLaunchConfig_t cfg{};
+    cfg.gridDim = dim3(nwg);
+    cfg.blockDim = dim3(NTP);
+    cfg.dynamicSmemBytes = 0;
+    cfg.stream = s;
+    cfg.attrs = attr;
+    cfg.numAttrs = 1;
+    return hipLaunchKernelExC(&cfg, (const void *)k_jcg_queue, args);
+}
+
 }  // namespace ecmg

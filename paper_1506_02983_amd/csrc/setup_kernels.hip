@@ -379,6 +379,16 @@ __global__ void __launch_bounds__(256) k_norms(const Geom g, const double *a, co
 // ---- launchers ----------------------------------------------------------------
 static inline unsigned nblk(int64_t n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
 
+__global__ void k_zero_u32(unsigned *p, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0u;
+}
+
+void launch_zero_u32(unsigned *p, int64_t n, hipStream_t s) {
+    const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(nblk(n), 1024));
+    hipLaunchKernelGGL(k_zero_u32, dim3(nb), dim3(256), 0, s, p, n);
+}
+
 void launch_fill(double *p, int64_t n, double v, hipStream_t s) {
     const unsigned nb = (unsigned)std::min<int64_t>(nblk(n), 8192);
     hipLaunchKernelGGL(k_fill, dim3(nb > 0 ? nb : 1), dim3(256), 0, s, p, n, v);

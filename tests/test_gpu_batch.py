@@ -118,3 +118,37 @@ def test_batch_autotune_and_cache(ecmg, boxes, tmp_path):
         s.close()
     for i in range(len(boxes)):
         assert np.array_equal(out2[i], out[i]), i
+
+
+def test_batch_graph_replay_matches_launch_by_launch(ecmg, boxes):
+    """The batched cascade captured into a HIP graph (first call) and replayed
+    (later calls, also after a change of tolerance, which captures again, and
+    after a new setup of one box) gives bit for bit the results of the launch
+    sequence enqueued launch by launch."""
+    def run(graph, tols, resetup=False):
+        solvers = [ecmg.Solver(dsolve_dense_max=0, batch_graph=graph).setup(p) for p in boxes]
+        outs = []
+        for k, eps in enumerate(tols):
+            if resetup and k == len(tols) - 1:
+                solvers[3].setup(boxes[3])
+            infos = ecmg.solve_batch(solvers, eps)
+            ecmg.extrapolate_batch(solvers)
+            outs.append(([[x["iters"] for x in inf] for inf in infos],
+                         [s.get(p.levels - 1, ecmg.VEC_UTILDE) for s, p in zip(solvers, boxes)],
+                         [[x["ms"] for x in inf] for inf in infos]))
+        for s in solvers:
+            s.close()
+        return outs
+    tols = [1e-8, 1e-8, 1e-9, 1e-9]
+    g = run(True, tols, resetup=True)
+    e = run(False, tols, resetup=True)
+    for k in range(len(tols)):
+        assert g[k][0] == e[k][0], k
+        for a, b in zip(g[k][1], e[k][1]):
+            assert np.array_equal(a, b), k
+        # per-level device times: measured launch by launch; a replayed graph
+        # reports -1 (its per-level time is not observable)
+        assert all(ms >= 0.0 for box in e[k][2] for ms in box), e[k][2]
+        assert all(ms == -1.0 for box in g[k][2] for ms in box), g[k][2]      # the graph ran
+    # a replayed solve repeats the first one exactly
+    assert g[0][0] == g[1][0] and all(np.array_equal(a, b) for a, b in zip(g[0][1], g[1][1]))
