@@ -15,8 +15,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libecmg.so")
-SOURCES = ["ecmg_api.hip", "jcg_kernels.hip", "extrap_kernels.hip", "setup_kernels.hip", "persistent_kernels.hip",
-           "tune_cache.cpp"]
+SOURCES = ["ecmg_api.hip", "jcg_kernels.hip", "col_kernels.hip", "extrap_kernels.hip", "setup_kernels.hip",
+           "persistent_kernels.hip", "tune_cache.cpp"]
 
 
 def hipcc():

@@ -95,6 +95,8 @@ struct ecmg_ctx {
     int KZ = 32;
     int kz_target = 1024;                      // tiled stencil: blocks aimed for per launch
     int fold_max = FOLD_MAX_BLOCKS;            // JCG scalar steps folded into the passes up to this many blocks
+    int col_enable = 1;                        // column kernels for init / iteration 0 on unfolded levels
+    int col_kz = 16;                           // planes per z-chunk of a column wave
     uint32_t timing_mask = 0;                  // kernel classes timed with HIP events (bit k = class k)
     // persistent JCG for grids of at most persist_max nodes (larger ones: the
     // tiled passes with folded scalar steps -- two launches per iteration,
@@ -417,6 +419,7 @@ static int rec_flush(ecmg_ctx *c, int iter_limit) {
 
 static int apply_tune_cache(ecmg_ctx *c);
 static int dense_prepare(ecmg_ctx *c, int l);
+static int ensure_partials(ecmg_ctx *c, int64_t n);
 
 // ---------------------------------------------------------------------------
 // JCG on one level (the JCG loop of Algorithm 4)
@@ -446,7 +449,8 @@ static StencilArgs<double> stencil_args(ecmg_ctx *c, Level &L) {
 // caller checks `done` once the stream has run it).
 template <typename T>
 static int jcg_chunks(ecmg_ctx *c, int l, const StencilArgs<T> &a, const PassBArgs<T> &b, JcgScalars *sc,
-                      int fixed, int kind_a, int kind_b, int hint, bool nowait = false) {
+                      int fixed, int kind_a, int kind_b, int hint, bool nowait = false, const ColArgs *col = nullptr,
+                      int col_waves_n = 0) {
     int done_iters = 0;
     int next = 2;
     int chunk = c->opt.chunk > 0 ? c->opt.chunk : (hint > 0 ? hint : 2);
@@ -467,8 +471,14 @@ static int jcg_chunks(ecmg_ctx *c, int l, const StencilArgs<T> &a, const PassBAr
             // iteration 0 from the p_0 init stored, when it did (its own timing class)
             const bool a0 = a.p_init && done_iters + t == 0;
             CHK(rec_begin(c, l, a0 ? 10 : kind_a, done_iters + t, &slot));
-            launch_stencil<T>(a0 ? MODE_PASSA0 : MODE_PASSA, a, c->stream);
-            CHK(rec_end(c, slot));
+            if (a0 && col) {
+                launch_col(MODE_PASSA0, *col, c->stream);
+                CHK(rec_end(c, slot));
+                launch_stencil_finish(MODE_PASSA, sc, col->partials, col_waves_n, c->stream);
+            } else {
+                launch_stencil<T>(a0 ? MODE_PASSA0 : MODE_PASSA, a, c->stream);
+                CHK(rec_end(c, slot));
+            }
             CHK(rec_begin(c, l, kind_b, done_iters + t, &slot));
             launch_passB<T>(b, c->stream);
             CHK(rec_end(c, slot));
@@ -640,6 +650,29 @@ static int jcg_result(ecmg_ctx *c, int l, const JcgScalars &s, int max_iter, boo
     return ECMG_OK;
 }
 
+// The column kernels take grids whose arrays index with 32-bit offsets.
+static bool col_usable(const ecmg_ctx *c, const Geom &g) {
+    return c->col_enable && g.nnodes < ((int64_t)1 << 31) && (int64_t)g.nx * g.ny * g.nz < ((int64_t)1 << 31);
+}
+
+// Column-kernel arguments of level L (input, output and partials set by the
+// caller); returns the partial pairs a launch writes (waves, then the blocks
+// of the Robin-face kernel).
+static int col_args(ecmg_ctx *c, Level &L, ColArgs *ca) {
+    ColArgs &x = *ca;
+    x.g = L.g;
+    x.KZ = std::max(1, std::min(c->col_kz, L.g.nz + 1));
+    const int waves = col_waves(L.g, x.KZ, &x.ntx, &x.nty, &x.nkz);
+    x.beta = L.beta;
+    for (int f = 0; f < 6; ++f) x.alpha[f] = L.alpha[f];
+    x.F = L.F;
+    x.dinv = L.dinv;
+    x.plain_cg = c->opt.method == ECMG_CG;
+    x.sc = c->sc;
+    ColFaces fl;
+    return waves + col_faces(L.g, &fl);
+}
+
 // Tiled JCG of level l, enqueued: init, the iterations (status reads only
 // between chunks), the last x update (the kernel checks whether one is
 // pending), which also copies the final scalars into the level's pinned slot;
@@ -679,15 +712,41 @@ static int enqueue_jcg(ecmg_ctx *c, int l, double tol_abs, int max_iter, int fix
         b.pq_partials = c->partials;
         b.nb_a = (int)nb_a;
     }
+    // the large (unfolded) levels: JCG init and iteration 0 of pass A by the
+    // column kernels, the later iterations by the tiled ones
+    ColArgs ca{};
+    int cw = 0;
+    const bool col = !fold && col_usable(c, L.g);
+    if (col) {
+        cw = col_args(c, L, &ca);
+        CHK(ensure_partials(c, 2 * (int64_t)cw));
+        ca.partials = c->partials;
+        a.partials = c->partials;
+        b.partials = c->partials;
+    }
     size_t slot = 0;
     CHK(rec_begin(c, l, 2, 0, &slot));
-    launch_stencil<double>(MODE_INIT, a, c->stream);
-    CHK(rec_end(c, slot));
+    if (col) {
+        ca.v = L.x;
+        ca.out = c->r;
+        ca.p_out = c->p1;
+        ca.p_init = 1;
+        launch_col(MODE_INIT, ca, c->stream);
+        CHK(rec_end(c, slot));
+        launch_stencil_finish(MODE_INIT, c->sc, c->partials, cw, c->stream);
+        ca.v = c->p1;                             // iteration 0: q = A p_0
+        ca.out = c->q;
+        ca.p_out = nullptr;
+        ca.p_init = 0;
+    } else {
+        launch_stencil<double>(MODE_INIT, a, c->stream);
+        CHK(rec_end(c, slot));
+    }
     HIPCHK(c, hipGetLastError());
 
     const int hint = fixed < 0 ? L.last_iters : 0;
     if (fold) CHK(jcg_chunks_folded(c, l, a, b, fixed, hint, (int)nb_a, (int)nb_b, L.spec_live));
-    else CHK(jcg_chunks(c, l, a, b, c->sc, fixed, 0, 1, hint, L.spec_live));
+    else CHK(jcg_chunks(c, l, a, b, c->sc, fixed, 0, 1, hint, L.spec_live, col ? &ca : nullptr, cw));
     launch_final_x(L.g, L.x, c->p0, c->p1, c->sc, c->sc_lv_dev + l, c->stream);
     HIPCHK(c, hipGetLastError());
     return ECMG_OK;
@@ -945,6 +1004,8 @@ int ecmg_create(const ecmg_options *opt, ecmg_ctx **out) {
     if (const char *kz = std::getenv("ECMG_KZ")) c->KZ = std::max(1, std::atoi(kz));
     if (const char *kt = std::getenv("ECMG_KZ_TARGET")) c->kz_target = std::max(1, std::atoi(kt));
     if (o.fold_blocks >= 0) c->fold_max = std::min<int>(o.fold_blocks, FOLD_MAX_BLOCKS);
+    if (const char *v = std::getenv("ECMG_COL")) c->col_enable = std::atoi(v) != 0;
+    if (const char *v = std::getenv("ECMG_COL_KZ")) c->col_kz = std::max(1, std::atoi(v));
     if (const char *v = std::getenv("ECMG_PERSIST_SEG")) c->persist_seglen = std::max(1, std::atoi(v));
     if (const char *v = std::getenv("ECMG_PERSIST_NWG")) c->persist_nwg = std::max(1, std::atoi(v));
     if (const char *v = std::getenv("ECMG_BATCH_NPW")) c->batch_npw = std::max(64, std::atoi(v));
@@ -1145,6 +1206,9 @@ int ecmg_setup(ecmg_ctx *c, const ecmg_problem *p) {
             int a, b, d;
             pn = std::max<int64_t>(pn, 2 * (int64_t)stencil_blocks(g, stencil_kz(g, c->KZ, c->kz_target), &a, &b, &d));
             pn = std::max<int64_t>(pn, 2 * passB_blocks(g.nnodes));
+            ColFaces fl;
+            pn = std::max<int64_t>(pn, 2 * ((int64_t)col_waves(g, std::max(1, std::min(c->col_kz, g.nz + 1)), &a, &b, &d) +
+                                            col_faces(g, &fl)));
         }
         c->partials_n = pn;
         CHK(dalloc_n(c, &c->partials, pn));

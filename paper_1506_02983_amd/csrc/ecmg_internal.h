@@ -166,6 +166,39 @@ struct PassBArgs {
 // itself instead of a one-block finishing kernel.
 constexpr int FOLD_MAX_BLOCKS = 4096;
 
+// Column stencil kernels (col_kernels.hip): one wave per (62-node x-segment,
+// COL_R rows, z-chunk of KZ planes), planes in registers, x neighbours by DPP.
+// Used for JCG init and iteration 0 of pass A on levels whose passes run
+// with one-block finishing kernels (the large grids).
+constexpr int COL_R = 2;
+struct ColArgs {
+    Geom g;
+    int ntx, nty, nkz, KZ;            // waves: x-segments, row groups, z-chunks; planes per chunk
+    const double *beta;
+    const double *alpha[6];
+    const double *v;                  // input: APPLY v, INIT x, PASSA0 p_0
+    double *out;                      // APPLY / PASSA0: q; INIT: r
+    const double *F, *dinv;           // INIT epilogue inputs
+    double *p_out;                    // INIT with p_init: p_0 = D^-1 r
+    int p_init;
+    int plain_cg;                     // INIT: M^-1 = 1 (ECMG_CG) instead of 1/diag from beta
+    JcgScalars *sc;                   // PASSA0: returns when done is set
+    double *partials;                 // 2 per wave, then 2 per block of the Robin-face kernel
+};
+// the Robin faces of a grid and the first thread of each in the face kernel
+struct ColFaces {
+    int nf;
+    int face[6];
+    int64_t start[7];
+};
+// waves of a column launch for z-chunks of KZ planes
+int col_waves(const Geom &g, int KZ, int *ntx, int *nty, int *nkz);
+// blocks of the Robin-face kernel
+int col_faces(const Geom &g, ColFaces *fl);
+// column kernel plus the Robin-face kernel; returns the partial pairs written
+// (waves, then face blocks), which the finishing kernel sums in that order
+int launch_col(int mode, const ColArgs &a, hipStream_t s);
+
 // One independent JCG solve inside the persistent kernel: a grid, its arrays,
 // its stop control, and the contiguous range of workgroups that works on it.
 struct PersistentTask {
@@ -258,6 +291,9 @@ int stencil_kz(const Geom &g, int kz_max, int target_blocks);
 
 template <typename T>
 void launch_stencil(int mode, const StencilArgs<T> &a, hipStream_t s);
+// the one-block finishing kernel of a stencil pass over nb partial pairs
+// (MODE_INIT: rho, ||r||^2 and the first stop test; MODE_PASSA: p.q and alpha)
+void launch_stencil_finish(int mode, JcgScalars *sc, const double *partials, int nb, hipStream_t s);
 template <typename T>
 void launch_passB(const PassBArgs<T> &a, hipStream_t s);
 // blocks of pass B for n nodes (its partial slots: twice as many)

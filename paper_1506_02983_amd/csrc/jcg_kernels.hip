@@ -812,6 +812,11 @@ void launch_stencil(int mode, const StencilArgs<T> &a, hipStream_t s) {
     }
 }
 
+void launch_stencil_finish(int mode, JcgScalars *sc, const double *partials, int nb, hipStream_t s) {
+    if (mode == MODE_INIT) hipLaunchKernelGGL(k_stencil_finish<MODE_INIT>, dim3(1), dim3(NTF), 0, s, sc, partials, nb);
+    else hipLaunchKernelGGL(k_stencil_finish<MODE_PASSA>, dim3(1), dim3(NTF), 0, s, sc, partials, nb);
+}
+
 int64_t passB_blocks(int64_t n) { return std::max<int64_t>(1, (n / 2 + UB * NTB - 1) / (UB * NTB)); }
 
 template <typename T>
