@@ -34,10 +34,14 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 KIND_NAMES = {0: "jcg_pass_a", 1: "jcg_pass_b", 2: "jcg_init", 3: "exp_finite", 4: "exp_true",
               5: "jcg_pass_a_fp32", 6: "jcg_pass_b_fp32", 7: "jcg_persistent", 10: "jcg_pass_a0"}
 # kernel names as rocprofv3 reports them (stencil: <type, mode, rows of
-# threads, rows per thread, waves per SIMD>)
-KERNEL_SYMBOL = {0: "k_stencil<double, 2, 8, 1, 4>", 1: "k_passB<double>", 2: "k_stencil<double, 1, 8, 1, 4>",
+# threads, rows per thread, waves per SIMD>; column kernels: <mode, node rows
+# per wave, waves per SIMD>, with the Robin-face kernel of the same mode).
+# JCG init and iteration 0 of pass A run the tiled kernel on the levels whose
+# scalars are folded into the passes, the column kernels on the larger ones.
+KERNEL_SYMBOL = {0: "k_stencil<double, 2, 8, 1, 4>", 1: "k_passB<double>",
+                 2: "k_stencil<double, 1, 8, 1, 4> | k_col<1, 2, 2> + k_col_face<1>",
                  3: "k_exp_finite", 4: "k_exp_true", 5: "k_stencil<float, 2, 8, 1, 4>", 6: "k_passB<float>",
-                 7: "k_jcg_persistent", 10: "k_stencil<double, 3, 4, 2, 2>"}
+                 7: "k_jcg_persistent", 10: "k_stencil<double, 3, 4, 2, 2> | k_col<3, 2, 3> + k_col_face<3>"}
 
 
 def workload(name):
@@ -89,7 +93,8 @@ def algorithmic_bytes(kind, n, e, n1, n0, iters=0):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("jcg_kernels.hip", "persistent_kernels.hip", "extrap_kernels.hip", "ecmg_internal.h"):
+    for f in ("jcg_kernels.hip", "col_kernels.hip", "persistent_kernels.hip", "extrap_kernels.hip",
+              "ecmg_internal.h"):
         with open(os.path.join(ROOT, "paper_1506_02983_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -396,7 +401,7 @@ def batched(E, torch, n_boxes=512, steps=3):
             "sequential_ms_estimate": 1e3 * seq, "speedup_vs_sequential": seq / dt, "autotune": tuned}
 
 
-def serving(E, n_measured=200, n_warmup=20, rate=50.0, budget=200 * 10 ** 9):
+def serving(E, n_measured=2000, n_warmup=100, rate=50.0, budget=200 * 10 ** 9):
     """Replay a seeded Poisson stream of requests (finest 32^3..256^3,
     random coefficients and faces) against the serving loop; latency is from
     each request's scheduled arrival to its U~ on the host."""
@@ -426,6 +431,9 @@ def serving(E, n_measured=200, n_warmup=20, rate=50.0, budget=200 * 10 ** 9):
                         sizes.append(stream[k].problem.nodes_at(stream[k].problem.levels - 1))
                         if t_first is None:
                             t_first = stream[k].arrival_s
+                        if len(lat) % 500 == 0:
+                            print("bench: serving %d of %d measured requests done (%.1f s)"
+                                  % (len(lat), n_measured, tnow), file=sys.stderr, flush=True)
                     srv.release(t)
                     del live[t]
         t_end = time.perf_counter() - t0
@@ -467,8 +475,8 @@ def main():
     ap.add_argument("--no-precision-comparison", action="store_true",
                     help="skip the FP64 vs mixed comparison on the high-contrast workload")
     ap.add_argument("--batch-boxes", type=int, default=512, help="boxes of the batched workload (0 = skip)")
-    ap.add_argument("--serve-requests", type=int, default=200,
-                    help="measured requests of the serving replay (0 = skip), after 20 warm-up requests")
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="measured requests of the serving replay (0 = skip), after 100 warm-up requests")
     ap.add_argument("--no-fourth-order", action="store_true",
                     help="skip the search for the eps that keeps the extrapolation fourth order")
     args = ap.parse_args()

@@ -63,7 +63,8 @@ extern "C" {
                           max(inner_tol, eps ||f_h|| / (2 ||r||)), x += ||r|| d in
                           FP64, repeated.  Small levels run in FP64: those the
                           persistent kernel solves and, on the tiled kernels,
-                          those of at most persistent_nodes nodes (300,000 when
+                          those of at most persistent_nodes nodes (8,388,608,
+                          the levels whose passes fold their scalar steps, when
                           persistent_nodes is -1).                                  */
 
 /* ---- EXP_finite interpolation (Section 4.3) --------------------------- */
@@ -303,14 +304,17 @@ int ecmg_extrapolate_batch(ecmg_ctx *const *ctxs, int32_t n);
 /* ---- serving: continuous batching of independent requests ----------------
  * A server solves requests (each a problem of eq. bvp run through Algorithm 4
  * and EXP_true on its finest level) as they arrive.  The caller drives it:
- * ecmg_server_step admits queued requests first come first served while the
- * device bytes of their hierarchies (ecmg_plan_bytes) fit the budget, sets
- * them up (callbacks run on the calling thread), then advances every admitted
- * request by one level: the levels small enough for the persistent kernel of
- * all requests share one launch (one workgroup range per request), larger
- * levels run the tiled kernels; finished requests get EXP_true, their U~ copied
- * to the caller's buffer and their device memory freed.  A request's result
- * does not depend on which other requests share its steps.  FP64 only. */
+ * A set-up thread of the server admits queued requests first come first
+ * served while the device bytes of their hierarchies (ecmg_plan_bytes) fit the
+ * budget and discretises them (Section 2) on a stream of its own, so the field
+ * callbacks of a request run on that thread, concurrently with the caller's
+ * thread.  ecmg_server_step moves the requests whose set-up has completed into
+ * the active set, then advances every active request by one level: the levels
+ * small enough for the persistent kernel of all requests share one launch (one
+ * workgroup range per request), larger levels run the tiled kernels; finished
+ * requests get EXP_true, their U~ copied to the caller's buffer and their
+ * device memory freed.  A request's result does not depend on which other
+ * requests share its steps or on when its set-up ran.  FP64 only. */
 typedef struct ecmg_server ecmg_server;
 
 /* opt: NULL = defaults (precision must be ECMG_FP64); the server's work runs
@@ -318,18 +322,22 @@ typedef struct ecmg_server ecmg_server;
 int ecmg_server_create(const ecmg_options *opt, size_t hbm_budget_bytes, ecmg_server **out);
 
 /* Queue a request.  problem and everything it points to (callbacks and their
- * user data) must stay valid until the request is admitted; host_out (NULL or
+ * user data) must stay valid until the request's state is 1 or later (set up);
+ * the callbacks are called on the server's set-up thread.  host_out (NULL or
  * a dense array of the finest level's nodes, caller-owned) receives U~ and must
  * stay valid until the request is done.  ECMG_ENOMEM if its hierarchy alone
  * exceeds the budget. */
 int ecmg_server_submit(ecmg_server *srv, const ecmg_problem *problem, double rel_tol, double *host_out,
                        uint64_t *ticket);
 
-/* Admit what fits, run one level of every admitted request, finish completed
- * ones.  n_done: NULL or the number completed in this step. */
+/* Take in the requests set up since the last step, run one level of every
+ * active request, finish completed ones.  With no active request but some
+ * queued or in set-up, first waits up to 2 ms for one to become ready.
+ * n_done: NULL or the number completed in this step. */
 int ecmg_server_step(ecmg_server *srv, int32_t *n_done);
 
-/* state: 0 queued, 1 running, 2 done, < 0 the error status of a failed request;
+/* state: 0 queued or in set-up, 1 set up (running), 2 done, < 0 the error
+ * status of a failed request;
  * info (NULL or `levels` entries) is filled once done. */
 int ecmg_server_poll(ecmg_server *srv, uint64_t ticket, int32_t *state, ecmg_level_info *info);
 

@@ -587,8 +587,10 @@ class Server:
     """ecmg_server: continuous batching of independent requests (FP64).
 
     submit() queues a problem (its field structures are kept alive here until
-    the request is done); step() admits, advances every admitted request by one
-    level and finishes completed ones; result() returns U~ on the finest grid."""
+    the request is released; the server's set-up thread calls them); step()
+    takes in the requests set up since the last step, advances every active
+    request by one level and finishes completed ones; result() returns U~ on
+    the finest grid."""
 
     def __init__(self, hbm_budget_bytes: int, device_fields: bool = True, **opts):
         self.L = load_library()
@@ -635,7 +637,13 @@ class Server:
         return self._req[ticket][2]
 
     def release(self, ticket: int):
-        """Drop the kept problem structures and result of a finished request."""
+        """Drop the kept problem structures and result of a finished request
+        (the set-up thread calls the field callbacks until it is set up, and
+        U~ is written to the result buffer when it is done)."""
+        if ticket in self._req:
+            st, _ = self.poll(ticket)
+            if st in (0, 1):
+                raise EcmgError(ESTATE, "request %d is still %s" % (ticket, "queued" if st == 0 else "running"))
         self._req.pop(ticket, None)
 
     def stats(self) -> dict:

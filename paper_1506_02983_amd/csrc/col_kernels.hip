@@ -10,10 +10,13 @@
 // and the elements of the layers k-1, k in registers, in rings of four planes
 // and layers so that the loads of plane k+2 (and layer k+1, and the epilogue
 // inputs of plane k+1) are in flight while plane k is computed.  The x
-// neighbours come from the adjacent lanes through DPP wavefront shifts (a VALU
-// operand modifier, no LDS traffic): the exchange through LDS, not HBM, bounded
-// the tiled kernels.  Every load is branch-free (clamped index, the value
-// zeroed afterwards), so the compiler waits for exactly the loads a step uses.
+// neighbours come from the adjacent lanes through DPP wavefront shifts (no LDS
+// traffic: the exchange through LDS, not HBM, bounded the tiled kernels); each
+// lane computes its column's parts of its own node and of both neighbours'
+// nodes, so a node needs two shifted partial sums and the shifted betas of one
+// element column rather than nine shifted plane values.  Every load is
+// branch-free (clamped index; betas outside the grid zeroed afterwards), so the
+// compiler waits for exactly the loads a step uses.
 //
 // Reductions: each wave sums its lanes' partials with shuffles and stores one
 // pair; the one-block finishing kernels of jcg_kernels.hip (fixed order) take
@@ -24,17 +27,24 @@ namespace ecmg {
 
 namespace {
 
-// lane i receives lane i-1 (DPP wave_shr:1); lane 0 receives 0
+// lane i receives lane i-1 (DPP wave_shr:1); lane 0 receives 0 (bound_ctrl)
 __device__ __forceinline__ double from_left(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)__double2loint(v), 0x138, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)__double2hiint(v), 0x138, 0xf, 0xf, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)__double2loint(v), 0x138, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)__double2hiint(v), 0x138, 0xf, 0xf, true);
     return __hiloint2double(hi, lo);
 }
-// lane i receives lane i+1 (DPP wave_shl:1); lane 63 receives 0
+// lane i receives lane i+1 (DPP wave_shl:1); lane 63 receives 0 (bound_ctrl)
 __device__ __forceinline__ double from_right(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)__double2loint(v), 0x130, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)__double2hiint(v), 0x130, 0xf, 0xf, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)__double2loint(v), 0x130, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)__double2hiint(v), 0x130, 0xf, 0xf, true);
     return __hiloint2double(hi, lo);
+}
+
+// block b of nb (dispatched round-robin over the 8 XCDs) -> the logical block
+// that gives every XCD a contiguous range
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    const int per = nb >> 3;
+    return b < (per << 3) ? (b & 7) * per + (b >> 3) : b;
 }
 
 __device__ __forceinline__ bool dir_node(const Geom &g, int i, int j, int k) {
@@ -75,37 +85,86 @@ __device__ __forceinline__ double robin_col(const Geom &g, int face, const doubl
     return s;
 }
 
-// register rings of one wave lane
-template <int R>
+// register rings of one wave lane, NR = D + 3 slots for a prefetch distance
+// of D z-steps (planes k-1, k, k+1 in use and D in flight; the layer and
+// epilogue rings use NR slots too, so that one unrolled pass of NR steps
+// returns every ring to its first slot)
+template <int R, int NR>
 struct ColRegs {
-    double P[4][R + 2];    // input planes: rows j0-1 .. j0+R
-    double B[4][R + 1];    // element layers: element rows j0-1 .. j0+R-1, element x = i
-    double E[2][1][R];     // epilogue input of the output rows (INIT: F)
+    double P[NR][R + 2];   // input planes: rows j0-1 .. j0+R
+    double B[NR][R + 1];   // element layers: element rows j0-1 .. j0+R-1, element x = i
+    double E[NR][R];       // epilogue input of the output rows (INIT: F)
 };
 
+// The 27-point row of node (i, j, k) split by neighbour column: the centre
+// column i (elements of x-index i-1 and i), column i-1 (elements i-1 only)
+// and column i+1 (elements i only).  Lane i holds column i and the elements
+// of x-index i, so it computes the centre part of its own node and, from its
+// column, the part of node i+1 (weights from its own elements: `tr`) and of
+// node i-1 (weights from the elements of x-index i-1, the left lane's: `tl`);
+// node i adds the neighbours' parts with one wave shift each.  A neighbour in
+// plane k-1 (k+1) couples through the lower (upper) layer's elements only, one
+// in plane k through both: with sl, su the beta sums of the shared elements
+// below and above, a neighbour row contributes
+//   sl (Cz vm + C v0) + su (Cz vp + C v0),
+// C, Cz the entries for the differing in-plane axes without / with z, each
+// product accumulated by a fused multiply-add.  The two side parts share those
+// plane combinations.
+// L, Rt: the elements of x-index i-1 and i of the lower layer (rows j0-1 ..);
+// LU, RU of the upper layer; r: the output row's index in the wave's rows.
+template <int R>
+__device__ __forceinline__ void col_row(const Geom &g, int r, const double (&L)[R + 1], const double (&Rt)[R + 1],
+                                        const double (&LU)[R + 1], const double (&RU)[R + 1],
+                                        const double (&Pm)[R + 2], const double (&P0)[R + 2],
+                                        const double (&Pp)[R + 2], double &qc, double &tr, double &tl) {
+    qc = 0.0;
+    tr = 0.0;
+    tl = 0.0;
+#pragma unroll
+    for (int oy = -1; oy <= 1; ++oy) {
+        const int t = r + 1 + oy;                 // plane row of the neighbour row
+        const int mo = (oy != 0) << 1;
+        // element rows below (row j-1) / above (row j) the node row
+        const double lL = oy > 0 ? L[r + 1] : oy < 0 ? L[r] : L[r] + L[r + 1];
+        const double lR = oy > 0 ? Rt[r + 1] : oy < 0 ? Rt[r] : Rt[r] + Rt[r + 1];
+        const double uL = oy > 0 ? LU[r + 1] : oy < 0 ? LU[r] : LU[r] + LU[r + 1];
+        const double uR = oy > 0 ? RU[r + 1] : oy < 0 ? RU[r] : RU[r] + RU[r + 1];
+        const double c0 = g.C[mo] * P0[t], s0 = g.C[mo | 1] * P0[t];
+        const double ac = fma(g.C[mo | 4], Pm[t], c0), bc = fma(g.C[mo | 4], Pp[t], c0);
+        const double as = fma(g.C[mo | 5], Pm[t], s0), bs = fma(g.C[mo | 5], Pp[t], s0);
+        qc = fma(lL + lR, ac, qc);
+        qc = fma(uL + uR, bc, qc);
+        tr = fma(lR, as, tr);
+        tr = fma(uR, bs, tr);
+        tl = fma(lL, as, tl);
+        tl = fma(uL, bs, tl);
+    }
+}
+
 // One z-step: output plane k from the planes Pm (k-1), P0 (k), Pp (k+1) and the
-// layers Bl (k-1), Bu (k); first issues the loads of plane k+2 into Pn, layer
-// k+1 into Bn and the epilogue inputs of plane k+1 into En.
-template <int MODE, int R>
-__device__ __forceinline__ void col_step(const ColArgs &a, int i, int j0, int k, int k1, bool out_lane, bool iok,
+// layers Bl (k-1), Bu (k); first issues the loads of plane k+1+D into Pn, layer
+// k+D into Bn and the epilogue inputs of plane k+D into En.  Plane values of
+// columns or rows outside the grid are clamped loads of grid nodes: every
+// element holding such a neighbour lies outside the grid and carries beta = 0,
+// so its weight is 0.
+template <int MODE, int R, int D>
+__device__ __forceinline__ void col_step(const ColArgs &a, int i, int j0, int k, int k1, bool out_lane,
                                          bool ieok, bool dir_i, bool rob_i, double (&Pm)[R + 2], double (&P0)[R + 2],
                                          double (&Pp)[R + 2],
                                          double (&Pn)[R + 2], double (&Bl)[R + 1], double (&Bu)[R + 1],
-                                         double (&Bn)[R + 1], double (&Ec)[1][R], double (&En)[1][R], double &acc0,
+                                         double (&Bn)[R + 1], double (&Ec)[R], double (&En)[R], double &acc0,
                                          double &acc1) {
     const Geom &g = a.g;
     const int sx = g.sx, sxy = g.sx * g.sy, exy = g.nx * g.ny;
     const int ic = min(max(i, 0), g.nx), ie = min(max(i, 0), g.nx - 1);
     const bool dir_k = (k == 0 && g.ft[4] == ECMG_DIRICHLET) || (k == g.nz && g.ft[5] == ECMG_DIRICHLET);
     const bool rob_k = (k == 0 && g.ft[4] == ECMG_ROBIN) || (k == g.nz && g.ft[5] == ECMG_ROBIN);
-    {   // prefetch: plane k+2 (inside the chunk and its upper halo plane), layer k+1, epilogue of plane k+1
-        const int kp = k + 2, kb = k + 1, ke = k + 1;
+    {   // prefetch: plane k+1+D, layer k+D, epilogue of plane k+D
+        const int kp = k + 1 + D, kb = k + D, ke = k + D;
 #pragma unroll
         for (int r = 0; r < R + 2; ++r) {
             const int jj = j0 - 1 + r;
-            const bool ok = iok && jj >= 0 && jj <= g.ny && kp <= g.nz && kp <= k1;
-            const double v = a.v[ic + sx * min(max(jj, 0), g.ny) + sxy * min(kp, g.nz)];
-            Pn[r] = ok ? v : 0.0;
+            Pn[r] = a.v[ic + sx * min(max(jj, 0), g.ny) + sxy * min(kp, g.nz)];
         }
 #pragma unroll
         for (int r = 0; r < R + 1; ++r) {
@@ -116,42 +175,24 @@ __device__ __forceinline__ void col_step(const ColArgs &a, int i, int j0, int k,
         }
         if (MODE == MODE_INIT) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) En[0][r] = __builtin_nontemporal_load(a.F + ic + sx * min(j0 + r, g.ny) +
-                                                                              sxy * min(ke, g.nz));
+            for (int r = 0; r < R; ++r) En[r] = __builtin_nontemporal_load(a.F + ic + sx * min(j0 + r, g.ny) +
+                                                                           sxy * min(ke, g.nz));
         }
     }
+    // elements of x-index i-1 (the left lane's)
+    double BlL[R + 1], BuL[R + 1];
+#pragma unroll
+    for (int r = 0; r < R + 1; ++r) {
+        BlL[r] = from_left(Bl[r]);
+        BuL[r] = from_left(Bu[r]);
+    }
+    double qc[R], tr[R], tl[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) col_row<R>(g, r, BlL, Bl, BuL, Bu, Pm, P0, Pp, qc[r], tr[r], tl[r]);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int j = j0 + r;
-        // beta of the 8 elements around the node: layer below (k-1, Bl) and
-        // above (k, Bu); in-plane [dy][dx] = element (i-1+dx, j-1+dy)
-        const double l01 = Bl[r], l11 = Bl[r + 1], u01 = Bu[r], u11 = Bu[r + 1];
-        const double l00 = from_left(l01), l10 = from_left(l11), u00 = from_left(u01), u10 = from_left(u11);
-        double q = 0.0;
-#pragma unroll
-        for (int oy = -1; oy <= 1; ++oy) {
-            const int rr = r + 1 + oy;
-#pragma unroll
-            for (int ox = -1; ox <= 1; ++ox) {
-                double sl, su;
-                if (oy < 0 && ox < 0) { sl = l00; su = u00; }
-                else if (oy < 0 && ox > 0) { sl = l01; su = u01; }
-                else if (oy > 0 && ox < 0) { sl = l10; su = u10; }
-                else if (oy > 0 && ox > 0) { sl = l11; su = u11; }
-                else if (oy < 0) { sl = l00 + l01; su = u00 + u01; }
-                else if (oy > 0) { sl = l10 + l11; su = u10 + u11; }
-                else if (ox < 0) { sl = l00 + l10; su = u00 + u10; }
-                else if (ox > 0) { sl = l01 + l11; su = u01 + u11; }
-                else { sl = (l00 + l01) + (l10 + l11); su = (u00 + u01) + (u10 + u11); }
-                const int m = (ox != 0) | ((oy != 0) << 1);
-                double vm = Pm[rr], v0 = P0[rr], vp = Pp[rr];
-                if (ox < 0) { vm = from_left(vm); v0 = from_left(v0); vp = from_left(vp); }
-                if (ox > 0) { vm = from_right(vm); v0 = from_right(v0); vp = from_right(vp); }
-                // neighbours in planes k-1 / k+1 share only the layer between;
-                // neighbours in plane k are shared by both layers
-                q += g.C[m | 4] * (sl * vm + su * vp) + g.C[m] * ((sl + su) * v0);
-            }
-        }
+        const double q = qc[r] + from_left(tr[r]) + from_right(tl[r]);
         // nodes on a Robin face (and on no Dirichlet face) are the face kernel's
         const bool dir = dir_i || (j == 0 && g.ft[2] == ECMG_DIRICHLET) || (j == g.ny && g.ft[3] == ECMG_DIRICHLET) ||
                          dir_k;
@@ -161,7 +202,7 @@ __device__ __forceinline__ void col_step(const ColArgs &a, int i, int j0, int k,
         if (MODE == MODE_APPLY) {
             __builtin_nontemporal_store(dir ? 0.0 : q, a.out + id);
         } else if (MODE == MODE_INIT) {
-            const double rv = dir ? 0.0 : Ec[0][r] - q;
+            const double rv = dir ? 0.0 : Ec[r] - q;
             __builtin_nontemporal_store(rv, a.out + id);
             // M^-1 from the beta already in registers: the diagonal C[0] * (sum of
             // the 8 element betas, in the order the setup's 1/D uses), so z is
@@ -170,7 +211,8 @@ __device__ __forceinline__ void col_step(const ColArgs &a, int i, int j0, int k,
             if (a.plain_cg) {
                 z = rv;
             } else {
-                const double s8 = ((((((l00 + l01) + l10) + l11) + u00) + u01) + u10) + u11;
+                const double s8 = ((((((BlL[r] + Bl[r]) + BlL[r + 1]) + Bl[r + 1]) + BuL[r]) + Bu[r]) + BuL[r + 1]) +
+                                  Bu[r + 1];
                 z = (1.0 / (g.C[0] * s8)) * rv;
             }
             if (a.p_init) __builtin_nontemporal_store(z, a.p_out + id);     // p_0 for iteration 0
@@ -184,21 +226,38 @@ __device__ __forceinline__ void col_step(const ColArgs &a, int i, int j0, int k,
     }
 }
 
-// WPE: waves per SIMD the register budget is set for (iteration 0 and apply:
-// 3, with a few bytes of spills, measured faster than 2 without; init keeps 2,
-// where 3 would spill 128 bytes per lane)
-template <int MODE, int R, int WPE>
+// WPE: waves per SIMD the register budget is set for (init 150 VGPRs and
+// iteration 0 122 VGPRs fit 3 and 4 waves); D: prefetch distance in z-steps
+template <int MODE, int R, int WPE, int D>
 __global__ void __launch_bounds__(256, WPE) k_col(const ColArgs a) {
+    constexpr int NR = D + 3;
     const Geom &g = a.g;
     if (MODE == MODE_PASSA0 && a.sc->done) return;      // uniform over the grid
     const int lane = threadIdx.x & 63;
-    // consecutive waves take consecutive x-segments of the same rows (blocks go
-    // round-robin over the XCDs; a contiguous range per XCD was measured slower)
-    const int wid = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int wid = blockIdx.x * 4 + (threadIdx.x >> 6);     // partial slot
     const int total = a.ntx * a.nty * a.nkz;
+    int tx, ty, tz;
+    if (a.order == 0) {
+        // consecutive waves take consecutive x-segments of the same rows
+        tx = wid % a.ntx;
+        const int t2 = wid / a.ntx;
+        ty = t2 % a.nty;
+        tz = t2 / a.nty;
+    } else {
+        // the 4 waves of a block take 4 consecutive row groups of one x-segment,
+        // so the y-halo rows they share are fetched once into the CU's caches;
+        // order 2 also gives each XCD a contiguous range of blocks (blocks are
+        // dispatched round-robin over the XCDs), so the halo rows between
+        // neighbouring blocks are shared through that XCD's L2
+        const int b = a.order == 2 ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
+        const int nty4 = a.nty >> 2;
+        tx = b % a.ntx;
+        const int t2 = b / a.ntx;
+        ty = 4 * (t2 % nty4) + (threadIdx.x >> 6);
+        tz = t2 / nty4;
+    }
     double acc0 = 0.0, acc1 = 0.0;
     if (wid < total) {
-        const int tx = wid % a.ntx, t2 = wid / a.ntx, ty = t2 % a.nty, tz = t2 / a.nty;
         const int i = 62 * tx - 1 + lane;
         const int j0 = ty * R;
         const int k0 = tz * a.KZ, k1 = min(k0 + a.KZ, g.nz + 1);
@@ -206,56 +265,57 @@ __global__ void __launch_bounds__(256, WPE) k_col(const ColArgs a) {
         const bool out_lane = lane >= 1 && lane <= 62 && iok;
         const int sx = g.sx, sxy = g.sx * g.sy, exy = g.nx * g.ny;
         const int ic = min(max(i, 0), g.nx), ie = min(max(i, 0), g.nx - 1);
-        ColRegs<R> S;
-        // prologue: planes k0-1, k0, k0+1, layers k0-1, k0, epilogue of plane k0
+        ColRegs<R, NR> S;
+        // prologue: planes k0-1 .. k0+D, layers k0-1 .. k0+D-1, epilogue of
+        // planes k0 .. k0+D-1
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
+        for (int c = 0; c < D + 2; ++c) {
             const int kk = k0 - 1 + c;
 #pragma unroll
             for (int r = 0; r < R + 2; ++r) {
                 const int jj = j0 - 1 + r;
-                const bool ok = iok && jj >= 0 && jj <= g.ny && kk >= 0 && kk <= g.nz && kk <= k1;
-                const double v = a.v[ic + sx * min(max(jj, 0), g.ny) + sxy * min(max(kk, 0), g.nz)];
-                S.P[c][r] = ok ? v : 0.0;
+                S.P[c][r] = a.v[ic + sx * min(max(jj, 0), g.ny) + sxy * min(max(kk, 0), g.nz)];
             }
         }
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
+        for (int c = 0; c < D + 1; ++c) {
             const int kk = k0 - 1 + c;
 #pragma unroll
             for (int r = 0; r < R + 1; ++r) {
                 const int jj = j0 - 1 + r;
-                const bool ok = ieok && jj >= 0 && jj < g.ny && kk >= 0 && kk < g.nz;
+                const bool ok = ieok && jj >= 0 && jj < g.ny && kk >= 0 && kk < g.nz && kk < k1;
                 const double v = a.beta[ie + g.nx * min(max(jj, 0), g.ny - 1) + exy * min(max(kk, 0), g.nz - 1)];
                 S.B[c][r] = ok ? v : 0.0;
             }
         }
         if (MODE == MODE_INIT) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) S.E[0][0][r] = a.F[ic + sx * min(j0 + r, g.ny) + sxy * k0];
+            for (int c = 0; c < D; ++c)
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    S.E[c][r] = a.F[ic + sx * min(j0 + r, g.ny) + sxy * min(k0 + c, g.nz)];
         }
         const bool dir_i = (i == 0 && g.ft[0] == ECMG_DIRICHLET) || (i == g.nx && g.ft[1] == ECMG_DIRICHLET);
         const bool rob_i = (i == 0 && g.ft[0] == ECMG_ROBIN) || (i == g.nx && g.ft[1] == ECMG_ROBIN);
+        // step s of a pass of NR steps: planes in slots s, s+1, s+2, the load
+        // into s+2+D; layers in s, s+1, the load into s+1+D; epilogue in s,
+        // the load into s+D (all mod NR)
         int k = k0;
-        for (; k + 3 < k1; k += 4) {
-            col_step<MODE, R>(a, i, j0, k, k1, out_lane, iok, ieok, dir_i, rob_i, S.P[0], S.P[1], S.P[2], S.P[3], S.B[0], S.B[1],
-                              S.B[2], S.E[0], S.E[1], acc0, acc1);
-            col_step<MODE, R>(a, i, j0, k + 1, k1, out_lane, iok, ieok, dir_i, rob_i, S.P[1], S.P[2], S.P[3], S.P[0], S.B[1],
-                              S.B[2], S.B[3], S.E[1], S.E[0], acc0, acc1);
-            col_step<MODE, R>(a, i, j0, k + 2, k1, out_lane, iok, ieok, dir_i, rob_i, S.P[2], S.P[3], S.P[0], S.P[1], S.B[2],
-                              S.B[3], S.B[0], S.E[0], S.E[1], acc0, acc1);
-            col_step<MODE, R>(a, i, j0, k + 3, k1, out_lane, iok, ieok, dir_i, rob_i, S.P[3], S.P[0], S.P[1], S.P[2], S.B[3],
-                              S.B[0], S.B[1], S.E[1], S.E[0], acc0, acc1);
+        for (; k + NR - 1 < k1; k += NR) {
+#pragma unroll
+            for (int t = 0; t < NR; ++t)
+                col_step<MODE, R, D>(a, i, j0, k + t, k1, out_lane, ieok, dir_i, rob_i, S.P[t % NR],
+                                     S.P[(t + 1) % NR], S.P[(t + 2) % NR], S.P[(t + 2 + D) % NR], S.B[t % NR],
+                                     S.B[(t + 1) % NR], S.B[(t + 1 + D) % NR], S.E[t % NR], S.E[(t + D) % NR], acc0,
+                                     acc1);
         }
-        if (k < k1)
-            col_step<MODE, R>(a, i, j0, k, k1, out_lane, iok, ieok, dir_i, rob_i, S.P[0], S.P[1], S.P[2], S.P[3], S.B[0], S.B[1],
-                              S.B[2], S.E[0], S.E[1], acc0, acc1);
-        if (k + 1 < k1)
-            col_step<MODE, R>(a, i, j0, k + 1, k1, out_lane, iok, ieok, dir_i, rob_i, S.P[1], S.P[2], S.P[3], S.P[0], S.B[1],
-                              S.B[2], S.B[3], S.E[1], S.E[0], acc0, acc1);
-        if (k + 2 < k1)
-            col_step<MODE, R>(a, i, j0, k + 2, k1, out_lane, iok, ieok, dir_i, rob_i, S.P[2], S.P[3], S.P[0], S.P[1], S.B[2],
-                              S.B[3], S.B[0], S.E[0], S.E[1], acc0, acc1);
+#pragma unroll
+        for (int t = 0; t < NR - 1; ++t)
+            if (k + t < k1)
+                col_step<MODE, R, D>(a, i, j0, k + t, k1, out_lane, ieok, dir_i, rob_i, S.P[t % NR],
+                                     S.P[(t + 1) % NR], S.P[(t + 2) % NR], S.P[(t + 2 + D) % NR], S.B[t % NR],
+                                     S.B[(t + 1) % NR], S.B[(t + 1 + D) % NR], S.E[t % NR], S.E[(t + D) % NR], acc0,
+                                     acc1);
     }
     if (MODE == MODE_APPLY || wid >= total) return;
     // wave partials in lane order (fixed), one pair per wave
@@ -376,9 +436,14 @@ __global__ void __launch_bounds__(256) k_col_face(const ColArgs a, const ColFace
 
 }  // namespace
 
-int col_waves(const Geom &g, int KZ, int *ntx, int *nty, int *nkz) {
+// wave grid: x-segments of 62 nodes, row groups of COL_R rows, z-chunks of KZ
+// planes.  order 0: waves in x-segment order; 1: the 4 waves of a block in
+// row-group order (row groups padded to a multiple of 4; the padding waves
+// produce nothing and store zero partials); 2: as 1, blocks contiguous per XCD.
+int col_waves(const Geom &g, int KZ, int order, int *ntx, int *nty, int *nkz) {
     *ntx = (g.nx + 1 + 61) / 62;
     *nty = (g.ny + 1 + COL_R - 1) / COL_R;
+    if (order != 0) *nty = (*nty + 3) & ~3;
     *nkz = (g.nz + 1 + KZ - 1) / KZ;
     return (*ntx) * (*nty) * (*nkz);
 }
@@ -400,9 +465,11 @@ int col_faces(const Geom &g, ColFaces *fl) {
 int launch_col(int mode, const ColArgs &a, hipStream_t s) {
     const int waves = a.ntx * a.nty * a.nkz;
     const int nb = (waves + 3) / 4;
-    if (mode == MODE_APPLY) launch_timed(k_col<MODE_APPLY, COL_R, 3>, dim3(nb), dim3(256), 0, s, a);
-    else if (mode == MODE_INIT) launch_timed(k_col<MODE_INIT, COL_R, 2>, dim3(nb), dim3(256), 0, s, a);
-    else launch_timed(k_col<MODE_PASSA0, COL_R, 3>, dim3(nb), dim3(256), 0, s, a);
+    // one z-step of prefetch: two steps, or 4 waves per SIMD for iteration 0,
+    // measured no faster on 513^3
+    if (mode == MODE_APPLY) launch_timed(k_col<MODE_APPLY, COL_R, 3, 1>, dim3(nb), dim3(256), 0, s, a);
+    else if (mode == MODE_INIT) launch_timed(k_col<MODE_INIT, COL_R, 2, 1>, dim3(nb), dim3(256), 0, s, a);
+    else launch_timed(k_col<MODE_PASSA0, COL_R, 3, 1>, dim3(nb), dim3(256), 0, s, a);
     ColFaces fl;
     const int fb = col_faces(a.g, &fl);
     if (fb > 0) {

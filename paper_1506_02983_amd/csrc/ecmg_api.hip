@@ -9,8 +9,10 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <deque>
 #include <mutex>
+#include <thread>
 #include <unordered_map>
 #include <cstdarg>
 #include <cstdio>
@@ -97,13 +99,17 @@ struct ecmg_ctx {
     int fold_max = FOLD_MAX_BLOCKS;            // JCG scalar steps folded into the passes up to this many blocks
     int col_enable = 1;                        // column kernels for init / iteration 0 on unfolded levels
     int col_kz = 16;                           // planes per z-chunk of a column wave
+    int col_order = 0;                         // wave order of the column kernels (col_waves)
     uint32_t timing_mask = 0;                  // kernel classes timed with HIP events (bit k = class k)
     // persistent JCG for grids of at most persist_max nodes (larger ones: the
     // tiled passes with folded scalar steps -- two launches per iteration,
     // whose boundaries cost about what one of the persistent kernel's three
     // device-wide barriers per iteration costs)
     int64_t persist_max = 20000;
-    int64_t mixed_min = 300000;                // ECMG_MIXED: levels up to this many nodes stay FP64
+    // ECMG_MIXED: levels up to this many nodes stay FP64 -- those whose JCG
+    // passes fold their scalar steps (pass B of at most FOLD_MAX_BLOCKS blocks
+    // of 2,048 nodes), where an iteration waits on launches, not bytes
+    int64_t mixed_min = (int64_t)FOLD_MAX_BLOCKS * 2048;
                                                // (an explicit persistent_nodes sets it too)
     int persist_blocks = 0;                    // co-resident workgroups (0 = unavailable)
     int persist_seglen = 0;                    // persistent kernel: nodes per thread along z (0 = by size)
@@ -662,7 +668,8 @@ static int col_args(ecmg_ctx *c, Level &L, ColArgs *ca) {
     ColArgs &x = *ca;
     x.g = L.g;
     x.KZ = std::max(1, std::min(c->col_kz, L.g.nz + 1));
-    const int waves = col_waves(L.g, x.KZ, &x.ntx, &x.nty, &x.nkz);
+    x.order = c->col_order;
+    const int waves = col_waves(L.g, x.KZ, x.order, &x.ntx, &x.nty, &x.nkz);
     x.beta = L.beta;
     for (int f = 0; f < 6; ++f) x.alpha[f] = L.alpha[f];
     x.F = L.F;
@@ -832,7 +839,8 @@ static bool uses_persistent(const ecmg_ctx *c, int l) {
 
 // Mixed precision applies to JCG levels (not DSOLVE) solved by the tiled
 // kernels above mixed_min nodes; smaller levels are latency-bound (FP32 saves
-// bytes they do not wait for, and the outer FP64 steps add host round trips)
+// bytes they do not wait for, the outer FP64 steps add host round trips, and
+// FP32 JCG needed up to 1.6x the FP64 iterations on a high-contrast problem)
 // and stay FP64, as do the persistent ones.
 static bool uses_mixed(const ecmg_ctx *c, int l) {
     return c->opt.precision == ECMG_MIXED && l >= 2 && !uses_persistent(c, l) && c->lv[l].g.nreal > c->mixed_min;
@@ -1006,6 +1014,7 @@ int ecmg_create(const ecmg_options *opt, ecmg_ctx **out) {
     if (o.fold_blocks >= 0) c->fold_max = std::min<int>(o.fold_blocks, FOLD_MAX_BLOCKS);
     if (const char *v = std::getenv("ECMG_COL")) c->col_enable = std::atoi(v) != 0;
     if (const char *v = std::getenv("ECMG_COL_KZ")) c->col_kz = std::max(1, std::atoi(v));
+    if (const char *v = std::getenv("ECMG_COL_ORDER")) c->col_order = std::min(2, std::max(0, std::atoi(v)));
     if (const char *v = std::getenv("ECMG_PERSIST_SEG")) c->persist_seglen = std::max(1, std::atoi(v));
     if (const char *v = std::getenv("ECMG_PERSIST_NWG")) c->persist_nwg = std::max(1, std::atoi(v));
     if (const char *v = std::getenv("ECMG_BATCH_NPW")) c->batch_npw = std::max(64, std::atoi(v));
@@ -1207,7 +1216,7 @@ int ecmg_setup(ecmg_ctx *c, const ecmg_problem *p) {
             pn = std::max<int64_t>(pn, 2 * (int64_t)stencil_blocks(g, stencil_kz(g, c->KZ, c->kz_target), &a, &b, &d));
             pn = std::max<int64_t>(pn, 2 * passB_blocks(g.nnodes));
             ColFaces fl;
-            pn = std::max<int64_t>(pn, 2 * ((int64_t)col_waves(g, std::max(1, std::min(c->col_kz, g.nz + 1)), &a, &b, &d) +
+            pn = std::max<int64_t>(pn, 2 * ((int64_t)col_waves(g, std::max(1, std::min(c->col_kz, g.nz + 1)), c->col_order, &a, &b, &d) +
                                             col_faces(g, &fl)));
         }
         c->partials_n = pn;
@@ -2480,10 +2489,17 @@ struct ecmg_server {
     ecmg_options opt{};
     std::string tune_cache;            // owned copy of opt.tune_cache (request contexts are created later)
     size_t budget = 0, used = 0;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;      // the solve steps of every request
+    hipStream_t setup_stream = nullptr;  // discretisation of requests, beside the solve steps
+    int device = 0;
     ecmg_ctx *lead = nullptr;          // holds the queue-kernel buffers
-    std::mutex mu;                     // guards queue, tickets and statistics
+    std::mutex mu;                     // guards queue, ready, used, tickets and statistics
+    std::condition_variable cv;        // queue, budget, ready or stop changed
+    std::thread setup_thread;
+    bool stop = false;
+    int in_setup = 0;                  // requests the setup thread holds
     std::deque<ServerReq *> queue;
+    std::deque<ServerReq *> ready;     // set up, joining the active set at the next step
     std::vector<ServerReq *> active;
     std::unordered_map<uint64_t, ServerReq *> reqs;
     uint64_t next_ticket = 1;
@@ -2508,16 +2524,65 @@ static int server_complete(ecmg_server *S, ServerReq *r) {
     if (rc == ECMG_OK && hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(c, ECMG_EDEVICE, "sync failed");
     ecmg_destroy(c);
     r->ctx = nullptr;
-    std::lock_guard<std::mutex> g(S->mu);
-    r->t_done = Clock::now();
-    r->state = rc == ECMG_OK ? 2 : rc;
-    S->used -= r->bytes;
-    if (rc == ECMG_OK) {
-        S->lat_ms.push_back(std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count());
-        ++S->ndone;
-        S->t_last = r->t_done;
+    {
+        std::lock_guard<std::mutex> g(S->mu);
+        r->t_done = Clock::now();
+        r->state = rc == ECMG_OK ? 2 : rc;
+        S->used -= r->bytes;
+        if (rc == ECMG_OK) {
+            S->lat_ms.push_back(std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count());
+            ++S->ndone;
+            S->t_last = r->t_done;
+        }
     }
+    S->cv.notify_all();                // budget freed
     return rc;
+}
+
+// The setup thread: admits queued requests first come first served while
+// their hierarchies fit the budget and discretises each on the setup stream
+// (field callbacks run on this thread), so that the set-up of new requests
+// overlaps the solve steps of admitted ones.  A request joins the active set
+// at the next step after its set-up has completed on the device.
+static void server_setup_loop(ecmg_server *S) {
+    (void)hipSetDevice(S->device);
+    for (;;) {
+        ServerReq *r = nullptr;
+        {
+            std::unique_lock<std::mutex> g(S->mu);
+            S->cv.wait(g, [S] {
+                return S->stop || (!S->queue.empty() && S->used + S->queue.front()->bytes <= S->budget);
+            });
+            if (S->stop) return;
+            r = S->queue.front();
+            S->queue.pop_front();
+            S->used += r->bytes;
+            ++S->in_setup;
+        }
+        ecmg_options o = S->opt;
+        o.hip_stream = S->setup_stream;
+        int rc = ecmg_create(&o, &r->ctx);
+        if (rc == ECMG_OK) rc = ecmg_setup(r->ctx, &r->prob);
+        if (rc == ECMG_OK && hipStreamSynchronize(S->setup_stream) != hipSuccess) rc = ECMG_EDEVICE;
+        if (rc == ECMG_OK) {
+            r->ctx->stream = S->stream;          // its solve steps run on the server's stream
+        } else if (r->ctx) {
+            ecmg_destroy(r->ctx);
+            r->ctx = nullptr;
+        }
+        {
+            std::lock_guard<std::mutex> g(S->mu);
+            --S->in_setup;
+            if (rc == ECMG_OK) {
+                r->state = 1;
+                S->ready.push_back(r);
+            } else {
+                r->state = rc;
+                S->used -= r->bytes;
+            }
+        }
+        S->cv.notify_all();
+    }
 }
 
 // One tick: the current level of every active request.  Levels the persistent
@@ -2672,12 +2737,17 @@ int ecmg_server_create(const ecmg_options *opt, size_t hbm_budget_bytes, ecmg_se
     }
     ecmg_options lo = S->opt;
     lo.hip_stream = S->stream;
-    const int rc = ecmg_create(&lo, &S->lead);
+    int rc = ecmg_create(&lo, &S->lead);
+    if (rc == ECMG_OK && (hipGetDevice(&S->device) != hipSuccess ||
+                          hipStreamCreateWithFlags(&S->setup_stream, hipStreamNonBlocking) != hipSuccess))
+        rc = fail(nullptr, ECMG_EDEVICE, "setup stream creation failed");
     if (rc != ECMG_OK) {
+        if (S->lead) ecmg_destroy(S->lead);
         if (!S->opt.hip_stream) (void)hipStreamDestroy(S->stream);
         delete S;
         return rc;
     }
+    S->setup_thread = std::thread(server_setup_loop, S);
     *out = S;
     return ECMG_OK;
 }
@@ -2707,37 +2777,21 @@ int ecmg_server_submit(ecmg_server *S, const ecmg_problem *problem, double rel_t
     S->queue.push_back(r);
     S->reqs[r->ticket] = r;
     *ticket = r->ticket;
+    S->cv.notify_all();
     return ECMG_OK;
 }
 
 int ecmg_server_step(ecmg_server *S, int32_t *n_done) {
     if (!S) return fail(nullptr, ECMG_EINVAL, "server is NULL");
     if (n_done) *n_done = 0;
-    // admission, first come first served, while the hierarchy fits the budget
-    for (;;) {
-        ServerReq *r = nullptr;
-        {
-            std::lock_guard<std::mutex> g(S->mu);
-            if (S->queue.empty()) break;
-            if (S->used + S->queue.front()->bytes > S->budget) break;
-            r = S->queue.front();
-            S->queue.pop_front();
-            S->used += r->bytes;
-        }
-        ecmg_options o = S->opt;
-        o.hip_stream = S->stream;
-        int rc = ecmg_create(&o, &r->ctx);
-        if (rc == ECMG_OK) rc = ecmg_setup(r->ctx, &r->prob);
-        if (rc != ECMG_OK) {
-            if (r->ctx) ecmg_destroy(r->ctx);
-            r->ctx = nullptr;
-            std::lock_guard<std::mutex> g(S->mu);
-            r->state = rc;
-            S->used -= r->bytes;
-            continue;
-        }
-        r->state = 1;
-        S->active.push_back(r);
+    // requests whose set-up has completed join the active set; with none
+    // active, wait (briefly, so the caller can keep submitting) for one
+    {
+        std::unique_lock<std::mutex> g(S->mu);
+        if (S->active.empty() && S->ready.empty() && (S->in_setup > 0 || !S->queue.empty()))
+            S->cv.wait_for(g, std::chrono::milliseconds(2), [S] { return !S->ready.empty(); });
+        for (ServerReq *r : S->ready) S->active.push_back(r);
+        S->ready.clear();
     }
     if (S->active.empty()) return ECMG_OK;
     CHK(server_tick(S));
@@ -2801,11 +2855,20 @@ int ecmg_server_reset_stats(ecmg_server *S) {
 
 void ecmg_server_destroy(ecmg_server *S) {
     if (!S) return;
+    {
+        std::lock_guard<std::mutex> g(S->mu);
+        S->stop = true;
+    }
+    S->cv.notify_all();
+    if (S->setup_thread.joinable()) S->setup_thread.join();   // finishes the set-up it holds
     for (ServerReq *r : S->active)
+        if (r->ctx) ecmg_destroy(r->ctx);
+    for (ServerReq *r : S->ready)
         if (r->ctx) ecmg_destroy(r->ctx);
     for (auto &kv : S->reqs) delete kv.second;
     if (S->lead) ecmg_destroy(S->lead);
     if (!S->opt.hip_stream && S->stream) (void)hipStreamDestroy(S->stream);
+    if (S->setup_stream) (void)hipStreamDestroy(S->setup_stream);
     delete S;
 }
 

@@ -174,6 +174,7 @@ constexpr int COL_R = 2;
 struct ColArgs {
     Geom g;
     int ntx, nty, nkz, KZ;            // waves: x-segments, row groups, z-chunks; planes per chunk
+    int order;                        // wave order (col_waves)
     const double *beta;
     const double *alpha[6];
     const double *v;                  // input: APPLY v, INIT x, PASSA0 p_0
@@ -192,7 +193,7 @@ struct ColFaces {
     int64_t start[7];
 };
 // waves of a column launch for z-chunks of KZ planes
-int col_waves(const Geom &g, int KZ, int *ntx, int *nty, int *nkz);
+int col_waves(const Geom &g, int KZ, int order, int *ntx, int *nty, int *nkz);
 // blocks of the Robin-face kernel
 int col_faces(const Geom &g, ColFaces *fl);
 // column kernel plus the Robin-face kernel; returns the partial pairs written

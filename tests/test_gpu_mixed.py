@@ -67,7 +67,7 @@ def test_mixed_meets_fp64_stop_test_and_accuracy(orc, ecmg, name):
 
 
 def test_mixed_default_levels_and_fixed_mode(orc, ecmg):
-    """By default, levels of at most 300,000 nodes stay FP64 (outer_steps 0)
+    """By default, levels of at most 8,388,608 nodes stay FP64 (outer_steps 0)
     whichever driver solves them; an explicit persistent_nodes moves that limit
     (0: every JCG level mixed).  Fixed-iteration mode (parity) always runs FP64."""
     p = workloads.variable_beta_robin_cube(levels=4)

@@ -98,3 +98,29 @@ def test_over_budget_rejected(ecmg, requests):
         with pytest.raises(ecmg.EcmgError) as e:
             srv.submit(requests[1], 1e-8)
         assert e.value.code == ecmg.ENOMEM
+
+
+def test_served_requests_match_oracle(orc, ecmg, requests):
+    """Three served requests (finest 32^3 and 64^3, mixed Dirichlet / Robin
+    faces) against the oracle's cascade (Algorithm 4 with EXP_true): per-level
+    JCG counts equal, U~ within 1e-12 relative in the max norm.  The server's
+    DSOLVE levels run JCG to round-off, the oracle's a direct solve; the
+    difference is far below the bound."""
+    picked = [requests[0], requests[1], requests[3]]
+    mix, _ = _run(ecmg, picked)
+    for i, p in enumerate(picked):
+        ref = orc.cascade(p, eps=1e-8, keep_vectors=True, errors=False)
+        L = p.levels - 1
+        assert [r.iters for r in ref[2:]] == [x["iters"] for x in mix[i][1][2:]], i
+        assert _rel(mix[i][0].ravel(), np.asarray(ref[L].Ut).ravel()) <= 1e-12, i
+
+
+def test_release_refuses_unfinished(ecmg, requests):
+    with ecmg.Server(1 << 40) as srv:
+        t = srv.submit(requests[0], 1e-8)
+        with pytest.raises(ecmg.EcmgError) as e:
+            srv.release(t)
+        assert e.value.code == ecmg.ESTATE
+        while srv.poll(t)[0] != 2:
+            srv.step()
+        srv.release(t)
