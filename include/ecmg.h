@@ -313,8 +313,11 @@ int ecmg_extrapolate_batch(ecmg_ctx *const *ctxs, int32_t n);
  * small enough for the persistent kernel of all requests share one launch (one
  * workgroup range per request), larger levels run the tiled kernels; finished
  * requests get EXP_true, their U~ copied to the caller's buffer and their
- * device memory freed.  A request's result does not depend on which other
- * requests share its steps or on when its set-up ran.  FP64 only. */
+ * device memory kept for the next request with the same grids (a few contexts
+ * per grid shape, counted in the budget and given up when a request needs the
+ * room) or freed.  A request's result does not depend on which other requests
+ * share its steps, on when its set-up ran or on which context it reused.
+ * FP64 only. */
 typedef struct ecmg_server ecmg_server;
 
 /* opt: NULL = defaults (precision must be ECMG_FP64); the server's work runs
@@ -344,6 +347,17 @@ int ecmg_server_poll(ecmg_server *srv, uint64_t ticket, int32_t *state, ecmg_lev
 /* Latency from submit to U~ on the host over completed requests (p50, p99, in
  * ms), completed requests per second since creation or the last reset. */
 int ecmg_server_stats(ecmg_server *srv, double *p50_ms, double *p99_ms, double *solves_per_s, int64_t *done);
+/* Drain the tickets of requests that finished (done or failed) since the last
+ * call, in the order they finished: up to cap of them into tickets (caller-
+ * owned), their number into *n.  A caller that polls only these tickets does
+ * not scan every pending request after each step. */
+int ecmg_server_completed(ecmg_server *srv, uint64_t *tickets, int32_t cap, int32_t *n);
+/* Host time (ms) since creation or the last reset: set-up of requests on the
+ * set-up thread (discretisation with the field callbacks, allocation), level
+ * work of the steps and finishing of requests (EXP_true, copy of U~) on the
+ * calling thread.  Any argument may be NULL. */
+int ecmg_server_times(ecmg_server *srv, double *setup_ms, double *step_ms, double *finish_ms);
+/* Clears the latency statistics and the host times. */
 int ecmg_server_reset_stats(ecmg_server *srv);
 void ecmg_server_destroy(ecmg_server *srv);
 

@@ -96,7 +96,8 @@ EXPORTS = ["ecmg_default_options", "ecmg_create", "ecmg_setup", "ecmg_solve", "e
            "ecmg_device_view", "ecmg_norms", "ecmg_level_dims", "ecmg_plan_bytes", "ecmg_kernel_times",
            "ecmg_reset_kernel_times", "ecmg_last_error", "ecmg_destroy", "ecmg_solve_batch",
            "ecmg_extrapolate_batch", "ecmg_server_create", "ecmg_server_submit", "ecmg_server_step",
-           "ecmg_server_poll", "ecmg_server_stats", "ecmg_server_reset_stats", "ecmg_server_destroy",
+           "ecmg_server_poll", "ecmg_server_stats", "ecmg_server_completed", "ecmg_server_times", "ecmg_server_reset_stats",
+           "ecmg_server_destroy",
            "ecmg_autotune", "ecmg_tune_lookup", "ecmg_set_timing", "ecmg_cascadic_schedule",
            "ecmg_solve_levels", "ecmg_tolerance_schedule", "ecmg_autotune_batch", "ecmg_norms_noalloc"]
 
@@ -172,6 +173,8 @@ def load_library(path: str = LIB_PATH):
     L.ecmg_server_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(i32), P]
     L.ecmg_server_stats.argtypes = [P, ctypes.POINTER(dbl), ctypes.POINTER(dbl), ctypes.POINTER(dbl),
                                     ctypes.POINTER(ctypes.c_int64)]
+    L.ecmg_server_completed.argtypes = [P, ctypes.POINTER(ctypes.c_uint64), i32, ctypes.POINTER(i32)]
+    L.ecmg_server_times.argtypes = [P, ctypes.POINTER(dbl), ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
     L.ecmg_server_reset_stats.argtypes = [P]
     L.ecmg_server_destroy.argtypes = [P]
     L.ecmg_server_destroy.restype = None
@@ -651,7 +654,21 @@ class Server:
         done = ctypes.c_int64()
         self._check(self.L.ecmg_server_stats(self.h, ctypes.byref(p50), ctypes.byref(p99), ctypes.byref(sps),
                                              ctypes.byref(done)))
-        return {"p50_ms": p50.value, "p99_ms": p99.value, "solves_per_s": sps.value, "done": done.value}
+        st, tk, fi = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        self._check(self.L.ecmg_server_times(self.h, ctypes.byref(st), ctypes.byref(tk), ctypes.byref(fi)))
+        return {"p50_ms": p50.value, "p99_ms": p99.value, "solves_per_s": sps.value, "done": done.value,
+                "host_ms": {"setup": st.value, "steps": tk.value, "finish": fi.value}}
+
+    def completed(self) -> list:
+        """Tickets of the requests finished (done or failed) since the last call."""
+        out = []
+        buf = (ctypes.c_uint64 * 256)()
+        n = ctypes.c_int32()
+        while True:
+            self._check(self.L.ecmg_server_completed(self.h, buf, 256, ctypes.byref(n)))
+            out.extend(buf[:n.value])
+            if n.value < 256:
+                return out
 
     def reset_stats(self):
         self._check(self.L.ecmg_server_reset_stats(self.h))

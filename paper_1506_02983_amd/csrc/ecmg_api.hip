@@ -11,6 +11,7 @@
 #include <cmath>
 #include <condition_variable>
 #include <deque>
+#include <map>
 #include <mutex>
 #include <thread>
 #include <unordered_map>
@@ -61,6 +62,16 @@ struct ecmg_ctx {
     ecmg_options opt{};
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    // device blocks by size: a set-up of a problem with the grids of the
+    // previous one takes its arrays back instead of freeing and allocating
+    std::unordered_map<void *, size_t> dsize;   // bytes of every live block
+    std::multimap<size_t, void *> bin;          // blocks kept for reuse
+    bool recycle = false;                       // dfree keeps blocks in the bin
+    // set-up scratch (field samples of a slab or face; coordinates passed to
+    // device callbacks): grown as needed, kept until the context is destroyed,
+    // reused in stream order without host waits or frees
+    double *stmp = nullptr, *scoord = nullptr;
+    int64_t stmp_n = 0, scoord_n = 0;
     int device = 0;
     rocblas_handle blas = nullptr;            // dense DSOLVE factorisation (lazy)
     // batched solves led by this context: task and scalar arrays for the queue kernel
@@ -168,6 +179,12 @@ static int fail(ecmg_ctx *c, int code, const char *fmt, ...) {
 
 static int dalloc(ecmg_ctx *c, void **p, size_t bytes) {
     if (bytes == 0) bytes = 8;
+    auto it = c->bin.find(bytes);                // a kept block of this size
+    if (it != c->bin.end()) {
+        *p = it->second;
+        c->bin.erase(it);
+        return ECMG_OK;
+    }
     if (c->opt.alloc) {                          // the caller's allocator (stream-ordered)
         *p = c->opt.alloc(bytes, (void *)c->stream, c->opt.alloc_user);
         if (!*p) return fail(c, ECMG_ENOMEM, "allocator hook returned NULL for %zu bytes", bytes);
@@ -176,6 +193,7 @@ static int dalloc(ecmg_ctx *c, void **p, size_t bytes) {
             *p = nullptr;
             return fail(c, ECMG_EINVAL, "allocator hook returned a pointer not aligned to 256 bytes");
         }
+        c->dsize[*p] = bytes;
         return ECMG_OK;
     }
     hipError_t e = hipMalloc(p, bytes);
@@ -183,6 +201,7 @@ static int dalloc(ecmg_ctx *c, void **p, size_t bytes) {
         *p = nullptr;
         return fail(c, ECMG_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
     }
+    c->dsize[*p] = bytes;
     return ECMG_OK;
 }
 template <typename T>
@@ -214,8 +233,23 @@ static hipError_t copy_out(const Geom &g, double *host, const double *dev, doubl
 }
 static void dfree(ecmg_ctx *c, void *p) {
     if (!p) return;
+    auto it = c->dsize.find(p);
+    if (c->recycle && it != c->dsize.end()) {    // kept for the set-up in progress
+        c->bin.insert({it->second, p});
+        return;
+    }
+    if (it != c->dsize.end()) c->dsize.erase(it);
     if (c->opt.free) c->opt.free(p, (void *)c->stream, c->opt.alloc_user);
     else (void)hipFree(p);
+}
+
+// free the kept blocks
+static void bin_flush(ecmg_ctx *c) {
+    const bool keep = c->recycle;
+    c->recycle = false;
+    for (auto &kv : c->bin) dfree(c, kv.second);
+    c->bin.clear();
+    c->recycle = keep;
 }
 
 // ---------------------------------------------------------------------------
@@ -312,24 +346,32 @@ static int ensure_stage(ecmg_ctx *c, int64_t n) {
     return ECMG_OK;
 }
 
+// a set-up scratch buffer of at least n doubles (grown: the old one freed)
+static int ensure_scratch(ecmg_ctx *c, double **buf, int64_t *cap, int64_t n) {
+    if (*cap >= n) return ECMG_OK;
+    dfree(c, *buf);
+    *buf = nullptr;
+    *cap = 0;
+    CHK(dalloc(c, (void **)buf, 8 * (size_t)std::max<int64_t>(n, 1)));
+    *cap = n;
+    return ECMG_OK;
+}
+
 static int sample(ecmg_ctx *c, const ecmg_field &fld, const char *name, int face, const std::vector<double> &x,
                   const std::vector<double> &y, const std::vector<double> &z, double *dout, int check) {
     const int64_t n = (int64_t)x.size() * (int64_t)y.size() * (int64_t)z.size();
     if (n == 0) return ECMG_OK;
     if (fld.device) {
-        double *dx = nullptr, *dy = nullptr, *dz = nullptr;
-        CHK(dalloc_n(c, &dx, (int64_t)x.size()));
-        CHK(dalloc_n(c, &dy, (int64_t)y.size()));
-        CHK(dalloc_n(c, &dz, (int64_t)z.size()));
+        // coordinates in the context's scratch: the callback's work, this copy
+        // and the next sample's copy are ordered on the stream, so nothing
+        // waits on the host here
+        CHK(ensure_scratch(c, &c->scoord, &c->scoord_n, (int64_t)(x.size() + y.size() + z.size())));
+        double *dx = c->scoord, *dy = dx + x.size(), *dz = dy + y.size();
         HIPCHK(c, hipMemcpyAsync(dx, x.data(), 8 * x.size(), hipMemcpyHostToDevice, c->stream));
         HIPCHK(c, hipMemcpyAsync(dy, y.data(), 8 * y.size(), hipMemcpyHostToDevice, c->stream));
         HIPCHK(c, hipMemcpyAsync(dz, z.data(), 8 * z.size(), hipMemcpyHostToDevice, c->stream));
         const int rc = fld.device(face, (int64_t)x.size(), (int64_t)y.size(), (int64_t)z.size(), dx, dy, dz, dout,
                                   (void *)c->stream, fld.user);
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        dfree(c, dx);
-        dfree(c, dy);
-        dfree(c, dz);
         if (rc != 0) return fail(c, ECMG_ECALLBACK, "device callback for %s returned %d", name, rc);
         return ECMG_OK;
     }
@@ -1065,6 +1107,9 @@ void ecmg_destroy(ecmg_ctx *c) {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     free_levels(c);
+    bin_flush(c);
+    dfree(c, c->stmp);
+    dfree(c, c->scoord);
     if (c->blas) (void)rocblas_destroy_handle(c->blas);
     batch_plan_free(c, c->bplan);
     c->bplan = nullptr;
@@ -1165,7 +1210,19 @@ int ecmg_setup(ecmg_ctx *c, const ecmg_problem *p) {
     if (!c) return fail(nullptr, ECMG_EINVAL, "ctx is NULL");
     CHK(validate(c, p));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    // the same grids as the current hierarchy: its blocks are kept and taken
+    // back by size (the serving loop sets up one request after another on a
+    // context); otherwise everything is freed first
+    bool same = c->nlev == p->levels;
+    for (int l = 0; same && l < p->levels; ++l) {
+        double lo[3];
+        const Geom g = make_geom(p, l, lo);
+        same = g.nnodes == c->lv[l].g.nnodes && g.nx == c->lv[l].g.nx && g.ny == c->lv[l].g.ny;
+    }
+    if (!same) bin_flush(c);
+    c->recycle = same;
     free_levels(c);
+    c->recycle = false;
     c->nlev = p->levels;
     c->gen = ++g_generation;
     for (int f = 0; f < 6; ++f) c->face_type[f] = p->face_type[f];
@@ -1253,17 +1310,13 @@ int ecmg_setup(ecmg_ctx *c, const ecmg_problem *p) {
         {
             const int64_t per = 8 * (int64_t)g.nx * g.ny;   // Gauss points per element layer
             const int step = (int)std::max<int64_t>(1, kBatchPoints / per);
-            double *dbuf = nullptr;
-            CHK(dalloc_n(c, &dbuf, per * std::min(step, g.nz)));
+            CHK(ensure_scratch(c, &c->stmp, &c->stmp_n, per * std::min(step, g.nz)));
             for (int e0 = 0; e0 < g.nz; e0 += step) {
                 const int e1 = std::min(g.nz, e0 + step);
                 std::vector<double> zz(gz.begin() + 2 * e0, gz.begin() + 2 * e1);
-                int rc = sample(c, p->f, "f", -1, gx, gy, zz, dbuf, 0);
-                if (rc != ECMG_OK) { dfree(c, dbuf); return rc; }
-                launch_load_volume(g, e0, e1, dbuf, L.F, c->stream);
-                HIPCHK(c, hipStreamSynchronize(c->stream));
+                CHK(sample(c, p->f, "f", -1, gx, gy, zz, c->stmp, 0));
+                launch_load_volume(g, e0, e1, c->stmp, L.F, c->stream);
             }
-            dfree(c, dbuf);
         }
         // Robin faces: alpha at face-element centroids, g_R at face Gauss points
         launch_fill(L.x, g.nnodes, 0.0, c->stream);
@@ -1283,13 +1336,9 @@ int ecmg_setup(ecmg_ctx *c, const ecmg_problem *p) {
                 CHK(sample(c, p->alpha, "alpha", f, s[0], s[1], s[2], L.alpha[f], 2));
                 s[pax] = gauss_coords(g, L.lo, pax);
                 s[qax] = gauss_coords(g, L.lo, qax);
-                double *dbuf = nullptr;
-                CHK(dalloc_n(c, &dbuf, 4 * L.nface[f]));
-                int rc = sample(c, p->g_R, "g_R", f, s[0], s[1], s[2], dbuf, 0);
-                if (rc != ECMG_OK) { dfree(c, dbuf); return rc; }
-                launch_load_face(g, f, dbuf, L.F, c->stream);
-                HIPCHK(c, hipStreamSynchronize(c->stream));
-                dfree(c, dbuf);
+                CHK(ensure_scratch(c, &c->stmp, &c->stmp_n, 4 * L.nface[f]));
+                CHK(sample(c, p->g_R, "g_R", f, s[0], s[1], s[2], c->stmp, 0));
+                launch_load_face(g, f, c->stmp, L.F, c->stream);
             }
         }
         // Dirichlet data at the nodes of Dirichlet faces
@@ -1303,13 +1352,9 @@ int ecmg_setup(ecmg_ctx *c, const ecmg_problem *p) {
             s[ax] = {(f & 1) ? nc.back() : nc.front()};
             s[pax] = node_coords(g, L.lo, pax);
             s[qax] = node_coords(g, L.lo, qax);
-            double *dbuf = nullptr;
-            CHK(dalloc_n(c, &dbuf, (int64_t)s[pax].size() * s[qax].size()));
-            int rc = sample(c, p->g_D, "g_D", f, s[0], s[1], s[2], dbuf, 0);
-            if (rc != ECMG_OK) { dfree(c, dbuf); return rc; }
-            launch_scatter_face(g, f, dbuf, L.x, c->stream);
-            HIPCHK(c, hipStreamSynchronize(c->stream));
-            dfree(c, dbuf);
+            CHK(ensure_scratch(c, &c->stmp, &c->stmp_n, (int64_t)s[pax].size() * s[qax].size()));
+            CHK(sample(c, p->g_D, "g_D", f, s[0], s[1], s[2], c->stmp, 0));
+            launch_scatter_face(g, f, c->stmp, L.x, c->stream);
         }
         const double *al[6];
         for (int f = 0; f < 6; ++f) al[f] = L.alpha[f];
@@ -2471,6 +2516,9 @@ int ecmg_tune_lookup(const char *path, int32_t precision, int32_t nx, int32_t ny
 namespace {
 using Clock = std::chrono::steady_clock;
 
+// contexts of finished requests the server keeps per grid shape for reuse
+constexpr int SERVER_IDLE_PER_SHAPE = 4;
+
 struct ServerReq {
     uint64_t ticket = 0;
     ecmg_problem prob{};
@@ -2501,6 +2549,19 @@ struct ecmg_server {
     std::deque<ServerReq *> queue;
     std::deque<ServerReq *> ready;     // set up, joining the active set at the next step
     std::vector<ServerReq *> active;
+    std::deque<uint64_t> finished;     // tickets done or failed, not yet drained
+    // contexts of finished requests kept for the next request with the same
+    // grids (its set-up takes the arrays back); their bytes stay in `used`
+    struct Idle {
+        ecmg_ctx *ctx;
+        int32_t n0[3], levels;
+        size_t bytes;
+    };
+    std::deque<Idle> idle;
+    size_t idle_bytes = 0;
+    // host time since creation or the last reset: set-up (set-up thread),
+    // steps' level work and finishing (calling thread), in ms
+    double t_setup = 0.0, t_tick = 0.0, t_finish = 0.0;
     std::unordered_map<uint64_t, ServerReq *> reqs;
     uint64_t next_ticket = 1;
     std::vector<double> lat_ms;
@@ -2522,20 +2583,32 @@ static int server_complete(ecmg_server *S, ServerReq *r) {
             rc = fail(c, ECMG_EDEVICE, "copy of U~ failed");
     }
     if (rc == ECMG_OK && hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(c, ECMG_EDEVICE, "sync failed");
-    ecmg_destroy(c);
     r->ctx = nullptr;
+    bool keep = false;
     {
         std::lock_guard<std::mutex> g(S->mu);
         r->t_done = Clock::now();
         r->state = rc == ECMG_OK ? 2 : rc;
-        S->used -= r->bytes;
+        S->finished.push_back(r->ticket);
         if (rc == ECMG_OK) {
             S->lat_ms.push_back(std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count());
             ++S->ndone;
             S->t_last = r->t_done;
         }
+        int same = 0;
+        for (const auto &e : S->idle)
+            same += e.levels == r->prob.levels && e.n0[0] == r->prob.n0[0] && e.n0[1] == r->prob.n0[1] &&
+                    e.n0[2] == r->prob.n0[2];
+        keep = rc == ECMG_OK && same < SERVER_IDLE_PER_SHAPE;
+        if (keep) {
+            S->idle.push_back({c, {r->prob.n0[0], r->prob.n0[1], r->prob.n0[2]}, r->prob.levels, r->bytes});
+            S->idle_bytes += r->bytes;
+        } else {
+            S->used -= r->bytes;
+        }
     }
-    S->cv.notify_all();                // budget freed
+    if (!keep) ecmg_destroy(c);
+    S->cv.notify_all();                // budget freed or a context to reuse
     return rc;
 }
 
@@ -2548,20 +2621,47 @@ static void server_setup_loop(ecmg_server *S) {
     (void)hipSetDevice(S->device);
     for (;;) {
         ServerReq *r = nullptr;
+        ecmg_ctx *reuse = nullptr;
+        std::vector<ecmg_ctx *> evict;
         {
+            // the budget counts kept contexts, which can be given up
             std::unique_lock<std::mutex> g(S->mu);
             S->cv.wait(g, [S] {
-                return S->stop || (!S->queue.empty() && S->used + S->queue.front()->bytes <= S->budget);
+                return S->stop ||
+                       (!S->queue.empty() && S->used - S->idle_bytes + S->queue.front()->bytes <= S->budget);
             });
             if (S->stop) return;
             r = S->queue.front();
             S->queue.pop_front();
+            for (auto it = S->idle.begin(); it != S->idle.end(); ++it)
+                if (it->levels == r->prob.levels && it->n0[0] == r->prob.n0[0] && it->n0[1] == r->prob.n0[1] &&
+                    it->n0[2] == r->prob.n0[2]) {
+                    reuse = it->ctx;
+                    S->used -= it->bytes;
+                    S->idle_bytes -= it->bytes;
+                    S->idle.erase(it);
+                    break;
+                }
+            while (S->used + r->bytes > S->budget && !S->idle.empty()) {   // oldest kept contexts first
+                evict.push_back(S->idle.front().ctx);
+                S->used -= S->idle.front().bytes;
+                S->idle_bytes -= S->idle.front().bytes;
+                S->idle.pop_front();
+            }
             S->used += r->bytes;
             ++S->in_setup;
         }
-        ecmg_options o = S->opt;
-        o.hip_stream = S->setup_stream;
-        int rc = ecmg_create(&o, &r->ctx);
+        const auto t_begin = Clock::now();
+        for (ecmg_ctx *e : evict) ecmg_destroy(e);
+        int rc = ECMG_OK;
+        if (reuse) {
+            r->ctx = reuse;
+            r->ctx->stream = S->setup_stream;
+        } else {
+            ecmg_options o = S->opt;
+            o.hip_stream = S->setup_stream;
+            rc = ecmg_create(&o, &r->ctx);
+        }
         if (rc == ECMG_OK) rc = ecmg_setup(r->ctx, &r->prob);
         if (rc == ECMG_OK && hipStreamSynchronize(S->setup_stream) != hipSuccess) rc = ECMG_EDEVICE;
         if (rc == ECMG_OK) {
@@ -2572,6 +2672,7 @@ static void server_setup_loop(ecmg_server *S) {
         }
         {
             std::lock_guard<std::mutex> g(S->mu);
+            S->t_setup += std::chrono::duration<double, std::milli>(Clock::now() - t_begin).count();
             --S->in_setup;
             if (rc == ECMG_OK) {
                 r->state = 1;
@@ -2579,6 +2680,7 @@ static void server_setup_loop(ecmg_server *S) {
             } else {
                 r->state = rc;
                 S->used -= r->bytes;
+                S->finished.push_back(r->ticket);
             }
         }
         S->cv.notify_all();
@@ -2794,7 +2896,9 @@ int ecmg_server_step(ecmg_server *S, int32_t *n_done) {
         S->ready.clear();
     }
     if (S->active.empty()) return ECMG_OK;
+    const auto t0 = Clock::now();
     CHK(server_tick(S));
+    const auto t1 = Clock::now();
     int32_t done = 0;
     std::vector<ServerReq *> keep;
     for (ServerReq *r : S->active) {
@@ -2807,6 +2911,11 @@ int ecmg_server_step(ecmg_server *S, int32_t *n_done) {
         ++done;
     }
     S->active.swap(keep);
+    {
+        std::lock_guard<std::mutex> g(S->mu);
+        S->t_tick += std::chrono::duration<double, std::milli>(t1 - t0).count();
+        S->t_finish += std::chrono::duration<double, std::milli>(Clock::now() - t1).count();
+    }
     if (n_done) *n_done = done;
     return ECMG_OK;
 }
@@ -2843,9 +2952,31 @@ int ecmg_server_stats(ecmg_server *S, double *p50_ms, double *p99_ms, double *so
     return ECMG_OK;
 }
 
+int ecmg_server_completed(ecmg_server *S, uint64_t *tickets, int32_t cap, int32_t *n) {
+    if (!S || !n || (cap > 0 && !tickets)) return fail(nullptr, ECMG_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> g(S->mu);
+    int32_t k = 0;
+    while (k < cap && !S->finished.empty()) {
+        tickets[k++] = S->finished.front();
+        S->finished.pop_front();
+    }
+    *n = k;
+    return ECMG_OK;
+}
+
+int ecmg_server_times(ecmg_server *S, double *setup_ms, double *step_ms, double *finish_ms) {
+    if (!S) return fail(nullptr, ECMG_EINVAL, "server is NULL");
+    std::lock_guard<std::mutex> g(S->mu);
+    if (setup_ms) *setup_ms = S->t_setup;
+    if (step_ms) *step_ms = S->t_tick;
+    if (finish_ms) *finish_ms = S->t_finish;
+    return ECMG_OK;
+}
+
 int ecmg_server_reset_stats(ecmg_server *S) {
     if (!S) return fail(nullptr, ECMG_EINVAL, "server is NULL");
     std::lock_guard<std::mutex> g(S->mu);
+    S->t_setup = S->t_tick = S->t_finish = 0.0;
     S->lat_ms.clear();
     S->ndone = 0;
     S->have_t0 = true;
@@ -2865,6 +2996,7 @@ void ecmg_server_destroy(ecmg_server *S) {
         if (r->ctx) ecmg_destroy(r->ctx);
     for (ServerReq *r : S->ready)
         if (r->ctx) ecmg_destroy(r->ctx);
+    for (auto &e : S->idle) ecmg_destroy(e.ctx);
     for (auto &kv : S->reqs) delete kv.second;
     if (S->lead) ecmg_destroy(S->lead);
     if (!S->opt.hip_stream && S->stream) (void)hipStreamDestroy(S->stream);

@@ -205,3 +205,27 @@ def test_per_level_tolerance_schedule(orc, ecmg, driver):
     for l in range(2, p.levels):
         assert infos[l]["rre"] <= sched[l]
     assert max(d) <= 1e-12, d
+
+
+def test_resetup_same_grids_matches_fresh(ecmg):
+    """A second set-up of a problem with the same grids takes the context's
+    device arrays back (by size) instead of freeing and allocating them; the
+    solve then equals a fresh context's bit for bit, also after a set-up of
+    other grids in between."""
+    rng = np.random.default_rng(5)
+    mk = lambda n: workloads.serving_request(n, rng.uniform(0, 1, 3), rng.uniform(1, 3, 3), rng.integers(0, 2, 6))
+    a, b, c = mk(32), mk(32), mk(64)
+
+    def solve(s, p):
+        s.setup(p)
+        s.solve(1e-8)
+        return s.extrapolate()
+
+    with ecmg.Solver(keep_w=True) as s:
+        solve(s, a)
+        got_b = solve(s, b)
+        solve(s, c)
+        got_b2 = solve(s, b)
+    with ecmg.Solver(keep_w=True) as f:
+        ref_b = solve(f, b)
+    assert np.array_equal(got_b, ref_b) and np.array_equal(got_b2, ref_b)

@@ -115,6 +115,28 @@ def test_served_requests_match_oracle(orc, ecmg, requests):
         assert _rel(mix[i][0].ravel(), np.asarray(ref[L].Ut).ravel()) <= 1e-12, i
 
 
+def test_completed_drains_each_ticket_once(ecmg, requests):
+    """ecmg_server_completed hands out every finished ticket once, in finishing
+    order; a context kept from a finished request serves the next request of
+    the same grids bit for bit like a fresh server."""
+    with ecmg.Server(1 << 40) as srv:
+        tickets = [srv.submit(p, 1e-8) for p in requests]
+        seen = []
+        while len(seen) < len(tickets):
+            srv.step()
+            got = srv.completed()
+            assert all(srv.poll(t)[0] == 2 for t in got)
+            seen += got
+        assert sorted(seen) == sorted(tickets) and srv.completed() == []
+        again = srv.submit(requests[0], 1e-8)       # reuses a kept 32^3 context
+        while srv.poll(again)[0] != 2:
+            srv.step()
+        assert srv.completed() == [again]
+        fresh, _ = _run(ecmg, [requests[0]])
+        assert np.array_equal(srv.result(again), fresh[0][0])
+        assert np.array_equal(srv.result(tickets[0]), fresh[0][0])
+
+
 def test_release_refuses_unfinished(ecmg, requests):
     with ecmg.Server(1 << 40) as srv:
         t = srv.submit(requests[0], 1e-8)
