@@ -226,8 +226,9 @@ __device__ __forceinline__ void col_step(const ColArgs &a, int i, int j0, int k,
     }
 }
 
-// WPE: waves per SIMD the register budget is set for (init 150 VGPRs and
-// iteration 0 122 VGPRs fit 3 and 4 waves); D: prefetch distance in z-steps
+// WPE: waves per SIMD the register budget is set for (init, 2 rows: 150
+// VGPRs, 3 waves fit; iteration 0, 4 rows: about 200 VGPRs, 2 waves); D:
+// prefetch distance in z-steps
 template <int MODE, int R, int WPE, int D>
 __global__ void __launch_bounds__(256, WPE) k_col(const ColArgs a) {
     constexpr int NR = D + 3;
@@ -436,13 +437,13 @@ __global__ void __launch_bounds__(256) k_col_face(const ColArgs a, const ColFace
 
 }  // namespace
 
-// wave grid: x-segments of 62 nodes, row groups of COL_R rows, z-chunks of KZ
+// wave grid: x-segments of 62 nodes, row groups of R rows, z-chunks of KZ
 // planes.  order 0: waves in x-segment order; 1: the 4 waves of a block in
 // row-group order (row groups padded to a multiple of 4; the padding waves
 // produce nothing and store zero partials); 2: as 1, blocks contiguous per XCD.
-int col_waves(const Geom &g, int KZ, int order, int *ntx, int *nty, int *nkz) {
+int col_waves(const Geom &g, int KZ, int order, int R, int *ntx, int *nty, int *nkz) {
     *ntx = (g.nx + 1 + 61) / 62;
-    *nty = (g.ny + 1 + COL_R - 1) / COL_R;
+    *nty = (g.ny + 1 + R - 1) / R;
     if (order != 0) *nty = (*nty + 3) & ~3;
     *nkz = (g.nz + 1 + KZ - 1) / KZ;
     return (*ntx) * (*nty) * (*nkz);
@@ -463,13 +464,15 @@ int col_faces(const Geom &g, ColFaces *fl) {
 }
 
 int launch_col(int mode, const ColArgs &a, hipStream_t s) {
+    // the wave grid (a.nty) was laid out for a.R rows per wave
+    if (a.R != (mode == MODE_PASSA0 ? COL_R_A0 : COL_R_INIT)) return -1;
     const int waves = a.ntx * a.nty * a.nkz;
     const int nb = (waves + 3) / 4;
     // one z-step of prefetch: two steps, or 4 waves per SIMD for iteration 0,
     // measured no faster on 513^3
-    if (mode == MODE_APPLY) launch_timed(k_col<MODE_APPLY, COL_R, 3, 1>, dim3(nb), dim3(256), 0, s, a);
-    else if (mode == MODE_INIT) launch_timed(k_col<MODE_INIT, COL_R, 2, 1>, dim3(nb), dim3(256), 0, s, a);
-    else launch_timed(k_col<MODE_PASSA0, COL_R, 3, 1>, dim3(nb), dim3(256), 0, s, a);
+    if (mode == MODE_APPLY) launch_timed(k_col<MODE_APPLY, COL_R_INIT, 3, 1>, dim3(nb), dim3(256), 0, s, a);
+    else if (mode == MODE_INIT) launch_timed(k_col<MODE_INIT, COL_R_INIT, 2, 1>, dim3(nb), dim3(256), 0, s, a);
+    else launch_timed(k_col<MODE_PASSA0, COL_R_A0, 2, 1>, dim3(nb), dim3(256), 0, s, a);
     ColFaces fl;
     const int fb = col_faces(a.g, &fl);
     if (fb > 0) {

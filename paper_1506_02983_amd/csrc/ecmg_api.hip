@@ -520,7 +520,8 @@ static int jcg_chunks(ecmg_ctx *c, int l, const StencilArgs<T> &a, const PassBAr
             const bool a0 = a.p_init && done_iters + t == 0;
             CHK(rec_begin(c, l, a0 ? 10 : kind_a, done_iters + t, &slot));
             if (a0 && col) {
-                launch_col(MODE_PASSA0, *col, c->stream);
+                if (launch_col(MODE_PASSA0, *col, c->stream) < 0)
+                    return fail(c, ECMG_EINVAL, "column wave grid mismatch");
                 CHK(rec_end(c, slot));
                 launch_stencil_finish(MODE_PASSA, sc, col->partials, col_waves_n, c->stream);
             } else {
@@ -706,12 +707,13 @@ static bool col_usable(const ecmg_ctx *c, const Geom &g) {
 // Column-kernel arguments of level L (input, output and partials set by the
 // caller); returns the partial pairs a launch writes (waves, then the blocks
 // of the Robin-face kernel).
-static int col_args(ecmg_ctx *c, Level &L, ColArgs *ca) {
+static int col_args(ecmg_ctx *c, Level &L, int R, ColArgs *ca) {
     ColArgs &x = *ca;
     x.g = L.g;
     x.KZ = std::max(1, std::min(c->col_kz, L.g.nz + 1));
     x.order = c->col_order;
-    const int waves = col_waves(L.g, x.KZ, x.order, &x.ntx, &x.nty, &x.nkz);
+    x.R = R;
+    const int waves = col_waves(L.g, x.KZ, x.order, R, &x.ntx, &x.nty, &x.nkz);
     x.beta = L.beta;
     for (int f = 0; f < 6; ++f) x.alpha[f] = L.alpha[f];
     x.F = L.F;
@@ -766,10 +768,13 @@ static int enqueue_jcg(ecmg_ctx *c, int l, double tol_abs, int max_iter, int fix
     ColArgs ca{};
     int cw = 0;
     const bool col = !fold && col_usable(c, L.g);
+    ColArgs ca0{};                                // iteration 0 (its own rows per wave)
+    int cw0 = 0;
     if (col) {
-        cw = col_args(c, L, &ca);
-        CHK(ensure_partials(c, 2 * (int64_t)cw));
-        ca.partials = c->partials;
+        cw = col_args(c, L, COL_R_INIT, &ca);
+        cw0 = col_args(c, L, COL_R_A0, &ca0);
+        CHK(ensure_partials(c, 2 * (int64_t)std::max(cw, cw0)));
+        ca.partials = ca0.partials = c->partials;
         a.partials = c->partials;
         b.partials = c->partials;
     }
@@ -780,13 +785,13 @@ static int enqueue_jcg(ecmg_ctx *c, int l, double tol_abs, int max_iter, int fix
         ca.out = c->r;
         ca.p_out = c->p1;
         ca.p_init = 1;
-        launch_col(MODE_INIT, ca, c->stream);
+        if (launch_col(MODE_INIT, ca, c->stream) < 0) return fail(c, ECMG_EINVAL, "column wave grid mismatch");
         CHK(rec_end(c, slot));
         launch_stencil_finish(MODE_INIT, c->sc, c->partials, cw, c->stream);
-        ca.v = c->p1;                             // iteration 0: q = A p_0
-        ca.out = c->q;
-        ca.p_out = nullptr;
-        ca.p_init = 0;
+        ca0.v = c->p1;                            // iteration 0: q = A p_0
+        ca0.out = c->q;
+        ca0.p_out = nullptr;
+        ca0.p_init = 0;
     } else {
         launch_stencil<double>(MODE_INIT, a, c->stream);
         CHK(rec_end(c, slot));
@@ -795,7 +800,7 @@ static int enqueue_jcg(ecmg_ctx *c, int l, double tol_abs, int max_iter, int fix
 
     const int hint = fixed < 0 ? L.last_iters : 0;
     if (fold) CHK(jcg_chunks_folded(c, l, a, b, fixed, hint, (int)nb_a, (int)nb_b, L.spec_live));
-    else CHK(jcg_chunks(c, l, a, b, c->sc, fixed, 0, 1, hint, L.spec_live, col ? &ca : nullptr, cw));
+    else CHK(jcg_chunks(c, l, a, b, c->sc, fixed, 0, 1, hint, L.spec_live, col ? &ca0 : nullptr, cw0));
     launch_final_x(L.g, L.x, c->p0, c->p1, c->sc, c->sc_lv_dev + l, c->stream);
     HIPCHK(c, hipGetLastError());
     return ECMG_OK;
@@ -1273,7 +1278,7 @@ int ecmg_setup(ecmg_ctx *c, const ecmg_problem *p) {
             pn = std::max<int64_t>(pn, 2 * (int64_t)stencil_blocks(g, stencil_kz(g, c->KZ, c->kz_target), &a, &b, &d));
             pn = std::max<int64_t>(pn, 2 * passB_blocks(g.nnodes));
             ColFaces fl;
-            pn = std::max<int64_t>(pn, 2 * ((int64_t)col_waves(g, std::max(1, std::min(c->col_kz, g.nz + 1)), c->col_order, &a, &b, &d) +
+            pn = std::max<int64_t>(pn, 2 * ((int64_t)col_waves(g, std::max(1, std::min(c->col_kz, g.nz + 1)), c->col_order, std::min(COL_R_INIT, COL_R_A0), &a, &b, &d) +
                                             col_faces(g, &fl)));
         }
         c->partials_n = pn;

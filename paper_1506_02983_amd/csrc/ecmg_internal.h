@@ -167,14 +167,18 @@ struct PassBArgs {
 constexpr int FOLD_MAX_BLOCKS = 4096;
 
 // Column stencil kernels (col_kernels.hip): one wave per (62-node x-segment,
-// COL_R rows, z-chunk of KZ planes), planes in registers, x neighbours by DPP.
+// R rows, z-chunk of KZ planes), planes in registers, x neighbours by DPP.
 // Used for JCG init and iteration 0 of pass A on levels whose passes run
-// with one-block finishing kernels (the large grids).
-constexpr int COL_R = 2;
+// with one-block finishing kernels (the large grids).  Rows per wave: init
+// keeps 2 (its epilogue inputs and outputs fill the registers: 4 rows would
+// leave 2 waves per SIMD and ran slower), iteration 0 takes 4 (halo rows 1.5x
+// instead of 2x its output rows: 513^3 0.75 -> 0.69 ms).
+constexpr int COL_R_INIT = 2, COL_R_A0 = 4;
 struct ColArgs {
     Geom g;
     int ntx, nty, nkz, KZ;            // waves: x-segments, row groups, z-chunks; planes per chunk
     int order;                        // wave order (col_waves)
+    int R;                            // node rows per wave (COL_R_INIT or COL_R_A0)
     const double *beta;
     const double *alpha[6];
     const double *v;                  // input: APPLY v, INIT x, PASSA0 p_0
@@ -193,11 +197,12 @@ struct ColFaces {
     int64_t start[7];
 };
 // waves of a column launch for z-chunks of KZ planes
-int col_waves(const Geom &g, int KZ, int order, int *ntx, int *nty, int *nkz);
+int col_waves(const Geom &g, int KZ, int order, int R, int *ntx, int *nty, int *nkz);
 // blocks of the Robin-face kernel
 int col_faces(const Geom &g, ColFaces *fl);
 // column kernel plus the Robin-face kernel; returns the partial pairs written
-// (waves, then face blocks), which the finishing kernel sums in that order
+// (waves, then face blocks), which the finishing kernel sums in that order, or
+// -1 (nothing launched) if a.R is not the mode's rows per wave
 int launch_col(int mode, const ColArgs &a, hipStream_t s);
 
 // One independent JCG solve inside the persistent kernel: a grid, its arrays,
