@@ -35,13 +35,14 @@ KIND_NAMES = {0: "jcg_pass_a", 1: "jcg_pass_b", 2: "jcg_init", 3: "exp_finite", 
               5: "jcg_pass_a_fp32", 6: "jcg_pass_b_fp32", 7: "jcg_persistent", 10: "jcg_pass_a0"}
 # kernel names as rocprofv3 reports them (stencil: <type, mode, rows of
 # threads, rows per thread, waves per SIMD>; column kernels: <mode, node rows
-# per wave, waves per SIMD>, with the Robin-face kernel of the same mode).
+# per wave, waves per SIMD, prefetch distance>, with the Robin-face kernel of
+# the same mode).
 # JCG init and iteration 0 of pass A run the tiled kernel on the levels whose
 # scalars are folded into the passes, the column kernels on the larger ones.
 KERNEL_SYMBOL = {0: "k_stencil<double, 2, 8, 1, 4>", 1: "k_passB<double>",
-                 2: "k_stencil<double, 1, 8, 1, 4> | k_col<1, 2, 2> + k_col_face<1>",
+                 2: "k_stencil<double, 1, 8, 1, 4> | k_col<1, 2, 2, 1> + k_col_face<1>",
                  3: "k_exp_finite", 4: "k_exp_true", 5: "k_stencil<float, 2, 8, 1, 4>", 6: "k_passB<float>",
-                 7: "k_jcg_persistent", 10: "k_stencil<double, 3, 4, 2, 2> | k_col<3, 2, 3> + k_col_face<3>"}
+                 7: "k_jcg_persistent", 10: "k_stencil<double, 3, 4, 2, 2> | k_col<3, 4, 2, 1> + k_col_face<3>"}
 
 
 def workload(name):
@@ -613,6 +614,12 @@ def main():
                 "bytes_per_launch": round(d["bytes"] / d["launches"]),
                 "region": "%d steps after the timed ones, HIP events only around this kernel's launches "
                           "(%.3f ms/step)" % (args.steps, region_ms)}
+    # the finest level's kernels against the same HBM peak (from the breakdown
+    # steps: every launch stamped; algorithmic bytes as above)
+    finest = [{"kernel": r["kernel"], "symbol": KERNEL_SYMBOL[r["kind"]].split(" | ")[-1], "launches": r["launches"],
+               "avg_us": round(r["avg_us"], 2), "achieved": round(r["gbs"], 1),
+               "frac": round(r["gbs"] / HBM_PEAK_GBS, 4), "bytes_per_launch": r["bytes_per_launch"]}
+              for r in kernels if r["level"] == L]
     jcg_fin = [r for r in kernels if r["level"] == L and r["kind"] in (0, 1, 10)]
     jcg_gbs = None
     if jcg_fin:
@@ -686,6 +693,7 @@ def main():
                                          "autotuned" if args.autotune else "built-in")},
         "autotune": tuned,
         "roofline": roofline,
+        "roofline_finest": {"level": L, "bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s", "kernels": finest},
         "cpu_baseline": cpu,
         "jcg_hbm_gbs_finest": jcg_gbs,
         "fourth_order": fourth,
