@@ -76,7 +76,10 @@ def algorithmic_bytes(kind, n, e, n1, n0, iters=0):
     if kind == 3:
         return 8 * (n + n1 + n0)        # write x; read u_{l-1}, u_{l-2} (the W copy is off when timed)
     if kind == 4:
-        return 8 * (2 * n + n1)         # read u_l, u_{l-1}; write U~
+        # a solve with EXP_true applies the finest level's last JCG update
+        # x += alpha p inside EXP_true (x is stored only when read later):
+        # read x, p, u_{l-1}; write U~
+        return 8 * (3 * n + n1)
     if kind == 5:
         return 4 * (6 * n + e)
     if kind == 6:

@@ -67,6 +67,11 @@ struct ecmg_ctx {
     std::unordered_map<void *, size_t> dsize;   // bytes of every live block
     std::multimap<size_t, void *> bin;          // blocks kept for reuse
     bool recycle = false;                       // dfree keeps blocks in the bin
+    // level whose last JCG x update (x += alpha p) is still pending on the
+    // device (c->sc, p0 / p1 hold it): a solve with EXP_true fuses the finest
+    // level's update into EXP_true; anything else that reads that x or reuses
+    // the JCG buffers applies it first (flush_x); -1: none
+    int x_pending = -1;
     // set-up scratch (field samples of a slab or face; coordinates passed to
     // device callbacks): grown as needed, kept until the context is destroyed,
     // reused in stream order without host waits or frees
@@ -730,7 +735,8 @@ static int col_args(ecmg_ctx *c, Level &L, int R, ColArgs *ca) {
 // the slot holds them once the stream has passed it.  speculate: a level whose
 // last two solves converged in the same number of iterations enqueues that
 // many and reads no status (L.spec_live; the caller checks `done` in the slot).
-static int enqueue_jcg(ecmg_ctx *c, int l, double tol_abs, int max_iter, int fixed, bool speculate = false) {
+static int enqueue_jcg(ecmg_ctx *c, int l, double tol_abs, int max_iter, int fixed, bool speculate = false,
+                       bool defer_x = false) {
     Level &L = c->lv[l];
     L.spec_live = speculate && fixed < 0 && c->opt.chunk <= 0 && c->opt.speculate && L.last_iters > 0 &&
                   L.spec_hits >= 1;
@@ -801,6 +807,19 @@ static int enqueue_jcg(ecmg_ctx *c, int l, double tol_abs, int max_iter, int fix
     const int hint = fixed < 0 ? L.last_iters : 0;
     if (fold) CHK(jcg_chunks_folded(c, l, a, b, fixed, hint, (int)nb_a, (int)nb_b, L.spec_live));
     else CHK(jcg_chunks(c, l, a, b, c->sc, fixed, 0, 1, hint, L.spec_live, col ? &ca0 : nullptr, cw0));
+    launch_final_x(L.g, L.x, c->p0, c->p1, c->sc, c->sc_lv_dev + l, c->stream, !defer_x);
+    HIPCHK(c, hipGetLastError());
+    if (defer_x) c->x_pending = l;
+    return ECMG_OK;
+}
+
+// Apply a pending last x update (see ecmg_ctx::x_pending).
+static int flush_x(ecmg_ctx *c) {
+    if (!c || c->x_pending < 0) return ECMG_OK;
+    const int l = c->x_pending;
+    c->x_pending = -1;
+    if (l >= c->nlev) return ECMG_OK;
+    const Level &L = c->lv[l];
     launch_final_x(L.g, L.x, c->p0, c->p1, c->sc, c->sc_lv_dev + l, c->stream);
     HIPCHK(c, hipGetLastError());
     return ECMG_OK;
@@ -938,7 +957,10 @@ static int do_exp_true(ecmg_ctx *c, int l) {
     if (!L.Ut) CHK(dalloc_n(c, &L.Ut, L.g.nnodes));
     size_t slot = 0;
     CHK(rec_begin(c, l, 4, 0, &slot));
-    launch_exp_true(L.g, L.x, c->lv[l - 1].x, L.Ut, c->stream);
+    if (c->x_pending == l)        // U~ from x + alpha p, the update itself stays pending
+        launch_exp_true(L.g, L.x, c->lv[l - 1].x, L.Ut, c->stream, c->sc, c->p0, c->p1);
+    else
+        launch_exp_true(L.g, L.x, c->lv[l - 1].x, L.Ut, c->stream);
     CHK(rec_end(c, slot));
     HIPCHK(c, hipGetLastError());
     return ECMG_OK;
@@ -1215,6 +1237,7 @@ int ecmg_setup(ecmg_ctx *c, const ecmg_problem *p) {
     if (!c) return fail(nullptr, ECMG_EINVAL, "ctx is NULL");
     CHK(validate(c, p));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->x_pending = -1;
     // the same grids as the current hierarchy: its blocks are kept and taken
     // back by size (the serving loop sets up one request after another on a
     // context); otherwise everything is freed first
@@ -1567,6 +1590,9 @@ static int solve_impl(ecmg_ctx *c, double rel_tol, const int32_t *fixed, ecmg_le
     if (level_tol)
         for (int l = 2; l < n; ++l)
             if (!(level_tol[l] >= 0.0)) return fail(c, ECMG_EINVAL, "rel_tol[%d] = %g must be >= 0", l, level_tol[l]);
+    // every level is computed again (the finest from EXP_finite): a pending
+    // update of the previous solve is void
+    c->x_pending = -1;
     std::vector<ecmg_level_info> li(n);
     std::vector<char> deferred(n, 0);        // JCG results still in the level's slot
     std::vector<int> cap(n, 0);              // their iteration caps
@@ -1615,6 +1641,7 @@ static int solve_impl(ecmg_ctx *c, double rel_tol, const int32_t *fixed, ecmg_le
             if (redo < 0) break;
             l = redo;
             redo = -1;
+            c->x_pending = -1;                   // the finest level is solved again
         }
         Level &L = c->lv[l];
         li[l].level = l;
@@ -1652,8 +1679,11 @@ static int solve_impl(ecmg_ctx *c, double rel_tol, const int32_t *fixed, ecmg_le
         }
         c->lv[l].spec_live = false;
         if (jcg) {
+            // the finest level's last x update goes into EXP_true, when nothing
+            // reads that x in between (the true residual does)
+            const bool defer_x = exp_true && l == n - 1 && !c->opt.true_residual;
             rc = uses_persistent(c, l) ? enqueue_jcg_persistent(c, l, tol, max_iter, fx)
-                                       : enqueue_jcg(c, l, tol, max_iter, fx, fixed == nullptr);
+                                       : enqueue_jcg(c, l, tol, max_iter, fx, fixed == nullptr, defer_x);
             deferred[l] = 1;
             cap[l] = max_iter;
         }
@@ -1981,6 +2011,7 @@ int ecmg_solve_batch(ecmg_ctx *const *ctxs, int32_t n, double rel_tol, ecmg_leve
     }
     if (c0->queue_blocks < 1) return fail(c0, ECMG_EDEVICE, "the queue kernel cannot be resident");
     hipStream_t s = c0->stream;
+    for (int i = 0; i < n; ++i) ctxs[i]->x_pending = -1;   // every level is computed again
     for (int i = 1; i < n; ++i)
         if (ctxs[i]->stream != s) HIPCHK(c0, hipStreamSynchronize(ctxs[i]->stream));
     BatchPlan *P = c0->bplan;
@@ -2043,6 +2074,7 @@ int ecmg_extrapolate_batch(ecmg_ctx *const *ctxs, int32_t n) {
         if (c->nlev < 2) return fail(c0, ECMG_EINVAL, "ctxs[%d] has fewer than 2 levels", i);
         // U~ is allocated (and zeroed on ctx's own stream) before that stream
         // is waited for: the batched kernel below runs on ctxs[0]'s stream
+        CHK(flush_x(c));
         Level &L = c->lv[c->nlev - 1];
         if (!L.Ut) CHK(dalloc_n(c, &L.Ut, L.g.nnodes));
         if (c->stream != s) HIPCHK(c0, hipStreamSynchronize(c->stream));
@@ -2106,7 +2138,7 @@ static int check_level(ecmg_ctx *c, int32_t *level, int min_level) {
     if (*level < 0) *level = c->nlev - 1;
     if (*level < min_level || *level >= c->nlev)
         return fail(c, ECMG_EINVAL, "level %d out of range [%d, %d)", *level, min_level, c->nlev);
-    return ECMG_OK;
+    return flush_x(c);               // the caller reads or replaces level data
 }
 
 int ecmg_extrapolate(ecmg_ctx *c, int32_t level, double *host_out) {
@@ -2306,6 +2338,7 @@ int ecmg_set_timing(ecmg_ctx *c, int32_t mask) {
 int ecmg_autotune(ecmg_ctx *c, int32_t iters, const char *cache_path, ecmg_tune_result *out) {
     if (!c) return fail(nullptr, ECMG_EINVAL, "ctx is NULL");
     if (!c->ready) return fail(c, ECMG_ESTATE, "ecmg_autotune before ecmg_setup");
+    CHK(flush_x(c));
     const int fixed_iters = iters;
     const std::string path = cache_path ? std::string(cache_path) : c->tune_cache;
     std::map<std::string, TuneEntry> entries;

@@ -304,8 +304,10 @@ template <typename T>
 void launch_passB(const PassBArgs<T> &a, hipStream_t s);
 // blocks of pass B for n nodes (its partial slots: twice as many)
 int64_t passB_blocks(int64_t n);
+// x += alpha p of the last iteration if pending (update = false: only the copy
+// of the final scalars to `out`, the update left to the caller)
 void launch_final_x(const Geom &g, double *x, const double *p0, const double *p1, const JcgScalars *sc,
-                    JcgScalars *out, hipStream_t s);
+                    JcgScalars *out, hipStream_t s, bool update = true);
 // mixed precision: r32 = r64 / s, d32 = 0, JCG start scalars (FP64 sums)
 void launch_mixed_start(const Geom &g, const double *r64, double inv_s, const float *dinv32, float *r32, float *d32,
                         JcgScalars *sc, double *partials, unsigned *counter, hipStream_t s);
@@ -317,7 +319,10 @@ void launch_jcg_reset(JcgScalars *sc, double tol, int max_iter, int fixed, hipSt
 
 void launch_exp_finite(const Geom &gf, const Geom &g1, const double *U1, const double *U0, double *x, double *W,
                        int variant, hipStream_t s);
-void launch_exp_true(const Geom &gf, const double *U1, const double *U0, double *Ut, hipStream_t s);
+// sc non-NULL: the fine solution is U1 + alpha p with the pending last update
+// of the JCG solve whose scalars are sc and search directions p0 / p1
+void launch_exp_true(const Geom &gf, const double *U1, const double *U0, double *Ut, hipStream_t s,
+                     const JcgScalars *sc = nullptr, const double *p0 = nullptr, const double *p1 = nullptr);
 
 // One box of a batched EXP_finite (U1 = u_{l-1}, U0 = u_{l-2}, x and optional
 // W on level l) or EXP_true (U1 = u_l, U0 = u_{l-1}, result into x).  b0 / nb:

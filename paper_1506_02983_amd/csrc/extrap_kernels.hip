@@ -294,9 +294,34 @@ __global__ void __launch_bounds__(256) k_exp_finite(const Geom gf, const Geom g1
 // 2048 blocks per launch: small grids do not march, large ones amortise the
 // re-read chunk boundary.
 
-__device__ __forceinline__ void exp_true_block(const Geom &gf, const double *__restrict__ U1,
-                                               const double *__restrict__ U0, double *__restrict__ Ut, int tkz,
-                                               int bx, int by, int bz) {
+// The fine solution read by EXP_true: U1 itself, or (FUSE) U1 + alpha p, the
+// last x update of the JCG solve that produced U1 when it is still pending
+// (the finest level of a solve with EXP_true applies it here instead of
+// storing it: x is read once either way, and p is read instead of x being
+// written back and read again).
+struct FineRead {
+    const double *__restrict__ U1;
+    const double *__restrict__ P;     // FUSE: the search direction of the last iteration
+    double al;                        // its step length, 0 if no update is pending
+    template <bool FUSE>
+    __device__ __forceinline__ double at(int64_t i) const {
+        return FUSE ? fma(al, P[i], U1[i]) : U1[i];
+    }
+    template <bool FUSE>
+    __device__ __forceinline__ double2 at2(int64_t i) const {
+        double2 v = *(const double2 *)(U1 + i);
+        if (FUSE) {
+            const double2 q = *(const double2 *)(P + i);
+            v.x = fma(al, q.x, v.x);
+            v.y = fma(al, q.y, v.y);
+        }
+        return v;
+    }
+};
+
+template <bool FUSE = false>
+__device__ __forceinline__ void exp_true_block(const Geom &gf, const FineRead &U, const double *__restrict__ U0,
+                                               double *__restrict__ Ut, int tkz, int bx, int by, int bz) {
     const int NX1 = gf.nx / 2, NY1 = gf.ny / 2, NZ1 = gf.nz / 2;   // coarse elements per axis
     const int p = bx * 64 + threadIdx.x, J = by * 4 + threadIdx.y;
     if (p > NX1 || J > NY1) return;
@@ -315,8 +340,8 @@ __device__ __forceinline__ void exp_true_block(const Geom &gf, const double *__r
             const int64_t fr = f + sx * (2 * (int64_t)jj), cr = c + cx * jj;
             const double c0 = U0[cr + p];
             if (dj == 0) c00 = c0;
-            d[dj][0] = U1[fr + 2 * p] - c0;
-            d[dj][1] = U1[fr + 2 * p2] - U0[cr + p2];
+            d[dj][0] = U.at<FUSE>(fr + 2 * p) - c0;
+            d[dj][1] = U.at<FUSE>(fr + 2 * p2) - U0[cr + p2];
         }
     };
     double dlo[2][2], dhi[2][2], clo, chi;
@@ -333,11 +358,11 @@ __device__ __forceinline__ void exp_true_block(const Geom &gf, const double *__r
                 const int64_t id = 2 * p + sx * (2 * (int64_t)J + b) + sxy * (2 * (int64_t)K + c);
                 double u_e, u_o = 0.0;
                 if (hx) {
-                    const double2 v = *(const double2 *)(U1 + id);   // 2p even, rows 16-byte aligned
+                    const double2 v = U.at2<FUSE>(id);   // 2p even, rows 16-byte aligned
                     u_e = v.x;
                     u_o = v.y;
                 } else {
-                    u_e = U1[id];
+                    u_e = U.at<FUSE>(id);
                 }
                 // sums over the contributing coarse rows (planes outer, rows inner)
                 double se = 0.0, so = 0.0;
@@ -375,7 +400,18 @@ __device__ __forceinline__ void exp_true_block(const Geom &gf, const double *__r
 
 __global__ void __launch_bounds__(256) k_exp_true(const Geom gf, const double *__restrict__ U1,
                                                   const double *__restrict__ U0, double *__restrict__ Ut, int tkz) {
-    exp_true_block(gf, U1, U0, Ut, tkz, blockIdx.x, blockIdx.y, blockIdx.z);
+    const FineRead U{U1, nullptr, 0.0};
+    exp_true_block<false>(gf, U, U0, Ut, tkz, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// EXP_true from x + alpha p (the JCG scalars say whether an update is pending
+// and which of the two search-direction buffers holds p)
+__global__ void __launch_bounds__(256) k_exp_true_fused(const Geom gf, const double *__restrict__ X,
+                                                        const double *__restrict__ U0, double *__restrict__ Ut,
+                                                        int tkz, const JcgScalars *__restrict__ sc,
+                                                        const double *__restrict__ p0, const double *__restrict__ p1) {
+    const FineRead U{X, (sc->iter & 1) ? p1 : p0, sc->pending ? sc->alpha : 0.0};
+    exp_true_block<true>(gf, U, U0, Ut, tkz, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 // ---------------------------------------------------------------------------
@@ -402,8 +438,9 @@ __global__ void __launch_bounds__(256) k_exp_true_batch(const ExpTask *__restric
     const ExpTask &t = tasks[find_box(tasks, n, b, 1)];
     const int64_t lb = b - t.b0[1];
     const int64_t pl = lb / t.gx[1];
-    exp_true_block(t.gf, t.U1, t.U0, t.x, t.tkz, (int)(lb - pl * t.gx[1]), (int)(pl % t.gy[1]),
-                   (int)(pl / t.gy[1]));
+    const FineRead U{t.U1, nullptr, 0.0};
+    exp_true_block<false>(t.gf, U, t.U0, t.x, t.tkz, (int)(lb - pl * t.gx[1]), (int)(pl % t.gy[1]),
+                          (int)(pl / t.gy[1]));
 }
 
 // Block counts of a box: EXP_finite one thread per coarse element (256 per
@@ -492,10 +529,12 @@ void launch_zero_pad_f32(const Geom &g, float *a, float *b, float *c, hipStream_
     hipLaunchKernelGGL(k_zero_pad_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, a, b, c);
 }
 
-void launch_exp_true(const Geom &gf, const double *U1, const double *U0, double *Ut, hipStream_t s) {
+void launch_exp_true(const Geom &gf, const double *U1, const double *U0, double *Ut, hipStream_t s,
+                     const JcgScalars *sc, const double *p0, const double *p1) {
     const int tkz = exp_true_tkz(gf);
     const dim3 grid(exp_true_gx(gf), exp_true_gy(gf), exp_true_gz(gf, tkz));
-    launch_timed(k_exp_true, grid, dim3(64, 4), 0, s, gf, U1, U0, Ut, tkz);
+    if (sc) launch_timed(k_exp_true_fused, grid, dim3(64, 4), 0, s, gf, U1, U0, Ut, tkz, sc, p0, p1);
+    else launch_timed(k_exp_true, grid, dim3(64, 4), 0, s, gf, U1, U0, Ut, tkz);
 }
 
 }  // namespace ecmg

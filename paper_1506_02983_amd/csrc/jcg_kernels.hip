@@ -827,9 +827,10 @@ void launch_passB(const PassBArgs<T> &a, hipStream_t s) {
 }
 
 void launch_final_x(const Geom &g, double *x, const double *p0, const double *p1, const JcgScalars *sc,
-                    JcgScalars *out, hipStream_t s) {
-    const int64_t nb = std::max<int64_t>(1, (g.nnodes / 2 + UB * 256 - 1) / (UB * 256));
-    hipLaunchKernelGGL((k_final_x<double>), dim3((unsigned)nb), dim3(256), 0, s, g.nnodes, x, p0, p1, sc, out);
+                    JcgScalars *out, hipStream_t s, bool update) {
+    const int64_t n = update ? g.nnodes : 0;
+    const int64_t nb = std::max<int64_t>(1, (n / 2 + UB * 256 - 1) / (UB * 256));
+    hipLaunchKernelGGL((k_final_x<double>), dim3((unsigned)nb), dim3(256), 0, s, n, x, p0, p1, sc, out);
 }
 
 void launch_jcg_reset(JcgScalars *sc, double tol, int max_iter, int fixed, hipStream_t s) {

@@ -153,21 +153,36 @@ def test_speculation_off_gives_the_same_iterates(ecmg):
 
 
 def test_solve_extrapolated_matches_solve_then_extrapolate(ecmg):
-    """ecmg_solve_extrapolated (EXP_true enqueued behind the cascade, one wait)
-    leaves the U~ of ecmg_solve + ecmg_extrapolate, also when a speculative
-    level falls short and the finest levels are solved again."""
+    """ecmg_solve_extrapolated (EXP_true enqueued behind the cascade, one wait;
+    the finest level's last x update fused into EXP_true and applied to x only
+    when x is read) leaves the U~ and U of ecmg_solve + ecmg_extrapolate, also
+    when a speculative level falls short and the finest levels are solved
+    again, and when the next call reads x (get, norms, extrapolate, a JCG
+    continuation) or replaces it (solve)."""
     p = workloads.variable_beta_robin_cube(levels=5)
     L = p.levels - 1
-    ref = {}
+    ref, refu, refj = {}, {}, None
     with ecmg.Solver(persistent_nodes=0) as s:
         s.setup(p)
         for eps in (1e-6, 1e-10):
             s.solve(eps)
+            refu[eps] = s.get(L, ecmg.VEC_U)
             s.extrapolate(L, out=False)
             ref[eps] = s.get(L, ecmg.VEC_UTILDE)
+        refn = s.norms(L, ecmg.VEC_U)
+        s.jcg(L, 1e-12)
+        refj = s.get(L, ecmg.VEC_U)
     with ecmg.Solver(persistent_nodes=0) as s:
         s.setup(p)
         for eps in (1e-6, 1e-6, 1e-6, 1e-10):                 # the last one falls short
             infos = s.solve(eps, extrapolate=True)
             assert all(i["status"] == ecmg.OK for i in infos)
             assert np.array_equal(s.get(L, ecmg.VEC_UTILDE), ref[eps]), eps
+            assert np.array_equal(s.get(L, ecmg.VEC_U), refu[eps]), eps
+        s.solve(1e-10, extrapolate=True)
+        assert s.norms(L, ecmg.VEC_U) == refn                 # norms apply the pending update first
+        s.solve(1e-10, extrapolate=True)
+        s.jcg(L, 1e-12)                                        # so does a JCG continuation
+        assert np.array_equal(s.get(L, ecmg.VEC_U), refj)
+        s.solve(1e-10, extrapolate=True)
+        assert np.array_equal(s.extrapolate(L), ref[1e-10])
