@@ -176,11 +176,11 @@ typedef struct {
                                   pass per level) and report it as info.rre_true; 0
                                   (default): rre_true = -1                              */
     int32_t batch_graph;       /* ecmg_solve_batch (options of ctxs[0]): 1 (default) =
-                                  capture the batched cascade's launch sequence into a
-                                  HIP graph on the first solve of a set of boxes and
-                                  tolerance and replay it on later ones (launch by
-                                  launch if the runtime cannot capture it); 0 = launch
-                                  by launch.  Same results either way                  */
+                                  the whole batched cascade as one launch, captured
+                                  into a HIP graph on the first solve of a set of boxes
+                                  and tolerance and replayed on later ones (level by
+                                  level if the runtime cannot capture it); 0 = level by
+                                  level, launch by launch.  Same results either way    */
     /* Device allocator hook (NULL = hipMalloc / hipFree).  alloc returns `bytes` of
      * device memory usable on hip_stream (the library's stream; hipStream_t as
      * void*), or NULL on failure (ECMG_ENOMEM); free releases a pointer alloc
@@ -281,16 +281,21 @@ int ecmg_tolerance_schedule(int32_t levels, double eps_finest, double ratio, dou
 int ecmg_extrapolate(ecmg_ctx *ctx, int32_t level, double *host_out);
 
 /* Algorithm 4 for n independent problems at once (each context set up with
- * its own problem, all on one device, none repeated).  Level by level over all
- * contexts: DSOLVE / EXP_finite per box, then the JCG of every box on that
- * level in one launch, one workgroup per box, boxes with more nodes first.
- * The whole sequence is enqueued at once and the call waits once; with
- * options.batch_graph (of ctxs[0]) it is captured into a HIP graph on the first
- * call for a set of contexts and rel_tol and replayed by later calls (a new
- * setup, tuning or tolerance captures again).
- * Per box the arithmetic is that of ecmg_solve with the persistent kernel on a
- * single workgroup, so a box's result does not depend on the other boxes of
- * the batch (it equals a batch of that box alone bit for bit).  Work runs on
+ * its own problem, all on one device, none repeated).  With options.batch_graph
+ * (of ctxs[0], the default) the whole cascade of every box is one cooperative
+ * launch of the queue kernel: each box's level is a task (DSOLVE levels from
+ * zero, finer levels building their x = W by EXP_finite first) that waits for
+ * the box's coarser levels to finish, so boxes move through their levels
+ * independently; that launch is captured into a HIP graph on the first call for
+ * a set of contexts and rel_tol and replayed by later calls (a new setup,
+ * tuning or tolerance captures again).  Without it (or if the runtime cannot
+ * capture), level by level: EXP_finite of every box, then the JCG of every box
+ * on that level in one launch, with per-level device times.  Either way a
+ * box's level runs on a few workgroups (about options' batched nodes per
+ * workgroup), boxes with more nodes first, and the call waits once.
+ * Per box the arithmetic is that of ecmg_solve with the persistent kernel, so
+ * a box's result does not depend on the other boxes of the batch or on the
+ * launch form (it equals a batch of that box alone bit for bit).  Work runs on
  * ctxs[0]'s stream (the other contexts' streams are synchronised first).
  * infos: NULL, or sum(levels of ctxs[i]) entries, box after box in input
  * order.  FP64 only (options.precision is ignored).  Returns ECMG_ENOTCONV /

@@ -1789,9 +1789,16 @@ struct BatchPlan {
     int n = 0, maxlev = 0;
     std::vector<Lv> lv;
     PersistentTask *d_tasks = nullptr;
+    // the whole cascade as one launch of the queue kernel: every level's tasks
+    // in level order (global work items), each box's level-l task (l >= 2)
+    // waiting for its levels l-1 and l-2 and building its own x = W
+    PersistentTask *d_tasks1 = nullptr;
+    int items1 = 0, nwg1 = 0;
     JcgScalars *d_sc = nullptr;
     JcgScalars *h_sc = nullptr;                  // pinned
-    unsigned *d_bar = nullptr;                   // per level: 32 words per box, then 16 words of queue counter
+    unsigned *d_bar = nullptr;                   // per level: 32 words per box (error flag 0, done
+                                                 // flag 8, counter 16), then 16 words of queue
+                                                 // counter; at the end the single launch's counter
     ExpTask *d_exp = nullptr;
     size_t nsc = 0, nbar = 0;
     std::vector<hipEvent_t> ev;                  // level boundaries
@@ -1817,6 +1824,7 @@ static void batch_plan_free(ecmg_ctx *c0, BatchPlan *P) {
     if (P->exec) (void)hipGraphExecDestroy(P->exec);
     if (P->graph) (void)hipGraphDestroy(P->graph);
     dfree(c0, P->d_tasks);
+    dfree(c0, P->d_tasks1);
     dfree(c0, P->d_sc);
     dfree(c0, P->d_bar);
     dfree(c0, P->d_exp);
@@ -1895,11 +1903,12 @@ static int batch_plan_build(ecmg_ctx *c0, ecmg_ctx *const *ctxs, int n, double r
         nbar += 32 * (size_t)V.nt + 16;
     }
     P->nsc = all_tasks.size();
-    P->nbar = nbar;
+    P->nbar = nbar + 16;                         // + the single launch's queue counter
     int rc = ECMG_OK;
     if ((rc = dalloc(c0, (void **)&P->d_tasks, sizeof(PersistentTask) * std::max<size_t>(1, P->nsc))) != ECMG_OK ||
+        (rc = dalloc(c0, (void **)&P->d_tasks1, sizeof(PersistentTask) * std::max<size_t>(1, P->nsc))) != ECMG_OK ||
         (rc = dalloc(c0, (void **)&P->d_sc, sizeof(JcgScalars) * std::max<size_t>(1, P->nsc))) != ECMG_OK ||
-        (rc = dalloc(c0, (void **)&P->d_bar, sizeof(unsigned) * std::max<size_t>(1, nbar))) != ECMG_OK ||
+        (rc = dalloc(c0, (void **)&P->d_bar, sizeof(unsigned) * P->nbar)) != ECMG_OK ||
         (rc = dalloc(c0, (void **)&P->d_exp, sizeof(ExpTask) * std::max<size_t>(1, all_exp.size()))) != ECMG_OK) {
         batch_plan_free(c0, P);
         return rc;
@@ -1920,6 +1929,41 @@ static int batch_plan_build(ecmg_ctx *c0, ecmg_ctx *const *ctxs, int n, double r
             t.bar = P->d_bar + V.bar_off + 32 * (size_t)k + 16;
         }
     }
+    // the single launch's tasks: global work items, dependencies on the box's
+    // two coarser levels (their done flags), EXP_finite inside the task
+    std::vector<PersistentTask> one(all_tasks);
+    {
+        std::vector<std::vector<int>> slot(P->maxlev, std::vector<int>(n, -1));   // (level, box) -> task
+        std::vector<std::vector<int>> exi(P->maxlev, std::vector<int>(n, -1));    // (level, box) -> ExpTask
+        for (int l = 0; l < P->maxlev; ++l) {
+            const BatchPlan::Lv &V = P->lv[l];
+            for (int k = 0; k < V.nt; ++k) slot[l][V.owner[k]] = k;
+            int e = 0;
+            for (int i = 0; i < n; ++i)
+                if (l >= 2 && l < ctxs[i]->nlev) exi[l][i] = e++;
+        }
+        int base = 0;
+        for (int l = 0; l < P->maxlev; ++l) {
+            const BatchPlan::Lv &V = P->lv[l];
+            for (int k = 0; k < V.nt; ++k) {
+                PersistentTask &t = one[V.task_off + k];
+                const int i = V.owner[k];
+                t.wg0 += base;
+                t.flag = P->d_bar + V.bar_off + 32 * (size_t)k + 8;
+                // a box's levels share its context's JCG scratch (r, q, p), so
+                // they run in order: level 1 after level 0, level l >= 2 after
+                // l-1 and l-2 (whose solutions its EXP_finite reads)
+                for (int d = 0; d < 2 && l - 1 - d >= 0; ++d) {
+                    const BatchPlan::Lv &U = P->lv[l - 1 - d];
+                    t.dep[d] = P->d_bar + U.bar_off + 32 * (size_t)slot[l - 1 - d][i] + 8;
+                }
+                if (l >= 2) t.exp = P->d_exp + V.exp_off + exi[l][i];
+            }
+            base += V.items;
+        }
+        P->items1 = base;
+        P->nwg1 = std::max(1, std::min(base, c0->queue_blocks));
+    }
     for (int l = 0; l <= P->maxlev; ++l) {
         hipEvent_t e;
         if (hipEventCreate(&e) != hipSuccess) {
@@ -1930,6 +1974,8 @@ static int batch_plan_build(ecmg_ctx *c0, ecmg_ctx *const *ctxs, int n, double r
     }
     hipStream_t s = c0->stream;
     if (hipMemcpyAsync(P->d_tasks, all_tasks.data(), sizeof(PersistentTask) * P->nsc, hipMemcpyHostToDevice, s) !=
+            hipSuccess ||
+        hipMemcpyAsync(P->d_tasks1, one.data(), sizeof(PersistentTask) * P->nsc, hipMemcpyHostToDevice, s) !=
             hipSuccess ||
         (!all_exp.empty() &&
          hipMemcpyAsync(P->d_exp, all_exp.data(), sizeof(ExpTask) * all_exp.size(), hipMemcpyHostToDevice, s) !=
@@ -1944,8 +1990,20 @@ static int batch_plan_build(ecmg_ctx *c0, ecmg_ctx *const *ctxs, int n, double r
 
 // The plan's launch sequence on stream s (eager: the cooperative launch
 // interface; under capture: the launch-attribute one, recorded as a kernel node
-// with the cooperative attribute).
-static int batch_enqueue(ecmg_ctx *c0, BatchPlan *P, hipStream_t s, bool eager) {
+// with the cooperative attribute).  single: the whole cascade as one launch of
+// the queue kernel; else level by level (EXP_finite of every box, then the
+// queue kernel over the level's tasks), with an event after each level when
+// the plan is timed.
+static int batch_enqueue(ecmg_ctx *c0, BatchPlan *P, hipStream_t s, bool eager, bool single) {
+    if (single) {
+        launch_zero_u32(P->d_bar, (int64_t)P->nbar, s);        // barrier words, flags, queue counters
+        HIPCHK(c0, hipGetLastError());
+        unsigned *next = P->d_bar + P->nbar - 16;
+        HIPCHK(c0, eager ? launch_jcg_queue(P->d_tasks1, (int)P->nsc, P->items1, P->nwg1, next, s)
+                         : launch_jcg_queue_attr(P->d_tasks1, (int)P->nsc, P->items1, P->nwg1, next, s));
+        HIPCHK(c0, hipMemcpyAsync(P->h_sc, P->d_sc, sizeof(JcgScalars) * P->nsc, hipMemcpyDeviceToHost, s));
+        return ECMG_OK;
+    }
     for (int l = 0; l < P->maxlev; ++l) {
         const BatchPlan::Lv &V = P->lv[l];
         unsigned *bar = P->d_bar + V.bar_off;
@@ -1968,7 +2026,7 @@ static int batch_enqueue(ecmg_ctx *c0, BatchPlan *P, hipStream_t s, bool eager) 
 static int batch_plan_capture(ecmg_ctx *c0, BatchPlan *P, hipStream_t s) {
     P->timed = false;
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
-        const int rc = batch_enqueue(c0, P, s, false);
+        const int rc = batch_enqueue(c0, P, s, false, true);
         hipGraph_t g = nullptr;
         const hipError_t e = hipStreamEndCapture(s, &g);
         if (rc == ECMG_OK && e == hipSuccess && g) {
@@ -2026,7 +2084,7 @@ int ecmg_solve_batch(ecmg_ctx *const *ctxs, int32_t n, double rel_tol, ecmg_leve
     HIPCHK(c0, hipEventRecord(P->ev[0], s));
     if (c0->opt.batch_graph && P->graph_state == 0) CHK(batch_plan_capture(c0, P, s));
     if (P->graph_state == 1) HIPCHK(c0, hipGraphLaunch(P->exec, s));
-    else CHK(batch_enqueue(c0, P, s, true));
+    else CHK(batch_enqueue(c0, P, s, true, false));
     HIPCHK(c0, hipStreamSynchronize(s));
     int worst = ECMG_OK;
     for (int l = 0; l < P->maxlev; ++l) {

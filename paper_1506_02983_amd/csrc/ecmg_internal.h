@@ -207,6 +207,7 @@ int launch_col(int mode, const ColArgs &a, hipStream_t s);
 
 // One independent JCG solve inside the persistent kernel: a grid, its arrays,
 // its stop control, and the contiguous range of workgroups that works on it.
+struct ExpTask;
 struct PersistentTask {
     Geom g;
     const double *beta;
@@ -224,6 +225,13 @@ struct PersistentTask {
     int wg0, nwg;
     int seglen;                       // z-march length: the nodes of a column are cut into segments
     int zero_x;                       // 1: start from x = 0 on free nodes (DSOLVE), keep g_D
+    // the whole batched cascade in one launch: wait until the tasks of the
+    // box's coarser levels (one or two) have set their flags, build x = W by
+    // EXP_finite (exp non-NULL), solve, then set this task's flag (all NULL
+    // otherwise)
+    const unsigned *dep[2];
+    const ExpTask *exp;
+    unsigned *flag;
 };
 
 // Modes of the tiled stencil kernel.

@@ -22,6 +22,7 @@
 // Waits are bounded: a barrier that does not complete within a spin budget
 // sets the task's error flag and every workgroup leaves the loop.
 #include "ecmg_internal.h"
+#include "exp_finite.h"
 
 #include <cmath>
 
@@ -65,6 +66,28 @@ __device__ __forceinline__ void task_barrier(const PersistentTask &t, int nwg, u
                 *s_err = 1;
                 __hip_atomic_store(t.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 break;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+}
+
+// Wait until the flags of the tasks this one depends on are set (bounded: the
+// error flag instead of a hang), then acquire what those tasks wrote.
+__device__ __forceinline__ void wait_deps(const PersistentTask &t, int *s_err) {
+    if (threadIdx.x == 0) {
+        for (int d = 0; d < 2; ++d) {
+            if (!t.dep[d]) continue;
+            long n = 0;
+            while (__hip_atomic_load(t.dep[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+                __builtin_amdgcn_s_sleep(2);
+                if ((++n & 63) == 0 &&
+                    (n > SPIN_LIMIT || __hip_atomic_load(t.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+                    *s_err = 1;
+                    __hip_atomic_store(t.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -336,6 +359,14 @@ __device__ __forceinline__ void jcg_task(const PersistentTask &t, int w, int nwg
     // own-node loops over a segment: loads of all its nodes first
 #define FOR_SEG(kk) _Pragma("unroll") for (int kk = 0; kk < SEG; ++kk)
     unsigned gen = 0;                  // barriers passed by this workgroup
+    if (t.dep[0] || t.dep[1]) wait_deps(t, &s_err);
+    if (t.exp && !s_err) {             // x = W from the box's two coarser levels
+        const ExpTask &e = *t.exp;
+        const int64_t ne = (int64_t)(e.gf.nx / 4) * (e.gf.ny / 4) * (e.gf.nz / 4);
+        for (int64_t k = (int64_t)w * NTP + threadIdx.x; k < ne; k += (int64_t)nwg * NTP)
+            exp_finite_elem<false>(e.gf, e.g1, e.U1, e.U0, e.x, e.W, e.variant, k, nullptr);
+        task_barrier(t, nwg, ++gen, &s_err);
+    }
     if (t.zero_x) {                    // x = 0 on free nodes, g_D stays on Dirichlet nodes
         FOR_UNITS({
             FOR_SEG(kk) {
@@ -454,6 +485,12 @@ __device__ __forceinline__ void jcg_task(const PersistentTask &t, int w, int nwg
         sc->done = s_err ? DONE_BREAKDOWN : done;
         sc->pending = 0;
         sc->tol = t.tol;
+    }
+    if (t.flag) {
+        // every workgroup's x is written (barrier), then the flag, released:
+        // set whatever happened, so no dependent task waits in vain
+        task_barrier(t, nwg, ++gen, &s_err);
+        if (w == 0 && threadIdx.x == 0) __hip_atomic_store(t.flag, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();                   // LDS is reused by the next task of this workgroup
 }
