@@ -152,3 +152,34 @@ def test_batch_graph_replay_matches_launch_by_launch(ecmg, boxes):
         assert all(ms == -1.0 for box in g[k][2] for ms in box), g[k][2]      # the graph ran
     # a replayed solve repeats the first one exactly
     assert g[0][0] == g[1][0] and all(np.array_equal(a, b) for a, b in zip(g[0][1], g[1][1]))
+
+
+def test_batch_uneven_level_counts_single_launch(ecmg):
+    """Boxes with 3 and 4 levels and Robin faces in one batch: the single
+    launch (every box level a dependent task) equals the level-by-level form
+    bit for bit, and each box matches the single-problem solver (same counts,
+    1e-12 relative)."""
+    rng = np.random.default_rng(11)
+    probs = [workloads.serving_request(n, rng.uniform(0, 1, 3), rng.uniform(1, 3, 3), rng.integers(0, 2, 6))
+             for n in (32, 64, 32, 64, 64, 32)]
+
+    def run(graph):
+        solvers = [ecmg.Solver(dsolve_dense_max=0, batch_graph=graph).setup(p) for p in probs]
+        infos = ecmg.solve_batch(solvers, 1e-8)
+        ecmg.extrapolate_batch(solvers)
+        out = [(s.get(p.levels - 1, ecmg.VEC_U), s.get(p.levels - 1, ecmg.VEC_UTILDE)) for s, p in
+               zip(solvers, probs)]
+        for s in solvers:
+            s.close()
+        return infos, out
+
+    ig, og = run(True)
+    ie, oe = run(False)
+    for i, p in enumerate(probs):
+        assert [x["iters"] for x in ig[i]] == [x["iters"] for x in ie[i]], i
+        assert np.array_equal(og[i][0], oe[i][0]) and np.array_equal(og[i][1], oe[i][1]), i
+        with ecmg.Solver() as s:
+            s.setup(p)
+            ref = s.solve(1e-8)
+            assert [x["iters"] for x in ref[2:]] == [x["iters"] for x in ig[i][2:]], i
+            assert _rel(og[i][0], s.get(p.levels - 1, ecmg.VEC_U)) <= 1e-12, i
