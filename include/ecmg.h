@@ -181,6 +181,14 @@ typedef struct {
                                   and tolerance and replayed on later ones (level by
                                   level if the runtime cannot capture it); 0 = level by
                                   level, launch by launch.  Same results either way    */
+    int32_t columns;           /* JCG levels that run one-block finishing kernels (those
+                                  above fold_blocks): 1 (default) = JCG init and the
+                                  stencil of pass A by the column kernels (a wavefront
+                                  marches a column of nodes with its planes in
+                                  registers), pass A of iterations >= 1 as a node-wise
+                                  p / x update followed by that stencil; 0 = the tiled
+                                  kernels (LDS plane tiles, pass A fused).  The same
+                                  recurrence; only the summation order differs         */
     /* Device allocator hook (NULL = hipMalloc / hipFree).  alloc returns `bytes` of
      * device memory usable on hip_stream (the library's stream; hipStream_t as
      * void*), or NULL on failure (ECMG_ENOMEM); free releases a pointer alloc
@@ -436,7 +444,9 @@ int ecmg_plan_bytes(const ecmg_problem *problem, int32_t precision, size_t *byte
  * persistent JCG used for small grids, 8 = mixed-precision start (r / ||r||
  * to FP32), 9 = mixed-precision update x += ||r|| d, 10 = JCG pass A of
  * iteration 0, which reads the p_0 that init stored; class 0 counts the later
- * iterations),
+ * iterations, 11 = JCG pass A of iterations >= 1 on the levels that run the
+ * column kernels: the node-wise p and x update, then the column stencil,
+ * timed from the start of the first kernel to the end of the second),
  * out[0] = total milliseconds and out[1] = launches that did work since the
  * last ecmg_reset_kernel_times.  Measured with HIP events on the library's
  * stream around each launch; both calls wait for the stream to finish the

@@ -64,7 +64,7 @@ class Options(ctypes.Structure):
                 ("persistent_nodes", ctypes.c_int64), ("dsolve_dense_max", ctypes.c_int64),
                 ("autotune", ctypes.c_int32), ("tune_cache", ctypes.c_char_p), ("method", ctypes.c_int32),
                 ("speculate", ctypes.c_int32), ("fold_blocks", ctypes.c_int32), ("true_residual", ctypes.c_int32),
-                ("batch_graph", ctypes.c_int32),
+                ("batch_graph", ctypes.c_int32), ("columns", ctypes.c_int32),
                 ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_user", ctypes.c_void_p)]
 
 
@@ -346,7 +346,7 @@ class Solver:
                  chunk: int = 0, timing: bool = False, stream=None, persistent_nodes: int = -1,
                  dsolve_dense_max: Optional[int] = None, autotune: int = 0, tune_cache: Optional[str] = None,
                  method: int = JCG, speculate: bool = True, fold_blocks: int = -1, true_residual: bool = False,
-                 batch_graph: bool = True, torch_allocator: bool = False):
+                 batch_graph: bool = True, columns: bool = True, torch_allocator: bool = False):
         self.L = load_library()
         o = Options()
         self.L.ecmg_default_options(ctypes.byref(o))
@@ -363,6 +363,7 @@ class Solver:
         o.fold_blocks = int(fold_blocks)
         o.true_residual = int(true_residual)
         o.batch_graph = int(batch_graph)
+        o.columns = int(columns)
         self._hooks = None
         if torch_allocator:
             self._hooks = _torch_allocator_hooks()

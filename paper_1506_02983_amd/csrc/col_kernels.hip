@@ -1,5 +1,6 @@
 // Column stencil kernels for the large JCG levels (gfx950): operator apply,
-// JCG initialisation and pass A of iteration 0, each a matrix-free 27-point
+// JCG initialisation and the stencil part of pass A (q = A p, p.q; at
+// iterations >= 1 after the node-wise p update), each a matrix-free 27-point
 // apply of the Q1 operator with one beta per element (Section 2), without LDS
 // and without block barriers.
 //
@@ -148,7 +149,8 @@ __device__ __forceinline__ void col_row(const Geom &g, int r, const double (&L)[
 // element holding such a neighbour lies outside the grid and carries beta = 0,
 // so its weight is 0.
 template <int MODE, int R, int D>
-__device__ __forceinline__ void col_step(const ColArgs &a, int i, int j0, int k, int k1, bool out_lane,
+__device__ __forceinline__ void col_step(const ColArgs &a, const double *__restrict__ vin, int i, int j0, int k,
+                                         int k1, bool out_lane,
                                          bool ieok, bool dir_i, bool rob_i, double (&Pm)[R + 2], double (&P0)[R + 2],
                                          double (&Pp)[R + 2],
                                          double (&Pn)[R + 2], double (&Bl)[R + 1], double (&Bu)[R + 1],
@@ -164,7 +166,7 @@ __device__ __forceinline__ void col_step(const ColArgs &a, int i, int j0, int k,
 #pragma unroll
         for (int r = 0; r < R + 2; ++r) {
             const int jj = j0 - 1 + r;
-            Pn[r] = a.v[ic + sx * min(max(jj, 0), g.ny) + sxy * min(kp, g.nz)];
+            Pn[r] = vin[ic + sx * min(max(jj, 0), g.ny) + sxy * min(kp, g.nz)];
         }
 #pragma unroll
         for (int r = 0; r < R + 1; ++r) {
@@ -193,7 +195,7 @@ __device__ __forceinline__ void col_step(const ColArgs &a, int i, int j0, int k,
     for (int r = 0; r < R; ++r) {
         const int j = j0 + r;
         const double q = qc[r] + from_left(tr[r]) + from_right(tl[r]);
-        // nodes on a Robin face (and on no Dirichlet face) are the face kernel's
+        // nodes on a Robin face (and on no Dirichlet face) are the face blocks'
         const bool dir = dir_i || (j == 0 && g.ft[2] == ECMG_DIRICHLET) || (j == g.ny && g.ft[3] == ECMG_DIRICHLET) ||
                          dir_k;
         const bool rob = rob_i || (j == 0 && g.ft[2] == ECMG_ROBIN) || (j == g.ny && g.ft[3] == ECMG_ROBIN) || rob_k;
@@ -226,121 +228,19 @@ __device__ __forceinline__ void col_step(const ColArgs &a, int i, int j0, int k,
     }
 }
 
-// WPE: waves per SIMD the register budget is set for (init, 2 rows: 150
-// VGPRs, 3 waves fit; iteration 0, 4 rows: about 200 VGPRs, 2 waves); D:
-// prefetch distance in z-steps
-template <int MODE, int R, int WPE, int D>
-__global__ void __launch_bounds__(256, WPE) k_col(const ColArgs a) {
-    constexpr int NR = D + 3;
-    const Geom &g = a.g;
-    if (MODE == MODE_PASSA0 && a.sc->done) return;      // uniform over the grid
-    const int lane = threadIdx.x & 63;
-    const int wid = blockIdx.x * 4 + (threadIdx.x >> 6);     // partial slot
-    const int total = a.ntx * a.nty * a.nkz;
-    int tx, ty, tz;
-    if (a.order == 0) {
-        // consecutive waves take consecutive x-segments of the same rows
-        tx = wid % a.ntx;
-        const int t2 = wid / a.ntx;
-        ty = t2 % a.nty;
-        tz = t2 / a.nty;
-    } else {
-        // the 4 waves of a block take 4 consecutive row groups of one x-segment,
-        // so the y-halo rows they share are fetched once into the CU's caches;
-        // order 2 also gives each XCD a contiguous range of blocks (blocks are
-        // dispatched round-robin over the XCDs), so the halo rows between
-        // neighbouring blocks are shared through that XCD's L2
-        const int b = a.order == 2 ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
-        const int nty4 = a.nty >> 2;
-        tx = b % a.ntx;
-        const int t2 = b / a.ntx;
-        ty = 4 * (t2 % nty4) + (threadIdx.x >> 6);
-        tz = t2 / nty4;
-    }
-    double acc0 = 0.0, acc1 = 0.0;
-    if (wid < total) {
-        const int i = 62 * tx - 1 + lane;
-        const int j0 = ty * R;
-        const int k0 = tz * a.KZ, k1 = min(k0 + a.KZ, g.nz + 1);
-        const bool iok = i >= 0 && i <= g.nx, ieok = i >= 0 && i < g.nx;
-        const bool out_lane = lane >= 1 && lane <= 62 && iok;
-        const int sx = g.sx, sxy = g.sx * g.sy, exy = g.nx * g.ny;
-        const int ic = min(max(i, 0), g.nx), ie = min(max(i, 0), g.nx - 1);
-        ColRegs<R, NR> S;
-        // prologue: planes k0-1 .. k0+D, layers k0-1 .. k0+D-1, epilogue of
-        // planes k0 .. k0+D-1
-#pragma unroll
-        for (int c = 0; c < D + 2; ++c) {
-            const int kk = k0 - 1 + c;
-#pragma unroll
-            for (int r = 0; r < R + 2; ++r) {
-                const int jj = j0 - 1 + r;
-                S.P[c][r] = a.v[ic + sx * min(max(jj, 0), g.ny) + sxy * min(max(kk, 0), g.nz)];
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < D + 1; ++c) {
-            const int kk = k0 - 1 + c;
-#pragma unroll
-            for (int r = 0; r < R + 1; ++r) {
-                const int jj = j0 - 1 + r;
-                const bool ok = ieok && jj >= 0 && jj < g.ny && kk >= 0 && kk < g.nz && kk < k1;
-                const double v = a.beta[ie + g.nx * min(max(jj, 0), g.ny - 1) + exy * min(max(kk, 0), g.nz - 1)];
-                S.B[c][r] = ok ? v : 0.0;
-            }
-        }
-        if (MODE == MODE_INIT) {
-#pragma unroll
-            for (int c = 0; c < D; ++c)
-#pragma unroll
-                for (int r = 0; r < R; ++r)
-                    S.E[c][r] = a.F[ic + sx * min(j0 + r, g.ny) + sxy * min(k0 + c, g.nz)];
-        }
-        const bool dir_i = (i == 0 && g.ft[0] == ECMG_DIRICHLET) || (i == g.nx && g.ft[1] == ECMG_DIRICHLET);
-        const bool rob_i = (i == 0 && g.ft[0] == ECMG_ROBIN) || (i == g.nx && g.ft[1] == ECMG_ROBIN);
-        // step s of a pass of NR steps: planes in slots s, s+1, s+2, the load
-        // into s+2+D; layers in s, s+1, the load into s+1+D; epilogue in s,
-        // the load into s+D (all mod NR)
-        int k = k0;
-        for (; k + NR - 1 < k1; k += NR) {
-#pragma unroll
-            for (int t = 0; t < NR; ++t)
-                col_step<MODE, R, D>(a, i, j0, k + t, k1, out_lane, ieok, dir_i, rob_i, S.P[t % NR],
-                                     S.P[(t + 1) % NR], S.P[(t + 2) % NR], S.P[(t + 2 + D) % NR], S.B[t % NR],
-                                     S.B[(t + 1) % NR], S.B[(t + 1 + D) % NR], S.E[t % NR], S.E[(t + D) % NR], acc0,
-                                     acc1);
-        }
-#pragma unroll
-        for (int t = 0; t < NR - 1; ++t)
-            if (k + t < k1)
-                col_step<MODE, R, D>(a, i, j0, k + t, k1, out_lane, ieok, dir_i, rob_i, S.P[t % NR],
-                                     S.P[(t + 1) % NR], S.P[(t + 2) % NR], S.P[(t + 2 + D) % NR], S.B[t % NR],
-                                     S.B[(t + 1) % NR], S.B[(t + 1 + D) % NR], S.E[t % NR], S.E[(t + D) % NR], acc0,
-                                     acc1);
-    }
-    if (MODE == MODE_APPLY || wid >= total) return;
-    // wave partials in lane order (fixed), one pair per wave
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        acc0 += __shfl_xor(acc0, off, 64);
-        acc1 += __shfl_xor(acc1, off, 64);
-    }
-    if (lane == 0) {
-        a.partials[2 * (int64_t)wid] = acc0;
-        if (MODE == MODE_INIT) a.partials[2 * (int64_t)wid + 1] = acc1;
-    }
-}
-
 // The nodes on a Robin face (and on no Dirichlet face), which the column
-// kernel leaves out: each is taken by the first Robin face (in face order) that
+// waves leave out: each is taken by the first Robin face (in face order) that
 // holds it, one thread per node, with its full row -- the 27-point stencil read
 // from global memory plus the face-mass terms of every Robin face it lies on --
-// and the column kernel's epilogue; block partials follow the waves' partials.
+// and the column epilogue.  These blocks follow the column blocks in the same
+// launch; block partials follow the waves' partials (part_off of them).
 template <int MODE>
-__global__ void __launch_bounds__(256) k_col_face(const ColArgs a, const ColFaces fl, int part_off) {
+__device__ __forceinline__ void col_face_block(const ColArgs &a, const double *__restrict__ vin, int bid,
+                                               int part_off) {
     const Geom &g = a.g;
+    const ColFaces &fl = a.fl;
     __shared__ double red[2][4];
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = (int64_t)bid * 256 + threadIdx.x;
     double acc0 = 0.0, acc1 = 0.0;
     if (t < fl.start[fl.nf]) {
         int s = 0;
@@ -361,7 +261,7 @@ __global__ void __launch_bounds__(256) k_col_face(const ColArgs a, const ColFace
             const int sx = g.sx, sxy = g.sx * g.sy;
             auto v = [&](int ii, int jj, int kk) -> double {
                 if (ii < 0 || ii > g.nx || jj < 0 || jj > g.ny || kk < 0 || kk > g.nz) return 0.0;
-                return a.v[ii + sx * jj + sxy * kk];
+                return vin[ii + sx * jj + sxy * kk];
             };
             auto be = [&](int ii, int jj, int kk) -> double {
                 if (ii < 0 || ii >= g.nx || jj < 0 || jj >= g.ny || kk < 0 || kk >= g.nz) return 0.0;
@@ -411,7 +311,7 @@ __global__ void __launch_bounds__(256) k_col_face(const ColArgs a, const ColFace
                 acc1 += rv * rv;
             } else {
                 __builtin_nontemporal_store(q, a.out + id);
-                acc0 += a.v[id] * q;
+                acc0 += vin[id] * q;
             }
         }
     }
@@ -429,9 +329,121 @@ __global__ void __launch_bounds__(256) k_col_face(const ColArgs a, const ColFace
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        a.partials[2 * ((int64_t)part_off + blockIdx.x)] = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
+        a.partials[2 * ((int64_t)part_off + bid)] = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
         if (MODE == MODE_INIT)
-            a.partials[2 * ((int64_t)part_off + blockIdx.x) + 1] = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
+            a.partials[2 * ((int64_t)part_off + bid) + 1] = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
+    }
+}
+
+// WPE: waves per SIMD the register budget is set for (init, 2 rows: 150
+// VGPRs, 3 waves fit; iteration 0, 4 rows: about 200 VGPRs, 2 waves); D:
+// prefetch distance in z-steps
+template <int MODE, int R, int WPE, int D>
+__global__ void __launch_bounds__(256, WPE) k_col(const ColArgs a) {
+    constexpr int NR = D + 3;
+    const Geom &g = a.g;
+    if (MODE == MODE_PASSA0 && a.sc->done) return;      // uniform over the grid
+    // iterations >= 1 alternate the direction buffers (the iteration's parity)
+    const double *__restrict__ vin = (MODE == MODE_PASSA0 && a.v_odd && (a.sc->iter & 1)) ? a.v_odd : a.v;
+    if ((int)blockIdx.x >= a.ncb) {               // the Robin-face blocks (uniform per block)
+        col_face_block<MODE>(a, vin, (int)blockIdx.x - a.ncb, a.ntx * a.nty * a.nkz);
+        return;
+    }
+    const int cb = blockIdx.x;                    // column block
+    const int lane = threadIdx.x & 63;
+    const int wid = cb * 4 + (threadIdx.x >> 6);             // partial slot
+    const int total = a.ntx * a.nty * a.nkz;
+    int tx, ty, tz;
+    if (a.order == 0) {
+        // consecutive waves take consecutive x-segments of the same rows
+        tx = wid % a.ntx;
+        const int t2 = wid / a.ntx;
+        ty = t2 % a.nty;
+        tz = t2 / a.nty;
+    } else {
+        // the 4 waves of a block take 4 consecutive row groups of one x-segment,
+        // so the y-halo rows they share are fetched once into the CU's caches;
+        // order 2 also gives each XCD a contiguous range of blocks (blocks are
+        // dispatched round-robin over the XCDs), so the halo rows between
+        // neighbouring blocks are shared through that XCD's L2
+        const int b = a.order == 2 ? xcd_block(cb, a.ncb) : cb;
+        const int nty4 = a.nty >> 2;
+        tx = b % a.ntx;
+        const int t2 = b / a.ntx;
+        ty = 4 * (t2 % nty4) + (threadIdx.x >> 6);
+        tz = t2 / nty4;
+    }
+    double acc0 = 0.0, acc1 = 0.0;
+    if (wid < total) {
+        const int i = 62 * tx - 1 + lane;
+        const int j0 = ty * R;
+        const int k0 = tz * a.KZ, k1 = min(k0 + a.KZ, g.nz + 1);
+        const bool iok = i >= 0 && i <= g.nx, ieok = i >= 0 && i < g.nx;
+        const bool out_lane = lane >= 1 && lane <= 62 && iok;
+        const int sx = g.sx, sxy = g.sx * g.sy, exy = g.nx * g.ny;
+        const int ic = min(max(i, 0), g.nx), ie = min(max(i, 0), g.nx - 1);
+        ColRegs<R, NR> S;
+        // prologue: planes k0-1 .. k0+D, layers k0-1 .. k0+D-1, epilogue of
+        // planes k0 .. k0+D-1
+#pragma unroll
+        for (int c = 0; c < D + 2; ++c) {
+            const int kk = k0 - 1 + c;
+#pragma unroll
+            for (int r = 0; r < R + 2; ++r) {
+                const int jj = j0 - 1 + r;
+                S.P[c][r] = vin[ic + sx * min(max(jj, 0), g.ny) + sxy * min(max(kk, 0), g.nz)];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < D + 1; ++c) {
+            const int kk = k0 - 1 + c;
+#pragma unroll
+            for (int r = 0; r < R + 1; ++r) {
+                const int jj = j0 - 1 + r;
+                const bool ok = ieok && jj >= 0 && jj < g.ny && kk >= 0 && kk < g.nz && kk < k1;
+                const double v = a.beta[ie + g.nx * min(max(jj, 0), g.ny - 1) + exy * min(max(kk, 0), g.nz - 1)];
+                S.B[c][r] = ok ? v : 0.0;
+            }
+        }
+        if (MODE == MODE_INIT) {
+#pragma unroll
+            for (int c = 0; c < D; ++c)
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    S.E[c][r] = a.F[ic + sx * min(j0 + r, g.ny) + sxy * min(k0 + c, g.nz)];
+        }
+        const bool dir_i = (i == 0 && g.ft[0] == ECMG_DIRICHLET) || (i == g.nx && g.ft[1] == ECMG_DIRICHLET);
+        const bool rob_i = (i == 0 && g.ft[0] == ECMG_ROBIN) || (i == g.nx && g.ft[1] == ECMG_ROBIN);
+        // step s of a pass of NR steps: planes in slots s, s+1, s+2, the load
+        // into s+2+D; layers in s, s+1, the load into s+1+D; epilogue in s,
+        // the load into s+D (all mod NR)
+        int k = k0;
+        for (; k + NR - 1 < k1; k += NR) {
+#pragma unroll
+            for (int t = 0; t < NR; ++t)
+                col_step<MODE, R, D>(a, vin, i, j0, k + t, k1, out_lane, ieok, dir_i, rob_i, S.P[t % NR],
+                                     S.P[(t + 1) % NR], S.P[(t + 2) % NR], S.P[(t + 2 + D) % NR], S.B[t % NR],
+                                     S.B[(t + 1) % NR], S.B[(t + 1 + D) % NR], S.E[t % NR], S.E[(t + D) % NR], acc0,
+                                     acc1);
+        }
+#pragma unroll
+        for (int t = 0; t < NR - 1; ++t)
+            if (k + t < k1)
+                col_step<MODE, R, D>(a, vin, i, j0, k + t, k1, out_lane, ieok, dir_i, rob_i, S.P[t % NR],
+                                     S.P[(t + 1) % NR], S.P[(t + 2) % NR], S.P[(t + 2 + D) % NR], S.B[t % NR],
+                                     S.B[(t + 1) % NR], S.B[(t + 1 + D) % NR], S.E[t % NR], S.E[(t + D) % NR], acc0,
+                                     acc1);
+    }
+    if (MODE == MODE_APPLY || wid >= total) return;
+    // wave partials in lane order (fixed), one pair per wave
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        acc0 += __shfl_xor(acc0, off, 64);
+        acc1 += __shfl_xor(acc1, off, 64);
+    }
+    if (lane == 0) {
+        a.partials[2 * (int64_t)wid] = acc0;
+        if (MODE == MODE_INIT) a.partials[2 * (int64_t)wid + 1] = acc1;
     }
 }
 
@@ -467,19 +479,17 @@ int launch_col(int mode, const ColArgs &a, hipStream_t s) {
     // the wave grid (a.nty) was laid out for a.R rows per wave
     if (a.R != (mode == MODE_PASSA0 ? COL_R_A0 : COL_R_INIT)) return -1;
     const int waves = a.ntx * a.nty * a.nkz;
-    const int nb = (waves + 3) / 4;
+    ColArgs b = a;
+    b.ncb = (waves + 3) / 4;
+    const int fb = col_faces(a.g, &b.fl);
+    // the face blocks after the column blocks, where they fill the launch's
+    // tail (spread among the column blocks they ran slower)
+    const dim3 grid(b.ncb + fb);
     // one z-step of prefetch: two steps, or 4 waves per SIMD for iteration 0,
     // measured no faster on 513^3
-    if (mode == MODE_APPLY) launch_timed(k_col<MODE_APPLY, COL_R_INIT, 3, 1>, dim3(nb), dim3(256), 0, s, a);
-    else if (mode == MODE_INIT) launch_timed(k_col<MODE_INIT, COL_R_INIT, 2, 1>, dim3(nb), dim3(256), 0, s, a);
-    else launch_timed(k_col<MODE_PASSA0, COL_R_A0, 2, 1>, dim3(nb), dim3(256), 0, s, a);
-    ColFaces fl;
-    const int fb = col_faces(a.g, &fl);
-    if (fb > 0) {
-        if (mode == MODE_APPLY) hipLaunchKernelGGL(k_col_face<MODE_APPLY>, dim3(fb), dim3(256), 0, s, a, fl, waves);
-        else if (mode == MODE_INIT) hipLaunchKernelGGL(k_col_face<MODE_INIT>, dim3(fb), dim3(256), 0, s, a, fl, waves);
-        else hipLaunchKernelGGL(k_col_face<MODE_PASSA0>, dim3(fb), dim3(256), 0, s, a, fl, waves);
-    }
+    if (mode == MODE_APPLY) launch_timed(k_col<MODE_APPLY, COL_R_INIT, 3, 1>, grid, dim3(256), 0, s, b);
+    else if (mode == MODE_INIT) launch_timed(k_col<MODE_INIT, COL_R_INIT, 2, 1>, grid, dim3(256), 0, s, b);
+    else launch_timed(k_col<MODE_PASSA0, COL_R_A0, 2, 1>, grid, dim3(256), 0, s, b);
     return waves + fb;
 }
 

@@ -113,7 +113,7 @@ struct ecmg_ctx {
     int KZ = 32;
     int kz_target = 1024;                      // tiled stencil: blocks aimed for per launch
     int fold_max = FOLD_MAX_BLOCKS;            // JCG scalar steps folded into the passes up to this many blocks
-    int col_enable = 1;                        // column kernels for init / iteration 0 on unfolded levels
+    int col_enable = 1;                        // column kernels for init / pass A on unfolded levels
     int col_kz = 16;                           // planes per z-chunk of a column wave
     int col_order = 0;                         // wave order of the column kernels (col_waves)
     uint32_t timing_mask = 0;                  // kernel classes timed with HIP events (bit k = class k)
@@ -440,7 +440,8 @@ static int rec_end(ecmg_ctx *c, size_t slot) {
     ecmg_ctx::Rec &r = c->recs[slot];
     if (!r.ext) {
         HIPCHK(c, hipEventRecord(r.b, c->stream));
-    } else if (g_pending_timing.start) {         // nothing was launched: no record
+    } else if (g_pending_timing.start || g_pending_timing.stop) {
+        // nothing was launched, or a timed group without its last launch: no record
         g_pending_timing = PendingTiming{};
         r.valid = false;
     }
@@ -449,7 +450,9 @@ static int rec_end(ecmg_ctx *c, size_t slot) {
 // Fold the finished records.  A JCG pass launch (classes 0, 1, 5, 6) whose
 // iteration index is at or beyond its level's limit (the iterations the level
 // ran) found the `done` flag set and did no work; it is not counted.
-static bool rec_is_pass(int kind) { return kind == 0 || kind == 1 || kind == 5 || kind == 6 || kind == 10; }
+static bool rec_is_pass(int kind) {
+    return kind == 0 || kind == 1 || kind == 5 || kind == 6 || kind == 10 || kind == 11;
+}
 static int rec_flush_levels(ecmg_ctx *c, const std::vector<int> &limit) {
     if (c->recs.empty()) return ECMG_OK;
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -523,8 +526,15 @@ static int jcg_chunks(ecmg_ctx *c, int l, const StencilArgs<T> &a, const PassBAr
         for (int t = 0; t < chunk; ++t) {
             // iteration 0 from the p_0 init stored, when it did (its own timing class)
             const bool a0 = a.p_init && done_iters + t == 0;
-            CHK(rec_begin(c, l, a0 ? 10 : kind_a, done_iters + t, &slot));
-            if (a0 && col) {
+            CHK(rec_begin(c, l, a0 ? 10 : col ? 11 : kind_a, done_iters + t, &slot));
+            if (col) {
+                // column levels: iteration 0 reads the p_0 init stored; later
+                // iterations form p (and the x update) node-wise first, then
+                // the column stencil reads it from the buffer of the
+                // iteration's parity
+                if constexpr (std::is_same<T, double>::value) {
+                    if (!a0) launch_p_update(a.g, a.dinv, a.r, a.p0, a.p1, a.x, sc, c->stream);
+                }
                 if (launch_col(MODE_PASSA0, *col, c->stream) < 0)
                     return fail(c, ECMG_EINVAL, "column wave grid mismatch");
                 CHK(rec_end(c, slot));
@@ -711,7 +721,7 @@ static bool col_usable(const ecmg_ctx *c, const Geom &g) {
 
 // Column-kernel arguments of level L (input, output and partials set by the
 // caller); returns the partial pairs a launch writes (waves, then the blocks
-// of the Robin-face kernel).
+// of the Robin faces).
 static int col_args(ecmg_ctx *c, Level &L, int R, ColArgs *ca) {
     ColArgs &x = *ca;
     x.g = L.g;
@@ -769,8 +779,8 @@ static int enqueue_jcg(ecmg_ctx *c, int l, double tol_abs, int max_iter, int fix
         b.pq_partials = c->partials;
         b.nb_a = (int)nb_a;
     }
-    // the large (unfolded) levels: JCG init and iteration 0 of pass A by the
-    // column kernels, the later iterations by the tiled ones
+    // the large (unfolded) levels: JCG init and the stencil of every pass A by
+    // the column kernels (after the node-wise p update from iteration 1 on)
     ColArgs ca{};
     int cw = 0;
     const bool col = !fold && col_usable(c, L.g);
@@ -794,7 +804,8 @@ static int enqueue_jcg(ecmg_ctx *c, int l, double tol_abs, int max_iter, int fix
         if (launch_col(MODE_INIT, ca, c->stream) < 0) return fail(c, ECMG_EINVAL, "column wave grid mismatch");
         CHK(rec_end(c, slot));
         launch_stencil_finish(MODE_INIT, c->sc, c->partials, cw, c->stream);
-        ca0.v = c->p1;                            // iteration 0: q = A p_0
+        ca0.v = c->p1;                            // iteration 0: q = A p_0 (p_0 in p1)
+        ca0.v_odd = c->p0;                        // later: p in p1 at even, p0 at odd iterations
         ca0.out = c->q;
         ca0.p_out = nullptr;
         ca0.p_init = 0;
@@ -1028,6 +1039,7 @@ void ecmg_default_options(ecmg_options *o) {
     o->fold_blocks = -1;
     o->true_residual = 0;
     o->batch_graph = 1;
+    o->columns = 1;
     o->alloc = nullptr;
     o->free = nullptr;
     o->alloc_user = nullptr;
@@ -1081,6 +1093,7 @@ int ecmg_create(const ecmg_options *opt, ecmg_ctx **out) {
     if (const char *kz = std::getenv("ECMG_KZ")) c->KZ = std::max(1, std::atoi(kz));
     if (const char *kt = std::getenv("ECMG_KZ_TARGET")) c->kz_target = std::max(1, std::atoi(kt));
     if (o.fold_blocks >= 0) c->fold_max = std::min<int>(o.fold_blocks, FOLD_MAX_BLOCKS);
+    c->col_enable = o.columns != 0;
     if (const char *v = std::getenv("ECMG_COL")) c->col_enable = std::atoi(v) != 0;
     if (const char *v = std::getenv("ECMG_COL_KZ")) c->col_kz = std::max(1, std::atoi(v));
     if (const char *v = std::getenv("ECMG_COL_ORDER")) c->col_order = std::min(2, std::max(0, std::atoi(v)));

@@ -79,6 +79,15 @@ inline void launch_timed(F kernel, dim3 grid, dim3 block, uint32_t shmem, hipStr
     g_pending_timing = PendingTiming{};
     hipExtLaunchKernelGGL(kernel, grid, block, shmem, s, t.start, t.stop, 0u, args...);
 }
+// The first launch of a group timed as one (start of the first kernel to the
+// end of the last): takes the start event and leaves the stop event to the
+// group's last launch, made by launch_timed.
+template <typename F, typename... Args>
+inline void launch_timed_first(F kernel, dim3 grid, dim3 block, uint32_t shmem, hipStream_t s, Args... args) {
+    hipEvent_t start = g_pending_timing.start;
+    g_pending_timing.start = nullptr;
+    hipExtLaunchKernelGGL(kernel, grid, block, shmem, s, start, nullptr, 0u, args...);
+}
 
 // Geometry of one level, passed to kernels by value.
 // Node arrays in HBM: node (i,j,k) at i + sx*(j + sy*k), rows padded to a
@@ -166,9 +175,16 @@ struct PassBArgs {
 // itself instead of a one-block finishing kernel.
 constexpr int FOLD_MAX_BLOCKS = 4096;
 
+// the Robin faces of a grid and the first thread of each in the face blocks
+struct ColFaces {
+    int nf;
+    int face[6];
+    int64_t start[7];
+};
 // Column stencil kernels (col_kernels.hip): one wave per (62-node x-segment,
-// R rows, z-chunk of KZ planes), planes in registers, x neighbours by DPP.
-// Used for JCG init and iteration 0 of pass A on levels whose passes run
+// R rows, z-chunk of KZ planes), planes in registers, x neighbours by DPP,
+// then one thread per Robin-face node in the launch's last blocks.
+// Used for JCG init and the stencil of pass A on levels whose passes run
 // with one-block finishing kernels (the large grids).  Rows per wave: init
 // keeps 2 (its epilogue inputs and outputs fill the registers: 4 rows would
 // leave 2 waves per SIMD and ran slower), iteration 0 takes 4 (halo rows 1.5x
@@ -181,28 +197,26 @@ struct ColArgs {
     int R;                            // node rows per wave (COL_R_INIT or COL_R_A0)
     const double *beta;
     const double *alpha[6];
-    const double *v;                  // input: APPLY v, INIT x, PASSA0 p_0
+    const double *v;                  // input: APPLY v, INIT x, PASSA0 p (p_0 at iteration 0)
+    const double *v_odd;              // PASSA0: the input p at odd iterations (NULL: always v)
     double *out;                      // APPLY / PASSA0: q; INIT: r
     const double *F, *dinv;           // INIT epilogue inputs
     double *p_out;                    // INIT with p_init: p_0 = D^-1 r
     int p_init;
     int plain_cg;                     // INIT: M^-1 = 1 (ECMG_CG) instead of 1/diag from beta
     JcgScalars *sc;                   // PASSA0: returns when done is set
-    double *partials;                 // 2 per wave, then 2 per block of the Robin-face kernel
-};
-// the Robin faces of a grid and the first thread of each in the face kernel
-struct ColFaces {
-    int nf;
-    int face[6];
-    int64_t start[7];
+    double *partials;                 // 2 per wave, then 2 per Robin-face block
+    int ncb;                          // column blocks (set by launch_col)
+    ColFaces fl;                      // Robin faces (set by launch_col)
 };
 // waves of a column launch for z-chunks of KZ planes
 int col_waves(const Geom &g, int KZ, int order, int R, int *ntx, int *nty, int *nkz);
-// blocks of the Robin-face kernel
+// Robin-face blocks of a column launch
 int col_faces(const Geom &g, ColFaces *fl);
-// column kernel plus the Robin-face kernel; returns the partial pairs written
-// (waves, then face blocks), which the finishing kernel sums in that order, or
-// -1 (nothing launched) if a.R is not the mode's rows per wave
+// the column launch (column blocks, then Robin-face blocks); returns the
+// partial pairs written (waves, then face blocks), which the finishing kernel
+// sums in that order, or -1 (nothing launched) if a.R is not the mode's rows
+// per wave
 int launch_col(int mode, const ColArgs &a, hipStream_t s);
 
 // One independent JCG solve inside the persistent kernel: a grid, its arrays,
@@ -241,7 +255,7 @@ enum { MODE_APPLY = 0, MODE_INIT = 1, MODE_PASSA = 2, MODE_PASSA0 = 3 };
 // kernel classes timed per level: 0 pass A, 1 pass B, 2 JCG init, 3 EXP_finite,
 // 4 EXP_true, 5 pass A FP32, 6 pass B FP32, 7 persistent JCG, 8 mixed start,
 // 9 mixed update
-constexpr int NKIND = 11;
+constexpr int NKIND = 12;
 
 struct Level {
     Geom g;
@@ -316,6 +330,10 @@ int64_t passB_blocks(int64_t n);
 // of the final scalars to `out`, the update left to the caller)
 void launch_final_x(const Geom &g, double *x, const double *p0, const double *p1, const JcgScalars *sc,
                     JcgScalars *out, hipStream_t s, bool update = true);
+// pass A of iteration >= 1 on the column-kernel levels, node-wise part:
+// p = D^-1 r + beta p_old, x += alpha p_old (the first launch of a timed group)
+void launch_p_update(const Geom &g, const double *dinv, const double *r, double *p0, double *p1, double *x,
+                     const JcgScalars *sc, hipStream_t s);
 // mixed precision: r32 = r64 / s, d32 = 0, JCG start scalars (FP64 sums)
 void launch_mixed_start(const Geom &g, const double *r64, double inv_s, const float *dinv32, float *r32, float *d32,
                         JcgScalars *sc, double *partials, unsigned *counter, hipStream_t s);

@@ -92,25 +92,34 @@ __device__ __forceinline__ void exp_true_block(const Geom &gf, const FineRead &U
     const int64_t cx = row_pitch(NX1 + 1), cxy = cx * (NY1 + 1);
     const bool hx = p < NX1, hy = J < NY1;                        // odd x node / odd row exist
     const int p2 = min(p + 1, NX1), J2 = min(J + 1, NY1);          // clamped: used only where they exist
-    // coarse differences d at x = 2p (dx 0) and 2p + 2 (dx 1) of rows 2J (dj 0)
-    // and 2J + 2 (dj 1) on one coarse plane kc, and U0 at (p, J, kc)
-    auto dplane = [&](int kc, double (&d)[2][2], double &c00) {
+    // On coarse plane kc: the fine pair (2p, 2p + 1) of row 2J (kept: it is
+    // also the first output row of the step on plane kc), the coarse
+    // differences d at x = 2p (dx 0) and 2p + 2 (dx 1) of rows 2J (dj 0) and
+    // 2J + 2 (dj 1), and U0 at (p, J, kc).  Row 2J + 2 is the lead row of the
+    // thread of row J + 1 on the same plane, so its lines are read by both at
+    // about the same time.
+    auto lead = [&](int kc, double2 &e0, double (&d)[2][2], double &c00) {
         const int64_t f = sxy * (2 * (int64_t)kc), c = cxy * (int64_t)kc;
-#pragma unroll
-        for (int dj = 0; dj < 2; ++dj) {
-            const int jj = dj ? J2 : J;
-            const int64_t fr = f + sx * (2 * (int64_t)jj), cr = c + cx * jj;
-            const double c0 = U0[cr + p];
-            if (dj == 0) c00 = c0;
-            d[dj][0] = U.at<FUSE>(fr + 2 * p) - c0;
-            d[dj][1] = U.at<FUSE>(fr + 2 * p2) - U0[cr + p2];
+        const int64_t fr0 = f + sx * (2 * (int64_t)J), cr0 = c + cx * J;
+        if (hx) {
+            e0 = U.at2<FUSE>(fr0 + 2 * p);                // 2p even, rows 16-byte aligned
+        } else {
+            e0.x = U.at<FUSE>(fr0 + 2 * p);
+            e0.y = 0.0;
         }
+        c00 = U0[cr0 + p];
+        d[0][0] = e0.x - c00;
+        d[0][1] = U.at<FUSE>(fr0 + 2 * p2) - U0[cr0 + p2];
+        const int64_t fr1 = f + sx * (2 * (int64_t)J2), cr1 = c + cx * J2;
+        d[1][0] = U.at<FUSE>(fr1 + 2 * p) - U0[cr1 + p];
+        d[1][1] = U.at<FUSE>(fr1 + 2 * p2) - U0[cr1 + p2];
     };
     double dlo[2][2], dhi[2][2], clo, chi;
-    dplane(K0, dlo, clo);
+    double2 elo, ehi;
+    lead(K0, elo, dlo, clo);
     for (int K = K0; K < K1; ++K) {
         const bool hz = K < NZ1;
-        if (hz) dplane(K + 1, dhi, chi);
+        if (hz) lead(K + 1, ehi, dhi, chi);
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
             if (c == 1 && !hz) break;
@@ -119,8 +128,11 @@ __device__ __forceinline__ void exp_true_block(const Geom &gf, const FineRead &U
                 if (b == 1 && !hy) break;
                 const int64_t id = 2 * p + sx * (2 * (int64_t)J + b) + sxy * (2 * (int64_t)K + c);
                 double u_e, u_o = 0.0;
-                if (hx) {
-                    const double2 v = U.at2<FUSE>(id);   // 2p even, rows 16-byte aligned
+                if (b == 0 && c == 0) {
+                    u_e = elo.x;
+                    u_o = elo.y;
+                } else if (hx) {
+                    const double2 v = U.at2<FUSE>(id);
                     u_e = v.x;
                     u_o = v.y;
                 } else {
@@ -156,6 +168,7 @@ __device__ __forceinline__ void exp_true_block(const Geom &gf, const FineRead &U
                 dlo[dj][1] = dhi[dj][1];
             }
             clo = chi;
+            elo = ehi;
         }
     }
 }

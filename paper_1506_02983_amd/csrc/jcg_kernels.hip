@@ -736,6 +736,59 @@ __global__ void __launch_bounds__(256) k_final_x(int64_t n, T *x, const T *p0, c
     }
 }
 
+// Pass A of iteration it >= 1 split for the column stencil (the grids too
+// large for folded scalars): the node-wise part, the search direction
+// p = D^-1 r + beta p_old and the previous iteration's x += alpha p_old, with
+// the same roundings as the fused tiled pass A; the column kernel then forms
+// q = A p and p.q.  One contiguous chunk of UB x 256 node pairs per block,
+// 16-byte accesses over the whole array (padding entries are zero in every
+// input and stay zero).
+__global__ void __launch_bounds__(256) k_p_update(int64_t n, const double *__restrict__ dinv,
+                                                  const double *__restrict__ r, double *p0, double *p1, double *x,
+                                                  const JcgScalars *sc) {
+    if (sc->done) return;                         // uniform over the grid
+    const int it = sc->iter;
+    const double bk = sc->beta, al = sc->alpha;
+    const bool first = it == 0;
+    const double2 *__restrict__ pin = (const double2 *)((it & 1) ? p1 : p0);
+    double2 *__restrict__ pout = (double2 *)((it & 1) ? p0 : p1);
+    const double2 *__restrict__ d2 = (const double2 *)dinv;
+    const double2 *__restrict__ r2 = (const double2 *)r;
+    double2 *__restrict__ x2 = (double2 *)x;
+    const int64_t n2 = n / 2;
+    const int64_t base = (int64_t)blockIdx.x * (UB * 256) + threadIdx.x;
+    double2 dv[UB], rv[UB], pv[UB], xv[UB];
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+        const int64_t i = base + u * 256;
+        if (i < n2) {
+            dv[u] = nt_load2(d2 + i);
+            rv[u] = nt_load2(r2 + i);
+            if (!first) {
+                pv[u] = nt_load2(pin + i);
+                xv[u] = nt_load2(x2 + i);
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+        const int64_t i = base + u * 256;
+        if (i < n2) {
+            double2 pn;
+            const double z0 = dv[u].x * rv[u].x, z1 = dv[u].y * rv[u].y;
+            pn.x = first ? z0 : z0 + bk * pv[u].x;
+            pn.y = first ? z1 : z1 + bk * pv[u].y;
+            nt_store2(pn, pout + i);
+            if (!first) {
+                double2 xn;
+                xn.x = xv[u].x + al * pv[u].x;
+                xn.y = xv[u].y + al * pv[u].y;
+                nt_store2(xn, x2 + i);
+            }
+        }
+    }
+}
+
 __global__ void k_jcg_reset(JcgScalars *sc, double tol, int max_iter, int fixed) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         sc->rho = sc->rr = sc->alpha = sc->beta = sc->pq = 0.0;
@@ -831,6 +884,12 @@ void launch_final_x(const Geom &g, double *x, const double *p0, const double *p1
     const int64_t n = update ? g.nnodes : 0;
     const int64_t nb = std::max<int64_t>(1, (n / 2 + UB * 256 - 1) / (UB * 256));
     hipLaunchKernelGGL((k_final_x<double>), dim3((unsigned)nb), dim3(256), 0, s, n, x, p0, p1, sc, out);
+}
+
+void launch_p_update(const Geom &g, const double *dinv, const double *r, double *p0, double *p1, double *x,
+                     const JcgScalars *sc, hipStream_t s) {
+    const int64_t nb = std::max<int64_t>(1, (g.nnodes / 2 + UB * 256 - 1) / (UB * 256));
+    launch_timed_first(k_p_update, dim3((unsigned)nb), dim3(256), 0, s, g.nnodes, dinv, r, p0, p1, x, sc);
 }
 
 void launch_jcg_reset(JcgScalars *sc, double tol, int max_iter, int fixed, hipStream_t s) {

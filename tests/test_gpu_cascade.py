@@ -27,13 +27,15 @@ def _rel(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
-# The three JCG drivers: the whole-loop persistent kernel (forced on every grid
-# it can take), the tiled two-pass kernels with the scalar steps folded into the
-# passes (what grids of up to 4096 blocks per pass use), and the tiled passes
-# with one-block finishing kernels (what the 257^3 and 513^3 grids use), forced
-# here with fold_blocks = 0.
+# The JCG drivers: the whole-loop persistent kernel (forced on every grid it
+# can take), the tiled two-pass kernels with the scalar steps folded into the
+# passes (what grids of up to 4096 blocks per pass use), and the passes with
+# one-block finishing kernels, forced here with fold_blocks = 0: by the column
+# kernels (init, and pass A as the node-wise p / x update plus the column
+# stencil: what the 257^3 and 513^3 grids use) or by the tiled kernels.
 DRIVERS = {"persistent": dict(persistent_nodes=300000), "tiled": dict(persistent_nodes=0),
-           "tiled-unfolded": dict(persistent_nodes=0, fold_blocks=0)}
+           "column-unfolded": dict(persistent_nodes=0, fold_blocks=0),
+           "tiled-unfolded": dict(persistent_nodes=0, fold_blocks=0, columns=False)}
 
 
 @pytest.mark.parametrize("driver", list(DRIVERS))
