@@ -33,7 +33,7 @@ METRIC = "unknowns/s to 4th-order accuracy (FP64 vs mixed); JCG HBM GB/s; serve 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 KIND_NAMES = {0: "jcg_pass_a", 1: "jcg_pass_b", 2: "jcg_init", 3: "exp_finite", 4: "exp_true",
               5: "jcg_pass_a_fp32", 6: "jcg_pass_b_fp32", 7: "jcg_persistent", 10: "jcg_pass_a0",
-              11: "jcg_pass_a_col"}
+              11: "jcg_pass_a_col", 12: "jcg_pass_b_last"}
 # kernel names as rocprofv3 reports them (stencil: <type, mode, rows of
 # threads, rows per thread, waves per SIMD>; column kernels: <mode, node rows
 # per wave, waves per SIMD, prefetch distance>, whose last blocks take the
@@ -41,12 +41,13 @@ KIND_NAMES = {0: "jcg_pass_a", 1: "jcg_pass_b", 2: "jcg_init", 3: "exp_finite", 
 # JCG init and iteration 0 of pass A run the tiled kernel on the levels whose
 # scalars are folded into the passes, the column kernels on the larger ones;
 # there pass A of the later iterations (class 11) is the node-wise p / x update
-# and the column stencil, timed as one.
-KERNEL_SYMBOL = {0: "k_stencil<double, 2, 8, 1, 4>", 1: "k_passB<double>",
+# and the column stencil, timed as one.  Class 12: the pass B a speculative
+# chunk expects to be the level's last (stop test only, no r stored).
+KERNEL_SYMBOL = {0: "k_stencil<double, 2, 8, 1, 4>", 1: "k_passB<double, false>",
                  2: "k_stencil<double, 1, 8, 1, 4> | k_col<1, 2, 2, 1>",
-                 3: "k_exp_finite", 4: "k_exp_true", 5: "k_stencil<float, 2, 8, 1, 4>", 6: "k_passB<float>",
+                 3: "k_exp_finite", 4: "k_exp_true", 5: "k_stencil<float, 2, 8, 1, 4>", 6: "k_passB<float, false>",
                  7: "k_jcg_persistent", 10: "k_stencil<double, 3, 4, 2, 2> | k_col<3, 4, 2, 1>",
-                 11: "k_p_update + k_col<3, 4, 2, 1>"}
+                 11: "k_p_update + k_col<3, 4, 2, 1>", 12: "k_passB<double, true>"}
 
 
 def workload(name):
@@ -75,6 +76,8 @@ def algorithmic_bytes(kind, n, e, n1, n0, iters=0):
         return 8 * (2 * n + e)          # iteration 0: read p_0 (stored by init), beta; write q
     if kind == 1:
         return 8 * 4 * n                # read r, q, 1/D; write r
+    if kind == 12:
+        return 8 * 2 * n                # the expected last pass B: read r, q (stop test only)
     if kind == 2:
         return 8 * (4 * n + e)          # read x, F, beta; write r, p_0 = D^-1 r (D from beta: 40 B/node)
     if kind == 3:
@@ -628,7 +631,7 @@ def main():
                "avg_us": round(r["avg_us"], 2), "achieved": round(r["gbs"], 1),
                "frac": round(r["gbs"] / HBM_PEAK_GBS, 4), "bytes_per_launch": r["bytes_per_launch"]}
               for r in kernels if r["level"] == L]
-    jcg_fin = [r for r in kernels if r["level"] == L and r["kind"] in (0, 1, 10, 11)]
+    jcg_fin = [r for r in kernels if r["level"] == L and r["kind"] in (0, 1, 10, 11, 12)]
     jcg_gbs = None
     if jcg_fin:
         tb = sum(r["bytes_per_launch"] * r["launches"] for r in jcg_fin)

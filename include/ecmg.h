@@ -163,7 +163,10 @@ typedef struct {
                                   levels; if it then falls short of the tolerance, that
                                   level and every finer one are solved again from their
                                   EXP_finite start with status reads (same results as
-                                  speculate = 0, at the cost of the repeated work)  */
+                                  speculate = 0, at the cost of the repeated work).  On
+                                  the levels with one-block finishing kernels the
+                                  expected last pass B stores no residual (only the
+                                  stop test reads it)                                   */
     int32_t fold_blocks;       /* tiled JCG levels whose two passes have at most this many
                                   blocks each take the CG scalar steps inside the passes
                                   (every block sums the previous pass's partials in one
@@ -446,7 +449,11 @@ int ecmg_plan_bytes(const ecmg_problem *problem, int32_t precision, size_t *byte
  * iteration 0, which reads the p_0 that init stored; class 0 counts the later
  * iterations, 11 = JCG pass A of iterations >= 1 on the levels that run the
  * column kernels: the node-wise p and x update, then the column stencil,
- * timed from the start of the first kernel to the end of the second),
+ * timed from the start of the first kernel to the end of the second, 12 =
+ * the JCG pass B a level solved without status reads expects to be its
+ * last (options.speculate): it takes the stop test without storing r or
+ * forming r.z, since nothing reads them if the test passes and the level is
+ * solved again if it fails; class 1 counts the other pass B launches),
  * out[0] = total milliseconds and out[1] = launches that did work since the
  * last ecmg_reset_kernel_times.  Measured with HIP events on the library's
  * stream around each launch; both calls wait for the stream to finish the

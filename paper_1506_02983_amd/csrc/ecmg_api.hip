@@ -451,7 +451,7 @@ static int rec_end(ecmg_ctx *c, size_t slot) {
 // iteration index is at or beyond its level's limit (the iterations the level
 // ran) found the `done` flag set and did no work; it is not counted.
 static bool rec_is_pass(int kind) {
-    return kind == 0 || kind == 1 || kind == 5 || kind == 6 || kind == 10 || kind == 11;
+    return kind == 0 || kind == 1 || kind == 5 || kind == 6 || kind == 10 || kind == 11 || kind == 12;
 }
 static int rec_flush_levels(ecmg_ctx *c, const std::vector<int> &limit) {
     if (c->recs.empty()) return ECMG_OK;
@@ -543,8 +543,12 @@ static int jcg_chunks(ecmg_ctx *c, int l, const StencilArgs<T> &a, const PassBAr
                 launch_stencil<T>(a0 ? MODE_PASSA0 : MODE_PASSA, a, c->stream);
                 CHK(rec_end(c, slot));
             }
-            CHK(rec_begin(c, l, kind_b, done_iters + t, &slot));
-            launch_passB<T>(b, c->stream);
+            // the last pass B of a speculative FP64 chunk stores no r (see
+            // PassBArgs::last): its own timing class
+            PassBArgs<T> bt = b;
+            bt.last = nowait && kind_b == 1 && t == chunk - 1;
+            CHK(rec_begin(c, l, bt.last ? 12 : kind_b, done_iters + t, &slot));
+            launch_passB<T>(bt, c->stream);
             CHK(rec_end(c, slot));
         }
         HIPCHK(c, hipGetLastError());

@@ -169,6 +169,11 @@ struct PassBArgs {
     // (stride 2) itself and takes alpha = rho_it / p.q
     int fold, it, nb_a;
     const double *pq_partials;
+    // unfolded only: the pass B a speculative chunk expects to be its level's
+    // last.  Computes r - alpha q and ||r||^2 for the stop test but stores
+    // no r and forms no r.z (no 1/D read): if the test passes nothing reads
+    // them, and if it fails the level is solved again from its start.
+    int last;
 };
 
 // Largest pass (blocks) whose partials every block of the next pass sums
@@ -255,7 +260,7 @@ enum { MODE_APPLY = 0, MODE_INIT = 1, MODE_PASSA = 2, MODE_PASSA0 = 3 };
 // kernel classes timed per level: 0 pass A, 1 pass B, 2 JCG init, 3 EXP_finite,
 // 4 EXP_true, 5 pass A FP32, 6 pass B FP32, 7 persistent JCG, 8 mixed start,
 // 9 mixed update
-constexpr int NKIND = 12;
+constexpr int NKIND = 13;
 
 struct Level {
     Geom g;

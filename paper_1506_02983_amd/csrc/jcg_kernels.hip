@@ -594,7 +594,7 @@ __global__ void __launch_bounds__(NTF) k_stencil_finish(JcgScalars *sc, const do
 constexpr int NTB = 256;
 constexpr int UB = 4;
 
-template <typename T>
+template <typename T, bool LAST>
 __global__ void __launch_bounds__(NTB) k_passB(const PassBArgs<T> a) {
     __shared__ double red[2][NTB / 64];
     __shared__ double s_alpha;
@@ -617,7 +617,7 @@ __global__ void __launch_bounds__(NTB) k_passB(const PassBArgs<T> a) {
         if (i < n2) {
             rv[u] = nt_load2(r2 + i);
             qv[u] = nt_load2(q2 + i);
-            dv[u] = nt_load2(d2 + i);
+            if (!LAST) dv[u] = nt_load2(d2 + i);
         }
     }
     T al;
@@ -657,9 +657,11 @@ __global__ void __launch_bounds__(NTB) k_passB(const PassBArgs<T> a) {
             V2 x;
             x.x = rv[u].x - al * qv[u].x;
             x.y = rv[u].y - al * qv[u].y;
-            nt_store2(x, w2 + i);
-            const T z0 = dv[u].x * x.x, z1 = dv[u].y * x.y;
-            rz += (double)x.x * (double)z0 + (double)x.y * (double)z1;
+            if (!LAST) {
+                nt_store2(x, w2 + i);
+                const T z0 = dv[u].x * x.x, z1 = dv[u].y * x.y;
+                rz += (double)x.x * (double)z0 + (double)x.y * (double)z1;
+            }
             rr += (double)x.x * (double)x.x + (double)x.y * (double)x.y;
         }
     }
@@ -875,7 +877,8 @@ int64_t passB_blocks(int64_t n) { return std::max<int64_t>(1, (n / 2 + UB * NTB 
 template <typename T>
 void launch_passB(const PassBArgs<T> &a, hipStream_t s) {
     const int64_t nb = passB_blocks(a.n);
-    launch_timed(k_passB<T>, dim3((unsigned)nb), dim3(NTB), 0, s, a);
+    if (a.last && !a.fold) launch_timed(k_passB<T, true>, dim3((unsigned)nb), dim3(NTB), 0, s, a);
+    else launch_timed(k_passB<T, false>, dim3((unsigned)nb), dim3(NTB), 0, s, a);
     if (!a.fold) hipLaunchKernelGGL(k_passB_finish, dim3(1), dim3(NTF), 0, s, a.sc, (const double *)a.partials, (int)nb);
 }
 

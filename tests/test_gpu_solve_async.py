@@ -89,16 +89,24 @@ def _stable(ecmg, s, p, eps, times=3):
         s.solve(eps)
 
 
-@pytest.mark.parametrize("persistent", [0, -1], ids=["tiled", "default"])
-def test_speculative_chunk_shortfall_matches_fresh_context(ecmg, persistent):
+# the drivers a speculative level can run: tiled with folded scalar steps, the
+# persistent kernel where it is the default, and the unfolded column path of
+# the large grids (forced with fold_blocks = 0), whose last speculative pass B
+# stores no residual
+SPEC_DRIVERS = {"tiled": dict(persistent_nodes=0), "default": dict(persistent_nodes=-1),
+                "unfolded": dict(persistent_nodes=0, fold_blocks=0)}
+
+
+@pytest.mark.parametrize("driver", list(SPEC_DRIVERS))
+def test_speculative_chunk_shortfall_matches_fresh_context(ecmg, driver):
     """A level enqueued with its previous count and no status read that then
     falls short of a tighter tolerance is solved again, with every finer level,
     from its EXP_finite start: iterates and counts equal a fresh context's."""
     p = workloads.variable_beta_robin_cube(levels=5)
-    with ecmg.Solver(persistent_nodes=persistent) as s:
+    with ecmg.Solver(**SPEC_DRIVERS[driver]) as s:
         s.setup(p)
         fresh = _solve(ecmg, s, p, 1e-10)
-    with ecmg.Solver(persistent_nodes=persistent) as s:
+    with ecmg.Solver(**SPEC_DRIVERS[driver]) as s:
         s.setup(p)
         _stable(ecmg, s, p, 1e-6)
         for _ in range(2):                                    # short speculation, then no speculation
@@ -108,19 +116,20 @@ def test_speculative_chunk_shortfall_matches_fresh_context(ecmg, persistent):
                 assert np.array_equal(u[l], fresh[1][l]), l
 
 
-def test_speculative_shortfall_on_a_middle_level(ecmg):
+@pytest.mark.parametrize("driver", ["tiled", "unfolded"])
+def test_speculative_shortfall_on_a_middle_level(ecmg, driver):
     """Only level 3's tolerance tightens: level 2 keeps its speculative result,
     levels 3 and 4 are solved again; the same as a fresh context."""
     p = workloads.variable_beta_robin_cube(levels=5)
     loose = [1e-6] * p.levels
     tight = list(loose)
     tight[3] = 1e-11
-    with ecmg.Solver(persistent_nodes=0) as s:
+    with ecmg.Solver(**SPEC_DRIVERS[driver]) as s:
         s.setup(p)
         s.solve_levels(loose)
         ref = s.solve_levels(tight)
         ref_u = {l: s.get(l, ecmg.VEC_U) for l in range(p.levels)}
-    with ecmg.Solver(persistent_nodes=0, timing=True) as s:
+    with ecmg.Solver(timing=True, **SPEC_DRIVERS[driver]) as s:
         s.setup(p)
         for _ in range(3):
             base = s.solve_levels(loose)
@@ -132,18 +141,24 @@ def test_speculative_shortfall_on_a_middle_level(ecmg):
             assert np.array_equal(s.get(l, ecmg.VEC_U), ref_u[l]), l
         # the discarded attempt leaves no kernel times: each tiled level counts
         # exactly the iterations of its kept solve
+        # (unfolded: pass A of iterations >= 1 is class 11, and the last pass B
+        # of a kept speculative level class 12)
         for l in range(2, p.levels):
             it = infos[l]["iters"]
-            counts = {k: s.kernel_times(l, k)[1] for k in (0, 1, 10)}
-            assert counts[10] == min(it, 1) and counts[0] == max(it - 1, 0), (l, counts, it)
-            assert counts[1] == it, (l, counts, it)
+            counts = {k: s.kernel_times(l, k)[1] for k in (0, 1, 10, 11, 12)}
+            assert counts[10] == min(it, 1) and counts[0] + counts[11] == max(it - 1, 0), (l, counts, it)
+            assert counts[1] + counts[12] == it, (l, counts, it)
+            # level 3 fell short and ran again with status reads; levels 2 and 4
+            # ran speculatively
+            assert counts[12] == (1 if driver == "unfolded" and l != 3 else 0), (l, counts)
 
 
-def test_speculation_off_gives_the_same_iterates(ecmg):
+@pytest.mark.parametrize("driver", ["tiled", "unfolded"])
+def test_speculation_off_gives_the_same_iterates(ecmg, driver):
     p = workloads.variable_beta_robin_cube(levels=5)
     out = []
     for spec in (True, False):
-        with ecmg.Solver(persistent_nodes=0, speculate=spec) as s:
+        with ecmg.Solver(speculate=spec, **SPEC_DRIVERS[driver]) as s:
             s.setup(p)
             _stable(ecmg, s, p, 1e-8)
             out.append(_solve(ecmg, s, p, 1e-8))
