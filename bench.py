@@ -543,8 +543,8 @@ def main():
         t0 = time.perf_counter()
         tuned = s.autotune(iters=0, cache=args.tune_cache)
         print("bench: autotune %.2f s: %s" % (time.perf_counter() - t0, ", ".join(
-            "L%d %s" % (r["level"], ("tiled kz=%d" % r["kz"]) if r["path"] == "tiled" else
-                        "persistent seg=%d nwg=%d" % (r["seg"], r["nwg"]))
+            "L%d %s" % (r["level"], ("tiled kz=%d" % r["kz"]) if r["path"] == "tiled" else "gather"
+                        if r["path"] == "gather" else "persistent seg=%d nwg=%d" % (r["seg"], r["nwg"]))
             for r in tuned)), file=sys.stderr, flush=True)
         s.solve(eps, extrapolate=True)
     # per-kernel breakdown: two untimed steps with every kernel class timed

@@ -192,6 +192,15 @@ typedef struct {
                                   p / x update followed by that stencil; 0 = the tiled
                                   kernels (LDS plane tiles, pass A fused).  The same
                                   recurrence; only the summation order differs         */
+    int64_t gather_nodes;      /* JCG levels of at most this many nodes whose passes fit
+                                  folded scalar steps (at most fold_blocks blocks of
+                                  256 nodes) run init and the stencil of pass A one
+                                  thread per node, reading each node's 27-point row
+                                  from the caches, after a node-wise p / x update that
+                                  takes the scalar step (three launches per iteration
+                                  instead of a tiled pass A's plane-by-plane march);
+                                  -1 = default (1,048,576), 0 = never.  A tuned choice
+                                  (autotune) takes precedence.  The same recurrence   */
     /* Device allocator hook (NULL = hipMalloc / hipFree).  alloc returns `bytes` of
      * device memory usable on hip_stream (the library's stream; hipStream_t as
      * void*), or NULL on failure (ECMG_ENOMEM); free releases a pointer alloc
@@ -205,7 +214,8 @@ typedef struct {
 /* One JCG level's configuration chosen by the autotuner. */
 typedef struct {
     int32_t level;             /* level (>= 2); -1 from ecmg_tune_lookup                */
-    int32_t path;              /* 0: tiled passes, 1: persistent kernel                  */
+    int32_t path;              /* 0: tiled passes, 1: persistent kernel, 3: gather
+                                  stencil (options.gather_nodes)                        */
     int32_t kz;                /* tiled: planes per z-chunk of a stencil block           */
     int32_t seg;               /* persistent: nodes per thread segment (1, 2 or 4)       */
     int32_t nwg;               /* persistent: most workgroups                            */
@@ -477,7 +487,8 @@ int ecmg_set_timing(ecmg_ctx *ctx, int32_t mask);
  * which is restored, under the built-in configuration and each candidate
  * (tiled passes with z-chunks of 1, 2, 4, 8, 16, 32 or 64 planes; the persistent
  * kernel with segments of 2 or 4 nodes and at most 32, 64, 128 or 256 workgroups, for
- * grids of at most 20,000,000 nodes), keeps the fastest for later solves on
+ * grids of at most 20,000,000 nodes; the gather path of options.gather_nodes
+ * where its passes fit folded scalar steps), keeps the fastest for later solves on
  * ctx and, if cache_path (or options.tune_cache, or $ECMG_TUNE_CACHE) names a
  * file, merges the choices into that JSON cache keyed by precision and
  * elements per axis (the file is replaced atomically).  out: NULL or

@@ -64,7 +64,7 @@ class Options(ctypes.Structure):
                 ("persistent_nodes", ctypes.c_int64), ("dsolve_dense_max", ctypes.c_int64),
                 ("autotune", ctypes.c_int32), ("tune_cache", ctypes.c_char_p), ("method", ctypes.c_int32),
                 ("speculate", ctypes.c_int32), ("fold_blocks", ctypes.c_int32), ("true_residual", ctypes.c_int32),
-                ("batch_graph", ctypes.c_int32), ("columns", ctypes.c_int32),
+                ("batch_graph", ctypes.c_int32), ("columns", ctypes.c_int32), ("gather_nodes", ctypes.c_int64),
                 ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_user", ctypes.c_void_p)]
 
 
@@ -75,7 +75,7 @@ class TuneResult(ctypes.Structure):
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
-        d["path"] = "persistent" if self.path == 1 else "tiled"
+        d["path"] = {1: "persistent", 3: "gather"}.get(self.path, "tiled")
         return d
 
 
@@ -346,7 +346,8 @@ class Solver:
                  chunk: int = 0, timing: bool = False, stream=None, persistent_nodes: int = -1,
                  dsolve_dense_max: Optional[int] = None, autotune: int = 0, tune_cache: Optional[str] = None,
                  method: int = JCG, speculate: bool = True, fold_blocks: int = -1, true_residual: bool = False,
-                 batch_graph: bool = True, columns: bool = True, torch_allocator: bool = False):
+                 batch_graph: bool = True, columns: bool = True, gather_nodes: int = -1,
+                 torch_allocator: bool = False):
         self.L = load_library()
         o = Options()
         self.L.ecmg_default_options(ctypes.byref(o))
@@ -364,6 +365,7 @@ class Solver:
         o.true_residual = int(true_residual)
         o.batch_graph = int(batch_graph)
         o.columns = int(columns)
+        o.gather_nodes = int(gather_nodes)
         self._hooks = None
         if torch_allocator:
             self._hooks = _torch_allocator_hooks()

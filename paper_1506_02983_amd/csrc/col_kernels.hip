@@ -447,6 +447,144 @@ __global__ void __launch_bounds__(256, WPE) k_col(const ColArgs a) {
     }
 }
 
+// The 27-point row of node (i, j, k), read from global memory through v(idx)
+// (the input value at flat node index idx): the stencil with the betas of the
+// 8 surrounding elements plus the face-mass terms of every Robin face the
+// node lies on.  Neighbour indices are clamped to the grid (an outside
+// neighbour couples only through outside elements, whose beta is 0).
+template <class V>
+__device__ __forceinline__ double gather_q(const ColArgs &a, int i, int j, int k, V v) {
+    const Geom &g = a.g;
+    const int sx = g.sx, sxy = g.sx * g.sy, exy = g.nx * g.ny;
+    int xo[3], yo[3], zo[3];
+#pragma unroll
+    for (int o = 0; o < 3; ++o) {
+        xo[o] = min(max(i - 1 + o, 0), g.nx);
+        yo[o] = sx * min(max(j - 1 + o, 0), g.ny);
+        zo[o] = sxy * min(max(k - 1 + o, 0), g.nz);
+    }
+    auto be = [&](int ii, int jj, int kk) -> double {
+        const bool ok = ii >= 0 && ii < g.nx && jj >= 0 && jj < g.ny && kk >= 0 && kk < g.nz;
+        const double b = a.beta[min(max(ii, 0), g.nx - 1) + g.nx * min(max(jj, 0), g.ny - 1) +
+                                exy * min(max(kk, 0), g.nz - 1)];
+        return ok ? b : 0.0;
+    };
+    const double l00 = be(i - 1, j - 1, k - 1), l01 = be(i, j - 1, k - 1), l10 = be(i - 1, j, k - 1),
+                 l11 = be(i, j, k - 1);
+    const double u00 = be(i - 1, j - 1, k), u01 = be(i, j - 1, k), u10 = be(i - 1, j, k), u11 = be(i, j, k);
+    double q = 0.0;
+#pragma unroll
+    for (int oy = -1; oy <= 1; ++oy)
+#pragma unroll
+        for (int ox = -1; ox <= 1; ++ox) {
+            double sl, su;
+            if (oy < 0 && ox < 0) { sl = l00; su = u00; }
+            else if (oy < 0 && ox > 0) { sl = l01; su = u01; }
+            else if (oy > 0 && ox < 0) { sl = l10; su = u10; }
+            else if (oy > 0 && ox > 0) { sl = l11; su = u11; }
+            else if (oy < 0) { sl = l00 + l01; su = u00 + u01; }
+            else if (oy > 0) { sl = l10 + l11; su = u10 + u11; }
+            else if (ox < 0) { sl = l00 + l10; su = u00 + u10; }
+            else if (ox > 0) { sl = l01 + l11; su = u01 + u11; }
+            else { sl = (l00 + l01) + (l10 + l11); su = (u00 + u01) + (u10 + u11); }
+            const int m = (ox != 0) | ((oy != 0) << 1);
+            const int row = xo[ox + 1] + yo[oy + 1];
+            q += g.C[m | 4] * (sl * v(row + zo[0]) + su * v(row + zo[2])) + g.C[m] * ((sl + su) * v(row + zo[1]));
+        }
+    const int ijk[3] = {i, j, k}, n3[3] = {g.nx, g.ny, g.nz};
+    for (int f = 0; f < 6; ++f) {
+        const int ax = f / 2;
+        if (g.ft[f] != ECMG_ROBIN || ijk[ax] != ((f & 1) ? n3[ax] : 0)) continue;
+        const int pa = ax == 0 ? 1 : 0, qa = ax == 2 ? 1 : 2;
+        auto nb = [&](int op, int oq) -> double {
+            int c[3] = {i, j, k};
+            c[pa] += op;
+            c[qa] += oq;
+            return v(c[0] + sx * c[1] + sxy * c[2]);
+        };
+        q += robin_col(g, f, a.alpha[f], ijk[pa], ijk[qa], n3[pa], n3[qa], nb);
+    }
+    return q;
+}
+
+// block partials in a fixed order (lanes, then the 4 waves); out[0] (and
+// out[1] if TWO) of block b at partials[2b], [2b + 1]
+template <bool TWO>
+__device__ __forceinline__ void gather_partials(double acc0, double acc1, double *partials, double (*red)[4]) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        acc0 += __shfl_xor(acc0, off, 64);
+        acc1 += __shfl_xor(acc1, off, 64);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[0][w] = acc0;
+        red[1][w] = acc1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        partials[2 * (int64_t)blockIdx.x] = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
+        if (TWO) partials[2 * (int64_t)blockIdx.x + 1] = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
+    }
+}
+
+// node of thread t of a launch over the grid's nodes (x fastest); false past the end
+__device__ __forceinline__ bool gather_node(const Geom &g, int64_t t, int &i, int &j, int &k) {
+    const int nxp = g.nx + 1, nyp = g.ny + 1;
+    if (t >= (int64_t)nxp * nyp * (g.nz + 1)) return false;
+    i = (int)(t % nxp);
+    const int64_t rw = t / nxp;
+    j = (int)(rw % nyp);
+    k = (int)(rw / nyp);
+    return true;
+}
+
+// JCG init one thread per node: r = F - A x, z = D^-1 r (p_0 = z stored if
+// p_init), r.z and r.r block partials.  For the small grids, whose vectors
+// stay in the caches between passes: there a block's march through its
+// planes is a chain of memory latencies, and one thread per node has none.
+__global__ void __launch_bounds__(256) k_gather_init(const ColArgs a) {
+    __shared__ double red[2][4];
+    const Geom &g = a.g;
+    double acc0 = 0.0, acc1 = 0.0;
+    int i, j, k;
+    if (gather_node(g, (int64_t)blockIdx.x * 256 + threadIdx.x, i, j, k)) {
+        const int id = i + g.sx * j + g.sx * g.sy * k;
+        const double *__restrict__ x = a.v;
+        const bool dir = dir_node(g, i, j, k);
+        const double q = dir ? 0.0 : gather_q(a, i, j, k, [&](int idx) { return x[idx]; });
+        const double rv = dir ? 0.0 : a.F[id] - q;
+        __builtin_nontemporal_store(rv, a.out + id);
+        const double z = a.dinv[id] * rv;
+        if (a.p_init) __builtin_nontemporal_store(z, a.p_out + id);
+        acc0 += rv * z;
+        acc1 += rv * rv;
+    }
+    gather_partials<true>(acc0, acc1, a.partials, red);
+}
+
+// The stencil of pass A one thread per node: q = A p and p.q block partials,
+// p read from the buffer of the iteration's parity (sc->iter, which the
+// node-wise p update of the same iteration has stored).  A version that formed
+// p at the 27 neighbours itself (one launch per pass A, three loads per
+// neighbour) ran 1.6x slower on 65^3 than the p update plus this kernel.
+__global__ void __launch_bounds__(256) k_gather_a(const ColArgs a) {
+    __shared__ double red[2][4];
+    const Geom &g = a.g;
+    if (a.sc->done) return;                       // uniform over the grid
+    const double *__restrict__ vin = (a.v_odd && (a.sc->iter & 1)) ? a.v_odd : a.v;
+    double acc0 = 0.0;
+    int i, j, k;
+    if (gather_node(g, (int64_t)blockIdx.x * 256 + threadIdx.x, i, j, k)) {
+        const int id = i + g.sx * j + g.sx * g.sy * k;
+        const bool dir = dir_node(g, i, j, k);
+        const double qv = dir ? 0.0 : gather_q(a, i, j, k, [&](int idx) { return vin[idx]; });
+        __builtin_nontemporal_store(qv, a.out + id);
+        acc0 += vin[id] * qv;
+    }
+    gather_partials<false>(acc0, 0.0, a.partials, red);
+}
+
 }  // namespace
 
 // wave grid: x-segments of 62 nodes, row groups of R rows, z-chunks of KZ
@@ -491,6 +629,22 @@ int launch_col(int mode, const ColArgs &a, hipStream_t s) {
     else if (mode == MODE_INIT) launch_timed(k_col<MODE_INIT, COL_R_INIT, 2, 1>, grid, dim3(256), 0, s, b);
     else launch_timed(k_col<MODE_PASSA0, COL_R_A0, 2, 1>, grid, dim3(256), 0, s, b);
     return waves + fb;
+}
+
+int gather_blocks(const Geom &g) {
+    return (int)(((int64_t)(g.nx + 1) * (g.ny + 1) * (g.nz + 1) + 255) / 256);
+}
+
+int launch_gather_init(const ColArgs &a, hipStream_t s) {
+    const int nb = gather_blocks(a.g);
+    launch_timed(k_gather_init, dim3(nb), dim3(256), 0, s, a);
+    return nb;
+}
+
+int launch_gather_a(const ColArgs &a, hipStream_t s) {
+    const int nb = gather_blocks(a.g);
+    launch_timed(k_gather_a, dim3(nb), dim3(256), 0, s, a);
+    return nb;
 }
 
 }  // namespace ecmg

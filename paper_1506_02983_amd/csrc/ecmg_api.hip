@@ -114,6 +114,7 @@ struct ecmg_ctx {
     int kz_target = 1024;                      // tiled stencil: blocks aimed for per launch
     int fold_max = FOLD_MAX_BLOCKS;            // JCG scalar steps folded into the passes up to this many blocks
     int col_enable = 1;                        // column kernels for init / pass A on unfolded levels
+    int64_t gather_max = GATHER_DEFAULT_NODES; // built-in rule: the gather path up to this many nodes
     int col_kz = 16;                           // planes per z-chunk of a column wave
     int col_order = 0;                         // wave order of the column kernels (col_waves)
     uint32_t timing_mask = 0;                  // kernel classes timed with HIP events (bit k = class k)
@@ -600,6 +601,56 @@ static int jcg_chunks_folded(ecmg_ctx *c, int l, StencilArgs<double> a, PassBArg
     return ECMG_OK;
 }
 
+// The gather levels (folded scalars, one thread per node for the stencils):
+// each iteration is the node-wise p update with the scalar step of the pass
+// before (U), the gather stencil (G) and pass B; the launches form U0 G0 B0
+// U1 G1 B1 ..., each with its iteration index, and every chunk ends on a U G
+// pair, whose U takes the stop test of the pass B before it (as
+// jcg_chunks_folded ends on a pass A).  U0 takes init's scalar step (nb_init
+// pairs), later U the pass B's (nb_b); pass B sums the gather's p.q pairs.
+static int jcg_chunks_gather(ecmg_ctx *c, int l, PUFoldArgs u, const ColArgs &ga, PassBArgs<double> b, int fixed,
+                             int hint, int nb_init, int nb_b, bool nowait) {
+    int next = 2;
+    int chunk = c->opt.chunk > 0 ? c->opt.chunk : (hint > 0 ? hint : 2);
+    if (fixed >= 0) chunk = std::max(fixed, 1);
+    int64_t seq = 0;                     // next launch: seq % 3 = 0 U, 1 G, 2 B of iteration seq / 3
+    size_t slot = 0;
+    for (bool first = true;; first = false) {
+        if (!first) {
+            HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(JcgScalars), hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            if (c->sc_host->done) break;
+            if (c->opt.chunk <= 0 && fixed < 0) {
+                chunk = next;
+                next = std::min(next * 2, 64);
+            }
+        }
+        const int64_t last = 3 * (seq / 3 + chunk) + 1;
+        for (; seq <= last; ++seq) {
+            const int it = (int)(seq / 3);
+            const int ph = (int)(seq % 3);
+            if (ph == 0) {
+                u.it = it;
+                u.fold_nb = it == 0 ? nb_init : nb_b;
+                // the p update and the stencil timed as one pass A
+                CHK(rec_begin(c, l, it == 0 ? 10 : 11, it, &slot));
+                launch_p_update_fold(u, c->stream);
+            } else if (ph == 1) {
+                launch_gather_a(ga, c->stream);
+                CHK(rec_end(c, slot));
+            } else {
+                b.it = it;
+                CHK(rec_begin(c, l, 1, it, &slot));
+                launch_passB<double>(b, c->stream);
+                CHK(rec_end(c, slot));
+            }
+        }
+        HIPCHK(c, hipGetLastError());
+        if (nowait) break;
+    }
+    return ECMG_OK;
+}
+
 // Mixed precision (FP32 stencil and CG vectors, FP64 dot products, FP64
 // residual and iterate): iterative refinement around an FP32 JCG.
 //   r = F - A x in FP64 (the stop test of Algorithm 4 is taken on it);
@@ -743,6 +794,18 @@ static int col_args(ecmg_ctx *c, Level &L, int R, ColArgs *ca) {
     return waves + col_faces(L.g, &fl);
 }
 
+// the gather path fits level grid g: folded scalars (each pass at most
+// fold_max blocks)
+static bool gather_possible(const ecmg_ctx *c, const Geom &g) {
+    return gather_blocks(g) <= c->fold_max && passB_blocks(g.nnodes) <= c->fold_max;
+}
+// the level runs the gather path: chosen by the tuner (path 3) or, with no
+// tuned choice, up to options.gather_nodes nodes
+static bool gather_level(const ecmg_ctx *c, const Level &L) {
+    const bool want = L.tune_path == 3 || (L.tune_path < 0 && L.g.nreal <= c->gather_max);
+    return want && gather_possible(c, L.g);
+}
+
 // Tiled JCG of level l, enqueued: init, the iterations (status reads only
 // between chunks), the last x update (the kernel checks whether one is
 // pending), which also copies the final scalars into the level's pinned slot;
@@ -771,9 +834,58 @@ static int enqueue_jcg(ecmg_ctx *c, int l, double tol_abs, int max_iter, int fix
     b.dinv = L.dinv;
     b.sc = c->sc;
     b.partials = c->partials;
+    const int64_t nb_b = passB_blocks(L.g.nnodes);
+    // the gather levels: init and the stencil of every pass A one thread per
+    // node, the node-wise p update taking the folded scalar step
+    if (gather_level(c, L)) {
+        const int64_t nb_g = gather_blocks(L.g);
+        CHK(ensure_partials(c, 2 * nb_g + 2 * std::max(nb_g, nb_b)));
+        double *pq = c->partials, *p2 = c->partials + 2 * nb_g;   // gather p.q; init / pass B pairs
+        ColArgs ga{};
+        ga.g = L.g;
+        ga.beta = L.beta;
+        for (int f = 0; f < 6; ++f) ga.alpha[f] = L.alpha[f];
+        ga.F = L.F;
+        ga.dinv = L.dinv;
+        ga.sc = c->sc;
+        size_t slot = 0;
+        CHK(rec_begin(c, l, 2, 0, &slot));
+        ga.v = L.x;
+        ga.out = c->r;
+        ga.p_out = c->p1;                         // p_0 in p1, as the tiled and column paths keep it
+        ga.p_init = 1;
+        ga.partials = p2;
+        launch_gather_init(ga, c->stream);
+        CHK(rec_end(c, slot));
+        ga.v = c->p1;                             // p in p1 at even, p0 at odd iterations
+        ga.v_odd = c->p0;
+        ga.out = c->q;
+        ga.p_out = nullptr;
+        ga.p_init = 0;
+        ga.partials = pq;
+        PUFoldArgs u{};
+        u.n = L.g.nnodes;
+        u.dinv = L.dinv;
+        u.r = c->r;
+        u.p0 = c->p0;
+        u.p1 = c->p1;
+        u.x = L.x;
+        u.sc = c->sc;
+        u.partials = p2;
+        b.fold = 1;
+        b.partials = p2;
+        b.pq_partials = pq;
+        b.nb_a = (int)nb_g;
+        const int hint = fixed < 0 ? L.last_iters : 0;
+        CHK(jcg_chunks_gather(c, l, u, ga, b, fixed, hint, (int)nb_g, (int)nb_b, L.spec_live));
+        launch_final_x(L.g, L.x, c->p0, c->p1, c->sc, c->sc_lv_dev + l, c->stream, !defer_x);
+        HIPCHK(c, hipGetLastError());
+        if (defer_x) c->x_pending = l;
+        return ECMG_OK;
+    }
     // folded scalars when both passes have few blocks: pass A's p.q partials
     // at the start of the buffer, init's and pass B's (r.z, r.r) pairs after
-    const int64_t nb_a = (int64_t)a.ntx * a.nty * a.nkz, nb_b = passB_blocks(L.g.nnodes);
+    const int64_t nb_a = (int64_t)a.ntx * a.nty * a.nkz;
     const bool fold = nb_a <= c->fold_max && nb_b <= c->fold_max &&
                       2 * nb_a + 2 * std::max(nb_a, nb_b) <= c->partials_n;
     if (fold) {
@@ -913,7 +1025,7 @@ static bool persist_possible(const ecmg_ctx *c, const Geom &g) {
 // kernel up to persist_max nodes.
 static bool uses_persistent(const ecmg_ctx *c, int l) {
     const Level &L = c->lv[l];
-    if (L.tune_path == 0) return false;
+    if (L.tune_path == 0 || L.tune_path == 3) return false;
     if (L.tune_path == 1) return persist_possible(c, L.g);
     return persist_possible(c, L.g) && L.g.nreal <= c->persist_max;
 }
@@ -1044,6 +1156,7 @@ void ecmg_default_options(ecmg_options *o) {
     o->true_residual = 0;
     o->batch_graph = 1;
     o->columns = 1;
+    o->gather_nodes = -1;
     o->alloc = nullptr;
     o->free = nullptr;
     o->alloc_user = nullptr;
@@ -1098,6 +1211,7 @@ int ecmg_create(const ecmg_options *opt, ecmg_ctx **out) {
     if (const char *kt = std::getenv("ECMG_KZ_TARGET")) c->kz_target = std::max(1, std::atoi(kt));
     if (o.fold_blocks >= 0) c->fold_max = std::min<int>(o.fold_blocks, FOLD_MAX_BLOCKS);
     c->col_enable = o.columns != 0;
+    if (o.gather_nodes >= 0) c->gather_max = o.gather_nodes;
     if (const char *v = std::getenv("ECMG_COL")) c->col_enable = std::atoi(v) != 0;
     if (const char *v = std::getenv("ECMG_COL_KZ")) c->col_kz = std::max(1, std::atoi(v));
     if (const char *v = std::getenv("ECMG_COL_ORDER")) c->col_order = std::min(2, std::max(0, std::atoi(v)));
@@ -1546,6 +1660,8 @@ static TuneEntry builtin_choice(const ecmg_ctx *c, int l) {
         e.path = 1;
         e.seg = seg >= 4 ? 4 : (seg >= 2 ? 2 : 1);
         e.nwg = c->persist_nwg;
+    } else if (L.g.nreal <= c->gather_max && gather_possible(c, L.g)) {
+        e.path = 3;
     } else {
         e.path = 0;
         e.kz = stencil_kz(L.g, c->KZ, c->kz_target);
@@ -1580,7 +1696,7 @@ static int apply_tune_cache(ecmg_ctx *c) {
     for (int l = 2; l < c->nlev; ++l) {
         const Level &L = c->lv[l];
         auto it = entries.find(tune_key(c->opt.precision, L.g.nx, L.g.ny, L.g.nz));
-        if (it == entries.end() || it->second.path > 1) continue;
+        if (it == entries.end() || it->second.path == 2) continue;
         const TuneEntry &e = it->second;
         CHK(apply_choice(c, l, e.path, e.kz, e.seg, e.nwg));
     }
@@ -2450,6 +2566,7 @@ int ecmg_autotune(ecmg_ctx *c, int32_t iters, const char *cache_path, ecmg_tune_
         std::vector<Cand> cands{{-1, 0, 0, 0}};   // the built-in configuration first
         for (int kz : {1, 2, 4, 8, 16, 32, 64})
             if (kz <= L.g.nz + 1) cands.push_back({0, kz, 0, 0});
+        if (gather_possible(c, L.g)) cands.push_back({3, 0, 0, 0});
         if (persist_possible(c, L.g) && L.g.nreal <= 20000000)
             for (int seg : {2, 4})
                 for (int nwg : {32, 64, 128, 256})
@@ -2467,7 +2584,7 @@ int ecmg_autotune(ecmg_ctx *c, int32_t iters, const char *cache_path, ecmg_tune_
                     break;
                 }
                 ecmg_level_info li{};
-            li.rre_true = -1.0;              // not computed by the batched form
+                li.rre_true = -1.0;
                 const int jr = run_level_jcg(c, l, 0.0, iters + 1, iters, &li);
                 if (jr == ECMG_EDEVICE) {
                     rc = jr;

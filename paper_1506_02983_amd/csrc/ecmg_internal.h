@@ -179,6 +179,9 @@ struct PassBArgs {
 // Largest pass (blocks) whose partials every block of the next pass sums
 // itself instead of a one-block finishing kernel.
 constexpr int FOLD_MAX_BLOCKS = 4096;
+// Built-in limit of the gather path (one thread per node for the stencil
+// passes, folded scalars): grids up to FOLD_MAX_BLOCKS blocks of 256 nodes.
+constexpr int64_t GATHER_DEFAULT_NODES = (int64_t)FOLD_MAX_BLOCKS * 256;
 
 // the Robin faces of a grid and the first thread of each in the face blocks
 struct ColFaces {
@@ -223,6 +226,28 @@ int col_faces(const Geom &g, ColFaces *fl);
 // sums in that order, or -1 (nothing launched) if a.R is not the mode's rows
 // per wave
 int launch_col(int mode, const ColArgs &a, hipStream_t s);
+// One thread per node (the gather levels: small grids, folded scalars).
+// Init: the ColArgs fields of MODE_INIT (v = x, out = r, p_out, p_init,
+// partials: r.z, r.r pairs).  Stencil of pass A: q = A p into out, p from v
+// (even iterations) or v_odd (odd, by sc->iter), p.q pairs into partials;
+// returns at once when sc->done is set.  Both return the partial pairs
+// written (one per block of 256 nodes).
+int gather_blocks(const Geom &g);
+int launch_gather_init(const ColArgs &a, hipStream_t s);
+int launch_gather_a(const ColArgs &a, hipStream_t s);
+// pass A of iteration `it` on the gather levels, node-wise part: the folded
+// scalar step of the previous pass from its fold_nb partial pairs, then (it
+// >= 1) p = D^-1 r + beta p_old, x += alpha p_old (the first launch of a
+// timed group)
+struct PUFoldArgs {
+    int64_t n;
+    const double *dinv, *r;
+    double *p0, *p1, *x;
+    JcgScalars *sc;
+    const double *partials;
+    int fold_nb, it;
+};
+void launch_p_update_fold(const PUFoldArgs &a, hipStream_t s);
 
 // One independent JCG solve inside the persistent kernel: a grid, its arrays,
 // its stop control, and the contiguous range of workgroups that works on it.
@@ -286,7 +311,7 @@ struct Level {
     int spec_hits = 0;                // consecutive solves that converged in exactly last_iters
     bool spec_live = false;           // the enqueued solve reads no status (its chunk is last_iters)
     // autotuned JCG configuration (tune_path -1: the built-in rules)
-    int tune_path = -1;               // 0 tiled passes, 1 persistent kernel
+    int tune_path = -1;               // 0 tiled passes, 1 persistent kernel, 3 gather stencil
     int tune_kz = 0;                  // tiled: planes per z-chunk
     int tune_seg = 0, tune_nwg = 0;   // persistent: nodes per segment, most workgroups
     // timing accumulators per kernel class
@@ -298,7 +323,8 @@ struct Ctx;
 
 // ---- autotuner: per-level choices and their JSON cache (tune_cache.cpp) ----
 struct TuneEntry {
-    int path = 0;                     // 0 tiled passes, 1 persistent kernel, 2 batched solve
+    int path = 0;                     // 0 tiled passes, 1 persistent kernel, 2 batched solve,
+                                      // 3 gather stencil (one thread per node)
     int kz = 0;                       // tiled: planes per z-chunk
     int seg = 0, nwg = 0;             // persistent: nodes per segment, most workgroups;
                                       // batched: nodes per segment (0: by box size),

@@ -791,6 +791,101 @@ __global__ void __launch_bounds__(256) k_p_update(int64_t n, const double *__res
     }
 }
 
+// The same node-wise part of pass A for the gather levels, whose scalar steps
+// are folded: iteration `it` (a launch argument) first takes the scalar step
+// of the pass before (init at it = 0, pass B after): every block sums that
+// pass's fold_nb partial pairs in one fixed order, then the stop test and
+// beta = rho_it / rho_{it-1}; block 0 stores the scalars (as the folded
+// tiled pass A does).  While running, it >= 1 forms p and x += alpha p_old;
+// at it = 0 init has stored p_0 already.
+__global__ void __launch_bounds__(256) k_p_update_fold(const PUFoldArgs a) {
+    __shared__ double red[2][4];
+    __shared__ double s_beta;
+    __shared__ int s_flag;
+    JcgScalars *sc = a.sc;
+    const int it = a.it, tid = threadIdx.x;
+    // the scalars the step reads; `done` (which block 0 may set in this
+    // launch) only through thread 0 and LDS
+    const int f_done = sc->done, f_brk = sc->brk, f_fixed = sc->fixed, f_maxit = sc->max_iter;
+    const double f_tol = sc->tol, f_alpha = sc->alpha;
+    const double f_rho_prev = it > 0 ? sc->rho_f[(it - 1) & 1] : 1.0;
+    double ft[2] = {0.0, 0.0};
+    for (int b = tid; b < a.fold_nb; b += 256) {
+        ft[0] += a.partials[2 * b];
+        ft[1] += a.partials[2 * b + 1];
+    }
+    // the vector loads (iterations >= 1) in flight during the scalar step
+    const bool first = it == 0;
+    const double2 *__restrict__ pin = (const double2 *)((it & 1) ? a.p1 : a.p0);
+    double2 *__restrict__ pout = (double2 *)((it & 1) ? a.p0 : a.p1);
+    const double2 *__restrict__ d2 = (const double2 *)a.dinv;
+    const double2 *__restrict__ r2 = (const double2 *)a.r;
+    double2 *__restrict__ x2 = (double2 *)a.x;
+    const int64_t n2 = a.n / 2;
+    const int64_t base = (int64_t)blockIdx.x * (UB * 256) + tid;
+    double2 dv[UB], rv[UB], pv[UB], xv[UB];
+    if (!first) {
+#pragma unroll
+        for (int u = 0; u < UB; ++u) {
+            const int64_t i = base + u * 256;
+            if (i < n2) {
+                dv[u] = nt_load2(d2 + i);
+                rv[u] = nt_load2(r2 + i);
+                pv[u] = nt_load2(pin + i);
+                xv[u] = nt_load2(x2 + i);
+            }
+        }
+    }
+    if (tid == 0) s_flag = f_done ? -1 : (f_brk ? -2 : 0);
+    __syncthreads();
+    const int pre = s_flag;
+    if (pre == -1) return;                        // stopped by an earlier launch
+    block_sum<2, 256>(ft, red);
+    if (tid == 0) {
+        int dn;
+        double bk = 0.0;
+        if (pre == -2) {
+            dn = DONE_BREAKDOWN;                  // the previous pass B found p.q <= 0
+        } else {
+            const double rz = ft[0], rr = ft[1], rn = sqrt(rr);
+            if (f_fixed >= 0) dn = (it >= f_fixed) ? DONE_CONVERGED : DONE_RUNNING;
+            else if (!(rn > f_tol)) dn = DONE_CONVERGED;
+            else if (it >= f_maxit) dn = DONE_MAXITER;
+            else dn = DONE_RUNNING;
+            if (it > 0) bk = rz / f_rho_prev;
+            if (blockIdx.x == 0) {
+                sc->iter = it;
+                sc->rho = rz;
+                sc->rho_f[it & 1] = rz;
+                sc->rr = rr;
+                sc->beta = bk;
+                // stopping after a pass B leaves that iteration's x update
+                sc->pending = (dn != DONE_RUNNING && it > 0) ? 1 : 0;
+            }
+        }
+        if (blockIdx.x == 0 && dn != DONE_RUNNING) sc->done = dn;
+        s_beta = bk;
+        s_flag = dn;
+    }
+    __syncthreads();
+    if (s_flag != DONE_RUNNING || first) return;
+    const double bk = s_beta;
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+        const int64_t i = base + u * 256;
+        if (i < n2) {
+            double2 pn, xn;
+            const double z0 = dv[u].x * rv[u].x, z1 = dv[u].y * rv[u].y;
+            pn.x = z0 + bk * pv[u].x;
+            pn.y = z1 + bk * pv[u].y;
+            nt_store2(pn, pout + i);
+            xn.x = xv[u].x + f_alpha * pv[u].x;
+            xn.y = xv[u].y + f_alpha * pv[u].y;
+            nt_store2(xn, x2 + i);
+        }
+    }
+}
+
 __global__ void k_jcg_reset(JcgScalars *sc, double tol, int max_iter, int fixed) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         sc->rho = sc->rr = sc->alpha = sc->beta = sc->pq = 0.0;
@@ -893,6 +988,11 @@ void launch_p_update(const Geom &g, const double *dinv, const double *r, double 
                      const JcgScalars *sc, hipStream_t s) {
     const int64_t nb = std::max<int64_t>(1, (g.nnodes / 2 + UB * 256 - 1) / (UB * 256));
     launch_timed_first(k_p_update, dim3((unsigned)nb), dim3(256), 0, s, g.nnodes, dinv, r, p0, p1, x, sc);
+}
+
+void launch_p_update_fold(const PUFoldArgs &a, hipStream_t s) {
+    const int64_t nb = std::max<int64_t>(1, (a.n / 2 + UB * 256 - 1) / (UB * 256));
+    launch_timed_first(k_p_update_fold, dim3((unsigned)nb), dim3(256), 0, s, a);
 }
 
 void launch_jcg_reset(JcgScalars *sc, double tol, int max_iter, int fixed, hipStream_t s) {

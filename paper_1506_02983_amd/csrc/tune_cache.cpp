@@ -2,7 +2,7 @@
 //
 // The file holds one object:
 //   {"format": "ecmg-tune-1", "device": "<name> <compute units> CUs",
-//    "levels": {"<precision> <nx>x<ny>x<nz>": {"path": "tiled" | "persistent",
+//    "levels": {"<precision> <nx>x<ny>x<nz>": {"path": "tiled" | "persistent" | "gather",
 //               "kz": K, "seg": S, "nwg": W, "us_default": D, "us_best": B}, ...,
 //               "batch <precision>": {"path": "batch", "seg": S, "nwg": NPW, ...}}}
 // keyed by the level's precision and elements per axis (the batched solve's
@@ -187,7 +187,7 @@ int tune_cache_read(const std::string &path, std::string *device, std::map<std::
             const JVal *pth = o.get("path");
             TuneEntry e;
             const std::string pname = (pth && pth->kind == JVal::STR) ? pth->str : std::string();
-            e.path = pname == "persistent" ? 1 : (pname == "batch" ? 2 : 0);
+            e.path = pname == "persistent" ? 1 : pname == "batch" ? 2 : pname == "gather" ? 3 : 0;
             e.kz = num_field(o, "kz", 0);
             e.seg = num_field(o, "seg", 0);
             e.nwg = num_field(o, "nwg", 0);
@@ -220,7 +220,8 @@ int tune_cache_write(const std::string &path, const std::string &device,
                           "%s\n  \"%s\": {\"path\": \"%s\", \"kz\": %d, \"seg\": %d, \"nwg\": %d, "
                           "\"us_default\": %.3f, \"us_best\": %.3f}",
                           first ? "" : ",", kv.first.c_str(),
-                          e.path == 2 ? "batch" : (e.path == 1 ? "persistent" : "tiled"), e.kz, e.seg,
+                          e.path == 3 ? "gather" : e.path == 2 ? "batch" : e.path == 1 ? "persistent" : "tiled",
+                          e.kz, e.seg,
                           e.nwg, e.us_default, e.us_best);
             f << b;
             first = false;

@@ -28,12 +28,15 @@ def _rel(a, b):
 
 
 # The JCG drivers: the whole-loop persistent kernel (forced on every grid it
-# can take), the tiled two-pass kernels with the scalar steps folded into the
-# passes (what grids of up to 4096 blocks per pass use), and the passes with
+# can take); with the scalar steps folded into the passes, the gather path
+# (one thread per node for the stencils after a node-wise p / x update: what
+# grids of up to 1,048,576 nodes use) and the tiled two-pass kernels (what the
+# grids up to 4096 blocks per pass use beyond that); and the passes with
 # one-block finishing kernels, forced here with fold_blocks = 0: by the column
 # kernels (init, and pass A as the node-wise p / x update plus the column
 # stencil: what the 257^3 and 513^3 grids use) or by the tiled kernels.
-DRIVERS = {"persistent": dict(persistent_nodes=300000), "tiled": dict(persistent_nodes=0),
+DRIVERS = {"persistent": dict(persistent_nodes=300000), "gather": dict(persistent_nodes=0),
+           "tiled": dict(persistent_nodes=0, gather_nodes=0),
            "column-unfolded": dict(persistent_nodes=0, fold_blocks=0),
            "tiled-unfolded": dict(persistent_nodes=0, fold_blocks=0, columns=False)}
 

@@ -23,7 +23,7 @@ def _solve(ecmg, s, p, eps):
     return [i["iters"] for i in infos], {l: s.get(l, ecmg.VEC_U) for l in range(p.levels)}
 
 
-@pytest.mark.parametrize("persistent", [0, -1, 300000], ids=["tiled", "default", "persistent"])
+@pytest.mark.parametrize("persistent", [0, -1, 300000], ids=["no-persistent", "default", "persistent"])
 def test_repeated_solves_match_fresh_context(ecmg, persistent):
     p = workloads.variable_beta_robin_cube(levels=5)
     fresh = {}
@@ -46,7 +46,7 @@ def test_kernel_times_count_working_launches(ecmg):
     solve whose first chunk was too long, each tiled level counts exactly its
     iterations (pass A: iteration 0 in class 10, the others in class 0)."""
     p = workloads.variable_beta_robin_cube(levels=5)
-    with ecmg.Solver(persistent_nodes=0, timing=True) as s:
+    with ecmg.Solver(persistent_nodes=0, gather_nodes=0, timing=True) as s:
         s.setup(p)
         s.solve(1e-10)
         s.reset_kernel_times()
@@ -89,12 +89,12 @@ def _stable(ecmg, s, p, eps, times=3):
         s.solve(eps)
 
 
-# the drivers a speculative level can run: tiled with folded scalar steps, the
-# persistent kernel where it is the default, and the unfolded column path of
-# the large grids (forced with fold_blocks = 0), whose last speculative pass B
-# stores no residual
-SPEC_DRIVERS = {"tiled": dict(persistent_nodes=0), "default": dict(persistent_nodes=-1),
-                "unfolded": dict(persistent_nodes=0, fold_blocks=0)}
+# the drivers a speculative level can run: tiled or gather with folded scalar
+# steps, the persistent kernel where it is the default, and the unfolded column
+# path of the large grids (forced with fold_blocks = 0), whose last speculative
+# pass B stores no residual
+SPEC_DRIVERS = {"tiled": dict(persistent_nodes=0, gather_nodes=0), "gather": dict(persistent_nodes=0),
+                "default": dict(persistent_nodes=-1), "unfolded": dict(persistent_nodes=0, fold_blocks=0)}
 
 
 @pytest.mark.parametrize("driver", list(SPEC_DRIVERS))
@@ -116,7 +116,7 @@ def test_speculative_chunk_shortfall_matches_fresh_context(ecmg, driver):
                 assert np.array_equal(u[l], fresh[1][l]), l
 
 
-@pytest.mark.parametrize("driver", ["tiled", "unfolded"])
+@pytest.mark.parametrize("driver", ["tiled", "gather", "unfolded"])
 def test_speculative_shortfall_on_a_middle_level(ecmg, driver):
     """Only level 3's tolerance tightens: level 2 keeps its speculative result,
     levels 3 and 4 are solved again; the same as a fresh context."""
@@ -153,7 +153,7 @@ def test_speculative_shortfall_on_a_middle_level(ecmg, driver):
             assert counts[12] == (1 if driver == "unfolded" and l != 3 else 0), (l, counts)
 
 
-@pytest.mark.parametrize("driver", ["tiled", "unfolded"])
+@pytest.mark.parametrize("driver", ["tiled", "gather", "unfolded"])
 def test_speculation_off_gives_the_same_iterates(ecmg, driver):
     p = workloads.variable_beta_robin_cube(levels=5)
     out = []

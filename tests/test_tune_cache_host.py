@@ -27,12 +27,14 @@ def test_lookup_entries(ecmg, tmp_path):
         "fp64 128x128x128": {"path": "tiled", "kz": 8, "seg": 0, "nwg": 0, "us_default": 61.5, "us_best": 53.25},
         "fp64 64x64x64": {"path": "persistent", "kz": 0, "seg": 4, "nwg": 128, "us_default": 41.0, "us_best": 39.5},
         "mixed 128x128x128": {"path": "tiled", "kz": 16, "seg": 0, "nwg": 0, "us_default": 40.0, "us_best": 35.0},
+        "fp64 64x32x32": {"path": "gather", "kz": 0, "seg": 0, "nwg": 0, "us_default": 12.0, "us_best": 10.5},
         "fp64 32x32x32": {"path": "tiled", "kz": 0}}})           # no usable choice: ignored
     r = ecmg.tune_lookup(path, (128, 128, 128))
     assert r["path"] == "tiled" and r["kz"] == 8 and r["us_best"] == 53.25 and r["level"] == -1
     r = ecmg.tune_lookup(path, (64, 64, 64))
     assert r["path"] == "persistent" and (r["seg"], r["nwg"]) == (4, 128)
     assert ecmg.tune_lookup(path, (128, 128, 128), precision=ecmg.MIXED)["kz"] == 16
+    assert ecmg.tune_lookup(path, (64, 32, 32))["path"] == "gather"
     assert ecmg.tune_lookup(path, (32, 32, 32)) is None
     assert ecmg.tune_lookup(path, (16, 16, 16)) is None
     assert ecmg.tune_lookup(str(tmp_path / "missing.json"), (128, 128, 128)) is None
