@@ -37,17 +37,39 @@ KIND_NAMES = {0: "jcg_pass_a", 1: "jcg_pass_b", 2: "jcg_init", 3: "exp_finite", 
 # kernel names as rocprofv3 reports them (stencil: <type, mode, rows of
 # threads, rows per thread, waves per SIMD>; column kernels: <mode, node rows
 # per wave, waves per SIMD, prefetch distance>, whose last blocks take the
-# Robin-face nodes).
-# JCG init and iteration 0 of pass A run the tiled kernel on the levels whose
-# scalars are folded into the passes, the column kernels on the larger ones;
-# there pass A of the later iterations (class 11) is the node-wise p / x update
-# and the column stencil, timed as one.  Class 12: the pass B a speculative
-# chunk expects to be the level's last (stop test only, no r stored).
-KERNEL_SYMBOL = {0: "k_stencil<double, 2, 8, 1, 4>", 1: "k_passB<double, false>",
-                 2: "k_stencil<double, 1, 8, 1, 4> | k_col<1, 2, 2, 1>",
-                 3: "k_exp_finite", 4: "k_exp_true", 5: "k_stencil<float, 2, 8, 1, 4>", 6: "k_passB<float, false>",
-                 7: "k_jcg_persistent", 10: "k_stencil<double, 3, 4, 2, 2> | k_col<3, 4, 2, 1>",
-                 11: "k_p_update + k_col<3, 4, 2, 1>", 12: "k_passB<double, true>"}
+# Robin-face nodes).  A class runs different kernels on levels that ran
+# different paths (ecmg_level_info.path): the tiled kernels with folded or
+# unfolded scalar steps, the column kernels on the large grids, the gather
+# kernels (one thread per node) on the small ones.  There pass A is a
+# node-wise p / x update followed by the stencil, timed as one (class 10 at
+# iteration 0, 11 after); class 12 is the pass B a speculative chunk expects
+# to be the level's last (stop test only, no r stored).
+def kernel_symbol(kind, path, nx, E):
+    col, gat = path == E.PATH_COLUMN, path == E.PATH_GATHER
+    if kind == 0:
+        return "k_stencil<double, 2, 8, 1, 4>"
+    if kind == 1:
+        return "k_passB<double, false>"
+    if kind == 2:
+        return "k_col<1, 2, 2, 1>" if col else "k_gather_init" if gat else "k_stencil<double, 1, 8, 1, 4>"
+    if kind == 3:
+        return "k_exp_finite<%s>" % ("true" if (nx // 4) % 64 == 0 else "false")
+    if kind == 4:
+        return "k_exp_true_fused"
+    if kind == 5:
+        return "k_stencil<float, 2, 8, 1, 4>"
+    if kind == 6:
+        return "k_passB<float, false>"
+    if kind == 7:
+        return "k_jcg_persistent"
+    if kind == 10:
+        return "k_col<3, 4, 2, 1>" if col else "k_p_update_fold + k_gather_a" if gat else \
+            "k_stencil<double, 3, 4, 2, 2>"
+    if kind == 11:
+        return "k_p_update_fold + k_gather_a" if gat else "k_p_update + k_col<3, 4, 2, 1>"
+    if kind == 12:
+        return "k_passB<double, true>"
+    return KIND_NAMES.get(kind, "?")
 
 
 def workload(name):
@@ -111,12 +133,12 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kind_name, launches_per_step):
+def measured_traffic(symbol, launches_per_step):
     """HBM bytes per launch: the kernel's HBM bytes per step from the committed
-    rocprofv3 counter summary (every dispatch of the kernel name; launches that
-    find the `done` flag set move next to nothing) over its working launches
-    per step, if the summary was taken on the current kernel source; else
-    None."""
+    rocprofv3 counter summary (every dispatch of the kernel name, or of the
+    pair timed as one; launches that find the `done` flag set move next to
+    nothing) over its working launches per step, if the summary was taken on
+    the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -124,7 +146,7 @@ def measured_traffic(kind_name, launches_per_step):
         t = json.load(fh)
     if t.get("kernel_source_hash") != kernel_source_hash():
         return None
-    k = t.get("kernels", {}).get(kind_name)
+    k = t.get("kernels", {}).get(symbol)
     if not k or not launches_per_step:
         return None
     return float(k["bytes_per_step"]) / launches_per_step
@@ -495,6 +517,9 @@ def main():
     ap.add_argument("--batch-boxes", type=int, default=512, help="boxes of the batched workload (0 = skip)")
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="measured requests of the serving replay (0 = skip), after 100 warm-up requests")
+    ap.add_argument("--roofline-kernel", default=None, metavar="SYMBOL",
+                    help="the roofline kernel (as the bench line names it) instead of the one with the largest "
+                         "total time, e.g. the choice of an unprofiled run when this run is profiled")
     ap.add_argument("--no-fourth-order", action="store_true",
                     help="skip the search for the eps that keeps the extrapolation fourth order")
     args = ap.parse_args()
@@ -566,15 +591,19 @@ def main():
             if cnt == 0:
                 continue
             b = algorithmic_bytes(k, nn, ee, n1, n0, infos_b[l]["iters"])
-            kernels.append({"level": l, "kernel": KIND_NAMES[k], "kind": k, "launches": cnt, "total_ms": ms,
-                            "avg_us": 1e3 * ms / cnt, "bytes_per_launch": b,
+            kernels.append({"level": l, "kernel": KIND_NAMES[k], "kind": k,
+                            "symbol": kernel_symbol(k, infos_b[l]["path"], nl[0], E), "launches": cnt,
+                            "total_ms": ms, "avg_us": 1e3 * ms / cnt, "bytes_per_launch": b,
                             "gbs": b / (ms / cnt * 1e-3) / 1e9, "nodes": nn})
     # the dominant kernel: largest total time, summed over all its launches
-    # (every level), as rocprofv3 reports it per kernel name
-    by_kind = {}
+    # (every level it runs on), as rocprofv3 reports it per kernel name
+    by_sym = {}
     for r in kernels:
-        by_kind[r["kind"]] = by_kind.get(r["kind"], 0.0) + r["total_ms"]
-    dkind = max(by_kind, key=by_kind.get)
+        by_sym[r["symbol"]] = by_sym.get(r["symbol"], 0.0) + r["total_ms"]
+    dsym = args.roofline_kernel if args.roofline_kernel in by_sym else max(by_sym, key=by_sym.get)
+    # the (level, class) pairs it ran as (a pair of kernels can serve two classes)
+    dpairs = sorted({(r["level"], r["kind"]) for r in kernels if r["symbol"] == dsym})
+    dkinds = sorted({k for _, k in dpairs})
 
     # timed region: no events (a timed launch costs about 5 us more, which the
     # launch-bound levels would add to the step)
@@ -593,7 +622,7 @@ def main():
 
     # roofline region: the same steps again with events (stamped by each
     # launch of the dominant kernel itself) around that kernel only
-    s.set_timing([dkind])
+    s.set_timing(dkinds)
     s.reset_kernel_times()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -603,7 +632,7 @@ def main():
     region_ms = 1e3 * (time.perf_counter() - t0) / args.steps
 
     d = {"total_ms": 0.0, "launches": 0, "bytes": 0.0}
-    for l in range(problem.levels):
+    for l, dkind in dpairs:
         ms, cnt = s.kernel_times(l, dkind)
         if cnt == 0:
             continue
@@ -616,18 +645,19 @@ def main():
         d["bytes"] += b * cnt
     s.set_timing(-1)
     achieved = d["bytes"] / (d["total_ms"] * 1e-3) / 1e9
-    traffic = measured_traffic(KIND_NAMES[dkind], d["launches"] / args.steps)
+    traffic = measured_traffic(dsym, d["launches"] / args.steps)
     traffic = round(traffic) if traffic else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": KERNEL_SYMBOL[dkind], "launches": d["launches"],
+                "kernel": dsym, "classes": [KIND_NAMES[k] for k in dkinds],
+                "levels": sorted({l for l, _ in dpairs}), "launches": d["launches"],
                 "avg_us": round(1e3 * d["total_ms"] / d["launches"], 2),
                 "bytes_per_launch": round(d["bytes"] / d["launches"]),
                 "region": "%d steps after the timed ones, HIP events only around this kernel's launches "
                           "(%.3f ms/step)" % (args.steps, region_ms)}
     # the finest level's kernels against the same HBM peak (from the breakdown
     # steps: every launch stamped; algorithmic bytes as above)
-    finest = [{"kernel": r["kernel"], "symbol": KERNEL_SYMBOL[r["kind"]].split(" | ")[-1], "launches": r["launches"],
+    finest = [{"kernel": r["kernel"], "symbol": r["symbol"], "launches": r["launches"],
                "avg_us": round(r["avg_us"], 2), "achieved": round(r["gbs"], 1),
                "frac": round(r["gbs"] / HBM_PEAK_GBS, 4), "bytes_per_launch": r["bytes_per_launch"]}
               for r in kernels if r["level"] == L]

@@ -91,6 +91,23 @@ extern "C" {
                                Dirichlet nodes                                            */
 #define ECMG_VEC_NONE  -1
 
+/* ecmg_level_info.path: the kernels a level ran on.  DENSE: DSOLVE by the
+ * explicit inverse (a GEMV); PERSISTENT: the whole JCG in one cooperative
+ * launch; TILED: tiled stencil passes with the scalar steps folded into them;
+ * TILED_UNFOLDED: tiled passes with one-block finishing kernels; COLUMN:
+ * column kernels for init and the stencil of pass A (finishing kernels);
+ * GATHER: one thread per node for init and the stencil of pass A (folded
+ * scalars); MIXED: FP32 JCG inside FP64 refinement; QUEUE: the batched queue
+ * kernel (ecmg_solve_batch, the serving loop). */
+#define ECMG_PATH_DENSE          0
+#define ECMG_PATH_PERSISTENT     1
+#define ECMG_PATH_TILED          2
+#define ECMG_PATH_TILED_UNFOLDED 3
+#define ECMG_PATH_COLUMN         4
+#define ECMG_PATH_GATHER         5
+#define ECMG_PATH_MIXED          6
+#define ECMG_PATH_QUEUE          7
+
 /* Field sampled on a tensor product of coordinates.  The library asks for
  * out[(k*ny + j)*nx + i] = value at (x[i], y[j], z[k]).  face = -1 for points
  * inside the box, 0..5 when every point lies on that face (Robin data needs the
@@ -231,7 +248,7 @@ typedef struct {
                                   for the dense direct solve)                           */
     int32_t outer_steps;       /* ECMG_MIXED: FP64 refinement steps; else 0            */
     int32_t status;            /* ECMG_OK, ECMG_ENOTCONV or ECMG_EBREAKDOWN            */
-    int32_t reserved;
+    int32_t path;              /* how the level ran (ECMG_PATH_*)                        */
     double rre;                /* ||r||_2 / ||f_h||_2 at exit (recurrence residual)     */
     double nf;                 /* ||f_h||_2 of the stopping test                        */
     double ms;                 /* wall time of the level on the device stream          */

@@ -31,6 +31,8 @@ FP64, MIXED = 0, 1
 SERENDIPITY20, LAGRANGE27 = 0, 1
 JCG, CG = 0, 1                      # iteration on the JCG levels: ECMG_jcg / ECMG_cg
 VEC_U, VEC_W, VEC_UTILDE, VEC_F, VEC_DINV, VEC_NONE = 0, 1, 2, 3, 4, -1
+# ecmg_level_info.path: the kernels a level ran on
+PATH_DENSE, PATH_PERSISTENT, PATH_TILED, PATH_TILED_UNFOLDED, PATH_COLUMN, PATH_GATHER, PATH_MIXED, PATH_QUEUE = range(8)
 K_PASSA, K_PASSB, K_INIT, K_EXPF, K_EXPT, K_PASSA32, K_PASSB32, K_PERSIST, K_MIXSTART, K_MIXUPDATE = range(10)
 
 _STATUS = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", ENOTCONV: "ENOTCONV", EBREAKDOWN: "EBREAKDOWN",
@@ -82,11 +84,11 @@ class TuneResult(ctypes.Structure):
 class LevelInfo(ctypes.Structure):
     _fields_ = [("level", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("iters", ctypes.c_int32), ("outer_steps", ctypes.c_int32), ("status", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("rre", ctypes.c_double), ("nf", ctypes.c_double),
+                ("path", ctypes.c_int32), ("rre", ctypes.c_double), ("nf", ctypes.c_double),
                 ("ms", ctypes.c_double), ("rre_true", ctypes.c_double)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 # Every symbol include/ecmg.h declares (checked by the CPU test suite).

@@ -739,6 +739,7 @@ static int run_jcg_mixed(ecmg_ctx *c, int l, double tol_abs, int max_iter, ecmg_
         info->rre = (L.nf > 0) ? rn / L.nf : 0.0;
         info->nf = L.nf;
         info->status = status;
+        info->path = ECMG_PATH_MIXED;
     }
     if (status == ECMG_EBREAKDOWN) return fail(c, status, "mixed JCG breakdown on level %d", l);
     if (status == ECMG_ENOTCONV)
@@ -757,6 +758,7 @@ static int jcg_result(ecmg_ctx *c, int l, const JcgScalars &s, int max_iter, boo
         info->nf = L.nf;
         info->status = (s.done == DONE_BREAKDOWN) ? ECMG_EBREAKDOWN
                        : (s.done == DONE_MAXITER) ? ECMG_ENOTCONV : ECMG_OK;
+        info->path = L.last_path;
     }
     if (s.done == DONE_BREAKDOWN) return fail(c, ECMG_EBREAKDOWN, "JCG breakdown on level %d (p.q = %g)", l, s.pq);
     if (s.done == DONE_MAXITER)
@@ -838,6 +840,7 @@ static int enqueue_jcg(ecmg_ctx *c, int l, double tol_abs, int max_iter, int fix
     // the gather levels: init and the stencil of every pass A one thread per
     // node, the node-wise p update taking the folded scalar step
     if (gather_level(c, L)) {
+        L.last_path = ECMG_PATH_GATHER;
         const int64_t nb_g = gather_blocks(L.g);
         CHK(ensure_partials(c, 2 * nb_g + 2 * std::max(nb_g, nb_b)));
         double *pq = c->partials, *p2 = c->partials + 2 * nb_g;   // gather p.q; init / pass B pairs
@@ -900,6 +903,7 @@ static int enqueue_jcg(ecmg_ctx *c, int l, double tol_abs, int max_iter, int fix
     ColArgs ca{};
     int cw = 0;
     const bool col = !fold && col_usable(c, L.g);
+    L.last_path = fold ? ECMG_PATH_TILED : col ? ECMG_PATH_COLUMN : ECMG_PATH_TILED_UNFOLDED;
     ColArgs ca0{};                                // iteration 0 (its own rows per wave)
     int cw0 = 0;
     if (col) {
@@ -965,6 +969,7 @@ static int run_jcg(ecmg_ctx *c, int l, double tol_abs, int max_iter, int fixed, 
 // scalars come back into the level's scalar slot.
 static int enqueue_jcg_persistent(ecmg_ctx *c, int l, double tol_abs, int max_iter, int fixed) {
     Level &L = c->lv[l];
+    L.last_path = ECMG_PATH_PERSISTENT;
     PersistentTask &t = c->task_lv[l];
     t = PersistentTask{};
     t.g = L.g;
@@ -1631,6 +1636,7 @@ static int run_dsolve_dense(ecmg_ctx *c, int l, ecmg_level_info *info) {
         info->rre = 0.0;
         info->nf = L.nf;
         info->status = ECMG_OK;
+        info->path = ECMG_PATH_DENSE;
     }
     return ECMG_OK;
 }
@@ -2241,6 +2247,7 @@ int ecmg_solve_batch(ecmg_ctx *const *ctxs, int32_t n, double rel_tol, ecmg_leve
             int st = (sc.done == DONE_BREAKDOWN) ? ECMG_EBREAKDOWN : (sc.done == DONE_MAXITER) ? ECMG_ENOTCONV : ECMG_OK;
             if (l < 2 && st == ECMG_ENOTCONV) st = ECMG_OK;   // DSOLVE: the iterate at the cap is kept
             li.status = st;
+            li.path = ECMG_PATH_QUEUE;
             if (infos) infos[info_off[V.owner[k]] + l] = li;
             if (st != ECMG_OK && worst == ECMG_OK) worst = st;
         }
@@ -3028,6 +3035,7 @@ static int server_tick(ecmg_server *S) {
         int st = (sc.done == DONE_BREAKDOWN) ? ECMG_EBREAKDOWN : (sc.done == DONE_MAXITER) ? ECMG_ENOTCONV : ECMG_OK;
         if (l < 2 && st == ECMG_ENOTCONV) st = ECMG_OK;
         li.status = st;
+        li.path = ECMG_PATH_QUEUE;
         r->info[l] = li;
     }
     for (ServerReq *r : S->active) {

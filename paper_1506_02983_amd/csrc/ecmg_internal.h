@@ -308,6 +308,7 @@ struct Level {
     float *dinv32 = nullptr;
     double nf = 0.0;                  // ||f_h||_2 of the stopping test
     int last_iters = -1;              // JCG iterations of the last converged solve (first chunk)
+    int last_path = -1;               // ECMG_PATH_* of the last JCG enqueued on the level
     int spec_hits = 0;                // consecutive solves that converged in exactly last_iters
     bool spec_live = false;           // the enqueued solve reads no status (its chunk is last_iters)
     // autotuned JCG configuration (tune_path -1: the built-in rules)

@@ -74,6 +74,18 @@ CASES = {
 
 
 @pytest.mark.parametrize("driver", list(DRIVERS))
+def test_level_info_names_the_driver(ecmg, driver):
+    """ecmg_level_info.path reports the kernels each level ran on."""
+    p = workloads.variable_beta_robin_cube(levels=4)
+    want = {"persistent": ecmg.PATH_PERSISTENT, "gather": ecmg.PATH_GATHER, "tiled": ecmg.PATH_TILED,
+            "column-unfolded": ecmg.PATH_COLUMN, "tiled-unfolded": ecmg.PATH_TILED_UNFOLDED}[driver]
+    with ecmg.Solver(**DRIVERS[driver]) as s:
+        s.setup(p)
+        infos = s.solve(1e-8)
+    assert [i["path"] for i in infos] == [ecmg.PATH_DENSE] * 2 + [want] * (p.levels - 2)
+
+
+@pytest.mark.parametrize("driver", list(DRIVERS))
 @pytest.mark.parametrize("name", list(CASES))
 def test_cascade_fixed_iterations(orc, ecmg, name, driver):
     """Every JCG driver (DRIVERS) with device-side stop control."""
