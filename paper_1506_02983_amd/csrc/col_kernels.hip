@@ -472,6 +472,17 @@ __device__ __forceinline__ double gather_q(const ColArgs &a, int i, int j, int k
     const double l00 = be(i - 1, j - 1, k - 1), l01 = be(i, j - 1, k - 1), l10 = be(i - 1, j, k - 1),
                  l11 = be(i, j, k - 1);
     const double u00 = be(i - 1, j - 1, k), u01 = be(i, j - 1, k), u10 = be(i - 1, j, k), u11 = be(i, j, k);
+    // all 27 values loaded before any is used: one memory round trip
+    double pv[3][3][3];                           // [z][y][x] offsets + 1
+#pragma unroll
+    for (int oz = 0; oz < 3; ++oz)
+#pragma unroll
+        for (int oy = 0; oy < 3; ++oy)
+#pragma unroll
+            for (int ox = 0; ox < 3; ++ox) pv[oz][oy][ox] = v(xo[ox] + yo[oy] + zo[oz]);
+    // keep the scheduler from interleaving the loads with their uses (it
+    // otherwise splits them into two dependent rounds)
+    __builtin_amdgcn_sched_barrier(0);
     double q = 0.0;
 #pragma unroll
     for (int oy = -1; oy <= 1; ++oy)
@@ -488,8 +499,8 @@ __device__ __forceinline__ double gather_q(const ColArgs &a, int i, int j, int k
             else if (ox > 0) { sl = l01 + l11; su = u01 + u11; }
             else { sl = (l00 + l01) + (l10 + l11); su = (u00 + u01) + (u10 + u11); }
             const int m = (ox != 0) | ((oy != 0) << 1);
-            const int row = xo[ox + 1] + yo[oy + 1];
-            q += g.C[m | 4] * (sl * v(row + zo[0]) + su * v(row + zo[2])) + g.C[m] * ((sl + su) * v(row + zo[1]));
+            q += g.C[m | 4] * (sl * pv[0][oy + 1][ox + 1] + su * pv[2][oy + 1][ox + 1]) +
+                 g.C[m] * ((sl + su) * pv[1][oy + 1][ox + 1]);
         }
     const int ijk[3] = {i, j, k}, n3[3] = {g.nx, g.ny, g.nz};
     for (int f = 0; f < 6; ++f) {
@@ -552,10 +563,11 @@ __global__ void __launch_bounds__(256) k_gather_init(const ColArgs a) {
         const int id = i + g.sx * j + g.sx * g.sy * k;
         const double *__restrict__ x = a.v;
         const bool dir = dir_node(g, i, j, k);
+        const double fv = a.F[id], dv = a.dinv[id];   // issued with the row's loads
         const double q = dir ? 0.0 : gather_q(a, i, j, k, [&](int idx) { return x[idx]; });
-        const double rv = dir ? 0.0 : a.F[id] - q;
+        const double rv = dir ? 0.0 : fv - q;
         __builtin_nontemporal_store(rv, a.out + id);
-        const double z = a.dinv[id] * rv;
+        const double z = dv * rv;
         if (a.p_init) __builtin_nontemporal_store(z, a.p_out + id);
         acc0 += rv * z;
         acc1 += rv * rv;
