@@ -28,6 +28,17 @@ namespace ecmg {
 
 namespace {
 
+// the iteration index (x) and the `done` flag (y) of the JCG scalars in one
+// load (a launch's first dependent read: one round trip instead of two)
+__device__ __forceinline__ int2 iter_done(const JcgScalars *sc) {
+    static_assert(offsetof(JcgScalars, done) == offsetof(JcgScalars, iter) + 4 && offsetof(JcgScalars, iter) % 8 == 0,
+                  "iter and done adjacent");
+    // an atomic 64-bit load, which the compiler cannot split into two
+    const unsigned long long w = __hip_atomic_load(reinterpret_cast<const unsigned long long *>(&sc->iter),
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return make_int2((int)(unsigned)w, (int)(unsigned)(w >> 32));
+}
+
 // lane i receives lane i-1 (DPP wave_shr:1); lane 0 receives 0 (bound_ctrl)
 __device__ __forceinline__ double from_left(double v) {
     const int lo = __builtin_amdgcn_mov_dpp((int)__double2loint(v), 0x138, 0xf, 0xf, true);
@@ -342,9 +353,10 @@ template <int MODE, int R, int WPE, int D>
 __global__ void __launch_bounds__(256, WPE) k_col(const ColArgs a) {
     constexpr int NR = D + 3;
     const Geom &g = a.g;
-    if (MODE == MODE_PASSA0 && a.sc->done) return;      // uniform over the grid
+    const int2 itd = MODE == MODE_PASSA0 ? iter_done(a.sc) : make_int2(0, 0);
+    if (itd.y) return;                            // done: uniform over the grid
     // iterations >= 1 alternate the direction buffers (the iteration's parity)
-    const double *__restrict__ vin = (MODE == MODE_PASSA0 && a.v_odd && (a.sc->iter & 1)) ? a.v_odd : a.v;
+    const double *__restrict__ vin = (MODE == MODE_PASSA0 && a.v_odd && (itd.x & 1)) ? a.v_odd : a.v;
     if ((int)blockIdx.x >= a.ncb) {               // the Robin-face blocks (uniform per block)
         col_face_block<MODE>(a, vin, (int)blockIdx.x - a.ncb, a.ntx * a.nty * a.nkz);
         return;
@@ -583,8 +595,9 @@ __global__ void __launch_bounds__(256) k_gather_init(const ColArgs a) {
 __global__ void __launch_bounds__(256) k_gather_a(const ColArgs a) {
     __shared__ double red[2][4];
     const Geom &g = a.g;
-    if (a.sc->done) return;                       // uniform over the grid
-    const double *__restrict__ vin = (a.v_odd && (a.sc->iter & 1)) ? a.v_odd : a.v;
+    const int2 itd = iter_done(a.sc);
+    if (itd.y) return;                            // done: uniform over the grid
+    const double *__restrict__ vin = (a.v_odd && (itd.x & 1)) ? a.v_odd : a.v;
     double acc0 = 0.0;
     int i, j, k;
     if (gather_node(g, (int64_t)blockIdx.x * 256 + threadIdx.x, i, j, k)) {
