@@ -475,8 +475,9 @@ int ecmg_plan_bytes(const ecmg_problem *problem, int32_t precision, size_t *byte
  * to FP32), 9 = mixed-precision update x += ||r|| d, 10 = JCG pass A of
  * iteration 0, which reads the p_0 that init stored; class 0 counts the later
  * iterations, 11 = JCG pass A of iterations >= 1 on the levels that run the
- * column kernels: the node-wise p and x update, then the column stencil,
- * timed from the start of the first kernel to the end of the second, 12 =
+ * column or the gather kernels (ecmg_level_info.path): the node-wise p and x
+ * update, then the stencil, timed from the start of the first kernel to the
+ * end of the second (on the gather levels class 10 is timed the same way), 12 =
  * the JCG pass B a level solved without status reads expects to be its
  * last (options.speculate): it takes the stop test without storing r or
  * forming r.z, since nothing reads them if the test passes and the level is
