@@ -63,6 +63,7 @@ def test_batch_matches_single_solver(ecmg, boxes):
             s.extrapolate(2, out=False)
             assert _rel(out[i][1], s.get(2, ecmg.VEC_UTILDE)) <= 1e-12, i
         assert all(x["status"] == 0 for x in infos[i])
+        assert all(x["path"] == ecmg.PATH_QUEUE for x in infos[i]), infos[i]
 
 
 def test_batch_parity_with_oracle(orc, ecmg, boxes):

@@ -75,10 +75,12 @@ def test_mixed_default_levels_and_fixed_mode(orc, ecmg):
         s.setup(p)
         infos = s.solve(1e-10)
         assert all(i["outer_steps"] == 0 for i in infos), infos
+        assert all(i["path"] != ecmg.PATH_MIXED for i in infos), infos
     with ecmg.Solver(precision=ecmg.MIXED, persistent_nodes=0) as s:
         s.setup(p)
         infos = s.solve(1e-10)
         assert all(i["outer_steps"] >= 1 for i in infos[2:]), infos
+        assert all(i["path"] == ecmg.PATH_MIXED for i in infos[2:]), infos
     with ecmg.Solver(precision=ecmg.MIXED, persistent_nodes=0) as s:
         s.setup(p)
         infos = s.solve_fixed([0, 0, 3, 2])

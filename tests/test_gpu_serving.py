@@ -70,6 +70,12 @@ def test_request_same_alone_and_in_mix(ecmg, requests, persistent):
         alone, _ = _run(ecmg, [requests[i]], persistent_nodes=persistent)
         assert [x["iters"] for x in alone[0][1]] == [x["iters"] for x in mix[i][1]]
         assert np.array_equal(alone[0][0], mix[i][0]), i
+        # the levels in the shared queue launches, and the larger ones (queue+tiled)
+        # on their own kernels: the gather path at these sizes
+        p = requests[i]
+        want = [ecmg.PATH_QUEUE if persistent < 0 or p.nodes_at(l) <= persistent else ecmg.PATH_GATHER
+                for l in range(p.levels)]
+        assert [x["path"] for x in mix[i][1]] == want, (i, [x["path"] for x in mix[i][1]])
 
 
 def test_budget_admission_queues_and_matches(ecmg, requests):
