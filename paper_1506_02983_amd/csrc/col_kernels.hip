@@ -239,6 +239,109 @@ __device__ __forceinline__ void col_step(const ColArgs &a, const double *__restr
     }
 }
 
+// The 27-point row of node (i, j, k), read from global memory through v(idx)
+// (the input value at flat node index idx): the stencil with the betas of the
+// 8 surrounding elements plus the face-mass terms of every Robin face the
+// node lies on.  Neighbour indices are clamped to the grid (an outside
+// neighbour couples only through outside elements, whose beta is 0).
+template <class V>
+__device__ __forceinline__ double gather_q(const ColArgs &a, int i, int j, int k, V v) {
+    const Geom &g = a.g;
+    const int sx = g.sx, sxy = g.sx * g.sy, exy = g.nx * g.ny;
+    int xo[3], yo[3], zo[3];
+#pragma unroll
+    for (int o = 0; o < 3; ++o) {
+        xo[o] = min(max(i - 1 + o, 0), g.nx);
+        yo[o] = sx * min(max(j - 1 + o, 0), g.ny);
+        zo[o] = sxy * min(max(k - 1 + o, 0), g.nz);
+    }
+    auto be = [&](int ii, int jj, int kk) -> double {
+        const bool ok = ii >= 0 && ii < g.nx && jj >= 0 && jj < g.ny && kk >= 0 && kk < g.nz;
+        const double b = a.beta[min(max(ii, 0), g.nx - 1) + g.nx * min(max(jj, 0), g.ny - 1) +
+                                exy * min(max(kk, 0), g.nz - 1)];
+        return ok ? b : 0.0;
+    };
+    const double l00 = be(i - 1, j - 1, k - 1), l01 = be(i, j - 1, k - 1), l10 = be(i - 1, j, k - 1),
+                 l11 = be(i, j, k - 1);
+    const double u00 = be(i - 1, j - 1, k), u01 = be(i, j - 1, k), u10 = be(i - 1, j, k), u11 = be(i, j, k);
+    // all 27 values loaded before any is used: one memory round trip
+    double pv[3][3][3];                           // [z][y][x] offsets + 1
+#pragma unroll
+    for (int oz = 0; oz < 3; ++oz)
+#pragma unroll
+        for (int oy = 0; oy < 3; ++oy)
+#pragma unroll
+            for (int ox = 0; ox < 3; ++ox) pv[oz][oy][ox] = v(xo[ox] + yo[oy] + zo[oz]);
+    // keep the scheduler from interleaving the loads with their uses (it
+    // otherwise splits them into two dependent rounds)
+    __builtin_amdgcn_sched_barrier(0);
+    double q = 0.0;
+#pragma unroll
+    for (int oy = -1; oy <= 1; ++oy)
+#pragma unroll
+        for (int ox = -1; ox <= 1; ++ox) {
+            double sl, su;
+            if (oy < 0 && ox < 0) { sl = l00; su = u00; }
+            else if (oy < 0 && ox > 0) { sl = l01; su = u01; }
+            else if (oy > 0 && ox < 0) { sl = l10; su = u10; }
+            else if (oy > 0 && ox > 0) { sl = l11; su = u11; }
+            else if (oy < 0) { sl = l00 + l01; su = u00 + u01; }
+            else if (oy > 0) { sl = l10 + l11; su = u10 + u11; }
+            else if (ox < 0) { sl = l00 + l10; su = u00 + u10; }
+            else if (ox > 0) { sl = l01 + l11; su = u01 + u11; }
+            else { sl = (l00 + l01) + (l10 + l11); su = (u00 + u01) + (u10 + u11); }
+            const int m = (ox != 0) | ((oy != 0) << 1);
+            q += g.C[m | 4] * (sl * pv[0][oy + 1][ox + 1] + su * pv[2][oy + 1][ox + 1]) +
+                 g.C[m] * ((sl + su) * pv[1][oy + 1][ox + 1]);
+        }
+    const int ijk[3] = {i, j, k}, n3[3] = {g.nx, g.ny, g.nz};
+    for (int f = 0; f < 6; ++f) {
+        const int ax = f / 2;
+        if (g.ft[f] != ECMG_ROBIN || ijk[ax] != ((f & 1) ? n3[ax] : 0)) continue;
+        const int pa = ax == 0 ? 1 : 0, qa = ax == 2 ? 1 : 2;
+        auto nb = [&](int op, int oq) -> double {
+            int c[3] = {i, j, k};
+            c[pa] += op;
+            c[qa] += oq;
+            return v(c[0] + sx * c[1] + sxy * c[2]);
+        };
+        q += robin_col(g, f, a.alpha[f], ijk[pa], ijk[qa], n3[pa], n3[qa], nb);
+    }
+    return q;
+}
+
+// block partials in a fixed order (lanes, then the 4 waves): acc0 (and acc1
+// if TWO) of the block into slot[0] (slot[1])
+template <bool TWO>
+__device__ __forceinline__ void block_partials(double acc0, double acc1, double *slot, double (*red)[4]) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        acc0 += __shfl_xor(acc0, off, 64);
+        acc1 += __shfl_xor(acc1, off, 64);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[0][w] = acc0;
+        red[1][w] = acc1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        slot[0] = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
+        if (TWO) slot[1] = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
+    }
+}
+
+// node of thread t of a launch over the grid's nodes (x fastest); false past the end
+__device__ __forceinline__ bool gather_node(const Geom &g, int64_t t, int &i, int &j, int &k) {
+    const int nxp = g.nx + 1, nyp = g.ny + 1;
+    if (t >= (int64_t)nxp * nyp * (g.nz + 1)) return false;
+    i = (int)(t % nxp);
+    const int64_t rw = t / nxp;
+    j = (int)(rw % nyp);
+    k = (int)(rw / nyp);
+    return true;
+}
+
 // The nodes on a Robin face (and on no Dirichlet face), which the column
 // waves leave out: each is taken by the first Robin face (in face order) that
 // holds it, one thread per node, with its full row -- the 27-point stencil read
@@ -270,46 +373,7 @@ __device__ __forceinline__ void col_face_block(const ColArgs &a, const double *_
             if (g.ft[f2] == ECMG_ROBIN && ijk[f2 / 2] == ((f2 & 1) ? n3[f2 / 2] : 0)) skip = true;
         if (!skip) {
             const int sx = g.sx, sxy = g.sx * g.sy;
-            auto v = [&](int ii, int jj, int kk) -> double {
-                if (ii < 0 || ii > g.nx || jj < 0 || jj > g.ny || kk < 0 || kk > g.nz) return 0.0;
-                return vin[ii + sx * jj + sxy * kk];
-            };
-            auto be = [&](int ii, int jj, int kk) -> double {
-                if (ii < 0 || ii >= g.nx || jj < 0 || jj >= g.ny || kk < 0 || kk >= g.nz) return 0.0;
-                return a.beta[ii + g.nx * jj + g.nx * g.ny * kk];
-            };
-            const double l00 = be(i - 1, j - 1, k - 1), l01 = be(i, j - 1, k - 1), l10 = be(i - 1, j, k - 1),
-                         l11 = be(i, j, k - 1);
-            const double u00 = be(i - 1, j - 1, k), u01 = be(i, j - 1, k), u10 = be(i - 1, j, k), u11 = be(i, j, k);
-            double q = 0.0;
-            for (int oy = -1; oy <= 1; ++oy)
-                for (int ox = -1; ox <= 1; ++ox) {
-                    double sl, su;
-                    if (oy < 0 && ox < 0) { sl = l00; su = u00; }
-                    else if (oy < 0 && ox > 0) { sl = l01; su = u01; }
-                    else if (oy > 0 && ox < 0) { sl = l10; su = u10; }
-                    else if (oy > 0 && ox > 0) { sl = l11; su = u11; }
-                    else if (oy < 0) { sl = l00 + l01; su = u00 + u01; }
-                    else if (oy > 0) { sl = l10 + l11; su = u10 + u11; }
-                    else if (ox < 0) { sl = l00 + l10; su = u00 + u10; }
-                    else if (ox > 0) { sl = l01 + l11; su = u01 + u11; }
-                    else { sl = (l00 + l01) + (l10 + l11); su = (u00 + u01) + (u10 + u11); }
-                    const int m = (ox != 0) | ((oy != 0) << 1);
-                    q += g.C[m | 4] * (sl * v(i + ox, j + oy, k - 1) + su * v(i + ox, j + oy, k + 1)) +
-                         g.C[m] * ((sl + su) * v(i + ox, j + oy, k));
-                }
-            for (int f2 = 0; f2 < 6; ++f2) {     // face-mass terms of every Robin face the node is on
-                const int a2 = f2 / 2;
-                if (g.ft[f2] != ECMG_ROBIN || ijk[a2] != ((f2 & 1) ? n3[a2] : 0)) continue;
-                const int p2 = a2 == 0 ? 1 : 0, q2 = a2 == 2 ? 1 : 2;
-                auto nb = [&](int op, int oq) -> double {
-                    int c[3] = {i, j, k};
-                    c[p2] += op;
-                    c[q2] += oq;
-                    return v(c[0], c[1], c[2]);
-                };
-                q += robin_col(g, f2, a.alpha[f2], ijk[p2], ijk[q2], n3[p2], n3[q2], nb);
-            }
+            const double q = gather_q(a, i, j, k, [&](int idx) { return vin[idx]; });
             const int id = i + sx * j + sxy * k;
             if (MODE == MODE_APPLY) {
                 __builtin_nontemporal_store(q, a.out + id);
@@ -327,23 +391,7 @@ __device__ __forceinline__ void col_face_block(const ColArgs &a, const double *_
         }
     }
     if (MODE == MODE_APPLY) return;
-    // block partials in a fixed order: lanes, then the 4 waves
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        acc0 += __shfl_xor(acc0, off, 64);
-        acc1 += __shfl_xor(acc1, off, 64);
-    }
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        red[0][w] = acc0;
-        red[1][w] = acc1;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        a.partials[2 * ((int64_t)part_off + bid)] = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
-        if (MODE == MODE_INIT)
-            a.partials[2 * ((int64_t)part_off + bid) + 1] = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
-    }
+    block_partials<MODE == MODE_INIT>(acc0, acc1, a.partials + 2 * ((int64_t)part_off + bid), red);
 }
 
 // WPE: waves per SIMD the register budget is set for (init, 2 rows: 150
@@ -459,109 +507,6 @@ __global__ void __launch_bounds__(256, WPE) k_col(const ColArgs a) {
     }
 }
 
-// The 27-point row of node (i, j, k), read from global memory through v(idx)
-// (the input value at flat node index idx): the stencil with the betas of the
-// 8 surrounding elements plus the face-mass terms of every Robin face the
-// node lies on.  Neighbour indices are clamped to the grid (an outside
-// neighbour couples only through outside elements, whose beta is 0).
-template <class V>
-__device__ __forceinline__ double gather_q(const ColArgs &a, int i, int j, int k, V v) {
-    const Geom &g = a.g;
-    const int sx = g.sx, sxy = g.sx * g.sy, exy = g.nx * g.ny;
-    int xo[3], yo[3], zo[3];
-#pragma unroll
-    for (int o = 0; o < 3; ++o) {
-        xo[o] = min(max(i - 1 + o, 0), g.nx);
-        yo[o] = sx * min(max(j - 1 + o, 0), g.ny);
-        zo[o] = sxy * min(max(k - 1 + o, 0), g.nz);
-    }
-    auto be = [&](int ii, int jj, int kk) -> double {
-        const bool ok = ii >= 0 && ii < g.nx && jj >= 0 && jj < g.ny && kk >= 0 && kk < g.nz;
-        const double b = a.beta[min(max(ii, 0), g.nx - 1) + g.nx * min(max(jj, 0), g.ny - 1) +
-                                exy * min(max(kk, 0), g.nz - 1)];
-        return ok ? b : 0.0;
-    };
-    const double l00 = be(i - 1, j - 1, k - 1), l01 = be(i, j - 1, k - 1), l10 = be(i - 1, j, k - 1),
-                 l11 = be(i, j, k - 1);
-    const double u00 = be(i - 1, j - 1, k), u01 = be(i, j - 1, k), u10 = be(i - 1, j, k), u11 = be(i, j, k);
-    // all 27 values loaded before any is used: one memory round trip
-    double pv[3][3][3];                           // [z][y][x] offsets + 1
-#pragma unroll
-    for (int oz = 0; oz < 3; ++oz)
-#pragma unroll
-        for (int oy = 0; oy < 3; ++oy)
-#pragma unroll
-            for (int ox = 0; ox < 3; ++ox) pv[oz][oy][ox] = v(xo[ox] + yo[oy] + zo[oz]);
-    // keep the scheduler from interleaving the loads with their uses (it
-    // otherwise splits them into two dependent rounds)
-    __builtin_amdgcn_sched_barrier(0);
-    double q = 0.0;
-#pragma unroll
-    for (int oy = -1; oy <= 1; ++oy)
-#pragma unroll
-        for (int ox = -1; ox <= 1; ++ox) {
-            double sl, su;
-            if (oy < 0 && ox < 0) { sl = l00; su = u00; }
-            else if (oy < 0 && ox > 0) { sl = l01; su = u01; }
-            else if (oy > 0 && ox < 0) { sl = l10; su = u10; }
-            else if (oy > 0 && ox > 0) { sl = l11; su = u11; }
-            else if (oy < 0) { sl = l00 + l01; su = u00 + u01; }
-            else if (oy > 0) { sl = l10 + l11; su = u10 + u11; }
-            else if (ox < 0) { sl = l00 + l10; su = u00 + u10; }
-            else if (ox > 0) { sl = l01 + l11; su = u01 + u11; }
-            else { sl = (l00 + l01) + (l10 + l11); su = (u00 + u01) + (u10 + u11); }
-            const int m = (ox != 0) | ((oy != 0) << 1);
-            q += g.C[m | 4] * (sl * pv[0][oy + 1][ox + 1] + su * pv[2][oy + 1][ox + 1]) +
-                 g.C[m] * ((sl + su) * pv[1][oy + 1][ox + 1]);
-        }
-    const int ijk[3] = {i, j, k}, n3[3] = {g.nx, g.ny, g.nz};
-    for (int f = 0; f < 6; ++f) {
-        const int ax = f / 2;
-        if (g.ft[f] != ECMG_ROBIN || ijk[ax] != ((f & 1) ? n3[ax] : 0)) continue;
-        const int pa = ax == 0 ? 1 : 0, qa = ax == 2 ? 1 : 2;
-        auto nb = [&](int op, int oq) -> double {
-            int c[3] = {i, j, k};
-            c[pa] += op;
-            c[qa] += oq;
-            return v(c[0] + sx * c[1] + sxy * c[2]);
-        };
-        q += robin_col(g, f, a.alpha[f], ijk[pa], ijk[qa], n3[pa], n3[qa], nb);
-    }
-    return q;
-}
-
-// block partials in a fixed order (lanes, then the 4 waves); out[0] (and
-// out[1] if TWO) of block b at partials[2b], [2b + 1]
-template <bool TWO>
-__device__ __forceinline__ void gather_partials(double acc0, double acc1, double *partials, double (*red)[4]) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        acc0 += __shfl_xor(acc0, off, 64);
-        acc1 += __shfl_xor(acc1, off, 64);
-    }
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        red[0][w] = acc0;
-        red[1][w] = acc1;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        partials[2 * (int64_t)blockIdx.x] = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
-        if (TWO) partials[2 * (int64_t)blockIdx.x + 1] = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
-    }
-}
-
-// node of thread t of a launch over the grid's nodes (x fastest); false past the end
-__device__ __forceinline__ bool gather_node(const Geom &g, int64_t t, int &i, int &j, int &k) {
-    const int nxp = g.nx + 1, nyp = g.ny + 1;
-    if (t >= (int64_t)nxp * nyp * (g.nz + 1)) return false;
-    i = (int)(t % nxp);
-    const int64_t rw = t / nxp;
-    j = (int)(rw % nyp);
-    k = (int)(rw / nyp);
-    return true;
-}
-
 // JCG init one thread per node: r = F - A x, z = D^-1 r (p_0 = z stored if
 // p_init), r.z and r.r block partials.  For the small grids, whose vectors
 // stay in the caches between passes: there a block's march through its
@@ -584,7 +529,7 @@ __global__ void __launch_bounds__(256) k_gather_init(const ColArgs a) {
         acc0 += rv * z;
         acc1 += rv * rv;
     }
-    gather_partials<true>(acc0, acc1, a.partials, red);
+    block_partials<true>(acc0, acc1, a.partials + 2 * (int64_t)blockIdx.x, red);
 }
 
 // The stencil of pass A one thread per node: q = A p and p.q block partials,
@@ -607,7 +552,7 @@ __global__ void __launch_bounds__(256) k_gather_a(const ColArgs a) {
         __builtin_nontemporal_store(qv, a.out + id);
         acc0 += vin[id] * qv;
     }
-    gather_partials<false>(acc0, 0.0, a.partials, red);
+    block_partials<false>(acc0, 0.0, a.partials + 2 * (int64_t)blockIdx.x, red);
 }
 
 }  // namespace
