@@ -395,8 +395,8 @@ __device__ __forceinline__ void col_face_block(const ColArgs &a, const double *_
 }
 
 // WPE: waves per SIMD the register budget is set for (init, 2 rows: 150
-// VGPRs, 3 waves fit; iteration 0, 4 rows: about 200 VGPRs, 2 waves); D:
-// prefetch distance in z-steps
+// VGPRs, 3 waves fit; the stencil of pass A, 4 rows: about 200 VGPRs, 2
+// waves); D: prefetch distance in z-steps
 template <int MODE, int R, int WPE, int D>
 __global__ void __launch_bounds__(256, WPE) k_col(const ColArgs a) {
     constexpr int NR = D + 3;
@@ -593,8 +593,8 @@ int launch_col(int mode, const ColArgs &a, hipStream_t s) {
     // the face blocks after the column blocks, where they fill the launch's
     // tail (spread among the column blocks they ran slower)
     const dim3 grid(b.ncb + fb);
-    // one z-step of prefetch: two steps, or 4 waves per SIMD for iteration 0,
-    // measured no faster on 513^3
+    // one z-step of prefetch: two steps, or 4 waves per SIMD for the stencil
+    // of pass A, measured no faster on 513^3
     if (mode == MODE_APPLY) launch_timed(k_col<MODE_APPLY, COL_R_INIT, 3, 1>, grid, dim3(256), 0, s, b);
     else if (mode == MODE_INIT) launch_timed(k_col<MODE_INIT, COL_R_INIT, 2, 1>, grid, dim3(256), 0, s, b);
     else launch_timed(k_col<MODE_PASSA0, COL_R_A0, 2, 1>, grid, dim3(256), 0, s, b);

@@ -195,8 +195,9 @@ struct ColFaces {
 // Used for JCG init and the stencil of pass A on levels whose passes run
 // with one-block finishing kernels (the large grids).  Rows per wave: init
 // keeps 2 (its epilogue inputs and outputs fill the registers: 4 rows would
-// leave 2 waves per SIMD and ran slower), iteration 0 takes 4 (halo rows 1.5x
-// instead of 2x its output rows: 513^3 0.75 -> 0.69 ms).
+// leave 2 waves per SIMD and ran slower; so did 3), the stencil of pass A
+// takes 4 (halo rows 1.5x instead of 2x its output rows: 513^3 0.75 -> 0.69
+// ms; 6 rows: no net change).
 constexpr int COL_R_INIT = 2, COL_R_A0 = 4;
 struct ColArgs {
     Geom g;
