@@ -65,6 +65,37 @@ template <typename V> __device__ __forceinline__ void nt_store2(const V &v, V *p
     __builtin_nontemporal_store(w, (typename NativeVec2<E>::type *)p);
 }
 
+// The streaming hint pays only where a pass's vectors would not stay in the
+// 256 MB last-level cache until the next pass reads them.  On smaller grids the
+// node-wise passes (pass B, the p and x updates) use ordinary accesses, which
+// keep those vectors cached between the passes of an iteration: measured per
+// level, 129^3 nodes 0.44 -> 0.40 ms and 65^3 1.20 -> 1.16 ms with them, while
+// 257^3 (136 MB per vector) went from 0.79 to 0.89 ms.
+constexpr int64_t STREAM_MIN_NODES = int64_t(1) << 23;
+template <bool NT, typename V> __device__ __forceinline__ V ld2(const V *p) {
+    if constexpr (NT) {
+        return nt_load2(p);
+    } else {
+        using E = decltype(p->x);
+        const typename NativeVec2<E>::type v = *(const typename NativeVec2<E>::type *)p;
+        V r;
+        r.x = v.x;
+        r.y = v.y;
+        return r;
+    }
+}
+template <bool NT, typename V> __device__ __forceinline__ void st2(const V &v, V *p) {
+    if constexpr (NT) {
+        nt_store2(v, p);
+    } else {
+        using E = decltype(p->x);
+        typename NativeVec2<E>::type w;
+        w.x = v.x;
+        w.y = v.y;
+        *(typename NativeVec2<E>::type *)p = w;
+    }
+}
+
 // HIP events for the next timed launch, set by the library's kernel-time
 // records.  launch_timed() hands them to the extended launch, which stamps
 // them with that kernel's own start and end (no marker packets between

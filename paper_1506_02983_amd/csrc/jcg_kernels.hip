@@ -586,16 +586,17 @@ __global__ void __launch_bounds__(NTF) k_stencil_finish(JcgScalars *sc, const do
 // pass B: r -= alpha q; z = D^-1 r; r.z, r.r; stop test
 // ---------------------------------------------------------------------------
 // A streaming kernel in which every block takes one contiguous chunk of UB x NTB
-// node pairs (16-byte non-temporal accesses; node arrays have an even length
-// and 16-byte alignment) and stores its two partial sums, then a one-block kernel that sums
+// node pairs (16-byte accesses, non-temporal on grids of STREAM_MIN_NODES nodes
+// or more; node arrays have an even length and 16-byte alignment) and stores
+// its two partial sums, then a one-block kernel that sums
 // the partials in block order and takes the scalar step.  Many short-lived
 // blocks with contiguous chunks stream faster than a grid-stride loop, and
 // plain partial stores avoid a device-scope fence and atomic per block.
 constexpr int NTB = 256;
 constexpr int UB = 4;
 
-template <typename T, bool LAST>
-__global__ void __launch_bounds__(NTB) k_passB(const PassBArgs<T> a) {
+template <typename T, bool LAST, bool NT>
+__device__ __forceinline__ void passB_body(const PassBArgs<T> &a) {
     __shared__ double red[2][NTB / 64];
     __shared__ double s_alpha;
     __shared__ int s_bad;
@@ -615,9 +616,9 @@ __global__ void __launch_bounds__(NTB) k_passB(const PassBArgs<T> a) {
     for (int u = 0; u < UB; ++u) {
         const int64_t i = base + u * NTB;
         if (i < n2) {
-            rv[u] = nt_load2(r2 + i);
-            qv[u] = nt_load2(q2 + i);
-            if (!LAST) dv[u] = nt_load2(d2 + i);
+            rv[u] = ld2<NT>(r2 + i);
+            qv[u] = ld2<NT>(q2 + i);
+            if (!LAST) dv[u] = ld2<NT>(d2 + i);
         }
     }
     T al;
@@ -658,7 +659,7 @@ __global__ void __launch_bounds__(NTB) k_passB(const PassBArgs<T> a) {
             x.x = rv[u].x - al * qv[u].x;
             x.y = rv[u].y - al * qv[u].y;
             if (!LAST) {
-                nt_store2(x, w2 + i);
+                st2<NT>(x, w2 + i);
                 const T z0 = dv[u].x * x.x, z1 = dv[u].y * x.y;
                 rz += (double)x.x * (double)z0 + (double)x.y * (double)z1;
             }
@@ -671,6 +672,12 @@ __global__ void __launch_bounds__(NTB) k_passB(const PassBArgs<T> a) {
         a.partials[2 * (int64_t)blockIdx.x] = acc[0];
         a.partials[2 * (int64_t)blockIdx.x + 1] = acc[1];
     }
+}
+
+template <typename T, bool LAST>
+__global__ void __launch_bounds__(NTB) k_passB(const PassBArgs<T> a) {
+    if (a.n >= STREAM_MIN_NODES) passB_body<T, LAST, true>(a);
+    else passB_body<T, LAST, false>(a);
 }
 
 // Totals of pass B's nb block partials (fixed order), then beta, rho, ||r||^2
@@ -700,6 +707,34 @@ __global__ void __launch_bounds__(NTF) k_passB_finish(JcgScalars *sc, const doub
 // pairs per block, 16-byte accesses.  Thread 0 of block 0 also copies the
 // final scalars to `out` (pinned host memory, read by the host once the stream
 // has passed this launch).
+template <typename T, bool NT>
+__device__ __forceinline__ void final_x_body(int64_t n, T *x, const T *p0, const T *p1, const JcgScalars *sc) {
+    using V2 = typename Vec2<T>::type;
+    const T al = (T)sc->alpha;
+    const V2 *__restrict__ p = (const V2 *)((sc->iter & 1) ? p1 : p0);
+    V2 *__restrict__ x2 = (V2 *)x;
+    const int64_t n2 = n / 2;
+    const int64_t base = (int64_t)blockIdx.x * (UB * 256) + threadIdx.x;
+    V2 xv[UB], pv[UB];
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+        const int64_t i = base + u * 256;
+        if (i < n2) {
+            xv[u] = ld2<NT>(x2 + i);
+            pv[u] = ld2<NT>(p + i);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+        const int64_t i = base + u * 256;
+        if (i < n2) {
+            xv[u].x += al * pv[u].x;
+            xv[u].y += al * pv[u].y;
+            st2<NT>(xv[u], x2 + i);
+        }
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_final_x(int64_t n, T *x, const T *p0, const T *p1, const JcgScalars *sc,
                                                  JcgScalars *out) {
@@ -712,30 +747,8 @@ __global__ void __launch_bounds__(256) k_final_x(int64_t n, T *x, const T *p0, c
             __hip_atomic_store(dst + w, src[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
     if (!sc->pending) return;
-    using V2 = typename Vec2<T>::type;
-    const T al = (T)sc->alpha;
-    const V2 *__restrict__ p = (const V2 *)((sc->iter & 1) ? p1 : p0);
-    V2 *__restrict__ x2 = (V2 *)x;
-    const int64_t n2 = n / 2;
-    const int64_t base = (int64_t)blockIdx.x * (UB * 256) + threadIdx.x;
-    V2 xv[UB], pv[UB];
-#pragma unroll
-    for (int u = 0; u < UB; ++u) {
-        const int64_t i = base + u * 256;
-        if (i < n2) {
-            xv[u] = nt_load2(x2 + i);
-            pv[u] = nt_load2(p + i);
-        }
-    }
-#pragma unroll
-    for (int u = 0; u < UB; ++u) {
-        const int64_t i = base + u * 256;
-        if (i < n2) {
-            xv[u].x += al * pv[u].x;
-            xv[u].y += al * pv[u].y;
-            nt_store2(xv[u], x2 + i);
-        }
-    }
+    if (n >= STREAM_MIN_NODES) final_x_body<T, true>(n, x, p0, p1, sc);
+    else final_x_body<T, false>(n, x, p0, p1, sc);
 }
 
 // Pass A of iteration it >= 1 split for the column stencil (the grids too
@@ -745,10 +758,10 @@ __global__ void __launch_bounds__(256) k_final_x(int64_t n, T *x, const T *p0, c
 // q = A p and p.q.  One contiguous chunk of UB x 256 node pairs per block,
 // 16-byte accesses over the whole array (padding entries are zero in every
 // input and stay zero).
-__global__ void __launch_bounds__(256) k_p_update(int64_t n, const double *__restrict__ dinv,
-                                                  const double *__restrict__ r, double *p0, double *p1, double *x,
-                                                  const JcgScalars *sc) {
-    if (sc->done) return;                         // uniform over the grid
+template <bool NT>
+__device__ __forceinline__ void p_update_body(int64_t n, const double *__restrict__ dinv,
+                                              const double *__restrict__ r, double *p0, double *p1, double *x,
+                                              const JcgScalars *sc) {
     const int it = sc->iter;
     const double bk = sc->beta, al = sc->alpha;
     const bool first = it == 0;
@@ -764,11 +777,11 @@ __global__ void __launch_bounds__(256) k_p_update(int64_t n, const double *__res
     for (int u = 0; u < UB; ++u) {
         const int64_t i = base + u * 256;
         if (i < n2) {
-            dv[u] = nt_load2(d2 + i);
-            rv[u] = nt_load2(r2 + i);
+            dv[u] = ld2<NT>(d2 + i);
+            rv[u] = ld2<NT>(r2 + i);
             if (!first) {
-                pv[u] = nt_load2(pin + i);
-                xv[u] = nt_load2(x2 + i);
+                pv[u] = ld2<NT>(pin + i);
+                xv[u] = ld2<NT>(x2 + i);
             }
         }
     }
@@ -780,15 +793,23 @@ __global__ void __launch_bounds__(256) k_p_update(int64_t n, const double *__res
             const double z0 = dv[u].x * rv[u].x, z1 = dv[u].y * rv[u].y;
             pn.x = first ? z0 : z0 + bk * pv[u].x;
             pn.y = first ? z1 : z1 + bk * pv[u].y;
-            nt_store2(pn, pout + i);
+            st2<NT>(pn, pout + i);
             if (!first) {
                 double2 xn;
                 xn.x = xv[u].x + al * pv[u].x;
                 xn.y = xv[u].y + al * pv[u].y;
-                nt_store2(xn, x2 + i);
+                st2<NT>(xn, x2 + i);
             }
         }
     }
+}
+
+__global__ void __launch_bounds__(256) k_p_update(int64_t n, const double *__restrict__ dinv,
+                                                  const double *__restrict__ r, double *p0, double *p1, double *x,
+                                                  const JcgScalars *sc) {
+    if (sc->done) return;                         // uniform over the grid
+    if (n >= STREAM_MIN_NODES) p_update_body<true>(n, dinv, r, p0, p1, x, sc);
+    else p_update_body<false>(n, dinv, r, p0, p1, x, sc);
 }
 
 // The same node-wise part of pass A for the gather levels, whose scalar steps
@@ -798,7 +819,8 @@ __global__ void __launch_bounds__(256) k_p_update(int64_t n, const double *__res
 // beta = rho_it / rho_{it-1}; block 0 stores the scalars (as the folded
 // tiled pass A does).  While running, it >= 1 forms p and x += alpha p_old;
 // at it = 0 init has stored p_0 already.
-__global__ void __launch_bounds__(256) k_p_update_fold(const PUFoldArgs a) {
+template <bool NT>
+__device__ __forceinline__ void p_update_fold_body(const PUFoldArgs &a) {
     __shared__ double red[2][4];
     __shared__ double s_beta;
     __shared__ int s_flag;
@@ -829,10 +851,10 @@ __global__ void __launch_bounds__(256) k_p_update_fold(const PUFoldArgs a) {
         for (int u = 0; u < UB; ++u) {
             const int64_t i = base + u * 256;
             if (i < n2) {
-                dv[u] = nt_load2(d2 + i);
-                rv[u] = nt_load2(r2 + i);
-                pv[u] = nt_load2(pin + i);
-                xv[u] = nt_load2(x2 + i);
+                dv[u] = ld2<NT>(d2 + i);
+                rv[u] = ld2<NT>(r2 + i);
+                pv[u] = ld2<NT>(pin + i);
+                xv[u] = ld2<NT>(x2 + i);
             }
         }
     }
@@ -878,12 +900,17 @@ __global__ void __launch_bounds__(256) k_p_update_fold(const PUFoldArgs a) {
             const double z0 = dv[u].x * rv[u].x, z1 = dv[u].y * rv[u].y;
             pn.x = z0 + bk * pv[u].x;
             pn.y = z1 + bk * pv[u].y;
-            nt_store2(pn, pout + i);
+            st2<NT>(pn, pout + i);
             xn.x = xv[u].x + f_alpha * pv[u].x;
             xn.y = xv[u].y + f_alpha * pv[u].y;
-            nt_store2(xn, x2 + i);
+            st2<NT>(xn, x2 + i);
         }
     }
+}
+
+__global__ void __launch_bounds__(256) k_p_update_fold(const PUFoldArgs a) {
+    if (a.n >= STREAM_MIN_NODES) p_update_fold_body<true>(a);
+    else p_update_fold_body<false>(a);
 }
 
 __global__ void k_jcg_reset(JcgScalars *sc, double tol, int max_iter, int fixed) {
