@@ -84,6 +84,16 @@ template <bool NT, typename V> __device__ __forceinline__ V ld2(const V *p) {
         return r;
     }
 }
+// one element (the compiler merges a run-time choice between the two forms of
+// the same access into the ordinary one, so the choice is a template argument)
+template <bool NT, typename T> __device__ __forceinline__ T ld1(const T *p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <bool NT, typename T> __device__ __forceinline__ void st1(T v, T *p) {
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
 template <bool NT, typename V> __device__ __forceinline__ void st2(const V &v, V *p) {
     if constexpr (NT) {
         nt_store2(v, p);

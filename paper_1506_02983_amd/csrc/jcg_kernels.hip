@@ -210,18 +210,29 @@ __device__ __forceinline__ T robin_term(const Geom &g, int face, const T *al, in
 // Block shape per instantiation: TYv rows of TX threads, RYv node rows per
 // thread (TYv * RYv == TYT, so every shape tiles the plane alike and the host's
 // tile counts and partial slots do not depend on it), WPE waves per SIMD.
-template <typename T, int MODE, int TYv, int RYv, int WPE>
-__global__ void __launch_bounds__(TX * TYv, WPE) k_stencil(const StencilArgs<T> a) {
+// Rolling LDS buffers: 4 node planes and 3 element layers, so the plane being
+// filled never aliases the three planes being read and one barrier per z-step
+// suffices.  Declared by the kernel, once for both forms of the body.
+template <typename T, int TYv>
+struct StencilLds {
+    T sv[4][TYT + 2][TX + 2];
+    T sb[3][TYT + 1][TX + 1];
+    double red[2][TX * TYv / 64];
+    double s_beta;
+    int s_flag;
+};
+
+// NT: streaming hints on the vector accesses (grids of STREAM_MIN_NODES nodes
+// or more)
+template <typename T, int MODE, int TYv, int RYv, bool NT>
+__device__ __forceinline__ void stencil_body(const StencilArgs<T> &a, StencilLds<T, TYv> &L) {
     constexpr int NTv = TX * TYv;
     static_assert(TYv * RYv == TYT, "a block shape covers the tile height");
-    // Rolling LDS buffers: 4 node planes and 3 element layers, so the plane
-    // being filled never aliases the three planes being read and one barrier per
-    // z-step suffices.
-    __shared__ T sv[4][TYT + 2][TX + 2];
-    __shared__ T sb[3][TYT + 1][TX + 1];
-    __shared__ double red[2][NTv / 64];
-    __shared__ double s_beta;
-    __shared__ int s_flag;
+    auto &sv = L.sv;
+    auto &sb = L.sb;
+    auto &red = L.red;
+    double &s_beta = L.s_beta;
+    int &s_flag = L.s_flag;
     constexpr int NH = 2 * (TX + 2) + 2 * TYT;   // halo nodes of a plane tile
     constexpr int NHB = (TX + 1) + TYT;          // halo elements of a layer tile
     static_assert(NH <= NTv && NHB <= NTv, "one halo value per thread");
@@ -350,12 +361,12 @@ __global__ void __launch_bounds__(TX * TYv, WPE) k_stencil(const StencilArgs<T> 
             S.ea[r] = S.eb[r] = 0;
             if (MODE == MODE_APPLY || MODE == MODE_PASSA0 || off[r] < 0 || k < 0 || k > g.nz) continue;
             const int64_t id = (int64_t)off[r] + sxy * k;
-            // epilogue inputs are read once: non-temporal
+            // epilogue inputs are read once: non-temporal on large grids
             if (MODE == MODE_PASSA) {
-                if (!first) S.ea[r] = __builtin_nontemporal_load(a.x + id);
+                if (!first) S.ea[r] = ld1<NT>(a.x + id);
             } else {
-                S.ea[r] = __builtin_nontemporal_load(a.F + id);
-                S.eb[r] = __builtin_nontemporal_load(a.dinv + id);
+                S.ea[r] = ld1<NT>(a.F + id);
+                S.eb[r] = ld1<NT>(a.dinv + id);
             }
         }
     };
@@ -503,23 +514,22 @@ __global__ void __launch_bounds__(TX * TYv, WPE) k_stencil(const StencilArgs<T> 
             if (k == g.nz && g.ft[5] == ECMG_ROBIN) q += robin_term<2>(g, 5, a.alpha[5], i, j, g.nx, g.ny, sv, s0, s1, s2, lj, li);
             const bool dir = is_dirichlet(g, i, j, k);
             const int64_t id = (int64_t)off[r] + sxy * k;
-            // outputs: coalesced rows, written once per pass (non-temporal)
+            // outputs: coalesced rows, written once per pass (non-temporal on large grids)
             if (MODE == MODE_APPLY) {
-                __builtin_nontemporal_store(dir ? (T)0 : q, a.q + id);
+                st1<NT>(dir ? (T)0 : q, a.q + id);
             } else if (MODE == MODE_INIT) {
                 const T rv = dir ? (T)0 : xa_cur[r] - q;
-                __builtin_nontemporal_store(rv, a.r + id);
+                st1<NT>(rv, a.r + id);
                 const T z = xb_cur[r] * rv;
-                if (a.p_init) __builtin_nontemporal_store(z, a.p1 + id);   // p_0 for MODE_PASSA0
+                if (a.p_init) st1<NT>(z, a.p1 + id);   // p_0 for MODE_PASSA0
                 acc0 += (double)rv * (double)z;
                 acc1 += (double)rv * (double)rv;
             } else {
                 const T pc = sv[s1][lj][li];
                 const T qv = dir ? (T)0 : q;
-                if (MODE == MODE_PASSA) __builtin_nontemporal_store(pc, pout + id);
-                __builtin_nontemporal_store(qv, a.q + id);
-                if (MODE == MODE_PASSA && !first)
-                    __builtin_nontemporal_store(xa_cur[r] + alpha_prev * pold_cur[r], a.x + id);
+                if (MODE == MODE_PASSA) st1<NT>(pc, pout + id);
+                st1<NT>(qv, a.q + id);
+                if (MODE == MODE_PASSA && !first) st1<NT>(xa_cur[r] + alpha_prev * pold_cur[r], a.x + id);
                 acc0 += (double)pc * (double)qv;
             }
         }
@@ -544,6 +554,13 @@ __global__ void __launch_bounds__(TX * TYv, WPE) k_stencil(const StencilArgs<T> 
         out[2 * (int64_t)blockIdx.x] = acc[0];
         if (MODE == MODE_INIT) out[2 * (int64_t)blockIdx.x + 1] = acc[1];
     }
+}
+
+template <typename T, int MODE, int TYv, int RYv, int WPE>
+__global__ void __launch_bounds__(TX * TYv, WPE) k_stencil(const StencilArgs<T> a) {
+    __shared__ StencilLds<T, TYv> lds;
+    if (a.g.nnodes >= STREAM_MIN_NODES) stencil_body<T, MODE, TYv, RYv, true>(a, lds);
+    else stencil_body<T, MODE, TYv, RYv, false>(a, lds);
 }
 
 // Totals of the stencil pass's nb block partials (fixed order), then the
