@@ -533,24 +533,31 @@ __global__ void __launch_bounds__(256) k_gather_init(const ColArgs a) {
 }
 
 // The stencil of pass A one thread per node: q = A p and p.q block partials,
-// p read from the buffer of the iteration's parity (sc->iter, which the
-// node-wise p update of the same iteration has stored).  A version that formed
+// p read from the buffer of the iteration's parity (a.it, the iteration whose
+// node-wise p update ran just before).  A version that formed
 // p at the 27 neighbours itself (one launch per pass A, three loads per
 // neighbour) ran 1.6x slower on 65^3 than the p update plus this kernel.
 __global__ void __launch_bounds__(256) k_gather_a(const ColArgs a) {
     __shared__ double red[2][4];
     const Geom &g = a.g;
-    const int2 itd = iter_done(a.sc);
-    if (itd.y) return;                            // done: uniform over the grid
-    const double *__restrict__ vin = (a.v_odd && (itd.x & 1)) ? a.v_odd : a.v;
-    double acc0 = 0.0;
+    // the iteration comes with the launch, so the row's loads depend on no
+    // other load; `done` (which this iteration's p update may have set) is
+    // loaded alongside them and checked before any store
+    const int dn = a.sc->done;
+    const double *__restrict__ vin = (a.v_odd && (a.it & 1)) ? a.v_odd : a.v;
+    double acc0 = 0.0, qv = 0.0, pv = 0.0;
+    int64_t id = -1;
     int i, j, k;
     if (gather_node(g, (int64_t)blockIdx.x * 256 + threadIdx.x, i, j, k)) {
-        const int id = i + g.sx * j + g.sx * g.sy * k;
+        id = i + g.sx * j + (int64_t)g.sx * g.sy * k;
         const bool dir = dir_node(g, i, j, k);
-        const double qv = dir ? 0.0 : gather_q(a, i, j, k, [&](int idx) { return vin[idx]; });
+        qv = dir ? 0.0 : gather_q(a, i, j, k, [&](int idx) { return vin[idx]; });
+        pv = vin[id];
+    }
+    if (dn) return;                               // uniform over the grid
+    if (id >= 0) {
         __builtin_nontemporal_store(qv, a.out + id);
-        acc0 += vin[id] * qv;
+        acc0 += pv * qv;
     }
     block_partials<false>(acc0, 0.0, a.partials + 2 * (int64_t)blockIdx.x, red);
 }

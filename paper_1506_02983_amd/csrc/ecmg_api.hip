@@ -636,7 +636,9 @@ static int jcg_chunks_gather(ecmg_ctx *c, int l, PUFoldArgs u, const ColArgs &ga
                 CHK(rec_begin(c, l, it == 0 ? 10 : 11, it, &slot));
                 launch_p_update_fold(u, c->stream);
             } else if (ph == 1) {
-                launch_gather_a(ga, c->stream);
+                ColArgs gi = ga;
+                gi.it = it;
+                launch_gather_a(gi, c->stream);
                 CHK(rec_end(c, slot));
             } else {
                 b.it = it;

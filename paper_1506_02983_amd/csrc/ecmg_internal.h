@@ -255,6 +255,7 @@ struct ColArgs {
     int p_init;
     int plain_cg;                     // INIT: M^-1 = 1 (ECMG_CG) instead of 1/diag from beta
     JcgScalars *sc;                   // PASSA0: returns when done is set
+    int it;                           // gather pass A: the iteration (its p buffer), set per launch
     double *partials;                 // 2 per wave, then 2 per Robin-face block
     int ncb;                          // column blocks (set by launch_col)
     ColFaces fl;                      // Robin faces (set by launch_col)
@@ -271,8 +272,8 @@ int launch_col(int mode, const ColArgs &a, hipStream_t s);
 // One thread per node (the gather levels: small grids, folded scalars).
 // Init: the ColArgs fields of MODE_INIT (v = x, out = r, p_out, p_init,
 // partials: r.z, r.r pairs).  Stencil of pass A: q = A p into out, p from v
-// (even iterations) or v_odd (odd, by sc->iter), p.q pairs into partials;
-// returns at once when sc->done is set.  Both return the partial pairs
+// (even iterations) or v_odd (odd, by a.it), p.q pairs into partials; stores
+// nothing when sc->done is set.  Both return the partial pairs
 // written (one per block of 256 nodes).
 int gather_blocks(const Geom &g);
 int launch_gather_init(const ColArgs &a, hipStream_t s);
