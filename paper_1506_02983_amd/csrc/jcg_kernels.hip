@@ -207,9 +207,6 @@ __device__ __forceinline__ T robin_term(const Geom &g, int face, const T *al, in
 // MODE_PASSA (fused JCG pass A), MODE_PASSA0 (its iteration 0 from a stored p_0)
 // ---------------------------------------------------------------------------
 
-// Block shape per instantiation: TYv rows of TX threads, RYv node rows per
-// thread (TYv * RYv == TYT, so every shape tiles the plane alike and the host's
-// tile counts and partial slots do not depend on it), WPE waves per SIMD.
 // Rolling LDS buffers: 4 node planes and 3 element layers, so the plane being
 // filled never aliases the three planes being read and one barrier per z-step
 // suffices.  Declared by the kernel, once for both forms of the body.
@@ -556,6 +553,10 @@ __device__ __forceinline__ void stencil_body(const StencilArgs<T> &a, StencilLds
     }
 }
 
+// Block shape per instantiation: TYv rows of TX threads, RYv node rows per
+// thread (TYv * RYv == TYT, so every shape tiles the plane alike and the host's
+// tile counts and partial slots do not depend on it), WPE waves per SIMD.  The
+// grid's size picks the form of the body.
 template <typename T, int MODE, int TYv, int RYv, int WPE>
 __global__ void __launch_bounds__(TX * TYv, WPE) k_stencil(const StencilArgs<T> a) {
     __shared__ StencilLds<T, TYv> lds;
